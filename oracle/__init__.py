@@ -1,0 +1,359 @@
+"""Plain FP64 CPU oracle of the per-surfel Gauss-Newton update (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark use it; the product library never imports it.  The
+arithmetic lives in ``sgo.c`` (plain C, IEEE double); this module only
+marshals numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgo.so")
+
+DEGENERATE = 1 << 0
+FEW_SAMPLES = 1 << 1
+SOLVE_FAIL = 1 << 2
+REJECTED = 1 << 3
+FP64_SOLVE = 1 << 4
+UNINIT = 1 << 5
+
+
+def build(force: bool = True) -> str:
+    """Compile sgo.c with gcc (no fast-math, no FMA contraction)."""
+    src = os.path.join(_HERE, "sgo.c")
+    if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= os.path.getmtime(src):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class Intrinsics(C.Structure):
+    _fields_ = [("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double)]
+
+
+class Pose(C.Structure):
+    _fields_ = [("R", C.c_double * 9), ("t", C.c_double * 3)]
+
+
+class Image(C.Structure):
+    _fields_ = [("pix", C.POINTER(C.c_double)), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class KeyframeC(C.Structure):
+    _fields_ = [("kf", Image), ("nbr", C.POINTER(Image)), ("pose", C.POINTER(Pose)),
+                ("n_nbr", C.c_int32), ("K", Intrinsics), ("patch", C.c_int32)]
+
+
+class SurfelsC(C.Structure):
+    _fields_ = [("inv_depth", C.POINTER(C.c_double)), ("nx", C.POINTER(C.c_double)),
+                ("ny", C.POINTER(C.c_double)), ("nz", C.POINTER(C.c_double)),
+                ("flags", C.POINTER(C.c_uint32)), ("cost", C.POINTER(C.c_double)),
+                ("nvalid", C.POINTER(C.c_int32)), ("last_update", C.POINTER(C.c_uint32)),
+                ("kappa", C.POINTER(C.c_double))]
+
+
+class ParamsC(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("huber_k", C.c_double), ("depth_only", C.c_int32),
+                ("beta_r", C.c_double), ("stamp", C.c_uint32), ("lm_lambda", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        L.sgo_pixel_inverse_depth.restype = C.c_double
+        L.sgo_pixel_inverse_depth.argtypes = [C.POINTER(Intrinsics), C.c_double, C.c_double,
+                                              C.c_double, dp, C.c_double, C.c_double]
+        L.sgo_warp.restype = C.c_int
+        L.sgo_warp.argtypes = [C.POINTER(Intrinsics), C.POINTER(Pose), C.c_double, C.c_double,
+                               C.c_double, dp]
+        L.sgo_bilinear.restype = C.c_int
+        L.sgo_bilinear.argtypes = [C.POINTER(Image), C.c_double, C.c_double, dp]
+        L.sgo_tangent_basis.restype = None
+        L.sgo_tangent_basis.argtypes = [dp, dp, dp]
+        L.sgo_eval_sample.restype = C.c_int
+        L.sgo_eval_sample.argtypes = [C.POINTER(Intrinsics), C.POINTER(Pose), C.POINTER(Image),
+                                      C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                                      C.c_double, dp, C.c_int, dp, dp]
+        L.sgo_linearize.restype = C.c_int32
+        L.sgo_linearize.argtypes = [C.POINTER(KeyframeC), C.c_int32, C.c_int32, C.c_double, dp,
+                                    C.c_double, C.c_int, dp, dp, dp]
+        L.sgo_solve3.restype = C.c_uint32
+        L.sgo_solve3.argtypes = [dp, dp, dp]
+        L.sgo_kappa_eq.restype = C.c_double
+        L.sgo_kappa_eq.argtypes = [dp]
+        ip = C.POINTER(C.c_int32)
+        L.sgo_optimize_keyframe.restype = C.c_int
+        L.sgo_optimize_keyframe.argtypes = [C.POINTER(KeyframeC), C.POINTER(SurfelsC),
+                                            C.POINTER(ParamsC), ip, C.c_int32]
+        L.sgo_init_from_neighbours.restype = C.c_int
+        L.sgo_init_from_neighbours.argtypes = [C.POINTER(KeyframeC), C.POINTER(SurfelsC),
+                                               C.POINTER(C.c_uint8), C.POINTER(ParamsC), ip,
+                                               C.c_int32]
+        L.sgo_render_inverse_depth.restype = C.c_int
+        L.sgo_render_inverse_depth.argtypes = [C.POINTER(KeyframeC), C.POINTER(SurfelsC), dp, ip]
+        L.sgo_transfer_surfels.restype = C.c_int
+        L.sgo_transfer_surfels.argtypes = [C.POINTER(Intrinsics), C.POINTER(Pose), C.c_int32,
+                                           dp, dp, dp, dp, dp, dp, dp, dp]
+        L.sgo_set_threads.restype = None
+        L.sgo_set_threads.argtypes = [C.c_int32]
+        L.sgo_max_threads.restype = C.c_int32
+        L.sgo_max_threads.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def intrinsics(K: Sequence[float]) -> Intrinsics:
+    return Intrinsics(*[float(v) for v in K])
+
+
+def pose(R, t) -> Pose:
+    p = Pose()
+    R = np.asarray(R, dtype=np.float64).reshape(9)
+    t = np.asarray(t, dtype=np.float64).reshape(3)
+    for i in range(9):
+        p.R[i] = float(R[i])
+    for i in range(3):
+        p.t[i] = float(t[i])
+    return p
+
+
+def image(arr: np.ndarray):
+    a = _f64(arr)
+    im = Image(_dp(a), a.shape[1], a.shape[0])
+    return im, a
+
+
+@dataclass
+class OracleParams:
+    iters: int = 10
+    huber_k: float = 9.0 / 255.0
+    depth_only: bool = False
+    beta_r: Optional[float] = None   # default: the tile edge S
+    stamp: int = 1
+    lm_lambda: float = 0.0
+
+    def c(self, patch: int) -> ParamsC:
+        br = float(self.beta_r) if self.beta_r is not None else float(patch)
+        return ParamsC(int(self.iters), float(self.huber_k), int(bool(self.depth_only)), br,
+                       int(self.stamp), float(self.lm_lambda))
+
+
+class OracleKeyframe:
+    """Keeps FP64 copies of one keyframe's images and poses alive for C calls.
+
+    ``kf_image`` (H, W) and ``nbr_images`` (N, H, W) must already hold the
+    exact values the device path sees (dequantised f16/u8 values included).
+    """
+
+    def __init__(self, K, kf_image, nbr_images, R, t, patch: int):
+        self.K = intrinsics(K)
+        self.patch = int(patch)
+        self.kf_img, self._kf_arr = image(kf_image)
+        nbr_images = np.asarray(nbr_images)
+        self.n_nbr = int(nbr_images.shape[0])
+        self._nbr_arrs = [_f64(nbr_images[i]) for i in range(self.n_nbr)]
+        self._nbr = (Image * max(1, self.n_nbr))()
+        for i, a in enumerate(self._nbr_arrs):
+            self._nbr[i] = Image(_dp(a), a.shape[1], a.shape[0])
+        self._poses = (Pose * max(1, self.n_nbr))()
+        for i in range(self.n_nbr):
+            self._poses[i] = pose(R[i], t[i])
+        self.c = KeyframeC(self.kf_img, self._nbr, self._poses, self.n_nbr, self.K, self.patch)
+        self.width = int(self._kf_arr.shape[1])
+        self.height = int(self._kf_arr.shape[0])
+
+    @property
+    def grid(self):
+        return (self.width // self.patch, self.height // self.patch)
+
+    @property
+    def n_surfels(self):
+        gw, gh = self.grid
+        return gw * gh
+
+
+def new_state(inv_depth, normals, flags=None) -> Dict[str, np.ndarray]:
+    inv_depth = _f64(inv_depth).reshape(-1).copy()
+    normals = _f64(normals).reshape(-1, 3)
+    n = inv_depth.shape[0]
+    return {
+        "inv_depth": inv_depth,
+        "nx": normals[:, 0].copy(), "ny": normals[:, 1].copy(), "nz": normals[:, 2].copy(),
+        "flags": (np.zeros(n, np.uint32) if flags is None
+                  else np.ascontiguousarray(np.asarray(flags, np.uint32).reshape(-1)).copy()),
+        "cost": np.zeros(n), "nvalid": np.zeros(n, np.int32),
+        "last_update": np.zeros(n, np.uint32), "kappa": np.zeros(n),
+    }
+
+
+def _surfels_c(st: Dict[str, np.ndarray]) -> SurfelsC:
+    return SurfelsC(_dp(st["inv_depth"]), _dp(st["nx"]), _dp(st["ny"]), _dp(st["nz"]),
+                    st["flags"].ctypes.data_as(C.POINTER(C.c_uint32)), _dp(st["cost"]),
+                    st["nvalid"].ctypes.data_as(C.POINTER(C.c_int32)),
+                    st["last_update"].ctypes.data_as(C.POINTER(C.c_uint32)), _dp(st["kappa"]))
+
+
+def _subset(subset):
+    if subset is None:
+        return None, 0, None
+    arr = np.ascontiguousarray(np.asarray(subset, dtype=np.int32))
+    return arr.ctypes.data_as(C.POINTER(C.c_int32)), int(arr.shape[0]), arr
+
+
+def optimize(kf: OracleKeyframe, st: Dict[str, np.ndarray], params: OracleParams,
+             subset=None) -> Dict[str, np.ndarray]:
+    """Gauss-Newton iterations, in place on ``st`` (returned for convenience)."""
+    sc = _surfels_c(st)
+    pc = params.c(kf.patch)
+    ptr, n, keep = _subset(subset)
+    rc = lib().sgo_optimize_keyframe(C.byref(kf.c), C.byref(sc), C.byref(pc), ptr, n)
+    if rc != 0:
+        raise RuntimeError("sgo_optimize_keyframe failed")
+    return st
+
+
+def init_from_neighbours(kf: OracleKeyframe, st, is_new, params: OracleParams, subset=None):
+    sc = _surfels_c(st)
+    pc = params.c(kf.patch)
+    nw = np.ascontiguousarray(np.asarray(is_new, dtype=np.uint8).reshape(-1))
+    ptr, n, keep = _subset(subset)
+    rc = lib().sgo_init_from_neighbours(C.byref(kf.c), C.byref(sc),
+                                        nw.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(pc),
+                                        ptr, n)
+    if rc != 0:
+        raise RuntimeError("sgo_init_from_neighbours failed")
+    return st
+
+
+def render(kf: OracleKeyframe, st):
+    sc = _surfels_c(st)
+    idm = np.zeros((kf.height, kf.width))
+    ind = np.zeros((kf.height, kf.width), np.int32)
+    lib().sgo_render_inverse_depth(C.byref(kf.c), C.byref(sc), _dp(idm),
+                                   ind.ctypes.data_as(C.POINTER(C.c_int32)))
+    return idm, ind
+
+
+def linearize(kf: OracleKeyframe, tx, ty, id_s, n, huber_k=9.0 / 255.0, depth_only=False):
+    H = np.zeros(9)
+    b = np.zeros(3)
+    cost = C.c_double(0.0)
+    nn = _f64(n)
+    nv = lib().sgo_linearize(C.byref(kf.c), int(tx), int(ty), float(id_s), _dp(nn),
+                             float(huber_k), int(bool(depth_only)), _dp(H), _dp(b), C.byref(cost))
+    return H.reshape(3, 3), b, float(cost.value), int(nv)
+
+
+def eval_sample(K, R, t, nbr_img, kf_value, us, u, id_s, n, depth_only=False):
+    Kc = intrinsics(K)
+    P = pose(R, t)
+    im, keep = image(nbr_img)
+    nn = _f64(n)
+    r = C.c_double(0.0)
+    J = np.zeros(3)
+    ok = lib().sgo_eval_sample(C.byref(Kc), C.byref(P), C.byref(im), float(kf_value),
+                               float(us[0]), float(us[1]), float(u[0]), float(u[1]),
+                               float(id_s), _dp(nn), int(bool(depth_only)), C.byref(r), _dp(J))
+    return bool(ok), float(r.value), J
+
+
+def pixel_inverse_depth(K, us, id_s, n, u):
+    Kc = intrinsics(K)
+    nn = _f64(n)
+    return float(lib().sgo_pixel_inverse_depth(C.byref(Kc), float(us[0]), float(us[1]),
+                                               float(id_s), _dp(nn), float(u[0]), float(u[1])))
+
+
+def warp(K, R, t, u, id_u):
+    Kc = intrinsics(K)
+    P = pose(R, t)
+    uv = np.zeros(2)
+    ok = lib().sgo_warp(C.byref(Kc), C.byref(P), float(u[0]), float(u[1]), float(id_u), _dp(uv))
+    return bool(ok), uv
+
+
+def bilinear(img, x, y):
+    im, keep = image(img)
+    out = np.zeros(3)
+    ok = lib().sgo_bilinear(C.byref(im), float(x), float(y), _dp(out))
+    return bool(ok), out
+
+
+def tangent_basis(n):
+    nn = _f64(n)
+    b1 = np.zeros(3)
+    b2 = np.zeros(3)
+    lib().sgo_tangent_basis(_dp(nn), _dp(b1), _dp(b2))
+    return b1, b2
+
+
+def solve3(H, b):
+    Hm = _f64(H).reshape(9).copy()
+    bb = _f64(b).reshape(3).copy()
+    d = np.zeros(3)
+    st = lib().sgo_solve3(_dp(Hm), _dp(bb), _dp(d))
+    return int(st), d
+
+
+def kappa_eq(H):
+    Hm = _f64(H).reshape(9).copy()
+    return float(lib().sgo_kappa_eq(_dp(Hm)))
+
+
+def transfer(K, R, t, us, id_s, n):
+    """Eq. 10 for arrays of surfels: us (M, 2), id_s (M,), n (M, 3)."""
+    Kc = intrinsics(K)
+    P = pose(R, t)
+    us = _f64(us).reshape(-1, 2)
+    m = us.shape[0]
+    usx = np.ascontiguousarray(us[:, 0])
+    usy = np.ascontiguousarray(us[:, 1])
+    ids = _f64(id_s).reshape(-1)
+    nn = _f64(n).reshape(-1, 3)
+    ux = np.zeros(m)
+    uy = np.zeros(m)
+    ido = np.zeros(m)
+    no = np.zeros((m, 3))
+    lib().sgo_transfer_surfels(C.byref(Kc), C.byref(P), m, _dp(usx), _dp(usy), _dp(ids),
+                               _dp(nn), _dp(ux), _dp(uy), _dp(ido), _dp(no))
+    return np.stack([ux, uy], 1), ido, no
+
+
+def set_threads(n: int):
+    lib().sgo_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().sgo_max_threads())
+
+
+def dequantize_u8(codes: np.ndarray, scale: float) -> np.ndarray:
+    """Exact FP64 value of u8 codes with a (float) scale: code * scale."""
+    return np.asarray(codes, dtype=np.float64) * float(scale)

@@ -1,0 +1,545 @@
+/*
+ * sgo.c -- plain FP64 CPU oracle of the per-surfel Gauss-Newton update.
+ *
+ * TEST INFRASTRUCTURE ONLY (tests, smoke check, CPU-baseline timing).  It
+ * shares no code with the HIP path.  See sgo.h for conventions.
+ *
+ * Structure follows the paper's Proposed Approach section:
+ *   Eq. 1  p_s = r_s / id_s                       (surfel point)
+ *   Eq. 2  r_u = K^-1 pi^-1(u)                    (pixel ray, z = 1)
+ *   Eq. 3  id_u = (r_u . n_s) / ((r_s / id_s) . n_s)
+ *   Eq. 5  C = sum_n sum_u huber(I_fn(u_p) - I_kf(u))
+ *   Eq. 6  u_p = pi(K P_kf^fn (K^-1 u~ / id_u))   (printed with pi / pi^-1
+ *          swapped; read as the projection of the back-projected point)
+ *   Eq. 7-9 chain rule J = dC/did_u * did_u/d[n_s, id_s]
+ *   normal updated with three components then renormalised (Surfel
+ *   Optimization section, last paragraph)
+ *   Surfel Initialization section: mean of neighbours' Eq. 3 inverse depths
+ *   at the new ray, mean of their normals.
+ *   Eq. 10 reference-frame change.
+ * Nothing is blocked, fused or hoisted: every (pixel, frame) sample forms its
+ * own full Jacobian row and is added to J^T W J and J^T W r directly.
+ */
+#include "sgo.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static double dot3(const double a[3], const double b[3]) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+static void cross3(const double a[3], const double b[3], double c[3]) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static int normalize3(double v[3]) {
+    double l = sqrt(dot3(v, v));
+    if (!(l > 0.0) || !isfinite(l)) return 0;
+    v[0] /= l; v[1] /= l; v[2] /= l;
+    return 1;
+}
+
+/* Eq. 2: r_u = K^-1 [x, y, 1]^T. */
+void sgo_ray(const sgo_intrinsics* K, double x, double y, double r[3]) {
+    r[0] = (x - K->cx) / K->fx;
+    r[1] = (y - K->cy) / K->fy;
+    r[2] = 1.0;
+}
+
+/* Eq. 3 as printed: id_u = (r_u . n_s) / ((r_s / id_s) . n_s). */
+double sgo_pixel_inverse_depth(const sgo_intrinsics* K, double usx, double usy,
+                               double id_s, const double n[3], double ux, double uy) {
+    double rs[3], ru[3], ps[3];
+    sgo_ray(K, usx, usy, rs);
+    sgo_ray(K, ux, uy, ru);
+    ps[0] = rs[0] / id_s; ps[1] = rs[1] / id_s; ps[2] = rs[2] / id_s;  /* Eq. 1 */
+    return dot3(ru, n) / dot3(ps, n);
+}
+
+/* Eq. 6: X = r_u / id_u, X_n = R X + t, u_p = pi(K X_n). */
+static int warp_point(const sgo_intrinsics* K, const sgo_pose* P, const double ru[3],
+                      double id_u, double Xn[3], double uv[2]) {
+    double X[3] = {ru[0] / id_u, ru[1] / id_u, ru[2] / id_u};
+    for (int i = 0; i < 3; ++i)
+        Xn[i] = P->R[3 * i] * X[0] + P->R[3 * i + 1] * X[1] + P->R[3 * i + 2] * X[2] + P->t[i];
+    if (!(Xn[2] > 0.0)) return 0;
+    uv[0] = K->fx * Xn[0] / Xn[2] + K->cx;
+    uv[1] = K->fy * Xn[1] / Xn[2] + K->cy;
+    return 1;
+}
+
+int sgo_warp(const sgo_intrinsics* K, const sgo_pose* P, double ux, double uy,
+             double id_u, double uv[2]) {
+    double ru[3], Xn[3];
+    sgo_ray(K, ux, uy, ru);
+    return warp_point(K, P, ru, id_u, Xn, uv);
+}
+
+/* Bilinear interpolation of the four pixels around (x, y) and the exact
+ * derivative of that interpolant (the image gradient nabla I_fn of Eq. 8). */
+int sgo_bilinear(const sgo_image* I, double x, double y, double out[3]) {
+    if (!(x >= 0.0 && y >= 0.0 && x < (double)(I->width - 1) && y < (double)(I->height - 1)))
+        return 0;
+    int x0 = (int)floor(x), y0 = (int)floor(y);
+    double ax = x - x0, ay = y - y0;
+    const double* row0 = I->pix + (size_t)y0 * I->width;
+    const double* row1 = row0 + I->width;
+    double i00 = row0[x0], i01 = row0[x0 + 1], i10 = row1[x0], i11 = row1[x0 + 1];
+    double top = i00 + ax * (i01 - i00);
+    double bot = i10 + ax * (i11 - i10);
+    out[0] = top + ay * (bot - top);
+    out[1] = (i01 - i00) + ay * ((i11 - i10) - (i01 - i00));
+    out[2] = bot - top;
+    return 1;
+}
+
+void sgo_tangent_basis(const double n[3], double b1[3], double b2[3]) {
+    double e[3] = {0.0, 0.0, 0.0};
+    if (fabs(n[0]) < 0.9) e[0] = 1.0; else e[1] = 1.0;
+    double en = dot3(e, n);
+    b1[0] = e[0] - en * n[0]; b1[1] = e[1] - en * n[1]; b1[2] = e[2] - en * n[2];
+    normalize3(b1);
+    cross3(n, b1, b2);
+}
+
+/* Huber norm of Eq. 5 and its IRLS weight w (Eq. 8: dC/dI_f = w r). */
+static double huber_rho(double r, double k) {
+    double a = fabs(r);
+    return a <= k ? 0.5 * r * r : k * a - 0.5 * k * k;
+}
+static double huber_w(double r, double k) {
+    double a = fabs(r);
+    return a <= k ? 1.0 : k / a;
+}
+
+/* Residual and Jacobian row of one (pixel, frame) sample, by the chain rule
+ * of Eq. 7-9:
+ *   dr/dtheta = nabla I_fn(u_p) * dpi/dq * dq/did_u * did_u/dtheta
+ * with did_u/did_s from Eq. 9 (correct as printed) and did_u/dn_s the exact
+ * derivative of Eq. 3 (the printed form collapses to zero; reading:
+ * id_s (r_u (n.r_s) - r_s (n.r_u)) / (n.r_s)^2), projected on the tangent
+ * basis because the normal is updated and then renormalised. */
+int sgo_eval_sample(const sgo_intrinsics* K, const sgo_pose* P, const sgo_image* In,
+                    double kf_value, double usx, double usy, double ux, double uy,
+                    double id_s, const double n[3], int depth_only,
+                    double* r, double J[3]) {
+    double rs[3], ru[3];
+    sgo_ray(K, usx, usy, rs);
+    sgo_ray(K, ux, uy, ru);
+    double ps[3] = {rs[0] / id_s, rs[1] / id_s, rs[2] / id_s};  /* Eq. 1 */
+    double ru_n = dot3(ru, n), rs_n = dot3(rs, n);
+    double id_u = ru_n / dot3(ps, n);                            /* Eq. 3 */
+    if (!(id_u > 0.0) || !isfinite(id_u)) return 0;
+    double Xn[3], uv[2];
+    if (!warp_point(K, P, ru, id_u, Xn, uv)) return 0;           /* Eq. 6 */
+    double s[3];
+    if (!sgo_bilinear(In, uv[0], uv[1], s)) return 0;
+    *r = s[0] - kf_value;
+    /* Eq. 8 chain with the projection read as pi(q), where q is the point's
+     * homogeneous pixel K X_n scaled by id_u (pi is scale invariant):
+     *   q = id_u K X_n = K R r_u + id_u K t,   so  dq/did_u = K t
+     * (the printed du_p/did_u is the derivative with respect to depth, not
+     * inverse depth), and dpi/dq = (1/q_z) [[1, 0, -u_x], [0, 1, -u_y]]
+     * (the printed matrix repeats -u_y and drops 1/q_z). */
+    double Kt[3] = {K->fx * P->t[0] + K->cx * P->t[2], K->fy * P->t[1] + K->cy * P->t[2], P->t[2]};
+    double qz = id_u * Xn[2];
+    double du[2];
+    du[0] = (Kt[0] - uv[0] * Kt[2]) / qz;
+    du[1] = (Kt[1] - uv[1] * Kt[2]) / qz;
+    double dr_did_u = s[1] * du[0] + s[2] * du[1];               /* Eq. 8 */
+    /* Eq. 9 */
+    double did_dids = ru_n / rs_n;
+    double dn[3];
+    for (int i = 0; i < 3; ++i)
+        dn[i] = id_s * (ru[i] * rs_n - rs[i] * ru_n) / (rs_n * rs_n);
+    double b1[3], b2[3];
+    sgo_tangent_basis(n, b1, b2);
+    J[0] = dr_did_u * did_dids;
+    if (depth_only) {
+        J[1] = 0.0;
+        J[2] = 0.0;
+    } else {
+        J[1] = dr_did_u * dot3(dn, b1);
+        J[2] = dr_did_u * dot3(dn, b2);
+    }
+    return 1;
+}
+
+static void tile_centre(const sgo_keyframe* kf, int32_t tx, int32_t ty, double* x, double* y) {
+    int S = kf->patch;
+    *x = S * tx + 0.5 * (S - 1);
+    *y = S * ty + 0.5 * (S - 1);
+}
+
+int32_t sgo_linearize(const sgo_keyframe* kf, int32_t tx, int32_t ty, double id_s,
+                      const double n[3], double huber_k, int depth_only,
+                      double H[9], double b[3], double* cost) {
+    int S = kf->patch;
+    double usx, usy;
+    tile_centre(kf, tx, ty, &usx, &usy);
+    memset(H, 0, 9 * sizeof(double));
+    memset(b, 0, 3 * sizeof(double));
+    *cost = 0.0;
+    int32_t nvalid = 0;
+    for (int py = 0; py < S; ++py) {
+        for (int px = 0; px < S; ++px) {
+            int ux = S * tx + px, uy = S * ty + py;
+            double ikf = kf->kf.pix[(size_t)uy * kf->kf.width + ux];
+            for (int f = 0; f < kf->n_nbr; ++f) {               /* sum over Omega */
+                double r, J[3];
+                if (!sgo_eval_sample(&kf->K, &kf->pose[f], &kf->nbr[f], ikf, usx, usy,
+                                     (double)ux, (double)uy, id_s, n, depth_only, &r, J))
+                    continue;
+                double w = huber_w(r, huber_k);
+                for (int i = 0; i < 3; ++i) {
+                    for (int j = 0; j < 3; ++j) H[3 * i + j] += w * J[i] * J[j];
+                    b[i] += w * J[i] * r;
+                }
+                *cost += huber_rho(r, huber_k);
+                ++nvalid;
+            }
+        }
+    }
+    return nvalid;
+}
+
+/* Textbook Cholesky H = L L^T, then forward/back substitution for
+ * H delta = -b.  A pivot <= 1e-12 * max diag(H) means "not positive
+ * definite". */
+uint32_t sgo_solve3(const double H[9], const double b[3], double delta[3]) {
+    double L[3][3] = {{0}};
+    double maxd = fmax(H[0], fmax(H[4], H[8]));
+    if (!(maxd > 0.0) || !isfinite(maxd)) return SGO_SOLVE_FAIL;
+    double tol = 1e-12 * maxd;
+    for (int j = 0; j < 3; ++j) {
+        double d = H[3 * j + j];
+        for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+        if (!(d > tol) || !isfinite(d)) return SGO_SOLVE_FAIL;
+        L[j][j] = sqrt(d);
+        for (int i = j + 1; i < 3; ++i) {
+            double v = H[3 * i + j];
+            for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+            L[i][j] = v / L[j][j];
+        }
+    }
+    double y[3];
+    for (int i = 0; i < 3; ++i) {
+        double v = -b[i];
+        for (int k = 0; k < i; ++k) v -= L[i][k] * y[k];
+        y[i] = v / L[i][i];
+    }
+    for (int i = 2; i >= 0; --i) {
+        double v = y[i];
+        for (int k = i + 1; k < 3; ++k) v -= L[k][i] * delta[k];
+        delta[i] = v / L[i][i];
+    }
+    return 0;
+}
+
+/* Eigenvalues of a symmetric 3x3 matrix by cyclic Jacobi rotations. */
+static void sym_eig3(const double A_in[9], double ev[3]) {
+    double A[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) A[i][j] = A_in[3 * i + j];
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+        double diag = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+        if (off <= 1e-34 * diag || off == 0.0) break;
+        for (int p = 0; p < 2; ++p) {
+            for (int q = p + 1; q < 3; ++q) {
+                if (A[p][q] == 0.0) continue;
+                double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < 3; ++k) {   /* A <- A J */
+                    double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = c * akp - s * akq;
+                    A[k][q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < 3; ++k) {   /* A <- J^T A */
+                    double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = c * apk - s * aqk;
+                    A[q][k] = s * apk + c * aqk;
+                }
+            }
+        }
+    }
+    ev[0] = A[0][0]; ev[1] = A[1][1]; ev[2] = A[2][2];
+}
+
+double sgo_kappa_eq(const double H[9]) {
+    double d[3];
+    for (int i = 0; i < 3; ++i) {
+        if (!(H[4 * i] > 0.0) || !isfinite(H[4 * i])) return INFINITY;
+        d[i] = 1.0 / sqrt(H[4 * i]);
+    }
+    double E[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) E[3 * i + j] = d[i] * H[3 * i + j] * d[j];
+    double ev[3];
+    sym_eig3(E, ev);
+    double lo = fmin(ev[0], fmin(ev[1], ev[2])), hi = fmax(ev[0], fmax(ev[1], ev[2]));
+    if (!(lo > 0.0)) return INFINITY;
+    return hi / lo;
+}
+
+/* Normal update with three components then renormalisation (Surfel
+ * Optimization section): the tangent step (alpha_1, alpha_2) is the 3-DOF
+ * step n + a1 b1 + a2 b2, renormalised. */
+static int apply_update(double id_s, const double n[3], const double b1[3], const double b2[3],
+                        const double delta[3], double* id_new, double n_new[3]) {
+    *id_new = id_s + delta[0];
+    for (int i = 0; i < 3; ++i) n_new[i] = n[i] + delta[1] * b1[i] + delta[2] * b2[i];
+    if (!normalize3(n_new)) return 0;
+    if (!(*id_new > 0.0) || !isfinite(*id_new)) return 0;
+    return 1;
+}
+
+static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_params* p, int32_t i) {
+    int S = kf->patch;
+    int gw = kf->kf.width / S;
+    int tx = i % gw, ty = i / gw;
+    double usx, usy, rs[3];
+    tile_centre(kf, tx, ty, &usx, &usy);
+    sgo_ray(&kf->K, usx, usy, rs);
+    double id_s = s->inv_depth[i];
+    double n[3] = {s->nx[i], s->ny[i], s->nz[i]};
+    uint32_t flags = s->flags[i] & ~(uint32_t)(SGO_DEGENERATE | SGO_FEW_SAMPLES | SGO_SOLVE_FAIL |
+                                              SGO_REJECTED | SGO_FP64_SOLVE);
+    double cost = 0.0, kappa = 0.0;
+    int32_t nvalid = 0;
+    int updated = 0;
+    double lambda = p->lm_lambda;
+    for (int it = 0; it < p->iters; ++it) {
+        if (fabs(dot3(n, rs)) < 1e-6) {           /* Eq. 3 undefined */
+            flags |= SGO_DEGENERATE;
+            cost = 0.0;
+            nvalid = 0;
+            break;
+        }
+        double b1[3], b2[3];
+        sgo_tangent_basis(n, b1, b2);
+        double H[9], b[3];
+        nvalid = sgo_linearize(kf, tx, ty, id_s, n, p->huber_k, p->depth_only, H, b, &cost);
+        kappa = p->depth_only ? 1.0 : sgo_kappa_eq(H);
+        double delta[3] = {0.0, 0.0, 0.0};
+        if (nvalid < 3) {
+            flags |= SGO_FEW_SAMPLES;
+            continue;
+        }
+        double Hs[9];
+        memcpy(Hs, H, sizeof(Hs));
+        if (lambda > 0.0)                          /* Levenberg-Marquardt damping */
+            for (int k = 0; k < 3; ++k) Hs[4 * k] *= 1.0 + lambda;
+        if (p->depth_only) {
+            if (!(Hs[0] > 0.0) || !isfinite(Hs[0])) {
+                flags |= SGO_SOLVE_FAIL;
+                continue;
+            }
+            delta[0] = -b[0] / Hs[0];
+        } else {
+            uint32_t st = sgo_solve3(Hs, b, delta);
+            if (st) {
+                flags |= st;
+                continue;
+            }
+        }
+        double id_new, n_new[3];
+        if (!apply_update(id_s, n, b1, b2, delta, &id_new, n_new)) {
+            flags |= SGO_REJECTED;
+            if (lambda > 0.0) lambda *= 10.0;
+            continue;
+        }
+        if (lambda > 0.0) {
+            /* accept only if the mean Huber cost does not increase */
+            double H2[9], b2v[3], cost2;
+            int32_t nv2 = sgo_linearize(kf, tx, ty, id_new, n_new, p->huber_k, p->depth_only,
+                                        H2, b2v, &cost2);
+            if (nv2 < 3 || cost2 / nv2 > cost / nvalid) {
+                lambda *= 10.0;
+                continue;
+            }
+            lambda = fmax(lambda * 0.1, 1e-9);
+        }
+        id_s = id_new;
+        n[0] = n_new[0]; n[1] = n_new[1]; n[2] = n_new[2];
+        updated = 1;
+    }
+    s->inv_depth[i] = id_s;
+    s->nx[i] = n[0]; s->ny[i] = n[1]; s->nz[i] = n[2];
+    s->flags[i] = flags;
+    s->cost[i] = cost;
+    s->nvalid[i] = nvalid;
+    if (s->kappa) s->kappa[i] = kappa;
+    if (updated) s->last_update[i] = p->stamp;
+}
+
+int sgo_optimize_keyframe(const sgo_keyframe* kf, sgo_surfels* s, const sgo_params* p,
+                          const int32_t* subset, int32_t n_subset) {
+    if (!kf || !s || !p || kf->patch <= 0) return -1;
+    int S = kf->patch;
+    int32_t total = (kf->kf.width / S) * (kf->kf.height / S);
+    int32_t count = subset ? n_subset : total;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int32_t k = 0; k < count; ++k) {
+        int32_t i = subset ? subset[k] : k;
+        if (i >= 0 && i < total) optimize_one(kf, s, p, i);
+    }
+    return 0;
+}
+
+/* Surfel Initialization section.  Neighbours of a new surfel at centre u_ns
+ * are the surfels (not new, not flagged unusable) that own at least one pixel
+ * closer than beta r to u_ns.  The new inverse depth is the mean over them of
+ * Eq. 3 evaluated with the neighbour's plane at the new surfel's ray; the new
+ * normal is the mean of their normals (sign-aligned to the first neighbour in
+ * index order), renormalised. */
+static void init_one(const sgo_keyframe* kf, sgo_surfels* s, const uint8_t* is_new,
+                     const sgo_params* p, int32_t i) {
+    int S = kf->patch;
+    int gw = kf->kf.width / S, gh = kf->kf.height / S;
+    int tx = i % gw, ty = i / gw;
+    double ux, uy;
+    tile_centre(kf, tx, ty, &ux, &uy);
+    double br = p->beta_r;
+    int reach = (int)ceil(br / S) + 1;
+    double id_sum = 0.0, nsum[3] = {0.0, 0.0, 0.0}, nref[3] = {0.0, 0.0, 0.0};
+    int count = 0;
+    for (int ny = ty - reach; ny <= ty + reach; ++ny) {
+        for (int nx = tx - reach; nx <= tx + reach; ++nx) {
+            if (nx < 0 || ny < 0 || nx >= gw || ny >= gh) continue;
+            int32_t j = ny * gw + nx;
+            if (j == i || is_new[j]) continue;
+            if (s->flags[j] & (SGO_UNINIT | SGO_DEGENERATE)) continue;
+            /* does surfel j own a pixel within beta r of u_ns? */
+            int near = 0;
+            for (int py = 0; py < S && !near; ++py)
+                for (int px = 0; px < S && !near; ++px) {
+                    double dx = (S * nx + px) - ux, dy = (S * ny + py) - uy;
+                    if (sqrt(dx * dx + dy * dy) < br) near = 1;
+                }
+            if (!near) continue;
+            double nj[3] = {s->nx[j], s->ny[j], s->nz[j]};
+            double jx, jy, rj[3];
+            tile_centre(kf, nx, ny, &jx, &jy);
+            sgo_ray(&kf->K, jx, jy, rj);
+            if (fabs(dot3(nj, rj)) < 1e-6) continue;
+            /* Eq. 3 with the neighbour's plane, at the new surfel's pixel */
+            double id = sgo_pixel_inverse_depth(&kf->K, jx, jy, s->inv_depth[j], nj, ux, uy);
+            if (count == 0) { nref[0] = nj[0]; nref[1] = nj[1]; nref[2] = nj[2]; }
+            double sg = dot3(nj, nref) < 0.0 ? -1.0 : 1.0;
+            id_sum += id;
+            for (int k = 0; k < 3; ++k) nsum[k] += sg * nj[k];
+            ++count;
+        }
+    }
+    if (count == 0) {
+        s->flags[i] |= SGO_UNINIT;
+        return;
+    }
+    double id_new = id_sum / count;
+    double n_new[3] = {nsum[0] / count, nsum[1] / count, nsum[2] / count};
+    if (!normalize3(n_new) || !(id_new > 0.0) || !isfinite(id_new)) {
+        s->flags[i] |= SGO_UNINIT;
+        return;
+    }
+    s->inv_depth[i] = id_new;
+    s->nx[i] = n_new[0]; s->ny[i] = n_new[1]; s->nz[i] = n_new[2];
+    s->flags[i] &= ~(uint32_t)SGO_UNINIT;
+}
+
+int sgo_init_from_neighbours(const sgo_keyframe* kf, sgo_surfels* s, const uint8_t* is_new,
+                             const sgo_params* p, const int32_t* subset, int32_t n_subset) {
+    if (!kf || !s || !is_new || !p || kf->patch <= 0) return -1;
+    int S = kf->patch;
+    int32_t total = (kf->kf.width / S) * (kf->kf.height / S);
+    int32_t count = subset ? n_subset : total;
+    /* New surfels read only non-new ones, so the order does not matter. */
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int32_t k = 0; k < count; ++k) {
+        int32_t i = subset ? subset[k] : k;
+        if (i >= 0 && i < total && is_new[i]) init_one(kf, s, is_new, p, i);
+    }
+    return 0;
+}
+
+/* Inverse Depth Calculation section: each pixel takes Eq. 3 of the surfel
+ * that owns it (tiles do not overlap, so no depth test is needed). */
+int sgo_render_inverse_depth(const sgo_keyframe* kf, const sgo_surfels* s,
+                             double* inv_depth, int32_t* surfel_index) {
+    int W = kf->kf.width, H = kf->kf.height, S = kf->patch;
+    int gw = W / S, gh = H / S;
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            size_t o = (size_t)y * W + x;
+            inv_depth[o] = 0.0;
+            if (surfel_index) surfel_index[o] = -1;
+            int tx = x / S, ty = y / S;
+            if (tx >= gw || ty >= gh) continue;
+            int32_t i = ty * gw + tx;
+            if (s->flags[i] & (SGO_DEGENERATE | SGO_UNINIT)) continue;
+            double n[3] = {s->nx[i], s->ny[i], s->nz[i]};
+            double usx, usy, rs[3];
+            tile_centre(kf, tx, ty, &usx, &usy);
+            sgo_ray(&kf->K, usx, usy, rs);
+            if (fabs(dot3(n, rs)) < 1e-6) continue;
+            double id = sgo_pixel_inverse_depth(&kf->K, usx, usy, s->inv_depth[i], n, x, y);
+            if (!(id > 0.0) || !isfinite(id)) continue;
+            inv_depth[o] = id;
+            if (surfel_index) surfel_index[o] = i;
+        }
+    }
+    return 0;
+}
+
+/* Eq. 10: p' = P p (p = r_s / id_s by Eq. 1), n' = R n, r' = pi(p'). */
+int sgo_transfer_surfels(const sgo_intrinsics* K, const sgo_pose* P, int32_t count,
+                         const double* usx, const double* usy, const double* id_s,
+                         const double* n, double* ux_out, double* uy_out,
+                         double* id_out, double* n_out) {
+    int ok = 0;
+    for (int32_t k = 0; k < count; ++k) {
+        double rs[3], p0[3], p1[3];
+        sgo_ray(K, usx[k], usy[k], rs);
+        for (int i = 0; i < 3; ++i) p0[i] = rs[i] / id_s[k];
+        for (int i = 0; i < 3; ++i)
+            p1[i] = P->R[3 * i] * p0[0] + P->R[3 * i + 1] * p0[1] + P->R[3 * i + 2] * p0[2] + P->t[i];
+        for (int i = 0; i < 3; ++i)
+            n_out[3 * k + i] = P->R[3 * i] * n[3 * k] + P->R[3 * i + 1] * n[3 * k + 1] +
+                               P->R[3 * i + 2] * n[3 * k + 2];
+        if (!(p1[2] > 0.0)) {
+            ux_out[k] = uy_out[k] = 0.0;
+            id_out[k] = 0.0;
+            continue;
+        }
+        double r1[3] = {p1[0] / p1[2], p1[1] / p1[2], 1.0};   /* pi(p') */
+        ux_out[k] = K->fx * r1[0] + K->cx;
+        uy_out[k] = K->fy * r1[1] + K->cy;
+        id_out[k] = 1.0 / p1[2];
+        ++ok;
+    }
+    return ok;
+}
+
+void sgo_set_threads(int32_t n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int32_t sgo_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

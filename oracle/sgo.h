@@ -1,0 +1,140 @@
+/*
+ * sgo.h -- plain FP64 CPU oracle of the per-surfel Gauss-Newton update.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library includes, links
+ * or calls this code; only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no source with the HIP path.
+ *
+ * Paper: "Dense monocular SLAM by direct surfel optimization" (Trabes,
+ * Dondo Gazzano, Sosa Paez).  Section and equation numbers below are the
+ * paper's.  All arithmetic is IEEE double, no fast-math, no reordering
+ * beyond what the equations state.
+ *
+ * Conventions (where the paper is silent; each is a stated reading):
+ *   - camera x right, y down, z forward; pixel (x, y) has its centre at
+ *     integer coordinates and homogeneous form u~ = (x, y, 1);
+ *   - a keyframe is tiled into S x S surfels; tile (tx, ty) owns pixels
+ *     [S tx, S tx + S) x [S ty, S ty + S) and its centre pixel is
+ *     u_s = (S tx + (S-1)/2, S ty + (S-1)/2); r_s = K^-1 u~_s (z = 1);
+ *   - a pose P_kf^fn is stored as X_n = R X_kf + t with R row-major;
+ *   - images are row-major doubles, width entries per row.
+ */
+#ifndef SGO_H
+#define SGO_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double fx, fy, cx, cy; } sgo_intrinsics;
+typedef struct { double R[9]; double t[3]; } sgo_pose;
+typedef struct { const double* pix; int32_t width, height; } sgo_image;
+
+typedef struct {
+    sgo_image kf;             /* I_kf */
+    const sgo_image* nbr;     /* I_fn, n = 0 .. n_nbr-1 (the group Omega) */
+    const sgo_pose* pose;     /* P_kf^fn */
+    int32_t n_nbr;
+    sgo_intrinsics K;
+    int32_t patch;            /* S */
+} sgo_keyframe;
+
+/* Surfel grid, structure of arrays, length gw*gh, index ty*gw + tx. */
+typedef struct {
+    double* inv_depth;        /* id_s */
+    double* nx; double* ny; double* nz;  /* n_s */
+    uint32_t* flags;
+    double* cost;             /* Huber cost at the last linearisation point */
+    int32_t* nvalid;          /* valid (pixel, frame) samples at that point */
+    uint32_t* last_update;
+    double* kappa;            /* optional (may be NULL): cond_2 of the equilibrated J^T J */
+} sgo_surfels;
+
+typedef struct {
+    int32_t iters;            /* Gauss-Newton iterations */
+    double huber_k;           /* Huber threshold (intensity units) */
+    int32_t depth_only;       /* ablation: d id_u / d n_s := 0 */
+    double beta_r;            /* neighbour radius for initialisation (pixels) */
+    uint32_t stamp;           /* written to last_update */
+    double lm_lambda;         /* 0: pure Gauss-Newton; >0: Levenberg-Marquardt start damping */
+} sgo_params;
+
+enum {
+    SGO_DEGENERATE  = 1u << 0,  /* |n_s . r_s| < 1e-6: plane through the camera centre */
+    SGO_FEW_SAMPLES = 1u << 1,  /* fewer than 3 valid samples */
+    SGO_SOLVE_FAIL  = 1u << 2,  /* J^T J not positive definite */
+    SGO_REJECTED    = 1u << 3,  /* update non-finite or id_s <= 0 */
+    SGO_FP64_SOLVE  = 1u << 4,  /* (device only) solved in double */
+    SGO_UNINIT      = 1u << 5   /* no neighbour available for initialisation */
+};
+
+/* Eq. 2 ray r_u = K^-1 pi^-1(u) for pixel (x, y). */
+void sgo_ray(const sgo_intrinsics* K, double x, double y, double r[3]);
+
+/* Eq. 3: inverse depth of pixel u on the plane of a surfel (centre pixel us,
+ * inverse depth id_s, normal n). */
+double sgo_pixel_inverse_depth(const sgo_intrinsics* K, double usx, double usy,
+                               double id_s, const double n[3], double ux, double uy);
+
+/* Eq. 6: coordinates u_p in frame n of keyframe pixel u at inverse depth id_u.
+ * Returns 0 when the point is not in front of the frame's camera. */
+int sgo_warp(const sgo_intrinsics* K, const sgo_pose* P, double ux, double uy,
+             double id_u, double uv[2]);
+
+/* Bilinear interpolant of an image and its exact gradient at (x, y).
+ * out = {value, d/dx, d/dy}.  Returns 0 outside 0 <= x < w-1, 0 <= y < h-1. */
+int sgo_bilinear(const sgo_image* I, double x, double y, double out[3]);
+
+/* Orthonormal tangent basis of a unit normal. */
+void sgo_tangent_basis(const double n[3], double b1[3], double b2[3]);
+
+/* One sample: residual r = I_fn(u_p) - I_kf(u) and its Jacobian row with
+ * respect to (id_s, alpha_1, alpha_2), where n(alpha) = normalise(n + a1 b1 +
+ * a2 b2).  Returns 1 when the sample is valid. */
+int sgo_eval_sample(const sgo_intrinsics* K, const sgo_pose* P, const sgo_image* In,
+                    double kf_value, double usx, double usy, double ux, double uy,
+                    double id_s, const double n[3], int depth_only,
+                    double* r, double J[3]);
+
+/* Huber IRLS normal equations of one surfel at its current state.
+ * H is 3x3 row-major.  Returns the number of valid samples. */
+int32_t sgo_linearize(const sgo_keyframe* kf, int32_t tx, int32_t ty, double id_s,
+                      const double n[3], double huber_k, int depth_only,
+                      double H[9], double b[3], double* cost);
+
+/* Cholesky solve of H delta = -b; returns 0 on success, SGO_SOLVE_FAIL when a
+ * pivot is <= 1e-12 * max diag (or not finite). */
+uint32_t sgo_solve3(const double H[9], const double b[3], double delta[3]);
+
+/* 2-norm condition number of D^-1/2 H D^-1/2, D = diag(H) (inf if singular). */
+double sgo_kappa_eq(const double H[9]);
+
+/* Gauss-Newton over all surfels (subset == NULL) or the listed surfel indices. */
+int sgo_optimize_keyframe(const sgo_keyframe* kf, sgo_surfels* s, const sgo_params* p,
+                          const int32_t* subset, int32_t n_subset);
+
+/* Neighbour-plane initialisation of surfels with is_new[i] != 0. */
+int sgo_init_from_neighbours(const sgo_keyframe* kf, sgo_surfels* s, const uint8_t* is_new,
+                             const sgo_params* p, const int32_t* subset, int32_t n_subset);
+
+/* Per-pixel inverse depth (0 = no measurement) and owning surfel (-1 = none). */
+int sgo_render_inverse_depth(const sgo_keyframe* kf, const sgo_surfels* s,
+                             double* inv_depth, int32_t* surfel_index);
+
+/* Eq. 10: move surfels of keyframe kf0 into keyframe kf1 (pose X1 = R X0 + t).
+ * For each input surfel (ray r_s, id_s, n) returns the transformed point's
+ * pixel (x, y), inverse depth and rotated normal.  Returns count of surfels in
+ * front of the new camera (others get id = 0). */
+int sgo_transfer_surfels(const sgo_intrinsics* K, const sgo_pose* P, int32_t count,
+                         const double* usx, const double* usy, const double* id_s,
+                         const double* n, double* ux_out, double* uy_out,
+                         double* id_out, double* n_out);
+
+void sgo_set_threads(int32_t n);
+int32_t sgo_max_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
