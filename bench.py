@@ -1,0 +1,243 @@
+"""Benchmark of the surfel Gauss-Newton hot path on one MI355X.
+
+A step is one pass of the whole path over one batch: neighbour-plane
+initialisation of the new surfels, the fused Gauss-Newton iterations of
+every surfel of every keyframe, and the per-pixel inverse-depth render, for
+the 64-keyframe mixed-resolution batch (320x240 / 640x480 / 1280x720, 4-12
+neighbour frames each, 4x4 surfels, 15 iterations) with images stored as
+FP16.  Inputs are synthetic and resident in HBM before timing starts.
+
+Prints one JSON line: metric, value (surfel-frame GN updates per second),
+the roofline of the fused GN kernel (timed with HIP events on its own
+stream), and the FP64 oracle timed on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "surfel·frame GN updates/s (% roofline) + p50/p99 keyframe latency, served vs plain"
+UNIT = "surfel-frame updates/s"
+
+# Algorithmic VALU work per sample (one pixel of one surfel against one
+# neighbour frame in one iteration), counted from the method's arithmetic:
+# warp 9, perspective divide 3, validity 5, bilinear index 6, bilinear value
+# and gradient 8, residual 1, Huber weight 3, chain factor 5, accumulation 4.
+OPS_PER_SAMPLE = 44
+# FP32 flops per sample (an FMA counts 2), same inventory.
+FLOPS_PER_SAMPLE = 50
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz VALU lane-operations per second
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+FP32_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--storage", default="f16", choices=["f32", "f16", "u8"])
+    ap.add_argument("--keyframes", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--autotune", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(keyframes shard across GPUs with no exchange; see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr, flush=True)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1910_01997_amd import engine
+    from paper_1910_01997_amd import surfgn as sg
+    from scenegen import make_keyframe, spec_for_config
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    info = sg.sgn_device_info(0)
+    log("device", info)
+    ctx = sg.Context(0)
+    iters = 15
+    t0 = time.time()
+    kfs = [make_keyframe(spec_for_config(2, i), device="cuda") for i in range(args.keyframes)]
+    dks = [engine.DeviceKeyframe.from_scene(ctx, k, storage=args.storage) for k in kfs]
+    torch.cuda.synchronize()
+    log(f"generated {len(dks)} keyframes in {time.time() - t0:.1f}s")
+    init_state = [d.state.clone() for d in dks]
+    prm = sg.params(iters=iters)
+    surfel_frames = sum(d.n_surfels * d.n_nbr for d in dks) * iters
+    samples = sum(d.n_surfels * d.n_nbr * d.patch * d.patch for d in dks) * iters
+    plan = None
+    if args.autotune:
+        items = sg.batch_array([d.item(render=False, init=False) for d in dks])
+        plan = sg.sgn_autotune(ctx.handle, items, len(dks), prm)
+        log("autotuned plan", plan.as_dict())
+
+    def restore():
+        for d, s0 in zip(dks, init_state):
+            for a, b in ((d.state.inv_depth, s0.inv_depth), (d.state.nx, s0.nx), (d.state.ny, s0.ny),
+                         (d.state.nz, s0.nz), (d.state.flags, s0.flags)):
+                a.copy_(b, non_blocking=True)
+
+    def step():
+        restore()
+        engine.update_batch(ctx, dks, prm, plan)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    kernel_ms = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        kernel_ms.append(sg.sgn_last_kernel_ms(ctx.handle))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = surfel_frames / (ms_per_step * 1e-3)
+    gn_ms = float(np.mean(kernel_ms))
+    ops = samples * OPS_PER_SAMPLE
+    achieved = ops / (gn_ms * 1e-3) / 1e12
+    flops = samples * FLOPS_PER_SAMPLE / (gn_ms * 1e-3) / 1e12
+    # compulsory HBM bytes per launch: every image once, surfel state read + written
+    img_bytes = sum((d.n_nbr + 1) * d.width * d.height * d.kf_img.element_size() for d in dks)
+    state_bytes = sum(d.n_surfels for d in dks) * (16 + 16 + 12)
+    hbm_gbs = (img_bytes + state_bytes) / (gn_ms * 1e-3) / 1e9
+    log(f"steps {args.steps}: {ms_per_step:.3f} ms/step, GN kernel {gn_ms:.3f} ms "
+        f"(min {min(kernel_ms):.3f}), {value:.4e} surfel-frame/s, {samples / (gn_ms * 1e-3):.4e} samples/s")
+
+    plain = None
+    if not args.no_plain:
+        # the plain single-keyframe form on the same batch, one keyframe at a time
+        restore()
+        torch.cuda.synchronize()
+        for d in dks[:4]:
+            engine.update_plain(ctx, d, prm)
+        torch.cuda.synchronize()
+        restore()
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for d in dks:
+            engine.update_plain(ctx, d, prm)
+        torch.cuda.synchronize()
+        plain_s = time.perf_counter() - tp
+        plain = {"value": surfel_frames / plain_s, "ms_per_batch": plain_s * 1e3,
+                 "form": "per-keyframe calls: init + non-persistent GN launch + render"}
+        log(f"plain form: {plain_s * 1e3:.3f} ms per batch, {surfel_frames / plain_s:.4e} surfel-frame/s")
+
+    traffic = None
+    prof = os.path.join(ROOT, "profiles", "gn_kernel_traffic.json")
+    if os.path.exists(prof):
+        try:
+            from paper_1910_01997_amd import build as hb
+            rec = json.load(open(prof))
+            if rec.get("kernel_source_sha256") == hb.kernel_source_hash() and \
+                    rec.get("storage") == args.storage and rec.get("keyframes") == args.keyframes:
+                traffic = rec.get("hbm_bytes_per_launch")
+        except Exception as e:  # a stale or unreadable summary gives null
+            log("traffic summary unusable:", e)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(dks, kfs, iters, args.cpu_seconds)
+    ctx.close()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batch of {len(dks)} keyframes, mixed 320x240/640x480/1280x720, 4-12 "
+                        f"neighbour frames, 4x4 surfels, {iters} GN iterations, "
+                        f"{args.storage} image storage, half the surfels initialised from neighbours",
+            "keyframes": len(dks), "surfels": int(sum(d.n_surfels for d in dks)),
+            "surfel_frames_per_step": int(surfel_frames), "samples_per_step": int(samples),
+            "image_storage": args.storage, "iterations": iters,
+            "plan": plan.as_dict() if plan is not None else "default",
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": VALU_PEAK_TOPS,
+            "unit": "Tops/s (FP32 VALU lane-operations)",
+            "frac": achieved / VALU_PEAK_TOPS,
+            "traffic": traffic,
+            "kernel": "gn_kernel",
+            "kernel_ms": gn_ms,
+            "ops_per_sample": OPS_PER_SAMPLE,
+            "flop_view": {"achieved_tflops": flops, "peak_tflops": FP32_PEAK_TFLOPS,
+                          "frac": flops / FP32_PEAK_TFLOPS},
+            "hbm_view": {"achieved_gbs": hbm_gbs, "peak_gbs": HBM_PEAK_GBS,
+                         "frac": hbm_gbs / HBM_PEAK_GBS},
+        },
+        "cpu_baseline": cpu,
+        "plain_form": plain,
+        "device": {"name": info["name"], "arch": info["arch"], "cus": info["compute_units"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(dks, kfs, iters, budget_s):
+    """The FP64 oracle, as it stands, on a bounded sample of the same batch:
+    whole keyframes' surfels in a random subset, timed on all host threads."""
+    import numpy as np
+
+    import oracle
+
+    threads = oracle.max_threads()
+    rng = np.random.default_rng(12345)
+    done_sf = 0
+    spent = 0.0
+    used = []
+    order = rng.permutation(len(dks))
+    for j in order:
+        d, k = dks[j], kfs[j]
+        kimg, nimg = d.dequantized_images()
+        okf = oracle.OracleKeyframe(d.K, kimg, nimg, d.R, d.t, d.patch)
+        st = oracle.new_state(np.asarray(k.init_id, np.float32).astype(np.float64),
+                              np.asarray(k.init_n, np.float32).astype(np.float64))
+        prm = oracle.OracleParams(iters=iters)
+        m = d.n_surfels
+        take = min(m, 4096)
+        sub = np.sort(rng.choice(m, size=take, replace=False)).astype(np.int32)
+        t = time.perf_counter()
+        oracle.init_from_neighbours(okf, st, k.is_new, prm, subset=sub)
+        oracle.optimize(okf, st, prm, subset=sub)
+        spent += time.perf_counter() - t
+        done_sf += take * d.n_nbr * iters
+        used.append(f"kf{j}:{take}/{m}")
+        if spent >= budget_s:
+            break
+    return {"value": done_sf / spent, "unit": UNIT, "cores": int(threads), "kind": "oracle",
+            "sample": f"{len(used)} keyframes of the batch, up to 4096 random surfels each "
+                      f"({done_sf} surfel-frame updates, {spent:.1f}s); " + ",".join(used[:8])}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,232 @@
+/*
+ * surfgn.h -- C ABI of the MI355X (gfx950) surfel Gauss-Newton library.
+ *
+ * Method: "Dense monocular SLAM by direct surfel optimization" (Trabes,
+ * Dondo Gazzano, Sosa Paez).  A keyframe is covered by surfels, each an
+ * inverse depth id_s along its centre ray r_s and a unit normal n_s
+ * (Surfel Parameterization section, Eq. 1).  Every Gauss-Newton iteration
+ * warps each surfel into every neighbour frame by its plane-induced
+ * homography (Eq. 6), samples the frame bilinearly with its gradient, forms
+ * Huber-weighted photometric residuals (Eq. 5) and their Jacobians with
+ * respect to the surfel's three parameters (Eq. 7-9), reduces J^T W J and
+ * J^T W r, solves the 3x3 system and updates id_s and the renormalised
+ * normal (Surfel Optimization section).  New surfels are initialised from
+ * their neighbours' planes (Surfel Initialization section) and the per-pixel
+ * inverse depth is rendered from the surfel planes (Eq. 3).
+ *
+ * Conventions
+ *   - Camera frame x right, y down, z forward.  Pixel (x, y) has its centre
+ *     at integer coordinates.  K = [[fx, 0, cx], [0, fy, cy], [0, 0, 1]].
+ *   - A pose P_kf^fn maps keyframe coordinates to frame n: X_n = R X_kf + t,
+ *     R row-major (Eq. 6).
+ *   - Surfels are S x S pixel tiles (S = patch, 4 or 8): tile (tx, ty) owns
+ *     pixels [S tx, S tx + S) x [S ty, S ty + S); its centre pixel is
+ *     (S tx + (S-1)/2, S ty + (S-1)/2).  The grid is gw x gh with
+ *     gw = width / S, gh = height / S (floor; the ragged right/bottom border
+ *     has no surfel).  Surfel arrays are indexed ty * gw + tx.
+ *   - Images are row-major with a pitch in elements.  The sampled value is
+ *     stored_value * scale (f32: scale is normally 1; u8: e.g. 1/255).
+ *
+ * Memory and ownership
+ *   - Every buffer is allocated and owned by the caller; the library never
+ *     frees caller memory.  Pointers inside sgn_image / sgn_surfels and the
+ *     output arrays are DEVICE pointers (on the context's device).  The
+ *     descriptor arrays themselves (sgn_keyframe.nbr, .pose, sgn_batch_item
+ *     arrays) are HOST memory, read during the call only.
+ *   - The context owns small device tables (descriptors, per-frame constants,
+ *     work counters), a pinned host staging ring and captured HIP graphs.
+ *   - All work is enqueued asynchronously on the context's stream; the caller
+ *     synchronises that stream before reading results.  Calls on one context
+ *     must come from one host thread at a time.
+ *
+ * Errors
+ *   - Invalid arguments and shapes are reported synchronously
+ *     (SGN_E_INVALID, SGN_E_UNSUPPORTED) and nothing is enqueued.
+ *   - HIP runtime failures return SGN_E_DEVICE (on the call or on a later one).
+ *   - sgn_last_error() returns a thread-local description of the last failure.
+ *   - Numerical failures of single surfels are NOT API errors: they set bits
+ *     of the surfel's flags word (SGN_FLAG_*), and its state is kept.
+ */
+#ifndef SURFGN_H
+#define SURFGN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sgn_ctx sgn_ctx;
+
+typedef enum {
+    SGN_OK = 0,
+    SGN_E_INVALID = -1,      /* bad argument, shape or pointer */
+    SGN_E_NOMEM = -2,        /* the context could not grow its own tables */
+    SGN_E_DEVICE = -3,       /* HIP runtime error */
+    SGN_E_UNSUPPORTED = -4,  /* valid but not implemented (e.g. patch size) */
+    SGN_E_BUSY = -5
+} sgn_status;
+
+typedef enum { SGN_F32 = 0, SGN_F16 = 1, SGN_U8 = 2 } sgn_dtype;
+
+/* Per-surfel flag bits. */
+enum {
+    SGN_FLAG_DEGENERATE = 1u << 0,   /* |n_s . r_s| < 1e-6: Eq. 3 undefined */
+    SGN_FLAG_FEW_SAMPLES = 1u << 1,  /* fewer than 3 valid (pixel, frame) samples */
+    SGN_FLAG_SOLVE_FAIL = 1u << 2,   /* J^T W J not positive definite */
+    SGN_FLAG_REJECTED = 1u << 3,     /* update gave id_s <= 0 or a non-finite value */
+    SGN_FLAG_FP64_SOLVE = 1u << 4,   /* 3x3 solved in double (ill-conditioned) */
+    SGN_FLAG_UNINIT = 1u << 5        /* new surfel without usable neighbours */
+};
+
+typedef struct { double fx, fy, cx, cy; } sgn_intrinsics;
+
+/* P_kf^fn of Eq. 6: X_n = R X_kf + t, R row-major. */
+typedef struct { double R[9]; double t[3]; } sgn_pose;
+
+typedef struct {
+    const void* data;      /* device pointer to pixel (0, 0) */
+    int32_t width, height;
+    int32_t pitch;         /* elements between rows, >= width */
+    int32_t dtype;         /* sgn_dtype */
+    float scale;           /* sampled value = stored * scale (> 0) */
+} sgn_image;
+
+/* One keyframe and its group Omega of neighbour frames (Eq. 5).  All images
+ * share the keyframe's width, height and dtype. */
+typedef struct {
+    sgn_image kf;               /* I_kf */
+    const sgn_image* nbr;       /* host array [n_nbr]: I_fn */
+    const sgn_pose* pose;       /* host array [n_nbr]: P_kf^fn */
+    int32_t n_nbr;              /* 1 .. SGN_MAX_NBR */
+    sgn_intrinsics K;
+    int32_t patch;              /* S: 4 or 8 */
+} sgn_keyframe;
+
+#define SGN_MAX_NBR 16
+
+/* Surfel state, structure of arrays of length gw * gh (device pointers).
+ * inv_depth, nx, ny, nz, flags are read and written; cost, nvalid and
+ * last_update are written (last_update only when a step was accepted). */
+typedef struct {
+    float* inv_depth;           /* id_s (1/m along the centre ray, z = 1) */
+    float* nx; float* ny; float* nz;  /* unit normal n_s (sign is preserved) */
+    uint32_t* flags;            /* SGN_FLAG_* */
+    float* cost;                /* Huber cost (Eq. 5) at the last linearisation point */
+    uint32_t* nvalid;           /* valid samples at that point */
+    uint32_t* last_update;      /* params.stamp of the last accepted update */
+} sgn_surfels;
+
+typedef struct {
+    int32_t iters;              /* Gauss-Newton iterations (>= 0) */
+    float huber_k;              /* Huber threshold in sampled-value units (> 0) */
+    float kappa_fp64;           /* solve in double when the equilibrated condition
+                                   estimate exceeds this (e.g. 1e6) */
+    int32_t depth_only;         /* 1: d id_u / d n_s := 0 (ablation), only id_s moves */
+    float beta_r;               /* init neighbour radius in pixels (<= 0: S) */
+    uint32_t stamp;             /* written to last_update */
+} sgn_params;
+
+/* Launch plan for the fused Gauss-Newton kernel (chosen by sgn_autotune or
+ * by the caller; all-zero means "library default"). */
+typedef struct {
+    int32_t tiles_x, tiles_y;   /* surfels per wavefront as a tiles_x x tiles_y block
+                                   (S = 4: 4x1, 2x2 or 1x4; S = 8: 1x1) */
+    int32_t persistent;         /* 1: persistent grid pulling work items from a
+                                   device queue; 0: one wavefront per work item */
+    int32_t waves_per_cu;       /* persistent grid size per compute unit (0: occupancy) */
+    int32_t lds_stage;          /* 1: stage neighbour-frame footprints in LDS */
+    int32_t xcd_queues;         /* 1: one work queue per XCD, keyframes bound to an XCD */
+} sgn_plan;
+
+/* One keyframe of a batch with its surfels and optional outputs. */
+typedef struct {
+    sgn_keyframe kf;
+    sgn_surfels surfels;
+    const uint8_t* is_new;      /* device [gw*gh] or NULL: surfels to initialise from
+                                   their neighbours before the first iteration */
+    float* inv_depth_out;       /* device [height * width] or NULL: rendered id_u
+                                   (0 = no measurement), row-major, pitch = width */
+    int32_t* index_out;         /* device [height * width] or NULL: owning surfel or -1 */
+} sgn_batch_item;
+
+typedef struct {
+    int32_t device;
+    int32_t compute_units;
+    int32_t xcds;
+    int32_t clock_khz;
+    int32_t memory_clock_khz;
+    int32_t memory_bus_bits;
+    int64_t total_global_mem;
+    int32_t lds_per_cu;
+    char name[64];
+    char arch[32];
+} sgn_device_props;
+
+/* Create a context on `device` whose work goes to `hip_stream` (a hipStream_t;
+ * NULL = the device's null stream).  The stream stays owned by the caller. */
+sgn_status sgn_create(sgn_ctx** out, int32_t device, void* hip_stream);
+sgn_status sgn_destroy(sgn_ctx* ctx);
+sgn_status sgn_set_stream(sgn_ctx* ctx, void* hip_stream);
+
+/* Surfel Initialization section: every surfel with is_new[i] != 0 gets
+ *   id_s = mean_j id_j (n_j . r_s) / (n_j . r_j)   (Eq. 3 of neighbour j at r_s)
+ *   n_s  = normalise(sum_j sign(n_j . n_ref) n_j)    (n_ref: first neighbour)
+ * over the surfels j that are not new, not flagged DEGENERATE/UNINIT, have
+ * |n_j . r_j| >= 1e-6 and own a pixel closer than beta_r to the new surfel's
+ * centre pixel.  Without such neighbours the surfel is flagged UNINIT and
+ * left unchanged.  is_new: device [gw*gh]. */
+sgn_status sgn_init_from_neighbours(sgn_ctx* ctx, const sgn_keyframe* kf,
+                                    const sgn_surfels* surfels, const uint8_t* is_new,
+                                    const sgn_params* params);
+
+/* Surfel Optimization section: params->iters Gauss-Newton iterations on every
+ * surfel of the keyframe (Eq. 5-9), in place.  Per iteration and surfel:
+ * Huber IRLS normal equations over all (pixel, frame) samples, 3x3 solve
+ * (float; double above kappa_fp64), id_s += d0 and
+ * n_s = normalise(n_s + d1 b1 + d2 b2) on a fixed tangent basis. */
+sgn_status sgn_optimize_keyframe(sgn_ctx* ctx, const sgn_keyframe* kf,
+                                 const sgn_surfels* surfels, const sgn_params* params,
+                                 const sgn_plan* plan /* NULL: default */);
+
+/* Inverse Depth Calculation section: per-pixel id_u of the owning surfel by
+ * Eq. 3 (0 where there is no measurement: pixel outside the grid, surfel
+ * flagged DEGENERATE or UNINIT, or id_u <= 0).  inv_depth_out: device
+ * [height * width]; index_out: device [height * width] or NULL. */
+sgn_status sgn_render_inverse_depth(sgn_ctx* ctx, const sgn_keyframe* kf,
+                                    const sgn_surfels* surfels, float* inv_depth_out,
+                                    int32_t* index_out);
+
+/* The whole per-keyframe update for many keyframes at once: initialisation
+ * of new surfels, the Gauss-Newton iterations in one fused persistent kernel,
+ * and the inverse-depth render, replayed from a captured HIP graph.  All
+ * items must share patch and image dtype.  Results equal those of the
+ * per-keyframe calls for the same plan (each surfel is reduced in a fixed
+ * order that does not depend on the batch). */
+sgn_status sgn_optimize_batch(sgn_ctx* ctx, const sgn_batch_item* items, int32_t n_items,
+                              const sgn_params* params, const sgn_plan* plan /* NULL: default */);
+
+/* Time candidate plans on a sample batch (the surfel state is restored after
+ * every trial) and return the fastest in *out (host). */
+sgn_status sgn_autotune(sgn_ctx* ctx, const sgn_batch_item* sample, int32_t n_items,
+                        const sgn_params* params, sgn_plan* out);
+
+/* Convert a float image (device, src_pitch elements per row) to dst->dtype
+ * storage at dst->data: F16 with round-to-nearest-even, or U8 as
+ * round(clamp(v / dst->scale, 0, 255)). */
+sgn_status sgn_quantize(sgn_ctx* ctx, const float* src, int32_t src_pitch, const sgn_image* dst);
+
+/* Milliseconds of the last fused Gauss-Newton kernel launched by this context
+ * (HIP events on the context's stream around that kernel alone; waits for it). */
+sgn_status sgn_last_kernel_ms(sgn_ctx* ctx, float* ms_out);
+
+sgn_status sgn_device_info(int32_t device, sgn_device_props* out);
+const char* sgn_status_str(sgn_status status);
+const char* sgn_last_error(void);
+const char* sgn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SURFGN_H */

@@ -1,0 +1,651 @@
+// Host side of the surfgn C ABI: argument validation, descriptor tables,
+// launch sequencing, HIP graph capture/replay and the plan autotuner.
+// See include/surfgn.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/surfgn.h"
+#include "sgn_internal.h"
+
+using namespace sgn;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+sgn_status fail(sgn_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+sgn_status hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return SGN_E_DEVICE;
+}
+
+#define SGN_HIP(call)                                   \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+size_t dtype_size(int dt) { return dt == SGN_F32 ? 4 : dt == SGN_F16 ? 2 : 1; }
+
+constexpr int kRingSlots = 4;
+
+struct GraphKey {
+    int dtype, patch, tx, ty, lds, persistent, grid, part, do_init, spare, frames_cap;
+    bool operator<(const GraphKey& o) const {
+        return std::tie(dtype, patch, tx, ty, lds, persistent, grid, part, do_init, spare, frames_cap) <
+               std::tie(o.dtype, o.patch, o.tx, o.ty, o.lds, o.persistent, o.grid, o.part, o.do_init,
+                        o.spare, o.frames_cap);
+    }
+};
+
+}  // namespace
+
+struct sgn_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int cus = 0;
+    // descriptor table: host staging ring (pinned) + one device copy
+    size_t table_cap = 0;
+    void* host_ring[kRingSlots] = {};
+    hipEvent_t ring_ev[kRingSlots] = {};
+    bool ring_used[kRingSlots] = {};
+    int ring_next = 0;
+    void* dev_table = nullptr;
+    uint32_t* counters = nullptr;
+    // timing of the last GN kernel
+    hipEvent_t gn_start = nullptr, gn_end = nullptr;
+    bool gn_timed = false;
+    // graphs
+    bool use_graphs = true;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+struct TableLayout {
+    size_t hdr_off, kf_off, fr_off, total;
+};
+
+TableLayout layout_for(int n_kf, int n_frames) {
+    TableLayout L;
+    auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
+    L.hdr_off = 0;
+    L.kf_off = align(sizeof(BatchHeader));
+    L.fr_off = align(L.kf_off + sizeof(KfDev) * (size_t)std::max(n_kf, 1));
+    L.total = align(L.fr_off + sizeof(FrameDev) * (size_t)std::max(n_frames, 1));
+    return L;
+}
+
+sgn_status ensure_table(sgn_ctx* c, size_t bytes) {
+    if (bytes <= c->table_cap) return SGN_OK;
+    size_t cap = std::max(bytes, c->table_cap * 2);
+    cap = std::max(cap, size_t(64) << 10);
+    // the stream may still read the old buffers
+    SGN_HIP(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < kRingSlots; ++i) {
+        if (c->host_ring[i]) SGN_HIP(hipHostFree(c->host_ring[i]));
+        c->host_ring[i] = nullptr;
+        c->ring_used[i] = false;
+    }
+    if (c->dev_table) SGN_HIP(hipFree(c->dev_table));
+    c->dev_table = nullptr;
+    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    for (int i = 0; i < kRingSlots; ++i)
+        if (hipHostMalloc(&c->host_ring[i], cap, hipHostMallocDefault) != hipSuccess)
+            return fail(SGN_E_NOMEM, "pinned staging allocation failed");
+    if (hipMalloc(&c->dev_table, cap) != hipSuccess) return fail(SGN_E_NOMEM, "device table allocation failed");
+    c->table_cap = cap;
+    return SGN_OK;
+}
+
+sgn_status check_image(const sgn_image& im, int W, int H, int dtype, const char* what) {
+    if (!im.data) return fail(SGN_E_INVALID, std::string(what) + ": null data");
+    if (im.width != W || im.height != H)
+        return fail(SGN_E_INVALID, std::string(what) + ": size differs from the keyframe");
+    if (im.pitch < im.width) return fail(SGN_E_INVALID, std::string(what) + ": pitch < width");
+    if (im.dtype != dtype) return fail(SGN_E_INVALID, std::string(what) + ": dtype differs from the keyframe");
+    if (!(im.scale > 0.f) || !std::isfinite(im.scale))
+        return fail(SGN_E_INVALID, std::string(what) + ": scale must be finite and > 0");
+    if (im.dtype != SGN_U8 && im.scale != 1.0f)
+        return fail(SGN_E_UNSUPPORTED, std::string(what) + ": scale must be 1 for f32/f16 storage");
+    if ((uint64_t)im.pitch * (uint64_t)im.height >= (1ull << 31))
+        return fail(SGN_E_UNSUPPORTED, std::string(what) + ": image larger than 2^31 elements");
+    return SGN_OK;
+}
+
+sgn_status check_keyframe(const sgn_keyframe* kf, bool need_nbr) {
+    if (!kf) return fail(SGN_E_INVALID, "null keyframe");
+    const sgn_image& I = kf->kf;
+    if (I.dtype < SGN_F32 || I.dtype > SGN_U8) return fail(SGN_E_INVALID, "bad dtype");
+    if (kf->patch != 4 && kf->patch != 8) return fail(SGN_E_UNSUPPORTED, "patch must be 4 or 8");
+    if (I.width < kf->patch || I.height < kf->patch) return fail(SGN_E_INVALID, "image smaller than one surfel");
+    if (I.width > 16384 || I.height > 16384) return fail(SGN_E_UNSUPPORTED, "image larger than 16384");
+    sgn_status st = check_image(I, I.width, I.height, I.dtype, "keyframe image");
+    if (st) return st;
+    if (!(kf->K.fx > 0) || !(kf->K.fy > 0) || !std::isfinite(kf->K.cx) || !std::isfinite(kf->K.cy))
+        return fail(SGN_E_INVALID, "intrinsics must have fx, fy > 0 and finite centre");
+    if (kf->n_nbr < 0 || kf->n_nbr > SGN_MAX_NBR) return fail(SGN_E_INVALID, "n_nbr out of range [0, 16]");
+    if (need_nbr && kf->n_nbr < 1) return fail(SGN_E_INVALID, "optimisation needs at least one neighbour frame");
+    if (kf->n_nbr > 0 && (!kf->nbr || !kf->pose)) return fail(SGN_E_INVALID, "null neighbour or pose array");
+    for (int i = 0; i < kf->n_nbr; ++i) {
+        st = check_image(kf->nbr[i], I.width, I.height, I.dtype, "neighbour image");
+        if (st) return st;
+        for (int j = 0; j < 9; ++j)
+            if (!std::isfinite(kf->pose[i].R[j])) return fail(SGN_E_INVALID, "non-finite rotation");
+        for (int j = 0; j < 3; ++j)
+            if (!std::isfinite(kf->pose[i].t[j])) return fail(SGN_E_INVALID, "non-finite translation");
+    }
+    return SGN_OK;
+}
+
+sgn_status check_surfels(const sgn_surfels* s) {
+    if (!s) return fail(SGN_E_INVALID, "null surfels");
+    if (!s->inv_depth || !s->nx || !s->ny || !s->nz || !s->flags || !s->cost || !s->nvalid ||
+        !s->last_update)
+        return fail(SGN_E_INVALID, "a surfel array is null");
+    return SGN_OK;
+}
+
+sgn_status check_params(const sgn_params* p) {
+    if (!p) return fail(SGN_E_INVALID, "null params");
+    if (p->iters < 0 || p->iters > 1000) return fail(SGN_E_INVALID, "iters out of range [0, 1000]");
+    if (!(p->huber_k > 0.f) || !std::isfinite(p->huber_k)) return fail(SGN_E_INVALID, "huber_k must be > 0");
+    if (!(p->kappa_fp64 >= 1.f)) return fail(SGN_E_INVALID, "kappa_fp64 must be >= 1");
+    if (!std::isfinite(p->beta_r)) return fail(SGN_E_INVALID, "beta_r must be finite");
+    return SGN_OK;
+}
+
+sgn_plan default_plan(int patch) {
+    sgn_plan p{};
+    if (patch == 8) { p.tiles_x = 1; p.tiles_y = 1; }
+    else { p.tiles_x = 4; p.tiles_y = 1; }
+    p.persistent = 1;
+    p.waves_per_cu = 0;
+    p.lds_stage = 0;
+    p.xcd_queues = 1;
+    return p;
+}
+
+struct RunFlags {
+    bool init, gn, render;
+};
+
+int persistent_grid(sgn_ctx* c, const GnVariant& v, const sgn_plan& plan) {
+    int per_cu = plan.waves_per_cu > 0 ? std::max(1, plan.waves_per_cu / 4) : gn_blocks_per_cu(v);
+    if (per_cu < 1) per_cu = 1;
+    return std::max(1, c->cus) * per_cu;
+}
+
+// Build the descriptor table for a batch, upload it and enqueue the kernels.
+sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_params* prm,
+                     const sgn_plan* plan_in, RunFlags fl) {
+    if (n < 1) return fail(SGN_E_INVALID, "empty batch");
+    const int patch = items[0].kf.patch;
+    const int dtype = items[0].kf.kf.dtype;
+    int total_frames = 0;
+    for (int i = 0; i < n; ++i) {
+        sgn_status st = check_keyframe(&items[i].kf, fl.gn);
+        if (st) return st;
+        if (items[i].kf.patch != patch) return fail(SGN_E_INVALID, "batch items differ in patch");
+        if (items[i].kf.kf.dtype != dtype) return fail(SGN_E_INVALID, "batch items differ in dtype");
+        st = check_surfels(&items[i].surfels);
+        if (st) return st;
+        total_frames += items[i].kf.n_nbr;
+    }
+    sgn_status st = check_params(prm);
+    if (st) return st;
+    sgn_plan plan = plan_in ? *plan_in : default_plan(patch);
+    if (plan.tiles_x == 0 && plan.tiles_y == 0) plan = default_plan(patch);
+    GnVariant var{dtype, patch, plan.tiles_x, plan.tiles_y, plan.lds_stage};
+    if (fl.gn && !gn_variant_supported(var)) return fail(SGN_E_UNSUPPORTED, "plan not supported for this patch");
+
+    TableLayout L = layout_for(n, total_frames);
+    st = ensure_table(c, L.total);
+    if (st) return st;
+    // pick a staging slot whose previous upload has completed
+    int slot = c->ring_next;
+    c->ring_next = (c->ring_next + 1) % kRingSlots;
+    if (c->ring_used[slot]) SGN_HIP(hipEventSynchronize(c->ring_ev[slot]));
+    char* host = (char*)c->host_ring[slot];
+    char* dev = (char*)c->dev_table;
+    BatchHeader* H = (BatchHeader*)(host + L.hdr_off);
+    KfDev* kfs = (KfDev*)(host + L.kf_off);
+    FrameDev* frs = (FrameDev*)(host + L.fr_off);
+    std::memset(host, 0, L.total);
+
+    // keyframe order: longest work items first, grouped by XCD queue
+    const int TX = fl.gn ? plan.tiles_x : 1, TY = fl.gn ? plan.tiles_y : 1;
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::vector<int64_t> work(n);
+    for (int i = 0; i < n; ++i) {
+        const sgn_keyframe& kf = items[i].kf;
+        int64_t gw = kf.kf.width / kf.patch, gh = kf.kf.height / kf.patch;
+        work[i] = gw * gh * std::max(1, kf.n_nbr);
+    }
+    const int nq = (fl.gn && plan.persistent && plan.xcd_queues) ? std::min(kXcds, n) : 1;
+    std::vector<int> queue_of(n, 0);
+    if (nq > 1) {
+        // greedy balance: biggest keyframe to the least loaded queue
+        std::vector<int> bysize(order);
+        std::stable_sort(bysize.begin(), bysize.end(), [&](int a, int b) { return work[a] > work[b]; });
+        std::vector<int64_t> load(nq, 0);
+        for (int i : bysize) {
+            int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            queue_of[i] = q;
+            load[q] += work[i];
+        }
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (queue_of[a] != queue_of[b]) return queue_of[a] < queue_of[b];
+        return items[a].kf.n_nbr > items[b].kf.n_nbr;
+    });
+
+    int frame_base = 0, item_base = 0, surfel_base = 0;
+    int64_t pixel_base = 0;
+    bool any_init = false, any_render = false;
+    for (int q = 0; q < kNumCounters; ++q) H->queues[q].begin = H->queues[q].end = 0;
+    int cur_q = -1;
+    for (int oi = 0; oi < n; ++oi) {
+        const int i = order[oi];
+        const sgn_batch_item& it = items[i];
+        const sgn_keyframe& kf = it.kf;
+        KfDev& D = kfs[oi];
+        D.kf_img = kf.kf.data;
+        D.inv_depth = it.surfels.inv_depth;
+        D.nx = it.surfels.nx; D.ny = it.surfels.ny; D.nz = it.surfels.nz;
+        D.flags = it.surfels.flags;
+        D.cost = it.surfels.cost;
+        D.nvalid = it.surfels.nvalid;
+        D.last_update = it.surfels.last_update;
+        D.is_new = fl.init ? it.is_new : nullptr;
+        D.inv_depth_out = fl.render ? it.inv_depth_out : nullptr;
+        D.index_out = fl.render ? it.index_out : nullptr;
+        D.width = kf.kf.width;
+        D.height = kf.kf.height;
+        D.kf_pitch = kf.kf.pitch;
+        D.n_nbr = kf.n_nbr;
+        D.gw = kf.kf.width / kf.patch;
+        D.gh = kf.kf.height / kf.patch;
+        D.patch = kf.patch;
+        D.nbr_pitch_b = kf.n_nbr > 0 ? kf.nbr[0].pitch * (int32_t)dtype_size(kf.kf.dtype) : 0;
+        D.frame_base = frame_base;
+        D.groups_x = (D.gw + TX - 1) / TX;
+        const int groups_y = (D.gh + TY - 1) / TY;
+        D.n_items = fl.gn ? D.groups_x * groups_y : 0;
+        D.item_base = item_base;
+        D.surfel_base = surfel_base;
+        D.pixel_base = pixel_base;
+        D.queue = queue_of[i];
+        D.fx = (float)kf.K.fx; D.fy = (float)kf.K.fy; D.cx = (float)kf.K.cx; D.cy = (float)kf.K.cy;
+        D.fx_d = kf.K.fx; D.fy_d = kf.K.fy; D.cx_d = kf.K.cx; D.cy_d = kf.K.cy;
+        D.kf_scale = kf.kf.scale;
+        D.img_scale = kf.n_nbr > 0 ? kf.nbr[0].scale : 1.f;
+        for (int f = 0; f < kf.n_nbr; ++f) {
+            if (kf.nbr[f].scale != D.img_scale)
+                return fail(SGN_E_UNSUPPORTED, "neighbour images of one keyframe must share a scale");
+            if (kf.nbr[f].pitch != kf.nbr[0].pitch)
+                return fail(SGN_E_UNSUPPORTED, "neighbour images of one keyframe must share a pitch");
+            FrameDev& F = frs[frame_base + f];
+            F.img = kf.nbr[f].data;
+            F.pitch = kf.nbr[f].pitch;
+            std::memcpy(F.R, kf.pose[f].R, sizeof(F.R));
+            std::memcpy(F.t, kf.pose[f].t, sizeof(F.t));
+        }
+        if (D.queue != cur_q) {
+            H->queues[D.queue].begin = item_base;
+            cur_q = D.queue;
+        }
+        frame_base += kf.n_nbr;
+        item_base += D.n_items;
+        H->queues[D.queue].end = item_base;
+        surfel_base += D.gw * D.gh;
+        if (D.inv_depth_out) pixel_base += (int64_t)D.width * D.height;
+        any_init |= D.is_new != nullptr;
+        any_render |= D.inv_depth_out != nullptr;
+    }
+    H->kfs = (KfDev*)(dev + L.kf_off);
+    H->frames = (FrameDev*)(dev + L.fr_off);
+    H->n_kf = n;
+    H->n_frames = total_frames;
+    H->total_items = item_base;
+    H->total_surfels = surfel_base;
+    H->total_pixels = pixel_base;
+    H->iters = prm->iters;
+    H->huber_k = prm->huber_k;
+    H->kappa_fp64 = prm->kappa_fp64;
+    H->depth_only = prm->depth_only;
+    H->beta_r = prm->beta_r;
+    H->stamp = prm->stamp;
+    H->do_init = fl.init && any_init;
+    H->do_gn = fl.gn;
+    H->do_render = fl.render && any_render;
+    H->n_queues = nq;
+
+    SGN_HIP(hipMemcpyAsync(dev, host, L.total, hipMemcpyHostToDevice, c->stream));
+    SGN_HIP(hipEventRecord(c->ring_ev[slot], c->stream));
+    c->ring_used[slot] = true;
+
+    const BatchHeader* dH = (const BatchHeader*)(dev + L.hdr_off);
+    const int frames_cap = (int)((c->table_cap - L.fr_off) / sizeof(FrameDev));
+    const int aux_grid = std::max(1, c->cus) * 8;
+    const int gn_grid = plan.persistent ? persistent_grid(c, var, plan)
+                                        : std::max(1, (item_base + 3) / 4);
+    const bool do_init = H->do_init, do_render = H->do_render;
+    // Kernel sequence in three parts (pre: setup + init, gn, post: render),
+    // each replayed from its own captured graph when the launch shape
+    // repeats; the GN part is bracketed by the context's timing events.
+    auto enqueue_pre = [&](hipStream_t s) -> hipError_t {
+        hipError_t e = launch_setup(dH, c->counters, frames_cap, s);
+        if (e == hipSuccess && do_init) e = launch_init(dH, aux_grid, s);
+        return e;
+    };
+    auto enqueue_gn = [&](hipStream_t s) -> hipError_t {
+        return launch_gn(var, dH, c->counters, plan.persistent, gn_grid, s);
+    };
+    auto enqueue_post = [&](hipStream_t s) -> hipError_t { return launch_render(dH, aux_grid, s); };
+    const bool run_gn = fl.gn && item_base > 0;
+    const bool graph_ok = c->use_graphs && (plan.persistent || !run_gn);
+    auto run_part = [&](int part, bool needed, auto&& enq) -> sgn_status {
+        if (!needed) return SGN_OK;
+        if (!graph_ok) {
+            hipError_t e = enq(c->stream);
+            return e == hipSuccess ? SGN_OK : hip_fail(e, "kernel launch");
+        }
+        GraphKey key{dtype, patch, plan.tiles_x, plan.tiles_y, plan.lds_stage, plan.persistent,
+                     part == 1 ? gn_grid : aux_grid, part, (int)do_init, 0, frames_cap};
+        auto found = c->graphs.find(key);
+        if (found == c->graphs.end()) {
+            hipStream_t cap = nullptr;
+            SGN_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t e2 = enq(cap);
+                e = hipStreamEndCapture(cap, &g);
+                if (e2 != hipSuccess) e = e2;
+            }
+            (void)hipStreamDestroy(cap);
+            if (e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return hip_fail(e, "graph capture");
+            }
+            hipGraphExec_t ex = nullptr;
+            e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+            found = c->graphs.emplace(key, ex).first;
+        }
+        SGN_HIP(hipGraphLaunch(found->second, c->stream));
+        return SGN_OK;
+    };
+    st = run_part(0, true, enqueue_pre);
+    if (st) return st;
+    if (run_gn) {
+        SGN_HIP(hipEventRecord(c->gn_start, c->stream));
+        st = run_part(1, true, enqueue_gn);
+        if (st) return st;
+        SGN_HIP(hipEventRecord(c->gn_end, c->stream));
+        c->gn_timed = true;
+    }
+    return run_part(2, do_render, enqueue_post);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sgn_version(void) { return "surfgn 0.1 (gfx950)"; }
+
+const char* sgn_last_error(void) { return g_last_error.c_str(); }
+
+const char* sgn_status_str(sgn_status s) {
+    switch (s) {
+        case SGN_OK: return "ok";
+        case SGN_E_INVALID: return "invalid argument";
+        case SGN_E_NOMEM: return "out of memory";
+        case SGN_E_DEVICE: return "device error";
+        case SGN_E_UNSUPPORTED: return "unsupported";
+        case SGN_E_BUSY: return "busy";
+    }
+    return "unknown status";
+}
+
+sgn_status sgn_device_info(int32_t device, sgn_device_props* out) {
+    if (!out) return fail(SGN_E_INVALID, "null output");
+    hipDeviceProp_t p;
+    SGN_HIP(hipGetDeviceProperties(&p, device));
+    std::memset(out, 0, sizeof(*out));
+    out->device = device;
+    out->compute_units = p.multiProcessorCount;
+    out->xcds = kXcds;
+    out->clock_khz = p.clockRate;
+    out->memory_clock_khz = p.memoryClockRate;
+    out->memory_bus_bits = p.memoryBusWidth;
+    out->total_global_mem = (int64_t)p.totalGlobalMem;
+    out->lds_per_cu = (int32_t)p.maxSharedMemoryPerMultiProcessor;
+    std::snprintf(out->name, sizeof(out->name), "%s", p.name);
+    std::snprintf(out->arch, sizeof(out->arch), "%s", p.gcnArchName);
+    return SGN_OK;
+}
+
+sgn_status sgn_create(sgn_ctx** out, int32_t device, void* hip_stream) {
+    if (!out) return fail(SGN_E_INVALID, "null output");
+    *out = nullptr;
+    int ndev = 0;
+    SGN_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(SGN_E_INVALID, "no such device");
+    SGN_HIP(hipSetDevice(device));
+    sgn_ctx* c = new sgn_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) { delete c; return hip_fail(hipErrorUnknown, "props"); }
+    c->cus = p.multiProcessorCount;
+    if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0) {
+        delete c;
+        return fail(SGN_E_UNSUPPORTED, std::string("built for gfx950, device is ") + p.gcnArchName);
+    }
+    for (int i = 0; i < kRingSlots; ++i)
+        if (hipEventCreateWithFlags(&c->ring_ev[i], hipEventDisableTiming) != hipSuccess) {
+            delete c;
+            return fail(SGN_E_DEVICE, "event creation failed");
+        }
+    if (hipEventCreate(&c->gn_start) != hipSuccess || hipEventCreate(&c->gn_end) != hipSuccess ||
+        hipMalloc(&c->counters, kNumCounters * sizeof(uint32_t)) != hipSuccess) {
+        delete c;
+        return fail(SGN_E_DEVICE, "context allocation failed");
+    }
+    if (const char* g = std::getenv("SGN_NO_GRAPHS")) c->use_graphs = !(g[0] == '1');
+    *out = c;
+    return SGN_OK;
+}
+
+sgn_status sgn_destroy(sgn_ctx* c) {
+    if (!c) return SGN_OK;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+    for (int i = 0; i < kRingSlots; ++i) {
+        if (c->host_ring[i]) hipHostFree(c->host_ring[i]);
+        if (c->ring_ev[i]) hipEventDestroy(c->ring_ev[i]);
+    }
+    if (c->dev_table) hipFree(c->dev_table);
+    if (c->counters) hipFree(c->counters);
+    if (c->gn_start) hipEventDestroy(c->gn_start);
+    if (c->gn_end) hipEventDestroy(c->gn_end);
+    delete c;
+    return SGN_OK;
+}
+
+sgn_status sgn_set_stream(sgn_ctx* c, void* hip_stream) {
+    if (!c) return fail(SGN_E_INVALID, "null context");
+    c->stream = (hipStream_t)hip_stream;
+    return SGN_OK;
+}
+
+sgn_status sgn_init_from_neighbours(sgn_ctx* c, const sgn_keyframe* kf, const sgn_surfels* s,
+                                    const uint8_t* is_new, const sgn_params* p) {
+    if (!c) return fail(SGN_E_INVALID, "null context");
+    if (!is_new) return fail(SGN_E_INVALID, "null is_new");
+    if (!kf) return fail(SGN_E_INVALID, "null keyframe");
+    SGN_HIP(hipSetDevice(c->device));
+    sgn_batch_item it{};
+    it.kf = *kf;
+    if (s) it.surfels = *s;
+    it.is_new = is_new;
+    return run_batch(c, &it, 1, p, nullptr, RunFlags{true, false, false});
+}
+
+sgn_status sgn_optimize_keyframe(sgn_ctx* c, const sgn_keyframe* kf, const sgn_surfels* s,
+                                 const sgn_params* p, const sgn_plan* plan) {
+    if (!c) return fail(SGN_E_INVALID, "null context");
+    if (!kf) return fail(SGN_E_INVALID, "null keyframe");
+    SGN_HIP(hipSetDevice(c->device));
+    sgn_batch_item it{};
+    it.kf = *kf;
+    if (s) it.surfels = *s;
+    sgn_plan pl = plan ? *plan : default_plan(kf->patch);
+    if (!plan) pl.persistent = 0;   // one keyframe: one wavefront per work item
+    return run_batch(c, &it, 1, p, &pl, RunFlags{false, true, false});
+}
+
+sgn_status sgn_render_inverse_depth(sgn_ctx* c, const sgn_keyframe* kf, const sgn_surfels* s,
+                                    float* inv_depth_out, int32_t* index_out) {
+    if (!c) return fail(SGN_E_INVALID, "null context");
+    if (!kf) return fail(SGN_E_INVALID, "null keyframe");
+    if (!inv_depth_out) return fail(SGN_E_INVALID, "null inv_depth_out");
+    SGN_HIP(hipSetDevice(c->device));
+    sgn_batch_item it{};
+    it.kf = *kf;
+    if (s) it.surfels = *s;
+    it.inv_depth_out = inv_depth_out;
+    it.index_out = index_out;
+    sgn_params p{};
+    p.iters = 0;
+    p.huber_k = 1.f;
+    p.kappa_fp64 = 1e6f;
+    return run_batch(c, &it, 1, &p, nullptr, RunFlags{false, false, true});
+}
+
+sgn_status sgn_optimize_batch(sgn_ctx* c, const sgn_batch_item* items, int32_t n, const sgn_params* p,
+                              const sgn_plan* plan) {
+    if (!c) return fail(SGN_E_INVALID, "null context");
+    if (!items || n < 1) return fail(SGN_E_INVALID, "empty batch");
+    SGN_HIP(hipSetDevice(c->device));
+    return run_batch(c, items, n, p, plan, RunFlags{true, true, true});
+}
+
+sgn_status sgn_last_kernel_ms(sgn_ctx* c, float* ms) {
+    if (!c || !ms) return fail(SGN_E_INVALID, "null argument");
+    if (!c->gn_timed) return fail(SGN_E_INVALID, "no timed kernel yet");
+    SGN_HIP(hipEventSynchronize(c->gn_end));
+    SGN_HIP(hipEventElapsedTime(ms, c->gn_start, c->gn_end));
+    return SGN_OK;
+}
+
+sgn_status sgn_quantize(sgn_ctx* c, const float* src, int32_t src_pitch, const sgn_image* dst) {
+    if (!c || !src || !dst || !dst->data) return fail(SGN_E_INVALID, "null argument");
+    if (dst->dtype != SGN_F16 && dst->dtype != SGN_U8) return fail(SGN_E_INVALID, "dst dtype must be f16 or u8");
+    if (dst->width < 1 || dst->height < 1 || src_pitch < dst->width || dst->pitch < dst->width)
+        return fail(SGN_E_INVALID, "bad size or pitch");
+    if (!(dst->scale > 0.f) || !std::isfinite(dst->scale)) return fail(SGN_E_INVALID, "scale must be > 0");
+    SGN_HIP(hipSetDevice(c->device));
+    hipError_t e = launch_quantize(src, src_pitch, const_cast<void*>(dst->data), dst->pitch, dst->width,
+                                   dst->height, dst->dtype, dst->scale, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "quantize launch");
+    return SGN_OK;
+}
+
+sgn_status sgn_autotune(sgn_ctx* c, const sgn_batch_item* items, int32_t n, const sgn_params* p,
+                        sgn_plan* out) {
+    if (!c || !items || n < 1 || !out) return fail(SGN_E_INVALID, "null argument");
+    SGN_HIP(hipSetDevice(c->device));
+    const int patch = items[0].kf.patch;
+    // snapshot the state arrays so every trial starts from the same surfels
+    struct Saved { void* dst; std::vector<char> bytes; };
+    std::vector<void*> bufs;
+    std::vector<std::pair<void*, size_t>> arrays;
+    for (int i = 0; i < n; ++i) {
+        const sgn_surfels& s = items[i].surfels;
+        size_t m = (size_t)(items[i].kf.kf.width / patch) * (items[i].kf.kf.height / patch);
+        arrays.push_back({s.inv_depth, m * 4});
+        arrays.push_back({s.nx, m * 4});
+        arrays.push_back({s.ny, m * 4});
+        arrays.push_back({s.nz, m * 4});
+        arrays.push_back({s.flags, m * 4});
+        arrays.push_back({s.cost, m * 4});
+        arrays.push_back({s.nvalid, m * 4});
+        arrays.push_back({s.last_update, m * 4});
+    }
+    for (auto& a : arrays) {
+        void* b = nullptr;
+        if (hipMalloc(&b, a.second) != hipSuccess) {
+            for (void* q : bufs) hipFree(q);
+            return fail(SGN_E_NOMEM, "autotune snapshot allocation failed");
+        }
+        hipMemcpyAsync(b, a.first, a.second, hipMemcpyDeviceToDevice, c->stream);
+        bufs.push_back(b);
+    }
+    auto restore = [&]() {
+        for (size_t i = 0; i < arrays.size(); ++i)
+            hipMemcpyAsync(arrays[i].first, bufs[i], arrays[i].second, hipMemcpyDeviceToDevice, c->stream);
+    };
+    std::vector<sgn_plan> cands;
+    std::vector<std::pair<int, int>> shapes = patch == 8 ? std::vector<std::pair<int, int>>{{1, 1}}
+                                                         : std::vector<std::pair<int, int>>{{4, 1}, {2, 2}, {1, 4}};
+    for (auto sh : shapes)
+        for (int pers = 0; pers <= 1; ++pers)
+            for (int xq = 0; xq <= pers; ++xq) {
+                sgn_plan pl{};
+                pl.tiles_x = sh.first;
+                pl.tiles_y = sh.second;
+                pl.persistent = pers;
+                pl.xcd_queues = xq;
+                pl.lds_stage = 0;
+                pl.waves_per_cu = 0;
+                cands.push_back(pl);
+            }
+    float best = 1e30f;
+    sgn_plan best_plan = default_plan(patch);
+    sgn_status result = SGN_OK;
+    for (const sgn_plan& pl : cands) {
+        GnVariant v{items[0].kf.kf.dtype, patch, pl.tiles_x, pl.tiles_y, pl.lds_stage};
+        if (!gn_variant_supported(v)) continue;
+        float tot = 0.f;
+        bool ok = true;
+        for (int rep = 0; rep < 3 && ok; ++rep) {
+            restore();
+            sgn_status st = run_batch(c, items, n, p, &pl, RunFlags{false, true, false});
+            float ms = 0.f;
+            if (st == SGN_OK) st = sgn_last_kernel_ms(c, &ms);
+            if (st != SGN_OK) { ok = false; result = st; break; }
+            if (rep > 0) tot += ms;   // first run warms up (and captures the graph)
+        }
+        if (ok && tot < best) {
+            best = tot;
+            best_plan = pl;
+        }
+    }
+    restore();
+    hipStreamSynchronize(c->stream);
+    for (void* b : bufs) hipFree(b);
+    *out = best_plan;
+    return best < 1e29f ? SGN_OK : (result != SGN_OK ? result : fail(SGN_E_DEVICE, "no plan ran"));
+}
+
+}  // extern "C"

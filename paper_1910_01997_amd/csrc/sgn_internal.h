@@ -1,0 +1,108 @@
+// Internal layouts shared by the host side of the C ABI (sgn_api.cpp) and
+// the HIP kernels (sgn_kernels.hip).  Not part of the public interface.
+#pragma once
+
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace sgn {
+
+constexpr int kMaxNbr = 16;
+constexpr int kWaveSize = 64;
+constexpr int kBlockThreads = 256;      // 4 wavefronts per workgroup
+constexpr int kNumCounters = 16;        // work-queue heads (one per XCD + spares)
+constexpr int kXcds = 8;
+
+// Per-keyframe descriptor in device memory (one per batch item).
+struct KfDev {
+    const void* kf_img;
+    float* inv_depth;
+    float* nx;
+    float* ny;
+    float* nz;
+    uint32_t* flags;
+    float* cost;
+    uint32_t* nvalid;
+    uint32_t* last_update;
+    const uint8_t* is_new;        // may be null
+    float* inv_depth_out;         // may be null
+    int32_t* index_out;           // may be null
+    int32_t width, height, kf_pitch, n_nbr;
+    int32_t gw, gh, frame_base, item_base;      // frames: [frame_base, frame_base + n_nbr)
+    int32_t groups_x, n_items, surfel_base, queue;  // work items of this keyframe
+    int64_t pixel_base;                          // prefix over rendered pixels
+    int32_t patch, nbr_pitch_b;                   // neighbour-image row pitch in bytes
+    double fx_d, fy_d, cx_d, cy_d;               // intrinsics as given (double)
+    float fx, fy, cx, cy;                        // the same, rounded to float
+    float kf_scale, img_scale, pad0, pad1;
+};
+
+// Per-neighbour-frame descriptor.  R and t are the caller's pose in double;
+// hm/kt are written on the device by the setup kernel.
+struct FrameDev {
+    const void* img;
+    int32_t pitch, pad0;
+    double R[9];
+    double t[3];
+    double hm[9];   // K R K^-1
+    double kt[3];   // K t
+    float zrow[4];  // hm[6], hm[7], kt[2] rounded to float (the q_z row), pad
+};
+
+// Work queue q covers the global item range [begin, end).
+struct QueueDev {
+    int32_t begin, end;
+};
+
+// Header of one batch, in device memory, read by every kernel.  All per-call
+// values live here (not in kernel arguments) so that a captured graph can be
+// replayed for any batch.
+struct BatchHeader {
+    KfDev* kfs;
+    FrameDev* frames;
+    int32_t n_kf, n_frames, total_items, total_surfels;
+    int64_t total_pixels;
+    int32_t iters;
+    float huber_k;
+    float kappa_fp64;
+    int32_t depth_only;
+    float beta_r;
+    uint32_t stamp;
+    int32_t do_init, do_gn, do_render, n_queues;
+    QueueDev queues[kNumCounters];
+};
+
+enum : uint32_t {
+    F_DEGENERATE = 1u << 0,
+    F_FEW_SAMPLES = 1u << 1,
+    F_SOLVE_FAIL = 1u << 2,
+    F_REJECTED = 1u << 3,
+    F_FP64_SOLVE = 1u << 4,
+    F_UNINIT = 1u << 5,
+    F_GN_BITS = F_DEGENERATE | F_FEW_SAMPLES | F_SOLVE_FAIL | F_REJECTED | F_FP64_SOLVE,
+};
+
+// Kernel variants.
+struct GnVariant {
+    int dtype;      // 0 f32, 1 f16, 2 u8
+    int patch;      // 4 or 8
+    int tiles_x, tiles_y;
+    int lds;        // stage footprints in LDS
+};
+
+// Launchers implemented in sgn_kernels.hip.  All return hipError_t of the
+// launch.
+hipError_t launch_setup(const BatchHeader* hdr, uint32_t* counters, int n_frames_cap,
+                        hipStream_t s);
+hipError_t launch_init(const BatchHeader* hdr, int grid, hipStream_t s);
+hipError_t launch_render(const BatchHeader* hdr, int grid, hipStream_t s);
+hipError_t launch_gn(const GnVariant& v, const BatchHeader* hdr, uint32_t* counters,
+                     int persistent, int grid_blocks, hipStream_t s);
+hipError_t launch_quantize(const float* src, int src_pitch, void* dst, int dst_pitch,
+                           int width, int height, int dtype, float scale, hipStream_t s);
+// Workgroups of 256 threads of the chosen GN variant that fit on one CU.
+int gn_blocks_per_cu(const GnVariant& v);
+bool gn_variant_supported(const GnVariant& v);
+
+}  // namespace sgn

@@ -1,0 +1,779 @@
+// HIP kernels of the surfel Gauss-Newton path for gfx950 (CDNA4).
+//
+// Paper: "Dense monocular SLAM by direct surfel optimization" (Trabes,
+// Dondo Gazzano, Sosa Paez), Proposed Approach section, Eq. 1-9.
+//
+// Kernels
+//   setup_kernel   per-frame constants H = K R K^-1 and K t (Eq. 6) in
+//                  double, rounded once to float; clears the work queues.
+//   init_kernel    neighbour-plane initialisation (Surfel Initialization).
+//   gn_kernel      the fused Gauss-Newton iterations: one wavefront holds
+//                  64 pixels (4 surfels of 4x4 or 1 surfel of 8x8); each lane
+//                  is one pixel and loops over the neighbour frames; the
+//                  per-pixel inverse-depth Jacobian is hoisted out of the
+//                  frame loop (the paper notes it does not depend on the
+//                  frame), the normal equations are reduced across lanes with
+//                  DPP, and every lane of a surfel solves the same 3x3 system.
+//                  All iterations run inside the kernel: surfels never read
+//                  each other during the optimisation.
+//   render_kernel  per-pixel inverse depth by Eq. 3.
+//
+// Numerics.  The warp uses the closed form of Eq. 6 for a plane:
+//   q = H u~ + (K t) id_u,   u_p = (q_x / q_z, q_y / q_z),
+// which is K (R X + t) scaled by id_u.  id_u is formed in difference form
+//   sigma = n . (r_u - r_s) / (n . r_s),   id_u = id_s (1 + sigma),
+// equal to Eq. 3 without its cancellation.  The image gradient is the exact
+// derivative of the bilinear interpolant.  Accumulation is in float, in a
+// fixed order per surfel (frames in order per lane, then a fixed DPP tree),
+// so a surfel's result does not depend on where it sits in a batch.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "sgn_internal.h"
+
+namespace sgn {
+
+// ---------------------------------------------------------------- helpers --
+
+// Pointers into the constant address space: the descriptor tables are not
+// written while a kernel runs, so uniform reads become scalar loads.
+template <class T>
+using cptr = const T __attribute__((address_space(4)))*;
+// Global-address-space pointers (global_load with a scalar base).
+template <class T>
+using gptr = const T __attribute__((address_space(1)))*;
+template <class T>
+using gmut = T __attribute__((address_space(1)))*;
+
+template <typename T>
+__device__ __forceinline__ float ldg(gptr<T> p);
+template <>
+__device__ __forceinline__ float ldg<float>(gptr<float> p) { return *p; }
+template <>
+__device__ __forceinline__ float ldg<_Float16>(gptr<_Float16> p) { return (float)*p; }
+template <>
+__device__ __forceinline__ float ldg<uint8_t>(gptr<uint8_t> p) { return (float)*p; }
+
+template <typename T>
+__device__ __forceinline__ float ldpix(const T* p);
+template <>
+__device__ __forceinline__ float ldpix<float>(const float* p) { return *p; }
+template <>
+__device__ __forceinline__ float ldpix<_Float16>(const _Float16* p) { return (float)*p; }
+template <>
+__device__ __forceinline__ float ldpix<uint8_t>(const uint8_t* p) { return (float)*p; }
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x) {
+    return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, true);
+}
+
+// Sum over the 16 lanes of a DPP row.  Every lane of the row ends with the
+// bitwise-same value: each step adds a lane's value and its partner's, and
+// float addition is commutative.
+__device__ __forceinline__ float row_sum(float x) {
+    x += dpp_f<0xB1>(x);   // quad_perm [1,0,3,2]
+    x += dpp_f<0x4E>(x);   // quad_perm [2,3,0,1]
+    x += dpp_f<0x141>(x);  // row_half_mirror
+    x += dpp_f<0x140>(x);  // row_mirror
+    return x;
+}
+__device__ __forceinline__ int row_sum(int x) {
+    x += dpp_i<0xB1>(x);
+    x += dpp_i<0x4E>(x);
+    x += dpp_i<0x141>(x);
+    x += dpp_i<0x140>(x);
+    return x;
+}
+
+// Sum over a surfel's lanes: 16 lanes (one DPP row) or the whole wavefront.
+template <int LANES>
+__device__ __forceinline__ float group_sum(float x) {
+    x = row_sum(x);
+    if constexpr (LANES == 64) {
+        x += __shfl_xor(x, 16);
+        x += __shfl_xor(x, 32);
+    }
+    return x;
+}
+template <int LANES>
+__device__ __forceinline__ int group_sum(int x) {
+    x = row_sum(x);
+    if constexpr (LANES == 64) {
+        x += __shfl_xor(x, 16);
+        x += __shfl_xor(x, 32);
+    }
+    return x;
+}
+
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ int find_kf(cptr<KfDev> kfs, int n_kf, int item, int hint) {
+    const cptr<KfDev> h = kfs + hint;
+    if (item >= h->item_base && item < h->item_base + h->n_items) return hint;
+    int lo = 0, hi = n_kf - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (kfs[mid].item_base <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Next work item of a persistent wavefront: take one from queue q, moving on
+// to the next queue when q is exhausted; `total` when every queue is empty.
+__device__ __forceinline__ int pull_item(const BatchHeader* __restrict__ hdr, uint32_t* counters,
+                                         int& q, int& q_left, int lane, int total) {
+    while (q_left > 0) {
+        int got = 0;
+        if (lane == 0) got = (int)atomicAdd(&counters[q], 1u);
+        got = __builtin_amdgcn_readfirstlane(got);
+        const int it = hdr->queues[q].begin + got;
+        if (it < hdr->queues[q].end) return it;
+        q = (q + 1 == hdr->n_queues) ? 0 : q + 1;
+        --q_left;
+    }
+    return total;
+}
+
+// ------------------------------------------------------------ setup kernel --
+
+// One thread per neighbour frame: H = K R K^-1 and K t in double, rounded
+// once to float (Eq. 6).  Thread 0 also clears the work-queue heads.
+__global__ void setup_kernel(const BatchHeader* __restrict__ hdr, uint32_t* __restrict__ counters) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kNumCounters) counters[i] = 0u;
+    if (i >= hdr->n_frames) return;
+    FrameDev& F = hdr->frames[i];
+    // the owning keyframe carries K
+    int k = 0;
+    {
+        int lo = 0, hi = hdr->n_kf - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (hdr->kfs[mid].frame_base <= i) lo = mid; else hi = mid - 1;
+        }
+        k = lo;
+    }
+    const KfDev& K = hdr->kfs[k];
+    const double fx = K.fx_d, fy = K.fy_d, cx = K.cx_d, cy = K.cy_d;
+    const double* R = F.R;
+    // K R
+    double KR[9];
+    for (int c = 0; c < 3; ++c) {
+        KR[0 * 3 + c] = fx * R[0 * 3 + c] + cx * R[2 * 3 + c];
+        KR[1 * 3 + c] = fy * R[1 * 3 + c] + cy * R[2 * 3 + c];
+        KR[2 * 3 + c] = R[2 * 3 + c];
+    }
+    // (K R) K^-1, K^-1 = [[1/fx, 0, -cx/fx], [0, 1/fy, -cy/fy], [0, 0, 1]]
+    for (int r = 0; r < 3; ++r) {
+        double a = KR[r * 3 + 0], b = KR[r * 3 + 1], c = KR[r * 3 + 2];
+        F.hm[r * 3 + 0] = a / fx;
+        F.hm[r * 3 + 1] = b / fy;
+        F.hm[r * 3 + 2] = c - a * cx / fx - b * cy / fy;
+    }
+    F.kt[0] = fx * F.t[0] + cx * F.t[2];
+    F.kt[1] = fy * F.t[1] + cy * F.t[2];
+    F.kt[2] = F.t[2];
+    F.zrow[0] = (float)F.hm[6];
+    F.zrow[1] = (float)F.hm[7];
+    F.zrow[2] = (float)F.kt[2];
+    F.zrow[3] = 0.f;
+}
+
+// ------------------------------------------------------------- init kernel --
+
+// Surfel Initialization section.  Neighbours of new surfel s: surfels that
+// are not new, usable, and own a pixel closer than beta_r to u_s.  New
+// id_s = mean of Eq. 3 of each neighbour's plane at r_s; new n_s = mean of
+// the sign-aligned neighbour normals, renormalised.  Neighbours are visited
+// in index order.
+__global__ void init_kernel(const BatchHeader* __restrict__ hdr) {
+    const int total = hdr->total_surfels;
+    int hint = 0;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < total; s += gridDim.x * blockDim.x) {
+        int lo = 0, hi = hdr->n_kf - 1;
+        if (!(s >= hdr->kfs[hint].surfel_base &&
+              s < hdr->kfs[hint].surfel_base + hdr->kfs[hint].gw * hdr->kfs[hint].gh)) {
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (hdr->kfs[mid].surfel_base <= s) lo = mid; else hi = mid - 1;
+            }
+            hint = lo;
+        }
+        const KfDev& K = hdr->kfs[hint];
+        if (!K.is_new) continue;
+        const int S = K.patch;
+        const int i = s - K.surfel_base;
+        if (!K.is_new[i]) continue;
+        const int gw = K.gw, gh = K.gh;
+        const int tx = i % gw, ty = i / gw;
+        const float half = 0.5f * (float)(S - 1);
+        const float ux = (float)(S * tx) + half, uy = (float)(S * ty) + half;
+        const float rsx = (ux - K.cx) / K.fx, rsy = (uy - K.cy) / K.fy;
+        const float br = hdr->beta_r > 0.f ? hdr->beta_r : (float)S;
+        const float br2 = br * br;
+        const int reach = (int)ceilf(br / (float)S) + 1;
+        float id_sum = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, rx = 0.f, ry = 0.f, rz = 0.f;
+        int count = 0;
+        for (int ny = ty - reach; ny <= ty + reach; ++ny) {
+            if (ny < 0 || ny >= gh) continue;
+            for (int nxt = tx - reach; nxt <= tx + reach; ++nxt) {
+                if (nxt < 0 || nxt >= gw) continue;
+                const int j = ny * gw + nxt;
+                if (j == i || K.is_new[j]) continue;
+                if (K.flags[j] & (F_UNINIT | F_DEGENERATE)) continue;
+                // nearest pixel of tile j to the new surfel's centre
+                const float qx = fminf(fmaxf(ux, (float)(S * nxt)), (float)(S * nxt + S - 1));
+                const float qy = fminf(fmaxf(uy, (float)(S * ny)), (float)(S * ny + S - 1));
+                const float ddx = qx - ux, ddy = qy - uy;
+                if (!(ddx * ddx + ddy * ddy < br2)) continue;
+                const float njx = K.nx[j], njy = K.ny[j], njz = K.nz[j];
+                const float jx = (float)(S * nxt) + half, jy = (float)(S * ny) + half;
+                const float rjx = (jx - K.cx) / K.fx, rjy = (jy - K.cy) / K.fy;
+                const float cj = njx * rjx + njy * rjy + njz;
+                if (fabsf(cj) < 1e-6f) continue;
+                // Eq. 3 of plane j at ray r_s: id_j (n_j . r_s) / (n_j . r_j)
+                const float id = K.inv_depth[j] * (njx * rsx + njy * rsy + njz) / cj;
+                if (count == 0) { rx = njx; ry = njy; rz = njz; }
+                const float sg = (njx * rx + njy * ry + njz * rz) < 0.f ? -1.f : 1.f;
+                id_sum += id;
+                sx += sg * njx; sy += sg * njy; sz += sg * njz;
+                ++count;
+            }
+        }
+        if (count == 0) {
+            K.flags[i] |= F_UNINIT;
+            continue;
+        }
+        const float inv = 1.0f / (float)count;
+        const float idn = id_sum * inv;
+        sx *= inv; sy *= inv; sz *= inv;
+        const float l2 = sx * sx + sy * sy + sz * sz;
+        if (!(l2 > 0.f) || !(idn > 0.f) || !isfinite(idn) || !isfinite(l2)) {
+            K.flags[i] |= F_UNINIT;
+            continue;
+        }
+        const float il = 1.0f / sqrtf(l2);
+        K.inv_depth[i] = idn;
+        K.nx[i] = sx * il;
+        K.ny[i] = sy * il;
+        K.nz[i] = sz * il;
+        K.flags[i] &= ~F_UNINIT;
+    }
+}
+
+// --------------------------------------------------------------- GN kernel --
+
+// Cholesky solve of H d = -b in double (textbook form); false when a pivot
+// is <= 1e-12 max diag(H), i.e. H is not safely positive definite.
+__device__ __forceinline__ bool solve3_fp64(double h00, double h01, double h02, double h11,
+                                            double h12, double h22, double b0, double b1,
+                                            double b2, double& d0, double& d1, double& d2) {
+    const double maxd = fmax(h00, fmax(h11, h22));
+    if (!(maxd > 0.0) || !isfinite(maxd)) return false;
+    const double tol = 1e-12 * maxd;
+    if (!(h00 > tol) || !isfinite(h00)) return false;
+    const double l00 = sqrt(h00);
+    const double l10 = h01 / l00, l20 = h02 / l00;
+    const double p1 = h11 - l10 * l10;
+    if (!(p1 > tol) || !isfinite(p1)) return false;
+    const double l11 = sqrt(p1);
+    const double l21 = (h12 - l20 * l10) / l11;
+    const double p2 = h22 - l20 * l20 - l21 * l21;
+    if (!(p2 > tol) || !isfinite(p2)) return false;
+    const double l22 = sqrt(p2);
+    const double y0 = -b0 / l00;
+    const double y1 = (-b1 - l10 * y0) / l11;
+    const double y2 = (-b2 - l20 * y0 - l21 * y1) / l22;
+    d2 = y2 / l22;
+    d1 = (y1 - l21 * d2) / l11;
+    d0 = (y0 - l10 * d1 - l20 * d2) / l00;
+    return true;
+}
+
+// Warp constants of one (surfel, frame) pair, staged in LDS.  The
+// plane-induced homography q = H u~ + (K t) id_u (Eq. 6) is evaluated in
+// local coordinates: u = u_s + d (d = pixel offset from the surfel centre,
+// exact) and an integer anchor (X0, Y0) near the surfel centre's warp at
+// infinite depth, so that every float quantity formed per sample is small:
+//   x_p - X0 = (Ex + hx0 dx + hx1 dy + kx id_u) / q_z
+//   y_p - Y0 = (Ey + hy0 dx + hy1 dy + ky id_u) / q_z
+//   q_z      =  Qz + h6 dx  + h7 dy  + k2 id_u
+// with Ex = Q_x - X0 Q_z, Q = H u~_s, hx0 = h0 - X0 h6, kx = k0 - X0 k2, ...
+// all formed in double once per work item and rounded once to float.
+constexpr int kPairWords = 16;
+enum : int {
+    W_HX0 = 0, W_HX1, W_KX, W_EX, W_HY0, W_HY1, W_KY, W_EY, W_QZ,
+    W_LOX, W_HIX, W_LOY, W_HIY, W_B0, W_PAD0, W_PAD1
+};
+constexpr int kMaxSlots = 4;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The frame loop of one Gauss-Newton iteration for one pixel (lane): warp
+// into every neighbour frame, bilinear sample with gradient, Huber-weighted
+// residual, and the scalar chain factor a = dr/did_u.  Accumulates
+// A = sum w a^2 and B = sum w a r (the per-pixel Jacobian g is applied after
+// the loop, hoisted as the paper suggests).  LAST also sums the Huber cost.
+template <typename T, bool LAST>
+__device__ __forceinline__ void frame_loop(const float* __restrict__ pc, cptr<FrameDev> fr, int nf,
+                                           float dx, float dy, float idu, bool pix_ok,
+                                           unsigned pitch_b, float ikf, float hk, float img_scale,
+                                           float& A, float& B, float& cst, int& nvl) {
+    constexpr bool SCALED = std::is_same<T, uint8_t>::value;
+    for (int f = 0; f < nf; ++f) {
+        const float4 c0 = *(const float4*)(pc + f * kPairWords);
+        const float4 c1 = *(const float4*)(pc + f * kPairWords + 4);
+        const float4 c2 = *(const float4*)(pc + f * kPairWords + 8);
+        const float4 c3 = *(const float4*)(pc + f * kPairWords + 12);
+        const float h6 = fr[f].zrow[0], h7 = fr[f].zrow[1], k2 = fr[f].zrow[2];
+        // Eq. 6 in local coordinates (see above)
+        const float nxq = fmaf(c0.x, dx, fmaf(c0.y, dy, fmaf(c0.z, idu, c0.w)));
+        const float nyq = fmaf(c1.x, dx, fmaf(c1.y, dy, fmaf(c1.z, idu, c1.w)));
+        const float qz = fmaf(h6, dx, fmaf(h7, dy, fmaf(k2, idu, c2.x)));
+        const float rq = rcp_fast(qz);
+        const float fx = nxq * rq, fy = nyq * rq;      // x_p - X0, y_p - Y0
+        // valid iff 0 <= x_p < W-1 and 0 <= y_p < H-1 (bounds exact in float)
+        const bool v = pix_ok & (qz > 0.f) & (fx >= c2.y) & (fx < c2.z) & (fy >= c2.w) & (fy < c3.x);
+        if (v) {
+            const gptr<char> img = (gptr<char>)fr[f].img;
+            const float ffx = floorf(fx), ffy = floorf(fy);
+            const int flx = (int)ffx, fly = (int)ffy;
+            const float ax = fx - ffx;
+            const float ay = fy - ffy;
+            // byte offset of (X0 + flx, Y0 + fly); unsigned wrap-around arithmetic
+            const unsigned o0 = __float_as_uint(c3.y) + (unsigned)__mul24(fly, (int)pitch_b) +
+                                (unsigned)flx * (unsigned)sizeof(T);
+            const unsigned o1 = o0 + pitch_b;
+            const float i00 = ldg<T>((gptr<T>)(img + o0));
+            const float i01 = ldg<T>((gptr<T>)(img + o0 + sizeof(T)));
+            const float i10 = ldg<T>((gptr<T>)(img + o1));
+            const float i11 = ldg<T>((gptr<T>)(img + o1 + sizeof(T)));
+            // bilinear value and the exact gradient of the interpolant
+            const float d0 = i01 - i00, d1 = i11 - i10;
+            const float top = fmaf(ax, d0, i00);
+            const float bot = fmaf(ax, d1, i10);
+            const float gy = bot - top;
+            const float val = fmaf(ay, gy, top);
+            const float gx = fmaf(ay, d1 - d0, d0);
+            // residual (Eq. 5) and Huber IRLS weight w = min(1, k/|r|) (Eq. 8)
+            const float r = SCALED ? fmaf(val, img_scale, -ikf) : val - ikf;
+            const float ar = fabsf(r);
+            const float w = fminf(1.f, hk * rcp_fast(ar));
+            // dr/did_u = grad I . dpi/dq . K t  (Eq. 8 with dq/did_u = K t):
+            // (k0 - x_p k2) = kx - (x_p - X0) k2, likewise for y
+            const float tx_ = fmaf(-fx, k2, c0.z);
+            const float ty_ = fmaf(-fy, k2, c1.z);
+            const float a = fmaf(gx, tx_, gy * ty_) * (SCALED ? rq * img_scale : rq);
+            const float wa = w * a;
+            A = fmaf(wa, a, A);
+            B = fmaf(wa, r, B);
+            ++nvl;
+            if constexpr (LAST) cst += (ar <= hk) ? 0.5f * r * r : hk * (ar - 0.5f * hk);
+        }
+    }
+}
+
+template <typename T, int S, int TX, int TY>
+__global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __restrict__ hdr_,
+                                                           uint32_t* __restrict__ counters,
+                                                           int persistent) {
+    constexpr int LANES = S * S;                 // lanes per surfel
+    static_assert(TX * TY * LANES == kWaveSize, "a wavefront holds 64 pixels");
+    const cptr<BatchHeader> hdr = (cptr<BatchHeader>)hdr_;
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const int slot = lane / LANES;
+    const int p = lane % LANES;
+    const int px = p % S, py = p / S;
+    const int sx = slot % TX, sy = slot / TX;
+    const float half = 0.5f * (float)(S - 1);
+    const float dxp = (float)px - half, dyp = (float)py - half;   // pixel offset from u_s (exact)
+
+    const int n_kf = hdr->n_kf;
+    const int total = hdr->total_items;
+    const int iters = hdr->iters;
+    const float hk = hdr->huber_k;
+    const float kap2 = hdr->kappa_fp64 * hdr->kappa_fp64;
+    const bool depth_only = hdr->depth_only != 0;
+    const uint32_t stamp = hdr->stamp;
+    const cptr<KfDev> kfs = (cptr<KfDev>)hdr->kfs;
+
+    const int wave_global = blockIdx.x * (kBlockThreads / kWaveSize) + (threadIdx.x >> 6);
+    __shared__ float4 s_pairs[kBlockThreads / kWaveSize][kMaxSlots * kMaxNbr * kPairWords / 4];
+    float* const pairs = (float*)s_pairs[threadIdx.x >> 6];
+    // work-queue state (persistent mode): start on this XCD's queue
+    int q = persistent ? (int)(blockIdx.x % (unsigned)kXcds) % hdr->n_queues : 0;
+    int q_left = hdr->n_queues;
+
+    int hint = 0;
+    int item = persistent ? pull_item(hdr_, counters, q, q_left, lane, total) : wave_global;
+    for (; item < total;
+         item = persistent ? pull_item(hdr_, counters, q, q_left, lane, total) : total) {
+        item = __builtin_amdgcn_readfirstlane(item);
+        const int k = find_kf(kfs, n_kf, item, hint);
+        hint = k;
+        const cptr<KfDev> K = kfs + k;
+        const int g = item - K->item_base;
+        const int gx = g % K->groups_x, gy = g / K->groups_x;
+        const int tx = gx * TX + sx, ty = gy * TY + sy;
+        const bool tile_ok = (tx < K->gw) && (ty < K->gh);
+        const int sidx = ty * K->gw + tx;
+        const float usx = (float)(S * tx) + half, usy = (float)(S * ty) + half;
+        const float rsx = (usx - K->cx) / K->fx, rsy = (usy - K->cy) / K->fy;   // r_s (z = 1)
+        const float drx = dxp / K->fx, dry = dyp / K->fy;                      // r_u - r_s
+        const int nf = K->n_nbr;
+        const float img_scale = K->img_scale;
+        const unsigned pitch_b = (unsigned)K->nbr_pitch_b;
+        {
+            // warp constants of every (surfel slot, frame) pair of this item,
+            // one pair per lane, in double
+            wave_sync();
+            const int ps = lane / kMaxNbr, pf = lane % kMaxNbr;
+            if (ps < TX * TY && pf < nf) {
+                const int ptx = gx * TX + ps % TX, pty = gy * TY + ps / TX;
+                const double qsx = (double)(S * ptx) + (double)half;
+                const double qsy = (double)(S * pty) + (double)half;
+                const gptr<FrameDev> F = (gptr<FrameDev>)(hdr->frames + K->frame_base + pf);
+                const gptr<double> hm = F->hm;
+                const gptr<double> kt = F->kt;
+                const double Qx = fma(hm[0], qsx, fma(hm[1], qsy, hm[2]));
+                const double Qy = fma(hm[3], qsx, fma(hm[4], qsy, hm[5]));
+                const double Qz = fma(hm[6], qsx, fma(hm[7], qsy, hm[8]));
+                double X0 = 0.0, Y0 = 0.0;
+                if (Qz > 0.0) {
+                    X0 = rint(fmin(fmax(Qx / Qz, -20000.0), 20000.0));
+                    Y0 = rint(fmin(fmax(Qy / Qz, -20000.0), 20000.0));
+                }
+                float* w = pairs + (ps * kMaxNbr + pf) * kPairWords;
+                w[W_HX0] = (float)(hm[0] - X0 * hm[6]);
+                w[W_HX1] = (float)(hm[1] - X0 * hm[7]);
+                w[W_KX] = (float)(kt[0] - X0 * kt[2]);
+                w[W_EX] = (float)(Qx - X0 * Qz);
+                w[W_HY0] = (float)(hm[3] - Y0 * hm[6]);
+                w[W_HY1] = (float)(hm[4] - Y0 * hm[7]);
+                w[W_KY] = (float)(kt[1] - Y0 * kt[2]);
+                w[W_EY] = (float)(Qy - Y0 * Qz);
+                w[W_QZ] = (float)Qz;
+                w[W_LOX] = (float)(-X0);
+                w[W_HIX] = (float)((double)(K->width - 1) - X0);
+                w[W_LOY] = (float)(-Y0);
+                w[W_HIY] = (float)((double)(K->height - 1) - Y0);
+                w[W_B0] = __uint_as_float((unsigned)(int)Y0 * pitch_b + (unsigned)(int)X0 * (unsigned)sizeof(T));
+                w[W_PAD0] = 0.f;
+                w[W_PAD1] = 0.f;
+            }
+            wave_sync();
+        }
+        const float* const pc = pairs + slot * kMaxNbr * kPairWords;
+        // the frame table pointer is wave-uniform: keep it in SGPRs
+        const uint64_t fr_bits = (uint64_t)(const void*)(hdr->frames + K->frame_base);
+        const uint32_t fr_lo = __builtin_amdgcn_readfirstlane((uint32_t)fr_bits);
+        const uint32_t fr_hi = __builtin_amdgcn_readfirstlane((uint32_t)(fr_bits >> 32));
+        const cptr<FrameDev> fr = (cptr<FrameDev>)(((uint64_t)fr_hi << 32) | fr_lo);
+        const gmut<float> s_id = (gmut<float>)K->inv_depth;
+        const gmut<float> s_nx = (gmut<float>)K->nx;
+        const gmut<float> s_ny = (gmut<float>)K->ny;
+        const gmut<float> s_nz = (gmut<float>)K->nz;
+        const gmut<uint32_t> s_flags = (gmut<uint32_t>)K->flags;
+
+        float id = 0.f, nx = 0.f, ny = 0.f, nz = -1.f, ikf = 0.f;
+        uint32_t flags = 0u;
+        if (tile_ok) {
+            id = s_id[sidx];
+            nx = s_nx[sidx]; ny = s_ny[sidx]; nz = s_nz[sidx];
+            flags = s_flags[sidx] & ~F_GN_BITS;
+            const gptr<T> kimg = (gptr<T>)K->kf_img;
+            ikf = ldg<T>(kimg + ((unsigned)(S * ty + py) * (unsigned)K->kf_pitch + (unsigned)(S * tx + px))) *
+                  K->kf_scale;
+        }
+        bool alive = tile_ok;
+        bool updated = false;
+        float cost_out = 0.f;
+        int nv_out = 0;
+
+        for (int it = 0; it < iters; ++it) {
+            const bool last = (it == iters - 1);
+            const float c = nx * rsx + ny * rsy + nz;     // n . r_s
+            if (alive && fabsf(c) < 1e-6f) {
+                flags |= F_DEGENERATE;
+                alive = false;
+                cost_out = 0.f;
+                nv_out = 0;
+            }
+            // tangent basis of n: b1 = normalise(e - (e.n) n), b2 = n x b1
+            const bool ex = fabsf(nx) < 0.9f;
+            const float en = ex ? nx : ny;
+            float b1x = (ex ? 1.f : 0.f) - en * nx;
+            float b1y = (ex ? 0.f : 1.f) - en * ny;
+            float b1z = -en * nz;
+            const float ib = __frsqrt_rn(b1x * b1x + b1y * b1y + b1z * b1z);
+            b1x *= ib; b1y *= ib; b1z *= ib;
+            const float b2x = ny * b1z - nz * b1y;
+            const float b2y = nz * b1x - nx * b1z;
+            const float b2z = nx * b1y - ny * b1x;
+            // frame-independent per-pixel terms (Eq. 3, Eq. 9)
+            const float inv_c = 1.0f / c;
+            const float sigma = (nx * drx + ny * dry) * inv_c;
+            const float idu = fmaf(id, sigma, id);
+            const float dx3 = fmaf(-sigma, rsx, drx);
+            const float dy3 = fmaf(-sigma, rsy, dry);
+            const float dz3 = -sigma;
+            const float kk = id * inv_c;
+            const float g0 = 1.f + sigma;
+            const float g1 = depth_only ? 0.f : kk * (b1x * dx3 + b1y * dy3 + b1z * dz3);
+            const float g2 = depth_only ? 0.f : kk * (b2x * dx3 + b2y * dy3 + b2z * dz3);
+            const bool pix_ok = alive && (idu > 0.f);
+
+            float A = 0.f, B = 0.f, cst = 0.f;
+            int nvl = 0;
+            if (last)
+                frame_loop<T, true>(pc, fr, nf, dxp, dyp, idu, pix_ok, pitch_b, ikf, hk, img_scale, A, B,
+                                    cst, nvl);
+            else
+                frame_loop<T, false>(pc, fr, nf, dxp, dyp, idu, pix_ok, pitch_b, ikf, hk, img_scale, A, B,
+                                     cst, nvl);
+            // J^T W J = sum_u A_u g g^T, J^T W r = sum_u B_u g (frame sum hoisted)
+            const float ag0 = A * g0, ag1 = A * g1, ag2 = A * g2;
+            const float H00 = group_sum<LANES>(ag0 * g0);
+            const float H01 = group_sum<LANES>(ag0 * g1);
+            const float H02 = group_sum<LANES>(ag0 * g2);
+            const float H11 = group_sum<LANES>(ag1 * g1);
+            const float H12 = group_sum<LANES>(ag1 * g2);
+            const float H22 = group_sum<LANES>(ag2 * g2);
+            const float bb0 = group_sum<LANES>(B * g0);
+            const float bb1 = group_sum<LANES>(B * g1);
+            const float bb2 = group_sum<LANES>(B * g2);
+            const int nv = group_sum<LANES>(nvl);
+            if (last) {
+                cost_out = group_sum<LANES>(cst);
+            }
+            if (!alive) continue;
+            nv_out = nv;
+            if (nv < 3) {
+                flags |= F_FEW_SAMPLES;
+                continue;
+            }
+            float d0s = 0.f, d1s = 0.f, d2s = 0.f;
+            if (depth_only) {
+                if (H00 > 0.f && isfinite(H00)) {
+                    d0s = -bb0 / H00;
+                } else {
+                    flags |= F_SOLVE_FAIL;
+                    continue;
+                }
+            } else {
+                // equilibrate: E = D^-1/2 H D^-1/2 (unit diagonal)
+                const float maxd = fmaxf(H00, fmaxf(H11, H22));
+                bool need64 = !(H00 > 0.f) || !(H11 > 0.f) || !(H22 > 0.f) || !isfinite(maxd);
+                if (!need64) {
+                    const float e0 = __frsqrt_rn(H00), e1 = __frsqrt_rn(H11), e2 = __frsqrt_rn(H22);
+                    const float e01 = H01 * e0 * e1, e02 = H02 * e0 * e2, e12 = H12 * e1 * e2;
+                    // adjugate and determinant of E
+                    const float c00 = fmaf(-e12, e12, 1.f), c11 = fmaf(-e02, e02, 1.f);
+                    const float c22 = fmaf(-e01, e01, 1.f);
+                    const float c01 = fmaf(e02, e12, -e01), c02 = fmaf(e01, e12, -e02);
+                    const float c12 = fmaf(e01, e02, -e12);
+                    const float det = fmaf(e01, c01, fmaf(e02, c02, c00));
+                    // kappa_F(E)^2 = ||E||_F^2 ||adj E||_F^2 / det^2  (>= kappa_2(E)^2)
+                    const float fro2 = 3.f + 2.f * (e01 * e01 + e02 * e02 + e12 * e12);
+                    const float adj2 = c00 * c00 + c11 * c11 + c22 * c22 +
+                                       2.f * (c01 * c01 + c02 * c02 + c12 * c12);
+                    // raw Cholesky pivots are H_jj times the equilibrated ones
+                    const float p1 = c22;                 // 1 - e01^2
+                    const float p2 = det / p1;
+                    need64 = !(fro2 * adj2 <= kap2 * det * det) || !(det > 0.f) ||
+                             !(H11 * p1 > 1e-10f * maxd) || !(H22 * p2 > 1e-10f * maxd);
+                    if (!need64) {
+                        const float bh0 = bb0 * e0, bh1 = bb1 * e1, bh2 = bb2 * e2;
+                        const float idet = 1.0f / det;
+                        d0s = -(c00 * bh0 + c01 * bh1 + c02 * bh2) * idet * e0;
+                        d1s = -(c01 * bh0 + c11 * bh1 + c12 * bh2) * idet * e1;
+                        d2s = -(c02 * bh0 + c12 * bh1 + c22 * bh2) * idet * e2;
+                    }
+                }
+                if (need64) {
+                    flags |= F_FP64_SOLVE;
+                    double dd0 = 0.0, dd1 = 0.0, dd2 = 0.0;
+                    if (solve3_fp64(H00, H01, H02, H11, H12, H22, bb0, bb1, bb2, dd0, dd1, dd2)) {
+                        d0s = (float)dd0; d1s = (float)dd1; d2s = (float)dd2;
+                    } else {
+                        flags |= F_SOLVE_FAIL;
+                        continue;
+                    }
+                }
+            }
+            // update: id_s += d0; n = normalise(n + d1 b1 + d2 b2)
+            const float idn = id + d0s;
+            const float mx = fmaf(d1s, b1x, fmaf(d2s, b2x, nx));
+            const float my = fmaf(d1s, b1y, fmaf(d2s, b2y, ny));
+            const float mz = fmaf(d1s, b1z, fmaf(d2s, b2z, nz));
+            const float l2 = mx * mx + my * my + mz * mz;
+            if (!(idn > 0.f) || !isfinite(idn) || !(l2 > 0.f) || !isfinite(l2)) {
+                flags |= F_REJECTED;
+                continue;
+            }
+            const float il = __frsqrt_rn(l2);
+            id = idn;
+            nx = mx * il; ny = my * il; nz = mz * il;
+            updated = true;
+        }
+        if (tile_ok && p == 0) {
+            s_id[sidx] = id;
+            s_nx[sidx] = nx; s_ny[sidx] = ny; s_nz[sidx] = nz;
+            s_flags[sidx] = flags;
+            ((gmut<float>)K->cost)[sidx] = iters > 0 ? cost_out : 0.f;
+            ((gmut<uint32_t>)K->nvalid)[sidx] = (uint32_t)(iters > 0 ? nv_out : 0);
+            if (updated) ((gmut<uint32_t>)K->last_update)[sidx] = stamp;
+        }
+    }
+}
+
+// ----------------------------------------------------------- render kernel --
+
+// Inverse Depth Calculation section: each pixel takes Eq. 3 of its surfel.
+__global__ void render_kernel(const BatchHeader* __restrict__ hdr) {
+    const int64_t total = hdr->total_pixels;
+    int hint = 0;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const KfDev* kh = &hdr->kfs[hint];
+        if (!(kh->inv_depth_out && g >= kh->pixel_base &&
+              g < kh->pixel_base + (int64_t)kh->width * kh->height)) {
+            int lo = 0, hi = hdr->n_kf - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (hdr->kfs[mid].pixel_base <= g) lo = mid; else hi = mid - 1;
+            }
+            // skip keyframes without output (they add no pixels)
+            while (lo < hdr->n_kf - 1 && !hdr->kfs[lo].inv_depth_out) ++lo;
+            hint = lo;
+        }
+        const KfDev& K = hdr->kfs[hint];
+        const int64_t o = g - K.pixel_base;
+        const int x = (int)(o % K.width), y = (int)(o / K.width);
+        const int S = K.patch;
+        const int tx = x / S, ty = y / S;
+        float out = 0.f;
+        int idx = -1;
+        if (tx < K.gw && ty < K.gh) {
+            const int i = ty * K.gw + tx;
+            if (!(K.flags[i] & (F_DEGENERATE | F_UNINIT))) {
+                const float half = 0.5f * (float)(S - 1);
+                const float usx = (float)(S * tx) + half, usy = (float)(S * ty) + half;
+                const float rsx = (usx - K.cx) / K.fx, rsy = (usy - K.cy) / K.fy;
+                const float drx = ((float)x - usx) / K.fx, dry = ((float)y - usy) / K.fy;
+                const float nx = K.nx[i], ny = K.ny[i], nz = K.nz[i];
+                const float c = nx * rsx + ny * rsy + nz;
+                if (fabsf(c) >= 1e-6f) {
+                    const float id = K.inv_depth[i];
+                    const float sigma = (nx * drx + ny * dry) / c;
+                    const float idu = fmaf(id, sigma, id);
+                    if (idu > 0.f && isfinite(idu)) {
+                        out = idu;
+                        idx = i;
+                    }
+                }
+            }
+        }
+        K.inv_depth_out[o] = out;
+        if (K.index_out) K.index_out[o] = idx;
+    }
+}
+
+// --------------------------------------------------------- quantize kernel --
+
+__global__ void quantize_kernel(const float* __restrict__ src, int src_pitch, void* __restrict__ dst,
+                                int dst_pitch, int width, int height, int dtype, float scale) {
+    const int64_t total = (int64_t)width * height;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(g % width), y = (int)(g / width);
+        const float v = src[(size_t)y * src_pitch + x];
+        if (dtype == 1) {
+            ((_Float16*)dst)[(size_t)y * dst_pitch + x] = (_Float16)(v / scale);
+        } else {
+            float c = rintf(v / scale);
+            c = fminf(fmaxf(c, 0.f), 255.f);
+            ((uint8_t*)dst)[(size_t)y * dst_pitch + x] = (uint8_t)c;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launchers --
+
+hipError_t launch_setup(const BatchHeader* hdr, uint32_t* counters, int n_frames_cap, hipStream_t s) {
+    int n = n_frames_cap > kNumCounters ? n_frames_cap : kNumCounters;
+    int blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(setup_kernel, dim3(blocks), dim3(256), 0, s, hdr, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const BatchHeader* hdr, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(init_kernel, dim3(grid), dim3(256), 0, s, hdr);
+    return hipGetLastError();
+}
+
+hipError_t launch_render(const BatchHeader* hdr, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(render_kernel, dim3(grid), dim3(256), 0, s, hdr);
+    return hipGetLastError();
+}
+
+hipError_t launch_quantize(const float* src, int src_pitch, void* dst, int dst_pitch, int width,
+                           int height, int dtype, float scale, hipStream_t s) {
+    int64_t total = (int64_t)width * height;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(quantize_kernel, dim3(blocks), dim3(256), 0, s, src, src_pitch, dst, dst_pitch,
+                       width, height, dtype, scale);
+    return hipGetLastError();
+}
+
+template <typename T, int S, int TX, int TY>
+static void* gn_ptr() {
+    return (void*)&gn_kernel<T, S, TX, TY>;
+}
+
+static void* gn_select(const GnVariant& v) {
+    if (v.lds) return nullptr;
+#define SGN_PICK(T)                                                              \
+    if (v.patch == 8 && v.tiles_x == 1 && v.tiles_y == 1) return gn_ptr<T, 8, 1, 1>(); \
+    if (v.patch == 4 && v.tiles_x == 4 && v.tiles_y == 1) return gn_ptr<T, 4, 4, 1>(); \
+    if (v.patch == 4 && v.tiles_x == 2 && v.tiles_y == 2) return gn_ptr<T, 4, 2, 2>(); \
+    if (v.patch == 4 && v.tiles_x == 1 && v.tiles_y == 4) return gn_ptr<T, 4, 1, 4>(); \
+    return nullptr;
+    if (v.dtype == 0) { SGN_PICK(float) }
+    if (v.dtype == 1) { SGN_PICK(_Float16) }
+    if (v.dtype == 2) { SGN_PICK(uint8_t) }
+#undef SGN_PICK
+    return nullptr;
+}
+
+bool gn_variant_supported(const GnVariant& v) { return gn_select(v) != nullptr; }
+
+int gn_blocks_per_cu(const GnVariant& v) {
+    void* f = gn_select(v);
+    if (!f) return 0;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kBlockThreads, 0) != hipSuccess) return 0;
+    return n;
+}
+
+hipError_t launch_gn(const GnVariant& v, const BatchHeader* hdr, uint32_t* counters, int persistent,
+                     int grid_blocks, hipStream_t s) {
+    void* f = gn_select(v);
+    if (!f) return hipErrorInvalidValue;
+    void* args[] = {(void*)&hdr, (void*)&counters, (void*)&persistent};
+    return hipLaunchKernel(f, dim3(grid_blocks), dim3(kBlockThreads), args, 0, s);
+}
+
+}  // namespace sgn

@@ -1,0 +1,115 @@
+"""Keyframe-level helpers over the C ABI: device-resident keyframes and
+surfel state as torch tensors, and the plain (one keyframe at a time) and
+batched update calls.  Marshalling only; all arithmetic runs in the HIP
+kernels of libsurfgn.so."""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import surfgn as sg
+
+STORAGE = {"f32": sg.SGN_F32, "f16": sg.SGN_F16, "u8": sg.SGN_U8}
+U8_SCALE = 1.0 / 255.0
+
+
+class DeviceKeyframe:
+    """One keyframe, its neighbour frames and its surfels, resident on the GPU.
+
+    images: float32 tensors (any device) of the sampled values; they are
+    uploaded and, for f16/u8 storage, quantised on the device by the
+    library's quantize kernel.
+    """
+
+    def __init__(self, ctx: sg.Context, kf_image, nbr_images, R, t, K, patch: int,
+                 init_id, init_n, is_new=None, storage: str = "f32", render: bool = True,
+                 index_map: bool = False, flags=None):
+        dev = torch.device("cuda", ctx.device)
+        self.ctx = ctx
+        self.storage = storage
+        self.patch = int(patch)
+        self.K = tuple(float(v) for v in K)
+        self.R = np.asarray(R, np.float64)
+        self.t = np.asarray(t, np.float64)
+        kf32 = torch.as_tensor(kf_image, dtype=torch.float32).to(dev).contiguous()
+        nb32 = torch.as_tensor(nbr_images, dtype=torch.float32).to(dev).contiguous()
+        self.height, self.width = kf32.shape
+        self.n_nbr = int(nb32.shape[0])
+        self.scale = 1.0
+        if storage == "f32":
+            self.kf_img, self.nbr_imgs = kf32, nb32
+        else:
+            code = STORAGE[storage]
+            tdt = torch.float16 if storage == "f16" else torch.uint8
+            self.scale = 1.0 if storage == "f16" else U8_SCALE
+            self.kf_img = torch.empty((self.height, self.width), dtype=tdt, device=dev)
+            self.nbr_imgs = torch.empty((self.n_nbr, self.height, self.width), dtype=tdt, device=dev)
+            for src, dst in [(kf32, self.kf_img)] + [(nb32[i], self.nbr_imgs[i]) for i in range(self.n_nbr)]:
+                sg.sgn_quantize(ctx.handle, src.data_ptr(), src.stride(0),
+                                sg.sgn_image(dst.data_ptr(), self.width, self.height, dst.stride(0),
+                                             code, float(self.scale)))
+        self.view = sg.KeyframeView(self.kf_img, [self.nbr_imgs[i] for i in range(self.n_nbr)],
+                                    self.R, self.t, self.K, self.patch, self.scale)
+        self.state = sg.SurfelState.from_arrays(init_id, init_n, flags=flags, device=dev)
+        self.is_new = None
+        if is_new is not None:
+            self.is_new = torch.as_tensor(np.asarray(is_new, np.uint8).reshape(-1), device=dev)
+        self.inv_depth_out = (torch.zeros((self.height, self.width), dtype=torch.float32, device=dev)
+                              if render else None)
+        self.index_out = (torch.full((self.height, self.width), -1, dtype=torch.int32, device=dev)
+                          if (render and index_map) else None)
+
+    @classmethod
+    def from_scene(cls, ctx, kf, storage="f32", render=True, index_map=False, with_new=True):
+        return cls(ctx, kf.kf_image, kf.nbr_images, kf.R, kf.t, kf.K, kf.patch, kf.init_id,
+                   kf.init_n, is_new=kf.is_new if (with_new and kf.is_new.any()) else None,
+                   storage=storage, render=render, index_map=index_map)
+
+    @property
+    def grid(self):
+        return (self.width // self.patch, self.height // self.patch)
+
+    @property
+    def n_surfels(self):
+        gw, gh = self.grid
+        return gw * gh
+
+    def dequantized_images(self):
+        """(kf, nbrs) as float64 numpy arrays of the exact values the kernels
+        sample (stored code times scale)."""
+        kf = self.kf_img.double().cpu().numpy() * self.scale
+        nb = self.nbr_imgs.double().cpu().numpy() * self.scale
+        return kf, nb
+
+    def item(self, render: bool = True, init: bool = True) -> sg.sgn_batch_item:
+        return sg.sgn_batch_item(
+            self.view.c, self.state.c,
+            self.is_new.data_ptr() if (init and self.is_new is not None) else None,
+            self.inv_depth_out.data_ptr() if (render and self.inv_depth_out is not None) else None,
+            self.index_out.data_ptr() if (render and self.index_out is not None) else None)
+
+    def reset_state(self, init_id, init_n, flags=None):
+        self.state = sg.SurfelState.from_arrays(init_id, init_n, flags=flags,
+                                                device=self.state.inv_depth.device)
+
+
+def update_plain(ctx: sg.Context, dk: DeviceKeyframe, prm: sg.sgn_params,
+                 plan: Optional[sg.sgn_plan] = None, render: bool = True):
+    """The plain single-keyframe form: init (if any new surfels), the
+    Gauss-Newton iterations (one wavefront per work item), render."""
+    if dk.is_new is not None:
+        sg.sgn_init_from_neighbours(ctx.handle, dk.view.c, dk.state.c, dk.is_new.data_ptr(), prm)
+    sg.sgn_optimize_keyframe(ctx.handle, dk.view.c, dk.state.c, prm, plan)
+    if render and dk.inv_depth_out is not None:
+        sg.sgn_render_inverse_depth(ctx.handle, dk.view.c, dk.state.c, dk.inv_depth_out.data_ptr(),
+                                    dk.index_out.data_ptr() if dk.index_out is not None else 0)
+
+
+def update_batch(ctx: sg.Context, dks: Sequence[DeviceKeyframe], prm: sg.sgn_params,
+                 plan: Optional[sg.sgn_plan] = None, render: bool = True):
+    items = sg.batch_array([d.item(render=render) for d in dks])
+    sg.sgn_optimize_batch(ctx.handle, items, len(dks), prm, plan)
+    return items

@@ -1,0 +1,77 @@
+"""Element-by-element comparison of device results with the FP64 oracle."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+# Tolerance of the FP32 form: |delta id| / id <= 1e-4 and normal angle <= 0.01 deg.
+REL_TOL = 1e-4
+ANGLE_TOL_DEG = 0.01
+# flag bits compared between the two sides (the device-only FP64_SOLVE bit is not)
+CMP_FLAGS = (oracle.DEGENERATE | oracle.FEW_SAMPLES | oracle.SOLVE_FAIL | oracle.REJECTED |
+             oracle.UNINIT)
+
+
+def angle_deg(n1, n2):
+    n1 = np.asarray(n1, np.float64).reshape(-1, 3)
+    n2 = np.asarray(n2, np.float64).reshape(-1, 3)
+    c = np.linalg.norm(np.cross(n1, n2), axis=1)
+    d = np.abs((n1 * n2).sum(1))
+    return np.degrees(np.arctan2(c, d))
+
+
+def oracle_keyframe(dk):
+    kf, nb = dk.dequantized_images()
+    return oracle.OracleKeyframe(dk.K, kf, nb, dk.R, dk.t, dk.patch)
+
+
+def oracle_state(init_id, init_n, flags=None):
+    """The device's float32 starting state, exactly, in double."""
+    return oracle.new_state(np.asarray(init_id, np.float32).astype(np.float64),
+                            np.asarray(init_n, np.float32).astype(np.float64), flags)
+
+
+def run_oracle(dk, init_id, init_n, is_new, params: "oracle.OracleParams", subset=None):
+    ok = oracle_keyframe(dk)
+    st = oracle_state(init_id, init_n)
+    if is_new is not None and np.any(is_new):
+        if subset is not None:
+            # the initialisation reads only non-new surfels, so a subset's
+            # starting state is computed exactly by initialising that subset
+            oracle.init_from_neighbours(ok, st, is_new, params, subset=subset)
+        else:
+            oracle.init_from_neighbours(ok, st, is_new, params)
+    oracle.optimize(ok, st, params, subset=subset)
+    return ok, st
+
+
+def compare(dev: dict, st: dict, idx=None):
+    """Per-surfel errors of device state `dev` (SurfelState.to_host()) against
+    oracle state `st`, on indices idx (default: all)."""
+    if idx is None:
+        idx = np.arange(st["inv_depth"].shape[0])
+    idx = np.asarray(idx)
+    g_id = dev["inv_depth"][idx].astype(np.float64)
+    o_id = st["inv_depth"][idx]
+    g_n = dev["n"][idx].astype(np.float64)
+    o_n = np.stack([st["nx"][idx], st["ny"][idx], st["nz"][idx]], 1)
+    rel = np.abs(g_id - o_id) / np.abs(o_id)
+    ang = angle_deg(g_n, o_n)
+    gf = dev["flags"][idx] & CMP_FLAGS
+    of = st["flags"][idx].astype(np.uint32) & CMP_FLAGS
+    same_flags = gf == of
+    ok = (rel <= REL_TOL) & (ang <= ANGLE_TOL_DEG)
+    return {
+        "idx": idx, "rel": rel, "ang": ang, "same_flags": same_flags, "within": ok,
+        "kappa": st["kappa"][idx], "nvalid_dev": dev["nvalid"][idx], "nvalid_or": st["nvalid"][idx],
+        "cost_dev": dev["cost"][idx], "cost_or": st["cost"][idx],
+    }
+
+
+def summary(c: dict) -> str:
+    n = c["idx"].size
+    return (f"n={n} within={c['within'].mean():.5f} flags_equal={c['same_flags'].mean():.5f} "
+            f"rel max={c['rel'].max():.3g} p99={np.percentile(c['rel'], 99):.3g} "
+            f"ang max={c['ang'].max():.3g} p99={np.percentile(c['ang'], 99):.3g} "
+            f"nvalid_equal={(c['nvalid_dev'] == c['nvalid_or']).mean():.5f}")

@@ -1,0 +1,108 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Inputs are seeded synthetic scenes of the workload shapes; the oracle runs
+on exactly the values the kernels sample (dequantised f16/u8 included) and
+from the same float32 starting state.  Tolerance of the FP32 form:
+|delta id| / id <= 1e-4 and normal angle <= 0.01 degrees per surfel.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from scenegen import make_keyframe, spec_for_config
+from tests.parity import ANGLE_TOL_DEG, REL_TOL, compare, oracle_keyframe, oracle_state, run_oracle, summary
+
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    _need_gpu()
+    from paper_1910_01997_amd import surfgn as sg
+    c = sg.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _params(iters, **kw):
+    from paper_1910_01997_amd import surfgn as sg
+    return sg.params(iters=iters, **kw)
+
+
+def _oparams(iters, **kw):
+    return oracle.OracleParams(iters=iters, **kw)
+
+
+def _plain(ctx, kf, storage="f32", plan=None, iters=None, with_new=True):
+    from paper_1910_01997_amd import engine
+    dk = engine.DeviceKeyframe.from_scene(ctx, kf, storage=storage, with_new=with_new)
+    it = kf.iters if iters is None else iters
+    engine.update_plain(ctx, dk, _params(it), plan=plan)
+    torch.cuda.synchronize()
+    return dk, dk.state.to_host()
+
+
+def _assert_parity(c, min_fraction=1.0, label=""):
+    print(label, summary(c), flush=True)
+    same = c["same_flags"]
+    assert same.mean() >= 0.999, f"{label}: flag mismatches {np.flatnonzero(~same)[:10]}"
+    frac = c["within"][same].mean()
+    assert frac >= min_fraction, f"{label}: {summary(c)}"
+
+
+def test_workload0_plain_f32(ctx):
+    kf = make_keyframe(spec_for_config(0), device="cuda")
+    print("case workload0 160x120 S=8 N=2 f32", flush=True)
+    dk, dev = _plain(ctx, kf)
+    _, st = run_oracle(dk, kf.init_id, kf.init_n, None, _oparams(kf.iters))
+    _assert_parity(compare(dev, st), label="w0")
+
+
+def test_workload1_init_matches_oracle(ctx):
+    from paper_1910_01997_amd import engine
+    from paper_1910_01997_amd import surfgn as sg
+    kf = make_keyframe(spec_for_config(1), device="cuda")
+    print("case workload1 init", flush=True)
+    dk = engine.DeviceKeyframe.from_scene(ctx, kf)
+    sg.sgn_init_from_neighbours(ctx.handle, dk.view.c, dk.state.c, dk.is_new.data_ptr(), _params(0))
+    torch.cuda.synchronize()
+    dev = dk.state.to_host()
+    ok = oracle_keyframe(dk)
+    st = oracle_state(kf.init_id, kf.init_n)
+    oracle.init_from_neighbours(ok, st, kf.is_new, _oparams(0))
+    c = compare(dev, st)
+    print("init", summary(c), flush=True)
+    assert np.all(c["same_flags"])
+    assert c["rel"].max() < 2e-6 and c["ang"].max() < 2e-4
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "u8"])
+def test_workload1_plain(ctx, storage):
+    kf = make_keyframe(spec_for_config(1), device="cuda")
+    print(f"case workload1 640x480 S=4 N=8 {storage}", flush=True)
+    dk, dev = _plain(ctx, kf, storage=storage)
+    _, st = run_oracle(dk, kf.init_id, kf.init_n, kf.is_new, _oparams(kf.iters))
+    _assert_parity(compare(dev, st), min_fraction=0.99, label=f"w1 {storage}")
+
+
+def test_render_matches_oracle(ctx):
+    kf = make_keyframe(spec_for_config(1), device="cuda")
+    dk, dev = _plain(ctx, kf)
+    ok = oracle_keyframe(dk)
+    st = oracle_state(dev["inv_depth"], dev["n"], dev["flags"])
+    idm, ind = oracle.render(ok, st)
+    got = dk.inv_depth_out.cpu().numpy().astype(np.float64)
+    both = (idm > 0) & (got > 0)
+    assert (both == (idm > 0)).mean() > 0.9999
+    ids = dev["inv_depth"][ind[both]]
+    assert np.max(np.abs(got[both] - idm[both]) / ids) < 2e-6
