@@ -66,7 +66,8 @@ class SurfelsC(C.Structure):
 
 class ParamsC(C.Structure):
     _fields_ = [("iters", C.c_int32), ("huber_k", C.c_double), ("depth_only", C.c_int32),
-                ("beta_r", C.c_double), ("stamp", C.c_uint32), ("lm_lambda", C.c_double)]
+                ("beta_r", C.c_double), ("stamp", C.c_uint32), ("lm_lambda", C.c_double),
+                ("perturb", C.c_double), ("perturb_seed", C.c_uint32)]
 
 
 _lib = None
@@ -158,11 +159,14 @@ class OracleParams:
     beta_r: Optional[float] = None   # default: the tile edge S
     stamp: int = 1
     lm_lambda: float = 0.0
+    perturb: float = 0.0        # conditioning probe (tests only), 0 = off
+    perturb_seed: int = 0
 
     def c(self, patch: int) -> ParamsC:
         br = float(self.beta_r) if self.beta_r is not None else float(patch)
         return ParamsC(int(self.iters), float(self.huber_k), int(bool(self.depth_only)), br,
-                       int(self.stamp), float(self.lm_lambda))
+                       int(self.stamp), float(self.lm_lambda), float(self.perturb),
+                       int(self.perturb_seed))
 
 
 class OracleKeyframe:

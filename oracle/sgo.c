@@ -302,6 +302,18 @@ static int apply_update(double id_s, const double n[3], const double b1[3], cons
     return 1;
 }
 
+/* Conditioning probe (test use only): a uniform number in [-1, 1) from a
+ * 64-bit mix of (seed, surfel, iteration, component) (splitmix64 finaliser). */
+static double probe_uniform(uint32_t seed, int32_t surfel, int it, int comp) {
+    uint64_t z = ((uint64_t)seed << 40) ^ ((uint64_t)(uint32_t)surfel << 12) ^ ((uint64_t)it << 3) ^
+                 (uint64_t)comp;
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
 static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_params* p, int32_t i) {
     int S = kf->patch;
     int gw = kf->kf.width / S;
@@ -367,6 +379,12 @@ static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_param
                 continue;
             }
             lambda = fmax(lambda * 0.1, 1e-9);
+        }
+        if (p->perturb > 0.0) {
+            id_new *= 1.0 + p->perturb * probe_uniform(p->perturb_seed, i, it, 0);
+            for (int k = 0; k < 3; ++k)
+                n_new[k] *= 1.0 + p->perturb * probe_uniform(p->perturb_seed, i, it, 1 + k);
+            normalize3(n_new);
         }
         id_s = id_new;
         n[0] = n_new[0]; n[1] = n_new[1]; n[2] = n_new[2];

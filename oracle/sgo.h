@@ -58,6 +58,10 @@ typedef struct {
     double beta_r;            /* neighbour radius for initialisation (pixels) */
     uint32_t stamp;           /* written to last_update */
     double lm_lambda;         /* 0: pure Gauss-Newton; >0: Levenberg-Marquardt start damping */
+    double perturb;           /* test probe, 0 = off: after every accepted step, scale id_s and
+                                 each normal component by (1 + perturb * u), u in [-1, 1) from a
+                                 counter hash of (perturb_seed, surfel, iteration, component) */
+    uint32_t perturb_seed;
 } sgo_params;
 
 enum {

@@ -199,89 +199,90 @@ def _make_planes(spec: SceneSpec, rng: np.random.Generator) -> List[Plane]:
 
 
 def _render(planes: Sequence[Plane], K, W, H, R, t, device, noise_sigma, gen):
-    """Ray-cast one view (pose X_cam = R X_kf + t) of the bounded planes."""
+    """Ray-cast one view (pose X_cam = R X_kf + t) of the bounded planes,
+    all planes at once."""
     fx, fy, cx, cy = K
     dt = torch.float64
-    ys = torch.arange(H, device=device, dtype=dt).view(H, 1).expand(H, W)
-    xs = torch.arange(W, device=device, dtype=dt).view(1, W).expand(H, W)
+    dev = torch.device(device)
+    ys = torch.arange(H, device=dev, dtype=dt).view(H, 1).expand(H, W)
+    xs = torch.arange(W, device=dev, dtype=dt).view(1, W).expand(H, W)
     dcam = torch.stack([(xs - cx) / fx, (ys - cy) / fy, torch.ones_like(xs)], dim=-1)
-    Rt = torch.as_tensor(np.asarray(R).T.copy(), device=device, dtype=dt)
-    C = -(torch.as_tensor(np.asarray(R).T @ np.asarray(t), device=device, dtype=dt))
-    d = dcam @ Rt.T                       # ray directions in keyframe coordinates
-    best = torch.full((H, W), float("inf"), device=device, dtype=dt)
-    pid = torch.full((H, W), -1, device=device, dtype=torch.int16)
+    Rt = torch.as_tensor(np.asarray(R).T.copy(), device=dev, dtype=dt)
+    C = -(torch.as_tensor(np.asarray(R).T @ np.asarray(t), device=dev, dtype=dt))
+    d = (dcam @ Rt.T).reshape(-1, 3)                 # ray directions, keyframe coordinates
+    quads = [i for i, p in enumerate(planes) if p.rect is not None]
     bg_index = len(planes) - 1
-    for i, p in enumerate(planes):
-        if p.rect is None:
-            continue
-        n = torch.as_tensor(p.n, device=device, dtype=dt)
-        p0 = torch.as_tensor(p.p0, device=device, dtype=dt)
-        den = d @ n
-        lam = torch.dot(n, p0 - C) / den
-        X = C + lam.unsqueeze(-1) * d
-        ok = (lam > 0) & (X[..., 2] > 1e-9) & torch.isfinite(lam)
-        u = fx * X[..., 0] / X[..., 2] + cx
-        v = fy * X[..., 1] / X[..., 2] + cy
-        x0, y0, x1, y1 = p.rect
-        ok &= (u >= x0 - 0.5) & (u < x1 - 0.5) & (v >= y0 - 0.5) & (v < y1 - 0.5)
-        closer = ok & (lam < best)
-        best = torch.where(closer, lam, best)
-        pid = torch.where(closer, torch.full_like(pid, i), pid)
-    miss = pid < 0
-    pid = torch.where(miss, torch.full_like(pid, bg_index), pid)
-    img = torch.zeros((H, W), device=device, dtype=dt)
-    for i, p in enumerate(planes):
-        m = pid == i
-        if not bool(m.any()):
-            continue
-        n = torch.as_tensor(p.n, device=device, dtype=dt)
-        p0 = torch.as_tensor(p.p0, device=device, dtype=dt)
-        dm = d[m]
-        lam = torch.dot(n, p0 - C) / (dm @ n)
-        X = C + lam.unsqueeze(-1) * dm - p0
-        a = X @ torch.as_tensor(p.e1, device=device, dtype=dt)
-        b = X @ torch.as_tensor(p.e2, device=device, dtype=dt)
-        om = torch.as_tensor(p.omega, device=device, dtype=dt)
-        ph = torch.as_tensor(p.phase, device=device, dtype=dt)
-        arg = 2.0 * math.pi * (a.unsqueeze(-1) * om[:, 0] + b.unsqueeze(-1) * om[:, 1]) + ph
-        img[m] = 0.5 + torch.sin(arg).sum(-1) / 16.0
+    N = torch.as_tensor(np.stack([planes[i].n for i in quads]), device=dev, dtype=dt)      # (P,3)
+    P0 = torch.as_tensor(np.stack([planes[i].p0 for i in quads]), device=dev, dtype=dt)    # (P,3)
+    rects = torch.as_tensor(np.array([planes[i].rect for i in quads], dtype=np.float64), device=dev, dtype=dt)
+    den = d @ N.T                                     # (M,P)
+    num = ((P0 - C) * N).sum(1)                       # (P,)
+    lam = num / den
+    X = C.view(1, 1, 3) + lam.unsqueeze(-1) * d.unsqueeze(1)   # (M,P,3)
+    Z = X[..., 2]
+    ok = (lam > 0) & (Z > 1e-9) & torch.isfinite(lam)
+    u = fx * X[..., 0] / Z + cx
+    v = fy * X[..., 1] / Z + cy
+    ok &= (u >= rects[:, 0] - 0.5) & (u < rects[:, 2] - 0.5) & (v >= rects[:, 1] - 0.5) & (v < rects[:, 3] - 0.5)
+    lam_ok = torch.where(ok, lam, torch.full_like(lam, float("inf")))
+    best, arg = lam_ok.min(dim=1)
+    hit = torch.isfinite(best)
+    qidx = torch.as_tensor(quads, device=dev, dtype=torch.int64)
+    pid = torch.where(hit, qidx[arg], torch.full_like(arg, bg_index))
+    # texture of the winning plane at its hit point
+    allN = torch.as_tensor(np.stack([p.n for p in planes]), device=dev, dtype=dt)
+    allP0 = torch.as_tensor(np.stack([p.p0 for p in planes]), device=dev, dtype=dt)
+    E1 = torch.as_tensor(np.stack([p.e1 for p in planes]), device=dev, dtype=dt)
+    E2 = torch.as_tensor(np.stack([p.e2 for p in planes]), device=dev, dtype=dt)
+    OM = torch.as_tensor(np.stack([p.omega for p in planes]), device=dev, dtype=dt)      # (Q,8,2)
+    PH = torch.as_tensor(np.stack([p.phase for p in planes]), device=dev, dtype=dt)      # (Q,8)
+    n_w, p0_w = allN[pid], allP0[pid]
+    lam_w = ((p0_w - C) * n_w).sum(1) / (d * n_w).sum(1)
+    Xw = C + lam_w.unsqueeze(-1) * d - p0_w
+    a = (Xw * E1[pid]).sum(1)
+    b = (Xw * E2[pid]).sum(1)
+    om = OM[pid]
+    arg_ = 2.0 * math.pi * (a.unsqueeze(-1) * om[..., 0] + b.unsqueeze(-1) * om[..., 1]) + PH[pid]
+    img = (0.5 + torch.sin(arg_).sum(-1) / 16.0).view(H, W)
     if noise_sigma > 0:
-        img = img + noise_sigma * torch.randn((H, W), device=device, dtype=dt, generator=gen)
+        img = img + noise_sigma * torch.randn((H, W), device=dev, dtype=dt, generator=gen)
     img = img.clamp(0.0, 1.0)
-    return img.to(torch.float32), pid
+    return img.to(torch.float32), pid.view(H, W).to(torch.int16)
 
 
 def _gt_surfels(planes, K, W, H, S, kf_pid: np.ndarray):
+    """Ground-truth plane of every tile: tiles are pure (rectangle edges lie
+    on multiples of 8 px), so the plane hit by the tile's first pixel owns it;
+    its inverse depth along the tile's centre ray is the ray/plane
+    intersection."""
     fx, fy, cx, cy = K
     gw, gh = W // S, H // S
-    gt_id = np.zeros((gh, gw))
-    gt_n = np.zeros((gh, gw, 3))
-    for ty in range(gh):
-        for tx in range(gw):
-            block = kf_pid[ty * S:(ty + 1) * S, tx * S:(tx + 1) * S]
-            i = int(np.bincount(block.ravel().astype(np.int64)).argmax())
-            p = planes[i]
-            us = S * tx + 0.5 * (S - 1)
-            vs = S * ty + 0.5 * (S - 1)
-            r = np.array([(us - cx) / fx, (vs - cy) / fy, 1.0])
-            gt_id[ty, tx] = np.dot(p.n, r) / np.dot(p.n, p.p0)   # ray/plane intersection, 1/z
-            gt_n[ty, tx] = p.n
-    return gt_id, gt_n
+    pid = kf_pid[0:gh * S:S, 0:gw * S:S].astype(np.int64)             # (gh, gw)
+    Nn = np.stack([p.n for p in planes])[pid]                          # (gh, gw, 3)
+    P0 = np.stack([p.p0 for p in planes])[pid]
+    tx = np.arange(gw)[None, :]
+    ty = np.arange(gh)[:, None]
+    us = S * tx + 0.5 * (S - 1)
+    vs = S * ty + 0.5 * (S - 1)
+    r = np.stack(np.broadcast_arrays((us - cx) / fx, (vs - cy) / fy, np.ones((gh, gw))), -1)
+    gt_id = (Nn * r).sum(-1) / (Nn * P0).sum(-1)
+    return gt_id, Nn.copy()
 
 
 def _perturb(rng, gt_id, gt_n, depth_noise, normal_deg):
     gh, gw = gt_id.shape
     scale = rng.uniform(1.0 - depth_noise, 1.0 + depth_noise, size=(gh, gw))
     init_id = gt_id / scale
-    init_n = np.zeros_like(gt_n)
     ang = np.radians(rng.uniform(0.0, normal_deg, size=(gh, gw)))
     psi = rng.uniform(0.0, 2.0 * math.pi, size=(gh, gw))
-    for ty in range(gh):
-        for tx in range(gw):
-            n = gt_n[ty, tx]
-            b1, b2 = _tangent_basis(n)
-            axis = math.cos(psi[ty, tx]) * b1 + math.sin(psi[ty, tx]) * b2
-            init_n[ty, tx] = rotation_about(axis, ang[ty, tx]) @ n
+    n = gt_n
+    e = np.where((np.abs(n[..., 0]) < 0.9)[..., None], np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0]))
+    b1 = e - (e * n).sum(-1, keepdims=True) * n
+    b1 /= np.linalg.norm(b1, axis=-1, keepdims=True)
+    b2 = np.cross(n, b1)
+    axis = np.cos(psi)[..., None] * b1 + np.sin(psi)[..., None] * b2      # unit, orthogonal to n
+    # Rodrigues for an axis orthogonal to n: n cos + (axis x n) sin
+    init_n = n * np.cos(ang)[..., None] + np.cross(axis, n) * np.sin(ang)[..., None]
     return init_id.astype(np.float32), init_n.astype(np.float32)
 
 
