@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="length of the Poisson serving trace (0: skip the serving leg)")
     return ap.parse_args()
 
 
@@ -81,7 +83,8 @@ def main():
     dks = [engine.DeviceKeyframe.from_scene(ctx, k, storage=args.storage) for k in kfs]
     torch.cuda.synchronize()
     log(f"generated {len(dks)} keyframes in {time.time() - t0:.1f}s")
-    init_state = [d.state.clone() for d in dks]
+    pool = engine.StatePool(dks)
+    init_state = pool.snapshot()
     prm = sg.params(iters=iters)
     surfel_frames = sum(d.n_surfels * d.n_nbr for d in dks) * iters
     samples = sum(d.n_surfels * d.n_nbr * d.patch * d.patch for d in dks) * iters
@@ -92,10 +95,7 @@ def main():
         log("autotuned plan", plan.as_dict())
 
     def restore():
-        for d, s0 in zip(dks, init_state):
-            for a, b in ((d.state.inv_depth, s0.inv_depth), (d.state.nx, s0.nx), (d.state.ny, s0.ny),
-                         (d.state.nz, s0.nz), (d.state.flags, s0.flags)):
-                a.copy_(b, non_blocking=True)
+        pool.restore(init_state)
 
     def step():
         restore()
@@ -159,6 +159,15 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(dks, kfs, iters, args.cpu_seconds)
     ctx.close()
+    del dks, kfs, pool, init_state
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+    serving = None
+    if args.serve_seconds > 0:
+        from paper_1910_01997_amd import serve
+        serving = serve.serving_benchmark(n_streams=32, rate=200.0, duration=args.serve_seconds,
+                                          warmup=1.0, storage=args.storage, iters=iters, log=log)
     out = {
         "metric": METRIC,
         "value": value,
@@ -198,6 +207,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "plain_form": plain,
+        "serving": serving,
         "device": {"name": info["name"], "arch": info["arch"], "cus": info["compute_units"]},
     }
     print(json.dumps(out), flush=True)

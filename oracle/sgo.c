@@ -294,8 +294,12 @@ double sgo_kappa_eq(const double H[9]) {
  * Optimization section): the tangent step (alpha_1, alpha_2) is the 3-DOF
  * step n + a1 b1 + a2 b2, renormalised. */
 static int apply_update(double id_s, const double n[3], const double b1[3], const double b2[3],
-                        const double delta[3], double* id_new, double n_new[3]) {
+                        const double delta[3], int depth_only, double* id_new, double n_new[3]) {
     *id_new = id_s + delta[0];
+    if (depth_only) {          /* only id_s is a parameter of the ablation */
+        n_new[0] = n[0]; n_new[1] = n[1]; n_new[2] = n[2];
+        return *id_new > 0.0 && isfinite(*id_new);
+    }
     for (int i = 0; i < 3; ++i) n_new[i] = n[i] + delta[1] * b1[i] + delta[2] * b2[i];
     if (!normalize3(n_new)) return 0;
     if (!(*id_new > 0.0) || !isfinite(*id_new)) return 0;
@@ -364,7 +368,7 @@ static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_param
             }
         }
         double id_new, n_new[3];
-        if (!apply_update(id_s, n, b1, b2, delta, &id_new, n_new)) {
+        if (!apply_update(id_s, n, b1, b2, delta, p->depth_only, &id_new, n_new)) {
             flags |= SGO_REJECTED;
             if (lambda > 0.0) lambda *= 10.0;
             continue;
@@ -382,9 +386,11 @@ static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_param
         }
         if (p->perturb > 0.0) {
             id_new *= 1.0 + p->perturb * probe_uniform(p->perturb_seed, i, it, 0);
-            for (int k = 0; k < 3; ++k)
-                n_new[k] *= 1.0 + p->perturb * probe_uniform(p->perturb_seed, i, it, 1 + k);
-            normalize3(n_new);
+            if (!p->depth_only) {
+                for (int k = 0; k < 3; ++k)
+                    n_new[k] *= 1.0 + p->perturb * probe_uniform(p->perturb_seed, i, it, 1 + k);
+                normalize3(n_new);
+            }
         }
         id_s = id_new;
         n[0] = n_new[0]; n[1] = n_new[1]; n[2] = n_new[2];

@@ -122,8 +122,12 @@ sgn_status check_image(const sgn_image& im, int W, int H, int dtype, const char*
         return fail(SGN_E_INVALID, std::string(what) + ": scale must be finite and > 0");
     if (im.dtype != SGN_U8 && im.scale != 1.0f)
         return fail(SGN_E_UNSUPPORTED, std::string(what) + ": scale must be 1 for f32/f16 storage");
-    if ((uint64_t)im.pitch * (uint64_t)im.height >= (1ull << 31))
-        return fail(SGN_E_UNSUPPORTED, std::string(what) + ": image larger than 2^31 elements");
+    if ((uint64_t)im.pitch * (uint64_t)im.height * dtype_size(im.dtype) >= (1ull << 31))
+        return fail(SGN_E_UNSUPPORTED, std::string(what) + ": image larger than 2 GiB");
+    if (((uint64_t)im.pitch * dtype_size(im.dtype)) % 4 != 0)
+        return fail(SGN_E_UNSUPPORTED, std::string(what) + ": row pitch must be a multiple of 4 bytes");
+    if (((uintptr_t)im.data) % 4 != 0)
+        return fail(SGN_E_UNSUPPORTED, std::string(what) + ": data must be 4-byte aligned");
     return SGN_OK;
 }
 

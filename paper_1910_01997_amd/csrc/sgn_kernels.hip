@@ -319,6 +319,79 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The four bilinear taps (x0, y0), (x0+1, y0), (x0, y0+1), (x0+1, y0+1) of
+// one image.  f32 images use global loads with a scalar base.  f16 and u8
+// images load each horizontal pair with one 8-byte range-checked buffer load
+// from the aligned dword below it (bytes past the image read as zero), and
+// extract the pair with a funnel shift.
+struct Taps {
+    float i00, i01, i10, i11;
+};
+
+template <typename T>
+__device__ __forceinline__ Taps load_taps(const void* img, unsigned nbytes, unsigned o0, unsigned pitch_b);
+
+template <>
+__device__ __forceinline__ Taps load_taps<float>(const void* img, unsigned, unsigned o0, unsigned pitch_b) {
+    const gptr<char> b = (gptr<char>)img;
+    Taps t;
+    t.i00 = *(gptr<float>)(b + o0);
+    t.i01 = *(gptr<float>)(b + o0 + 4);
+    t.i10 = *(gptr<float>)(b + o0 + pitch_b);
+    t.i11 = *(gptr<float>)(b + o0 + pitch_b + 4);
+    return t;
+}
+
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ unsigned load_pair_bits(__amdgpu_buffer_rsrc_t rs, unsigned o, unsigned shift) {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, o & ~3u, 0, 0);
+    return __builtin_amdgcn_alignbit(v.y, v.x, shift);
+}
+
+template <>
+__device__ __forceinline__ Taps load_taps<_Float16>(const void* img, unsigned nbytes, unsigned o0,
+                                                   unsigned pitch_b) {
+#ifdef SGN_F16_UNALIGNED_PAIRS
+    // each horizontal pair as one 4-byte load at 2-byte alignment
+    const gptr<char> bp = (gptr<char>)img;
+    Taps t;
+    t.i00 = (float)*(gptr<_Float16>)(bp + o0);
+    t.i01 = (float)*(gptr<_Float16>)(bp + o0 + 2);
+    t.i10 = (float)*(gptr<_Float16>)(bp + o0 + pitch_b);
+    t.i11 = (float)*(gptr<_Float16>)(bp + o0 + pitch_b + 2);
+    (void)nbytes;
+    return t;
+#endif
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(img), (short)0, (int)nbytes, 0x00020000);
+    const unsigned sh = (o0 & 2u) * 8u;          // pitch_b is a multiple of 4
+    const unsigned a = load_pair_bits(rs, o0, sh);
+    const unsigned b = load_pair_bits(rs, o0 + pitch_b, sh);
+    Taps t;
+    t.i00 = (float)__builtin_bit_cast(_Float16, (unsigned short)(a & 0xffffu));
+    t.i01 = (float)__builtin_bit_cast(_Float16, (unsigned short)(a >> 16));
+    t.i10 = (float)__builtin_bit_cast(_Float16, (unsigned short)(b & 0xffffu));
+    t.i11 = (float)__builtin_bit_cast(_Float16, (unsigned short)(b >> 16));
+    return t;
+}
+
+template <>
+__device__ __forceinline__ Taps load_taps<uint8_t>(const void* img, unsigned nbytes, unsigned o0,
+                                                  unsigned pitch_b) {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(img), (short)0, (int)nbytes, 0x00020000);
+    const unsigned sh = (o0 & 3u) * 8u;          // pitch_b is a multiple of 4
+    const unsigned a = load_pair_bits(rs, o0, sh);
+    const unsigned b = load_pair_bits(rs, o0 + pitch_b, sh);
+    Taps t;
+    t.i00 = (float)(a & 0xffu);
+    t.i01 = (float)((a >> 8) & 0xffu);
+    t.i10 = (float)(b & 0xffu);
+    t.i11 = (float)((b >> 8) & 0xffu);
+    return t;
+}
+
 // The frame loop of one Gauss-Newton iteration for one pixel (lane): warp
 // into every neighbour frame, bilinear sample with gradient, Huber-weighted
 // residual, and the scalar chain factor a = dr/did_u.  Accumulates
@@ -327,7 +400,8 @@ __device__ __forceinline__ void wave_sync() {
 template <typename T, bool LAST>
 __device__ __forceinline__ void frame_loop(const float* __restrict__ pc, cptr<FrameDev> fr, int nf,
                                            float dx, float dy, float idu, bool pix_ok,
-                                           unsigned pitch_b, float ikf, float hk, float img_scale,
+                                           unsigned pitch_b, unsigned img_bytes, float ikf, float hk,
+                                           float img_scale,
                                            float& A, float& B, float& cst, int& nvl) {
     constexpr bool SCALED = std::is_same<T, uint8_t>::value;
     for (int f = 0; f < nf; ++f) {
@@ -345,7 +419,7 @@ __device__ __forceinline__ void frame_loop(const float* __restrict__ pc, cptr<Fr
         // valid iff 0 <= x_p < W-1 and 0 <= y_p < H-1 (bounds exact in float)
         const bool v = pix_ok & (qz > 0.f) & (fx >= c2.y) & (fx < c2.z) & (fy >= c2.w) & (fy < c3.x);
         if (v) {
-            const gptr<char> img = (gptr<char>)fr[f].img;
+            const void* img = fr[f].img;
             const float ffx = floorf(fx), ffy = floorf(fy);
             const int flx = (int)ffx, fly = (int)ffy;
             const float ax = fx - ffx;
@@ -353,11 +427,8 @@ __device__ __forceinline__ void frame_loop(const float* __restrict__ pc, cptr<Fr
             // byte offset of (X0 + flx, Y0 + fly); unsigned wrap-around arithmetic
             const unsigned o0 = __float_as_uint(c3.y) + (unsigned)__mul24(fly, (int)pitch_b) +
                                 (unsigned)flx * (unsigned)sizeof(T);
-            const unsigned o1 = o0 + pitch_b;
-            const float i00 = ldg<T>((gptr<T>)(img + o0));
-            const float i01 = ldg<T>((gptr<T>)(img + o0 + sizeof(T)));
-            const float i10 = ldg<T>((gptr<T>)(img + o1));
-            const float i11 = ldg<T>((gptr<T>)(img + o1 + sizeof(T)));
+            const Taps tp = load_taps<T>(img, img_bytes, o0, pitch_b);
+            const float i00 = tp.i00, i01 = tp.i01, i10 = tp.i10, i11 = tp.i11;
             // bilinear value and the exact gradient of the interpolant
             const float d0 = i01 - i00, d1 = i11 - i10;
             const float top = fmaf(ax, d0, i00);
@@ -433,6 +504,7 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
         const int nf = K->n_nbr;
         const float img_scale = K->img_scale;
         const unsigned pitch_b = (unsigned)K->nbr_pitch_b;
+        const unsigned img_bytes = pitch_b * (unsigned)K->height;
         {
             // warp constants of every (surfel slot, frame) pair of this item,
             // one pair per lane, in double
@@ -536,11 +608,11 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
             float A = 0.f, B = 0.f, cst = 0.f;
             int nvl = 0;
             if (last)
-                frame_loop<T, true>(pc, fr, nf, dxp, dyp, idu, pix_ok, pitch_b, ikf, hk, img_scale, A, B,
-                                    cst, nvl);
+                frame_loop<T, true>(pc, fr, nf, dxp, dyp, idu, pix_ok, pitch_b, img_bytes, ikf, hk,
+                                    img_scale, A, B, cst, nvl);
             else
-                frame_loop<T, false>(pc, fr, nf, dxp, dyp, idu, pix_ok, pitch_b, ikf, hk, img_scale, A, B,
-                                     cst, nvl);
+                frame_loop<T, false>(pc, fr, nf, dxp, dyp, idu, pix_ok, pitch_b, img_bytes, ikf, hk,
+                                     img_scale, A, B, cst, nvl);
             // J^T W J = sum_u A_u g g^T, J^T W r = sum_u B_u g (frame sum hoisted)
             const float ag0 = A * g0, ag1 = A * g1, ag2 = A * g2;
             const float H00 = group_sum<LANES>(ag0 * g0);
@@ -611,8 +683,18 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                     }
                 }
             }
-            // update: id_s += d0; n = normalise(n + d1 b1 + d2 b2)
+            // update: id_s += d0; n = normalise(n + d1 b1 + d2 b2) (the depth-only
+            // ablation moves id_s alone and leaves n as it is)
             const float idn = id + d0s;
+            if (depth_only) {
+                if (!(idn > 0.f) || !isfinite(idn)) {
+                    flags |= F_REJECTED;
+                    continue;
+                }
+                id = idn;
+                updated = true;
+                continue;
+            }
             const float mx = fmaf(d1s, b1x, fmaf(d2s, b2x, nx));
             const float my = fmaf(d1s, b1y, fmaf(d2s, b2y, ny));
             const float mz = fmaf(d1s, b1z, fmaf(d2s, b2z, nz));

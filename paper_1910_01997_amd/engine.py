@@ -113,3 +113,33 @@ def update_batch(ctx: sg.Context, dks: Sequence[DeviceKeyframe], prm: sg.sgn_par
     items = sg.batch_array([d.item(render=render) for d in dks])
     sg.sgn_optimize_batch(ctx.handle, items, len(dks), prm, plan)
     return items
+
+
+_STATE_FIELDS = ("inv_depth", "nx", "ny", "nz", "flags", "cost", "nvalid", "last_update")
+
+
+class StatePool:
+    """Moves the surfel state of many keyframes into one allocation per field
+    (each keyframe keeps a view), so that snapshots and restores of a whole
+    batch are one copy per field."""
+
+    def __init__(self, dks: Sequence[DeviceKeyframe]):
+        counts = [d.n_surfels for d in dks]
+        total = sum(counts)
+        first = dks[0].state
+        self.fields = {f: torch.empty(total, dtype=getattr(first, f).dtype,
+                                      device=getattr(first, f).device) for f in _STATE_FIELDS}
+        off = 0
+        for d, m in zip(dks, counts):
+            views = {f: t[off:off + m] for f, t in self.fields.items()}
+            for f, v in views.items():
+                v.copy_(getattr(d.state, f))
+            d.state = sg.SurfelState(*[views[f] for f in _STATE_FIELDS])
+            off += m
+
+    def snapshot(self):
+        return {f: t.clone() for f, t in self.fields.items()}
+
+    def restore(self, snap, fields=("inv_depth", "nx", "ny", "nz", "flags")):
+        for f in fields:
+            self.fields[f].copy_(snap[f], non_blocking=True)

@@ -1,0 +1,472 @@
+"""Serving loop: keyframe-update requests from many camera streams.
+
+Each registered stream keeps its keyframe image, a ring of neighbour frames
+and its surfel state resident on the GPU.  A request brings one new
+neighbour frame (image + pose) that replaces the oldest one in the ring, then
+asks for the Gauss-Newton iterations on the stream's surfels and returns the
+surfels and the per-pixel inverse depth.
+
+Scheduling (host side, this module):
+  * admission by memory: a request is admitted only when its response buffers
+    fit in the pool budget; otherwise it waits (FIFO) and is admitted as soon
+    as completed requests release memory;
+  * continuous batching: whenever an execution lane is free, every admitted
+    request whose stream has nothing in flight is packed into one batch and
+    launched (one persistent fused kernel for the whole batch); batches on
+    different lanes overlap on the device;
+  * per-stream order: a stream never has two requests in flight, so each
+    request sees the state left by the previous one;
+  * a request whose execution fails is completed with its error and its
+    memory released; the rest of its batch is not affected by the scheduler.
+
+The executor does the device work.  HipExecutor uses the C ABI
+(sgn_optimize_batch on per-lane contexts and streams); tests substitute a
+CPU executor to check the scheduling logic without a GPU.
+"""
+from __future__ import annotations
+
+import collections
+import heapq
+import threading
+import time
+from dataclasses import dataclass, field
+from typing import Any, Callable, Deque, Dict, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    stream: int
+    arrival: float                       # host clock (time.perf_counter) at arrival
+    frame_index: int                     # which prepared frame of the stream this request brings
+    rid: int = 0
+    admitted: float = 0.0
+    launched: float = 0.0
+    done: float = 0.0
+    nbytes: int = 0
+    error: Optional[str] = None
+    result: Any = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class MemoryPool:
+    """Byte budget for per-request buffers (admission control)."""
+
+    def __init__(self, budget: int):
+        self.budget = int(budget)
+        self.used = 0
+        self.peak = 0
+
+    def try_take(self, n: int) -> bool:
+        if n > self.budget:
+            raise ValueError(f"request needs {n} bytes, more than the whole pool ({self.budget})")
+        if self.used + n > self.budget:
+            return False
+        self.used += n
+        self.peak = max(self.peak, self.used)
+        return True
+
+    def give(self, n: int):
+        self.used -= n
+        assert self.used >= 0
+
+
+class Executor:
+    """Device side of the server.  launch() enqueues one batch on a lane and
+    returns a handle; poll() says whether it finished; finish() returns the
+    per-request errors (None = success)."""
+
+    lanes = 1
+
+    def request_bytes(self, req: Request) -> int:
+        raise NotImplementedError
+
+    def launch(self, lane: int, batch: List[Request]) -> Any:
+        raise NotImplementedError
+
+    def poll(self, handle) -> bool:
+        raise NotImplementedError
+
+    def finish(self, handle) -> List[Optional[str]]:
+        raise NotImplementedError
+
+
+class Server:
+    def __init__(self, executor: Executor, pool_bytes: int, max_batch: int = 32,
+                 clock: Callable[[], float] = time.perf_counter):
+        self.ex = executor
+        self.pool = MemoryPool(pool_bytes)
+        self.max_batch = max_batch
+        self.clock = clock
+        self.waiting: Deque[Request] = collections.deque()     # not yet admitted (FIFO)
+        self.admitted: Deque[Request] = collections.deque()    # admitted, not launched
+        self.busy_streams: set = set()
+        self.lanes_free = list(range(executor.lanes))
+        self.inflight: List[tuple] = []                        # (handle, lane, batch)
+        self.completed: List[Request] = []
+        self.batches: List[int] = []
+        self._rid = 0
+
+    # -- requests ----------------------------------------------------------
+    def submit(self, req: Request):
+        self._rid += 1
+        req.rid = self._rid
+        req.nbytes = self.ex.request_bytes(req)
+        self.waiting.append(req)
+
+    def _admit(self):
+        while self.waiting and self.pool.try_take(self.waiting[0].nbytes):
+            r = self.waiting.popleft()
+            r.admitted = self.clock()
+            self.admitted.append(r)
+
+    def _launch(self):
+        while self.lanes_free and self.admitted:
+            batch, keep = [], collections.deque()
+            taken = set()
+            while self.admitted:
+                r = self.admitted.popleft()
+                if (r.stream in self.busy_streams or r.stream in taken or
+                        len(batch) >= self.max_batch):
+                    keep.append(r)
+                else:
+                    batch.append(r)
+                    taken.add(r.stream)
+            self.admitted = keep
+            if not batch:
+                return
+            lane = self.lanes_free.pop(0)
+            now = self.clock()
+            for r in batch:
+                r.launched = now
+            self.busy_streams |= taken
+            try:
+                h = self.ex.launch(lane, batch)
+            except Exception as e:            # nothing was enqueued for this batch
+                self.lanes_free.append(lane)
+                self._complete(batch, [f"launch failed: {e}"] * len(batch))
+                continue
+            self.inflight.append((h, lane, batch))
+            self.batches.append(len(batch))
+
+    def _complete(self, batch, errors):
+        now = self.clock()
+        for r, err in zip(batch, errors):
+            r.done = now
+            r.error = err
+            self.pool.give(r.nbytes)
+            self.busy_streams.discard(r.stream)
+            self.completed.append(r)
+
+    def _reap(self):
+        still = []
+        for h, lane, batch in self.inflight:
+            if self.ex.poll(h):
+                try:
+                    errors = self.ex.finish(h)
+                except Exception as e:
+                    errors = [f"execution failed: {e}"] * len(batch)
+                self._complete(batch, errors)
+                self.lanes_free.append(lane)
+            else:
+                still.append((h, lane, batch))
+        self.inflight = still
+
+    def tick(self):
+        """One scheduler pass: reap finished batches, admit, launch."""
+        self._reap()
+        self._admit()
+        self._launch()
+
+    def idle(self) -> bool:
+        return not (self.waiting or self.admitted or self.inflight)
+
+    def drain(self, timeout: float = 60.0):
+        t0 = self.clock()
+        while not self.idle():
+            self.tick()
+            if self.clock() - t0 > timeout:
+                raise TimeoutError("server did not drain")
+
+
+def poisson_arrivals(rate: float, duration: float, n_streams: int, seed: int, frames_per_stream: int):
+    """(time, stream, frame_index) for Poisson arrivals at `rate` per second
+    over `duration` seconds, the stream picked uniformly."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    counters = [0] * n_streams
+    out = []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        s = int(rng.integers(0, n_streams))
+        out.append((t, s, counters[s] % frames_per_stream))
+        counters[s] += 1
+    return out
+
+
+def run_trace(server: Server, trace, warmup: float = 0.0, idle_sleep: float = 2e-5):
+    """Replay (t, stream, frame) arrivals in real time through the server.
+    Returns the completed requests that arrived after `warmup` seconds."""
+    t0 = server.clock()
+    i = 0
+    while i < len(trace) or not server.idle():
+        now = server.clock() - t0
+        while i < len(trace) and trace[i][0] <= now:
+            t, s, fi = trace[i]
+            server.submit(Request(stream=s, arrival=t0 + t, frame_index=fi))
+            i += 1
+        server.tick()
+        if server.idle() and i < len(trace):
+            wait = trace[i][0] - (server.clock() - t0)
+            if wait > 0:
+                time.sleep(min(wait, 1e-3))
+        elif idle_sleep:
+            time.sleep(idle_sleep)
+    return [r for r in server.completed if r.arrival - t0 >= warmup]
+
+
+def latency_stats(reqs: Sequence[Request]) -> Dict[str, float]:
+    ok = [r for r in reqs if r.error is None]
+    if not ok:
+        return {"count": 0}
+    lat = np.array([r.latency for r in ok]) * 1e3
+    t_first = min(r.arrival for r in ok)
+    t_last = max(r.done for r in ok)
+    return {"count": len(ok), "errors": len(reqs) - len(ok),
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+            "throughput_rps": len(ok) / max(t_last - t_first, 1e-9)}
+
+
+# --------------------------------------------------------------------------
+# GPU executor over the C ABI
+# --------------------------------------------------------------------------
+
+class CameraStream:
+    """Resident device state of one camera stream."""
+
+    def __init__(self, ctx, kf, extra_frames, storage: str = "f16"):
+        import torch
+
+        from . import engine
+        self.dk = engine.DeviceKeyframe.from_scene(ctx, kf, storage=storage, render=True)
+        self.n_nbr = self.dk.n_nbr
+        self.oldest = 0
+        self.first = True
+        self.R = np.array(self.dk.R)
+        self.t = np.array(self.dk.t)
+        # prepared request frames (stored in the image dtype) and their poses
+        self.frames = extra_frames["images"]          # device tensor (E, H, W) storage dtype
+        self.frame_R = extra_frames["R"]
+        self.frame_t = extra_frames["t"]
+        self.resp_depth = None
+        self.resp_state = None
+
+    @property
+    def response_bytes(self) -> int:
+        return self.dk.width * self.dk.height * 4 + self.dk.n_surfels * 8 * 4
+
+
+class HipExecutor(Executor):
+    """Runs batches through sgn_optimize_batch on `lanes` contexts, each on
+    its own torch stream (default priority)."""
+
+    def __init__(self, streams: List[CameraStream], lanes: int = 2, iters: int = 15,
+                 plan=None, pinned_pool: bool = True):
+        import torch
+
+        from . import surfgn as sg
+        self.sg = sg
+        self.torch = torch
+        self.streams = streams
+        self.lanes = lanes
+        self.tstreams = [torch.cuda.Stream() for _ in range(lanes)]
+        self.ctxs = [sg.Context(0, stream=s) for s in self.tstreams]
+        self.params = sg.params(iters=iters)
+        self.plan = plan
+        self.pinned_pool = pinned_pool
+
+    def request_bytes(self, req: Request) -> int:
+        return self.streams[req.stream].response_bytes
+
+    def launch(self, lane: int, batch: List[Request]):
+        torch = self.torch
+        ts = self.tstreams[lane]
+        items = []
+        outs = []
+        with torch.cuda.stream(ts):
+            for r in batch:
+                cs = self.streams[r.stream]
+                dk = cs.dk
+                slot = cs.oldest
+                # the new frame replaces the oldest neighbour (device copy on this lane)
+                dk.nbr_imgs[slot].copy_(cs.frames[r.frame_index], non_blocking=True)
+                cs.R[slot] = cs.frame_R[r.frame_index]
+                cs.t[slot] = cs.frame_t[r.frame_index]
+                cs.oldest = (cs.oldest + 1) % cs.n_nbr
+                view = self.sg.KeyframeView(dk.kf_img, [dk.nbr_imgs[i] for i in range(dk.n_nbr)],
+                                            cs.R, cs.t, dk.K, dk.patch, dk.scale)
+                it = self.sg.sgn_batch_item(view.c, dk.state.c,
+                                            dk.is_new.data_ptr() if (cs.first and dk.is_new is not None) else None,
+                                            dk.inv_depth_out.data_ptr(), None)
+                cs.first = False
+                items.append(it)
+                outs.append(view)
+            arr = self.sg.batch_array(items)
+            self.sg.sgn_optimize_batch(self.ctxs[lane].handle, arr, len(items), self.params, self.plan)
+            # responses: depth map and surfels copied to host memory
+            results = []
+            for r in batch:
+                dk = self.streams[r.stream].dk
+                depth = torch.empty(dk.inv_depth_out.shape, dtype=torch.float32, pin_memory=self.pinned_pool)
+                depth.copy_(dk.inv_depth_out, non_blocking=True)
+                st = torch.empty((8, dk.n_surfels), dtype=torch.float32, pin_memory=self.pinned_pool)
+                for k, src in enumerate((dk.state.inv_depth, dk.state.nx, dk.state.ny, dk.state.nz,
+                                         dk.state.flags.view(torch.float32), dk.state.cost,
+                                         dk.state.nvalid.view(torch.float32),
+                                         dk.state.last_update.view(torch.float32))):
+                    st[k].copy_(src, non_blocking=True)
+                results.append((depth, st))
+            ev = torch.cuda.Event()
+            ev.record(ts)
+        return (ev, batch, results, outs, arr)
+
+    def poll(self, handle) -> bool:
+        return handle[0].query()
+
+    def finish(self, handle):
+        ev, batch, results, _, _ = handle
+        ev.synchronize()
+        for r, res in zip(batch, results):
+            r.result = res
+        return [None] * len(batch)
+
+
+class PlainExecutor(HipExecutor):
+    """The plain form: one request at a time with the single-keyframe calls
+    (init, non-persistent Gauss-Newton launch, render) on one lane."""
+
+    def __init__(self, streams, iters: int = 15):
+        super().__init__(streams, lanes=1, iters=iters)
+
+    def launch(self, lane: int, batch: List[Request]):
+        assert len(batch) == 1
+        torch = self.torch
+        ts = self.tstreams[0]
+        r = batch[0]
+        cs = self.streams[r.stream]
+        dk = cs.dk
+        ctx = self.ctxs[0]
+        with torch.cuda.stream(ts):
+            slot = cs.oldest
+            dk.nbr_imgs[slot].copy_(cs.frames[r.frame_index], non_blocking=True)
+            cs.R[slot] = cs.frame_R[r.frame_index]
+            cs.t[slot] = cs.frame_t[r.frame_index]
+            cs.oldest = (cs.oldest + 1) % cs.n_nbr
+            view = self.sg.KeyframeView(dk.kf_img, [dk.nbr_imgs[i] for i in range(dk.n_nbr)],
+                                        cs.R, cs.t, dk.K, dk.patch, dk.scale)
+            if cs.first and dk.is_new is not None:
+                self.sg.sgn_init_from_neighbours(ctx.handle, view.c, dk.state.c, dk.is_new.data_ptr(),
+                                                 self.params)
+            cs.first = False
+            self.sg.sgn_optimize_keyframe(ctx.handle, view.c, dk.state.c, self.params)
+            self.sg.sgn_render_inverse_depth(ctx.handle, view.c, dk.state.c, dk.inv_depth_out.data_ptr())
+            depth = torch.empty(dk.inv_depth_out.shape, dtype=torch.float32, pin_memory=True)
+            depth.copy_(dk.inv_depth_out, non_blocking=True)
+            st = torch.empty((8, dk.n_surfels), dtype=torch.float32, pin_memory=True)
+            for k, src in enumerate((dk.state.inv_depth, dk.state.nx, dk.state.ny, dk.state.nz,
+                                     dk.state.flags.view(torch.float32), dk.state.cost,
+                                     dk.state.nvalid.view(torch.float32),
+                                     dk.state.last_update.view(torch.float32))):
+                st[k].copy_(src, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(ts)
+        return (ev, batch, [(depth, st)], [view], None)
+
+
+def make_streams(ctx, specs, extra: int = 4, storage: str = "f16", device="cuda"):
+    """Camera streams from scene specs: the spec's neighbours fill the ring,
+    `extra` more rendered views become the frames requests bring."""
+    import dataclasses
+
+    import torch
+
+    from scenegen import make_keyframe
+    out = []
+    for sp in specs:
+        big = make_keyframe(dataclasses.replace(sp, n_nbr=sp.n_nbr + extra), device=device)
+        base = dataclasses.replace(big, nbr_images=big.nbr_images[:sp.n_nbr], R=big.R[:sp.n_nbr],
+                                   t=big.t[:sp.n_nbr])
+        cs = CameraStream(ctx, base, {"images": None, "R": big.R[sp.n_nbr:], "t": big.t[sp.n_nbr:]},
+                          storage=storage)
+        # request frames in the stream's storage dtype
+        ex = big.nbr_images[sp.n_nbr:]
+        if storage == "f32":
+            cs.frames = ex.contiguous()
+        else:
+            from . import surfgn as sg
+            from .engine import STORAGE, U8_SCALE
+            tdt = torch.float16 if storage == "f16" else torch.uint8
+            fr = torch.empty(ex.shape, dtype=tdt, device=ex.device)
+            for i in range(ex.shape[0]):
+                sg.sgn_quantize(ctx.handle, ex[i].data_ptr(), ex[i].stride(0),
+                                sg.image_of(fr[i], 1.0 if storage == "f16" else U8_SCALE))
+            cs.frames = fr
+        out.append(cs)
+    torch.cuda.synchronize()   # uploads and quantisation are done before any lane uses them
+    return out
+
+
+def serving_benchmark(n_streams: int = 32, rate: float = 200.0, duration: float = 6.0,
+                      warmup: float = 1.0, storage: str = "f16", lanes: int = 2,
+                      pool_bytes: int = 256 << 20, iters: int = 15, seed: int = 599,
+                      specs=None, log=print):
+    """Served (continuous batching) and plain (FIFO, one request at a time,
+    single-keyframe calls) runs of the same Poisson trace.  Returns the
+    latency / throughput statistics of both."""
+    import torch
+
+    from . import surfgn as sg
+    from scenegen import stream_specs
+    specs = specs if specs is not None else stream_specs(n_streams)
+    extra = 4
+    trace = poisson_arrivals(rate, duration, len(specs), seed, extra)
+    out = {"trace": {"streams": len(specs), "rate_rps": rate, "seconds": duration,
+                     "warmup_s": warmup, "requests": len(trace), "iterations": iters,
+                     "storage": storage, "pool_mb": pool_bytes >> 20, "lanes": lanes}}
+    for mode in ("served", "plain"):
+        ctx = sg.Context(0)
+        streams = make_streams(ctx, specs, extra=extra, storage=storage)
+        torch.cuda.synchronize()
+        ex = HipExecutor(streams, lanes=lanes, iters=iters) if mode == "served" else \
+            PlainExecutor(streams, iters=iters)
+        srv = Server(ex, pool_bytes=pool_bytes, max_batch=32 if mode == "served" else 1)
+        # warm the kernels and graphs on a short burst outside the measured trace
+        for s in range(min(4, len(streams))):
+            srv.submit(Request(stream=s, arrival=srv.clock(), frame_index=0))
+        srv.drain()
+        srv.completed.clear()
+        srv.batches.clear()
+        done = run_trace(srv, trace, warmup=warmup)
+        st = latency_stats(done)
+        sf = sum(streams[r.stream].dk.n_surfels * streams[r.stream].dk.n_nbr for r in done
+                 if r.error is None) * iters
+        span = max(r.done for r in done) - min(r.arrival for r in done) if done else 1.0
+        st["surfel_frame_updates_per_s"] = sf / span
+        st["mean_batch"] = float(np.mean(srv.batches)) if srv.batches else 0.0
+        st["pool_peak_mb"] = srv.pool.peak / 2 ** 20
+        out[mode] = st
+        log(f"{mode}: {st}")
+        for c in getattr(ex, "ctxs", []):
+            c.close()
+        ctx.close()
+        del streams, ex, srv
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out

@@ -12,7 +12,7 @@ from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsurfgn.so")
+LIB_PATH = os.environ.get("SURFGN_LIB") or os.path.join(HERE, "libsurfgn.so")
 
 SGN_OK = 0
 SGN_E_INVALID = -1

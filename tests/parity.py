@@ -76,7 +76,7 @@ def compare(dev: dict, st: dict, idx=None):
 # (an equally good minimum of the cost) instead of closeness.
 PROBE_EPS = 2e-6
 PROBE_SEEDS = (1, 2, 3)
-UNSTABLE_COST_RATIO = 1.5
+UNSTABLE_COST_RATIO = 1.10
 
 
 def as_dev(st: dict) -> dict:
@@ -85,17 +85,20 @@ def as_dev(st: dict) -> dict:
 
 
 def unstable_set(dk, init_id, init_n, is_new, params, base, subset=None):
-    """Surfels whose oracle result is not stable under the conditioning probe."""
+    """Surfels whose oracle result is not stable under the conditioning
+    probe, and the probe runs' final states."""
     import dataclasses
     n = base["inv_depth"].shape[0]
     idx = np.arange(n) if subset is None else np.asarray(subset)
     bad = np.zeros(n, bool)
+    runs = []
     for seed in PROBE_SEEDS:
         p = dataclasses.replace(params, perturb=PROBE_EPS, perturb_seed=seed)
         _, st = run_oracle(dk, init_id, init_n, is_new, p, subset=subset)
         c = compare(as_dev(st), base, idx=idx)
         bad[idx] |= ~c["within"] | ~c["same_flags"]
-    return bad
+        runs.append(st)
+    return bad, runs
 
 
 def final_costs(okf, states: dict, idx, huber_k=9.0 / 255.0):
@@ -116,13 +119,18 @@ def check_parity(dk, dev: dict, init_id, init_n, is_new, params, subset=None, la
     okf, base = run_oracle(dk, init_id, init_n, is_new, params, subset=subset)
     idx = np.arange(base["inv_depth"].shape[0]) if subset is None else np.asarray(subset)
     c = compare(dev, base, idx=idx)
-    uns = unstable_set(dk, init_id, init_n, is_new, params, base, subset=subset)[idx]
+    uns_all, runs = unstable_set(dk, init_id, init_n, is_new, params, base, subset=subset)
+    uns = uns_all[idx]
     ratios = np.zeros(0)
     ui = idx[uns & ~c["within"]]
     if ui.size:
+        # the device result must be as good as the worst of the oracle's own
+        # FP32-level outcomes (base run and probe runs) for that surfel
         cg = final_costs(okf, dev, ui, params.huber_k)
-        co = final_costs(okf, as_dev(base), ui, params.huber_k)
-        ratios = cg / np.maximum(co, 1e-12)
+        ref = final_costs(okf, as_dev(base), ui, params.huber_k)
+        for st in runs:
+            ref = np.maximum(ref, final_costs(okf, as_dev(st), ui, params.huber_k))
+        ratios = cg / np.maximum(ref, 1e-12)
     stable = ~uns
     print(f"{label} {summary(c)} | unstable {uns.mean():.4f} within-stable "
           f"{c['within'][stable].mean() if stable.any() else 1.0:.5f} "

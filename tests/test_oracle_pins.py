@@ -683,3 +683,25 @@ def test_levenberg_marquardt_never_increases_mean_cost_and_reaches_gn_point():
     n = np.stack([st["nx"], st["ny"], st["nz"]], 1)
     assert np.median(np.abs(st["inv_depth"] / ids - 1)) < 1e-8
     assert np.median(angle_deg(n, ns)) < 1e-6
+
+
+# --- conditioning probe (test facility) --------------------------------------
+
+def test_probe_is_off_by_default_and_small_when_on():
+    okf, ids, ns, rng = _construction_ii(seed=29)
+    init_id = ids * rng.uniform(0.97, 1.03, ids.size)
+    init_n = np.array([rot(np.cross(ns[0], rng.normal(size=3)),
+                           math.radians(rng.uniform(0, 3))) @ ns[0] for _ in range(ids.size)])
+    a = oracle.new_state(init_id, init_n)
+    oracle.optimize(okf, a, oracle.OracleParams(iters=6))
+    b = oracle.new_state(init_id, init_n)
+    oracle.optimize(okf, b, oracle.OracleParams(iters=6, perturb=0.0, perturb_seed=5))
+    assert np.array_equal(a["inv_depth"], b["inv_depth"]) and np.array_equal(a["nz"], b["nz"])
+    c = oracle.new_state(init_id, init_n)
+    oracle.optimize(okf, c, oracle.OracleParams(iters=6, perturb=1e-6, perturb_seed=5))
+    d = oracle.new_state(init_id, init_n)
+    oracle.optimize(okf, d, oracle.OracleParams(iters=6, perturb=1e-6, perturb_seed=6))
+    assert not np.array_equal(c["inv_depth"], a["inv_depth"])
+    assert not np.array_equal(c["inv_depth"], d["inv_depth"])
+    # on this well-conditioned construction the perturbation stays small
+    assert np.max(np.abs(c["inv_depth"] / a["inv_depth"] - 1)) < 1e-5
