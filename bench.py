@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (a kernel of "
+                         "known traffic for scaling the HBM counters)")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of the Poisson serving trace (0: skip the serving leg)")
     return ap.parse_args()
@@ -76,6 +79,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     info = sg.sgn_device_info(0)
     log("device", info)
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib << 18          # float32 elements
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calibrate_copy_mib} MiB read + {args.calibrate_copy_mib} MiB written")
+        del a, b
     ctx = sg.Context(0)
     iters = 15
     t0 = time.time()
@@ -159,6 +171,8 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(dks, kfs, iters, args.cpu_seconds)
     ctx.close()
+    n_kf = len(dks)
+    n_surfels = int(sum(d.n_surfels for d in dks))
     del dks, kfs, pool, init_state
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
@@ -182,10 +196,10 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"batch of {len(dks)} keyframes, mixed 320x240/640x480/1280x720, 4-12 "
+            "workload": f"batch of {n_kf} keyframes, mixed 320x240/640x480/1280x720, 4-12 "
                         f"neighbour frames, 4x4 surfels, {iters} GN iterations, "
                         f"{args.storage} image storage, half the surfels initialised from neighbours",
-            "keyframes": len(dks), "surfels": int(sum(d.n_surfels for d in dks)),
+            "keyframes": n_kf, "surfels": n_surfels,
             "surfel_frames_per_step": int(surfel_frames), "samples_per_step": int(samples),
             "image_storage": args.storage, "iterations": iters,
             "plan": plan.as_dict() if plan is not None else "default",

@@ -126,6 +126,13 @@ typedef struct {
     int32_t depth_only;         /* 1: d id_u / d n_s := 0 (ablation), only id_s moves */
     float beta_r;               /* init neighbour radius in pixels (<= 0: S) */
     uint32_t stamp;             /* written to last_update */
+    float lm_lambda;            /* 0: Gauss-Newton.  > 0: Levenberg-Marquardt (the method
+                                   names it; the paper gives no schedule): each iteration
+                                   solves (H + lambda diag H) d = -b, evaluates the Huber cost
+                                   at the candidate and accepts it when the mean cost per
+                                   valid sample does not increase (lambda /= 10, floor 1e-9),
+                                   else keeps the state (lambda *= 10).  lm_lambda is the
+                                   starting lambda of every surfel. */
 } sgn_params;
 
 /* Launch plan for the fused Gauss-Newton kernel (chosen by sgn_autotune or

@@ -170,6 +170,8 @@ sgn_status check_params(const sgn_params* p) {
     if (!(p->huber_k > 0.f) || !std::isfinite(p->huber_k)) return fail(SGN_E_INVALID, "huber_k must be > 0");
     if (!(p->kappa_fp64 >= 1.f)) return fail(SGN_E_INVALID, "kappa_fp64 must be >= 1");
     if (!std::isfinite(p->beta_r)) return fail(SGN_E_INVALID, "beta_r must be finite");
+    if (!(p->lm_lambda >= 0.f) || !std::isfinite(p->lm_lambda))
+        return fail(SGN_E_INVALID, "lm_lambda must be finite and >= 0");
     return SGN_OK;
 }
 
@@ -318,7 +320,8 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
         item_base += D.n_items;
         H->queues[D.queue].end = item_base;
         surfel_base += D.gw * D.gh;
-        if (D.inv_depth_out) pixel_base += (int64_t)D.width * D.height;
+        if (D.inv_depth_out)
+            pixel_base += ((int64_t)D.width * D.height + kRenderRun - 1) / kRenderRun * kRenderRun;
         any_init |= D.is_new != nullptr;
         any_render |= D.inv_depth_out != nullptr;
     }
@@ -335,6 +338,7 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
     H->depth_only = prm->depth_only;
     H->beta_r = prm->beta_r;
     H->stamp = prm->stamp;
+    H->lm_lambda = prm->lm_lambda;
     H->do_init = fl.init && any_init;
     H->do_gn = fl.gn;
     H->do_render = fl.render && any_render;

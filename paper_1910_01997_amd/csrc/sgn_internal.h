@@ -13,6 +13,7 @@ constexpr int kWaveSize = 64;
 constexpr int kBlockThreads = 256;      // 4 wavefronts per workgroup
 constexpr int kNumCounters = 16;        // work-queue heads (one per XCD + spares)
 constexpr int kXcds = 8;
+constexpr int kRenderRun = 4;            // pixels per render thread (ranges padded to it)
 
 // Per-keyframe descriptor in device memory (one per batch item).
 struct KfDev {
@@ -70,6 +71,8 @@ struct BatchHeader {
     float beta_r;
     uint32_t stamp;
     int32_t do_init, do_gn, do_render, n_queues;
+    float lm_lambda;
+    int32_t pad_lm;
     QueueDev queues[kNumCounters];
 };
 

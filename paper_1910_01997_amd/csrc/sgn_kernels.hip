@@ -77,6 +77,7 @@ __device__ __forceinline__ int dpp_i(int x) {
 // bitwise-same value: each step adds a lane's value and its partner's, and
 // float addition is commutative.
 __device__ __forceinline__ float row_sum(float x) {
+#pragma clang fp contract(off)
     x += dpp_f<0xB1>(x);   // quad_perm [1,0,3,2]
     x += dpp_f<0x4E>(x);   // quad_perm [2,3,0,1]
     x += dpp_f<0x141>(x);  // row_half_mirror
@@ -94,6 +95,7 @@ __device__ __forceinline__ int row_sum(int x) {
 // Sum over a surfel's lanes: 16 lanes (one DPP row) or the whole wavefront.
 template <int LANES>
 __device__ __forceinline__ float group_sum(float x) {
+#pragma clang fp contract(off)
     x = row_sum(x);
     if constexpr (LANES == 64) {
         x += __shfl_xor(x, 16);
@@ -306,10 +308,9 @@ __device__ __forceinline__ bool solve3_fp64(double h00, double h01, double h02, 
 //   q_z      =  Qz + h6 dx  + h7 dy  + k2 id_u
 // with Ex = Q_x - X0 Q_z, Q = H u~_s, hx0 = h0 - X0 h6, kx = k0 - X0 k2, ...
 // all formed in double once per work item and rounded once to float.
-constexpr int kPairWords = 16;
+constexpr int kPairWords = 12;
 enum : int {
-    W_HX0 = 0, W_HX1, W_KX, W_EX, W_HY0, W_HY1, W_KY, W_EY, W_QZ,
-    W_LOX, W_HIX, W_LOY, W_HIY, W_B0, W_PAD0, W_PAD1
+    W_HX0 = 0, W_HX1, W_KX, W_EX, W_HY0, W_HY1, W_KY, W_EY, W_QZ, W_X0, W_Y0, W_B0
 };
 constexpr int kMaxSlots = 4;
 
@@ -320,54 +321,43 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // The four bilinear taps (x0, y0), (x0+1, y0), (x0, y0+1), (x0+1, y0+1) of
-// one image.  f32 images use global loads with a scalar base.  f16 and u8
-// images load each horizontal pair with one 8-byte range-checked buffer load
-// from the aligned dword below it (bytes past the image read as zero), and
-// extract the pair with a funnel shift.
+// one image, read with range-checked buffer loads (bytes past the image read
+// as zero, nothing faults); the second row uses the row pitch as the scalar
+// offset.  f32: one 8-byte load per row.  f16 / u8: one 8-byte load per row
+// from the aligned dword below the pair, and a funnel shift.  o0 is the byte
+// offset of (x0, y0).
 struct Taps {
     float i00, i01, i10, i11;
 };
 
-template <typename T>
-__device__ __forceinline__ Taps load_taps(const void* img, unsigned nbytes, unsigned o0, unsigned pitch_b);
-
-template <>
-__device__ __forceinline__ Taps load_taps<float>(const void* img, unsigned, unsigned o0, unsigned pitch_b) {
-    const gptr<char> b = (gptr<char>)img;
-    Taps t;
-    t.i00 = *(gptr<float>)(b + o0);
-    t.i01 = *(gptr<float>)(b + o0 + 4);
-    t.i10 = *(gptr<float>)(b + o0 + pitch_b);
-    t.i11 = *(gptr<float>)(b + o0 + pitch_b + 4);
-    return t;
-}
-
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ unsigned load_pair_bits(__amdgpu_buffer_rsrc_t rs, unsigned o, unsigned shift) {
-    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, o & ~3u, 0, 0);
-    return __builtin_amdgcn_alignbit(v.y, v.x, shift);
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const void* img, unsigned nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(img), (short)0, (int)nbytes, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ Taps load_taps(__amdgpu_buffer_rsrc_t rs, unsigned o0, unsigned pitch_b);
+
+template <>
+__device__ __forceinline__ Taps load_taps<float>(__amdgpu_buffer_rsrc_t rs, unsigned o0, unsigned pitch_b) {
+    const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(rs, o0, 0, 0);
+    const u32x2 b = __builtin_amdgcn_raw_buffer_load_b64(rs, o0, pitch_b, 0);
+    Taps t;
+    t.i00 = __uint_as_float(a.x);
+    t.i01 = __uint_as_float(a.y);
+    t.i10 = __uint_as_float(b.x);
+    t.i11 = __uint_as_float(b.y);
+    return t;
 }
 
 template <>
-__device__ __forceinline__ Taps load_taps<_Float16>(const void* img, unsigned nbytes, unsigned o0,
-                                                   unsigned pitch_b) {
-#ifdef SGN_F16_UNALIGNED_PAIRS
-    // each horizontal pair as one 4-byte load at 2-byte alignment
-    const gptr<char> bp = (gptr<char>)img;
-    Taps t;
-    t.i00 = (float)*(gptr<_Float16>)(bp + o0);
-    t.i01 = (float)*(gptr<_Float16>)(bp + o0 + 2);
-    t.i10 = (float)*(gptr<_Float16>)(bp + o0 + pitch_b);
-    t.i11 = (float)*(gptr<_Float16>)(bp + o0 + pitch_b + 2);
-    (void)nbytes;
-    return t;
-#endif
-    const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(img), (short)0, (int)nbytes, 0x00020000);
-    const unsigned sh = (o0 & 2u) * 8u;          // pitch_b is a multiple of 4
-    const unsigned a = load_pair_bits(rs, o0, sh);
-    const unsigned b = load_pair_bits(rs, o0 + pitch_b, sh);
+__device__ __forceinline__ Taps load_taps<_Float16>(__amdgpu_buffer_rsrc_t rs, unsigned o0, unsigned pitch_b) {
+    const unsigned base = o0 & ~3u, sh = (o0 & 2u) * 8u;          // pitch_b is a multiple of 4
+    const u32x2 va = __builtin_amdgcn_raw_buffer_load_b64(rs, base, 0, 0);
+    const u32x2 vb = __builtin_amdgcn_raw_buffer_load_b64(rs, base, pitch_b, 0);
+    const unsigned a = __builtin_amdgcn_alignbit(va.y, va.x, sh);
+    const unsigned b = __builtin_amdgcn_alignbit(vb.y, vb.x, sh);
     Taps t;
     t.i00 = (float)__builtin_bit_cast(_Float16, (unsigned short)(a & 0xffffu));
     t.i01 = (float)__builtin_bit_cast(_Float16, (unsigned short)(a >> 16));
@@ -377,19 +367,58 @@ __device__ __forceinline__ Taps load_taps<_Float16>(const void* img, unsigned nb
 }
 
 template <>
-__device__ __forceinline__ Taps load_taps<uint8_t>(const void* img, unsigned nbytes, unsigned o0,
-                                                  unsigned pitch_b) {
-    const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(img), (short)0, (int)nbytes, 0x00020000);
-    const unsigned sh = (o0 & 3u) * 8u;          // pitch_b is a multiple of 4
-    const unsigned a = load_pair_bits(rs, o0, sh);
-    const unsigned b = load_pair_bits(rs, o0 + pitch_b, sh);
+__device__ __forceinline__ Taps load_taps<uint8_t>(__amdgpu_buffer_rsrc_t rs, unsigned o0, unsigned pitch_b) {
+    const unsigned base = o0 & ~3u, sh = (o0 & 3u) * 8u;
+    const u32x2 va = __builtin_amdgcn_raw_buffer_load_b64(rs, base, 0, 0);
+    const u32x2 vb = __builtin_amdgcn_raw_buffer_load_b64(rs, base, pitch_b, 0);
+    const unsigned a = __builtin_amdgcn_alignbit(va.y, va.x, sh);
+    const unsigned b = __builtin_amdgcn_alignbit(vb.y, vb.x, sh);
     Taps t;
     t.i00 = (float)(a & 0xffu);
     t.i01 = (float)((a >> 8) & 0xffu);
     t.i10 = (float)(b & 0xffu);
     t.i11 = (float)((b >> 8) & 0xffu);
     return t;
+}
+
+// floor(x) converted to int in one instruction (v_cvt_flr_i32_f32).
+__device__ __forceinline__ int cvt_floor(float x) {
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// Warp of one sample into frame f in local coordinates (see the pair words):
+// returns validity; on success the integer tap corner offset o0 and the
+// bilinear fractions.  Valid iff q_z > 0 and 0 <= x_p < W-1, 0 <= y_p < H-1,
+// decided exactly on the integer corner X0 + floor(x_p - X0).
+struct Warp {
+    float fx, fy, rq, ax, ay;
+    unsigned o0;
+    bool v;
+};
+
+template <typename T>
+__device__ __forceinline__ Warp warp_sample(const float4& c0, const float4& c1, const float4& c2,
+                                            float h6, float h7, float k2, float dx, float dy,
+                                            float idu, bool pix_ok, unsigned wm1, unsigned hm1,
+                                            unsigned pitch_b) {
+    Warp w;
+    const float nxq = fmaf(c0.x, dx, fmaf(c0.y, dy, fmaf(c0.z, idu, c0.w)));
+    const float nyq = fmaf(c1.x, dx, fmaf(c1.y, dy, fmaf(c1.z, idu, c1.w)));
+    const float qz = fmaf(h6, dx, fmaf(h7, dy, fmaf(k2, idu, c2.x)));
+    w.rq = rcp_fast(qz);
+    w.fx = nxq * w.rq;                                   // x_p - X0
+    w.fy = nyq * w.rq;                                   // y_p - Y0
+    const int flx = cvt_floor(w.fx), fly = cvt_floor(w.fy);
+    // unsigned wrap-around: out-of-range (or saturated) corners fail the test
+    const unsigned ix = __float_as_uint(c2.y) + (unsigned)flx;
+    const unsigned iy = __float_as_uint(c2.z) + (unsigned)fly;
+    w.v = pix_ok & (qz > 0.f) & (ix < wm1) & (iy < hm1);
+    w.ax = __builtin_amdgcn_fractf(w.fx);
+    w.ay = __builtin_amdgcn_fractf(w.fy);
+    w.o0 = __umul24(iy, pitch_b) + ix * (unsigned)sizeof(T);
+    return w;
 }
 
 // The frame loop of one Gauss-Newton iteration for one pixel (lane): warp
@@ -400,56 +429,69 @@ __device__ __forceinline__ Taps load_taps<uint8_t>(const void* img, unsigned nby
 template <typename T, bool LAST>
 __device__ __forceinline__ void frame_loop(const float* __restrict__ pc, cptr<FrameDev> fr, int nf,
                                            float dx, float dy, float idu, bool pix_ok,
-                                           unsigned pitch_b, unsigned img_bytes, float ikf, float hk,
-                                           float img_scale,
+                                           unsigned pitch_b, unsigned img_bytes, unsigned wm1,
+                                           unsigned hm1, float ikf, float hk, float img_scale,
                                            float& A, float& B, float& cst, int& nvl) {
     constexpr bool SCALED = std::is_same<T, uint8_t>::value;
     for (int f = 0; f < nf; ++f) {
         const float4 c0 = *(const float4*)(pc + f * kPairWords);
         const float4 c1 = *(const float4*)(pc + f * kPairWords + 4);
         const float4 c2 = *(const float4*)(pc + f * kPairWords + 8);
-        const float4 c3 = *(const float4*)(pc + f * kPairWords + 12);
         const float h6 = fr[f].zrow[0], h7 = fr[f].zrow[1], k2 = fr[f].zrow[2];
-        // Eq. 6 in local coordinates (see above)
-        const float nxq = fmaf(c0.x, dx, fmaf(c0.y, dy, fmaf(c0.z, idu, c0.w)));
-        const float nyq = fmaf(c1.x, dx, fmaf(c1.y, dy, fmaf(c1.z, idu, c1.w)));
-        const float qz = fmaf(h6, dx, fmaf(h7, dy, fmaf(k2, idu, c2.x)));
-        const float rq = rcp_fast(qz);
-        const float fx = nxq * rq, fy = nyq * rq;      // x_p - X0, y_p - Y0
-        // valid iff 0 <= x_p < W-1 and 0 <= y_p < H-1 (bounds exact in float)
-        const bool v = pix_ok & (qz > 0.f) & (fx >= c2.y) & (fx < c2.z) & (fy >= c2.w) & (fy < c3.x);
-        if (v) {
-            const void* img = fr[f].img;
-            const float ffx = floorf(fx), ffy = floorf(fy);
-            const int flx = (int)ffx, fly = (int)ffy;
-            const float ax = fx - ffx;
-            const float ay = fy - ffy;
-            // byte offset of (X0 + flx, Y0 + fly); unsigned wrap-around arithmetic
-            const unsigned o0 = __float_as_uint(c3.y) + (unsigned)__mul24(fly, (int)pitch_b) +
-                                (unsigned)flx * (unsigned)sizeof(T);
-            const Taps tp = load_taps<T>(img, img_bytes, o0, pitch_b);
-            const float i00 = tp.i00, i01 = tp.i01, i10 = tp.i10, i11 = tp.i11;
+        // Eq. 6 in local coordinates
+        const Warp w = warp_sample<T>(c0, c1, c2, h6, h7, k2, dx, dy, idu, pix_ok, wm1, hm1, pitch_b);
+        if (w.v) {
+            const Taps tp = load_taps<T>(image_rsrc(fr[f].img, img_bytes), w.o0, pitch_b);
             // bilinear value and the exact gradient of the interpolant
-            const float d0 = i01 - i00, d1 = i11 - i10;
-            const float top = fmaf(ax, d0, i00);
-            const float bot = fmaf(ax, d1, i10);
+            const float d0 = tp.i01 - tp.i00, d1 = tp.i11 - tp.i10;
+            const float top = fmaf(w.ax, d0, tp.i00);
+            const float bot = fmaf(w.ax, d1, tp.i10);
             const float gy = bot - top;
-            const float val = fmaf(ay, gy, top);
-            const float gx = fmaf(ay, d1 - d0, d0);
+            const float val = fmaf(w.ay, gy, top);
+            const float gx = fmaf(w.ay, d1 - d0, d0);
             // residual (Eq. 5) and Huber IRLS weight w = min(1, k/|r|) (Eq. 8)
             const float r = SCALED ? fmaf(val, img_scale, -ikf) : val - ikf;
             const float ar = fabsf(r);
-            const float w = fminf(1.f, hk * rcp_fast(ar));
+            const float wt = fminf(1.f, hk * rcp_fast(ar));
             // dr/did_u = grad I . dpi/dq . K t  (Eq. 8 with dq/did_u = K t):
             // (k0 - x_p k2) = kx - (x_p - X0) k2, likewise for y
-            const float tx_ = fmaf(-fx, k2, c0.z);
-            const float ty_ = fmaf(-fy, k2, c1.z);
-            const float a = fmaf(gx, tx_, gy * ty_) * (SCALED ? rq * img_scale : rq);
-            const float wa = w * a;
+            const float tx_ = fmaf(-w.fx, k2, c0.z);
+            const float ty_ = fmaf(-w.fy, k2, c1.z);
+            const float a = fmaf(gx, tx_, gy * ty_) * (SCALED ? w.rq * img_scale : w.rq);
+            const float wa = wt * a;
             A = fmaf(wa, a, A);
             B = fmaf(wa, r, B);
             ++nvl;
             if constexpr (LAST) cst += (ar <= hk) ? 0.5f * r * r : hk * (ar - 0.5f * hk);
+        }
+    }
+}
+
+// Huber cost (Eq. 5) and valid-sample count of one pixel at a candidate
+// state, over all neighbour frames (no Jacobian): the Levenberg-Marquardt
+// acceptance test.
+template <typename T>
+__device__ __forceinline__ void frame_cost(const float* __restrict__ pc, cptr<FrameDev> fr, int nf,
+                                           float dx, float dy, float idu, bool pix_ok,
+                                           unsigned pitch_b, unsigned img_bytes, unsigned wm1,
+                                           unsigned hm1, float ikf, float hk, float img_scale,
+                                           float& cst, int& nvl) {
+    constexpr bool SCALED = std::is_same<T, uint8_t>::value;
+    for (int f = 0; f < nf; ++f) {
+        const float4 c0 = *(const float4*)(pc + f * kPairWords);
+        const float4 c1 = *(const float4*)(pc + f * kPairWords + 4);
+        const float4 c2 = *(const float4*)(pc + f * kPairWords + 8);
+        const float h6 = fr[f].zrow[0], h7 = fr[f].zrow[1], k2 = fr[f].zrow[2];
+        const Warp w = warp_sample<T>(c0, c1, c2, h6, h7, k2, dx, dy, idu, pix_ok, wm1, hm1, pitch_b);
+        if (w.v) {
+            const Taps tp = load_taps<T>(image_rsrc(fr[f].img, img_bytes), w.o0, pitch_b);
+            const float top = fmaf(w.ax, tp.i01 - tp.i00, tp.i00);
+            const float bot = fmaf(w.ax, tp.i11 - tp.i10, tp.i10);
+            const float val = fmaf(w.ay, bot - top, top);
+            const float r = SCALED ? fmaf(val, img_scale, -ikf) : val - ikf;
+            const float ar = fabsf(r);
+            cst += (ar <= hk) ? 0.5f * r * r : hk * (ar - 0.5f * hk);
+            ++nvl;
         }
     }
 }
@@ -476,6 +518,8 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
     const float kap2 = hdr->kappa_fp64 * hdr->kappa_fp64;
     const bool depth_only = hdr->depth_only != 0;
     const uint32_t stamp = hdr->stamp;
+    const float lm0 = hdr->lm_lambda;
+    const bool lm = lm0 > 0.f;
     const cptr<KfDev> kfs = (cptr<KfDev>)hdr->kfs;
 
     const int wave_global = blockIdx.x * (kBlockThreads / kWaveSize) + (threadIdx.x >> 6);
@@ -505,6 +549,7 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
         const float img_scale = K->img_scale;
         const unsigned pitch_b = (unsigned)K->nbr_pitch_b;
         const unsigned img_bytes = pitch_b * (unsigned)K->height;
+        const unsigned wm1 = (unsigned)(K->width - 1), hm1 = (unsigned)(K->height - 1);
         {
             // warp constants of every (surfel slot, frame) pair of this item,
             // one pair per lane, in double
@@ -535,13 +580,9 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                 w[W_KY] = (float)(kt[1] - Y0 * kt[2]);
                 w[W_EY] = (float)(Qy - Y0 * Qz);
                 w[W_QZ] = (float)Qz;
-                w[W_LOX] = (float)(-X0);
-                w[W_HIX] = (float)((double)(K->width - 1) - X0);
-                w[W_LOY] = (float)(-Y0);
-                w[W_HIY] = (float)((double)(K->height - 1) - Y0);
-                w[W_B0] = __uint_as_float((unsigned)(int)Y0 * pitch_b + (unsigned)(int)X0 * (unsigned)sizeof(T));
-                w[W_PAD0] = 0.f;
-                w[W_PAD1] = 0.f;
+                w[W_X0] = __int_as_float((int)X0);
+                w[W_Y0] = __int_as_float((int)Y0);
+                w[W_B0] = 0.f;
             }
             wave_sync();
         }
@@ -571,9 +612,13 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
         bool updated = false;
         float cost_out = 0.f;
         int nv_out = 0;
+        float lam = lm0;             // Levenberg-Marquardt damping of this surfel
 
         for (int it = 0; it < iters; ++it) {
             const bool last = (it == iters - 1);
+            float id_cand = 0.f, nx_cand = 0.f, ny_cand = 0.f, nz_cand = 0.f;
+            bool have_cand = false;
+            (void)have_cand;
             const float c = nx * rsx + ny * rsy + nz;     // n . r_s
             if (alive && fabsf(c) < 1e-6f) {
                 flags |= F_DEGENERATE;
@@ -607,26 +652,36 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
 
             float A = 0.f, B = 0.f, cst = 0.f;
             int nvl = 0;
-            if (last)
-                frame_loop<T, true>(pc, fr, nf, dxp, dyp, idu, pix_ok, pitch_b, img_bytes, ikf, hk,
-                                    img_scale, A, B, cst, nvl);
+            if (last || lm)
+                frame_loop<T, true>(pc, fr, nf, dxp, dyp, idu, pix_ok, pitch_b, img_bytes, wm1, hm1,
+                                    ikf, hk, img_scale, A, B, cst, nvl);
             else
-                frame_loop<T, false>(pc, fr, nf, dxp, dyp, idu, pix_ok, pitch_b, img_bytes, ikf, hk,
-                                     img_scale, A, B, cst, nvl);
+                frame_loop<T, false>(pc, fr, nf, dxp, dyp, idu, pix_ok, pitch_b, img_bytes, wm1, hm1,
+                                     ikf, hk, img_scale, A, B, cst, nvl);
             // J^T W J = sum_u A_u g g^T, J^T W r = sum_u B_u g (frame sum hoisted)
-            const float ag0 = A * g0, ag1 = A * g1, ag2 = A * g2;
-            const float H00 = group_sum<LANES>(ag0 * g0);
-            const float H01 = group_sum<LANES>(ag0 * g1);
-            const float H02 = group_sum<LANES>(ag0 * g2);
-            const float H11 = group_sum<LANES>(ag1 * g1);
-            const float H12 = group_sum<LANES>(ag1 * g2);
-            const float H22 = group_sum<LANES>(ag2 * g2);
-            const float bb0 = group_sum<LANES>(B * g0);
-            const float bb1 = group_sum<LANES>(B * g1);
-            const float bb2 = group_sum<LANES>(B * g2);
-            const int nv = group_sum<LANES>(nvl);
-            if (last) {
-                cost_out = group_sum<LANES>(cst);
+            float H00, H01, H02, H11, H12, H22, bb0, bb1, bb2;
+            int nv;
+            {
+                // No FMA contraction here: each butterfly step must be a plain
+                // add of two rounded values so that every lane of a surfel
+                // ends with bitwise-identical sums (and identical states).
+#pragma clang fp contract(off)
+                const float ag0 = A * g0, ag1 = A * g1, ag2 = A * g2;
+                H00 = group_sum<LANES>(ag0 * g0);
+                H01 = group_sum<LANES>(ag0 * g1);
+                H02 = group_sum<LANES>(ag0 * g2);
+                H11 = group_sum<LANES>(ag1 * g1);
+                H12 = group_sum<LANES>(ag1 * g2);
+                H22 = group_sum<LANES>(ag2 * g2);
+                bb0 = group_sum<LANES>(B * g0);
+                bb1 = group_sum<LANES>(B * g1);
+                bb2 = group_sum<LANES>(B * g2);
+                nv = group_sum<LANES>(nvl);
+            }
+            float cost_here = 0.f;
+            if (last || lm) {
+                cost_here = group_sum<LANES>(cst);
+                if (last) cost_out = cost_here;
             }
             if (!alive) continue;
             nv_out = nv;
@@ -635,9 +690,10 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                 continue;
             }
             float d0s = 0.f, d1s = 0.f, d2s = 0.f;
+            const float dd = 1.f + lam;          // (H + lam diag H): equilibrated diagonal
             if (depth_only) {
                 if (H00 > 0.f && isfinite(H00)) {
-                    d0s = -bb0 / H00;
+                    d0s = -bb0 / (H00 * dd);
                 } else {
                     flags |= F_SOLVE_FAIL;
                     continue;
@@ -649,21 +705,22 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                 if (!need64) {
                     const float e0 = __frsqrt_rn(H00), e1 = __frsqrt_rn(H11), e2 = __frsqrt_rn(H22);
                     const float e01 = H01 * e0 * e1, e02 = H02 * e0 * e2, e12 = H12 * e1 * e2;
-                    // adjugate and determinant of E
-                    const float c00 = fmaf(-e12, e12, 1.f), c11 = fmaf(-e02, e02, 1.f);
-                    const float c22 = fmaf(-e01, e01, 1.f);
-                    const float c01 = fmaf(e02, e12, -e01), c02 = fmaf(e01, e12, -e02);
-                    const float c12 = fmaf(e01, e02, -e12);
-                    const float det = fmaf(e01, c01, fmaf(e02, c02, c00));
+                    // adjugate and determinant of E (diagonal dd = 1 + lambda)
+                    const float d2 = dd * dd;
+                    const float c00 = fmaf(-e12, e12, d2), c11 = fmaf(-e02, e02, d2);
+                    const float c22 = fmaf(-e01, e01, d2);
+                    const float c01 = fmaf(e02, e12, -dd * e01), c02 = fmaf(e01, e12, -dd * e02);
+                    const float c12 = fmaf(e01, e02, -dd * e12);
+                    const float det = fmaf(e01, c01, fmaf(e02, c02, dd * c00));
                     // kappa_F(E)^2 = ||E||_F^2 ||adj E||_F^2 / det^2  (>= kappa_2(E)^2)
-                    const float fro2 = 3.f + 2.f * (e01 * e01 + e02 * e02 + e12 * e12);
+                    const float fro2 = 3.f * d2 + 2.f * (e01 * e01 + e02 * e02 + e12 * e12);
                     const float adj2 = c00 * c00 + c11 * c11 + c22 * c22 +
                                        2.f * (c01 * c01 + c02 * c02 + c12 * c12);
                     // raw Cholesky pivots are H_jj times the equilibrated ones
-                    const float p1 = c22;                 // 1 - e01^2
-                    const float p2 = det / p1;
-                    need64 = !(fro2 * adj2 <= kap2 * det * det) || !(det > 0.f) ||
-                             !(H11 * p1 > 1e-10f * maxd) || !(H22 * p2 > 1e-10f * maxd);
+                    const float p1 = c22 / dd;            // dd - e01^2 / dd
+                    const float p2 = det / c22;
+                    need64 = !(fro2 * adj2 <= kap2 * det * det) || !(det > 0.f) || !(c22 > 0.f) ||
+                             !(H11 * p1 > 1e-10f * maxd * dd) || !(H22 * p2 > 1e-10f * maxd * dd);
                     if (!need64) {
                         const float bh0 = bb0 * e0, bh1 = bb1 * e1, bh2 = bb2 * e2;
                         const float idet = 1.0f / det;
@@ -675,7 +732,9 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                 if (need64) {
                     flags |= F_FP64_SOLVE;
                     double dd0 = 0.0, dd1 = 0.0, dd2 = 0.0;
-                    if (solve3_fp64(H00, H01, H02, H11, H12, H22, bb0, bb1, bb2, dd0, dd1, dd2)) {
+                    const double dmp = 1.0 + (double)lam;
+                    if (solve3_fp64((double)H00 * dmp, H01, H02, (double)H11 * dmp, H12,
+                                    (double)H22 * dmp, bb0, bb1, bb2, dd0, dd1, dd2)) {
                         d0s = (float)dd0; d1s = (float)dd1; d2s = (float)dd2;
                     } else {
                         flags |= F_SOLVE_FAIL;
@@ -686,26 +745,50 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
             // update: id_s += d0; n = normalise(n + d1 b1 + d2 b2) (the depth-only
             // ablation moves id_s alone and leaves n as it is)
             const float idn = id + d0s;
+            float cnx = nx, cny = ny, cnz = nz;
+            bool ok_step;
             if (depth_only) {
-                if (!(idn > 0.f) || !isfinite(idn)) {
-                    flags |= F_REJECTED;
+                ok_step = (idn > 0.f) && isfinite(idn);
+            } else {
+                const float mx = fmaf(d1s, b1x, fmaf(d2s, b2x, nx));
+                const float my = fmaf(d1s, b1y, fmaf(d2s, b2y, ny));
+                const float mz = fmaf(d1s, b1z, fmaf(d2s, b2z, nz));
+                const float l2 = mx * mx + my * my + mz * mz;
+                ok_step = (idn > 0.f) && isfinite(idn) && (l2 > 0.f) && isfinite(l2);
+                if (ok_step) {
+                    const float il = __frsqrt_rn(l2);
+                    cnx = mx * il; cny = my * il; cnz = mz * il;
+                }
+            }
+            if (!ok_step) {
+                flags |= F_REJECTED;
+                if (lm) lam *= 10.f;
+                continue;
+            }
+            id_cand = idn; nx_cand = cnx; ny_cand = cny; nz_cand = cnz;
+            have_cand = true;
+            if (lm) {
+                // Levenberg-Marquardt: accept the step only if the mean Huber
+                // cost per valid sample does not increase.  All lanes of a
+                // surfel take the same branches, so the row reductions below
+                // see every lane of the surfel.
+                const float cc = nx_cand * rsx + ny_cand * rsy + nz_cand;
+                const float sig = (nx_cand * drx + ny_cand * dry) * (1.0f / cc);
+                const float idu_c = fmaf(id_cand, sig, id_cand);
+                float cst2 = 0.f;
+                int nv2l = 0;
+                frame_cost<T>(pc, fr, nf, dxp, dyp, idu_c, idu_c > 0.f, pitch_b, img_bytes, wm1, hm1,
+                              ikf, hk, img_scale, cst2, nv2l);
+                const float cost2 = group_sum<LANES>(cst2);
+                const int nv2 = group_sum<LANES>(nv2l);
+                if (nv2 < 3 || cost2 / (float)nv2 > cost_here / (float)nv) {
+                    lam *= 10.f;
                     continue;
                 }
-                id = idn;
-                updated = true;
-                continue;
+                lam = fmaxf(lam * 0.1f, 1e-9f);
             }
-            const float mx = fmaf(d1s, b1x, fmaf(d2s, b2x, nx));
-            const float my = fmaf(d1s, b1y, fmaf(d2s, b2y, ny));
-            const float mz = fmaf(d1s, b1z, fmaf(d2s, b2z, nz));
-            const float l2 = mx * mx + my * my + mz * mz;
-            if (!(idn > 0.f) || !isfinite(idn) || !(l2 > 0.f) || !isfinite(l2)) {
-                flags |= F_REJECTED;
-                continue;
-            }
-            const float il = __frsqrt_rn(l2);
-            id = idn;
-            nx = mx * il; ny = my * il; nz = mz * il;
+            id = id_cand;
+            nx = nx_cand; ny = ny_cand; nz = nz_cand;
             updated = true;
         }
         if (tile_ok && p == 0) {
@@ -721,53 +804,70 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
 
 // ----------------------------------------------------------- render kernel --
 
-// Inverse Depth Calculation section: each pixel takes Eq. 3 of its surfel.
-__global__ void render_kernel(const BatchHeader* __restrict__ hdr) {
+// Inverse Depth Calculation section: each pixel takes Eq. 3 of its surfel,
+// id_u = id_s (1 + sigma), sigma = n . (r_u - r_s) / (n . r_s).  Pixels are
+// numbered keyframe after keyframe (only keyframes with an output, each range
+// padded to a multiple of kRenderRun so that a run never spans two
+// keyframes); each thread walks one run of kRenderRun consecutive pixels.
+
+__global__ void render_kernel(const BatchHeader* __restrict__ hdr_) {
+    const cptr<BatchHeader> hdr = (cptr<BatchHeader>)hdr_;
+    const cptr<KfDev> kfs = (cptr<KfDev>)hdr->kfs;
+    const int n_kf = hdr->n_kf;
     const int64_t total = hdr->total_pixels;
     int hint = 0;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
-         g += (int64_t)gridDim.x * blockDim.x) {
-        const KfDev* kh = &hdr->kfs[hint];
-        if (!(kh->inv_depth_out && g >= kh->pixel_base &&
-              g < kh->pixel_base + (int64_t)kh->width * kh->height)) {
-            int lo = 0, hi = hdr->n_kf - 1;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (hdr->kfs[mid].pixel_base <= g) lo = mid; else hi = mid - 1;
+    for (int64_t g0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRenderRun; g0 < total;
+         g0 += (int64_t)gridDim.x * blockDim.x * kRenderRun) {
+        // keyframe of pixel g0 (fast path: the previous one)
+        {
+            const cptr<KfDev> kh = kfs + hint;
+            if (!(kh->inv_depth_out && g0 >= kh->pixel_base &&
+                  g0 < kh->pixel_base + (int64_t)kh->width * kh->height)) {
+                int lo = 0, hi = n_kf - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (kfs[mid].pixel_base <= g0) lo = mid; else hi = mid - 1;
+                }
+                hint = lo;
             }
-            // skip keyframes without output (they add no pixels)
-            while (lo < hdr->n_kf - 1 && !hdr->kfs[lo].inv_depth_out) ++lo;
-            hint = lo;
         }
-        const KfDev& K = hdr->kfs[hint];
-        const int64_t o = g - K.pixel_base;
-        const int x = (int)(o % K.width), y = (int)(o / K.width);
-        const int S = K.patch;
-        const int tx = x / S, ty = y / S;
-        float out = 0.f;
-        int idx = -1;
-        if (tx < K.gw && ty < K.gh) {
-            const int i = ty * K.gw + tx;
-            if (!(K.flags[i] & (F_DEGENERATE | F_UNINIT))) {
-                const float half = 0.5f * (float)(S - 1);
-                const float usx = (float)(S * tx) + half, usy = (float)(S * ty) + half;
-                const float rsx = (usx - K.cx) / K.fx, rsy = (usy - K.cy) / K.fy;
-                const float drx = ((float)x - usx) / K.fx, dry = ((float)y - usy) / K.fy;
-                const float nx = K.nx[i], ny = K.ny[i], nz = K.nz[i];
-                const float c = nx * rsx + ny * rsy + nz;
-                if (fabsf(c) >= 1e-6f) {
-                    const float id = K.inv_depth[i];
-                    const float sigma = (nx * drx + ny * dry) / c;
-                    const float idu = fmaf(id, sigma, id);
-                    if (idu > 0.f && isfinite(idu)) {
-                        out = idu;
-                        idx = i;
+        const cptr<KfDev> K = kfs + hint;
+        const int W = K->width, H = K->height, S = K->patch;
+        const int npix = W * H;
+        const int o_first = (int)(g0 - K->pixel_base);
+        const float half = 0.5f * (float)(S - 1);
+        float* const out = K->inv_depth_out;
+        int32_t* const idx_out = K->index_out;
+        for (int j = 0; j < kRenderRun; ++j) {
+            const int o = o_first + j;
+            if (o >= npix) break;            // padding after the keyframe's last pixel
+            const int y = o / W, x = o - y * W;
+            const int tx = x / S, ty = y / S;
+            float val = 0.f;
+            int idx = -1;
+            if (tx < K->gw && ty < K->gh) {
+                const int i = ty * K->gw + tx;
+                if (!(K->flags[i] & (F_DEGENERATE | F_UNINIT))) {
+                    const float usx = (float)(S * tx) + half, usy = (float)(S * ty) + half;
+                    const float rsx = (usx - K->cx) / K->fx, rsy = (usy - K->cy) / K->fy;
+                    const float nx = K->nx[i], ny = K->ny[i], nz = K->nz[i];
+                    const float c = nx * rsx + ny * rsy + nz;
+                    if (fabsf(c) >= 1e-6f) {
+                        const float drx = ((float)x - usx) / K->fx, dry = ((float)y - usy) / K->fy;
+                        const float id = K->inv_depth[i];
+                        const float sigma = (nx * drx + ny * dry) / c;
+                        const float idu = fmaf(id, sigma, id);
+                        if (idu > 0.f && isfinite(idu)) {
+                            val = idu;
+                            idx = i;
+                        }
                     }
                 }
             }
+            out[o] = val;
+            if (idx_out) idx_out[o] = idx;
         }
-        K.inv_depth_out[o] = out;
-        if (K.index_out) K.index_out[o] = idx;
+        (void)H;
     }
 }
 

@@ -72,7 +72,8 @@ class sgn_surfels(C.Structure):
 
 class sgn_params(C.Structure):
     _fields_ = [("iters", C.c_int32), ("huber_k", C.c_float), ("kappa_fp64", C.c_float),
-                ("depth_only", C.c_int32), ("beta_r", C.c_float), ("stamp", C.c_uint32)]
+                ("depth_only", C.c_int32), ("beta_r", C.c_float), ("stamp", C.c_uint32),
+                ("lm_lambda", C.c_float)]
 
 
 class sgn_plan(C.Structure):
@@ -315,9 +316,9 @@ class SurfelState:
 
 
 def params(iters=15, huber_k=9.0 / 255.0, kappa_fp64=1e6, depth_only=False, beta_r=0.0,
-           stamp=1) -> sgn_params:
+           stamp=1, lm_lambda=0.0) -> sgn_params:
     return sgn_params(int(iters), float(huber_k), float(kappa_fp64), int(bool(depth_only)),
-                      float(beta_r), int(stamp))
+                      float(beta_r), int(stamp), float(lm_lambda))
 
 
 def plan(tiles_x=0, tiles_y=0, persistent=1, waves_per_cu=0, lds_stage=0, xcd_queues=1) -> sgn_plan:

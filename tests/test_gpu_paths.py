@@ -271,3 +271,43 @@ def test_full_benchmark_batch_sampled_parity(ctx):
         if ratios.size:
             assert ratios.max() <= UNSTABLE_COST_RATIO
     assert tot_within / tot_stable >= 0.995
+
+
+def test_levenberg_marquardt_matches_oracle(ctx):
+    sg, engine = sgmod()
+    kf = make_keyframe(_small_spec(half_new=True, width=320, height=240, n_rects=8), device="cuda")
+    print("case LM 320x240 lambda=1e-2", flush=True)
+    d = engine.DeviceKeyframe.from_scene(ctx, kf)
+    engine.update_plain(ctx, d, sg.params(iters=10, lm_lambda=1e-2))
+    torch.cuda.synchronize()
+    dev = d.state.to_host()
+    c, uns, ratios = check_parity(d, dev, kf.init_id, kf.init_n, kf.is_new,
+                                  oracle.OracleParams(iters=10, lm_lambda=1e-2), label="LM")
+    assert c["within"][~uns].mean() >= 0.995
+    assert c["same_flags"][~uns].mean() >= 0.999
+
+
+def test_batch_render_with_odd_sizes_matches_plain(ctx):
+    """Keyframes whose pixel counts are not multiples of the render run
+    length: the batched render covers every pixel exactly like the plain one."""
+    sg, engine = sgmod()
+    sizes = [(101, 71), (66, 50), (97, 43)]
+    kfs = [make_keyframe(_small_spec(width=w, height=h, n_nbr=2, half_new=True, n_rects=3, seed=40 + i),
+                         device="cuda") for i, (w, h) in enumerate(sizes)]
+    prm = sg.params(iters=4)
+    ref = []
+    for k in kfs:
+        d = engine.DeviceKeyframe.from_scene(ctx, k, index_map=True)
+        engine.update_plain(ctx, d, prm)
+        torch.cuda.synchronize()
+        ref.append((d.inv_depth_out.cpu().numpy(), d.index_out.cpu().numpy()))
+    ds = [engine.DeviceKeyframe.from_scene(ctx, k, index_map=True) for k in kfs]
+    for d in ds:
+        d.inv_depth_out.fill_(-7.0)
+    engine.update_batch(ctx, ds, prm)
+    torch.cuda.synchronize()
+    for d, (dm, im) in zip(ds, ref):
+        got = d.inv_depth_out.cpu().numpy()
+        assert not np.any(got == -7.0)
+        assert np.array_equal(got, dm)
+        assert np.array_equal(d.index_out.cpu().numpy(), im)
