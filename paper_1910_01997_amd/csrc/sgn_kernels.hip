@@ -352,21 +352,6 @@ __device__ __forceinline__ Taps load_taps<float>(__amdgpu_buffer_rsrc_t rs, unsi
 }
 
 template <>
-__device__ __forceinline__ Taps load_taps<_Float16>(__amdgpu_buffer_rsrc_t rs, unsigned o0, unsigned pitch_b) {
-    const unsigned base = o0 & ~3u, sh = (o0 & 2u) * 8u;          // pitch_b is a multiple of 4
-    const u32x2 va = __builtin_amdgcn_raw_buffer_load_b64(rs, base, 0, 0);
-    const u32x2 vb = __builtin_amdgcn_raw_buffer_load_b64(rs, base, pitch_b, 0);
-    const unsigned a = __builtin_amdgcn_alignbit(va.y, va.x, sh);
-    const unsigned b = __builtin_amdgcn_alignbit(vb.y, vb.x, sh);
-    Taps t;
-    t.i00 = (float)__builtin_bit_cast(_Float16, (unsigned short)(a & 0xffffu));
-    t.i01 = (float)__builtin_bit_cast(_Float16, (unsigned short)(a >> 16));
-    t.i10 = (float)__builtin_bit_cast(_Float16, (unsigned short)(b & 0xffffu));
-    t.i11 = (float)__builtin_bit_cast(_Float16, (unsigned short)(b >> 16));
-    return t;
-}
-
-template <>
 __device__ __forceinline__ Taps load_taps<uint8_t>(__amdgpu_buffer_rsrc_t rs, unsigned o0, unsigned pitch_b) {
     const unsigned base = o0 & ~3u, sh = (o0 & 3u) * 8u;
     const u32x2 va = __builtin_amdgcn_raw_buffer_load_b64(rs, base, 0, 0);
@@ -379,6 +364,55 @@ __device__ __forceinline__ Taps load_taps<uint8_t>(__amdgpu_buffer_rsrc_t rs, un
     t.i10 = (float)(b & 0xffu);
     t.i11 = (float)((b >> 8) & 0xffu);
     return t;
+}
+
+// The two row interpolants of a bilinear sample: for each tap row the
+// difference d = I(x0+1) - I(x0) and the value I(x0) + ax d.  f32 and u8
+// decode the taps first; f16 works on the packed pair directly with mixed
+// precision FMAs (the halves convert exactly to float, so the rounding is
+// that of the float form).
+struct Lerp {
+    float d0, top, d1, bot;
+};
+
+template <typename T>
+__device__ __forceinline__ Lerp lerp_rows(__amdgpu_buffer_rsrc_t rs, unsigned o0, unsigned pitch_b, float ax) {
+    const Taps t = load_taps<T>(rs, o0, pitch_b);
+    Lerp l;
+    l.d0 = t.i01 - t.i00;
+    l.d1 = t.i11 - t.i10;
+    l.top = fmaf(ax, l.d0, t.i00);
+    l.bot = fmaf(ax, l.d1, t.i10);
+    return l;
+}
+
+// hi - lo of a packed pair of halves, in float
+__device__ __forceinline__ float half_pair_diff(unsigned pk) {
+    float r;
+    asm("v_fma_mix_f32 %0, %1, 1.0, -%1 op_sel:[1,0,0] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(pk));
+    return r;
+}
+// a * b + lo (the low half of pk), in float
+__device__ __forceinline__ float half_lo_fma(float a, float b, unsigned pk) {
+    float r;
+    asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[0,0,1]" : "=v"(r) : "v"(a), "v"(b), "v"(pk));
+    return r;
+}
+
+template <>
+__device__ __forceinline__ Lerp lerp_rows<_Float16>(__amdgpu_buffer_rsrc_t rs, unsigned o0, unsigned pitch_b,
+                                                    float ax) {
+    const unsigned base = o0 & ~3u, sh = (o0 & 2u) * 8u;          // pitch_b is a multiple of 4
+    const u32x2 va = __builtin_amdgcn_raw_buffer_load_b64(rs, base, 0, 0);
+    const u32x2 vb = __builtin_amdgcn_raw_buffer_load_b64(rs, base, pitch_b, 0);
+    const unsigned a = __builtin_amdgcn_alignbit(va.y, va.x, sh);   // (I(x0), I(x0+1)) of row y0
+    const unsigned b = __builtin_amdgcn_alignbit(vb.y, vb.x, sh);   // of row y0 + 1
+    Lerp l;
+    l.d0 = half_pair_diff(a);
+    l.d1 = half_pair_diff(b);
+    l.top = half_lo_fma(ax, l.d0, a);
+    l.bot = half_lo_fma(ax, l.d1, b);
+    return l;
 }
 
 // floor(x) converted to int in one instruction (v_cvt_flr_i32_f32).
@@ -441,14 +475,11 @@ __device__ __forceinline__ void frame_loop(const float* __restrict__ pc, cptr<Fr
         // Eq. 6 in local coordinates
         const Warp w = warp_sample<T>(c0, c1, c2, h6, h7, k2, dx, dy, idu, pix_ok, wm1, hm1, pitch_b);
         if (w.v) {
-            const Taps tp = load_taps<T>(image_rsrc(fr[f].img, img_bytes), w.o0, pitch_b);
+            const Lerp l = lerp_rows<T>(image_rsrc(fr[f].img, img_bytes), w.o0, pitch_b, w.ax);
             // bilinear value and the exact gradient of the interpolant
-            const float d0 = tp.i01 - tp.i00, d1 = tp.i11 - tp.i10;
-            const float top = fmaf(w.ax, d0, tp.i00);
-            const float bot = fmaf(w.ax, d1, tp.i10);
-            const float gy = bot - top;
-            const float val = fmaf(w.ay, gy, top);
-            const float gx = fmaf(w.ay, d1 - d0, d0);
+            const float gy = l.bot - l.top;
+            const float val = fmaf(w.ay, gy, l.top);
+            const float gx = fmaf(w.ay, l.d1 - l.d0, l.d0);
             // residual (Eq. 5) and Huber IRLS weight w = min(1, k/|r|) (Eq. 8)
             const float r = SCALED ? fmaf(val, img_scale, -ikf) : val - ikf;
             const float ar = fabsf(r);
@@ -484,10 +515,8 @@ __device__ __forceinline__ void frame_cost(const float* __restrict__ pc, cptr<Fr
         const float h6 = fr[f].zrow[0], h7 = fr[f].zrow[1], k2 = fr[f].zrow[2];
         const Warp w = warp_sample<T>(c0, c1, c2, h6, h7, k2, dx, dy, idu, pix_ok, wm1, hm1, pitch_b);
         if (w.v) {
-            const Taps tp = load_taps<T>(image_rsrc(fr[f].img, img_bytes), w.o0, pitch_b);
-            const float top = fmaf(w.ax, tp.i01 - tp.i00, tp.i00);
-            const float bot = fmaf(w.ax, tp.i11 - tp.i10, tp.i10);
-            const float val = fmaf(w.ay, bot - top, top);
+            const Lerp l = lerp_rows<T>(image_rsrc(fr[f].img, img_bytes), w.o0, pitch_b, w.ax);
+            const float val = fmaf(w.ay, l.bot - l.top, l.top);
             const float r = SCALED ? fmaf(val, img_scale, -ikf) : val - ikf;
             const float ar = fabsf(r);
             cst += (ar <= hk) ? 0.5f * r * r : hk * (ar - 0.5f * hk);

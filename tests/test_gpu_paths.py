@@ -98,6 +98,27 @@ def test_ragged_sizes_and_neighbour_counts(ctx, W, H, S, N):
     assert np.all(dm[(H // S) * S:, :] == 0) and np.all(dm[:, (W // S) * S:] == 0)
 
 
+def test_f16_storage_equals_f32_on_half_exact_images(ctx):
+    """With images whose values are exact in half precision, f16 storage
+    samples the same numbers as f32 storage and the interpolation rounds the
+    same way, so the two forms agree bitwise: a check of the f16 tap decode
+    and its mixed-precision interpolation."""
+    sg, engine = sgmod()
+    kf = make_keyframe(_small_spec(width=160, height=120, patch=4, n_nbr=5, seed=23), device="cuda")
+    kf = dataclasses.replace(kf, kf_image=kf.kf_image.half().float(),
+                             nbr_images=kf.nbr_images.half().float())
+    print("case f16 == f32 on half-exact images 160x120 S4 N5", flush=True)
+    prm = sg.params(iters=10)
+    out = {}
+    for st in ("f32", "f16"):
+        d = engine.DeviceKeyframe.from_scene(ctx, kf, storage=st)
+        engine.update_batch(ctx, [d], prm)
+        torch.cuda.synchronize()
+        out[st] = (d.state.to_host(), d.inv_depth_out.cpu().numpy())
+    _state_equal(out["f32"][0], out["f16"][0])
+    assert np.array_equal(out["f32"][1], out["f16"][1])
+
+
 def test_zero_iterations_leave_the_state(ctx):
     sg, engine = sgmod()
     kf = make_keyframe(_small_spec(half_new=False), device="cuda")
