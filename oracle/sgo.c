@@ -374,11 +374,17 @@ static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_param
             continue;
         }
         if (lambda > 0.0) {
-            /* accept only if the mean Huber cost does not increase */
+            /* accept only if the mean Huber cost does not increase; a
+             * candidate plane that contains the centre ray is refused */
+            if (fabs(dot3(n_new, rs)) < 1e-6) {
+                flags |= SGO_REJECTED;
+                lambda *= 10.0;
+                continue;
+            }
             double H2[9], b2v[3], cost2;
             int32_t nv2 = sgo_linearize(kf, tx, ty, id_new, n_new, p->huber_k, p->depth_only,
                                         H2, b2v, &cost2);
-            if (nv2 < 3 || cost2 / nv2 > cost / nvalid) {
+            if (nv2 < 3 || !(cost2 / nv2 <= cost / nvalid)) {
                 lambda *= 10.0;
                 continue;
             }

@@ -667,7 +667,7 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
             const float b2y = nz * b1x - nx * b1z;
             const float b2z = nx * b1y - ny * b1x;
             // frame-independent per-pixel terms (Eq. 3, Eq. 9)
-            const float inv_c = 1.0f / c;
+            const float inv_c = rcp_fast(c);               // |c| >= 1e-6 where used
             const float sigma = (nx * drx + ny * dry) * inv_c;
             const float idu = fmaf(id, sigma, id);
             const float dx3 = fmaf(-sigma, rsx, drx);
@@ -722,7 +722,7 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
             const float dd = 1.f + lam;          // (H + lam diag H): equilibrated diagonal
             if (depth_only) {
                 if (H00 > 0.f && isfinite(H00)) {
-                    d0s = -bb0 / (H00 * dd);
+                    d0s = -bb0 * rcp_fast(H00 * dd);
                 } else {
                     flags |= F_SOLVE_FAIL;
                     continue;
@@ -752,7 +752,7 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                              !(H11 * p1 > 1e-10f * maxd * dd) || !(H22 * p2 > 1e-10f * maxd * dd);
                     if (!need64) {
                         const float bh0 = bb0 * e0, bh1 = bb1 * e1, bh2 = bb2 * e2;
-                        const float idet = 1.0f / det;
+                        const float idet = rcp_fast(det);
                         d0s = -(c00 * bh0 + c01 * bh1 + c02 * bh2) * idet * e0;
                         d1s = -(c01 * bh0 + c11 * bh1 + c12 * bh2) * idet * e1;
                         d2s = -(c02 * bh0 + c12 * bh1 + c22 * bh2) * idet * e2;
@@ -802,7 +802,12 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                 // surfel take the same branches, so the row reductions below
                 // see every lane of the surfel.
                 const float cc = nx_cand * rsx + ny_cand * rsy + nz_cand;
-                const float sig = (nx_cand * drx + ny_cand * dry) * (1.0f / cc);
+                if (fabsf(cc) < 1e-6f) {             // candidate plane contains r_s
+                    flags |= F_REJECTED;
+                    lam *= 10.f;
+                    continue;
+                }
+                const float sig = (nx_cand * drx + ny_cand * dry) * rcp_fast(cc);
                 const float idu_c = fmaf(id_cand, sig, id_cand);
                 float cst2 = 0.f;
                 int nv2l = 0;
@@ -810,7 +815,7 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                               ikf, hk, img_scale, cst2, nv2l);
                 const float cost2 = group_sum<LANES>(cst2);
                 const int nv2 = group_sum<LANES>(nv2l);
-                if (nv2 < 3 || cost2 / (float)nv2 > cost_here / (float)nv) {
+                if (nv2 < 3 || !(cost2 * (float)nv <= cost_here * (float)nv2)) {   // mean cost rose
                     lam *= 10.f;
                     continue;
                 }
