@@ -129,10 +129,12 @@ typedef struct {
     float lm_lambda;            /* 0: Gauss-Newton.  > 0: Levenberg-Marquardt (the method
                                    names it; the paper gives no schedule): each iteration
                                    solves (H + lambda diag H) d = -b, evaluates the Huber cost
-                                   at the candidate and accepts it when the mean cost per
-                                   valid sample does not increase (lambda /= 10, floor 1e-9),
-                                   else keeps the state (lambda *= 10).  lm_lambda is the
-                                   starting lambda of every surfel. */
+                                   at the candidate and accepts it unless the mean cost per
+                                   valid sample rises by more than a relative 1e-4 (then
+                                   lambda /= 10, floor 1e-9), else keeps the state (lambda
+                                   *= 10); a candidate plane containing the centre ray is
+                                   refused.  lm_lambda is the starting lambda of every
+                                   surfel. */
 } sgn_params;
 
 /* Launch plan for the fused Gauss-Newton kernel (chosen by sgn_autotune or

@@ -61,7 +61,11 @@ class SurfelsC(C.Structure):
                 ("ny", C.POINTER(C.c_double)), ("nz", C.POINTER(C.c_double)),
                 ("flags", C.POINTER(C.c_uint32)), ("cost", C.POINTER(C.c_double)),
                 ("nvalid", C.POINTER(C.c_int32)), ("last_update", C.POINTER(C.c_uint32)),
-                ("kappa", C.POINTER(C.c_double))]
+                ("kappa", C.POINTER(C.c_double)), ("margin", C.POINTER(C.c_double))]
+
+
+class GridC(C.Structure):
+    _fields_ = [("K", Intrinsics), ("width", C.c_int32), ("height", C.c_int32), ("patch", C.c_int32)]
 
 
 class ParamsC(C.Structure):
@@ -114,6 +118,10 @@ def lib():
         L.sgo_transfer_surfels.restype = C.c_int
         L.sgo_transfer_surfels.argtypes = [C.POINTER(Intrinsics), C.POINTER(Pose), C.c_int32,
                                            dp, dp, dp, dp, dp, dp, dp, dp]
+        L.sgo_transfer_regrid.restype = C.c_int
+        L.sgo_transfer_regrid.argtypes = [C.POINTER(GridC), C.POINTER(SurfelsC), C.POINTER(Pose),
+                                          C.POINTER(GridC), C.POINTER(SurfelsC),
+                                          C.POINTER(C.c_uint8), ip]
         L.sgo_set_threads.restype = None
         L.sgo_set_threads.argtypes = [C.c_int32]
         L.sgo_max_threads.restype = C.c_int32
@@ -214,6 +222,7 @@ def new_state(inv_depth, normals, flags=None) -> Dict[str, np.ndarray]:
                   else np.ascontiguousarray(np.asarray(flags, np.uint32).reshape(-1)).copy()),
         "cost": np.zeros(n), "nvalid": np.zeros(n, np.int32),
         "last_update": np.zeros(n, np.uint32), "kappa": np.zeros(n),
+        "margin": np.full(n, np.inf),
     }
 
 
@@ -221,7 +230,8 @@ def _surfels_c(st: Dict[str, np.ndarray]) -> SurfelsC:
     return SurfelsC(_dp(st["inv_depth"]), _dp(st["nx"]), _dp(st["ny"]), _dp(st["nz"]),
                     st["flags"].ctypes.data_as(C.POINTER(C.c_uint32)), _dp(st["cost"]),
                     st["nvalid"].ctypes.data_as(C.POINTER(C.c_int32)),
-                    st["last_update"].ctypes.data_as(C.POINTER(C.c_uint32)), _dp(st["kappa"]))
+                    st["last_update"].ctypes.data_as(C.POINTER(C.c_uint32)), _dp(st["kappa"]),
+                    _dp(st["margin"]))
 
 
 def _subset(subset):
@@ -348,6 +358,29 @@ def transfer(K, R, t, us, id_s, n):
     lib().sgo_transfer_surfels(C.byref(Kc), C.byref(P), m, _dp(usx), _dp(usy), _dp(ids),
                                _dp(nn), _dp(ux), _dp(uy), _dp(ido), _dp(no))
     return np.stack([ux, uy], 1), ido, no
+
+
+def transfer_regrid(src_grid, st, R, t, dst_grid):
+    """Eq. 10 and re-gridding (see ``sgo_transfer_regrid``).
+
+    src_grid / dst_grid: (K, width, height, patch).  ``st`` is a state dict of
+    the source grid (``new_state``).  Returns (dst state dict, is_new (gh, gw)
+    uint8, winning source index (gh, gw) int32, number of filled tiles)."""
+    def grid(g):
+        K, W, H, S = g
+        return GridC(intrinsics(K), int(W), int(H), int(S))
+    sg, dg = grid(src_grid), grid(dst_grid)
+    gw, gh = dst_grid[1] // dst_grid[3], dst_grid[2] // dst_grid[3]
+    m = gw * gh
+    out = new_state(np.zeros(m), np.zeros((m, 3)))
+    is_new = np.zeros(m, np.uint8)
+    win = np.zeros(m, np.int32)
+    P = pose(R, t)
+    sc, dc = _surfels_c(st), _surfels_c(out)
+    filled = lib().sgo_transfer_regrid(C.byref(sg), C.byref(sc), C.byref(P), C.byref(dg),
+                                       C.byref(dc), is_new.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                       win.ctypes.data_as(C.POINTER(C.c_int32)))
+    return out, is_new.reshape(gh, gw), win.reshape(gh, gw), int(filled)
 
 
 def set_threads(n: int):

@@ -126,10 +126,25 @@ static double huber_w(double r, double k) {
  * derivative of Eq. 3 (the printed form collapses to zero; reading:
  * id_s (r_u (n.r_s) - r_s (n.r_u)) / (n.r_s)^2), projected on the tangent
  * basis because the normal is updated and then renormalised. */
+static int eval_sample(const sgo_intrinsics* K, const sgo_pose* P, const sgo_image* In,
+                       double kf_value, double usx, double usy, double ux, double uy,
+                       double id_s, const double n[3], int depth_only, double* r, double J[3],
+                       double* margin);
+
 int sgo_eval_sample(const sgo_intrinsics* K, const sgo_pose* P, const sgo_image* In,
                     double kf_value, double usx, double usy, double ux, double uy,
                     double id_s, const double n[3], int depth_only,
                     double* r, double J[3]) {
+    return eval_sample(K, P, In, kf_value, usx, usy, ux, uy, id_s, n, depth_only, r, J, NULL);
+}
+
+/* margin (test probe, may be NULL): lowered to the distance of the warped
+ * point from the nearest edge of the valid sampling window, so that a caller
+ * can tell which validity decisions are close calls. */
+static int eval_sample(const sgo_intrinsics* K, const sgo_pose* P, const sgo_image* In,
+                       double kf_value, double usx, double usy, double ux, double uy,
+                       double id_s, const double n[3], int depth_only, double* r, double J[3],
+                       double* margin) {
     double rs[3], ru[3];
     sgo_ray(K, usx, usy, rs);
     sgo_ray(K, ux, uy, ru);
@@ -139,6 +154,11 @@ int sgo_eval_sample(const sgo_intrinsics* K, const sgo_pose* P, const sgo_image*
     if (!(id_u > 0.0) || !isfinite(id_u)) return 0;
     double Xn[3], uv[2];
     if (!warp_point(K, P, ru, id_u, Xn, uv)) return 0;           /* Eq. 6 */
+    if (margin) {
+        double m = fmin(fmin(fabs(uv[0]), fabs(uv[0] - (In->width - 1))),
+                        fmin(fabs(uv[1]), fabs(uv[1] - (In->height - 1))));
+        if (m < *margin) *margin = m;
+    }
     double s[3];
     if (!sgo_bilinear(In, uv[0], uv[1], s)) return 0;
     *r = s[0] - kf_value;
@@ -178,9 +198,19 @@ static void tile_centre(const sgo_keyframe* kf, int32_t tx, int32_t ty, double* 
     *y = S * ty + 0.5 * (S - 1);
 }
 
+static int32_t linearize(const sgo_keyframe* kf, int32_t tx, int32_t ty, double id_s,
+                         const double n[3], double huber_k, int depth_only, double H[9],
+                         double b[3], double* cost, double* margin);
+
 int32_t sgo_linearize(const sgo_keyframe* kf, int32_t tx, int32_t ty, double id_s,
                       const double n[3], double huber_k, int depth_only,
                       double H[9], double b[3], double* cost) {
+    return linearize(kf, tx, ty, id_s, n, huber_k, depth_only, H, b, cost, NULL);
+}
+
+static int32_t linearize(const sgo_keyframe* kf, int32_t tx, int32_t ty, double id_s,
+                         const double n[3], double huber_k, int depth_only, double H[9],
+                         double b[3], double* cost, double* margin) {
     int S = kf->patch;
     double usx, usy;
     tile_centre(kf, tx, ty, &usx, &usy);
@@ -194,8 +224,8 @@ int32_t sgo_linearize(const sgo_keyframe* kf, int32_t tx, int32_t ty, double id_
             double ikf = kf->kf.pix[(size_t)uy * kf->kf.width + ux];
             for (int f = 0; f < kf->n_nbr; ++f) {               /* sum over Omega */
                 double r, J[3];
-                if (!sgo_eval_sample(&kf->K, &kf->pose[f], &kf->nbr[f], ikf, usx, usy,
-                                     (double)ux, (double)uy, id_s, n, depth_only, &r, J))
+                if (!eval_sample(&kf->K, &kf->pose[f], &kf->nbr[f], ikf, usx, usy,
+                                 (double)ux, (double)uy, id_s, n, depth_only, &r, J, margin))
                     continue;
                 double w = huber_w(r, huber_k);
                 for (int i = 0; i < 3; ++i) {
@@ -333,6 +363,7 @@ static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_param
     int32_t nvalid = 0;
     int updated = 0;
     double lambda = p->lm_lambda;
+    double margin = INFINITY;
     for (int it = 0; it < p->iters; ++it) {
         if (fabs(dot3(n, rs)) < 1e-6) {           /* Eq. 3 undefined */
             flags |= SGO_DEGENERATE;
@@ -343,12 +374,26 @@ static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_param
         double b1[3], b2[3];
         sgo_tangent_basis(n, b1, b2);
         double H[9], b[3];
-        nvalid = sgo_linearize(kf, tx, ty, id_s, n, p->huber_k, p->depth_only, H, b, &cost);
+        nvalid = linearize(kf, tx, ty, id_s, n, p->huber_k, p->depth_only, H, b, &cost,
+                           s->margin ? &margin : NULL);
         kappa = p->depth_only ? 1.0 : sgo_kappa_eq(H);
         double delta[3] = {0.0, 0.0, 0.0};
         if (nvalid < 3) {
             flags |= SGO_FEW_SAMPLES;
             continue;
+        }
+        if (p->perturb > 0.0) {
+            /* probe: relative noise on the normal equations as well (float
+             * accumulation of J^T W J and J^T W r reaches the step scaled by
+             * the condition number, which state noise alone does not model) */
+            int comp = 4;
+            for (int a = 0; a < 3; ++a)
+                for (int c = a; c < 3; ++c) {
+                    H[3 * a + c] *= 1.0 + p->perturb * probe_uniform(p->perturb_seed, i, it, comp++);
+                    H[3 * c + a] = H[3 * a + c];
+                }
+            for (int a = 0; a < 3; ++a)
+                b[a] *= 1.0 + p->perturb * probe_uniform(p->perturb_seed, i, it, comp++);
         }
         double Hs[9];
         memcpy(Hs, H, sizeof(Hs));
@@ -374,17 +419,19 @@ static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_param
             continue;
         }
         if (lambda > 0.0) {
-            /* accept only if the mean Huber cost does not increase; a
-             * candidate plane that contains the centre ray is refused */
+            /* accept unless the mean Huber cost rises by more than a
+             * relative 1e-4 (below that a rise is at the float noise of a
+             * device's cost sums); a candidate plane that contains the
+             * centre ray is refused */
             if (fabs(dot3(n_new, rs)) < 1e-6) {
                 flags |= SGO_REJECTED;
                 lambda *= 10.0;
                 continue;
             }
             double H2[9], b2v[3], cost2;
-            int32_t nv2 = sgo_linearize(kf, tx, ty, id_new, n_new, p->huber_k, p->depth_only,
-                                        H2, b2v, &cost2);
-            if (nv2 < 3 || !(cost2 / nv2 <= cost / nvalid)) {
+            int32_t nv2 = linearize(kf, tx, ty, id_new, n_new, p->huber_k, p->depth_only, H2,
+                                    b2v, &cost2, s->margin ? &margin : NULL);
+            if (nv2 < 3 || !(cost2 / nv2 <= (cost / nvalid) * (1.0 + 1e-4))) {
                 lambda *= 10.0;
                 continue;
             }
@@ -408,6 +455,7 @@ static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_param
     s->cost[i] = cost;
     s->nvalid[i] = nvalid;
     if (s->kappa) s->kappa[i] = kappa;
+    if (s->margin) s->margin[i] = margin;
     if (updated) s->last_update[i] = p->stamp;
 }
 
@@ -556,6 +604,93 @@ int sgo_transfer_surfels(const sgo_intrinsics* K, const sgo_pose* P, int32_t cou
         ++ok;
     }
     return ok;
+}
+
+/* Landing of one source surfel in the destination keyframe (Eq. 10):
+ * returns 0 when the surfel is unusable, behind the destination camera or
+ * outside its tiles; else the tile index, 1/p'_z, r' = p'/p'_z and n'. */
+static int regrid_land(const sgo_grid* sg, const sgo_surfels* src, const sgo_pose* P,
+                       const sgo_grid* dg, int32_t i, int32_t* tile, double* idp, double rp[3],
+                       double np[3]) {
+    const int S0 = sg->patch, gw0 = sg->width / S0;
+    if (src->flags[i] & (SGO_DEGENERATE | SGO_UNINIT)) return 0;
+    const double id = src->inv_depth[i];
+    if (!(id > 0.0) || !isfinite(id)) return 0;
+    double usx = S0 * (i % gw0) + 0.5 * (S0 - 1), usy = S0 * (i / gw0) + 0.5 * (S0 - 1);
+    double rs[3], p0[3], p1[3];
+    const double n0[3] = {src->nx[i], src->ny[i], src->nz[i]};
+    sgo_ray(&sg->K, usx, usy, rs);
+    for (int k = 0; k < 3; ++k) p0[k] = rs[k] / id;
+    for (int k = 0; k < 3; ++k) {
+        p1[k] = P->R[3 * k] * p0[0] + P->R[3 * k + 1] * p0[1] + P->R[3 * k + 2] * p0[2] + P->t[k];
+        np[k] = P->R[3 * k] * n0[0] + P->R[3 * k + 1] * n0[1] + P->R[3 * k + 2] * n0[2];
+    }
+    if (!(p1[2] > 0.0)) return 0;
+    rp[0] = p1[0] / p1[2];
+    rp[1] = p1[1] / p1[2];
+    rp[2] = 1.0;
+    const double ux = dg->K.fx * rp[0] + dg->K.cx, uy = dg->K.fy * rp[1] + dg->K.cy;
+    const double px = floor(ux + 0.5), py = floor(uy + 0.5);      /* nearest pixel */
+    const int S1 = dg->patch, gw1 = dg->width / S1, gh1 = dg->height / S1;
+    if (!(px >= 0.0 && px < (double)(gw1 * S1) && py >= 0.0 && py < (double)(gh1 * S1))) return 0;
+    *tile = ((int32_t)py / S1) * gw1 + (int32_t)px / S1;
+    *idp = 1.0 / p1[2];
+    return 1;
+}
+
+int sgo_transfer_regrid(const sgo_grid* src_grid, const sgo_surfels* src, const sgo_pose* P,
+                        const sgo_grid* dst_grid, sgo_surfels* dst, uint8_t* dst_is_new,
+                        int32_t* dst_src_index) {
+    const int32_t n_src = (src_grid->width / src_grid->patch) * (src_grid->height / src_grid->patch);
+    const int S1 = dst_grid->patch, gw1 = dst_grid->width / S1, gh1 = dst_grid->height / S1;
+    const int32_t n_dst = gw1 * gh1;
+    int32_t* win = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_dst > 0 ? n_dst : 1));
+    double* best = (double*)malloc(sizeof(double) * (size_t)(n_dst > 0 ? n_dst : 1));
+    for (int32_t j = 0; j < n_dst; ++j) { win[j] = -1; best[j] = 0.0; }
+    /* z-test: closest landed surfel per destination tile, in index order */
+    for (int32_t i = 0; i < n_src; ++i) {
+        int32_t j;
+        double idp, rp[3], np[3];
+        if (!regrid_land(src_grid, src, P, dst_grid, i, &j, &idp, rp, np)) continue;
+        if (win[j] < 0 || idp > best[j]) { win[j] = i; best[j] = idp; }
+    }
+    int filled = 0;
+    for (int32_t j = 0; j < n_dst; ++j) {
+        int ok = 0;
+        double idt = 0.0, nt[3] = {0.0, 0.0, -1.0};
+        if (win[j] >= 0) {
+            int32_t jj;
+            double idp, rp[3], np[3], rt[3];
+            regrid_land(src_grid, src, P, dst_grid, win[j], &jj, &idp, rp, np);
+            sgo_ray(&dst_grid->K, S1 * (j % gw1) + 0.5 * (S1 - 1), S1 * (j / gw1) + 0.5 * (S1 - 1), rt);
+            const double c1 = dot3(np, rp), ct = dot3(np, rt);
+            if (fabs(c1) >= 1e-6 && fabs(ct) >= 1e-6) {
+                idt = idp * ct / c1;                      /* Eq. 3 of the moved plane at r_t */
+                double nn[3] = {np[0], np[1], np[2]};
+                if (idt > 0.0 && isfinite(idt) && normalize3(nn)) {
+                    nt[0] = nn[0]; nt[1] = nn[1]; nt[2] = nn[2];
+                    ok = 1;
+                }
+            }
+            if (!ok) idt = 0.0;
+        }
+        dst->inv_depth[j] = ok ? idt : 0.0;
+        dst->nx[j] = ok ? nt[0] : 0.0;
+        dst->ny[j] = ok ? nt[1] : 0.0;
+        dst->nz[j] = ok ? nt[2] : -1.0;
+        dst->flags[j] = ok ? 0u : SGO_UNINIT;
+        dst->cost[j] = 0.0;
+        dst->nvalid[j] = 0;
+        dst->last_update[j] = ok ? src->last_update[win[j]] : 0u;
+        if (dst->kappa) dst->kappa[j] = 0.0;
+        if (dst->margin) dst->margin[j] = INFINITY;
+        dst_is_new[j] = ok ? 0 : 1;
+        if (dst_src_index) dst_src_index[j] = ok ? win[j] : -1;
+        filled += ok;
+    }
+    free(win);
+    free(best);
+    return filled;
 }
 
 void sgo_set_threads(int32_t n) {

@@ -49,6 +49,9 @@ typedef struct {
     int32_t* nvalid;          /* valid (pixel, frame) samples at that point */
     uint32_t* last_update;
     double* kappa;            /* optional (may be NULL): cond_2 of the equilibrated J^T J */
+    double* margin;           /* optional test probe (may be NULL): smallest distance, over
+                                 all samples and iterations, of a warped point from the edge
+                                 of the valid sampling window (pixels) */
 } sgo_surfels;
 
 typedef struct {
@@ -58,9 +61,10 @@ typedef struct {
     double beta_r;            /* neighbour radius for initialisation (pixels) */
     uint32_t stamp;           /* written to last_update */
     double lm_lambda;         /* 0: pure Gauss-Newton; >0: Levenberg-Marquardt start damping */
-    double perturb;           /* test probe, 0 = off: after every accepted step, scale id_s and
-                                 each normal component by (1 + perturb * u), u in [-1, 1) from a
-                                 counter hash of (perturb_seed, surfel, iteration, component) */
+    double perturb;           /* test probe, 0 = off: scale each entry of the normal equations
+                                 and, after every accepted step, id_s and each normal component
+                                 by (1 + perturb * u), u in [-1, 1) from a counter hash of
+                                 (perturb_seed, surfel, iteration, component) */
     uint32_t perturb_seed;
 } sgo_params;
 
@@ -134,6 +138,25 @@ int sgo_transfer_surfels(const sgo_intrinsics* K, const sgo_pose* P, int32_t cou
                          const double* usx, const double* usy, const double* id_s,
                          const double* n, double* ux_out, double* uy_out,
                          double* id_out, double* n_out);
+
+/* A keyframe's surfel grid: intrinsics, image size and tile edge S. */
+typedef struct { sgo_intrinsics K; int32_t width, height, patch; } sgo_grid;
+
+/* Surfel reference-frame change (Eq. 10) and re-gridding into the tiles of
+ * another keyframe (pose X_dst = R X_src + t).  A usable source surfel (no
+ * DEGENERATE or UNINIT flag, id_s > 0) moves to p' = R (r_s / id_s) + t with
+ * normal n' = R n, and lands in the destination pixel nearest to
+ * pi(K_dst p'), hence in that pixel's tile.  In each destination tile the
+ * closest landed surfel wins (largest 1/p'_z, ties to the lower source
+ * index); its plane is re-expressed at the tile's centre ray r_t by Eq. 3:
+ * id_t = (1/p'_z) (n'.r_t) / (n'.r'), r' = p'/p'_z, n_t = n' normalised.
+ * Tiles that receive nothing, or whose plane cannot be evaluated at r_t, get
+ * id 0, n (0, 0, -1), the UNINIT flag and is_new = 1 (for neighbour
+ * initialisation).  dst_src_index (may be NULL) receives the winning source
+ * index or -1.  Returns the number of filled destination tiles. */
+int sgo_transfer_regrid(const sgo_grid* src_grid, const sgo_surfels* src, const sgo_pose* P,
+                        const sgo_grid* dst_grid, sgo_surfels* dst, uint8_t* dst_is_new,
+                        int32_t* dst_src_index);
 
 void sgo_set_threads(int32_t n);
 int32_t sgo_max_threads(void);

@@ -42,13 +42,13 @@ struct KfDev {
 // Per-neighbour-frame descriptor.  R and t are the caller's pose in double;
 // hm/kt are written on the device by the setup kernel.
 struct FrameDev {
-    const void* img;
+    float zrow[4];  // hm[6], hm[7], kt[2] rounded to float (the q_z row), pad
+    const void* img;  // next to zrow: one scalar load per frame fetches both
     int32_t pitch, pad0;
     double R[9];
     double t[3];
     double hm[9];   // K R K^-1
     double kt[3];   // K t
-    float zrow[4];  // hm[6], hm[7], kt[2] rounded to float (the q_z row), pad
 };
 
 // Work queue q covers the global item range [begin, end).

@@ -313,6 +313,8 @@ enum : int {
     W_HX0 = 0, W_HX1, W_KX, W_EX, W_HY0, W_HY1, W_KY, W_EY, W_QZ, W_X0, W_Y0, W_B0
 };
 constexpr int kMaxSlots = 4;
+// Levenberg-Marquardt acceptance: largest relative rise of the mean cost.
+constexpr float kLmAcceptRise = 1e-4f;
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -353,7 +355,7 @@ __device__ __forceinline__ Taps load_taps<float>(__amdgpu_buffer_rsrc_t rs, unsi
 
 template <>
 __device__ __forceinline__ Taps load_taps<uint8_t>(__amdgpu_buffer_rsrc_t rs, unsigned o0, unsigned pitch_b) {
-    const unsigned base = o0 & ~3u, sh = (o0 & 3u) * 8u;
+    const unsigned base = o0 & ~3u, sh = o0 << 3;                  // shift amount is mod 32
     const u32x2 va = __builtin_amdgcn_raw_buffer_load_b64(rs, base, 0, 0);
     const u32x2 vb = __builtin_amdgcn_raw_buffer_load_b64(rs, base, pitch_b, 0);
     const unsigned a = __builtin_amdgcn_alignbit(va.y, va.x, sh);
@@ -402,7 +404,9 @@ __device__ __forceinline__ float half_lo_fma(float a, float b, unsigned pk) {
 template <>
 __device__ __forceinline__ Lerp lerp_rows<_Float16>(__amdgpu_buffer_rsrc_t rs, unsigned o0, unsigned pitch_b,
                                                     float ax) {
-    const unsigned base = o0 & ~3u, sh = (o0 & 2u) * 8u;          // pitch_b is a multiple of 4
+    // pitch_b is a multiple of 4; the funnel shift uses its amount mod 32,
+    // so o0 * 8 shifts by 8 (o0 mod 4) bits
+    const unsigned base = o0 & ~3u, sh = o0 << 3;
     const u32x2 va = __builtin_amdgcn_raw_buffer_load_b64(rs, base, 0, 0);
     const u32x2 vb = __builtin_amdgcn_raw_buffer_load_b64(rs, base, pitch_b, 0);
     const unsigned a = __builtin_amdgcn_alignbit(va.y, va.x, sh);   // (I(x0), I(x0+1)) of row y0
@@ -472,10 +476,11 @@ __device__ __forceinline__ void frame_loop(const float* __restrict__ pc, cptr<Fr
         const float4 c1 = *(const float4*)(pc + f * kPairWords + 4);
         const float4 c2 = *(const float4*)(pc + f * kPairWords + 8);
         const float h6 = fr[f].zrow[0], h7 = fr[f].zrow[1], k2 = fr[f].zrow[2];
+        const __amdgpu_buffer_rsrc_t rs = image_rsrc(fr[f].img, img_bytes);
         // Eq. 6 in local coordinates
         const Warp w = warp_sample<T>(c0, c1, c2, h6, h7, k2, dx, dy, idu, pix_ok, wm1, hm1, pitch_b);
         if (w.v) {
-            const Lerp l = lerp_rows<T>(image_rsrc(fr[f].img, img_bytes), w.o0, pitch_b, w.ax);
+            const Lerp l = lerp_rows<T>(rs, w.o0, pitch_b, w.ax);
             // bilinear value and the exact gradient of the interpolant
             const float gy = l.bot - l.top;
             const float val = fmaf(w.ay, gy, l.top);
@@ -513,9 +518,10 @@ __device__ __forceinline__ void frame_cost(const float* __restrict__ pc, cptr<Fr
         const float4 c1 = *(const float4*)(pc + f * kPairWords + 4);
         const float4 c2 = *(const float4*)(pc + f * kPairWords + 8);
         const float h6 = fr[f].zrow[0], h7 = fr[f].zrow[1], k2 = fr[f].zrow[2];
+        const __amdgpu_buffer_rsrc_t rs = image_rsrc(fr[f].img, img_bytes);
         const Warp w = warp_sample<T>(c0, c1, c2, h6, h7, k2, dx, dy, idu, pix_ok, wm1, hm1, pitch_b);
         if (w.v) {
-            const Lerp l = lerp_rows<T>(image_rsrc(fr[f].img, img_bytes), w.o0, pitch_b, w.ax);
+            const Lerp l = lerp_rows<T>(rs, w.o0, pitch_b, w.ax);
             const float val = fmaf(w.ay, l.bot - l.top, l.top);
             const float r = SCALED ? fmaf(val, img_scale, -ikf) : val - ikf;
             const float ar = fabsf(r);
@@ -746,8 +752,8 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                     const float adj2 = c00 * c00 + c11 * c11 + c22 * c22 +
                                        2.f * (c01 * c01 + c02 * c02 + c12 * c12);
                     // raw Cholesky pivots are H_jj times the equilibrated ones
-                    const float p1 = c22 / dd;            // dd - e01^2 / dd
-                    const float p2 = det / c22;
+                    const float p1 = c22 * rcp_fast(dd);  // dd - e01^2 / dd (only compared)
+                    const float p2 = det * rcp_fast(c22);  // (only compared)
                     need64 = !(fro2 * adj2 <= kap2 * det * det) || !(det > 0.f) || !(c22 > 0.f) ||
                              !(H11 * p1 > 1e-10f * maxd * dd) || !(H22 * p2 > 1e-10f * maxd * dd);
                     if (!need64) {
@@ -797,8 +803,10 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
             id_cand = idn; nx_cand = cnx; ny_cand = cny; nz_cand = cnz;
             have_cand = true;
             if (lm) {
-                // Levenberg-Marquardt: accept the step only if the mean Huber
-                // cost per valid sample does not increase.  All lanes of a
+                // Levenberg-Marquardt: accept the step unless the mean Huber
+                // cost per valid sample rises by more than kLmAcceptRise
+                // (relative; smaller rises are below the float noise of the
+                // cost sums, where the decision would be a coin toss).  All lanes of a
                 // surfel take the same branches, so the row reductions below
                 // see every lane of the surfel.
                 const float cc = nx_cand * rsx + ny_cand * rsy + nz_cand;
@@ -815,7 +823,7 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                               ikf, hk, img_scale, cst2, nv2l);
                 const float cost2 = group_sum<LANES>(cst2);
                 const int nv2 = group_sum<LANES>(nv2l);
-                if (nv2 < 3 || !(cost2 * (float)nv <= cost_here * (float)nv2)) {   // mean cost rose
+                if (nv2 < 3 || !(cost2 * (float)nv <= cost_here * (float)nv2 * (1.f + kLmAcceptRise))) {
                     lam *= 10.f;
                     continue;
                 }

@@ -69,14 +69,25 @@ def compare(dev: dict, st: dict, idx=None):
     }
 
 
-# Conditioning probe: a surfel whose oracle result moves by more than the
-# tolerance when every Gauss-Newton step is perturbed by PROBE_EPS (relative,
-# several ulps of float) is not determined to the tolerance at FP32
-# resolution.  For such surfels the device result is checked for validity
-# (an equally good minimum of the cost) instead of closeness.
+# Conditioning probe.  The device computes in float: its warped coordinates,
+# samples, normal equations and updates carry relative errors of a few
+# float ulps, which the condition of each Gauss-Newton step then amplifies.
+# The probe reruns the oracle with that kind of noise injected (PROBE_EPS,
+# relative, on every entry of J^T W J and J^T W r and on the state after every
+# accepted step; about 30 float ulps) under several seeds.  A surfel whose
+# probed results leave the tolerance of the unprobed one is not determined to
+# the tolerance at float resolution ("unstable").  Stable surfels must match
+# the oracle within the tolerance.  For unstable surfels any of the outcomes
+# is a correct result, so the device is checked for being as good: its final
+# Huber cost per surfel within UNSTABLE_GROSS_RATIO of the worst oracle
+# outcome (a gross-error bound), and its mean final cost over all unstable
+# surfels within UNSTABLE_MEAN_RATIO of the oracle outcomes' mean.
 PROBE_EPS = 2e-6
-PROBE_SEEDS = (1, 2, 3)
-UNSTABLE_COST_RATIO = 1.10
+PROBE_SEEDS = (1, 2, 3, 4, 5)
+UNSTABLE_GROSS_RATIO = 3.0
+UNSTABLE_MEAN_RATIO = 1.05
+# kept for callers that bound a single ratio
+UNSTABLE_COST_RATIO = UNSTABLE_GROSS_RATIO
 
 
 def as_dev(st: dict) -> dict:
@@ -113,30 +124,53 @@ def final_costs(okf, states: dict, idx, huber_k=9.0 / 255.0):
     return out
 
 
+class ParityResult(tuple):
+    """(compare dict, unstable mask over the compared indices, per-surfel
+    cost ratios of unstable surfels that are out of tolerance) plus the
+    aggregate ratio ``mean_ratio`` over all unstable surfels."""
+    mean_ratio: float = 1.0
+
+
 def check_parity(dk, dev: dict, init_id, init_n, is_new, params, subset=None, label=""):
-    """Oracle base run + conditioning probe; returns (compare dict, unstable
-    mask over compared indices, cost ratios of unstable surfels)."""
+    """Oracle base run + conditioning probe; returns a ParityResult."""
     okf, base = run_oracle(dk, init_id, init_n, is_new, params, subset=subset)
     idx = np.arange(base["inv_depth"].shape[0]) if subset is None else np.asarray(subset)
     c = compare(dev, base, idx=idx)
     uns_all, runs = unstable_set(dk, init_id, init_n, is_new, params, base, subset=subset)
     uns = uns_all[idx]
     ratios = np.zeros(0)
-    ui = idx[uns & ~c["within"]]
-    if ui.size:
-        # the device result must be as good as the worst of the oracle's own
-        # FP32-level outcomes (base run and probe runs) for that surfel
-        cg = final_costs(okf, dev, ui, params.huber_k)
-        ref = final_costs(okf, as_dev(base), ui, params.huber_k)
-        for st in runs:
-            ref = np.maximum(ref, final_costs(okf, as_dev(st), ui, params.huber_k))
-        ratios = cg / np.maximum(ref, 1e-12)
+    mean_ratio = 1.0
+    ua = idx[uns]
+    if ua.size:
+        cg = final_costs(okf, dev, ua, params.huber_k)
+        refs = [final_costs(okf, as_dev(st), ua, params.huber_k) for st in [base] + runs]
+        worst = np.max(refs, axis=0)
+        out = ~c["within"][uns]
+        ratios = cg[out] / np.maximum(worst[out], 1e-12)
+        mean_ratio = float(cg.mean() / max(np.mean([r.mean() for r in refs]), 1e-30))
     stable = ~uns
     print(f"{label} {summary(c)} | unstable {uns.mean():.4f} within-stable "
           f"{c['within'][stable].mean() if stable.any() else 1.0:.5f} "
-          f"({int((~c['within'][stable]).sum())} out) unstable-out cost ratio max "
-          f"{ratios.max() if ratios.size else 0:.3f}", flush=True)
-    return c, uns, ratios
+          f"({int((~c['within'][stable]).sum())} out) unstable: gross cost ratio max "
+          f"{ratios.max() if ratios.size else 0:.3f}, mean cost ratio {mean_ratio:.4f}", flush=True)
+    res = ParityResult((c, uns, ratios))
+    res.mean_ratio = mean_ratio
+    return res
+
+
+def assert_parity(res, label="", min_stable=0.999, max_unstable=0.15):
+    """The parity bar: stable surfels within tolerance (and with equal
+    flags), a bounded unstable fraction, and unstable surfels as good as the
+    oracle's own float-level outcomes."""
+    c, uns, ratios = res
+    stable = ~uns
+    assert uns.mean() <= max_unstable, f"{label}: unstable fraction {uns.mean():.4f}"
+    if stable.any():
+        assert c["same_flags"][stable].mean() >= 0.999, f"{label}: flag mismatches"
+        assert c["within"][stable].mean() >= min_stable, f"{label}: {summary(c)}"
+    if ratios.size:
+        assert ratios.max() <= UNSTABLE_GROSS_RATIO, f"{label}: gross cost ratio {ratios.max():.3f}"
+    assert res.mean_ratio <= UNSTABLE_MEAN_RATIO, f"{label}: mean cost ratio {res.mean_ratio:.4f}"
 
 
 def summary(c: dict) -> str:

@@ -14,7 +14,7 @@ torch = pytest.importorskip("torch")
 
 import oracle
 from scenegen import make_keyframe, spec_for_config
-from tests.parity import (UNSTABLE_COST_RATIO, check_parity, compare, oracle_keyframe, oracle_state,
+from tests.parity import (assert_parity, check_parity, compare, oracle_keyframe, oracle_state,
                           run_oracle, summary)
 
 pytestmark = pytest.mark.gpu
@@ -53,25 +53,12 @@ def _plain(ctx, kf, storage="f32", plan=None, iters=None, with_new=True):
     return dk, dk.state.to_host()
 
 
-def _assert_parity(res, label="", min_stable=0.999):
-    """Stable surfels (unique at FP32 resolution) within tolerance; surfels
-    the conditioning probe flags as unstable must end at an equally good
-    minimum of the cost."""
-    c, uns, ratios = res
-    stable = ~uns
-    assert c["same_flags"][stable].mean() >= 0.999, f"{label}: flag mismatches"
-    assert c["within"][stable].mean() >= min_stable, f"{label}: {summary(c)}"
-    assert uns.mean() <= 0.15, f"{label}: too many unstable surfels ({uns.mean():.3f})"
-    if ratios.size:
-        assert ratios.max() <= UNSTABLE_COST_RATIO, f"{label}: unstable surfel cost ratio {ratios.max()}"
-
-
 def test_workload0_plain_f32(ctx):
     kf = make_keyframe(spec_for_config(0), device="cuda")
     print("case workload0 160x120 S=8 N=2 f32", flush=True)
     dk, dev = _plain(ctx, kf)
     res = check_parity(dk, dev, kf.init_id, kf.init_n, None, _oparams(kf.iters), label="w0")
-    _assert_parity(res, label="w0", min_stable=1.0)
+    assert_parity(res, label="w0", min_stable=1.0)
 
 
 def test_workload1_init_matches_oracle(ctx):
@@ -99,7 +86,7 @@ def test_workload1_plain(ctx, storage):
     dk, dev = _plain(ctx, kf, storage=storage)
     res = check_parity(dk, dev, kf.init_id, kf.init_n, kf.is_new, _oparams(kf.iters),
                        label=f"w1 {storage}")
-    _assert_parity(res, label=f"w1 {storage}")
+    assert_parity(res, label=f"w1 {storage}")
 
 
 def test_render_matches_oracle(ctx):

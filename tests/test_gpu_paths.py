@@ -11,7 +11,7 @@ torch = pytest.importorskip("torch")
 
 import oracle
 from scenegen import make_keyframe, spec_for_config
-from tests.parity import check_parity, run_oracle, compare, summary, UNSTABLE_COST_RATIO
+from tests.parity import assert_parity, check_parity, run_oracle, compare, summary
 
 pytestmark = pytest.mark.gpu
 
@@ -91,8 +91,9 @@ def test_ragged_sizes_and_neighbour_counts(ctx, W, H, S, N):
     assert dev["inv_depth"].size == (W // S) * (H // S)
     res = check_parity(d, dev, kf.init_id, kf.init_n, None, oracle.OracleParams(iters=8),
                        label=f"ragged {W}x{H} S{S} N{N}")
-    c, uns, ratios = res
-    assert c["within"][~uns].mean() >= 0.999
+    # with one or two neighbour frames a 4x4 surfel has 16-32 samples for
+    # three parameters: many are not determined at float resolution
+    assert_parity(res, label=f"ragged {W}x{H} S{S} N{N}", max_unstable=0.15 if N >= 3 else 0.35)
     # pixels outside the grid are never rendered
     dm = d.inv_depth_out.cpu().numpy()
     assert np.all(dm[(H // S) * S:, :] == 0) and np.all(dm[:, (W // S) * S:] == 0)
@@ -210,8 +211,7 @@ def test_depth_only_ablation_matches_oracle(ctx):
     assert np.array_equal(dev["n"], kf.init_n.reshape(-1, 3))
     res = check_parity(d, dev, kf.init_id, kf.init_n, None,
                        oracle.OracleParams(iters=10, depth_only=True), label="depth-only")
-    c, uns, _ = res
-    assert c["within"][~uns].mean() >= 0.999
+    assert_parity(res, label="depth-only")
 
 
 def test_quantize_matches_rounding_rules(ctx):
@@ -284,14 +284,16 @@ def test_full_benchmark_batch_sampled_parity(ctx):
     for j in (0, 9, 21, 33, 47, 63):
         d, k = ds[j], kfs[j]
         sub = np.sort(rng.choice(d.n_surfels, size=min(250, d.n_surfels), replace=False))
-        c, uns, ratios = check_parity(d, d.state.to_host(), k.init_id, k.init_n, k.is_new,
-                                      oracle.OracleParams(iters=15), subset=sub,
-                                      label=f"batch kf{j} {d.width}x{d.height} N={d.n_nbr}")
+        label = f"batch kf{j} {d.width}x{d.height} N={d.n_nbr}"
+        res = check_parity(d, d.state.to_host(), k.init_id, k.init_n, k.is_new,
+                           oracle.OracleParams(iters=15), subset=sub, label=label)
+        c, uns, ratios = res
         tot_within += int(c["within"][~uns].sum())
         tot_stable += int((~uns).sum())
-        if ratios.size:
-            assert ratios.max() <= UNSTABLE_COST_RATIO
-    assert tot_within / tot_stable >= 0.995
+        # per keyframe: the unstable fraction and cost checks (the within
+        # fraction is judged over all sampled stable surfels together)
+        assert_parity(res, label=label, min_stable=0.98, max_unstable=0.2)
+    assert tot_within / tot_stable >= 0.998
 
 
 def test_levenberg_marquardt_matches_oracle(ctx):
@@ -302,10 +304,9 @@ def test_levenberg_marquardt_matches_oracle(ctx):
     engine.update_plain(ctx, d, sg.params(iters=10, lm_lambda=1e-2))
     torch.cuda.synchronize()
     dev = d.state.to_host()
-    c, uns, ratios = check_parity(d, dev, kf.init_id, kf.init_n, kf.is_new,
-                                  oracle.OracleParams(iters=10, lm_lambda=1e-2), label="LM")
-    assert c["within"][~uns].mean() >= 0.995
-    assert c["same_flags"][~uns].mean() >= 0.999
+    res = check_parity(d, dev, kf.init_id, kf.init_n, kf.is_new,
+                       oracle.OracleParams(iters=10, lm_lambda=1e-2), label="LM")
+    assert_parity(res, label="LM")
 
 
 def test_batch_render_with_odd_sizes_matches_plain(ctx):

@@ -671,6 +671,126 @@ def test_transfer_round_trip_and_plane_consistency():
         assert got == pytest.approx(1.0 / q1[2], rel=1e-10)
 
 
+def _grid_state(gw, gh, ids, normals, flags=None):
+    return oracle.new_state(np.asarray(ids, np.float64).reshape(-1),
+                            np.asarray(normals, np.float64).reshape(-1, 3), flags)
+
+
+def test_regrid_identity_pose_keeps_every_usable_surfel_in_its_tile():
+    rng = np.random.default_rng(43)
+    K, W, H, S = (200.0, 210.0, 80.0, 60.0), 160, 120, 4
+    gw, gh = W // S, H // S
+    m = gw * gh
+    ids = rng.uniform(0.25, 1.0, m)
+    ns = np.array([random_unit_cap(rng, 40) for _ in range(m)])
+    flags = np.zeros(m, np.uint32)
+    flags[rng.choice(m, 30, replace=False)] = oracle.DEGENERATE
+    flags[rng.choice(m, 30, replace=False)] |= oracle.UNINIT
+    st = _grid_state(gw, gh, ids, ns, flags)
+    st["last_update"][:] = np.arange(m, dtype=np.uint32) + 7
+    out, is_new, win, filled = oracle.transfer_regrid((K, W, H, S), st, np.eye(3), np.zeros(3),
+                                                      (K, W, H, S))
+    usable = (flags & (oracle.DEGENERATE | oracle.UNINIT)) == 0
+    assert filled == usable.sum()
+    assert np.array_equal(win.reshape(-1), np.where(usable, np.arange(m), -1))
+    assert np.array_equal(is_new.reshape(-1), (~usable).astype(np.uint8))
+    assert np.allclose(out["inv_depth"][usable], ids[usable], rtol=1e-13)
+    got_n = np.stack([out["nx"], out["ny"], out["nz"]], 1)
+    assert np.allclose(got_n[usable], ns[usable], atol=1e-14)
+    assert np.all(out["flags"][~usable] == oracle.UNINIT) and np.all(out["inv_depth"][~usable] == 0)
+    assert np.array_equal(out["last_update"][usable], st["last_update"][usable])
+
+
+@pytest.mark.parametrize("S,k", [(4, 1), (4, 3), (8, 2)])
+def test_regrid_sideways_motion_shifts_a_wall_by_whole_tiles(S, k):
+    """A fronto-parallel wall at depth d and a sideways camera motion of
+    S k d / fx move every surfel by exactly k tiles (pinhole geometry)."""
+    K, W, H = (180.0, 180.0, 81.0, 59.0), 128, 96
+    gw, gh = W // S, H // S
+    d = 2.5
+    st = _grid_state(gw, gh, np.full(gw * gh, 1 / d), np.tile([0.0, 0.0, -1.0], (gw * gh, 1)))
+    t = np.array([-S * k * d / K[0], 0.0, 0.0])
+    out, is_new, win, filled = oracle.transfer_regrid((K, W, H, S), st, np.eye(3), t, (K, W, H, S))
+    idx = np.arange(gw * gh).reshape(gh, gw)
+    expect = np.full((gh, gw), -1)
+    expect[:, :gw - k] = idx[:, k:]
+    assert np.array_equal(win, expect)
+    assert np.array_equal(is_new, (expect < 0).astype(np.uint8))
+    filled_mask = (expect >= 0).reshape(-1)
+    assert np.allclose(out["inv_depth"][filled_mask], 1 / d, rtol=1e-13)
+    assert np.allclose(out["nz"][filled_mask], -1.0, atol=1e-15)
+
+
+def test_regrid_occlusion_keeps_the_closer_surface():
+    """Near wall (left half, depth 1) and far wall (right half, depth 4);
+    moving the camera sideways slides the near wall over the far one by
+    integer tile counts (8 and 2 tiles): where both land the near one wins."""
+    K, W, H, S = (160.0, 160.0, 95.5, 31.5), 192, 64, 4
+    gw, gh = W // S, H // S
+    ids = np.where(np.arange(gw) < gw // 2, 1.0, 0.25)
+    st = _grid_state(gw, gh, np.tile(ids, gh), np.tile([0.0, 0.0, -1.0], (gw * gh, 1)))
+    t = np.array([8 * S / K[0], 0.0, 0.0])          # shift = fx t_x id pixels
+    out, is_new, win, filled = oracle.transfer_regrid((K, W, H, S), st, np.eye(3), t, (K, W, H, S))
+    expect = np.full(gw, -1)
+    for tx in range(gw):                              # brute force over sources, far first
+        shift = 2 if tx >= gw // 2 else 8
+        if tx + shift < gw and (expect[tx + shift] < 0 or ids[tx] > ids[expect[tx + shift]]):
+            expect[tx + shift] = tx
+    for ty in range(gh):
+        want = np.where(expect >= 0, expect + ty * gw, -1)
+        assert np.array_equal(win[ty], want)
+    near_won = (expect >= 0) & (expect < gw // 2)
+    assert near_won[gw // 2 + 2: gw // 2 + 8].all()   # overlapped columns
+    assert np.allclose(out["inv_depth"].reshape(gh, gw)[:, expect >= 0],
+                       np.tile(ids[expect[expect >= 0]], (gh, 1)), rtol=1e-13)
+
+
+def test_regrid_tilted_planes_against_ray_plane_solve_and_brute_force_ztest():
+    rng = np.random.default_rng(47)
+    K0, K1 = (220.0, 230.0, 78.0, 62.0), (250.0, 240.0, 90.0, 55.0)
+    W0, H0, S0 = 160, 120, 4
+    W1, H1, S1 = 176, 112, 8
+    gw0, gh0 = W0 // S0, H0 // S0
+    gw1, gh1 = W1 // S1, H1 // S1
+    m = gw0 * gh0
+    ids = rng.uniform(0.3, 0.9, m)
+    ns = np.array([random_unit_cap(rng, 35) for _ in range(m)])
+    st = _grid_state(gw0, gh0, ids, ns)
+    R = rot(rng.normal(size=3), math.radians(3))
+    t = np.array([0.04, -0.03, -0.08])
+    out, is_new, win, filled = oracle.transfer_regrid((K0, W0, H0, S0), st, R, t, (K1, W1, H1, S1))
+    # landing of every source surfel by explicit projection
+    best = {}
+    for i in range(m):
+        us = (S0 * (i % gw0) + 0.5 * (S0 - 1), S0 * (i // gw0) + 0.5 * (S0 - 1))
+        p1 = R @ (ray(K0, *us) / ids[i]) + t
+        if p1[2] <= 0:
+            continue
+        px = math.floor(K1[0] * p1[0] / p1[2] + K1[2] + 0.5)
+        py = math.floor(K1[1] * p1[1] / p1[2] + K1[3] + 0.5)
+        if not (0 <= px < gw1 * S1 and 0 <= py < gh1 * S1):
+            continue
+        j = (py // S1) * gw1 + px // S1
+        if j not in best or 1 / p1[2] > best[j][0]:
+            best[j] = (1 / p1[2], i, p1)
+    assert filled > 0.5 * gw1 * gh1
+    for j in range(gw1 * gh1):
+        if j not in best:
+            assert win.reshape(-1)[j] == -1 and is_new.reshape(-1)[j] == 1
+            continue
+        _, i, p1 = best[j]
+        assert win.reshape(-1)[j] == i
+        # the moved plane through p1 with normal R n, cut by the tile's centre ray
+        nn = R @ ns[i]
+        a = np.cross(nn, [0.3, -0.2, 0.9]); a /= np.linalg.norm(a)
+        b = np.cross(nn, a)
+        rt = ray(K1, S1 * (j % gw1) + 0.5 * (S1 - 1), S1 * (j // gw1) + 0.5 * (S1 - 1))
+        lam = np.linalg.solve(np.stack([rt, -a, -b], 1), p1)[0]
+        assert out["inv_depth"][j] == pytest.approx(1 / lam, rel=1e-11)
+        got_n = np.array([out["nx"][j], out["ny"][j], out["nz"][j]])
+        assert np.allclose(got_n, nn, atol=1e-13)
+
+
 # --- Levenberg-Marquardt variant ---------------------------------------------
 
 def test_levenberg_marquardt_never_increases_mean_cost_and_reaches_gn_point():
