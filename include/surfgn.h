@@ -147,6 +147,9 @@ typedef struct {
     int32_t waves_per_cu;       /* persistent grid size per compute unit (0: occupancy) */
     int32_t lds_stage;          /* 1: stage neighbour-frame footprints in LDS */
     int32_t xcd_queues;         /* 1: one work queue per XCD, keyframes bound to an XCD */
+    int32_t groups;             /* tiles_x x tiles_y groups per work item: 1, 2 or 4 (0:
+                                   default).  A work item lies in one aligned 16 x 16-pixel
+                                   block; its per-surfel solves run together, one lane each */
 } sgn_plan;
 
 /* One keyframe of a batch with its surfels and optional outputs. */

@@ -43,11 +43,11 @@ size_t dtype_size(int dt) { return dt == SGN_F32 ? 4 : dt == SGN_F16 ? 2 : 1; }
 constexpr int kRingSlots = 4;
 
 struct GraphKey {
-    int dtype, patch, tx, ty, lds, persistent, grid, part, do_init, spare, frames_cap;
+    int dtype, patch, tx, ty, lds, persistent, grid, part, do_init, groups, frames_cap;
     bool operator<(const GraphKey& o) const {
-        return std::tie(dtype, patch, tx, ty, lds, persistent, grid, part, do_init, spare, frames_cap) <
+        return std::tie(dtype, patch, tx, ty, lds, persistent, grid, part, do_init, groups, frames_cap) <
                std::tie(o.dtype, o.patch, o.tx, o.ty, o.lds, o.persistent, o.grid, o.part, o.do_init,
-                        o.spare, o.frames_cap);
+                        o.groups, o.frames_cap);
     }
 };
 
@@ -179,6 +179,7 @@ sgn_plan default_plan(int patch) {
     sgn_plan p{};
     if (patch == 8) { p.tiles_x = 1; p.tiles_y = 1; }
     else { p.tiles_x = 4; p.tiles_y = 1; }
+    p.groups = 4;
     p.persistent = 1;
     p.waves_per_cu = 0;
     p.lds_stage = 0;
@@ -216,7 +217,8 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
     if (st) return st;
     sgn_plan plan = plan_in ? *plan_in : default_plan(patch);
     if (plan.tiles_x == 0 && plan.tiles_y == 0) plan = default_plan(patch);
-    GnVariant var{dtype, patch, plan.tiles_x, plan.tiles_y, plan.lds_stage};
+    if (plan.groups == 0) plan.groups = default_plan(patch).groups;
+    GnVariant var{dtype, patch, plan.tiles_x, plan.tiles_y, plan.lds_stage, plan.groups};
     if (fl.gn && !gn_variant_supported(var)) return fail(SGN_E_UNSUPPORTED, "plan not supported for this patch");
 
     TableLayout L = layout_for(n, total_frames);
@@ -234,7 +236,8 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
     std::memset(host, 0, L.total);
 
     // keyframe order: longest work items first, grouped by XCD queue
-    const int TX = fl.gn ? plan.tiles_x : 1, TY = fl.gn ? plan.tiles_y : 1;
+    const ItemGeo geo = fl.gn ? item_geo(patch, plan.tiles_x, plan.tiles_y, plan.groups)
+                              : item_geo(patch, patch == 8 ? 1 : 4, 1, 1);
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::vector<int64_t> work(n);
@@ -290,9 +293,9 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
         D.patch = kf.patch;
         D.nbr_pitch_b = kf.n_nbr > 0 ? kf.nbr[0].pitch * (int32_t)dtype_size(kf.kf.dtype) : 0;
         D.frame_base = frame_base;
-        D.groups_x = (D.gw + TX - 1) / TX;
-        const int groups_y = (D.gh + TY - 1) / TY;
-        D.n_items = fl.gn ? D.groups_x * groups_y : 0;
+        D.groups_x = (D.gw + geo.ab - 1) / geo.ab;            // anchor blocks per row
+        const int blocks_y = (D.gh + geo.ab - 1) / geo.ab;
+        D.n_items = fl.gn ? D.groups_x * blocks_y * geo.ipb : 0;
         D.item_base = item_base;
         D.surfel_base = surfel_base;
         D.pixel_base = pixel_base;
@@ -375,7 +378,7 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
             return e == hipSuccess ? SGN_OK : hip_fail(e, "kernel launch");
         }
         GraphKey key{dtype, patch, plan.tiles_x, plan.tiles_y, plan.lds_stage, plan.persistent,
-                     part == 1 ? gn_grid : aux_grid, part, (int)do_init, 0, frames_cap};
+                     part == 1 ? gn_grid : aux_grid, part, (int)do_init, plan.groups, frames_cap};
         auto found = c->graphs.find(key);
         if (found == c->graphs.end()) {
             hipStream_t cap = nullptr;
@@ -617,22 +620,24 @@ sgn_status sgn_autotune(sgn_ctx* c, const sgn_batch_item* items, int32_t n, cons
     std::vector<std::pair<int, int>> shapes = patch == 8 ? std::vector<std::pair<int, int>>{{1, 1}}
                                                          : std::vector<std::pair<int, int>>{{4, 1}, {2, 2}, {1, 4}};
     for (auto sh : shapes)
-        for (int pers = 0; pers <= 1; ++pers)
-            for (int xq = 0; xq <= pers; ++xq) {
-                sgn_plan pl{};
-                pl.tiles_x = sh.first;
-                pl.tiles_y = sh.second;
-                pl.persistent = pers;
-                pl.xcd_queues = xq;
-                pl.lds_stage = 0;
-                pl.waves_per_cu = 0;
-                cands.push_back(pl);
-            }
+        for (int groups : {1, 2, 4})
+            for (int pers = 0; pers <= 1; ++pers)
+                for (int xq = 0; xq <= pers; ++xq) {
+                    sgn_plan pl{};
+                    pl.tiles_x = sh.first;
+                    pl.tiles_y = sh.second;
+                    pl.groups = groups;
+                    pl.persistent = pers;
+                    pl.xcd_queues = xq;
+                    pl.lds_stage = 0;
+                    pl.waves_per_cu = 0;
+                    cands.push_back(pl);
+                }
     float best = 1e30f;
     sgn_plan best_plan = default_plan(patch);
     sgn_status result = SGN_OK;
     for (const sgn_plan& pl : cands) {
-        GnVariant v{items[0].kf.kf.dtype, patch, pl.tiles_x, pl.tiles_y, pl.lds_stage};
+        GnVariant v{items[0].kf.kf.dtype, patch, pl.tiles_x, pl.tiles_y, pl.lds_stage, pl.groups};
         if (!gn_variant_supported(v)) continue;
         float tot = 0.f;
         bool ok = true;

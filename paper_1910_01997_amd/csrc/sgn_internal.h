@@ -31,7 +31,7 @@ struct KfDev {
     int32_t* index_out;           // may be null
     int32_t width, height, kf_pitch, n_nbr;
     int32_t gw, gh, frame_base, item_base;      // frames: [frame_base, frame_base + n_nbr)
-    int32_t groups_x, n_items, surfel_base, queue;  // work items of this keyframe
+    int32_t groups_x, n_items, surfel_base, queue;  // anchor blocks per row; work items
     int64_t pixel_base;                          // prefix over rendered pixels
     int32_t patch, nbr_pitch_b;                   // neighbour-image row pitch in bytes
     double fx_d, fy_d, cx_d, cy_d;               // intrinsics as given (double)
@@ -92,7 +92,24 @@ struct GnVariant {
     int patch;      // 4 or 8
     int tiles_x, tiles_y;
     int lds;        // stage footprints in LDS
+    int groups;     // surfel groups per work item (1, 2 or 4)
 };
+
+// Work-item geometry of the Gauss-Newton kernel.  Surfels are taken in
+// aligned anchor blocks of 16 x 16 pixels (ab x ab tiles).  A work item is an
+// ix x iy tile sub-block of one anchor block holding K groups of tx x ty
+// tiles (one group fills a wavefront: four 4 x 4 surfels or one 8 x 8
+// surfel), arranged gx x gy; ipb items tile an anchor block.
+struct ItemGeo {
+    int ab, gx, gy, ix, iy, ipb;
+};
+constexpr ItemGeo item_geo(int S, int TX, int TY, int K) {
+    const int ab = 16 / S;
+    const int gx = (S == 4) ? (K == 4 ? 4 / TX : (K == 2 ? (TX == 4 ? 1 : 2) : 1)) : (K >= 2 ? 2 : 1);
+    const int gy = K / gx;
+    const int ix = gx * TX, iy = gy * TY;
+    return ItemGeo{ab, gx, gy, ix, iy, (ab / ix) * (ab / iy)};
+}
 
 // Launchers implemented in sgn_kernels.hip.  All return hipError_t of the
 // launch.

@@ -298,21 +298,24 @@ __device__ __forceinline__ bool solve3_fp64(double h00, double h01, double h02, 
     return true;
 }
 
-// Warp constants of one (surfel, frame) pair, staged in LDS.  The
+// Warp constants of one (anchor block, frame) pair, staged in LDS.  The
 // plane-induced homography q = H u~ + (K t) id_u (Eq. 6) is evaluated in
-// local coordinates: u = u_s + d (d = pixel offset from the surfel centre,
-// exact) and an integer anchor (X0, Y0) near the surfel centre's warp at
-// infinite depth, so that every float quantity formed per sample is small:
+// local coordinates: u = u_b + d, with u_b the centre of the aligned
+// 16 x 16-pixel anchor block that holds the surfel and d the pixel's offset
+// from it (exact, |d| <= 7.5), and an integer anchor (X0, Y0) near the block
+// centre's warp at infinite depth, so that every float quantity formed per
+// sample is small:
 //   x_p - X0 = (Ex + hx0 dx + hx1 dy + kx id_u) / q_z
 //   y_p - Y0 = (Ey + hy0 dx + hy1 dy + ky id_u) / q_z
 //   q_z      =  Qz + h6 dx  + h7 dy  + k2 id_u
-// with Ex = Q_x - X0 Q_z, Q = H u~_s, hx0 = h0 - X0 h6, kx = k0 - X0 k2, ...
-// all formed in double once per work item and rounded once to float.
+// with Ex = Q_x - X0 Q_z, Q = H u~_b, hx0 = h0 - X0 h6, kx = k0 - X0 k2, ...
+// all formed in double once per work item and rounded once to float.  The
+// block depends only on the surfel's position, so every launch plan forms
+// the same words for a surfel.
 constexpr int kPairWords = 12;
 enum : int {
     W_HX0 = 0, W_HX1, W_KX, W_EX, W_HY0, W_HY1, W_KY, W_EY, W_QZ, W_X0, W_Y0, W_B0
 };
-constexpr int kMaxSlots = 4;
 // Levenberg-Marquardt acceptance: largest relative rise of the mean cost.
 constexpr float kLmAcceptRise = 1e-4f;
 
@@ -531,20 +534,76 @@ __device__ __forceinline__ void frame_cost(const float* __restrict__ pc, cptr<Fr
     }
 }
 
-template <typename T, int S, int TX, int TY>
+// Per-surfel records exchanged through LDS between the pixel lanes and the
+// surfel's owner lane (see gn_kernel).
+enum : int {
+    // state broadcast to the pixel lanes
+    ST_ID = 0, ST_NX, ST_NY, ST_NZ, ST_B1X, ST_B1Y, ST_B1Z, ST_B2X, ST_B2Y, ST_B2Z, ST_INVC,
+    ST_RSX, ST_RSY, ST_ALIVE, ST_WORDS = 16
+};
+enum : int {
+    // reduced normal equations sent to the owner
+    SM_H00 = 0, SM_H01, SM_H02, SM_H11, SM_H12, SM_H22, SM_B0, SM_B1, SM_B2, SM_NV, SM_COST,
+    SM_WORDS = 12
+};
+constexpr int kMaxItemSurfels = 16;
+
+// Tangent basis of n: b1 = normalise(e - (e.n) n), e = x^ if |n_x| < 0.9
+// else y^, and b2 = n x b1.
+__device__ __forceinline__ void tangent_basis(float nx, float ny, float nz, float& b1x, float& b1y,
+                                              float& b1z, float& b2x, float& b2y, float& b2z) {
+    const bool ex = fabsf(nx) < 0.9f;
+    const float en = ex ? nx : ny;
+    b1x = (ex ? 1.f : 0.f) - en * nx;
+    b1y = (ex ? 0.f : 1.f) - en * ny;
+    b1z = -en * nz;
+    const float ib = __frsqrt_rn(b1x * b1x + b1y * b1y + b1z * b1z);
+    b1x *= ib; b1y *= ib; b1z *= ib;
+    b2x = ny * b1z - nz * b1y;
+    b2y = nz * b1x - nx * b1z;
+    b2z = nx * b1y - ny * b1x;
+}
+
+// The fused Gauss-Newton kernel.
+//
+// Mapping.  A work item is a block of surfels inside one aligned anchor
+// block (16 x 16 pixels): K groups, each filling the 64 lanes of the
+// wavefront with pixels (S = 4: a TX x TY arrangement of four 4 x 4 surfels,
+// one DPP row of 16 lanes per surfel; S = 8: one 8 x 8 surfel).  Per
+// iteration the wavefront walks its groups; for each, every lane (one pixel)
+// forms the frame-independent terms of its surfel (hoisted as the paper
+// suggests), loops over the neighbour frames (warp, bilinear sample and
+// gradient, Huber-weighted residual, chain factor) and the surfel's lanes
+// reduce J^T W J and J^T W r with DPP.  Each surfel has an owner lane
+// (S = 4: lane k of its row in group k; S = 8: lane k); the owners then solve
+// all K groups' 3 x 3 systems at once, so the per-surfel work (solve,
+// update, tangent basis) is issued once per K groups.  Sums and states pass
+// between the pixel lanes and the owners through LDS.  All iterations run in
+// the kernel: surfels never read each other during the optimisation.
+template <typename T, int S, int TX, int TY, int K>
 __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __restrict__ hdr_,
                                                            uint32_t* __restrict__ counters,
                                                            int persistent) {
+    constexpr ItemGeo G = item_geo(S, TX, TY, K);
     constexpr int LANES = S * S;                 // lanes per surfel
-    static_assert(TX * TY * LANES == kWaveSize, "a wavefront holds 64 pixels");
+    constexpr int SLOTS = kWaveSize / LANES;     // surfels per group
+    constexpr int NS = K * SLOTS;                // surfels per work item
+    static_assert(TX * TY * LANES == kWaveSize, "a group fills the wavefront");
+    static_assert(NS <= kMaxItemSurfels, "surfels per item");
     const cptr<BatchHeader> hdr = (cptr<BatchHeader>)hdr_;
     const int lane = threadIdx.x & (kWaveSize - 1);
-    const int slot = lane / LANES;
+    const int wave = threadIdx.x >> 6;
+    // pixel role: slot r of a group and pixel (px, py) of that surfel
+    const int r = lane / LANES;
     const int p = lane % LANES;
     const int px = p % S, py = p / S;
-    const int sx = slot % TX, sy = slot / TX;
     const float half = 0.5f * (float)(S - 1);
-    const float dxp = (float)px - half, dyp = (float)py - half;   // pixel offset from u_s (exact)
+    const float dxp = (float)px - half, dyp = (float)py - half;   // offset from u_s (exact)
+    // owner role: surfel (group ok_g, slot ok_r) of the item
+    const int ok_g = (S == 4) ? (lane & 15) : lane;
+    const int ok_r = (S == 4) ? (lane >> 4) : 0;
+    const bool owner = ok_g < K;
+    const int own = ok_g * SLOTS + ok_r;
 
     const int n_kf = hdr->n_kf;
     const int total = hdr->total_items;
@@ -557,55 +616,60 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
     const bool lm = lm0 > 0.f;
     const cptr<KfDev> kfs = (cptr<KfDev>)hdr->kfs;
 
-    const int wave_global = blockIdx.x * (kBlockThreads / kWaveSize) + (threadIdx.x >> 6);
-    __shared__ float4 s_pairs[kBlockThreads / kWaveSize][kMaxSlots * kMaxNbr * kPairWords / 4];
-    float* const pairs = (float*)s_pairs[threadIdx.x >> 6];
-    // work-queue state (persistent mode): start on this XCD's queue
+    __shared__ float4 s_pairs[kBlockThreads / kWaveSize][kMaxNbr * kPairWords / 4];
+    __shared__ float4 s_state[kBlockThreads / kWaveSize][kMaxItemSurfels * ST_WORDS / 4];
+    __shared__ float4 s_sums[kBlockThreads / kWaveSize][kMaxItemSurfels * SM_WORDS / 4];
+    float* const pairs = (float*)s_pairs[wave];
+    float* const lst = (float*)s_state[wave];
+    float* const lsm = (float*)s_sums[wave];
+
     int q = persistent ? (int)(blockIdx.x % (unsigned)kXcds) % hdr->n_queues : 0;
     int q_left = hdr->n_queues;
-
+    const int wave_global = blockIdx.x * (kBlockThreads / kWaveSize) + wave;
     int hint = 0;
     int item = persistent ? pull_item(hdr_, counters, q, q_left, lane, total) : wave_global;
     for (; item < total;
          item = persistent ? pull_item(hdr_, counters, q, q_left, lane, total) : total) {
         item = __builtin_amdgcn_readfirstlane(item);
-        const int k = find_kf(kfs, n_kf, item, hint);
-        hint = k;
-        const cptr<KfDev> K = kfs + k;
-        const int g = item - K->item_base;
-        const int gx = g % K->groups_x, gy = g / K->groups_x;
-        const int tx = gx * TX + sx, ty = gy * TY + sy;
-        const bool tile_ok = (tx < K->gw) && (ty < K->gh);
-        const int sidx = ty * K->gw + tx;
-        const float usx = (float)(S * tx) + half, usy = (float)(S * ty) + half;
-        const float rsx = (usx - K->cx) / K->fx, rsy = (usy - K->cy) / K->fy;   // r_s (z = 1)
-        const float drx = dxp / K->fx, dry = dyp / K->fy;                      // r_u - r_s
-        const int nf = K->n_nbr;
-        const float img_scale = K->img_scale;
-        const unsigned pitch_b = (unsigned)K->nbr_pitch_b;
-        const unsigned img_bytes = pitch_b * (unsigned)K->height;
-        const unsigned wm1 = (unsigned)(K->width - 1), hm1 = (unsigned)(K->height - 1);
+        const int kidx = find_kf(kfs, n_kf, item, hint);
+        hint = kidx;
+        const cptr<KfDev> Kd = kfs + kidx;
+        // item -> anchor block (bx, by) and the item's place in it
+        const int g = item - Kd->item_base;
+        const int blk = g / G.ipb, sub = g - blk * G.ipb;
+        const int bx = blk % Kd->groups_x, by = blk / Kd->groups_x;
+        const int it0x = bx * G.ab + (sub % (G.ab / G.ix)) * G.ix;
+        const int it0y = by * G.ab + (sub / (G.ab / G.ix)) * G.iy;
+        const int gw = Kd->gw, gh = Kd->gh;
+        if (it0x >= gw || it0y >= gh) continue;          // item entirely outside the grid
+        const int nf = Kd->n_nbr;
+        const float img_scale = Kd->img_scale;
+        const unsigned pitch_b = (unsigned)Kd->nbr_pitch_b;
+        const unsigned img_bytes = pitch_b * (unsigned)Kd->height;
+        const unsigned wm1 = (unsigned)(Kd->width - 1), hm1 = (unsigned)(Kd->height - 1);
+        const float fxk = Kd->fx, fyk = Kd->fy, cxk = Kd->cx, cyk = Kd->cy;
+        const float drx = dxp / fxk, dry = dyp / fyk;                  // r_u - r_s
+        // anchor block centre (pixels)
+        const int bpx = bx * G.ab * S, bpy = by * G.ab * S;
         {
-            // warp constants of every (surfel slot, frame) pair of this item,
-            // one pair per lane, in double
+            // warp constants of every frame for this anchor block, one frame
+            // per lane, in double
             wave_sync();
-            const int ps = lane / kMaxNbr, pf = lane % kMaxNbr;
-            if (ps < TX * TY && pf < nf) {
-                const int ptx = gx * TX + ps % TX, pty = gy * TY + ps / TX;
-                const double qsx = (double)(S * ptx) + (double)half;
-                const double qsy = (double)(S * pty) + (double)half;
-                const gptr<FrameDev> F = (gptr<FrameDev>)(hdr->frames + K->frame_base + pf);
+            if (lane < nf) {
+                const double qbx = (double)bpx + 0.5 * (double)(G.ab * S - 1);
+                const double qby = (double)bpy + 0.5 * (double)(G.ab * S - 1);
+                const gptr<FrameDev> F = (gptr<FrameDev>)(hdr->frames + Kd->frame_base + lane);
                 const gptr<double> hm = F->hm;
                 const gptr<double> kt = F->kt;
-                const double Qx = fma(hm[0], qsx, fma(hm[1], qsy, hm[2]));
-                const double Qy = fma(hm[3], qsx, fma(hm[4], qsy, hm[5]));
-                const double Qz = fma(hm[6], qsx, fma(hm[7], qsy, hm[8]));
+                const double Qx = fma(hm[0], qbx, fma(hm[1], qby, hm[2]));
+                const double Qy = fma(hm[3], qbx, fma(hm[4], qby, hm[5]));
+                const double Qz = fma(hm[6], qbx, fma(hm[7], qby, hm[8]));
                 double X0 = 0.0, Y0 = 0.0;
                 if (Qz > 0.0) {
                     X0 = rint(fmin(fmax(Qx / Qz, -20000.0), 20000.0));
                     Y0 = rint(fmin(fmax(Qy / Qz, -20000.0), 20000.0));
                 }
-                float* w = pairs + (ps * kMaxNbr + pf) * kPairWords;
+                float* w = pairs + lane * kPairWords;
                 w[W_HX0] = (float)(hm[0] - X0 * hm[6]);
                 w[W_HX1] = (float)(hm[1] - X0 * hm[7]);
                 w[W_KX] = (float)(kt[0] - X0 * kt[2]);
@@ -619,227 +683,313 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                 w[W_Y0] = __int_as_float((int)Y0);
                 w[W_B0] = 0.f;
             }
-            wave_sync();
         }
-        const float* const pc = pairs + slot * kMaxNbr * kPairWords;
         // the frame table pointer is wave-uniform: keep it in SGPRs
-        const uint64_t fr_bits = (uint64_t)(const void*)(hdr->frames + K->frame_base);
+        const uint64_t fr_bits = (uint64_t)(const void*)(hdr->frames + Kd->frame_base);
         const uint32_t fr_lo = __builtin_amdgcn_readfirstlane((uint32_t)fr_bits);
         const uint32_t fr_hi = __builtin_amdgcn_readfirstlane((uint32_t)(fr_bits >> 32));
         const cptr<FrameDev> fr = (cptr<FrameDev>)(((uint64_t)fr_hi << 32) | fr_lo);
-        const gmut<float> s_id = (gmut<float>)K->inv_depth;
-        const gmut<float> s_nx = (gmut<float>)K->nx;
-        const gmut<float> s_ny = (gmut<float>)K->ny;
-        const gmut<float> s_nz = (gmut<float>)K->nz;
-        const gmut<uint32_t> s_flags = (gmut<uint32_t>)K->flags;
 
-        float id = 0.f, nx = 0.f, ny = 0.f, nz = -1.f, ikf = 0.f;
-        uint32_t flags = 0u;
-        if (tile_ok) {
-            id = s_id[sidx];
-            nx = s_nx[sidx]; ny = s_ny[sidx]; nz = s_nz[sidx];
-            flags = s_flags[sidx] & ~F_GN_BITS;
-            const gptr<T> kimg = (gptr<T>)K->kf_img;
-            ikf = ldg<T>(kimg + ((unsigned)(S * ty + py) * (unsigned)K->kf_pitch + (unsigned)(S * tx + px))) *
-                  K->kf_scale;
+        // pixel lanes: keyframe value of this lane's pixel in every group
+        float ikf[K];
+        const gptr<T> kimg = (gptr<T>)Kd->kf_img;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int tx = it0x + (k % G.gx) * TX + r % TX, ty = it0y + (k / G.gx) * TY + r / TX;
+            ikf[k] = 0.f;
+            if (tx < gw && ty < gh)
+                ikf[k] = ldg<T>(kimg + ((unsigned)(S * ty + py) * (unsigned)Kd->kf_pitch +
+                                        (unsigned)(S * tx + px))) * Kd->kf_scale;
         }
-        bool alive = tile_ok;
+
+        // owner lanes: the surfel's state
+        const int otx = it0x + (ok_g % G.gx) * TX + ok_r % TX;
+        const int oty = it0y + (ok_g / G.gx) * TY + ok_r / TX;
+        const bool own_ok = owner && otx < gw && oty < gh;
+        const int sidx = oty * gw + otx;
+        const float usx = (float)(S * otx) + half, usy = (float)(S * oty) + half;
+        const float rsx = (usx - cxk) / fxk, rsy = (usy - cyk) / fyk;   // r_s (z = 1)
+        float id = 0.f, nx = 0.f, ny = 0.f, nz = -1.f;
+        uint32_t flags = 0u;
+        if (own_ok) {
+            id = ((gptr<float>)Kd->inv_depth)[sidx];
+            nx = ((gptr<float>)Kd->nx)[sidx];
+            ny = ((gptr<float>)Kd->ny)[sidx];
+            nz = ((gptr<float>)Kd->nz)[sidx];
+            flags = ((gptr<uint32_t>)Kd->flags)[sidx] & ~F_GN_BITS;
+        }
+        bool alive = own_ok;
         bool updated = false;
         float cost_out = 0.f;
         int nv_out = 0;
         float lam = lm0;             // Levenberg-Marquardt damping of this surfel
+        float b1x = 0.f, b1y = 0.f, b1z = 0.f, b2x = 0.f, b2y = 0.f, b2z = 0.f;
 
         for (int it = 0; it < iters; ++it) {
             const bool last = (it == iters - 1);
-            float id_cand = 0.f, nx_cand = 0.f, ny_cand = 0.f, nz_cand = 0.f;
-            bool have_cand = false;
-            (void)have_cand;
-            const float c = nx * rsx + ny * rsy + nz;     // n . r_s
-            if (alive && fabsf(c) < 1e-6f) {
-                flags |= F_DEGENERATE;
-                alive = false;
-                cost_out = 0.f;
-                nv_out = 0;
+            // ---- owners: degeneracy, tangent basis, broadcast of the state
+            if (owner) {
+                const float c = nx * rsx + ny * rsy + nz;     // n . r_s
+                if (alive && fabsf(c) < 1e-6f) {
+                    flags |= F_DEGENERATE;
+                    alive = false;
+                    cost_out = 0.f;
+                    nv_out = 0;
+                }
+                tangent_basis(nx, ny, nz, b1x, b1y, b1z, b2x, b2y, b2z);
+                float* o = lst + own * ST_WORDS;
+                o[ST_ID] = id; o[ST_NX] = nx; o[ST_NY] = ny; o[ST_NZ] = nz;
+                o[ST_B1X] = b1x; o[ST_B1Y] = b1y; o[ST_B1Z] = b1z;
+                o[ST_B2X] = b2x; o[ST_B2Y] = b2y; o[ST_B2Z] = b2z;
+                o[ST_INVC] = rcp_fast(c);                    // |c| >= 1e-6 where used
+                o[ST_RSX] = rsx; o[ST_RSY] = rsy;
+                o[ST_ALIVE] = alive ? 1.f : 0.f;
             }
-            // tangent basis of n: b1 = normalise(e - (e.n) n), b2 = n x b1
-            const bool ex = fabsf(nx) < 0.9f;
-            const float en = ex ? nx : ny;
-            float b1x = (ex ? 1.f : 0.f) - en * nx;
-            float b1y = (ex ? 0.f : 1.f) - en * ny;
-            float b1z = -en * nz;
-            const float ib = __frsqrt_rn(b1x * b1x + b1y * b1y + b1z * b1z);
-            b1x *= ib; b1y *= ib; b1z *= ib;
-            const float b2x = ny * b1z - nz * b1y;
-            const float b2y = nz * b1x - nx * b1z;
-            const float b2z = nx * b1y - ny * b1x;
-            // frame-independent per-pixel terms (Eq. 3, Eq. 9)
-            const float inv_c = rcp_fast(c);               // |c| >= 1e-6 where used
-            const float sigma = (nx * drx + ny * dry) * inv_c;
-            const float idu = fmaf(id, sigma, id);
-            const float dx3 = fmaf(-sigma, rsx, drx);
-            const float dy3 = fmaf(-sigma, rsy, dry);
-            const float dz3 = -sigma;
-            const float kk = id * inv_c;
-            const float g0 = 1.f + sigma;
-            const float g1 = depth_only ? 0.f : kk * (b1x * dx3 + b1y * dy3 + b1z * dz3);
-            const float g2 = depth_only ? 0.f : kk * (b2x * dx3 + b2y * dy3 + b2z * dz3);
-            const bool pix_ok = alive && (idu > 0.f);
-
-            float A = 0.f, B = 0.f, cst = 0.f;
-            int nvl = 0;
-            if (last || lm)
-                frame_loop<T, true>(pc, fr, nf, dxp, dyp, idu, pix_ok, pitch_b, img_bytes, wm1, hm1,
-                                    ikf, hk, img_scale, A, B, cst, nvl);
-            else
-                frame_loop<T, false>(pc, fr, nf, dxp, dyp, idu, pix_ok, pitch_b, img_bytes, wm1, hm1,
-                                     ikf, hk, img_scale, A, B, cst, nvl);
-            // J^T W J = sum_u A_u g g^T, J^T W r = sum_u B_u g (frame sum hoisted)
-            float H00, H01, H02, H11, H12, H22, bb0, bb1, bb2;
-            int nv;
-            {
-                // No FMA contraction here: each butterfly step must be a plain
-                // add of two rounded values so that every lane of a surfel
-                // ends with bitwise-identical sums (and identical states).
+            wave_sync();
+            // ---- pixel lanes: linearise every group and reduce per surfel
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const float* st = lst + (k * SLOTS + r) * ST_WORDS;
+                const float4 sa = *(const float4*)(st + 0);      // id, nx, ny, nz
+                const float4 sb = *(const float4*)(st + 4);      // b1, b2x
+                const float4 sc = *(const float4*)(st + 8);      // b2y, b2z, 1/c, rsx
+                const float2 sd = *(const float2*)(st + 12);     // rsy, alive
+                const float sid = sa.x, snx = sa.y, sny = sa.z;
+                const float sb1x = sb.x, sb1y = sb.y, sb1z = sb.z;
+                const float sb2x = sb.w, sb2y = sc.x, sb2z = sc.y, inv_c = sc.z, srsx = sc.w;
+                const float srsy = sd.x;
+                const bool salive = sd.y != 0.f;
+                // frame-independent per-pixel terms (Eq. 3, Eq. 9)
+                const float sigma = (snx * drx + sny * dry) * inv_c;
+                const float idu = fmaf(sid, sigma, sid);
+                const float dx3 = fmaf(-sigma, srsx, drx);
+                const float dy3 = fmaf(-sigma, srsy, dry);
+                const float dz3 = -sigma;
+                const float kk = sid * inv_c;
+                const float g0 = 1.f + sigma;
+                const float g1 = depth_only ? 0.f : kk * (sb1x * dx3 + sb1y * dy3 + sb1z * dz3);
+                const float g2 = depth_only ? 0.f : kk * (sb2x * dx3 + sb2y * dy3 + sb2z * dz3);
+                const bool pix_ok = salive && (idu > 0.f);
+                // pixel offset from the anchor block centre
+                const int tx = it0x + (k % G.gx) * TX + r % TX, ty = it0y + (k / G.gx) * TY + r / TX;
+                const float bdx = (float)(S * tx + px - bpx) - 0.5f * (float)(G.ab * S - 1);
+                const float bdy = (float)(S * ty + py - bpy) - 0.5f * (float)(G.ab * S - 1);
+                float A = 0.f, B = 0.f, cst = 0.f;
+                int nvl = 0;
+                if (last || lm)
+                    frame_loop<T, true>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes, wm1,
+                                        hm1, ikf[k], hk, img_scale, A, B, cst, nvl);
+                else
+                    frame_loop<T, false>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes, wm1,
+                                         hm1, ikf[k], hk, img_scale, A, B, cst, nvl);
+                // J^T W J = sum_u A_u g g^T, J^T W r = sum_u B_u g (frame sum hoisted)
+                float h00, h01, h02, h11, h12, h22, v0, v1, v2;
+                int nv;
+                {
+                    // No FMA contraction: each butterfly step must be a plain
+                    // add of two rounded values so that the sums are
+                    // bitwise-identical on every lane of the surfel.
 #pragma clang fp contract(off)
-                const float ag0 = A * g0, ag1 = A * g1, ag2 = A * g2;
-                H00 = group_sum<LANES>(ag0 * g0);
-                H01 = group_sum<LANES>(ag0 * g1);
-                H02 = group_sum<LANES>(ag0 * g2);
-                H11 = group_sum<LANES>(ag1 * g1);
-                H12 = group_sum<LANES>(ag1 * g2);
-                H22 = group_sum<LANES>(ag2 * g2);
-                bb0 = group_sum<LANES>(B * g0);
-                bb1 = group_sum<LANES>(B * g1);
-                bb2 = group_sum<LANES>(B * g2);
-                nv = group_sum<LANES>(nvl);
-            }
-            float cost_here = 0.f;
-            if (last || lm) {
-                cost_here = group_sum<LANES>(cst);
-                if (last) cost_out = cost_here;
-            }
-            if (!alive) continue;
-            nv_out = nv;
-            if (nv < 3) {
-                flags |= F_FEW_SAMPLES;
-                continue;
-            }
-            float d0s = 0.f, d1s = 0.f, d2s = 0.f;
-            const float dd = 1.f + lam;          // (H + lam diag H): equilibrated diagonal
-            if (depth_only) {
-                if (H00 > 0.f && isfinite(H00)) {
-                    d0s = -bb0 * rcp_fast(H00 * dd);
-                } else {
-                    flags |= F_SOLVE_FAIL;
-                    continue;
+                    const float ag0 = A * g0, ag1 = A * g1, ag2 = A * g2;
+                    h00 = group_sum<LANES>(ag0 * g0);
+                    h01 = group_sum<LANES>(ag0 * g1);
+                    h02 = group_sum<LANES>(ag0 * g2);
+                    h11 = group_sum<LANES>(ag1 * g1);
+                    h12 = group_sum<LANES>(ag1 * g2);
+                    h22 = group_sum<LANES>(ag2 * g2);
+                    v0 = group_sum<LANES>(B * g0);
+                    v1 = group_sum<LANES>(B * g1);
+                    v2 = group_sum<LANES>(B * g2);
+                    nv = group_sum<LANES>(nvl);
                 }
-            } else {
-                // equilibrate: E = D^-1/2 H D^-1/2 (unit diagonal)
-                const float maxd = fmaxf(H00, fmaxf(H11, H22));
-                bool need64 = !(H00 > 0.f) || !(H11 > 0.f) || !(H22 > 0.f) || !isfinite(maxd);
-                if (!need64) {
-                    const float e0 = __frsqrt_rn(H00), e1 = __frsqrt_rn(H11), e2 = __frsqrt_rn(H22);
-                    const float e01 = H01 * e0 * e1, e02 = H02 * e0 * e2, e12 = H12 * e1 * e2;
-                    // adjugate and determinant of E (diagonal dd = 1 + lambda)
-                    const float d2 = dd * dd;
-                    const float c00 = fmaf(-e12, e12, d2), c11 = fmaf(-e02, e02, d2);
-                    const float c22 = fmaf(-e01, e01, d2);
-                    const float c01 = fmaf(e02, e12, -dd * e01), c02 = fmaf(e01, e12, -dd * e02);
-                    const float c12 = fmaf(e01, e02, -dd * e12);
-                    const float det = fmaf(e01, c01, fmaf(e02, c02, dd * c00));
-                    // kappa_F(E)^2 = ||E||_F^2 ||adj E||_F^2 / det^2  (>= kappa_2(E)^2)
-                    const float fro2 = 3.f * d2 + 2.f * (e01 * e01 + e02 * e02 + e12 * e12);
-                    const float adj2 = c00 * c00 + c11 * c11 + c22 * c22 +
-                                       2.f * (c01 * c01 + c02 * c02 + c12 * c12);
-                    // raw Cholesky pivots are H_jj times the equilibrated ones
-                    const float p1 = c22 * rcp_fast(dd);  // dd - e01^2 / dd (only compared)
-                    const float p2 = det * rcp_fast(c22);  // (only compared)
-                    need64 = !(fro2 * adj2 <= kap2 * det * det) || !(det > 0.f) || !(c22 > 0.f) ||
-                             !(H11 * p1 > 1e-10f * maxd * dd) || !(H22 * p2 > 1e-10f * maxd * dd);
-                    if (!need64) {
-                        const float bh0 = bb0 * e0, bh1 = bb1 * e1, bh2 = bb2 * e2;
-                        const float idet = rcp_fast(det);
-                        d0s = -(c00 * bh0 + c01 * bh1 + c02 * bh2) * idet * e0;
-                        d1s = -(c01 * bh0 + c11 * bh1 + c12 * bh2) * idet * e1;
-                        d2s = -(c02 * bh0 + c12 * bh1 + c22 * bh2) * idet * e2;
+                float cs = 0.f;
+                if (last || lm) cs = group_sum<LANES>(cst);
+                if (p == 0) {
+                    float* o = lsm + (k * SLOTS + r) * SM_WORDS;
+                    o[SM_H00] = h00; o[SM_H01] = h01; o[SM_H02] = h02;
+                    o[SM_H11] = h11; o[SM_H12] = h12; o[SM_H22] = h22;
+                    o[SM_B0] = v0; o[SM_B1] = v1; o[SM_B2] = v2;
+                    o[SM_NV] = __int_as_float(nv);
+                    o[SM_COST] = cs;
+                }
+            }
+            wave_sync();
+            // ---- owners: solve, update (Levenberg-Marquardt candidate test below)
+            bool cand = false;
+            float id_c = 0.f, nx_c = 0.f, ny_c = 0.f, nz_c = 0.f, cost_here = 0.f;
+            int nv = 0;
+            if (owner) {
+                const float* sm = lsm + own * SM_WORDS;
+                const float H00 = sm[SM_H00], H01 = sm[SM_H01], H02 = sm[SM_H02];
+                const float H11 = sm[SM_H11], H12 = sm[SM_H12], H22 = sm[SM_H22];
+                const float bb0 = sm[SM_B0], bb1 = sm[SM_B1], bb2 = sm[SM_B2];
+                nv = __float_as_int(sm[SM_NV]);
+                cost_here = sm[SM_COST];
+                if (alive && last) cost_out = cost_here;
+                if (alive) {
+                    nv_out = nv;
+                    float d0s = 0.f, d1s = 0.f, d2s = 0.f;
+                    bool ok = true;
+                    if (nv < 3) {
+                        flags |= F_FEW_SAMPLES;
+                        ok = false;
+                    }
+                    const float dd = 1.f + lam;          // (H + lam diag H): equilibrated diagonal
+                    if (ok && depth_only) {
+                        if (H00 > 0.f && isfinite(H00)) {
+                            d0s = -bb0 * rcp_fast(H00 * dd);
+                        } else {
+                            flags |= F_SOLVE_FAIL;
+                            ok = false;
+                        }
+                    } else if (ok) {
+                        // equilibrate: E = D^-1/2 H D^-1/2 (unit diagonal)
+                        const float maxd = fmaxf(H00, fmaxf(H11, H22));
+                        bool need64 = !(H00 > 0.f) || !(H11 > 0.f) || !(H22 > 0.f) || !isfinite(maxd);
+                        if (!need64) {
+                            const float e0 = __frsqrt_rn(H00), e1 = __frsqrt_rn(H11), e2 = __frsqrt_rn(H22);
+                            const float e01 = H01 * e0 * e1, e02 = H02 * e0 * e2, e12 = H12 * e1 * e2;
+                            // adjugate and determinant of E (diagonal dd = 1 + lambda)
+                            const float d2 = dd * dd;
+                            const float c00 = fmaf(-e12, e12, d2), c11 = fmaf(-e02, e02, d2);
+                            const float c22 = fmaf(-e01, e01, d2);
+                            const float c01 = fmaf(e02, e12, -dd * e01), c02 = fmaf(e01, e12, -dd * e02);
+                            const float c12 = fmaf(e01, e02, -dd * e12);
+                            const float det = fmaf(e01, c01, fmaf(e02, c02, dd * c00));
+                            // kappa_F(E)^2 = ||E||_F^2 ||adj E||_F^2 / det^2  (>= kappa_2(E)^2)
+                            const float fro2 = 3.f * d2 + 2.f * (e01 * e01 + e02 * e02 + e12 * e12);
+                            const float adj2 = c00 * c00 + c11 * c11 + c22 * c22 +
+                                               2.f * (c01 * c01 + c02 * c02 + c12 * c12);
+                            // raw Cholesky pivots are H_jj times the equilibrated ones
+                            const float p1 = c22 * rcp_fast(dd);   // dd - e01^2 / dd (only compared)
+                            const float p2 = det * rcp_fast(c22);  // (only compared)
+                            need64 = !(fro2 * adj2 <= kap2 * det * det) || !(det > 0.f) || !(c22 > 0.f) ||
+                                     !(H11 * p1 > 1e-10f * maxd * dd) || !(H22 * p2 > 1e-10f * maxd * dd);
+                            if (!need64) {
+                                const float bh0 = bb0 * e0, bh1 = bb1 * e1, bh2 = bb2 * e2;
+                                const float idet = rcp_fast(det);
+                                d0s = -(c00 * bh0 + c01 * bh1 + c02 * bh2) * idet * e0;
+                                d1s = -(c01 * bh0 + c11 * bh1 + c12 * bh2) * idet * e1;
+                                d2s = -(c02 * bh0 + c12 * bh1 + c22 * bh2) * idet * e2;
+                            }
+                        }
+                        if (need64) {
+                            flags |= F_FP64_SOLVE;
+                            double dd0 = 0.0, dd1 = 0.0, dd2 = 0.0;
+                            const double dmp = 1.0 + (double)lam;
+                            if (solve3_fp64((double)H00 * dmp, H01, H02, (double)H11 * dmp, H12,
+                                            (double)H22 * dmp, bb0, bb1, bb2, dd0, dd1, dd2)) {
+                                d0s = (float)dd0; d1s = (float)dd1; d2s = (float)dd2;
+                            } else {
+                                flags |= F_SOLVE_FAIL;
+                                ok = false;
+                            }
+                        }
+                    }
+                    if (ok) {
+                        // update: id_s += d0; n = normalise(n + d1 b1 + d2 b2) (the
+                        // depth-only ablation moves id_s alone and keeps n)
+                        id_c = id + d0s;
+                        nx_c = nx; ny_c = ny; nz_c = nz;
+                        bool ok_step;
+                        if (depth_only) {
+                            ok_step = (id_c > 0.f) && isfinite(id_c);
+                        } else {
+                            const float mx = fmaf(d1s, b1x, fmaf(d2s, b2x, nx));
+                            const float my = fmaf(d1s, b1y, fmaf(d2s, b2y, ny));
+                            const float mz = fmaf(d1s, b1z, fmaf(d2s, b2z, nz));
+                            const float l2 = mx * mx + my * my + mz * mz;
+                            ok_step = (id_c > 0.f) && isfinite(id_c) && (l2 > 0.f) && isfinite(l2);
+                            if (ok_step) {
+                                const float il = __frsqrt_rn(l2);
+                                nx_c = mx * il; ny_c = my * il; nz_c = mz * il;
+                            }
+                        }
+                        if (!ok_step) {
+                            flags |= F_REJECTED;
+                            if (lm) lam *= 10.f;
+                        } else {
+                            cand = true;
+                        }
                     }
                 }
-                if (need64) {
-                    flags |= F_FP64_SOLVE;
-                    double dd0 = 0.0, dd1 = 0.0, dd2 = 0.0;
-                    const double dmp = 1.0 + (double)lam;
-                    if (solve3_fp64((double)H00 * dmp, H01, H02, (double)H11 * dmp, H12,
-                                    (double)H22 * dmp, bb0, bb1, bb2, dd0, dd1, dd2)) {
-                        d0s = (float)dd0; d1s = (float)dd1; d2s = (float)dd2;
-                    } else {
-                        flags |= F_SOLVE_FAIL;
-                        continue;
-                    }
-                }
             }
-            // update: id_s += d0; n = normalise(n + d1 b1 + d2 b2) (the depth-only
-            // ablation moves id_s alone and leaves n as it is)
-            const float idn = id + d0s;
-            float cnx = nx, cny = ny, cnz = nz;
-            bool ok_step;
-            if (depth_only) {
-                ok_step = (idn > 0.f) && isfinite(idn);
-            } else {
-                const float mx = fmaf(d1s, b1x, fmaf(d2s, b2x, nx));
-                const float my = fmaf(d1s, b1y, fmaf(d2s, b2y, ny));
-                const float mz = fmaf(d1s, b1z, fmaf(d2s, b2z, nz));
-                const float l2 = mx * mx + my * my + mz * mz;
-                ok_step = (idn > 0.f) && isfinite(idn) && (l2 > 0.f) && isfinite(l2);
-                if (ok_step) {
-                    const float il = __frsqrt_rn(l2);
-                    cnx = mx * il; cny = my * il; cnz = mz * il;
-                }
-            }
-            if (!ok_step) {
-                flags |= F_REJECTED;
-                if (lm) lam *= 10.f;
-                continue;
-            }
-            id_cand = idn; nx_cand = cnx; ny_cand = cny; nz_cand = cnz;
-            have_cand = true;
             if (lm) {
                 // Levenberg-Marquardt: accept the step unless the mean Huber
                 // cost per valid sample rises by more than kLmAcceptRise
                 // (relative; smaller rises are below the float noise of the
-                // cost sums, where the decision would be a coin toss).  All lanes of a
-                // surfel take the same branches, so the row reductions below
-                // see every lane of the surfel.
-                const float cc = nx_cand * rsx + ny_cand * rsy + nz_cand;
-                if (fabsf(cc) < 1e-6f) {             // candidate plane contains r_s
-                    flags |= F_REJECTED;
-                    lam *= 10.f;
-                    continue;
+                // cost sums, where the decision would be a coin toss).
+                float inv_cc = 0.f;
+                bool cand_ok = cand;
+                if (owner && cand) {
+                    const float cc = nx_c * rsx + ny_c * rsy + nz_c;
+                    if (fabsf(cc) < 1e-6f) {             // candidate plane contains r_s
+                        flags |= F_REJECTED;
+                        lam *= 10.f;
+                        cand_ok = false;
+                    }
+                    inv_cc = rcp_fast(cc);
                 }
-                const float sig = (nx_cand * drx + ny_cand * dry) * rcp_fast(cc);
-                const float idu_c = fmaf(id_cand, sig, id_cand);
-                float cst2 = 0.f;
-                int nv2l = 0;
-                frame_cost<T>(pc, fr, nf, dxp, dyp, idu_c, idu_c > 0.f, pitch_b, img_bytes, wm1, hm1,
-                              ikf, hk, img_scale, cst2, nv2l);
-                const float cost2 = group_sum<LANES>(cst2);
-                const int nv2 = group_sum<LANES>(nv2l);
-                if (nv2 < 3 || !(cost2 * (float)nv <= cost_here * (float)nv2 * (1.f + kLmAcceptRise))) {
-                    lam *= 10.f;
-                    continue;
+                if (owner) {
+                    float* o = lst + own * ST_WORDS;
+                    o[ST_ID] = id_c; o[ST_NX] = nx_c; o[ST_NY] = ny_c; o[ST_NZ] = nz_c;
+                    o[ST_INVC] = inv_cc;
+                    o[ST_ALIVE] = cand_ok ? 1.f : 0.f;
                 }
-                lam = fmaxf(lam * 0.1f, 1e-9f);
+                wave_sync();
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const float* st = lst + (k * SLOTS + r) * ST_WORDS;
+                    const float4 sa = *(const float4*)(st + 0);
+                    const float inv_c = st[ST_INVC];
+                    const bool calive = st[ST_ALIVE] != 0.f;
+                    const float sig = (sa.y * drx + sa.z * dry) * inv_c;
+                    const float idu_c = fmaf(sa.x, sig, sa.x);
+                    const int tx = it0x + (k % G.gx) * TX + r % TX, ty = it0y + (k / G.gx) * TY + r / TX;
+                    const float bdx = (float)(S * tx + px - bpx) - 0.5f * (float)(G.ab * S - 1);
+                    const float bdy = (float)(S * ty + py - bpy) - 0.5f * (float)(G.ab * S - 1);
+                    float cst2 = 0.f;
+                    int nv2l = 0;
+                    frame_cost<T>(pairs, fr, nf, bdx, bdy, idu_c, calive && (idu_c > 0.f), pitch_b,
+                                  img_bytes, wm1, hm1, ikf[k], hk, img_scale, cst2, nv2l);
+                    const float c2 = group_sum<LANES>(cst2);
+                    const int n2 = group_sum<LANES>(nv2l);
+                    if (p == 0) {
+                        float* o = lsm + (k * SLOTS + r) * SM_WORDS;
+                        o[SM_COST] = c2;
+                        o[SM_NV] = __int_as_float(n2);
+                    }
+                }
+                wave_sync();
+                if (owner && cand_ok) {
+                    const float* sm = lsm + own * SM_WORDS;
+                    const float cost2 = sm[SM_COST];
+                    const int nv2 = __float_as_int(sm[SM_NV]);
+                    if (nv2 < 3 ||
+                        !(cost2 * (float)nv <= cost_here * (float)nv2 * (1.f + kLmAcceptRise))) {
+                        lam *= 10.f;
+                        cand_ok = false;
+                    } else {
+                        lam = fmaxf(lam * 0.1f, 1e-9f);
+                    }
+                }
+                cand = cand_ok;
             }
-            id = id_cand;
-            nx = nx_cand; ny = ny_cand; nz = nz_cand;
-            updated = true;
+            if (owner && cand) {
+                id = id_c;
+                nx = nx_c; ny = ny_c; nz = nz_c;
+                updated = true;
+            }
         }
-        if (tile_ok && p == 0) {
-            s_id[sidx] = id;
-            s_nx[sidx] = nx; s_ny[sidx] = ny; s_nz[sidx] = nz;
-            s_flags[sidx] = flags;
-            ((gmut<float>)K->cost)[sidx] = iters > 0 ? cost_out : 0.f;
-            ((gmut<uint32_t>)K->nvalid)[sidx] = (uint32_t)(iters > 0 ? nv_out : 0);
-            if (updated) ((gmut<uint32_t>)K->last_update)[sidx] = stamp;
+        if (own_ok) {
+            ((gmut<float>)Kd->inv_depth)[sidx] = id;
+            ((gmut<float>)Kd->nx)[sidx] = nx;
+            ((gmut<float>)Kd->ny)[sidx] = ny;
+            ((gmut<float>)Kd->nz)[sidx] = nz;
+            ((gmut<uint32_t>)Kd->flags)[sidx] = flags;
+            ((gmut<float>)Kd->cost)[sidx] = iters > 0 ? cost_out : 0.f;
+            ((gmut<uint32_t>)Kd->nvalid)[sidx] = (uint32_t)(iters > 0 ? nv_out : 0);
+            if (updated) ((gmut<uint32_t>)Kd->last_update)[sidx] = stamp;
         }
     }
 }
@@ -962,23 +1112,33 @@ hipError_t launch_quantize(const float* src, int src_pitch, void* dst, int dst_p
     return hipGetLastError();
 }
 
-template <typename T, int S, int TX, int TY>
+template <typename T, int S, int TX, int TY, int K>
 static void* gn_ptr() {
-    return (void*)&gn_kernel<T, S, TX, TY>;
+    return (void*)&gn_kernel<T, S, TX, TY, K>;
+}
+
+template <typename T, int S, int TX, int TY>
+static void* gn_pick_groups(int groups) {
+    if (groups == 1) return gn_ptr<T, S, TX, TY, 1>();
+    if (groups == 2) return gn_ptr<T, S, TX, TY, 2>();
+    if (groups == 4) return gn_ptr<T, S, TX, TY, 4>();
+    return nullptr;
+}
+
+template <typename T>
+static void* gn_pick(const GnVariant& v) {
+    if (v.patch == 8 && v.tiles_x == 1 && v.tiles_y == 1) return gn_pick_groups<T, 8, 1, 1>(v.groups);
+    if (v.patch == 4 && v.tiles_x == 4 && v.tiles_y == 1) return gn_pick_groups<T, 4, 4, 1>(v.groups);
+    if (v.patch == 4 && v.tiles_x == 2 && v.tiles_y == 2) return gn_pick_groups<T, 4, 2, 2>(v.groups);
+    if (v.patch == 4 && v.tiles_x == 1 && v.tiles_y == 4) return gn_pick_groups<T, 4, 1, 4>(v.groups);
+    return nullptr;
 }
 
 static void* gn_select(const GnVariant& v) {
     if (v.lds) return nullptr;
-#define SGN_PICK(T)                                                              \
-    if (v.patch == 8 && v.tiles_x == 1 && v.tiles_y == 1) return gn_ptr<T, 8, 1, 1>(); \
-    if (v.patch == 4 && v.tiles_x == 4 && v.tiles_y == 1) return gn_ptr<T, 4, 4, 1>(); \
-    if (v.patch == 4 && v.tiles_x == 2 && v.tiles_y == 2) return gn_ptr<T, 4, 2, 2>(); \
-    if (v.patch == 4 && v.tiles_x == 1 && v.tiles_y == 4) return gn_ptr<T, 4, 1, 4>(); \
-    return nullptr;
-    if (v.dtype == 0) { SGN_PICK(float) }
-    if (v.dtype == 1) { SGN_PICK(_Float16) }
-    if (v.dtype == 2) { SGN_PICK(uint8_t) }
-#undef SGN_PICK
+    if (v.dtype == 0) return gn_pick<float>(v);
+    if (v.dtype == 1) return gn_pick<_Float16>(v);
+    if (v.dtype == 2) return gn_pick<uint8_t>(v);
     return nullptr;
 }
 

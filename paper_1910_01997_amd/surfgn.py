@@ -78,7 +78,8 @@ class sgn_params(C.Structure):
 
 class sgn_plan(C.Structure):
     _fields_ = [("tiles_x", C.c_int32), ("tiles_y", C.c_int32), ("persistent", C.c_int32),
-                ("waves_per_cu", C.c_int32), ("lds_stage", C.c_int32), ("xcd_queues", C.c_int32)]
+                ("waves_per_cu", C.c_int32), ("lds_stage", C.c_int32), ("xcd_queues", C.c_int32),
+                ("groups", C.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -321,8 +322,9 @@ def params(iters=15, huber_k=9.0 / 255.0, kappa_fp64=1e6, depth_only=False, beta
                       float(beta_r), int(stamp), float(lm_lambda))
 
 
-def plan(tiles_x=0, tiles_y=0, persistent=1, waves_per_cu=0, lds_stage=0, xcd_queues=1) -> sgn_plan:
-    return sgn_plan(tiles_x, tiles_y, persistent, waves_per_cu, lds_stage, xcd_queues)
+def plan(tiles_x=0, tiles_y=0, persistent=1, waves_per_cu=0, lds_stage=0, xcd_queues=1,
+         groups=0) -> sgn_plan:
+    return sgn_plan(tiles_x, tiles_y, persistent, waves_per_cu, lds_stage, xcd_queues, groups)
 
 
 class Context:
