@@ -224,6 +224,32 @@ sgn_status sgn_optimize_batch(sgn_ctx* ctx, const sgn_batch_item* items, int32_t
 sgn_status sgn_autotune(sgn_ctx* ctx, const sgn_batch_item* sample, int32_t n_items,
                         const sgn_params* params, sgn_plan* out);
 
+/* A keyframe's surfel grid for re-gridding: intrinsics, image size and tile
+ * edge S (4 or 8); the grid is (width / S) x (height / S) tiles. */
+typedef struct {
+    sgn_intrinsics K;
+    int32_t width, height, patch;
+} sgn_grid;
+
+/* Surfel reference-frame change (Eq. 10) and re-gridding into the tiles of
+ * another keyframe whose pose is X_dst = R X_src + t (pose, host memory).
+ * A usable source surfel (no DEGENERATE or UNINIT flag, inv_depth > 0) moves
+ * to p' = R (r_s / id_s) + t with normal n' = R n and lands in the
+ * destination pixel nearest to pi(K_dst p'), hence in that pixel's tile.  In
+ * each destination tile the closest landed surfel wins (largest 1/p'_z; ties
+ * to the lower source index) and its plane is re-expressed at the tile's
+ * centre ray by Eq. 3.  Tiles that receive nothing get id 0, n (0, 0, -1),
+ * the UNINIT flag and dst_is_new = 1, ready for sgn_init_from_neighbours.
+ * Landing decisions are taken in double.  src, dst: device surfel arrays of
+ * the two grids (all fields written for dst; cost and nvalid are zeroed,
+ * last_update is the winner's).  dst_is_new: device [dst tiles];
+ * dst_src_index: device [dst tiles] or NULL (winning source index or -1).
+ * The context keeps a scratch buffer of 12 bytes per destination tile,
+ * allocated on first use and grown as needed; src and dst must not overlap. */
+sgn_status sgn_transfer_surfels(sgn_ctx* ctx, const sgn_grid* src_grid, const sgn_surfels* src,
+                                const sgn_pose* pose, const sgn_grid* dst_grid, sgn_surfels* dst,
+                                uint8_t* dst_is_new, int32_t* dst_src_index);
+
 /* Convert a float image (device, src_pitch elements per row) to dst->dtype
  * storage at dst->data: F16 with round-to-nearest-even, or U8 as
  * round(clamp(v / dst->scale, 0, 255)). */

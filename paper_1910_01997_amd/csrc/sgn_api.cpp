@@ -71,6 +71,9 @@ struct sgn_ctx {
     // graphs
     bool use_graphs = true;
     std::map<GraphKey, hipGraphExec_t> graphs;
+    // re-gridding scratch (12 bytes per destination tile, grown on demand)
+    void* regrid_scratch = nullptr;
+    size_t regrid_cap = 0;
 };
 
 namespace {
@@ -499,6 +502,7 @@ sgn_status sgn_destroy(sgn_ctx* c) {
     if (c->counters) hipFree(c->counters);
     if (c->gn_start) hipEventDestroy(c->gn_start);
     if (c->gn_end) hipEventDestroy(c->gn_end);
+    if (c->regrid_scratch) hipFree(c->regrid_scratch);
     delete c;
     return SGN_OK;
 }
@@ -579,6 +583,64 @@ sgn_status sgn_quantize(sgn_ctx* c, const float* src, int32_t src_pitch, const s
     hipError_t e = launch_quantize(src, src_pitch, const_cast<void*>(dst->data), dst->pitch, dst->width,
                                    dst->height, dst->dtype, dst->scale, c->stream);
     if (e != hipSuccess) return hip_fail(e, "quantize launch");
+    return SGN_OK;
+}
+
+sgn_status sgn_transfer_surfels(sgn_ctx* c, const sgn_grid* src_grid, const sgn_surfels* src,
+                                const sgn_pose* pose, const sgn_grid* dst_grid, sgn_surfels* dst,
+                                uint8_t* dst_is_new, int32_t* dst_src_index) {
+    if (!c || !src_grid || !src || !pose || !dst_grid || !dst || !dst_is_new)
+        return fail(SGN_E_INVALID, "null argument");
+    for (const sgn_grid* g : {src_grid, dst_grid}) {
+        if (g->patch != 4 && g->patch != 8) return fail(SGN_E_INVALID, "patch must be 4 or 8");
+        if (g->width < g->patch || g->height < g->patch || g->width > 16384 || g->height > 16384)
+            return fail(SGN_E_INVALID, "grid size out of range");
+        if (!(g->K.fx > 0.0) || !(g->K.fy > 0.0) || !std::isfinite(g->K.cx) || !std::isfinite(g->K.cy))
+            return fail(SGN_E_INVALID, "bad intrinsics");
+    }
+    sgn_status st = check_surfels(src);
+    if (st) return st;
+    st = check_surfels(dst);
+    if (st) return st;
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(pose->R[i])) return fail(SGN_E_INVALID, "pose is not finite");
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(pose->t[i])) return fail(SGN_E_INVALID, "pose is not finite");
+    SGN_HIP(hipSetDevice(c->device));
+    const size_t n_dst = (size_t)(dst_grid->width / dst_grid->patch) * (dst_grid->height / dst_grid->patch);
+    const size_t need = n_dst * (sizeof(unsigned long long) + sizeof(int32_t));
+    if (need > c->regrid_cap) {
+        if (c->regrid_scratch) {
+            SGN_HIP(hipStreamSynchronize(c->stream));
+            SGN_HIP(hipFree(c->regrid_scratch));
+            c->regrid_scratch = nullptr;
+            c->regrid_cap = 0;
+        }
+        if (hipMalloc(&c->regrid_scratch, need) != hipSuccess)
+            return fail(SGN_E_NOMEM, "re-gridding scratch allocation failed");
+        c->regrid_cap = need;
+    }
+    RegridArgs a{};
+    auto conv = [](const sgn_surfels* x) {
+        return RegridSurfels{x->inv_depth, x->nx, x->ny, x->nz, x->flags, x->cost, x->nvalid,
+                             x->last_update};
+    };
+    a.src = conv(src);
+    a.dst = conv(dst);
+    a.src_K[0] = src_grid->K.fx; a.src_K[1] = src_grid->K.fy; a.src_K[2] = src_grid->K.cx;
+    a.src_K[3] = src_grid->K.cy;
+    a.dst_K[0] = dst_grid->K.fx; a.dst_K[1] = dst_grid->K.fy; a.dst_K[2] = dst_grid->K.cx;
+    a.dst_K[3] = dst_grid->K.cy;
+    for (int i = 0; i < 9; ++i) a.R[i] = pose->R[i];
+    for (int i = 0; i < 3; ++i) a.t[i] = pose->t[i];
+    a.src_w = src_grid->width; a.src_h = src_grid->height; a.src_patch = src_grid->patch;
+    a.dst_w = dst_grid->width; a.dst_h = dst_grid->height; a.dst_patch = dst_grid->patch;
+    a.best = (unsigned long long*)c->regrid_scratch;
+    a.win = (int32_t*)((char*)c->regrid_scratch + n_dst * sizeof(unsigned long long));
+    a.is_new = dst_is_new;
+    a.src_index = dst_src_index;
+    hipError_t e = launch_regrid(a, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "re-gridding launch");
     return SGN_OK;
 }
 

@@ -111,6 +111,29 @@ constexpr ItemGeo item_geo(int S, int TX, int TY, int K) {
     return ItemGeo{ab, gx, gy, ix, iy, (ab / ix) * (ab / iy)};
 }
 
+// Arguments of the re-gridding kernels (Eq. 10).  Surfel arrays are device
+// memory; best/win are scratch of one entry per destination tile.
+struct RegridSurfels {
+    float* inv_depth;
+    float* nx;
+    float* ny;
+    float* nz;
+    uint32_t* flags;
+    float* cost;
+    uint32_t* nvalid;
+    uint32_t* last_update;
+};
+struct RegridArgs {
+    RegridSurfels src, dst;
+    double src_K[4], dst_K[4];   // fx, fy, cx, cy
+    double R[9], t[3];           // X_dst = R X_src + t
+    int32_t src_w, src_h, src_patch, dst_w, dst_h, dst_patch;
+    unsigned long long* best;    // closest landing per destination tile (bits of 1/p'_z)
+    int32_t* win;                // winning source index per destination tile
+    uint8_t* is_new;
+    int32_t* src_index;          // may be null
+};
+
 // Launchers implemented in sgn_kernels.hip.  All return hipError_t of the
 // launch.
 hipError_t launch_setup(const BatchHeader* hdr, uint32_t* counters, int n_frames_cap,
@@ -119,6 +142,7 @@ hipError_t launch_init(const BatchHeader* hdr, int grid, hipStream_t s);
 hipError_t launch_render(const BatchHeader* hdr, int grid, hipStream_t s);
 hipError_t launch_gn(const GnVariant& v, const BatchHeader* hdr, uint32_t* counters,
                      int persistent, int grid_blocks, hipStream_t s);
+hipError_t launch_regrid(const RegridArgs& a, hipStream_t s);
 hipError_t launch_quantize(const float* src, int src_pitch, void* dst, int dst_pitch,
                            int width, int height, int dtype, float scale, hipStream_t s);
 // Workgroups of 256 threads of the chosen GN variant that fit on one CU.

@@ -28,6 +28,7 @@
 // so a surfel's result does not depend on where it sits in a batch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "sgn_internal.h"
@@ -1061,6 +1062,116 @@ __global__ void render_kernel(const BatchHeader* __restrict__ hdr_) {
         }
         (void)H;
     }
+}
+
+// ----------------------------------------------------------- regrid kernels --
+
+// Surfel reference-frame change (Eq. 10) and re-gridding into the tiles of
+// another keyframe.  Every landing decision (destination tile, closest
+// surfel) is taken in double with a fixed operation order and no
+// contraction, so it is the same decision the plain double definition takes.
+struct Land {
+    double idp, rp0, rp1, np0, np1, np2;
+    int tile;
+};
+
+__device__ __forceinline__ bool regrid_land(const RegridArgs& a, int i, Land& L) {
+#pragma clang fp contract(off)
+    const int S0 = a.src_patch, gw0 = a.src_w / S0;
+    if (a.src.flags[i] & (F_DEGENERATE | F_UNINIT)) return false;
+    const double id = (double)a.src.inv_depth[i];
+    if (!(id > 0.0) || !isfinite(id)) return false;
+    const double usx = S0 * (i % gw0) + 0.5 * (S0 - 1), usy = S0 * (i / gw0) + 0.5 * (S0 - 1);
+    const double rs0 = (usx - a.src_K[2]) / a.src_K[0], rs1 = (usy - a.src_K[3]) / a.src_K[1];
+    const double p00 = rs0 / id, p01 = rs1 / id, p02 = 1.0 / id;          // Eq. 1
+    const double n0 = a.src.nx[i], n1 = a.src.ny[i], n2 = a.src.nz[i];
+    const double* R = a.R;
+    const double p10 = R[0] * p00 + R[1] * p01 + R[2] * p02 + a.t[0];
+    const double p11 = R[3] * p00 + R[4] * p01 + R[5] * p02 + a.t[1];
+    const double p12 = R[6] * p00 + R[7] * p01 + R[8] * p02 + a.t[2];
+    L.np0 = R[0] * n0 + R[1] * n1 + R[2] * n2;
+    L.np1 = R[3] * n0 + R[4] * n1 + R[5] * n2;
+    L.np2 = R[6] * n0 + R[7] * n1 + R[8] * n2;
+    if (!(p12 > 0.0)) return false;
+    L.rp0 = p10 / p12;
+    L.rp1 = p11 / p12;
+    const double ux = a.dst_K[0] * L.rp0 + a.dst_K[2], uy = a.dst_K[1] * L.rp1 + a.dst_K[3];
+    const double px = floor(ux + 0.5), py = floor(uy + 0.5);          // nearest pixel
+    const int S1 = a.dst_patch, gw1 = a.dst_w / S1, gh1 = a.dst_h / S1;
+    if (!(px >= 0.0 && px < (double)(gw1 * S1) && py >= 0.0 && py < (double)(gh1 * S1))) return false;
+    L.tile = ((int)py / S1) * gw1 + (int)px / S1;
+    L.idp = 1.0 / p12;
+    return true;
+}
+
+__global__ void regrid_clear_kernel(RegridArgs a) {
+    const int n = (a.dst_w / a.dst_patch) * (a.dst_h / a.dst_patch);
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+        a.best[j] = 0ull;
+        a.win[j] = 0x7fffffff;
+    }
+}
+
+// pass 0: closest landing per tile (1/p'_z > 0, so its bits order like the
+// value); pass 1: the lowest source index among the closest
+__global__ void regrid_scatter_kernel(RegridArgs a, int pass) {
+    const int n = (a.src_w / a.src_patch) * (a.src_h / a.src_patch);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        Land L;
+        if (!regrid_land(a, i, L)) continue;
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(L.idp);
+        if (pass == 0)
+            atomicMax(&a.best[L.tile], bits);
+        else if (a.best[L.tile] == bits)
+            atomicMin(&a.win[L.tile], i);
+    }
+}
+
+__global__ void regrid_gather_kernel(RegridArgs a) {
+#pragma clang fp contract(off)
+    const int S1 = a.dst_patch, gw1 = a.dst_w / S1, gh1 = a.dst_h / S1;
+    const int n = gw1 * gh1;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+        const int w = a.win[j];
+        bool ok = false;
+        double idt = 0.0, t0 = 0.0, t1 = 0.0, t2 = -1.0;
+        Land L;
+        if (w != 0x7fffffff && regrid_land(a, w, L)) {
+            const double rt0 = (S1 * (j % gw1) + 0.5 * (S1 - 1) - a.dst_K[2]) / a.dst_K[0];
+            const double rt1 = (S1 * (j / gw1) + 0.5 * (S1 - 1) - a.dst_K[3]) / a.dst_K[1];
+            const double c1 = L.np0 * L.rp0 + L.np1 * L.rp1 + L.np2 * 1.0;
+            const double ct = L.np0 * rt0 + L.np1 * rt1 + L.np2 * 1.0;
+            if (fabs(c1) >= 1e-6 && fabs(ct) >= 1e-6) {
+                idt = L.idp * ct / c1;                    // Eq. 3 of the moved plane at r_t
+                const double l = sqrt(L.np0 * L.np0 + L.np1 * L.np1 + L.np2 * L.np2);
+                if (idt > 0.0 && isfinite(idt) && l > 0.0 && isfinite(l)) {
+                    t0 = L.np0 / l; t1 = L.np1 / l; t2 = L.np2 / l;
+                    ok = true;
+                }
+            }
+        }
+        a.dst.inv_depth[j] = ok ? (float)idt : 0.f;
+        a.dst.nx[j] = ok ? (float)t0 : 0.f;
+        a.dst.ny[j] = ok ? (float)t1 : 0.f;
+        a.dst.nz[j] = ok ? (float)t2 : -1.f;
+        a.dst.flags[j] = ok ? 0u : F_UNINIT;
+        a.dst.cost[j] = 0.f;
+        a.dst.nvalid[j] = 0u;
+        a.dst.last_update[j] = ok ? a.src.last_update[w] : 0u;
+        a.is_new[j] = ok ? 0 : 1;
+        if (a.src_index) a.src_index[j] = ok ? w : -1;
+    }
+}
+
+hipError_t launch_regrid(const RegridArgs& a, hipStream_t s) {
+    const int n_src = (a.src_w / a.src_patch) * (a.src_h / a.src_patch);
+    const int n_dst = (a.dst_w / a.dst_patch) * (a.dst_h / a.dst_patch);
+    auto blocks = [](int n) { return std::max(1, std::min(4096, (n + 255) / 256)); };
+    hipLaunchKernelGGL(regrid_clear_kernel, dim3(blocks(n_dst)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(regrid_scatter_kernel, dim3(blocks(n_src)), dim3(256), 0, s, a, 0);
+    hipLaunchKernelGGL(regrid_scatter_kernel, dim3(blocks(n_src)), dim3(256), 0, s, a, 1);
+    hipLaunchKernelGGL(regrid_gather_kernel, dim3(blocks(n_dst)), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 // --------------------------------------------------------- quantize kernel --

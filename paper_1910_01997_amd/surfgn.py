@@ -36,7 +36,7 @@ EXPORTED = [
     "sgn_create", "sgn_destroy", "sgn_set_stream", "sgn_init_from_neighbours",
     "sgn_optimize_keyframe", "sgn_render_inverse_depth", "sgn_optimize_batch", "sgn_autotune",
     "sgn_quantize", "sgn_last_kernel_ms", "sgn_device_info", "sgn_status_str", "sgn_last_error",
-    "sgn_version",
+    "sgn_version", "sgn_transfer_surfels",
 ]
 
 
@@ -62,6 +62,11 @@ class sgn_image(C.Structure):
 class sgn_keyframe(C.Structure):
     _fields_ = [("kf", sgn_image), ("nbr", C.POINTER(sgn_image)), ("pose", C.POINTER(sgn_pose)),
                 ("n_nbr", C.c_int32), ("K", sgn_intrinsics), ("patch", C.c_int32)]
+
+
+class sgn_grid(C.Structure):
+    _fields_ = [("K", sgn_intrinsics), ("width", C.c_int32), ("height", C.c_int32),
+                ("patch", C.c_int32)]
 
 
 class sgn_surfels(C.Structure):
@@ -133,6 +138,10 @@ def lib():
                                    C.POINTER(sgn_plan)]
         L.sgn_quantize.restype = st
         L.sgn_quantize.argtypes = [vp, vp, C.c_int32, C.POINTER(sgn_image)]
+        L.sgn_transfer_surfels.restype = st
+        L.sgn_transfer_surfels.argtypes = [vp, C.POINTER(sgn_grid), C.POINTER(sgn_surfels),
+                                           C.POINTER(sgn_pose), C.POINTER(sgn_grid),
+                                           C.POINTER(sgn_surfels), vp, vp]
         L.sgn_last_kernel_ms.restype = st
         L.sgn_last_kernel_ms.argtypes = [vp, C.POINTER(C.c_float)]
         L.sgn_device_info.restype = st
@@ -205,6 +214,20 @@ def sgn_autotune(ctx, items, n: int, params: sgn_params) -> sgn_plan:
 def sgn_quantize(ctx, src_ptr: int, src_pitch: int, dst: sgn_image):
     check(lib().sgn_quantize(C.c_void_p(ctx), C.c_void_p(src_ptr), int(src_pitch), C.byref(dst)),
           "sgn_quantize")
+
+
+def sgn_transfer_surfels(ctx, src_grid: sgn_grid, src: sgn_surfels, pose: sgn_pose,
+                         dst_grid: sgn_grid, dst: sgn_surfels, dst_is_new_ptr: int,
+                         dst_src_index_ptr: Optional[int] = None):
+    check(lib().sgn_transfer_surfels(C.c_void_p(ctx), C.byref(src_grid), C.byref(src),
+                                     C.byref(pose), C.byref(dst_grid), C.byref(dst),
+                                     C.c_void_p(dst_is_new_ptr),
+                                     C.c_void_p(dst_src_index_ptr) if dst_src_index_ptr else None),
+          "sgn_transfer_surfels")
+
+
+def grid_of(K, width: int, height: int, patch: int) -> sgn_grid:
+    return sgn_grid(sgn_intrinsics(*[float(v) for v in K]), int(width), int(height), int(patch))
 
 
 def sgn_last_kernel_ms(ctx) -> float:

@@ -54,8 +54,9 @@ def test_batch_equals_plain_bitwise_and_plans_agree(ctx):
         engine.update_plain(ctx, d, prm)
         torch.cuda.synchronize()
         ref.append((d.state.to_host(), d.inv_depth_out.cpu().numpy()))
-    plans = [None, sg.plan(4, 1, 1, 0, 0, 1), sg.plan(2, 2, 1, 0, 0, 1), sg.plan(1, 4, 1, 0, 0, 0),
-             sg.plan(2, 2, 0, 0, 0, 0)]
+    plans = [None, sg.plan(4, 1, 1, 0, 0, 1, groups=1), sg.plan(2, 2, 1, 0, 0, 1, groups=2),
+             sg.plan(1, 4, 1, 0, 0, 0, groups=4), sg.plan(2, 2, 0, 0, 0, 0, groups=1),
+             sg.plan(4, 1, 0, 0, 0, 0, groups=4)]
     for pl in plans:
         ds = [engine.DeviceKeyframe.from_scene(ctx, k) for k in kfs]
         engine.update_batch(ctx, ds, prm, pl)

@@ -1,0 +1,125 @@
+"""Surfel reference-frame change (Eq. 10) and re-gridding on the device,
+through the C ABI, against the FP64 oracle: the winning source surfel of
+every destination tile and the empty tiles must be identical (both sides
+take the landing decisions in double), the re-expressed planes equal to
+float rounding."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from tests.helpers import random_unit_cap, rot
+from tests.parity import angle_deg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_01997_amd import surfgn as sg
+    c = sg.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _run(ctx, src_grid, ids, ns, flags, last, R, t, dst_grid):
+    from paper_1910_01997_amd import surfgn as sg
+    K0, W0, H0, S0 = src_grid
+    K1, W1, H1, S1 = dst_grid
+    src = sg.SurfelState.from_arrays(ids, ns, flags=flags)
+    src.last_update.copy_(torch.as_tensor(last.astype(np.int32), device="cuda"))
+    m1 = (W1 // S1) * (H1 // S1)
+    dst = sg.SurfelState.from_arrays(np.full(m1, 7.0, np.float32), np.ones((m1, 3), np.float32))
+    is_new = torch.full((m1,), 9, dtype=torch.uint8, device="cuda")
+    win = torch.full((m1,), -5, dtype=torch.int32, device="cuda")
+    sg.sgn_transfer_surfels(ctx.handle, sg.grid_of(K0, W0, H0, S0), src.c, sg.pose_of(R, t),
+                            sg.grid_of(K1, W1, H1, S1), dst.c, is_new.data_ptr(), win.data_ptr())
+    torch.cuda.synchronize()
+    return dst.to_host(), is_new.cpu().numpy(), win.cpu().numpy()
+
+
+def _oracle(src_grid, ids, ns, flags, last, R, t, dst_grid):
+    st = oracle.new_state(np.asarray(ids, np.float32).astype(np.float64),
+                          np.asarray(ns, np.float32).astype(np.float64), flags)
+    st["last_update"][:] = last
+    return oracle.transfer_regrid(src_grid, st, R, t, dst_grid)
+
+
+def _check(dev, is_new, win, ref):
+    out, o_new, o_win, filled = ref
+    assert np.array_equal(win, o_win.reshape(-1)), "winning source surfels differ"
+    assert np.array_equal(is_new, o_new.reshape(-1).astype(np.uint8))
+    assert np.array_equal(dev["flags"], out["flags"].astype(np.uint32))
+    ok = o_win.reshape(-1) >= 0
+    assert int(ok.sum()) == filled
+    rel = np.abs(dev["inv_depth"][ok] / out["inv_depth"][ok] - 1)
+    ang = angle_deg(dev["n"][ok], np.stack([out["nx"], out["ny"], out["nz"]], 1)[ok])
+    assert rel.max() <= 2e-7 and ang.max() <= 2e-5, (rel.max(), ang.max())
+    assert np.all(dev["inv_depth"][~ok] == 0) and np.all(dev["n"][~ok] == [0, 0, -1])
+    assert np.array_equal(dev["last_update"][ok], out["last_update"][ok])
+    assert np.all(dev["cost"] == 0) and np.all(dev["nvalid"] == 0)
+
+
+@pytest.mark.parametrize("case", ["same_grid", "coarser_grid", "finer_grid"])
+def test_regrid_matches_oracle(ctx, case):
+    rng = np.random.default_rng({"same_grid": 5, "coarser_grid": 6, "finer_grid": 7}[case])
+    src_grid = ((600.0, 600.0, 320.0, 240.0), 640, 480, 4)
+    dst_grid = {"same_grid": src_grid,
+                "coarser_grid": ((420.0, 430.0, 200.0, 150.0), 400, 300, 8),
+                "finer_grid": ((1100.0, 1100.0, 640.0, 360.0), 1280, 720, 4)}[case]
+    print(f"case regrid {case}", flush=True)
+    m = (640 // 4) * (480 // 4)
+    ids = rng.uniform(0.25, 1.0, m).astype(np.float32)
+    ns = np.array([random_unit_cap(rng, 40) for _ in range(m)], np.float32)
+    flags = np.zeros(m, np.uint32)
+    flags[rng.choice(m, 200, replace=False)] = oracle.DEGENERATE
+    flags[rng.choice(m, 200, replace=False)] |= oracle.UNINIT
+    last = rng.integers(1, 1000, m).astype(np.uint32)
+    R = rot(rng.normal(size=3), math.radians(3))
+    t = np.array([0.05, -0.02, -0.06])
+    dev, is_new, win = _run(ctx, src_grid, ids, ns, flags, last, R, t, dst_grid)
+    ref = _oracle(src_grid, ids, ns, flags, last, R, t, dst_grid)
+    _check(dev, is_new, win, ref)
+
+
+def test_regrid_sideways_wall_and_occlusion(ctx):
+    """Exact constructions: a wall moved by whole tiles, and a near wall
+    sliding over a far one (the near one wins where both land)."""
+    K, W, H, S = (160.0, 160.0, 95.5, 31.5), 192, 64, 4
+    gw, gh = W // S, H // S
+    ids = np.tile(np.where(np.arange(gw) < gw // 2, 1.0, 0.25), gh).astype(np.float32)
+    ns = np.tile([0.0, 0.0, -1.0], (gw * gh, 1)).astype(np.float32)
+    flags = np.zeros(gw * gh, np.uint32)
+    last = np.ones(gw * gh, np.uint32)
+    t = np.array([8 * S / K[0], 0.0, 0.0])
+    print("case regrid occlusion", flush=True)
+    dev, is_new, win = _run(ctx, (K, W, H, S), ids, ns, flags, last, np.eye(3), t, (K, W, H, S))
+    ref = _oracle((K, W, H, S), ids, ns, flags, last, np.eye(3), t, (K, W, H, S))
+    _check(dev, is_new, win, ref)
+    w = win.reshape(gh, gw)
+    assert np.all(w[:, :8] == -1)
+    near = (w >= 0) & (w % gw < gw // 2)
+    assert near[:, gw // 2 + 2: gw // 2 + 8].all()
+
+
+def test_regrid_argument_errors(ctx):
+    from paper_1910_01997_amd import surfgn as sg
+    src = sg.SurfelState.from_arrays(np.ones(4, np.float32), np.tile([0, 0, -1.0], (4, 1)))
+    dst = src.clone()
+    nw = torch.zeros(4, dtype=torch.uint8, device="cuda")
+    g_ok = sg.grid_of((100.0, 100.0, 4.0, 4.0), 8, 8, 4)
+    g_bad = sg.grid_of((100.0, 100.0, 4.0, 4.0), 8, 8, 5)
+    pose = sg.pose_of(np.eye(3), np.zeros(3))
+    with pytest.raises(sg.SurfgnError):
+        sg.sgn_transfer_surfels(ctx.handle, g_bad, src.c, pose, g_ok, dst.c, nw.data_ptr())
+    with pytest.raises(sg.SurfgnError):
+        sg.sgn_transfer_surfels(ctx.handle, g_ok, src.c, pose, g_ok, dst.c, 0)
+    bad_pose = sg.pose_of(np.full((3, 3), np.nan), np.zeros(3))
+    with pytest.raises(sg.SurfgnError):
+        sg.sgn_transfer_surfels(ctx.handle, g_ok, src.c, bad_pose, g_ok, dst.c, nw.data_ptr())
