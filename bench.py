@@ -59,6 +59,10 @@ def parse():
                          "known traffic for scaling the HBM counters)")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of the Poisson serving trace (0: skip the serving leg)")
+    ap.add_argument("--serve-load-rate", type=float, default=3000.0,
+                    help="arrival rate of a second, saturating serving trace (req/s)")
+    ap.add_argument("--serve-load-seconds", type=float, default=2.0,
+                    help="length of the saturating trace (0: skip it)")
     return ap.parse_args()
 
 
@@ -182,6 +186,12 @@ def main():
         from paper_1910_01997_amd import serve
         serving = serve.serving_benchmark(n_streams=32, rate=200.0, duration=args.serve_seconds,
                                           warmup=1.0, storage=args.storage, iters=iters, log=log)
+        if args.serve_load_seconds > 0:
+            # the same streams under a load that keeps the device busy: here
+            # continuous batching has several requests to merge
+            serving["saturated"] = serve.serving_benchmark(
+                n_streams=32, rate=args.serve_load_rate, duration=args.serve_load_seconds,
+                warmup=0.5, storage=args.storage, iters=iters, log=log)
     out = {
         "metric": METRIC,
         "value": value,
