@@ -58,7 +58,7 @@ def test_workload0_plain_f32(ctx):
     print("case workload0 160x120 S=8 N=2 f32", flush=True)
     dk, dev = _plain(ctx, kf)
     res = check_parity(dk, dev, kf.init_id, kf.init_n, None, _oparams(kf.iters), label="w0")
-    assert_parity(res, label="w0", min_stable=1.0)
+    assert_parity(res, label="w0", min_stable=1.0, slack=0)
 
 
 def test_workload1_init_matches_oracle(ctx):
