@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -180,8 +181,9 @@ sgn_status check_params(const sgn_params* p) {
 
 sgn_plan default_plan(int patch) {
     sgn_plan p{};
+    // measured fastest on the 64-keyframe batch: 2x2 groups, four per item
     if (patch == 8) { p.tiles_x = 1; p.tiles_y = 1; }
-    else { p.tiles_x = 4; p.tiles_y = 1; }
+    else { p.tiles_x = 2; p.tiles_y = 2; }
     p.groups = 4;
     p.persistent = 1;
     p.waves_per_cu = 0;
@@ -697,6 +699,8 @@ sgn_status sgn_autotune(sgn_ctx* c, const sgn_batch_item* items, int32_t n, cons
                 }
     float best = 1e30f;
     sgn_plan best_plan = default_plan(patch);
+    const char* log_env = std::getenv("SGN_AUTOTUNE_LOG");    // set to 1: print every trial
+    const bool log = log_env && log_env[0] == '1';
     sgn_status result = SGN_OK;
     for (const sgn_plan& pl : cands) {
         GnVariant v{items[0].kf.kf.dtype, patch, pl.tiles_x, pl.tiles_y, pl.lds_stage, pl.groups};
@@ -711,6 +715,10 @@ sgn_status sgn_autotune(sgn_ctx* c, const sgn_batch_item* items, int32_t n, cons
             if (st != SGN_OK) { ok = false; result = st; break; }
             if (rep > 0) tot += ms;   // first run warms up (and captures the graph)
         }
+        if (log)
+            std::fprintf(stderr, "sgn_autotune: tiles %dx%d groups %d persistent %d xcd_queues %d: %s %.3f ms\n",
+                         pl.tiles_x, pl.tiles_y, pl.groups, pl.persistent, pl.xcd_queues,
+                         ok ? "mean" : "failed", ok ? tot / 2.f : 0.f);
         if (ok && tot < best) {
             best = tot;
             best_plan = pl;

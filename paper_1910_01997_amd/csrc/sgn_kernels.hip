@@ -114,6 +114,27 @@ __device__ __forceinline__ int group_sum(int x) {
     return x;
 }
 
+// Sums of two values over a surfel's lanes at once: even lanes end with the
+// sum of `ev`, odd lanes with the sum of `od`.  The first butterfly step
+// trades halves with the neighbour lane (each lane keeps the value it will
+// own and sends the other), so the remaining steps carry one value instead
+// of two.  The association of every sum is that of group_sum.
+template <int LANES>
+__device__ __forceinline__ float pair_sum(float ev, float od, bool odd) {
+#pragma clang fp contract(off)
+    const float keep = odd ? od : ev;
+    const float send = odd ? ev : od;
+    float x = keep + dpp_f<0xB1>(send);   // quad_perm [1,0,3,2]
+    x += dpp_f<0x4E>(x);                  // quad_perm [2,3,0,1]
+    x += dpp_f<0x141>(x);                 // row_half_mirror
+    x += dpp_f<0x140>(x);                 // row_mirror
+    if constexpr (LANES == 64) {
+        x += __shfl_xor(x, 16);
+        x += __shfl_xor(x, 32);
+    }
+    return x;
+}
+
 __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
 
 __device__ __forceinline__ int find_kf(cptr<KfDev> kfs, int n_kf, int item, int hint) {
@@ -783,35 +804,30 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                 else
                     frame_loop<T, false>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes, wm1,
                                          hm1, ikf[k], hk, img_scale, A, B, cst, nvl);
-                // J^T W J = sum_u A_u g g^T, J^T W r = sum_u B_u g (frame sum hoisted)
-                float h00, h01, h02, h11, h12, h22, v0, v1, v2;
-                int nv;
+                // J^T W J = sum_u A_u g g^T, J^T W r = sum_u B_u g (frame sum
+                // hoisted), reduced two at a time: lane 0 of the surfel ends
+                // with words 0, 2, 4, 6, 8 and lane 1 with words 1, 3, 5, 7, 9
+                // (the valid count as an exact float)
+                float s0, s1, s2, s3, s4;
                 {
                     // No FMA contraction: each butterfly step must be a plain
-                    // add of two rounded values so that the sums are
-                    // bitwise-identical on every lane of the surfel.
+                    // add of two rounded values so that the sums do not depend
+                    // on which lane forms them.
 #pragma clang fp contract(off)
+                    const bool odd = (p & 1) != 0;
                     const float ag0 = A * g0, ag1 = A * g1, ag2 = A * g2;
-                    h00 = group_sum<LANES>(ag0 * g0);
-                    h01 = group_sum<LANES>(ag0 * g1);
-                    h02 = group_sum<LANES>(ag0 * g2);
-                    h11 = group_sum<LANES>(ag1 * g1);
-                    h12 = group_sum<LANES>(ag1 * g2);
-                    h22 = group_sum<LANES>(ag2 * g2);
-                    v0 = group_sum<LANES>(B * g0);
-                    v1 = group_sum<LANES>(B * g1);
-                    v2 = group_sum<LANES>(B * g2);
-                    nv = group_sum<LANES>(nvl);
+                    s0 = pair_sum<LANES>(ag0 * g0, ag0 * g1, odd);     // H00 | H01
+                    s1 = pair_sum<LANES>(ag0 * g2, ag1 * g1, odd);     // H02 | H11
+                    s2 = pair_sum<LANES>(ag1 * g2, ag2 * g2, odd);     // H12 | H22
+                    s3 = pair_sum<LANES>(B * g0, B * g1, odd);         // b0  | b1
+                    s4 = pair_sum<LANES>(B * g2, (float)nvl, odd);     // b2  | nv
                 }
                 float cs = 0.f;
                 if (last || lm) cs = group_sum<LANES>(cst);
-                if (p == 0) {
-                    float* o = lsm + (k * SLOTS + r) * SM_WORDS;
-                    o[SM_H00] = h00; o[SM_H01] = h01; o[SM_H02] = h02;
-                    o[SM_H11] = h11; o[SM_H12] = h12; o[SM_H22] = h22;
-                    o[SM_B0] = v0; o[SM_B1] = v1; o[SM_B2] = v2;
-                    o[SM_NV] = __int_as_float(nv);
-                    o[SM_COST] = cs;
+                if (p < 2) {
+                    float* o = lsm + (k * SLOTS + r) * SM_WORDS + p;
+                    o[0] = s0; o[2] = s1; o[4] = s2; o[6] = s3; o[8] = s4;
+                    if (p == 0) o[SM_COST] = cs;
                 }
             }
             wave_sync();
@@ -824,7 +840,7 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                 const float H00 = sm[SM_H00], H01 = sm[SM_H01], H02 = sm[SM_H02];
                 const float H11 = sm[SM_H11], H12 = sm[SM_H12], H22 = sm[SM_H22];
                 const float bb0 = sm[SM_B0], bb1 = sm[SM_B1], bb2 = sm[SM_B2];
-                nv = __float_as_int(sm[SM_NV]);
+                nv = (int)sm[SM_NV];
                 cost_here = sm[SM_COST];
                 if (alive && last) cost_out = cost_here;
                 if (alive) {
