@@ -114,11 +114,13 @@ __device__ __forceinline__ int group_sum(int x) {
     return x;
 }
 
-// Sums of two values over a surfel's lanes at once: even lanes end with the
-// sum of `ev`, odd lanes with the sum of `od`.  The first butterfly step
-// trades halves with the neighbour lane (each lane keeps the value it will
-// own and sends the other), so the remaining steps carry one value instead
-// of two.  The association of every sum is that of group_sum.
+// Sums of two values over a surfel's lanes at once: lane 0 of the surfel
+// ends with the sum of `ev`, lane 1 with the sum of `od`.  The first
+// butterfly step trades halves with the neighbour lane (each lane keeps the
+// value it will own and sends the other), so the remaining steps carry one
+// value instead of two; they pair lanes of equal parity only (quad_perm,
+// then row rotations by 4 and 8).  Lanes 0 and 1 form their sums in a fixed
+// order that depends only on the surfel's pixels.
 template <int LANES>
 __device__ __forceinline__ float pair_sum(float ev, float od, bool odd) {
 #pragma clang fp contract(off)
@@ -126,8 +128,8 @@ __device__ __forceinline__ float pair_sum(float ev, float od, bool odd) {
     const float send = odd ? ev : od;
     float x = keep + dpp_f<0xB1>(send);   // quad_perm [1,0,3,2]
     x += dpp_f<0x4E>(x);                  // quad_perm [2,3,0,1]
-    x += dpp_f<0x141>(x);                 // row_half_mirror
-    x += dpp_f<0x140>(x);                 // row_mirror
+    x += dpp_f<0x124>(x);                 // row_ror:4
+    x += dpp_f<0x128>(x);                 // row_ror:8
     if constexpr (LANES == 64) {
         x += __shfl_xor(x, 16);
         x += __shfl_xor(x, 32);

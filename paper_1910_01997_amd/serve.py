@@ -290,6 +290,8 @@ class HipExecutor(Executor):
         self.ctxs = [sg.Context(0, stream=s) for s in self.tstreams]
         self.params = sg.params(iters=iters)
         self.plan = plan
+        self.small_plan = sg.plan(2, 2, 1, 0, 0, 1, groups=1)
+        self.small_batch_surfels = 200_000
         self.pinned_pool = pinned_pool
 
     def request_bytes(self, req: Request) -> int:
@@ -319,7 +321,13 @@ class HipExecutor(Executor):
                 items.append(it)
                 outs.append(view)
             arr = self.sg.batch_array(items)
-            self.sg.sgn_optimize_batch(self.ctxs[lane].handle, arr, len(items), self.params, self.plan)
+            plan = self.plan
+            if plan is None:
+                # a small batch cannot fill the device with four groups per
+                # work item: use one group per wavefront there
+                total = sum(self.streams[r.stream].dk.n_surfels for r in batch)
+                plan = self.small_plan if total < self.small_batch_surfels else None
+            self.sg.sgn_optimize_batch(self.ctxs[lane].handle, arr, len(items), self.params, plan)
             # responses: depth map and surfels copied to host memory
             results = []
             for r in batch:
@@ -354,6 +362,8 @@ class PlainExecutor(HipExecutor):
 
     def __init__(self, streams, iters: int = 15):
         super().__init__(streams, lanes=1, iters=iters)
+        # the single-keyframe plan: one group per wavefront, one wavefront per item
+        self.plain_plan = self.sg.plan(2, 2, 0, 0, 0, 0, groups=1)
 
     def launch(self, lane: int, batch: List[Request]):
         assert len(batch) == 1
@@ -375,7 +385,8 @@ class PlainExecutor(HipExecutor):
                 self.sg.sgn_init_from_neighbours(ctx.handle, view.c, dk.state.c, dk.is_new.data_ptr(),
                                                  self.params)
             cs.first = False
-            self.sg.sgn_optimize_keyframe(ctx.handle, view.c, dk.state.c, self.params)
+            self.sg.sgn_optimize_keyframe(ctx.handle, view.c, dk.state.c, self.params,
+                                          self.plain_plan)
             self.sg.sgn_render_inverse_depth(ctx.handle, view.c, dk.state.c, dk.inv_depth_out.data_ptr())
             depth = torch.empty(dk.inv_depth_out.shape, dtype=torch.float32, pin_memory=True)
             depth.copy_(dk.inv_depth_out, non_blocking=True)
