@@ -291,6 +291,7 @@ class HipExecutor(Executor):
         self.params = sg.params(iters=iters)
         self.plan = plan
         self.small_plan = sg.plan(2, 2, 1, 0, 0, 1, groups=1)
+        self.single_plan = sg.plan(2, 2, 0, 0, 0, 0, groups=1)
         self.small_batch_surfels = 200_000
         self.pinned_pool = pinned_pool
 
@@ -327,7 +328,18 @@ class HipExecutor(Executor):
                 # work item: use one group per wavefront there
                 total = sum(self.streams[r.stream].dk.n_surfels for r in batch)
                 plan = self.small_plan if total < self.small_batch_surfels else None
-            self.sg.sgn_optimize_batch(self.ctxs[lane].handle, arr, len(items), self.params, plan)
+            ctx = self.ctxs[lane].handle
+            if len(items) == 1:
+                # a lone request: the single-keyframe calls launch directly and
+                # skip the batch table (same results, bitwise)
+                it, view = items[0], outs[0]
+                dk = self.streams[batch[0].stream].dk
+                if it.is_new:
+                    self.sg.sgn_init_from_neighbours(ctx, view.c, dk.state.c, it.is_new, self.params)
+                self.sg.sgn_optimize_keyframe(ctx, view.c, dk.state.c, self.params, self.single_plan)
+                self.sg.sgn_render_inverse_depth(ctx, view.c, dk.state.c, dk.inv_depth_out.data_ptr())
+            else:
+                self.sg.sgn_optimize_batch(ctx, arr, len(items), self.params, plan)
             # responses: depth map and surfels copied to host memory
             results = []
             for r in batch:
