@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--storage", default="f16", choices=["f32", "f16", "u8"])
     ap.add_argument("--keyframes", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-precision-forms", action="store_true",
                     help="skip timing the GN kernel with the other image storages")
