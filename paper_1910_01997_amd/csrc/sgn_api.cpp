@@ -328,8 +328,8 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
         item_base += D.n_items;
         H->queues[D.queue].end = item_base;
         surfel_base += D.gw * D.gh;
-        if (D.inv_depth_out)
-            pixel_base += ((int64_t)D.width * D.height + kRenderRun - 1) / kRenderRun * kRenderRun;
+        if (D.inv_depth_out)     // render segments: rows x tile columns
+            pixel_base += (int64_t)D.height * ((D.width + D.patch - 1) / D.patch);
         any_init |= D.is_new != nullptr;
         any_render |= D.inv_depth_out != nullptr;
     }

@@ -13,7 +13,6 @@ constexpr int kWaveSize = 64;
 constexpr int kBlockThreads = 256;      // 4 wavefronts per workgroup
 constexpr int kNumCounters = 16;        // work-queue heads (one per XCD + spares)
 constexpr int kXcds = 8;
-constexpr int kRenderRun = 4;            // pixels per render thread (ranges padded to it)
 
 // Per-keyframe descriptor in device memory (one per batch item).
 struct KfDev {
@@ -32,7 +31,7 @@ struct KfDev {
     int32_t width, height, kf_pitch, n_nbr;
     int32_t gw, gh, frame_base, item_base;      // frames: [frame_base, frame_base + n_nbr)
     int32_t groups_x, n_items, surfel_base, queue;  // anchor blocks per row; work items
-    int64_t pixel_base;                          // prefix over rendered pixels
+    int64_t pixel_base;                          // prefix over render segments (row x tile column)
     int32_t patch, nbr_pitch_b;                   // neighbour-image row pitch in bytes
     double fx_d, fy_d, cx_d, cy_d;               // intrinsics as given (double)
     float fx, fy, cx, cy;                        // the same, rounded to float
@@ -63,7 +62,7 @@ struct BatchHeader {
     KfDev* kfs;
     FrameDev* frames;
     int32_t n_kf, n_frames, total_items, total_surfels;
-    int64_t total_pixels;
+    int64_t total_pixels;           // render segments of the batch
     int32_t iters;
     float huber_k;
     float kappa_fp64;

@@ -1016,69 +1016,79 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
 // ----------------------------------------------------------- render kernel --
 
 // Inverse Depth Calculation section: each pixel takes Eq. 3 of its surfel,
-// id_u = id_s (1 + sigma), sigma = n . (r_u - r_s) / (n . r_s).  Pixels are
-// numbered keyframe after keyframe (only keyframes with an output, each range
-// padded to a multiple of kRenderRun so that a run never spans two
-// keyframes); each thread walks one run of kRenderRun consecutive pixels.
+// id_u = id_s (1 + sigma), sigma = n . (r_u - r_s) / (n . r_s).  A thread
+// renders one segment: the up-to-S pixels of one image row that lie in one
+// tile column (segments past the grid write "no measurement"), so a surfel's
+// state is read once per segment.  Segments are numbered keyframe after
+// keyframe (only keyframes with an output).
 
 __global__ void render_kernel(const BatchHeader* __restrict__ hdr_) {
     const cptr<BatchHeader> hdr = (cptr<BatchHeader>)hdr_;
     const cptr<KfDev> kfs = (cptr<KfDev>)hdr->kfs;
     const int n_kf = hdr->n_kf;
-    const int64_t total = hdr->total_pixels;
+    const int64_t total = hdr->total_pixels;           // render segments
     int hint = 0;
-    for (int64_t g0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRenderRun; g0 < total;
-         g0 += (int64_t)gridDim.x * blockDim.x * kRenderRun) {
-        // keyframe of pixel g0 (fast path: the previous one)
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        // keyframe of segment g (fast path: the previous one)
         {
             const cptr<KfDev> kh = kfs + hint;
-            if (!(kh->inv_depth_out && g0 >= kh->pixel_base &&
-                  g0 < kh->pixel_base + (int64_t)kh->width * kh->height)) {
+            const int64_t nseg = (int64_t)kh->height * ((kh->width + kh->patch - 1) / kh->patch);
+            if (!(kh->inv_depth_out && g >= kh->pixel_base && g < kh->pixel_base + nseg)) {
+                // the last keyframe whose base is <= g owns it (keyframes
+                // without an output add no segments, so the next base is
+                // larger than g only past the owner)
                 int lo = 0, hi = n_kf - 1;
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
-                    if (kfs[mid].pixel_base <= g0) lo = mid; else hi = mid - 1;
+                    if (kfs[mid].pixel_base <= g) lo = mid; else hi = mid - 1;
                 }
                 hint = lo;
             }
         }
         const cptr<KfDev> K = kfs + hint;
-        const int W = K->width, H = K->height, S = K->patch;
-        const int npix = W * H;
-        const int o_first = (int)(g0 - K->pixel_base);
+        const int W = K->width, S = K->patch;
+        const int nsx = (W + S - 1) / S;
+        const int sg = (int)(g - K->pixel_base);
+        const int y = sg / nsx, tx = sg - y * nsx;
+        const int x0 = tx * S, ty = y / S;
         const float half = 0.5f * (float)(S - 1);
-        float* const out = K->inv_depth_out;
-        int32_t* const idx_out = K->index_out;
-        for (int j = 0; j < kRenderRun; ++j) {
-            const int o = o_first + j;
-            if (o >= npix) break;            // padding after the keyframe's last pixel
-            const int y = o / W, x = o - y * W;
-            const int tx = x / S, ty = y / S;
+        float* const out = K->inv_depth_out + (size_t)y * W + x0;
+        int32_t* const idx_out = K->index_out ? K->index_out + (size_t)y * W + x0 : nullptr;
+        bool ok = false;
+        int i = -1;
+        float id = 0.f, nx = 0.f, ny = 0.f, c = 1.f, usx = 0.f, usy = 0.f;
+        if (tx < K->gw && ty < K->gh) {
+            i = ty * K->gw + tx;
+            if (!(K->flags[i] & (F_DEGENERATE | F_UNINIT))) {
+                usx = (float)(S * tx) + half;
+                usy = (float)(S * ty) + half;
+                const float rsx = (usx - K->cx) / K->fx, rsy = (usy - K->cy) / K->fy;
+                nx = K->nx[i];
+                ny = K->ny[i];
+                const float nz = K->nz[i];
+                c = nx * rsx + ny * rsy + nz;
+                id = K->inv_depth[i];
+                ok = fabsf(c) >= 1e-6f;
+            }
+        }
+        const float dry = ((float)y - usy) / K->fy;
+        const int n_px = min(S, W - x0);
+        for (int j = 0; j < n_px; ++j) {
             float val = 0.f;
-            int idx = -1;
-            if (tx < K->gw && ty < K->gh) {
-                const int i = ty * K->gw + tx;
-                if (!(K->flags[i] & (F_DEGENERATE | F_UNINIT))) {
-                    const float usx = (float)(S * tx) + half, usy = (float)(S * ty) + half;
-                    const float rsx = (usx - K->cx) / K->fx, rsy = (usy - K->cy) / K->fy;
-                    const float nx = K->nx[i], ny = K->ny[i], nz = K->nz[i];
-                    const float c = nx * rsx + ny * rsy + nz;
-                    if (fabsf(c) >= 1e-6f) {
-                        const float drx = ((float)x - usx) / K->fx, dry = ((float)y - usy) / K->fy;
-                        const float id = K->inv_depth[i];
-                        const float sigma = (nx * drx + ny * dry) / c;
-                        const float idu = fmaf(id, sigma, id);
-                        if (idu > 0.f && isfinite(idu)) {
-                            val = idu;
-                            idx = i;
-                        }
-                    }
+            int who = -1;
+            if (ok) {
+                const float drx = ((float)(x0 + j) - usx) / K->fx;
+                const float sigma = (nx * drx + ny * dry) / c;
+                const float idu = fmaf(id, sigma, id);
+                if (idu > 0.f && isfinite(idu)) {
+                    val = idu;
+                    who = i;
                 }
             }
-            out[o] = val;
-            if (idx_out) idx_out[o] = idx;
+            out[j] = val;
+            if (idx_out) idx_out[j] = who;
         }
-        (void)H;
     }
 }
 

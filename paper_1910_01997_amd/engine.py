@@ -26,7 +26,7 @@ class DeviceKeyframe:
 
     def __init__(self, ctx: sg.Context, kf_image, nbr_images, R, t, K, patch: int,
                  init_id, init_n, is_new=None, storage: str = "f32", render: bool = True,
-                 index_map: bool = False, flags=None):
+                 index_map: bool = False, flags=None, u8_scale: float = U8_SCALE):
         dev = torch.device("cuda", ctx.device)
         self.ctx = ctx
         self.storage = storage
@@ -44,7 +44,7 @@ class DeviceKeyframe:
         else:
             code = STORAGE[storage]
             tdt = torch.float16 if storage == "f16" else torch.uint8
-            self.scale = 1.0 if storage == "f16" else U8_SCALE
+            self.scale = 1.0 if storage == "f16" else float(u8_scale)
             self.kf_img = torch.empty((self.height, self.width), dtype=tdt, device=dev)
             self.nbr_imgs = torch.empty((self.n_nbr, self.height, self.width), dtype=tdt, device=dev)
             for src, dst in [(kf32, self.kf_img)] + [(nb32[i], self.nbr_imgs[i]) for i in range(self.n_nbr)]:
@@ -63,10 +63,11 @@ class DeviceKeyframe:
                           if (render and index_map) else None)
 
     @classmethod
-    def from_scene(cls, ctx, kf, storage="f32", render=True, index_map=False, with_new=True):
+    def from_scene(cls, ctx, kf, storage="f32", render=True, index_map=False, with_new=True,
+                   u8_scale: float = U8_SCALE):
         return cls(ctx, kf.kf_image, kf.nbr_images, kf.R, kf.t, kf.K, kf.patch, kf.init_id,
                    kf.init_n, is_new=kf.is_new if (with_new and kf.is_new.any()) else None,
-                   storage=storage, render=render, index_map=index_map)
+                   storage=storage, render=render, index_map=index_map, u8_scale=u8_scale)
 
     @property
     def grid(self):
