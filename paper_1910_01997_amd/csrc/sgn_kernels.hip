@@ -243,7 +243,9 @@ __global__ void init_kernel(const BatchHeader* __restrict__ hdr) {
         const float rsx = (ux - K.cx) / K.fx, rsy = (uy - K.cy) / K.fy;
         const float br = hdr->beta_r > 0.f ? hdr->beta_r : (float)S;
         const float br2 = br * br;
-        const int reach = (int)ceilf(br / (float)S) + 1;
+        // a tile dx columns away has its nearest pixel at |dx| S - half from
+        // u_s: none beyond floor((br + half) / S) can be closer than br
+        const int reach = (int)floorf((br + half) / (float)S);
         float id_sum = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, rx = 0.f, ry = 0.f, rz = 0.f;
         int count = 0;
         for (int ny = ty - reach; ny <= ty + reach; ++ny) {

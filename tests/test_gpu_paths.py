@@ -197,6 +197,9 @@ def test_argument_errors_are_reported(ctx):
     # bad params
     assert L.sgn_optimize_keyframe(ctx.handle, d.view.c, d.state.c, sg.params(iters=-1), None) == sg.SGN_E_INVALID
     assert L.sgn_optimize_keyframe(ctx.handle, d.view.c, d.state.c, sg.params(huber_k=0.0), None) == sg.SGN_E_INVALID
+    # plans the kernel does not have: LDS-staged taps, 3 groups, 3x1 tiles
+    for pl in (sg.plan(2, 2, lds_stage=1, groups=4), sg.plan(2, 2, groups=3), sg.plan(3, 1, groups=1)):
+        assert L.sgn_optimize_keyframe(ctx.handle, d.view.c, d.state.c, prm, pl) == sg.SGN_E_UNSUPPORTED
     # nothing was enqueued: the state is untouched
     torch.cuda.synchronize()
     assert np.array_equal(d.state.to_host()["inv_depth"], kf.init_id.reshape(-1))

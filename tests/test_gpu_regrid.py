@@ -123,3 +123,68 @@ def test_regrid_argument_errors(ctx):
     bad_pose = sg.pose_of(np.full((3, 3), np.nan), np.zeros(3))
     with pytest.raises(sg.SurfgnError):
         sg.sgn_transfer_surfels(ctx.handle, g_ok, src.c, bad_pose, g_ok, dst.c, nw.data_ptr())
+
+
+def test_keyframe_switch_chain_matches_oracle(ctx):
+    """Optimise keyframe A, move its surfels into keyframe B (one of A's
+    neighbour views, with A and the other views as B's neighbours),
+    initialise B's empty tiles from their neighbours and optimise B: the
+    device chain against the oracle chain."""
+    import dataclasses
+    from paper_1910_01997_amd import engine
+    from paper_1910_01997_amd import surfgn as sg
+    from scenegen import make_keyframe, spec_for_config
+    from tests.parity import assert_parity, check_parity, oracle_keyframe
+
+    spec = dataclasses.replace(spec_for_config(1), width=256, height=192, n_rects=6, n_nbr=4,
+                               seed=41, half_new=False)
+    kf = make_keyframe(spec, device="cuda")
+    print("case keyframe switch 256x192 S4 N4", flush=True)
+    prm = sg.params(iters=8)
+    op = oracle.OracleParams(iters=8)
+    # keyframe A on both sides
+    dA = engine.DeviceKeyframe.from_scene(ctx, kf)
+    engine.update_plain(ctx, dA, prm)
+    torch.cuda.synchronize()
+    okA = oracle_keyframe(dA)
+    stA = oracle.new_state(np.asarray(kf.init_id, np.float32).astype(np.float64),
+                           np.asarray(kf.init_n, np.float32).astype(np.float64))
+    oracle.optimize(okA, stA, op)
+    # keyframe B = neighbour view 0; its neighbours: A and views 1..N-1
+    R0, t0 = kf.R[0], kf.t[0]                      # X_B = R0 X_A + t0
+    R0i, t0i = R0.T, -R0.T @ t0                     # X_A = R0i X_B + t0i
+    Rb = [R0i] + [kf.R[j] @ R0i for j in range(1, kf.n_nbr)]
+    tb = [t0i] + [kf.R[j] @ t0i + kf.t[j] for j in range(1, kf.n_nbr)]
+    imgs_b = torch.stack([kf.kf_image] + [kf.nbr_images[j] for j in range(1, kf.n_nbr)])
+    grid = (kf.K, kf.width, kf.height, kf.patch)
+    m = (kf.width // kf.patch) * (kf.height // kf.patch)
+    # device: transfer A's surfels into B's tiles
+    stB = sg.SurfelState.from_arrays(np.zeros(m, np.float32), np.tile([0, 0, -1.0], (m, 1)))
+    is_new = torch.zeros(m, dtype=torch.uint8, device="cuda")
+    sg.sgn_transfer_surfels(ctx.handle, sg.grid_of(*grid), dA.state.c, sg.pose_of(R0, t0),
+                            sg.grid_of(*grid), stB.c, is_new.data_ptr())
+    torch.cuda.synchronize()
+    hB = stB.to_host()
+    dB = engine.DeviceKeyframe(ctx, kf.nbr_images[0], imgs_b, np.stack(Rb), np.stack(tb), kf.K,
+                               kf.patch, hB["inv_depth"], hB["n"], is_new=is_new.cpu().numpy(),
+                               flags=hB["flags"])
+    engine.update_plain(ctx, dB, prm)
+    torch.cuda.synchronize()
+    devB = dB.state.to_host()
+    # oracle: the same chain from the oracle's own A
+    outB, o_new, o_win, _ = oracle.transfer_regrid(grid, stA, R0, t0, grid)
+    okB = oracle_keyframe(dB)
+    stB_o = outB
+    oracle.init_from_neighbours(okB, stB_o, o_new.reshape(-1), op)
+    oracle.optimize(okB, stB_o, op)
+    # the two chains start B from A's results, which differ at float level
+    # for the surfels of A that are not determined at float resolution: most
+    # of B still agrees to the tolerance
+    from tests.parity import compare, summary
+    c = compare(devB, stB_o)
+    print("keyframe B, oracle chain", summary(c), flush=True)
+    assert c["within"].mean() >= 0.8
+    # the device's own chain from its own A is checked exactly by the parity bar
+    res = check_parity(dB, devB, hB["inv_depth"], hB["n"], is_new.cpu().numpy(), op,
+                       label="keyframe B from device A")
+    assert_parity(res, label="keyframe B from device A", max_unstable=0.2)
