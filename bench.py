@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a kernel of "
                          "known traffic for scaling the HBM counters)")
-    ap.add_argument("--serve-seconds", type=float, default=5.0,
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of the Poisson serving trace (0: skip the serving leg)")
     ap.add_argument("--serve-load-rate", type=float, default=3000.0,
                     help="arrival rate of a second, saturating serving trace (req/s)")
@@ -217,8 +217,8 @@ def main():
     serving = None
     if args.serve_seconds > 0:
         from paper_1910_01997_amd import serve
-        serving = serve.serving_benchmark(n_streams=32, rate=200.0, duration=args.serve_seconds,
-                                          warmup=1.0, storage=args.storage, iters=iters, log=log)
+        serving = serve.serving_benchmark(n_streams=32, rate=200.0, duration=args.serve_seconds + 2.0,
+                                          warmup=2.0, storage=args.storage, iters=iters, log=log)
         if args.serve_load_seconds > 0:
             # the same streams under a load that keeps the device busy: here
             # continuous batching has several requests to merge

@@ -58,7 +58,8 @@ def compare(dev: dict, st: dict, idx=None):
     o_id = st["inv_depth"][idx]
     g_n = dev["n"][idx].astype(np.float64)
     o_n = np.stack([st["nx"][idx], st["ny"][idx], st["nz"][idx]], 1)
-    rel = np.abs(g_id - o_id) / np.abs(o_id)
+    diff = np.abs(g_id - o_id)
+    rel = np.where(diff == 0, 0.0, diff / np.maximum(np.abs(o_id), np.finfo(np.float64).tiny))
     ang = angle_deg(g_n, o_n)
     gf = dev["flags"][idx] & CMP_FLAGS
     of = st["flags"][idx].astype(np.uint32) & CMP_FLAGS
@@ -87,6 +88,10 @@ def compare(dev: dict, st: dict, idx=None):
 # worst oracle outcome for that surfel.
 PROBE_EPS = 2e-6
 PROBE_SEEDS = (1, 2, 3, 4, 5)
+# small cases (at most SMALL_CASE surfels compared) afford more probe runs,
+# which catch more of the surfels that are unstable only now and then
+SMALL_CASE = 5000
+PROBE_SEEDS_SMALL = tuple(range(1, 11))
 UNSTABLE_MEAN_RATIO = 1.05
 UNSTABLE_GROSS_RATIO = 3.0
 UNSTABLE_GROSS_FRACTION = 0.01
@@ -105,7 +110,7 @@ def unstable_set(dk, init_id, init_n, is_new, params, base, subset=None):
     idx = np.arange(n) if subset is None else np.asarray(subset)
     bad = np.zeros(n, bool)
     runs = []
-    for seed in PROBE_SEEDS:
+    for seed in (PROBE_SEEDS if idx.size > SMALL_CASE else PROBE_SEEDS_SMALL):
         p = dataclasses.replace(params, perturb=PROBE_EPS, perturb_seed=seed)
         _, st = run_oracle(dk, init_id, init_n, is_new, p, subset=subset)
         c = compare(as_dev(st), base, idx=idx)
