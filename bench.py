@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-precision-forms", action="store_true",
                     help="skip timing the GN kernel with the other image storages")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the depth-only vs full comparison against ground truth")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a kernel of "
@@ -141,6 +143,50 @@ def main():
     hbm_gbs = (img_bytes + state_bytes) / (gn_ms * 1e-3) / 1e9
     log(f"steps {args.steps}: {ms_per_step:.3f} ms/step, GN kernel {gn_ms:.3f} ms "
         f"(min {min(kernel_ms):.3f}), {value:.4e} surfel-frame/s, {samples / (gn_ms * 1e-3):.4e} samples/s")
+
+    ablation = None
+    if not args.no_ablation:
+        # the paper's controlled comparison (depth-only vs full surfel
+        # optimisation) on the batch's synthetic scenes: error of the
+        # converged surfels against the ground-truth planes, on surfels whose
+        # tile lies on one plane
+        def gt_errors(dk_list):
+            rel, ang = [], []
+            for d, k in zip(dk_list, kfs):
+                st = d.state.to_host()
+                S = k.patch
+                gh, gw = k.gt_id.shape
+                pid = k.kf_plane_id[:gh * S, :gw * S].reshape(gh, S, gw, S)
+                pure = (pid == pid[:, :1, :, :1]).all(axis=(1, 3)).reshape(-1)
+                bad = (sg.FLAG_DEGENERATE | sg.FLAG_FEW_SAMPLES | sg.FLAG_SOLVE_FAIL |
+                       sg.FLAG_REJECTED | sg.FLAG_UNINIT)
+                ok = pure & ((st["flags"] & bad) == 0)
+                gid = k.gt_id.reshape(-1)
+                gn = k.gt_n.reshape(-1, 3)
+                rel.append(np.abs(st["inv_depth"][ok] / gid[ok] - 1))
+                g = st["n"][ok].astype(np.float64)
+                cr = np.linalg.norm(np.cross(g, gn[ok]), axis=1)
+                ang.append(np.degrees(np.arctan2(cr, np.abs((g * gn[ok]).sum(1)))))
+            rel, ang = np.concatenate(rel), np.concatenate(ang)
+            return {"surfels": int(rel.size), "depth_rel_err_p50": float(np.median(rel)),
+                    "depth_rel_err_p90": float(np.percentile(rel, 90)),
+                    "normal_err_deg_p50": float(np.median(ang)),
+                    "normal_err_deg_p90": float(np.percentile(ang, 90))}
+        restore()
+        engine.update_batch(ctx, dks, prm, plan)
+        torch.cuda.synchronize()
+        ablation = {"full": gt_errors(dks)}
+        restore()
+        engine.update_batch(ctx, dks, sg.params(iters=iters, depth_only=True), plan)
+        dms = sg.sgn_last_kernel_ms(ctx.handle)
+        torch.cuda.synchronize()
+        ablation["depth_only"] = gt_errors(dks)
+        ablation["depth_only"]["gn_ms"] = dms
+        ablation["initial"] = {"depth_rel_err_p50": float(np.median(np.concatenate(
+            [np.abs(np.asarray(k.init_id, np.float64).reshape(-1) / k.gt_id.reshape(-1) - 1)
+             for k in kfs])))}
+        log(f"ablation: full {ablation['full']}, depth-only {ablation['depth_only']}")
+        restore()
 
     forms = None
     if not args.no_precision_forms:
@@ -265,6 +311,7 @@ def main():
         "cpu_baseline": cpu,
         "plain_form": plain,
         "precision_forms": forms,
+        "ablation": ablation,
         "serving": serving,
         "device": {"name": info["name"], "arch": info["arch"], "cus": info["compute_units"]},
     }

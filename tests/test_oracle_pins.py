@@ -805,6 +805,38 @@ def test_levenberg_marquardt_never_increases_mean_cost_and_reaches_gn_point():
     assert np.median(angle_deg(n, ns)) < 1e-6
 
 
+def test_levenberg_marquardt_refuses_a_step_that_raises_the_mean_cost():
+    """Find starting states where one Gauss-Newton step raises the mean Huber
+    cost (judged by an independent evaluation of the cost at both states);
+    from there the damped variant with a negligible lambda must keep the
+    state, and plain Gauss-Newton must take the step."""
+    okf, ids, ns, rng = _construction_ii(seed=31)
+    gw = okf.grid[0]
+    found = 0
+    for trial in range(400):
+        i = int(rng.integers(ids.size))
+        id0 = ids[i] * rng.uniform(0.6, 1.5)
+        n0 = rot(np.cross(ns[i], rng.normal(size=3)), math.radians(rng.uniform(5, 35))) @ ns[i]
+        one = np.array([i], np.int32)
+        st = oracle.new_state(np.full(ids.size, id0), np.tile(n0, (ids.size, 1)))
+        oracle.optimize(okf, st, oracle.OracleParams(iters=1), subset=one)
+        n1 = np.array([st["nx"][i], st["ny"][i], st["nz"][i]])
+        if st["inv_depth"][i] == id0:
+            continue
+        _, _, c0, v0 = oracle.linearize(okf, i % gw, i // gw, id0, n0)
+        _, _, c1, v1 = oracle.linearize(okf, i % gw, i // gw, st["inv_depth"][i], n1)
+        if v1 < 3 or not (c1 / v1 > (c0 / v0) * (1 + 1e-4)):
+            continue
+        found += 1
+        lm = oracle.new_state(np.full(ids.size, id0), np.tile(n0, (ids.size, 1)))
+        oracle.optimize(okf, lm, oracle.OracleParams(iters=1, lm_lambda=1e-9), subset=one)
+        assert lm["inv_depth"][i] == id0
+        assert np.array_equal([lm["nx"][i], lm["ny"][i], lm["nz"][i]], n0)
+        if found >= 3:
+            break
+    assert found >= 1, "no cost-raising Gauss-Newton step found"
+
+
 # --- conditioning probe (test facility) --------------------------------------
 
 def test_probe_is_off_by_default_and_small_when_on():
