@@ -1,22 +1,28 @@
 // HIP kernels of the surfel Gauss-Newton path for gfx950 (CDNA4).
 //
 // Paper: "Dense monocular SLAM by direct surfel optimization" (Trabes,
-// Dondo Gazzano, Sosa Paez), Proposed Approach section, Eq. 1-9.
+// Dondo Gazzano, Sosa Paez), Proposed Approach section, Eq. 1-10.
 //
 // Kernels
 //   setup_kernel   per-frame constants H = K R K^-1 and K t (Eq. 6) in
-//                  double, rounded once to float; clears the work queues.
+//                  double; clears the work queues.
 //   init_kernel    neighbour-plane initialisation (Surfel Initialization).
-//   gn_kernel      the fused Gauss-Newton iterations: one wavefront holds
-//                  64 pixels (4 surfels of 4x4 or 1 surfel of 8x8); each lane
-//                  is one pixel and loops over the neighbour frames; the
-//                  per-pixel inverse-depth Jacobian is hoisted out of the
-//                  frame loop (the paper notes it does not depend on the
-//                  frame), the normal equations are reduced across lanes with
-//                  DPP, and every lane of a surfel solves the same 3x3 system.
-//                  All iterations run inside the kernel: surfels never read
-//                  each other during the optimisation.
-//   render_kernel  per-pixel inverse depth by Eq. 3.
+//   gn_kernel      the fused Gauss-Newton iterations.  A work item is a set
+//                  of surfel groups inside one aligned 16 x 16-pixel block;
+//                  a group fills the 64 lanes of a wavefront with pixels (four
+//                  4x4 surfels or one 8x8 surfel).  Each lane loops over the
+//                  neighbour frames for its pixel, with the per-pixel
+//                  inverse-depth Jacobian hoisted out of the frame loop (the
+//                  paper notes it does not depend on the frame); the normal
+//                  equations are reduced across the surfel's lanes with DPP,
+//                  and one owner lane per surfel solves its 3x3 system, all
+//                  groups of the item at once.  All iterations run inside the
+//                  kernel: surfels never read each other during the
+//                  optimisation.
+//   render_kernel  per-pixel inverse depth (and owning surfel) by Eq. 3.
+//   regrid_*       surfel reference-frame change (Eq. 10) and re-gridding
+//                  into another keyframe's tiles.
+//   quantize_kernel  f32 images to f16 / u8 storage.
 //
 // Numerics.  The warp uses the closed form of Eq. 6 for a plane:
 //   q = H u~ + (K t) id_u,   u_p = (q_x / q_z, q_y / q_z),
@@ -25,7 +31,8 @@
 // equal to Eq. 3 without its cancellation.  The image gradient is the exact
 // derivative of the bilinear interpolant.  Accumulation is in float, in a
 // fixed order per surfel (frames in order per lane, then a fixed DPP tree),
-// so a surfel's result does not depend on where it sits in a batch.
+// so a surfel's result depends neither on where it sits in a batch nor on
+// the launch plan.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
