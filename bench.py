@@ -150,9 +150,9 @@ def main():
         # optimisation) on the batch's synthetic scenes: error of the
         # converged surfels against the ground-truth planes, on surfels whose
         # tile lies on one plane
-        def gt_errors(dk_list):
+        def gt_errors(dk_list, kf_list=None):
             rel, ang = [], []
-            for d, k in zip(dk_list, kfs):
+            for d, k in zip(dk_list, kf_list if kf_list is not None else kfs):
                 st = d.state.to_host()
                 S = k.patch
                 gh, gw = k.gt_id.shape
@@ -182,10 +182,33 @@ def main():
         torch.cuda.synchronize()
         ablation["depth_only"] = gt_errors(dks)
         ablation["depth_only"]["gn_ms"] = dms
+        restore()
+        engine.update_batch(ctx, dks, sg.params(iters=iters, lm_lambda=1e-2), plan)
+        lms = sg.sgn_last_kernel_ms(ctx.handle)
+        torch.cuda.synchronize()
+        ablation["damped_full"] = gt_errors(dks)
+        ablation["damped_full"]["gn_ms"] = lms
         ablation["initial"] = {"depth_rel_err_p50": float(np.median(np.concatenate(
             [np.abs(np.asarray(k.init_id, np.float64).reshape(-1) / k.gt_id.reshape(-1) - 1)
              for k in kfs])))}
-        log(f"ablation: full {ablation['full']}, depth-only {ablation['depth_only']}")
+        # the same comparison with 8x8 surfels (16 keyframes of the batch's
+        # scene recipe): four times the pixels and twice the span per surfel
+        import dataclasses
+        kf8 = [make_keyframe(dataclasses.replace(spec_for_config(2, i), patch=8), device="cuda")
+               for i in range(16)]
+        dk8 = [engine.DeviceKeyframe.from_scene(ctx, k, storage=args.storage) for k in kf8]
+        pool8 = engine.StatePool(dk8)
+        init8 = pool8.snapshot()
+        ablation["surfels_8x8"] = {}
+        for name, p8 in (("full", sg.params(iters=iters)),
+                         ("depth_only", sg.params(iters=iters, depth_only=True)),
+                         ("damped_full", sg.params(iters=iters, lm_lambda=1e-2))):
+            pool8.restore(init8)
+            engine.update_batch(ctx, dk8, p8)
+            torch.cuda.synchronize()
+            ablation["surfels_8x8"][name] = gt_errors(dk8, kf8)
+        del kf8, dk8, pool8, init8
+        log(f"ablation: {ablation}")
         restore()
 
     forms = None

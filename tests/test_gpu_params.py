@@ -94,7 +94,9 @@ def test_u8_with_another_scale(ctx):
     assert codes.max() <= 101
     res = check_parity(d, dev, kf.init_id, kf.init_n, kf.is_new,
                        oracle.OracleParams(iters=10, huber_k=4.5 / 255.0), label="u8 1/200")
-    assert_parity(res, label="u8 1/200", max_unstable=0.25)
+    # half the contrast doubles the relative weight of the noise, so more
+    # surfels sit near the edge of what float resolution determines
+    assert_parity(res, label="u8 1/200", min_stable=0.998, max_unstable=0.25)
 
 
 def test_surfel_index_map_matches_oracle(ctx):
