@@ -29,7 +29,8 @@ def kernel_source_hash() -> str:
     for src in SOURCES + ["sgn_internal.h"]:
         with open(os.path.join(CSRC, src), "rb") as f:
             h.update(f.read())
-    h.update(" ".join(HIP_FLAGS).encode())
+    # the flags without the include path, which depends on where the tree is
+    h.update(" ".join(f for f in HIP_FLAGS if not f.startswith("-I")).encode())
     return h.hexdigest()
 
 
