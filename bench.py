@@ -191,23 +191,26 @@ def main():
         ablation["initial"] = {"depth_rel_err_p50": float(np.median(np.concatenate(
             [np.abs(np.asarray(k.init_id, np.float64).reshape(-1) / k.gt_id.reshape(-1) - 1)
              for k in kfs])))}
-        # the same comparison with 8x8 surfels (16 keyframes of the batch's
-        # scene recipe): four times the pixels and twice the span per surfel
+        # the same comparison with 8x8 and 16x16 surfels (16 keyframes of the
+        # batch's scene recipe): four and sixteen times the pixels, twice and
+        # four times the span per surfel
         import dataclasses
-        kf8 = [make_keyframe(dataclasses.replace(spec_for_config(2, i), patch=8), device="cuda")
-               for i in range(16)]
-        dk8 = [engine.DeviceKeyframe.from_scene(ctx, k, storage=args.storage) for k in kf8]
-        pool8 = engine.StatePool(dk8)
-        init8 = pool8.snapshot()
-        ablation["surfels_8x8"] = {}
-        for name, p8 in (("full", sg.params(iters=iters)),
-                         ("depth_only", sg.params(iters=iters, depth_only=True)),
-                         ("damped_full", sg.params(iters=iters, lm_lambda=1e-2))):
-            pool8.restore(init8)
-            engine.update_batch(ctx, dk8, p8)
-            torch.cuda.synchronize()
-            ablation["surfels_8x8"][name] = gt_errors(dk8, kf8)
-        del kf8, dk8, pool8, init8
+        for S in (8, 16):
+            kfS = [make_keyframe(dataclasses.replace(spec_for_config(2, i), patch=S), device="cuda")
+                   for i in range(16)]
+            dkS = [engine.DeviceKeyframe.from_scene(ctx, k, storage=args.storage) for k in kfS]
+            poolS = engine.StatePool(dkS)
+            initS = poolS.snapshot()
+            leg = ablation[f"surfels_{S}x{S}"] = {}
+            for name, pS in (("full", sg.params(iters=iters)),
+                             ("depth_only", sg.params(iters=iters, depth_only=True)),
+                             ("damped_full", sg.params(iters=iters, lm_lambda=1e-2))):
+                poolS.restore(initS)
+                engine.update_batch(ctx, dkS, pS)
+                leg[name] = {"gn_ms": sg.sgn_last_kernel_ms(ctx.handle)}
+                torch.cuda.synchronize()
+                leg[name].update(gt_errors(dkS, kfS))
+            del kfS, dkS, poolS, initS
         log(f"ablation: {ablation}")
         restore()
 

@@ -19,7 +19,7 @@
  *     at integer coordinates.  K = [[fx, 0, cx], [0, fy, cy], [0, 0, 1]].
  *   - A pose P_kf^fn maps keyframe coordinates to frame n: X_n = R X_kf + t,
  *     R row-major (Eq. 6).
- *   - Surfels are S x S pixel tiles (S = patch, 4 or 8): tile (tx, ty) owns
+ *   - Surfels are S x S pixel tiles (S = patch, 4, 8 or 16): tile (tx, ty) owns
  *     pixels [S tx, S tx + S) x [S ty, S ty + S); its centre pixel is
  *     (S tx + (S-1)/2, S ty + (S-1)/2).  The grid is gw x gh with
  *     gw = width / S, gh = height / S (floor; the ragged right/bottom border
@@ -101,7 +101,7 @@ typedef struct {
     const sgn_pose* pose;       /* host array [n_nbr]: P_kf^fn */
     int32_t n_nbr;              /* 1 .. SGN_MAX_NBR */
     sgn_intrinsics K;
-    int32_t patch;              /* S: 4 or 8 */
+    int32_t patch;              /* S: 4, 8 or 16 */
 } sgn_keyframe;
 
 #define SGN_MAX_NBR 16
@@ -141,15 +141,17 @@ typedef struct {
  * by the caller; all-zero means "library default"). */
 typedef struct {
     int32_t tiles_x, tiles_y;   /* surfels per wavefront as a tiles_x x tiles_y block
-                                   (S = 4: 4x1, 2x2 or 1x4; S = 8: 1x1) */
+                                   (S = 4: 4x1, 2x2 or 1x4; S = 8 and 16: 1x1; an
+                                   S = 16 surfel gives each lane four pixels) */
     int32_t persistent;         /* 1: persistent grid pulling work items from a
                                    device queue; 0: one wavefront per work item */
     int32_t waves_per_cu;       /* persistent grid size per compute unit (0: occupancy) */
     int32_t lds_stage;          /* 1: stage neighbour-frame footprints in LDS */
     int32_t xcd_queues;         /* 1: one work queue per XCD, keyframes bound to an XCD */
-    int32_t groups;             /* tiles_x x tiles_y groups per work item: 1, 2 or 4 (0:
-                                   default).  A work item lies in one aligned 16 x 16-pixel
-                                   block; its per-surfel solves run together, one lane each */
+    int32_t groups;             /* tiles_x x tiles_y groups per work item: 1, 2 or 4, and
+                                   1 for S = 16 (0: default).  A work item lies in one
+                                   aligned 16 x 16-pixel block; its per-surfel solves run
+                                   together, one lane each */
 } sgn_plan;
 
 /* One keyframe of a batch with its surfels and optional outputs. */
@@ -225,7 +227,7 @@ sgn_status sgn_autotune(sgn_ctx* ctx, const sgn_batch_item* sample, int32_t n_it
                         const sgn_params* params, sgn_plan* out);
 
 /* A keyframe's surfel grid for re-gridding: intrinsics, image size and tile
- * edge S (4 or 8); the grid is (width / S) x (height / S) tiles. */
+ * edge S (4, 8 or 16); the grid is (width / S) x (height / S) tiles. */
 typedef struct {
     sgn_intrinsics K;
     int32_t width, height, patch;

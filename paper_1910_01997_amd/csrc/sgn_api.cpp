@@ -139,7 +139,8 @@ sgn_status check_keyframe(const sgn_keyframe* kf, bool need_nbr) {
     if (!kf) return fail(SGN_E_INVALID, "null keyframe");
     const sgn_image& I = kf->kf;
     if (I.dtype < SGN_F32 || I.dtype > SGN_U8) return fail(SGN_E_INVALID, "bad dtype");
-    if (kf->patch != 4 && kf->patch != 8) return fail(SGN_E_UNSUPPORTED, "patch must be 4 or 8");
+    if (kf->patch != 4 && kf->patch != 8 && kf->patch != 16)
+        return fail(SGN_E_UNSUPPORTED, "patch must be 4, 8 or 16");
     if (I.width < kf->patch || I.height < kf->patch) return fail(SGN_E_INVALID, "image smaller than one surfel");
     if (I.width > 16384 || I.height > 16384) return fail(SGN_E_UNSUPPORTED, "image larger than 16384");
     sgn_status st = check_image(I, I.width, I.height, I.dtype, "keyframe image");
@@ -181,10 +182,11 @@ sgn_status check_params(const sgn_params* p) {
 
 sgn_plan default_plan(int patch) {
     sgn_plan p{};
-    // measured fastest on the 64-keyframe batch: 2x2 groups, four per item
-    if (patch == 8) { p.tiles_x = 1; p.tiles_y = 1; }
-    else { p.tiles_x = 2; p.tiles_y = 2; }
-    p.groups = 4;
+    // measured fastest on the 64-keyframe batch: 2x2 groups, four per item;
+    // a 16 x 16 surfel spans a whole anchor block, so it is one group per item
+    if (patch == 4) { p.tiles_x = 2; p.tiles_y = 2; }
+    else { p.tiles_x = 1; p.tiles_y = 1; }
+    p.groups = patch == 16 ? 1 : 4;
     p.persistent = 1;
     p.waves_per_cu = 0;
     p.lds_stage = 0;
@@ -242,7 +244,7 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
 
     // keyframe order: longest work items first, grouped by XCD queue
     const ItemGeo geo = fl.gn ? item_geo(patch, plan.tiles_x, plan.tiles_y, plan.groups)
-                              : item_geo(patch, patch == 8 ? 1 : 4, 1, 1);
+                              : item_geo(patch, patch == 4 ? 4 : 1, 1, 1);
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::vector<int64_t> work(n);
@@ -594,7 +596,8 @@ sgn_status sgn_transfer_surfels(sgn_ctx* c, const sgn_grid* src_grid, const sgn_
     if (!c || !src_grid || !src || !pose || !dst_grid || !dst || !dst_is_new)
         return fail(SGN_E_INVALID, "null argument");
     for (const sgn_grid* g : {src_grid, dst_grid}) {
-        if (g->patch != 4 && g->patch != 8) return fail(SGN_E_INVALID, "patch must be 4 or 8");
+        if (g->patch != 4 && g->patch != 8 && g->patch != 16)
+            return fail(SGN_E_INVALID, "patch must be 4, 8 or 16");
         if (g->width < g->patch || g->height < g->patch || g->width > 16384 || g->height > 16384)
             return fail(SGN_E_INVALID, "grid size out of range");
         if (!(g->K.fx > 0.0) || !(g->K.fy > 0.0) || !std::isfinite(g->K.cx) || !std::isfinite(g->K.cy))
@@ -681,10 +684,11 @@ sgn_status sgn_autotune(sgn_ctx* c, const sgn_batch_item* items, int32_t n, cons
             hipMemcpyAsync(arrays[i].first, bufs[i], arrays[i].second, hipMemcpyDeviceToDevice, c->stream);
     };
     std::vector<sgn_plan> cands;
-    std::vector<std::pair<int, int>> shapes = patch == 8 ? std::vector<std::pair<int, int>>{{1, 1}}
+    std::vector<std::pair<int, int>> shapes = patch != 4 ? std::vector<std::pair<int, int>>{{1, 1}}
                                                          : std::vector<std::pair<int, int>>{{4, 1}, {2, 2}, {1, 4}};
+    const std::vector<int> group_counts = patch == 16 ? std::vector<int>{1} : std::vector<int>{1, 2, 4};
     for (auto sh : shapes)
-        for (int groups : {1, 2, 4})
+        for (int groups : group_counts)
             for (int pers = 0; pers <= 1; ++pers)
                 for (int xq = 0; xq <= pers; ++xq) {
                     sgn_plan pl{};

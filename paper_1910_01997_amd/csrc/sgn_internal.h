@@ -88,7 +88,7 @@ enum : uint32_t {
 // Kernel variants.
 struct GnVariant {
     int dtype;      // 0 f32, 1 f16, 2 u8
-    int patch;      // 4 or 8
+    int patch;      // 4, 8 or 16
     int tiles_x, tiles_y;
     int lds;        // stage footprints in LDS
     int groups;     // surfel groups per work item (1, 2 or 4)

@@ -618,20 +618,30 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                                                            uint32_t* __restrict__ counters,
                                                            int persistent) {
     constexpr ItemGeo G = item_geo(S, TX, TY, K);
-    constexpr int LANES = S * S;                 // lanes per surfel
-    constexpr int SLOTS = kWaveSize / LANES;     // surfels per group
-    constexpr int NS = K * SLOTS;                // surfels per work item
+    constexpr int PIX = S * S;                                // pixels per surfel
+    constexpr int LANES = PIX < kWaveSize ? PIX : kWaveSize;  // lanes per surfel
+    constexpr int PPL = PIX / LANES;                          // pixels per lane
+    constexpr int SLOTS = kWaveSize / LANES;                  // surfels per group
+    constexpr int NS = K * SLOTS;                             // surfels per work item
     static_assert(TX * TY * LANES == kWaveSize, "a group fills the wavefront");
     static_assert(NS <= kMaxItemSurfels, "surfels per item");
     const cptr<BatchHeader> hdr = (cptr<BatchHeader>)hdr_;
     const int lane = threadIdx.x & (kWaveSize - 1);
     const int wave = threadIdx.x >> 6;
-    // pixel role: slot r of a group and pixel (px, py) of that surfel
+    // pixel role: slot r of a group; pixels p + LANES j (j < PPL) of that surfel
     const int r = lane / LANES;
     const int p = lane % LANES;
-    const int px = p % S, py = p / S;
     const float half = 0.5f * (float)(S - 1);
-    const float dxp = (float)px - half, dyp = (float)py - half;   // offset from u_s (exact)
+    int pxs[PPL], pys[PPL];
+    float dxp[PPL], dyp[PPL];                    // offsets from u_s (exact)
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+        const int q = p + LANES * j;
+        pxs[j] = q % S;
+        pys[j] = q / S;
+        dxp[j] = (float)pxs[j] - half;
+        dyp[j] = (float)pys[j] - half;
+    }
     // owner role: surfel (group ok_g, slot ok_r) of the item
     const int ok_g = (S == 4) ? (lane & 15) : lane;
     const int ok_r = (S == 4) ? (lane >> 4) : 0;
@@ -681,7 +691,12 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
         const unsigned img_bytes = pitch_b * (unsigned)Kd->height;
         const unsigned wm1 = (unsigned)(Kd->width - 1), hm1 = (unsigned)(Kd->height - 1);
         const float fxk = Kd->fx, fyk = Kd->fy, cxk = Kd->cx, cyk = Kd->cy;
-        const float drx = dxp / fxk, dry = dyp / fyk;                  // r_u - r_s
+        float drx[PPL], dry[PPL];                                       // r_u - r_s
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            drx[j] = dxp[j] / fxk;
+            dry[j] = dyp[j] / fyk;
+        }
         // anchor block centre (pixels)
         const int bpx = bx * G.ab * S, bpy = by * G.ab * S;
         {
@@ -723,16 +738,19 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
         const uint32_t fr_hi = __builtin_amdgcn_readfirstlane((uint32_t)(fr_bits >> 32));
         const cptr<FrameDev> fr = (cptr<FrameDev>)(((uint64_t)fr_hi << 32) | fr_lo);
 
-        // pixel lanes: keyframe value of this lane's pixel in every group
-        float ikf[K];
+        // pixel lanes: keyframe value of this lane's pixels in every group
+        float ikf[K][PPL];
         const gptr<T> kimg = (gptr<T>)Kd->kf_img;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int tx = it0x + (k % G.gx) * TX + r % TX, ty = it0y + (k / G.gx) * TY + r / TX;
-            ikf[k] = 0.f;
-            if (tx < gw && ty < gh)
-                ikf[k] = ldg<T>(kimg + ((unsigned)(S * ty + py) * (unsigned)Kd->kf_pitch +
-                                        (unsigned)(S * tx + px))) * Kd->kf_scale;
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                ikf[k][j] = 0.f;
+                if (tx < gw && ty < gh)
+                    ikf[k][j] = ldg<T>(kimg + ((unsigned)(S * ty + pys[j]) * (unsigned)Kd->kf_pitch +
+                                               (unsigned)(S * tx + pxs[j]))) * Kd->kf_scale;
+            }
         }
 
         // owner lanes: the surfel's state
@@ -792,33 +810,49 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                 const float sb2x = sb.w, sb2y = sc.x, sb2z = sc.y, inv_c = sc.z, srsx = sc.w;
                 const float srsy = sd.x;
                 const bool salive = sd.y != 0.f;
-                // frame-independent per-pixel terms (Eq. 3, Eq. 9)
-                const float sigma = (snx * drx + sny * dry) * inv_c;
-                const float idu = fmaf(sid, sigma, sid);
-                const float dx3 = fmaf(-sigma, srsx, drx);
-                const float dy3 = fmaf(-sigma, srsy, dry);
-                const float dz3 = -sigma;
-                const float kk = sid * inv_c;
-                const float g0 = 1.f + sigma;
-                const float g1 = depth_only ? 0.f : kk * (sb1x * dx3 + sb1y * dy3 + sb1z * dz3);
-                const float g2 = depth_only ? 0.f : kk * (sb2x * dx3 + sb2y * dy3 + sb2z * dz3);
-                const bool pix_ok = salive && (idu > 0.f);
-                // pixel offset from the anchor block centre
                 const int tx = it0x + (k % G.gx) * TX + r % TX, ty = it0y + (k / G.gx) * TY + r / TX;
-                const float bdx = (float)(S * tx + px - bpx) - 0.5f * (float)(G.ab * S - 1);
-                const float bdy = (float)(S * ty + py - bpy) - 0.5f * (float)(G.ab * S - 1);
-                float A = 0.f, B = 0.f, cst = 0.f;
-                int nvl = 0;
-                if (last || lm)
-                    frame_loop<T, true>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes, wm1,
-                                        hm1, ikf[k], hk, img_scale, A, B, cst, nvl);
-                else
-                    frame_loop<T, false>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes, wm1,
-                                         hm1, ikf[k], hk, img_scale, A, B, cst, nvl);
-                // J^T W J = sum_u A_u g g^T, J^T W r = sum_u B_u g (frame sum
-                // hoisted), reduced two at a time: lane 0 of the surfel ends
-                // with words 0, 2, 4, 6, 8 and lane 1 with words 1, 3, 5, 7, 9
-                // (the valid count as an exact float)
+                // this lane's share of J^T W J = sum_u A_u g g^T and
+                // J^T W r = sum_u B_u g (the frame sum hoisted), its valid
+                // count and cost, over its pixels in order
+                float ph[9], pnv, pcs;
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) {
+                    // frame-independent per-pixel terms (Eq. 3, Eq. 9)
+                    const float sigma = (snx * drx[j] + sny * dry[j]) * inv_c;
+                    const float idu = fmaf(sid, sigma, sid);
+                    const float dx3 = fmaf(-sigma, srsx, drx[j]);
+                    const float dy3 = fmaf(-sigma, srsy, dry[j]);
+                    const float dz3 = -sigma;
+                    const float kk = sid * inv_c;
+                    const float g0 = 1.f + sigma;
+                    const float g1 = depth_only ? 0.f : kk * (sb1x * dx3 + sb1y * dy3 + sb1z * dz3);
+                    const float g2 = depth_only ? 0.f : kk * (sb2x * dx3 + sb2y * dy3 + sb2z * dz3);
+                    const bool pix_ok = salive && (idu > 0.f);
+                    // pixel offset from the anchor block centre
+                    const float bdx = (float)(S * tx + pxs[j] - bpx) - 0.5f * (float)(G.ab * S - 1);
+                    const float bdy = (float)(S * ty + pys[j] - bpy) - 0.5f * (float)(G.ab * S - 1);
+                    float A = 0.f, B = 0.f, cst = 0.f;
+                    int nvl = 0;
+                    if (last || lm)
+                        frame_loop<T, true>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes,
+                                            wm1, hm1, ikf[k][j], hk, img_scale, A, B, cst, nvl);
+                    else
+                        frame_loop<T, false>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes,
+                                             wm1, hm1, ikf[k][j], hk, img_scale, A, B, cst, nvl);
+                    {
+#pragma clang fp contract(off)
+                        const float ag0 = A * g0, ag1 = A * g1, ag2 = A * g2;
+                        const float t[9] = {ag0 * g0, ag0 * g1, ag0 * g2, ag1 * g1, ag1 * g2,
+                                            ag2 * g2, B * g0, B * g1, B * g2};
+#pragma unroll
+                        for (int e = 0; e < 9; ++e) ph[e] = (j == 0) ? t[e] : ph[e] + t[e];
+                        pnv = (j == 0) ? (float)nvl : pnv + (float)nvl;
+                        pcs = (j == 0) ? cst : pcs + cst;
+                    }
+                }
+                // reduced two at a time: lane 0 of the surfel ends with words
+                // 0, 2, 4, 6, 8 and lane 1 with words 1, 3, 5, 7, 9 (the valid
+                // count as an exact float)
                 float s0, s1, s2, s3, s4;
                 {
                     // No FMA contraction: each butterfly step must be a plain
@@ -826,15 +860,14 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                     // on which lane forms them.
 #pragma clang fp contract(off)
                     const bool odd = (p & 1) != 0;
-                    const float ag0 = A * g0, ag1 = A * g1, ag2 = A * g2;
-                    s0 = pair_sum<LANES>(ag0 * g0, ag0 * g1, odd);     // H00 | H01
-                    s1 = pair_sum<LANES>(ag0 * g2, ag1 * g1, odd);     // H02 | H11
-                    s2 = pair_sum<LANES>(ag1 * g2, ag2 * g2, odd);     // H12 | H22
-                    s3 = pair_sum<LANES>(B * g0, B * g1, odd);         // b0  | b1
-                    s4 = pair_sum<LANES>(B * g2, (float)nvl, odd);     // b2  | nv
+                    s0 = pair_sum<LANES>(ph[0], ph[1], odd);     // H00 | H01
+                    s1 = pair_sum<LANES>(ph[2], ph[3], odd);     // H02 | H11
+                    s2 = pair_sum<LANES>(ph[4], ph[5], odd);     // H12 | H22
+                    s3 = pair_sum<LANES>(ph[6], ph[7], odd);     // b0  | b1
+                    s4 = pair_sum<LANES>(ph[8], pnv, odd);       // b2  | nv
                 }
                 float cs = 0.f;
-                if (last || lm) cs = group_sum<LANES>(cst);
+                if (last || lm) cs = group_sum<LANES>(pcs);
                 if (p < 2) {
                     float* o = lsm + (k * SLOTS + r) * SM_WORDS + p;
                     o[0] = s0; o[2] = s1; o[4] = s2; o[6] = s3; o[8] = s4;
@@ -971,15 +1004,18 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                     const float4 sa = *(const float4*)(st + 0);
                     const float inv_c = st[ST_INVC];
                     const bool calive = st[ST_ALIVE] != 0.f;
-                    const float sig = (sa.y * drx + sa.z * dry) * inv_c;
-                    const float idu_c = fmaf(sa.x, sig, sa.x);
                     const int tx = it0x + (k % G.gx) * TX + r % TX, ty = it0y + (k / G.gx) * TY + r / TX;
-                    const float bdx = (float)(S * tx + px - bpx) - 0.5f * (float)(G.ab * S - 1);
-                    const float bdy = (float)(S * ty + py - bpy) - 0.5f * (float)(G.ab * S - 1);
                     float cst2 = 0.f;
                     int nv2l = 0;
-                    frame_cost<T>(pairs, fr, nf, bdx, bdy, idu_c, calive && (idu_c > 0.f), pitch_b,
-                                  img_bytes, wm1, hm1, ikf[k], hk, img_scale, cst2, nv2l);
+#pragma unroll
+                    for (int j = 0; j < PPL; ++j) {
+                        const float sig = (sa.y * drx[j] + sa.z * dry[j]) * inv_c;
+                        const float idu_c = fmaf(sa.x, sig, sa.x);
+                        const float bdx = (float)(S * tx + pxs[j] - bpx) - 0.5f * (float)(G.ab * S - 1);
+                        const float bdy = (float)(S * ty + pys[j] - bpy) - 0.5f * (float)(G.ab * S - 1);
+                        frame_cost<T>(pairs, fr, nf, bdx, bdy, idu_c, calive && (idu_c > 0.f), pitch_b,
+                                      img_bytes, wm1, hm1, ikf[k][j], hk, img_scale, cst2, nv2l);
+                    }
                     const float c2 = group_sum<LANES>(cst2);
                     const int n2 = group_sum<LANES>(nv2l);
                     if (p == 0) {
@@ -1276,6 +1312,8 @@ static void* gn_pick_groups(int groups) {
 template <typename T>
 static void* gn_pick(const GnVariant& v) {
     if (v.patch == 8 && v.tiles_x == 1 && v.tiles_y == 1) return gn_pick_groups<T, 8, 1, 1>(v.groups);
+    // a 16 x 16 surfel is its own anchor block: one group per item
+    if (v.patch == 16 && v.tiles_x == 1 && v.tiles_y == 1 && v.groups == 1) return gn_ptr<T, 16, 1, 1, 1>();
     if (v.patch == 4 && v.tiles_x == 4 && v.tiles_y == 1) return gn_pick_groups<T, 4, 4, 1>(v.groups);
     if (v.patch == 4 && v.tiles_x == 2 && v.tiles_y == 2) return gn_pick_groups<T, 4, 2, 2>(v.groups);
     if (v.patch == 4 && v.tiles_x == 1 && v.tiles_y == 4) return gn_pick_groups<T, 4, 1, 4>(v.groups);

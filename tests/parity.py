@@ -198,6 +198,30 @@ def assert_parity(res, label="", min_stable=0.999, max_unstable=0.15, slack=1):
     assert res.gross_fraction <= UNSTABLE_GROSS_FRACTION, f"{label}: gross fraction {res.gross_fraction:.4f}"
 
 
+def assert_render(dk, dev: dict, got):
+    """The device's rendered inverse-depth map `got` against the oracle's
+    render of the device's own final state."""
+    st = oracle_state(dev["inv_depth"], dev["n"], dev["flags"])
+    idm, ind = oracle.render(oracle_keyframe(dk), st)
+    got = np.asarray(got, np.float64)
+    both = (idm > 0) & (got > 0)
+    assert (both == (idm > 0)).mean() > 0.9999
+    assert (both == (got > 0)).mean() > 0.9999
+    # float error of id_u = id_s (1 + sigma), sigma = n.(r_u - r_s) / (n.r_s):
+    # a few ulps of id_s, amplified by |r_s| / |n.r_s| for planes seen edge-on
+    gw = dk.grid[0]
+    i = ind[both]
+    S = dk.patch
+    fx, fy, cx, cy = dk.K
+    rsx = (S * (i % gw) + (S - 1) / 2 - cx) / fx
+    rsy = (S * (i // gw) + (S - 1) / 2 - cy) / fy
+    n = dev["n"][i].astype(np.float64)
+    c = np.abs(n[:, 0] * rsx + n[:, 1] * rsy + n[:, 2])
+    amp = np.sqrt(rsx ** 2 + rsy ** 2 + 1) / c
+    tol = 2e-6 * (np.abs(idm[both]) + dev["inv_depth"][i]) * np.maximum(1.0, amp)
+    assert np.all(np.abs(got[both] - idm[both]) <= tol)
+
+
 def summary(c: dict) -> str:
     n = c["idx"].size
     return (f"n={n} within={c['within'].mean():.5f} flags_equal={c['same_flags'].mean():.5f} "

@@ -14,8 +14,8 @@ torch = pytest.importorskip("torch")
 
 import oracle
 from scenegen import make_keyframe, spec_for_config
-from tests.parity import (assert_parity, check_parity, compare, oracle_keyframe, oracle_state,
-                          run_oracle, summary)
+from tests.parity import (assert_parity, assert_render, check_parity, compare, oracle_keyframe,
+                          oracle_state, run_oracle, summary)
 
 pytestmark = pytest.mark.gpu
 
@@ -92,22 +92,4 @@ def test_workload1_plain(ctx, storage):
 def test_render_matches_oracle(ctx):
     kf = make_keyframe(spec_for_config(1), device="cuda")
     dk, dev = _plain(ctx, kf)
-    ok = oracle_keyframe(dk)
-    st = oracle_state(dev["inv_depth"], dev["n"], dev["flags"])
-    idm, ind = oracle.render(ok, st)
-    got = dk.inv_depth_out.cpu().numpy().astype(np.float64)
-    both = (idm > 0) & (got > 0)
-    assert (both == (idm > 0)).mean() > 0.9999
-    # float error of id_u = id_s (1 + sigma), sigma = n.(r_u - r_s) / (n.r_s):
-    # a few ulps of id_s, amplified by |r_s| / |n.r_s| for planes seen edge-on
-    gw = dk.grid[0]
-    i = ind[both]
-    S = dk.patch
-    fx, fy, cx, cy = dk.K
-    rsx = (S * (i % gw) + (S - 1) / 2 - cx) / fx
-    rsy = (S * (i // gw) + (S - 1) / 2 - cy) / fy
-    n = dev["n"][i].astype(np.float64)
-    c = np.abs(n[:, 0] * rsx + n[:, 1] * rsy + n[:, 2])
-    amp = np.sqrt(rsx ** 2 + rsy ** 2 + 1) / c
-    tol = 2e-6 * (np.abs(idm[both]) + dev["inv_depth"][i]) * np.maximum(1.0, amp)
-    assert np.all(np.abs(got[both] - idm[both]) <= tol)
+    assert_render(dk, dev, dk.inv_depth_out.cpu().numpy())

@@ -66,13 +66,14 @@ def _check(dev, is_new, win, ref):
     assert np.all(dev["cost"] == 0) and np.all(dev["nvalid"] == 0)
 
 
-@pytest.mark.parametrize("case", ["same_grid", "coarser_grid", "finer_grid"])
+@pytest.mark.parametrize("case", ["same_grid", "coarser_grid", "finer_grid", "sixteen_grid"])
 def test_regrid_matches_oracle(ctx, case):
-    rng = np.random.default_rng({"same_grid": 5, "coarser_grid": 6, "finer_grid": 7}[case])
+    rng = np.random.default_rng({"same_grid": 5, "coarser_grid": 6, "finer_grid": 7, "sixteen_grid": 8}[case])
     src_grid = ((600.0, 600.0, 320.0, 240.0), 640, 480, 4)
     dst_grid = {"same_grid": src_grid,
                 "coarser_grid": ((420.0, 430.0, 200.0, 150.0), 400, 300, 8),
-                "finer_grid": ((1100.0, 1100.0, 640.0, 360.0), 1280, 720, 4)}[case]
+                "finer_grid": ((1100.0, 1100.0, 640.0, 360.0), 1280, 720, 4),
+                "sixteen_grid": ((610.0, 600.0, 330.0, 236.0), 650, 490, 16)}[case]
     print(f"case regrid {case}", flush=True)
     m = (640 // 4) * (480 // 4)
     ids = rng.uniform(0.25, 1.0, m).astype(np.float32)
