@@ -8,6 +8,7 @@ marshals numpy arrays.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -122,6 +123,24 @@ def lib():
         L.sgo_transfer_regrid.argtypes = [C.POINTER(GridC), C.POINTER(SurfelsC), C.POINTER(Pose),
                                           C.POINTER(GridC), C.POINTER(SurfelsC),
                                           C.POINTER(C.c_uint8), ip]
+        L.sgo_disc_support.restype = C.c_int32
+        L.sgo_disc_support.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
+                                       ip, ip, C.c_int32]
+        L.sgo_disc_linearize.restype = C.c_int32
+        L.sgo_disc_linearize.argtypes = [C.POINTER(KeyframeC), C.c_double, C.c_double, C.c_double,
+                                         C.c_double, dp, C.c_double, C.c_int, dp, dp, dp]
+        L.sgo_disc_optimize.restype = C.c_int
+        L.sgo_disc_optimize.argtypes = [C.POINTER(KeyframeC), C.POINTER(SurfelsC), dp, dp,
+                                        C.c_int32, C.c_double, C.POINTER(ParamsC), ip, C.c_int32]
+        L.sgo_disc_render.restype = C.c_int
+        L.sgo_disc_render.argtypes = [C.POINTER(KeyframeC), C.POINTER(SurfelsC), dp, dp,
+                                      C.c_int32, C.c_double, dp, ip]
+        L.sgo_disc_search.restype = C.c_int32
+        L.sgo_disc_search.argtypes = [C.c_int32, C.c_int32, ip, C.c_double, C.c_double,
+                                      C.c_int32, ip, ip, C.c_int32]
+        L.sgo_disc_init.restype = C.c_int
+        L.sgo_disc_init.argtypes = [C.POINTER(KeyframeC), C.POINTER(SurfelsC), dp, dp, ip,
+                                    C.c_int32, C.c_int32, C.c_double, C.c_double]
         L.sgo_set_threads.restype = None
         L.sgo_set_threads.argtypes = [C.c_int32]
         L.sgo_max_threads.restype = C.c_int32
@@ -381,6 +400,82 @@ def transfer_regrid(src_grid, st, R, t, dst_grid):
                                        C.byref(dc), is_new.ctypes.data_as(C.POINTER(C.c_uint8)),
                                        win.ctypes.data_as(C.POINTER(C.c_int32)))
     return out, is_new.reshape(gh, gw), win.reshape(gh, gw), int(filled)
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def disc_support(width, height, us, radius):
+    """Pixels (x, y) of the disc of radius r centred at us (Eq. 4), row by row."""
+    cap = 4 * int(math.ceil(radius) + 1) ** 2 + 16
+    xs = np.zeros(cap, np.int32)
+    ys = np.zeros(cap, np.int32)
+    n = lib().sgo_disc_support(int(width), int(height), float(us[0]), float(us[1]), float(radius),
+                               _ip(xs), _ip(ys), cap)
+    return xs[:n].copy(), ys[:n].copy()
+
+
+def disc_linearize(kf: OracleKeyframe, us, radius, id_s, n, huber_k=9.0 / 255.0, depth_only=False):
+    H = np.zeros(9)
+    b = np.zeros(3)
+    cost = C.c_double(0.0)
+    nn = _f64(n)
+    nv = lib().sgo_disc_linearize(C.byref(kf.c), float(us[0]), float(us[1]), float(radius),
+                                  float(id_s), _dp(nn), float(huber_k), int(bool(depth_only)),
+                                  _dp(H), _dp(b), C.byref(cost))
+    return H.reshape(3, 3), b, float(cost.value), int(nv)
+
+
+def disc_optimize(kf: OracleKeyframe, st, ux, uy, radius, params: OracleParams, subset=None):
+    """Gauss-Newton over disc surfels, in place on ``st`` (centres ux, uy)."""
+    sc = _surfels_c(st)
+    pc = params.c(1)
+    cx, cy = _f64(ux).reshape(-1), _f64(uy).reshape(-1)
+    ptr, n, keep = _subset(subset)
+    rc = lib().sgo_disc_optimize(C.byref(kf.c), C.byref(sc), _dp(cx), _dp(cy), int(cx.size),
+                                 float(radius), C.byref(pc), ptr, n)
+    if rc != 0:
+        raise RuntimeError("sgo_disc_optimize failed")
+    return st
+
+
+def disc_render(kf: OracleKeyframe, st, ux, uy, radius):
+    sc = _surfels_c(st)
+    cx, cy = _f64(ux).reshape(-1), _f64(uy).reshape(-1)
+    idm = np.zeros((kf.height, kf.width))
+    ind = np.zeros((kf.height, kf.width), np.int32)
+    lib().sgo_disc_render(C.byref(kf.c), C.byref(sc), _dp(cx), _dp(cy), int(cx.size), float(radius),
+                          _dp(idm), _ip(ind))
+    return idm, ind
+
+
+def disc_search(index_map, radius, alpha, spacing, capacity=None):
+    """Lattice candidates farther than alpha r from every non-empty pixel:
+    (xs, ys) of the first ``capacity`` and the number that qualify."""
+    im = np.ascontiguousarray(np.asarray(index_map, np.int32))
+    H, W = im.shape
+    cap = (W // max(1, spacing) + 1) * (H // max(1, spacing) + 1) if capacity is None else int(capacity)
+    xs = np.zeros(max(1, cap), np.int32)
+    ys = np.zeros(max(1, cap), np.int32)
+    found = lib().sgo_disc_search(W, H, _ip(im), float(radius), float(alpha), int(spacing),
+                                  _ip(xs), _ip(ys), cap)
+    if found < 0:
+        raise RuntimeError("sgo_disc_search failed")
+    k = min(found, cap)
+    return xs[:k].copy(), ys[:k].copy(), int(found)
+
+
+def disc_init(kf: OracleKeyframe, st, ux, uy, index_map, first, radius, beta):
+    """Neighbour initialisation of surfels first .. len(ux)-1, in place on ``st``."""
+    sc = _surfels_c(st)
+    cx, cy = _f64(ux).reshape(-1), _f64(uy).reshape(-1)
+    im = np.ascontiguousarray(np.asarray(index_map, np.int32))
+    rc = lib().sgo_disc_init(C.byref(kf.c), C.byref(sc), _dp(cx), _dp(cy), _ip(im), int(first),
+                             int(cx.size) - int(first), float(radius), float(beta))
+    if rc != 0:
+        raise RuntimeError("sgo_disc_init failed")
+    return st
 
 
 def set_threads(n: int):

@@ -17,6 +17,10 @@
  *   Surfel Initialization section: mean of neighbours' Eq. 3 inverse depths
  *   at the new ray, mean of their normals.
  *   Eq. 10 reference-frame change.
+ *   Eq. 4 disc surfels: support |u_s - u| < r, depth-buffered render with a
+ *   surfel-index map, the search for empty areas and neighbour
+ *   initialisation from that map (Inverse Depth Calculation and Surfel
+ *   Initialization sections).
  * Nothing is blocked, fused or hoisted: every (pixel, frame) sample forms its
  * own full Jacobian row and is added to J^T W J and J^T W r directly.
  */
@@ -198,33 +202,89 @@ static void tile_centre(const sgo_keyframe* kf, int32_t tx, int32_t ty, double* 
     *y = S * ty + 0.5 * (S - 1);
 }
 
-static int32_t linearize(const sgo_keyframe* kf, int32_t tx, int32_t ty, double id_s,
+/* Pixel support of one surfel (the pixels u of "u in s" in Eq. 5): the
+ * candidate pixels are the box [x0, x1] x [y0, y1] (inclusive, inside the
+ * image).  For a tile every box pixel belongs; for a disc (Eq. 4) a box
+ * pixel u belongs when |u - u_s| < r, decided as dx^2 + dy^2 < r^2 in
+ * double. */
+typedef struct {
+    double usx, usy;          /* centre pixel u_s */
+    int x0, y0, x1, y1;
+    double r2;                /* disc: r^2; tile: negative */
+} support;
+
+static support tile_support(const sgo_keyframe* kf, int32_t tx, int32_t ty) {
+    support sp;
+    int S = kf->patch;
+    tile_centre(kf, tx, ty, &sp.usx, &sp.usy);
+    sp.x0 = S * tx; sp.x1 = S * tx + S - 1;
+    sp.y0 = S * ty; sp.y1 = S * ty + S - 1;
+    sp.r2 = -1.0;
+    return sp;
+}
+
+static support disc_support(int32_t width, int32_t height, double usx, double usy, double r) {
+    support sp;
+    sp.usx = usx; sp.usy = usy;
+    sp.r2 = r * r;
+    sp.x0 = (int)fmax(0.0, ceil(usx - r));
+    sp.x1 = (int)fmin((double)(width - 1), floor(usx + r));
+    sp.y0 = (int)fmax(0.0, ceil(usy - r));
+    sp.y1 = (int)fmin((double)(height - 1), floor(usy + r));
+    return sp;
+}
+
+static int in_support(const support* sp, int x, int y) {
+    if (sp->r2 < 0.0) return 1;
+    double dx = (double)x - sp->usx, dy = (double)y - sp->usy;
+    return dx * dx + dy * dy < sp->r2;
+}
+
+static int32_t linearize(const sgo_keyframe* kf, const support* sp, double id_s,
                          const double n[3], double huber_k, int depth_only, double H[9],
                          double b[3], double* cost, double* margin);
 
 int32_t sgo_linearize(const sgo_keyframe* kf, int32_t tx, int32_t ty, double id_s,
                       const double n[3], double huber_k, int depth_only,
                       double H[9], double b[3], double* cost) {
-    return linearize(kf, tx, ty, id_s, n, huber_k, depth_only, H, b, cost, NULL);
+    support sp = tile_support(kf, tx, ty);
+    return linearize(kf, &sp, id_s, n, huber_k, depth_only, H, b, cost, NULL);
 }
 
-static int32_t linearize(const sgo_keyframe* kf, int32_t tx, int32_t ty, double id_s,
+int32_t sgo_disc_linearize(const sgo_keyframe* kf, double usx, double usy, double radius,
+                           double id_s, const double n[3], double huber_k, int depth_only,
+                           double H[9], double b[3], double* cost) {
+    support sp = disc_support(kf->kf.width, kf->kf.height, usx, usy, radius);
+    return linearize(kf, &sp, id_s, n, huber_k, depth_only, H, b, cost, NULL);
+}
+
+int32_t sgo_disc_support(int32_t width, int32_t height, double usx, double usy, double radius,
+                         int32_t* xs, int32_t* ys, int32_t capacity) {
+    support sp = disc_support(width, height, usx, usy, radius);
+    int32_t count = 0;
+    for (int y = sp.y0; y <= sp.y1; ++y)
+        for (int x = sp.x0; x <= sp.x1; ++x) {
+            if (!in_support(&sp, x, y)) continue;
+            if (count < capacity) { xs[count] = x; ys[count] = y; }
+            ++count;
+        }
+    return count;
+}
+
+static int32_t linearize(const sgo_keyframe* kf, const support* sp, double id_s,
                          const double n[3], double huber_k, int depth_only, double H[9],
                          double b[3], double* cost, double* margin) {
-    int S = kf->patch;
-    double usx, usy;
-    tile_centre(kf, tx, ty, &usx, &usy);
     memset(H, 0, 9 * sizeof(double));
     memset(b, 0, 3 * sizeof(double));
     *cost = 0.0;
     int32_t nvalid = 0;
-    for (int py = 0; py < S; ++py) {
-        for (int px = 0; px < S; ++px) {
-            int ux = S * tx + px, uy = S * ty + py;
+    for (int uy = sp->y0; uy <= sp->y1; ++uy) {
+        for (int ux = sp->x0; ux <= sp->x1; ++ux) {
+            if (!in_support(sp, ux, uy)) continue;
             double ikf = kf->kf.pix[(size_t)uy * kf->kf.width + ux];
             for (int f = 0; f < kf->n_nbr; ++f) {               /* sum over Omega */
                 double r, J[3];
-                if (!eval_sample(&kf->K, &kf->pose[f], &kf->nbr[f], ikf, usx, usy,
+                if (!eval_sample(&kf->K, &kf->pose[f], &kf->nbr[f], ikf, sp->usx, sp->usy,
                                  (double)ux, (double)uy, id_s, n, depth_only, &r, J, margin))
                     continue;
                 double w = huber_w(r, huber_k);
@@ -348,13 +408,10 @@ static double probe_uniform(uint32_t seed, int32_t surfel, int it, int comp) {
     return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
-static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_params* p, int32_t i) {
-    int S = kf->patch;
-    int gw = kf->kf.width / S;
-    int tx = i % gw, ty = i / gw;
-    double usx, usy, rs[3];
-    tile_centre(kf, tx, ty, &usx, &usy);
-    sgo_ray(&kf->K, usx, usy, rs);
+static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_params* p, int32_t i,
+                         const support* sp) {
+    double rs[3];
+    sgo_ray(&kf->K, sp->usx, sp->usy, rs);
     double id_s = s->inv_depth[i];
     double n[3] = {s->nx[i], s->ny[i], s->nz[i]};
     uint32_t flags = s->flags[i] & ~(uint32_t)(SGO_DEGENERATE | SGO_FEW_SAMPLES | SGO_SOLVE_FAIL |
@@ -374,7 +431,7 @@ static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_param
         double b1[3], b2[3];
         sgo_tangent_basis(n, b1, b2);
         double H[9], b[3];
-        nvalid = linearize(kf, tx, ty, id_s, n, p->huber_k, p->depth_only, H, b, &cost,
+        nvalid = linearize(kf, sp, id_s, n, p->huber_k, p->depth_only, H, b, &cost,
                            s->margin ? &margin : NULL);
         kappa = p->depth_only ? 1.0 : sgo_kappa_eq(H);
         double delta[3] = {0.0, 0.0, 0.0};
@@ -429,7 +486,7 @@ static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_param
                 continue;
             }
             double H2[9], b2v[3], cost2;
-            int32_t nv2 = linearize(kf, tx, ty, id_new, n_new, p->huber_k, p->depth_only, H2,
+            int32_t nv2 = linearize(kf, sp, id_new, n_new, p->huber_k, p->depth_only, H2,
                                     b2v, &cost2, s->margin ? &margin : NULL);
             if (nv2 < 3 || !(cost2 / nv2 <= (cost / nvalid) * (1.0 + 1e-4))) {
                 lambda *= 10.0;
@@ -465,10 +522,31 @@ int sgo_optimize_keyframe(const sgo_keyframe* kf, sgo_surfels* s, const sgo_para
     int S = kf->patch;
     int32_t total = (kf->kf.width / S) * (kf->kf.height / S);
     int32_t count = subset ? n_subset : total;
+    int gw = kf->kf.width / S;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int32_t k = 0; k < count; ++k) {
         int32_t i = subset ? subset[k] : k;
-        if (i >= 0 && i < total) optimize_one(kf, s, p, i);
+        if (i >= 0 && i < total) {
+            support sp = tile_support(kf, i % gw, i / gw);
+            optimize_one(kf, s, p, i, &sp);
+        }
+    }
+    return 0;
+}
+
+/* Gauss-Newton over disc surfels (Eq. 4 support, centres ux, uy). */
+int sgo_disc_optimize(const sgo_keyframe* kf, sgo_surfels* s, const double* ux, const double* uy,
+                      int32_t count, double radius, const sgo_params* p,
+                      const int32_t* subset, int32_t n_subset) {
+    if (!kf || !s || !ux || !uy || !p || !(radius > 0.0)) return -1;
+    int32_t m = subset ? n_subset : count;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int32_t k = 0; k < m; ++k) {
+        int32_t i = subset ? subset[k] : k;
+        if (i >= 0 && i < count) {
+            support sp = disc_support(kf->kf.width, kf->kf.height, ux[i], uy[i], radius);
+            optimize_one(kf, s, p, i, &sp);
+        }
     }
     return 0;
 }
@@ -574,6 +652,149 @@ int sgo_render_inverse_depth(const sgo_keyframe* kf, const sgo_surfels* s,
             if (surfel_index) surfel_index[o] = i;
         }
     }
+    return 0;
+}
+
+/* Inverse Depth Calculation section with disc surfels: pixel u takes Eq. 3
+ * of every surfel whose disc (Eq. 4) contains it, and the depth buffer keeps
+ * the closest one (the largest id_u; equal values go to the lower surfel
+ * index).  Surfels flagged DEGENERATE or UNINIT, planes through the camera
+ * centre (|n . r_s| < 1e-6) and non-positive or non-finite id_u give no
+ * measurement. */
+int sgo_disc_render(const sgo_keyframe* kf, const sgo_surfels* s, const double* ux,
+                    const double* uy, int32_t count, double radius, double* inv_depth,
+                    int32_t* surfel_index) {
+    int W = kf->kf.width, H = kf->kf.height;
+    for (size_t o = 0; o < (size_t)W * H; ++o) {
+        inv_depth[o] = 0.0;
+        surfel_index[o] = -1;
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        if (s->flags[i] & (SGO_DEGENERATE | SGO_UNINIT)) continue;
+        double n[3] = {s->nx[i], s->ny[i], s->nz[i]}, rs[3];
+        sgo_ray(&kf->K, ux[i], uy[i], rs);
+        if (fabs(dot3(n, rs)) < 1e-6) continue;
+        support sp = disc_support(W, H, ux[i], uy[i], radius);
+        for (int y = sp.y0; y <= sp.y1; ++y)
+            for (int x = sp.x0; x <= sp.x1; ++x) {
+                if (!in_support(&sp, x, y)) continue;
+                double id = sgo_pixel_inverse_depth(&kf->K, ux[i], uy[i], s->inv_depth[i], n, x, y);
+                if (!(id > 0.0) || !isfinite(id)) continue;
+                size_t o = (size_t)y * W + x;
+                if (id > inv_depth[o]) {          /* depth test; ties keep the lower index */
+                    inv_depth[o] = id;
+                    surfel_index[o] = i;
+                }
+            }
+    }
+    return 0;
+}
+
+/* Surfel Initialization section, the search for an empty area: a candidate
+ * pixel u_ns qualifies when every non-empty pixel u_nn of the surfel-index
+ * map (index >= 0) lies farther than alpha r from it, decided on the
+ * integer squared distance against (alpha r)^2 in double.  The candidates
+ * are the pixels (spacing/2 + i spacing, spacing/2 + j spacing) of a fixed
+ * lattice, visited row by row.  Writes the first `capacity` qualifying
+ * candidates and returns how many qualify. */
+int32_t sgo_disc_search(int32_t width, int32_t height, const int32_t* surfel_index,
+                        double radius, double alpha, int32_t spacing, int32_t* out_x,
+                        int32_t* out_y, int32_t capacity) {
+    if (spacing < 1) return -1;
+    double ar = alpha * radius;
+    double ar2 = ar * ar;
+    int reach = (int)floor(ar);
+    int32_t found = 0;
+    for (int cy = spacing / 2; cy < height; cy += spacing) {
+        for (int cx = spacing / 2; cx < width; cx += spacing) {
+            int empty = 1;
+            for (int y = cy - reach; y <= cy + reach && empty; ++y) {
+                if (y < 0 || y >= height) continue;
+                for (int x = cx - reach; x <= cx + reach; ++x) {
+                    if (x < 0 || x >= width) continue;
+                    if (surfel_index[(size_t)y * width + x] < 0) continue;
+                    int dx = x - cx, dy = y - cy;
+                    if ((double)(dx * dx + dy * dy) <= ar2) { empty = 0; break; }
+                }
+            }
+            if (!empty) continue;
+            if (found < capacity) { out_x[found] = cx; out_y[found] = cy; }
+            ++found;
+        }
+    }
+    return found;
+}
+
+/* Surfel Initialization section with disc surfels: the neighbours of a new
+ * surfel at u_ns are the surfels that own, in the surfel-index map, a pixel
+ * u with |u_ns - u| < beta r (integer squared distance against (beta r)^2 in
+ * double), skipping those flagged DEGENERATE or UNINIT and planes through
+ * the camera centre.  The new inverse depth is the mean over them, in index
+ * order, of Eq. 3 of the neighbour's plane at u_ns; the new normal the mean
+ * of their normals sign-aligned to the first, renormalised.  Surfels
+ * first .. first + n_new - 1 (centres ux, uy) are written: id, n, flags (0,
+ * or UNINIT with id 0 and n = (0, 0, -1) when nothing qualifies), cost 0,
+ * nvalid 0, last_update 0.  Only surfels below `first` are neighbours. */
+int sgo_disc_init(const sgo_keyframe* kf, sgo_surfels* s, const double* ux, const double* uy,
+                  const int32_t* surfel_index, int32_t first, int32_t n_new, double radius,
+                  double beta) {
+    int W = kf->kf.width, H = kf->kf.height;
+    double br = beta * radius;
+    double br2 = br * br;
+    int reach = (int)ceil(br);
+    uint8_t* seen = (uint8_t*)calloc(first > 0 ? (size_t)first : 1, 1);
+    if (!seen) return -1;
+    for (int32_t i = first; i < first + n_new; ++i) {
+        double cx = ux[i], cy = uy[i];
+        int icx = (int)cx, icy = (int)cy;        /* new centres are lattice pixels */
+        memset(seen, 0, first > 0 ? (size_t)first : 1);
+        for (int y = icy - reach; y <= icy + reach; ++y) {
+            if (y < 0 || y >= H) continue;
+            for (int x = icx - reach; x <= icx + reach; ++x) {
+                if (x < 0 || x >= W) continue;
+                int32_t j = surfel_index[(size_t)y * W + x];
+                if (j < 0 || j >= first) continue;
+                int dx = x - icx, dy = y - icy;
+                if ((double)(dx * dx + dy * dy) < br2) seen[j] = 1;
+            }
+        }
+        double id_sum = 0.0, nsum[3] = {0.0, 0.0, 0.0}, nref[3] = {0.0, 0.0, 0.0};
+        int count = 0;
+        for (int32_t j = 0; j < first; ++j) {
+            if (!seen[j]) continue;
+            if (s->flags[j] & (SGO_UNINIT | SGO_DEGENERATE)) continue;
+            double nj[3] = {s->nx[j], s->ny[j], s->nz[j]}, rj[3];
+            sgo_ray(&kf->K, ux[j], uy[j], rj);
+            if (fabs(dot3(nj, rj)) < 1e-6) continue;
+            /* Eq. 3 with the neighbour's plane, at the new surfel's pixel */
+            double id = sgo_pixel_inverse_depth(&kf->K, ux[j], uy[j], s->inv_depth[j], nj, cx, cy);
+            if (count == 0) { nref[0] = nj[0]; nref[1] = nj[1]; nref[2] = nj[2]; }
+            double sg = dot3(nj, nref) < 0.0 ? -1.0 : 1.0;
+            id_sum += id;
+            for (int k = 0; k < 3; ++k) nsum[k] += sg * nj[k];
+            ++count;
+        }
+        double id_new = count ? id_sum / count : 0.0;
+        double n_new[3] = {0.0, 0.0, 0.0};
+        int ok = count > 0;
+        if (ok) {
+            for (int k = 0; k < 3; ++k) n_new[k] = nsum[k] / count;
+            ok = normalize3(n_new) && id_new > 0.0 && isfinite(id_new);
+        }
+        if (ok) {
+            s->inv_depth[i] = id_new;
+            s->nx[i] = n_new[0]; s->ny[i] = n_new[1]; s->nz[i] = n_new[2];
+            s->flags[i] = 0;
+        } else {
+            s->inv_depth[i] = 0.0;
+            s->nx[i] = 0.0; s->ny[i] = 0.0; s->nz[i] = -1.0;
+            s->flags[i] = SGO_UNINIT;
+        }
+        s->cost[i] = 0.0;
+        s->nvalid[i] = 0;
+        s->last_update[i] = 0;
+    }
+    free(seen);
     return 0;
 }
 

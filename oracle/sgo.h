@@ -158,6 +158,45 @@ int sgo_transfer_regrid(const sgo_grid* src_grid, const sgo_surfels* src, const 
                         const sgo_grid* dst_grid, sgo_surfels* dst, uint8_t* dst_is_new,
                         int32_t* dst_src_index);
 
+/* Disc surfels (Eq. 4).  Surfel i is centred at pixel (ux[i], uy[i]) of the
+ * keyframe and covers the pixels u (integer coordinates, inside the image)
+ * with |u - u_s| < r; r (pixels) is the same for every surfel.  The state
+ * arrays are indexed by surfel, length count.  kf->patch is not used. */
+
+/* Pixels of one disc, row by row: writes the first `capacity`, returns the count. */
+int32_t sgo_disc_support(int32_t width, int32_t height, double usx, double usy, double radius,
+                         int32_t* xs, int32_t* ys, int32_t capacity);
+
+/* Huber IRLS normal equations of one disc surfel (as sgo_linearize). */
+int32_t sgo_disc_linearize(const sgo_keyframe* kf, double usx, double usy, double radius,
+                           double id_s, const double n[3], double huber_k, int depth_only,
+                           double H[9], double b[3], double* cost);
+
+/* Gauss-Newton over all disc surfels (subset == NULL) or the listed ones. */
+int sgo_disc_optimize(const sgo_keyframe* kf, sgo_surfels* s, const double* ux, const double* uy,
+                      int32_t count, double radius, const sgo_params* p,
+                      const int32_t* subset, int32_t n_subset);
+
+/* Depth-buffered render: per pixel the largest Eq. 3 inverse depth over the
+ * discs that contain it (ties to the lower index), 0 and -1 where none. */
+int sgo_disc_render(const sgo_keyframe* kf, const sgo_surfels* s, const double* ux,
+                    const double* uy, int32_t count, double radius, double* inv_depth,
+                    int32_t* surfel_index);
+
+/* Empty-area search on the lattice (spacing/2 + i spacing, spacing/2 + j
+ * spacing): candidates farther than alpha r from every non-empty pixel of
+ * the index map.  Writes the first `capacity`, returns how many qualify. */
+int32_t sgo_disc_search(int32_t width, int32_t height, const int32_t* surfel_index,
+                        double radius, double alpha, int32_t spacing, int32_t* out_x,
+                        int32_t* out_y, int32_t capacity);
+
+/* Neighbour initialisation of disc surfels first .. first + n_new - 1 from
+ * the surfels below `first` that own a pixel of the index map closer than
+ * beta r to the new centre. */
+int sgo_disc_init(const sgo_keyframe* kf, sgo_surfels* s, const double* ux, const double* uy,
+                  const int32_t* surfel_index, int32_t first, int32_t n_new, double radius,
+                  double beta);
+
 void sgo_set_threads(int32_t n);
 int32_t sgo_max_threads(void);
 
