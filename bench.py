@@ -57,6 +57,9 @@ def parse():
                     help="skip timing the GN kernel with the other image storages")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the depth-only vs full comparison against ground truth")
+    ap.add_argument("--no-disc", action="store_true",
+                    help="skip the disc-surfel leg (Eq. 4 support, 10 px radius)")
+    ap.add_argument("--disc-steps", type=int, default=10)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a kernel of "
@@ -68,6 +71,160 @@ def parse():
     ap.add_argument("--serve-load-seconds", type=float, default=2.0,
                     help="length of the saturating trace (0: skip it)")
     return ap.parse_args()
+
+
+def disc_pixel_counts(ux, uy, radius, width, height):
+    """Pixels of each disc inside the image (|u - u_s| < r): the samples per
+    surfel and frame of the disc workload."""
+    import numpy as np
+    R = int(np.ceil(radius)) + 1
+    off = np.arange(-R, R + 1)
+    out = np.zeros(ux.size, np.int64)
+    for dy in off:
+        for dx in off:
+            x = np.floor(ux.astype(np.float64)) + dx
+            y = np.floor(uy.astype(np.float64)) + dy
+            d2 = (x - ux) ** 2 + (y - uy) ** 2
+            out += ((d2 < radius * radius) & (x >= 0) & (y >= 0) & (x < width) & (y < height))
+    return out
+
+
+def disc_leg(ctx, kfs, storage, iters, steps, with_ablation):
+    """Disc surfels (Eq. 4) on the batch's keyframes: radius 10 px (the
+    paper's evaluation setting) on the 14 px lattice with three holes per
+    keyframe.  Times the batched disc Gauss-Newton kernel and the whole
+    keyframe step (render, empty-area search and placement, Gauss-Newton,
+    render)."""
+    import numpy as np
+    import torch
+
+    from paper_1910_01997_amd import engine
+    from paper_1910_01997_amd import surfgn as sg
+    from scenegen import make_disc_surfels
+
+    radius = 10.0
+    t0 = time.time()
+    sets = [make_disc_surfels(k, radius=radius) for k in kfs]
+    dks = [engine.DiscKeyframe.from_scene(ctx, k, d, capacity=d.ux.size + d.ux.size // 4 + 64,
+                                          storage=storage) for k, d in zip(kfs, sets)]
+    torch.cuda.synchronize()
+    log(f"disc leg: {sum(d.count for d in dks)} disc surfels on {len(dks)} keyframes "
+        f"({time.time() - t0:.1f}s)")
+    fields = ("inv_depth", "nx", "ny", "nz", "flags", "cost", "nvalid", "last_update")
+    snaps = [([getattr(d.state, f).clone() for f in fields], d.ux.clone(), d.uy.clone(), d.count)
+             for d in dks]
+
+    def restore():
+        for d, (st, ux, uy, m) in zip(dks, snaps):
+            for f, t in zip(fields, st):
+                getattr(d.state, f).copy_(t)
+            d.ux.copy_(ux)
+            d.uy.copy_(uy)
+            d.count = m
+
+    prm = sg.params(iters=iters)
+    pp = sg.sgn_disc_place_params(1.0, 2.0, sets[0].spacing)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+
+    def step():
+        ev[0].record()
+        for d in dks:
+            d.render()
+        ev[1].record()
+        for d in dks:
+            sg.sgn_disc_place(ctx.handle, d.item(), d.index_out.data_ptr(), d.capacity, pp,
+                              d.counts.data_ptr())
+        ev[2].record()
+        counts = torch.stack([d.counts for d in dks]).cpu().numpy()
+        for d, c in zip(dks, counts):
+            d.count += int(c[0])
+        engine.disc_update(ctx, dks, prm)
+        ev[3].record()
+        for d in dks:
+            d.render()
+        ev[4].record()
+        return counts
+
+    restore()
+    step()
+    torch.cuda.synchronize()
+    wall, phases, gn = [], [], []
+    for _ in range(steps):
+        restore()
+        torch.cuda.synchronize()
+        tw = time.perf_counter()
+        counts = step()
+        torch.cuda.synchronize()
+        wall.append(time.perf_counter() - tw)
+        gn.append(sg.sgn_last_kernel_ms(ctx.handle))
+        phases.append([ev[i].elapsed_time(ev[i + 1]) for i in range(4)])
+    ph = np.median(np.array(phases), axis=0)
+    gn_ms = float(np.median(gn))
+    n_old = sum(s.ux.size for s in sets)
+    n_new = int(counts[:, 0].sum())
+    # algorithmic samples: initialised surfels (new ones without neighbours
+    # carry id 0 and give none) x their disc pixels x frames x iterations
+    samples, sframes = 0, 0
+    for d in dks:
+        h = d.state_host()
+        ux, uy = d.centres()
+        use = (h["flags"] & sg.FLAG_UNINIT) == 0
+        npx = disc_pixel_counts(ux[use], uy[use], radius, d.width, d.height)
+        samples += int(npx.sum()) * d.img.n_nbr * iters
+        sframes += int(use.sum()) * d.img.n_nbr * iters
+    ops = samples * OPS_PER_SAMPLE
+    achieved = ops / (gn_ms * 1e-3) / 1e12
+    step_ms = float(np.median(wall)) * 1e3
+    out = {
+        "workload": f"{len(dks)} keyframes of the batch, disc surfels of radius {radius:g} px on a "
+                    f"{sets[0].spacing} px lattice with 3 holes each, {iters} GN iterations, "
+                    f"{storage} image storage; step = render, empty-area search and placement "
+                    f"(alpha 1, beta 2), Gauss-Newton over old and new surfels, render",
+        "surfels": n_old, "placed": n_new, "qualifying": int(counts[:, 1].sum()),
+        "gn_ms": gn_ms, "step_ms": step_ms,
+        "phase_ms": {"render": float(ph[0]), "place": float(ph[1]), "gn_with_table": float(ph[2]),
+                     "render_after": float(ph[3])},
+        "surfel_frame_per_s_gn": sframes / (gn_ms * 1e-3),
+        "surfel_frame_per_s_step": sframes / (step_ms * 1e-3),
+        "samples_per_s": samples / (gn_ms * 1e-3),
+        "samples_per_surfel_frame": samples / max(1, sframes),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "Tops/s (FP32 VALU lane-operations)", "frac": achieved / VALU_PEAK_TOPS,
+                     "kernel": "disc_gn_kernel"},
+    }
+    log(f"disc leg: step {step_ms:.3f} ms (render {ph[0]:.3f}, place {ph[1]:.3f}, GN {ph[2]:.3f}, "
+        f"render {ph[3]:.3f}); GN kernel {gn_ms:.3f} ms, {samples / (gn_ms * 1e-3):.4e} samples/s, "
+        f"frac {achieved / VALU_PEAK_TOPS:.3f}; placed {n_new}")
+    if with_ablation:
+        # full vs depth-only against the true planes, on the original discs
+        # that see one plane
+        def errors():
+            rel, ang = [], []
+            for d, sset in zip(dks, sets):
+                h = d.state_host()
+                m = sset.ux.size
+                bad = (sg.FLAG_DEGENERATE | sg.FLAG_FEW_SAMPLES | sg.FLAG_SOLVE_FAIL |
+                       sg.FLAG_REJECTED | sg.FLAG_UNINIT)
+                ok = sset.pure & ((h["flags"][:m] & bad) == 0)
+                rel.append(np.abs(h["inv_depth"][:m][ok] / sset.gt_id[ok] - 1))
+                g = h["n"][:m][ok].astype(np.float64)
+                cr = np.linalg.norm(np.cross(g, sset.gt_n[ok]), axis=1)
+                ang.append(np.degrees(np.arctan2(cr, np.abs((g * sset.gt_n[ok]).sum(1)))))
+            rel, ang = np.concatenate(rel), np.concatenate(ang)
+            return {"surfels": int(rel.size), "depth_rel_err_p50": float(np.median(rel)),
+                    "depth_rel_err_p90": float(np.percentile(rel, 90)),
+                    "normal_err_deg_p50": float(np.median(ang)),
+                    "normal_err_deg_p90": float(np.percentile(ang, 90))}
+        abl = {}
+        for name, p in (("full", prm), ("depth_only", sg.params(iters=iters, depth_only=True))):
+            restore()
+            engine.disc_update(ctx, dks, p)
+            torch.cuda.synchronize()
+            abl[name] = errors()
+        out["ablation"] = abl
+        log(f"disc ablation: {abl}")
+    restore()
+    return out
 
 
 def main():
@@ -237,6 +394,11 @@ def main():
             del odks, opool, oinit
         torch.cuda.synchronize()
 
+    discs = None
+    if not args.no_disc:
+        discs = disc_leg(ctx, kfs, args.storage, iters, args.disc_steps, not args.no_ablation)
+        torch.cuda.synchronize()
+
     plain = None
     if not args.no_plain:
         # the plain single-keyframe form on the same batch, one keyframe at a
@@ -337,6 +499,7 @@ def main():
         "cpu_baseline": cpu,
         "plain_form": plain,
         "precision_forms": forms,
+        "disc_surfels": discs,
         "ablation": ablation,
         "serving": serving,
         "device": {"name": info["name"], "arch": info["arch"], "cus": info["compute_units"]},

@@ -252,6 +252,76 @@ sgn_status sgn_transfer_surfels(sgn_ctx* ctx, const sgn_grid* src_grid, const sg
                                 const sgn_pose* pose, const sgn_grid* dst_grid, sgn_surfels* dst,
                                 uint8_t* dst_is_new, int32_t* dst_src_index);
 
+/* ------------------------------------------------------------ disc surfels
+ *
+ * Disc surfels (Eq. 4): surfel i is centred at u_s = (ux[i], uy[i]) in
+ * keyframe pixels and covers the pixels u inside the image with
+ * |u - u_s| < r.  The radius r is the same for every surfel of a keyframe
+ * (the paper sizes it so that every surfel covers the same screen area).
+ * Membership is decided as dx^2 + dy^2 < r^2 in double.  A disc item's
+ * kf.patch is not used; its surfel arrays (sgn_surfels fields plus ux, uy)
+ * hold `count` surfels, or more for sgn_disc_place. */
+typedef struct {
+    sgn_keyframe kf;
+    sgn_surfels surfels;        /* device arrays, [count] or more */
+    float* ux;                  /* device: centre x of each surfel (pixels) */
+    float* uy;                  /* device: centre y */
+    int32_t count;              /* surfels 0 .. count-1 */
+    float radius;               /* r in pixels, 0 < r <= 12 */
+} sgn_disc_item;
+
+/* Gauss-Newton over the disc surfels of n_items keyframes (Proposed
+ * Approach section, Eq. 5-9): as sgn_optimize_batch, with each surfel's
+ * cost summed over the pixels of its disc (Eq. 5 with u in s read as Eq. 4).
+ * One wavefront per surfel; per-surfel results do not depend on the batch.
+ * params as for tiles (beta_r unused).  Asynchronous on the context's
+ * stream; sgn_last_kernel_ms times the Gauss-Newton kernel.  Errors: invalid
+ * items or params (SGN_E_INVALID, nothing enqueued). */
+sgn_status sgn_disc_optimize(sgn_ctx* ctx, const sgn_disc_item* items, int32_t n_items,
+                             const sgn_params* params);
+
+/* Inverse Depth Calculation section with disc surfels: every surfel without
+ * the DEGENERATE or UNINIT flag whose plane does not contain its centre ray
+ * (|n . r_s| >= 1e-6) writes Eq. 3 into the pixels of its disc; the depth
+ * buffer keeps the closest (largest id_u > 0; equal values go to the lower
+ * index).  id_u is evaluated in double and rounded to float.
+ * inv_depth_out: device float [height * width] (row-major, width per row,
+ * 0 = no measurement); index_out: device int32 of the same shape (winning
+ * surfel, -1 = none) or NULL.  Reads only the item's surfels, intrinsics and
+ * image size.  The context keeps a scratch buffer of 12 bytes per pixel. */
+sgn_status sgn_disc_render(sgn_ctx* ctx, const sgn_disc_item* item, float* inv_depth_out,
+                           int32_t* index_out);
+
+/* Parameters of the empty-area search (the paper leaves alpha and beta open). */
+typedef struct {
+    float alpha;                /* a candidate needs no measurement within alpha r: (0, 4] */
+    float beta;                 /* neighbours own a pixel closer than beta r: (0, 4] */
+    int32_t spacing;            /* candidate lattice step in pixels: [1, 1024] */
+} sgn_disc_place_params;
+
+/* Surfel Initialization section with disc surfels.  Candidates are the
+ * pixels (spacing/2 + i spacing, spacing/2 + j spacing) of the keyframe; a
+ * candidate u_ns qualifies when every non-empty pixel of index_map lies
+ * farther than alpha r from it (integer squared distance against
+ * (alpha r)^2 in double).  The qualifying candidates, in row-by-row lattice
+ * order, become surfels count, count + 1, ... up to capacity - 1 (their
+ * centres are written to ux, uy).  Each new surfel is initialised from its
+ * neighbours: the surfels below `count` that own a pixel of index_map closer
+ * than beta r to u_ns (skipping DEGENERATE / UNINIT ones and planes through
+ * the camera centre), visited in index order; id_s = the mean of Eq. 3 of
+ * their planes at r_ns, n_s = the mean of their normals sign-aligned to the
+ * first, renormalised; with no usable neighbour the surfel gets id 0,
+ * n = (0, 0, -1) and UNINIT.  cost, nvalid and last_update of new surfels
+ * are zeroed.  index_map: device int32 [height * width], normally
+ * sgn_disc_render's index_out for surfels 0 .. count-1.  capacity: entries
+ * the surfel arrays and ux, uy hold (>= count).  counts_out: device int32[2]
+ * receiving the number placed and the number that qualified (which may
+ * exceed the room).  Asynchronous: read counts_out after synchronising to
+ * learn the new count. */
+sgn_status sgn_disc_place(sgn_ctx* ctx, const sgn_disc_item* item, const int32_t* index_map,
+                          int32_t capacity, const sgn_disc_place_params* params,
+                          int32_t* counts_out);
+
 /* Convert a float image (device, src_pitch elements per row) to dst->dtype
  * storage at dst->data: F16 with round-to-nearest-even, or U8 as
  * round(clamp(v / dst->scale, 0, 255)). */

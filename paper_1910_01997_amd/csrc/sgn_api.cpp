@@ -72,9 +72,11 @@ struct sgn_ctx {
     // graphs
     bool use_graphs = true;
     std::map<GraphKey, hipGraphExec_t> graphs;
-    // re-gridding scratch (12 bytes per destination tile, grown on demand)
-    void* regrid_scratch = nullptr;
-    size_t regrid_cap = 0;
+    // scratch of re-gridding (12 bytes per destination tile) and of the disc
+    // render and placement (12 bytes per pixel, one byte per candidate),
+    // grown on demand
+    void* scratch = nullptr;
+    size_t scratch_cap = 0;
 };
 
 namespace {
@@ -135,13 +137,15 @@ sgn_status check_image(const sgn_image& im, int W, int H, int dtype, const char*
     return SGN_OK;
 }
 
-sgn_status check_keyframe(const sgn_keyframe* kf, bool need_nbr) {
+// disc: the keyframe of disc surfels, whose patch is not used
+sgn_status check_keyframe(const sgn_keyframe* kf, bool need_nbr, bool disc = false) {
     if (!kf) return fail(SGN_E_INVALID, "null keyframe");
     const sgn_image& I = kf->kf;
     if (I.dtype < SGN_F32 || I.dtype > SGN_U8) return fail(SGN_E_INVALID, "bad dtype");
-    if (kf->patch != 4 && kf->patch != 8 && kf->patch != 16)
+    if (!disc && kf->patch != 4 && kf->patch != 8 && kf->patch != 16)
         return fail(SGN_E_UNSUPPORTED, "patch must be 4, 8 or 16");
-    if (I.width < kf->patch || I.height < kf->patch) return fail(SGN_E_INVALID, "image smaller than one surfel");
+    const int min_side = disc ? 2 : kf->patch;
+    if (I.width < min_side || I.height < min_side) return fail(SGN_E_INVALID, "image smaller than one surfel");
     if (I.width > 16384 || I.height > 16384) return fail(SGN_E_UNSUPPORTED, "image larger than 16384");
     sgn_status st = check_image(I, I.width, I.height, I.dtype, "keyframe image");
     if (st) return st;
@@ -158,6 +162,19 @@ sgn_status check_keyframe(const sgn_keyframe* kf, bool need_nbr) {
         for (int j = 0; j < 3; ++j)
             if (!std::isfinite(kf->pose[i].t[j])) return fail(SGN_E_INVALID, "non-finite translation");
     }
+    return SGN_OK;
+}
+
+sgn_status ensure_scratch(sgn_ctx* c, size_t need) {
+    if (need <= c->scratch_cap) return SGN_OK;
+    if (c->scratch) {
+        SGN_HIP(hipStreamSynchronize(c->stream));
+        SGN_HIP(hipFree(c->scratch));
+        c->scratch = nullptr;
+        c->scratch_cap = 0;
+    }
+    if (hipMalloc(&c->scratch, need) != hipSuccess) return fail(SGN_E_NOMEM, "scratch allocation failed");
+    c->scratch_cap = need;
     return SGN_OK;
 }
 
@@ -423,6 +440,126 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
     return run_part(2, do_render, enqueue_post);
 }
 
+sgn_status check_disc_item(const sgn_disc_item* it, bool need_nbr) {
+    if (!it) return fail(SGN_E_INVALID, "null disc item");
+    sgn_status st = check_keyframe(&it->kf, need_nbr, true);
+    if (st) return st;
+    if (!(it->radius > 0.f) || !(it->radius <= kDiscMaxRadius))
+        return fail(SGN_E_INVALID, "radius must be in (0, 12]");
+    if (it->count < 0) return fail(SGN_E_INVALID, "negative surfel count");
+    if (it->count > 0) {
+        if (!it->ux || !it->uy) return fail(SGN_E_INVALID, "null centre array");
+        st = check_surfels(&it->surfels);
+        if (st) return st;
+    }
+    return SGN_OK;
+}
+
+// Disc surfels: descriptor table (one KfDev per keyframe, items = surfels),
+// frame constants, then one wavefront per surfel.
+sgn_status run_disc_batch(sgn_ctx* c, const sgn_disc_item* items, int n, const sgn_params* prm) {
+    if (n < 1) return fail(SGN_E_INVALID, "empty batch");
+    if (!items) return fail(SGN_E_INVALID, "null items");
+    const int dtype = items[0].kf.kf.dtype;
+    int total_frames = 0;
+    int64_t total_surfels = 0;
+    for (int i = 0; i < n; ++i) {
+        sgn_status st = check_disc_item(&items[i], true);
+        if (st) return st;
+        if (items[i].kf.kf.dtype != dtype) return fail(SGN_E_INVALID, "batch items differ in dtype");
+        total_frames += items[i].kf.n_nbr;
+        total_surfels += items[i].count;
+    }
+    if (total_surfels > (int64_t)INT32_MAX / 2) return fail(SGN_E_UNSUPPORTED, "too many surfels in one batch");
+    sgn_status st = check_params(prm);
+    if (st) return st;
+    SGN_HIP(hipSetDevice(c->device));
+    TableLayout L = layout_for(n, total_frames);
+    st = ensure_table(c, L.total);
+    if (st) return st;
+    int slot = c->ring_next;
+    c->ring_next = (c->ring_next + 1) % kRingSlots;
+    if (c->ring_used[slot]) SGN_HIP(hipEventSynchronize(c->ring_ev[slot]));
+    char* host = (char*)c->host_ring[slot];
+    char* dev = (char*)c->dev_table;
+    BatchHeader* H = (BatchHeader*)(host + L.hdr_off);
+    KfDev* kfs = (KfDev*)(host + L.kf_off);
+    FrameDev* frs = (FrameDev*)(host + L.fr_off);
+    std::memset(host, 0, L.total);
+    int frame_base = 0, surfel_base = 0;
+    for (int i = 0; i < n; ++i) {
+        const sgn_disc_item& it = items[i];
+        const sgn_keyframe& kf = it.kf;
+        KfDev& D = kfs[i];
+        D.kf_img = kf.kf.data;
+        D.inv_depth = it.surfels.inv_depth;
+        D.nx = it.surfels.nx; D.ny = it.surfels.ny; D.nz = it.surfels.nz;
+        D.flags = it.surfels.flags;
+        D.cost = it.surfels.cost;
+        D.nvalid = it.surfels.nvalid;
+        D.last_update = it.surfels.last_update;
+        D.width = kf.kf.width;
+        D.height = kf.kf.height;
+        D.kf_pitch = kf.kf.pitch;
+        D.n_nbr = kf.n_nbr;
+        D.nbr_pitch_b = kf.n_nbr > 0 ? kf.nbr[0].pitch * (int32_t)dtype_size(kf.kf.dtype) : 0;
+        D.frame_base = frame_base;
+        D.item_base = surfel_base;
+        D.n_items = it.count;
+        D.surfel_base = surfel_base;
+        D.fx = (float)kf.K.fx; D.fy = (float)kf.K.fy; D.cx = (float)kf.K.cx; D.cy = (float)kf.K.cy;
+        D.fx_d = kf.K.fx; D.fy_d = kf.K.fy; D.cx_d = kf.K.cx; D.cy_d = kf.K.cy;
+        D.kf_scale = kf.kf.scale;
+        D.img_scale = kf.n_nbr > 0 ? kf.nbr[0].scale : 1.f;
+        D.disc_ux = it.ux;
+        D.disc_uy = it.uy;
+        D.disc_r = it.radius;
+        for (int f = 0; f < kf.n_nbr; ++f) {
+            if (kf.nbr[f].scale != D.img_scale)
+                return fail(SGN_E_UNSUPPORTED, "neighbour images of one keyframe must share a scale");
+            if (kf.nbr[f].pitch != kf.nbr[0].pitch)
+                return fail(SGN_E_UNSUPPORTED, "neighbour images of one keyframe must share a pitch");
+            FrameDev& F = frs[frame_base + f];
+            F.img = kf.nbr[f].data;
+            F.pitch = kf.nbr[f].pitch;
+            std::memcpy(F.R, kf.pose[f].R, sizeof(F.R));
+            std::memcpy(F.t, kf.pose[f].t, sizeof(F.t));
+        }
+        frame_base += kf.n_nbr;
+        surfel_base += it.count;
+    }
+    H->kfs = (KfDev*)(dev + L.kf_off);
+    H->frames = (FrameDev*)(dev + L.fr_off);
+    H->n_kf = n;
+    H->n_frames = total_frames;
+    H->total_items = surfel_base;
+    H->total_surfels = surfel_base;
+    H->iters = prm->iters;
+    H->huber_k = prm->huber_k;
+    H->kappa_fp64 = prm->kappa_fp64;
+    H->depth_only = prm->depth_only;
+    H->beta_r = prm->beta_r;
+    H->stamp = prm->stamp;
+    H->lm_lambda = prm->lm_lambda;
+    H->do_gn = 1;
+    H->n_queues = 1;
+    SGN_HIP(hipMemcpyAsync(dev, host, L.total, hipMemcpyHostToDevice, c->stream));
+    SGN_HIP(hipEventRecord(c->ring_ev[slot], c->stream));
+    c->ring_used[slot] = true;
+    const BatchHeader* dH = (const BatchHeader*)(dev + L.hdr_off);
+    const int frames_cap = (int)((c->table_cap - L.fr_off) / sizeof(FrameDev));
+    hipError_t e = launch_setup(dH, c->counters, frames_cap, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "setup launch");
+    if (surfel_base > 0) {
+        SGN_HIP(hipEventRecord(c->gn_start, c->stream));
+        e = launch_disc_gn(dtype, dH, surfel_base, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "disc Gauss-Newton launch");
+        SGN_HIP(hipEventRecord(c->gn_end, c->stream));
+        c->gn_timed = true;
+    }
+    return SGN_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -506,7 +643,7 @@ sgn_status sgn_destroy(sgn_ctx* c) {
     if (c->counters) hipFree(c->counters);
     if (c->gn_start) hipEventDestroy(c->gn_start);
     if (c->gn_end) hipEventDestroy(c->gn_end);
-    if (c->regrid_scratch) hipFree(c->regrid_scratch);
+    if (c->scratch) hipFree(c->scratch);
     delete c;
     return SGN_OK;
 }
@@ -613,18 +750,8 @@ sgn_status sgn_transfer_surfels(sgn_ctx* c, const sgn_grid* src_grid, const sgn_
         if (!std::isfinite(pose->t[i])) return fail(SGN_E_INVALID, "pose is not finite");
     SGN_HIP(hipSetDevice(c->device));
     const size_t n_dst = (size_t)(dst_grid->width / dst_grid->patch) * (dst_grid->height / dst_grid->patch);
-    const size_t need = n_dst * (sizeof(unsigned long long) + sizeof(int32_t));
-    if (need > c->regrid_cap) {
-        if (c->regrid_scratch) {
-            SGN_HIP(hipStreamSynchronize(c->stream));
-            SGN_HIP(hipFree(c->regrid_scratch));
-            c->regrid_scratch = nullptr;
-            c->regrid_cap = 0;
-        }
-        if (hipMalloc(&c->regrid_scratch, need) != hipSuccess)
-            return fail(SGN_E_NOMEM, "re-gridding scratch allocation failed");
-        c->regrid_cap = need;
-    }
+    st = ensure_scratch(c, n_dst * (sizeof(unsigned long long) + sizeof(int32_t)));
+    if (st) return st;
     RegridArgs a{};
     auto conv = [](const sgn_surfels* x) {
         return RegridSurfels{x->inv_depth, x->nx, x->ny, x->nz, x->flags, x->cost, x->nvalid,
@@ -640,12 +767,88 @@ sgn_status sgn_transfer_surfels(sgn_ctx* c, const sgn_grid* src_grid, const sgn_
     for (int i = 0; i < 3; ++i) a.t[i] = pose->t[i];
     a.src_w = src_grid->width; a.src_h = src_grid->height; a.src_patch = src_grid->patch;
     a.dst_w = dst_grid->width; a.dst_h = dst_grid->height; a.dst_patch = dst_grid->patch;
-    a.best = (unsigned long long*)c->regrid_scratch;
-    a.win = (int32_t*)((char*)c->regrid_scratch + n_dst * sizeof(unsigned long long));
+    a.best = (unsigned long long*)c->scratch;
+    a.win = (int32_t*)((char*)c->scratch + n_dst * sizeof(unsigned long long));
     a.is_new = dst_is_new;
     a.src_index = dst_src_index;
     hipError_t e = launch_regrid(a, c->stream);
     if (e != hipSuccess) return hip_fail(e, "re-gridding launch");
+    return SGN_OK;
+}
+
+sgn_status sgn_disc_optimize(sgn_ctx* c, const sgn_disc_item* items, int32_t n, const sgn_params* p) {
+    if (!c) return fail(SGN_E_INVALID, "null context");
+    return run_disc_batch(c, items, n, p);
+}
+
+sgn_status sgn_disc_render(sgn_ctx* c, const sgn_disc_item* item, float* inv_depth_out,
+                           int32_t* index_out) {
+    if (!c) return fail(SGN_E_INVALID, "null context");
+    sgn_status st = check_disc_item(item, false);
+    if (st) return st;
+    if (!inv_depth_out) return fail(SGN_E_INVALID, "null output");
+    SGN_HIP(hipSetDevice(c->device));
+    const int W = item->kf.kf.width, H = item->kf.kf.height;
+    const size_t npix = (size_t)W * (size_t)H;
+    st = ensure_scratch(c, npix * (sizeof(unsigned long long) + sizeof(int32_t)));
+    if (st) return st;
+    DiscRenderArgs a{};
+    a.inv_depth = item->surfels.inv_depth;
+    a.nx = item->surfels.nx; a.ny = item->surfels.ny; a.nz = item->surfels.nz;
+    a.flags = item->surfels.flags;
+    a.ux = item->ux; a.uy = item->uy;
+    a.count = item->count;
+    a.width = W; a.height = H;
+    a.radius = item->radius;
+    a.fx = item->kf.K.fx; a.fy = item->kf.K.fy; a.cx = item->kf.K.cx; a.cy = item->kf.K.cy;
+    a.key = (unsigned long long*)c->scratch;
+    a.idx = (int32_t*)((char*)c->scratch + npix * sizeof(unsigned long long));
+    a.inv_depth_out = inv_depth_out;
+    a.index_out = index_out;
+    hipError_t e = launch_disc_render(a, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "disc render launch");
+    return SGN_OK;
+}
+
+sgn_status sgn_disc_place(sgn_ctx* c, const sgn_disc_item* item, const int32_t* index_map,
+                          int32_t capacity, const sgn_disc_place_params* pp, int32_t* counts_out) {
+    if (!c) return fail(SGN_E_INVALID, "null context");
+    sgn_status st = check_disc_item(item, false);
+    if (st) return st;
+    if (!index_map || !pp || !counts_out) return fail(SGN_E_INVALID, "null argument");
+    if (!item->ux || !item->uy) return fail(SGN_E_INVALID, "null centre array");
+    st = check_surfels(&item->surfels);
+    if (st) return st;
+    if (capacity < item->count) return fail(SGN_E_INVALID, "capacity below the surfel count");
+    if (!(pp->alpha > 0.f) || !(pp->alpha <= 4.f)) return fail(SGN_E_INVALID, "alpha must be in (0, 4]");
+    if (!(pp->beta > 0.f) || !(pp->beta <= 4.f)) return fail(SGN_E_INVALID, "beta must be in (0, 4]");
+    if (pp->spacing < 1 || pp->spacing > 1024) return fail(SGN_E_INVALID, "spacing must be in [1, 1024]");
+    SGN_HIP(hipSetDevice(c->device));
+    const int W = item->kf.kf.width, H = item->kf.kf.height, sp = pp->spacing;
+    const int cand_x = W > sp / 2 ? (W - sp / 2 + sp - 1) / sp : 0;
+    const int cand_y = H > sp / 2 ? (H - sp / 2 + sp - 1) / sp : 0;
+    st = ensure_scratch(c, (size_t)cand_x * (size_t)cand_y + 256);
+    if (st) return st;
+    DiscPlaceArgs a{};
+    a.inv_depth = item->surfels.inv_depth;
+    a.nx = item->surfels.nx; a.ny = item->surfels.ny; a.nz = item->surfels.nz;
+    a.flags = item->surfels.flags;
+    a.cost = item->surfels.cost;
+    a.nvalid = item->surfels.nvalid;
+    a.last_update = item->surfels.last_update;
+    a.ux = item->ux; a.uy = item->uy;
+    a.index_map = index_map;
+    a.first = item->count;
+    a.room = capacity - item->count;
+    a.width = W; a.height = H; a.spacing = sp;
+    a.cand_x = cand_x; a.cand_y = cand_y;
+    a.radius = item->radius; a.alpha = pp->alpha; a.beta = pp->beta;
+    a.fx = (float)item->kf.K.fx; a.fy = (float)item->kf.K.fy;
+    a.cx = (float)item->kf.K.cx; a.cy = (float)item->kf.K.cy;
+    a.cand_flag = (uint8_t*)c->scratch;
+    a.counts = counts_out;
+    hipError_t e = launch_disc_place(a, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "disc placement launch");
     return SGN_OK;
 }
 

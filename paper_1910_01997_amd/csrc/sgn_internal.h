@@ -36,6 +36,12 @@ struct KfDev {
     double fx_d, fy_d, cx_d, cy_d;               // intrinsics as given (double)
     float fx, fy, cx, cy;                        // the same, rounded to float
     float kf_scale, img_scale, pad0, pad1;
+    // disc surfels (Eq. 4): centres of the surfels, radius in pixels; null
+    // and 0 for tiles
+    const float* disc_ux;
+    const float* disc_uy;
+    float disc_r;
+    int32_t pad2;
 };
 
 // Per-neighbour-frame descriptor.  R and t are the caller's pose in double;
@@ -142,6 +148,54 @@ hipError_t launch_render(const BatchHeader* hdr, int grid, hipStream_t s);
 hipError_t launch_gn(const GnVariant& v, const BatchHeader* hdr, uint32_t* counters,
                      int persistent, int grid_blocks, hipStream_t s);
 hipError_t launch_regrid(const RegridArgs& a, hipStream_t s);
+
+// Disc surfels (Eq. 4).
+constexpr float kDiscMaxRadius = 12.f;
+// Gauss-Newton over the disc surfels of a batch: one wavefront per surfel,
+// items are surfels (KfDev::item_base = surfel_base, n_items = count).
+hipError_t launch_disc_gn(int dtype, const BatchHeader* hdr, int total_surfels, hipStream_t s);
+// Depth-buffered render of one keyframe's discs into key/idx scratch (one
+// 64-bit key and one index per pixel), then into the outputs.
+struct DiscRenderArgs {
+    const float* inv_depth;
+    const float* nx;
+    const float* ny;
+    const float* nz;
+    const uint32_t* flags;
+    const float* ux;
+    const float* uy;
+    int32_t count, width, height;
+    float radius;
+    double fx, fy, cx, cy;
+    unsigned long long* key;      // scratch [width * height]
+    int32_t* idx;                 // scratch [width * height]
+    float* inv_depth_out;         // [width * height]
+    int32_t* index_out;           // [width * height] or null
+};
+hipError_t launch_disc_render(const DiscRenderArgs& a, hipStream_t s);
+// The search for empty areas on the lattice (spacing/2 + i spacing, ...),
+// placement of the qualifying candidates as surfels first .. and their
+// neighbour initialisation from the index map.
+struct DiscPlaceArgs {
+    float* inv_depth;
+    float* nx;
+    float* ny;
+    float* nz;
+    uint32_t* flags;
+    float* cost;
+    uint32_t* nvalid;
+    uint32_t* last_update;
+    float* ux;
+    float* uy;
+    const int32_t* index_map;     // [width * height]
+    int32_t first, room;          // existing surfels; free entries after them
+    int32_t width, height, spacing, cand_x, cand_y;   // lattice of cand_x x cand_y candidates
+    float radius, alpha, beta;
+    float fx, fy, cx, cy;
+    uint8_t* cand_flag;           // scratch [cand_x * cand_y]
+    int32_t* counts;              // device [2]: placed, qualifying
+};
+hipError_t launch_disc_place(const DiscPlaceArgs& a, hipStream_t s);
 hipError_t launch_quantize(const float* src, int src_pitch, void* dst, int dst_pitch,
                            int width, int height, int dtype, float scale, hipStream_t s);
 // Workgroups of 256 threads of the chosen GN variant that fit on one CU.

@@ -349,6 +349,39 @@ constexpr int kPairWords = 12;
 enum : int {
     W_HX0 = 0, W_HX1, W_KX, W_EX, W_HY0, W_HY1, W_KY, W_EY, W_QZ, W_X0, W_Y0, W_B0
 };
+// The pair words of every neighbour frame for the anchor point (qbx, qby),
+// one frame per lane (lanes below nf), formed in double and rounded once,
+// into the wavefront's LDS words.
+__device__ __forceinline__ void stage_pair_words(const FrameDev* frames, int nf, int lane,
+                                                 double qbx, double qby, float* pairs) {
+    if (lane < nf) {
+        const gptr<FrameDev> F = (gptr<FrameDev>)(frames + lane);
+        const gptr<double> hm = F->hm;
+        const gptr<double> kt = F->kt;
+        const double Qx = fma(hm[0], qbx, fma(hm[1], qby, hm[2]));
+        const double Qy = fma(hm[3], qbx, fma(hm[4], qby, hm[5]));
+        const double Qz = fma(hm[6], qbx, fma(hm[7], qby, hm[8]));
+        double X0 = 0.0, Y0 = 0.0;
+        if (Qz > 0.0) {
+            X0 = rint(fmin(fmax(Qx / Qz, -20000.0), 20000.0));
+            Y0 = rint(fmin(fmax(Qy / Qz, -20000.0), 20000.0));
+        }
+        float* w = pairs + lane * kPairWords;
+        w[W_HX0] = (float)(hm[0] - X0 * hm[6]);
+        w[W_HX1] = (float)(hm[1] - X0 * hm[7]);
+        w[W_KX] = (float)(kt[0] - X0 * kt[2]);
+        w[W_EX] = (float)(Qx - X0 * Qz);
+        w[W_HY0] = (float)(hm[3] - Y0 * hm[6]);
+        w[W_HY1] = (float)(hm[4] - Y0 * hm[7]);
+        w[W_KY] = (float)(kt[1] - Y0 * kt[2]);
+        w[W_EY] = (float)(Qy - Y0 * Qz);
+        w[W_QZ] = (float)Qz;
+        w[W_X0] = __int_as_float((int)X0);
+        w[W_Y0] = __int_as_float((int)Y0);
+        w[W_B0] = 0.f;
+    }
+}
+
 // Levenberg-Marquardt acceptance: largest relative rise of the mean cost.
 constexpr float kLmAcceptRise = 1e-4f;
 
@@ -597,6 +630,135 @@ __device__ __forceinline__ void tangent_basis(float nx, float ny, float nz, floa
     b2z = nx * b1y - ny * b1x;
 }
 
+// One Gauss-Newton step of a surfel on its owner lane, from the reduced
+// normal equations sm[] (J^T W J, J^T W r, valid count and cost, laid out as
+// SM_*): FEW_SAMPLES below three samples; otherwise the equilibrated 3 x 3
+// system (diagonal scaled by 1 + lam) is solved in float by its adjugate, or
+// in double by Cholesky when its Frobenius condition exceeds kappa_fp64 or a
+// pivot is not safely positive; then id_s += d0 and n = normalise(n + d1 b1 +
+// d2 b2) (id_s alone for the depth-only ablation).  Returns true with the
+// candidate state when a step is proposed; sets the flags otherwise (a
+// rejected step raises lam tenfold when damping is on).
+__device__ __forceinline__ bool owner_step(const float* sm, bool alive, bool last,
+                                           bool depth_only, bool lm, float kap2, float& lam,
+                                           float id, float nx, float ny, float nz, float b1x,
+                                           float b1y, float b1z, float b2x, float b2y, float b2z,
+                                           uint32_t& flags, float& cost_out, int& nv_out, int& nv,
+                                           float& cost_here, float& id_c, float& nx_c,
+                                           float& ny_c, float& nz_c) {
+    bool cand = false;
+    const float H00 = sm[SM_H00], H01 = sm[SM_H01], H02 = sm[SM_H02];
+    const float H11 = sm[SM_H11], H12 = sm[SM_H12], H22 = sm[SM_H22];
+    const float bb0 = sm[SM_B0], bb1 = sm[SM_B1], bb2 = sm[SM_B2];
+    nv = (int)sm[SM_NV];
+    cost_here = sm[SM_COST];
+    if (alive && last) cost_out = cost_here;
+    if (alive) {
+        nv_out = nv;
+        float d0s = 0.f, d1s = 0.f, d2s = 0.f;
+        bool ok = true;
+        if (nv < 3) {
+            flags |= F_FEW_SAMPLES;
+            ok = false;
+        }
+        const float dd = 1.f + lam;          // (H + lam diag H): equilibrated diagonal
+        if (ok && depth_only) {
+            if (H00 > 0.f && isfinite(H00)) {
+                d0s = -bb0 * rcp_fast(H00 * dd);
+            } else {
+                flags |= F_SOLVE_FAIL;
+                ok = false;
+            }
+        } else if (ok) {
+            // equilibrate: E = D^-1/2 H D^-1/2 (unit diagonal)
+            const float maxd = fmaxf(H00, fmaxf(H11, H22));
+            bool need64 = !(H00 > 0.f) || !(H11 > 0.f) || !(H22 > 0.f) || !isfinite(maxd);
+            if (!need64) {
+                const float e0 = __frsqrt_rn(H00), e1 = __frsqrt_rn(H11), e2 = __frsqrt_rn(H22);
+                const float e01 = H01 * e0 * e1, e02 = H02 * e0 * e2, e12 = H12 * e1 * e2;
+                // adjugate and determinant of E (diagonal dd = 1 + lambda)
+                const float d2 = dd * dd;
+                const float c00 = fmaf(-e12, e12, d2), c11 = fmaf(-e02, e02, d2);
+                const float c22 = fmaf(-e01, e01, d2);
+                const float c01 = fmaf(e02, e12, -dd * e01), c02 = fmaf(e01, e12, -dd * e02);
+                const float c12 = fmaf(e01, e02, -dd * e12);
+                const float det = fmaf(e01, c01, fmaf(e02, c02, dd * c00));
+                // kappa_F(E)^2 = ||E||_F^2 ||adj E||_F^2 / det^2  (>= kappa_2(E)^2)
+                const float fro2 = 3.f * d2 + 2.f * (e01 * e01 + e02 * e02 + e12 * e12);
+                const float adj2 = c00 * c00 + c11 * c11 + c22 * c22 +
+                                   2.f * (c01 * c01 + c02 * c02 + c12 * c12);
+                // raw Cholesky pivots are H_jj times the equilibrated ones
+                const float p1 = c22 * rcp_fast(dd);   // dd - e01^2 / dd (only compared)
+                const float p2 = det * rcp_fast(c22);  // (only compared)
+                need64 = !(fro2 * adj2 <= kap2 * det * det) || !(det > 0.f) || !(c22 > 0.f) ||
+                         !(H11 * p1 > 1e-10f * maxd * dd) || !(H22 * p2 > 1e-10f * maxd * dd);
+                if (!need64) {
+                    const float bh0 = bb0 * e0, bh1 = bb1 * e1, bh2 = bb2 * e2;
+                    const float idet = rcp_fast(det);
+                    d0s = -(c00 * bh0 + c01 * bh1 + c02 * bh2) * idet * e0;
+                    d1s = -(c01 * bh0 + c11 * bh1 + c12 * bh2) * idet * e1;
+                    d2s = -(c02 * bh0 + c12 * bh1 + c22 * bh2) * idet * e2;
+                }
+            }
+            if (need64) {
+                flags |= F_FP64_SOLVE;
+                double dd0 = 0.0, dd1 = 0.0, dd2 = 0.0;
+                const double dmp = 1.0 + (double)lam;
+                if (solve3_fp64((double)H00 * dmp, H01, H02, (double)H11 * dmp, H12,
+                                (double)H22 * dmp, bb0, bb1, bb2, dd0, dd1, dd2)) {
+                    d0s = (float)dd0; d1s = (float)dd1; d2s = (float)dd2;
+                } else {
+                    flags |= F_SOLVE_FAIL;
+                    ok = false;
+                }
+            }
+        }
+        if (ok) {
+            // update: id_s += d0; n = normalise(n + d1 b1 + d2 b2) (the
+            // depth-only ablation moves id_s alone and keeps n)
+            id_c = id + d0s;
+            nx_c = nx; ny_c = ny; nz_c = nz;
+            bool ok_step;
+            if (depth_only) {
+                ok_step = (id_c > 0.f) && isfinite(id_c);
+            } else {
+                const float mx = fmaf(d1s, b1x, fmaf(d2s, b2x, nx));
+                const float my = fmaf(d1s, b1y, fmaf(d2s, b2y, ny));
+                const float mz = fmaf(d1s, b1z, fmaf(d2s, b2z, nz));
+                const float l2 = mx * mx + my * my + mz * mz;
+                ok_step = (id_c > 0.f) && isfinite(id_c) && (l2 > 0.f) && isfinite(l2);
+                if (ok_step) {
+                    const float il = __frsqrt_rn(l2);
+                    nx_c = mx * il; ny_c = my * il; nz_c = mz * il;
+                }
+            }
+            if (!ok_step) {
+                flags |= F_REJECTED;
+                if (lm) lam *= 10.f;
+            } else {
+                cand = true;
+            }
+        }
+    }
+    return cand;
+}
+
+// Levenberg-Marquardt acceptance of a candidate on its owner lane: the
+// candidate's cost cost2 over nv2 valid samples against the current cost
+// over nv.  Accepted unless the mean Huber cost per valid sample rises by
+// more than kLmAcceptRise (relative; smaller rises are below the float noise
+// of the cost sums, where the decision would be a coin toss) or fewer than
+// three samples remain.  lam shrinks tenfold (floor 1e-9) on acceptance and
+// grows tenfold on refusal.
+__device__ __forceinline__ bool lm_accept(float cost2, int nv2, float cost_here, int nv, float& lam) {
+    if (nv2 < 3 || !(cost2 * (float)nv <= cost_here * (float)nv2 * (1.f + kLmAcceptRise))) {
+        lam *= 10.f;
+        return false;
+    }
+    lam = fmaxf(lam * 0.1f, 1e-9f);
+    return true;
+}
+
 // The fused Gauss-Newton kernel.
 //
 // Mapping.  A work item is a block of surfels inside one aligned anchor
@@ -703,34 +865,9 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
             // warp constants of every frame for this anchor block, one frame
             // per lane, in double
             wave_sync();
-            if (lane < nf) {
-                const double qbx = (double)bpx + 0.5 * (double)(G.ab * S - 1);
-                const double qby = (double)bpy + 0.5 * (double)(G.ab * S - 1);
-                const gptr<FrameDev> F = (gptr<FrameDev>)(hdr->frames + Kd->frame_base + lane);
-                const gptr<double> hm = F->hm;
-                const gptr<double> kt = F->kt;
-                const double Qx = fma(hm[0], qbx, fma(hm[1], qby, hm[2]));
-                const double Qy = fma(hm[3], qbx, fma(hm[4], qby, hm[5]));
-                const double Qz = fma(hm[6], qbx, fma(hm[7], qby, hm[8]));
-                double X0 = 0.0, Y0 = 0.0;
-                if (Qz > 0.0) {
-                    X0 = rint(fmin(fmax(Qx / Qz, -20000.0), 20000.0));
-                    Y0 = rint(fmin(fmax(Qy / Qz, -20000.0), 20000.0));
-                }
-                float* w = pairs + lane * kPairWords;
-                w[W_HX0] = (float)(hm[0] - X0 * hm[6]);
-                w[W_HX1] = (float)(hm[1] - X0 * hm[7]);
-                w[W_KX] = (float)(kt[0] - X0 * kt[2]);
-                w[W_EX] = (float)(Qx - X0 * Qz);
-                w[W_HY0] = (float)(hm[3] - Y0 * hm[6]);
-                w[W_HY1] = (float)(hm[4] - Y0 * hm[7]);
-                w[W_KY] = (float)(kt[1] - Y0 * kt[2]);
-                w[W_EY] = (float)(Qy - Y0 * Qz);
-                w[W_QZ] = (float)Qz;
-                w[W_X0] = __int_as_float((int)X0);
-                w[W_Y0] = __int_as_float((int)Y0);
-                w[W_B0] = 0.f;
-            }
+            stage_pair_words(hdr->frames + Kd->frame_base, nf, lane,
+                             (double)bpx + 0.5 * (double)(G.ab * S - 1),
+                             (double)bpy + 0.5 * (double)(G.ab * S - 1), pairs);
         }
         // the frame table pointer is wave-uniform: keep it in SGPRs
         const uint64_t fr_bits = (uint64_t)(const void*)(hdr->frames + Kd->frame_base);
@@ -880,6 +1017,8 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
             float id_c = 0.f, nx_c = 0.f, ny_c = 0.f, nz_c = 0.f, cost_here = 0.f;
             int nv = 0;
             if (owner) {
+                // the step of owner_step, written out here: as a call it costs
+                // this kernel seven VGPRs (and a wavefront of occupancy)
                 const float* sm = lsm + own * SM_WORDS;
                 const float H00 = sm[SM_H00], H01 = sm[SM_H01], H02 = sm[SM_H02];
                 const float H11 = sm[SM_H11], H12 = sm[SM_H12], H22 = sm[SM_H22];
@@ -976,10 +1115,8 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                 }
             }
             if (lm) {
-                // Levenberg-Marquardt: accept the step unless the mean Huber
-                // cost per valid sample rises by more than kLmAcceptRise
-                // (relative; smaller rises are below the float noise of the
-                // cost sums, where the decision would be a coin toss).
+                // Levenberg-Marquardt: the candidate's cost over the pixels,
+                // then the acceptance test (lm_accept)
                 float inv_cc = 0.f;
                 bool cand_ok = cand;
                 if (owner && cand) {
@@ -1027,15 +1164,7 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                 wave_sync();
                 if (owner && cand_ok) {
                     const float* sm = lsm + own * SM_WORDS;
-                    const float cost2 = sm[SM_COST];
-                    const int nv2 = __float_as_int(sm[SM_NV]);
-                    if (nv2 < 3 ||
-                        !(cost2 * (float)nv <= cost_here * (float)nv2 * (1.f + kLmAcceptRise))) {
-                        lam *= 10.f;
-                        cand_ok = false;
-                    } else {
-                        lam = fmaxf(lam * 0.1f, 1e-9f);
-                    }
+                    cand_ok = lm_accept(sm[SM_COST], __float_as_int(sm[SM_NV]), cost_here, nv, lam);
                 }
                 cand = cand_ok;
             }
@@ -1344,6 +1473,559 @@ hipError_t launch_gn(const GnVariant& v, const BatchHeader* hdr, uint32_t* count
     if (!f) return hipErrorInvalidValue;
     void* args[] = {(void*)&hdr, (void*)&counters, (void*)&persistent};
     return hipLaunchKernel(f, dim3(grid_blocks), dim3(kBlockThreads), args, 0, s);
+}
+
+// ------------------------------------------------------------ disc surfels --
+//
+// Disc surfels (Eq. 4): surfel s is centred at u_s = (ux, uy) in keyframe
+// pixels and covers the pixels u (inside the image) with |u - u_s| < r, r
+// the same for every surfel of a keyframe (0 < r <= kDiscMaxRadius).
+// Membership is decided as dx^2 + dy^2 < r^2 in double (dx = x - ux is
+// exact there).  A disc's pixels are numbered row by row; a wavefront holds
+// one surfel and lane l takes pixels l, l + 64, ... (at most kDiscPPL).
+
+constexpr int kDiscMaxRows = 2 * (int)kDiscMaxRadius + 2;
+constexpr int kDiscPPL = 8;        // 512 pixels > pi (12 + sqrt(2)/2)^2, the largest disc
+constexpr int kDiscRowWords = 2 * kDiscMaxRows + 2;
+
+struct DiscRows {
+    int y0, nrows, total;
+};
+
+// The rows of one disc (clipped to the image): lanes below the row count
+// find their row's run of pixels (a disc meets a row in one run), lane 0
+// forms the running counts.  row_x0[i] is the first column of row y0 + i and
+// row_start[i] the number of disc pixels before it.  A non-finite centre
+// gives an empty disc.  The caller synchronises the wavefront before.
+__device__ DiscRows disc_rows(float ux, float uy, float radius, int W, int H, int lane,
+                              int* row_x0, int* row_start) {
+#pragma clang fp contract(off)
+    DiscRows d{0, 0, 0};
+    const double cx = (double)ux, cy = (double)uy, r = (double)radius, r2 = r * r;
+    if (!isfinite(cx) || !isfinite(cy)) return d;
+    const double xlo = fmax(0.0, ceil(cx - r)), xhi = fmin((double)(W - 1), floor(cx + r));
+    const double ylo = fmax(0.0, ceil(cy - r)), yhi = fmin((double)(H - 1), floor(cy + r));
+    if (!(xlo <= xhi) || !(ylo <= yhi) || yhi - ylo >= (double)(kDiscMaxRows - 1)) return d;
+    const int x0 = (int)xlo, x1 = (int)xhi;
+    d.y0 = (int)ylo;
+    d.nrows = (int)yhi - d.y0 + 1;
+    if (lane < d.nrows) {
+        const double dy = (double)(d.y0 + lane) - cy;
+        int first = x0, cnt = 0;
+        for (int x = x0; x <= x1; ++x) {
+            const double dx = (double)x - cx;
+            if (dx * dx + dy * dy < r2) {
+                if (cnt == 0) first = x;
+                ++cnt;
+            }
+        }
+        row_x0[lane] = first;
+        row_start[lane + 1] = cnt;
+    }
+    wave_sync();
+    if (lane == 0) {
+        int acc = 0;
+        row_start[0] = 0;
+        for (int i = 0; i < d.nrows; ++i) {
+            acc += row_start[i + 1];
+            row_start[i + 1] = acc;
+        }
+    }
+    wave_sync();
+    d.total = min(row_start[d.nrows], kWaveSize * kDiscPPL);
+    return d;
+}
+
+// Pixel k (< total) of a disc.
+__device__ __forceinline__ void disc_pixel(const DiscRows& d, const int* row_x0, const int* row_start,
+                                           int k, int& x, int& y) {
+    int i = 0;
+    while (row_start[i + 1] <= k) ++i;
+    x = row_x0[i] + (k - row_start[i]);
+    y = d.y0 + i;
+}
+
+// Gauss-Newton over disc surfels: one wavefront per surfel (the batch's
+// items are its surfels), the same per-pixel terms, frame loop, reduction
+// and owner-lane step as the tile kernel, over the disc's pixels.  The warp
+// constants are anchored at the pixel nearest the centre.
+template <typename T>
+__global__ __launch_bounds__(kBlockThreads) void disc_gn_kernel(const BatchHeader* __restrict__ hdr_,
+                                                                int total) {
+    const cptr<BatchHeader> hdr = (cptr<BatchHeader>)hdr_;
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const int wave = threadIdx.x >> 6;
+    const int item = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlockThreads / kWaveSize) + wave);
+    if (item >= total) return;
+    __shared__ float4 s_pairs[kBlockThreads / kWaveSize][kMaxNbr * kPairWords / 4];
+    __shared__ float4 s_state[kBlockThreads / kWaveSize][ST_WORDS / 4];
+    __shared__ float4 s_sums[kBlockThreads / kWaveSize][SM_WORDS / 4];
+    __shared__ int s_rows[kBlockThreads / kWaveSize][kDiscRowWords];
+    float* const pairs = (float*)s_pairs[wave];
+    float* const lst = (float*)s_state[wave];
+    float* const lsm = (float*)s_sums[wave];
+    int* const row_x0 = s_rows[wave];
+    int* const row_start = s_rows[wave] + kDiscMaxRows;
+
+    const cptr<KfDev> kfs = (cptr<KfDev>)hdr->kfs;
+    const int kidx = find_kf(kfs, hdr->n_kf, item, 0);
+    const cptr<KfDev> Kd = kfs + kidx;
+    const int sidx = item - Kd->item_base;
+    const int iters = hdr->iters;
+    const float hk = hdr->huber_k;
+    const float kap2 = hdr->kappa_fp64 * hdr->kappa_fp64;
+    const bool depth_only = hdr->depth_only != 0;
+    const float lm0 = hdr->lm_lambda;
+    const bool lm = lm0 > 0.f;
+    const int W = Kd->width, H = Kd->height;
+    const int nf = Kd->n_nbr;
+    const float img_scale = Kd->img_scale;
+    const unsigned pitch_b = (unsigned)Kd->nbr_pitch_b;
+    const unsigned img_bytes = pitch_b * (unsigned)H;
+    const unsigned wm1 = (unsigned)(W - 1), hm1 = (unsigned)(H - 1);
+    const float fxk = Kd->fx, fyk = Kd->fy, cxk = Kd->cx, cyk = Kd->cy;
+    const float ux = ((gptr<float>)Kd->disc_ux)[sidx];
+    const float uy = ((gptr<float>)Kd->disc_uy)[sidx];
+
+    wave_sync();
+    const DiscRows d = disc_rows(ux, uy, Kd->disc_r, W, H, lane, row_x0, row_start);
+    const int nslots = (d.total + kWaveSize - 1) / kWaveSize;
+    // anchor pixel (nearest the centre; any fixed point works for the local
+    // warp coordinates)
+    const int ax = (int)rint(fmin(fmax((double)ux, -1e6), 1e6));
+    const int ay = (int)rint(fmin(fmax((double)uy, -1e6), 1e6));
+    stage_pair_words(hdr->frames + Kd->frame_base, nf, lane, (double)ax, (double)ay, pairs);
+    const uint64_t fr_bits = (uint64_t)(const void*)(hdr->frames + Kd->frame_base);
+    const uint32_t fr_lo = __builtin_amdgcn_readfirstlane((uint32_t)fr_bits);
+    const uint32_t fr_hi = __builtin_amdgcn_readfirstlane((uint32_t)(fr_bits >> 32));
+    const cptr<FrameDev> fr = (cptr<FrameDev>)(((uint64_t)fr_hi << 32) | fr_lo);
+
+    // this lane's pixels: offsets from the anchor and keyframe values
+    float bdx[kDiscPPL], bdy[kDiscPPL], ikf[kDiscPPL];
+    bool pv[kDiscPPL];
+    const gptr<T> kimg = (gptr<T>)Kd->kf_img;
+#pragma unroll
+    for (int j = 0; j < kDiscPPL; ++j) {
+        const int k = lane + kWaveSize * j;
+        pv[j] = k < d.total;
+        bdx[j] = 0.f;
+        bdy[j] = 0.f;
+        ikf[j] = 0.f;
+        if (pv[j]) {
+            int x, y;
+            disc_pixel(d, row_x0, row_start, k, x, y);
+            bdx[j] = (float)(x - ax);
+            bdy[j] = (float)(y - ay);
+            ikf[j] = ldg<T>(kimg + ((unsigned)y * (unsigned)Kd->kf_pitch + (unsigned)x)) * Kd->kf_scale;
+        }
+    }
+    // r_u - r_s = (anchor offset + (anchor - u_s)) / f
+    const float fox = (float)((double)ax - (double)ux), foy = (float)((double)ay - (double)uy);
+    const float ifx = 1.f / fxk, ify = 1.f / fyk;
+
+    // owner (lane 0): the surfel's state
+    const bool owner = lane == 0;
+    const float rsx = (ux - cxk) / fxk, rsy = (uy - cyk) / fyk;
+    float id = ((gptr<float>)Kd->inv_depth)[sidx];
+    float nx = ((gptr<float>)Kd->nx)[sidx];
+    float ny = ((gptr<float>)Kd->ny)[sidx];
+    float nz = ((gptr<float>)Kd->nz)[sidx];
+    uint32_t flags = ((gptr<uint32_t>)Kd->flags)[sidx] & ~F_GN_BITS;
+    bool alive = true, updated = false;
+    float cost_out = 0.f;
+    int nv_out = 0;
+    float lam = lm0;
+    float b1x = 0.f, b1y = 0.f, b1z = 0.f, b2x = 0.f, b2y = 0.f, b2z = 0.f;
+
+    for (int it = 0; it < iters; ++it) {
+        const bool last = (it == iters - 1);
+        if (owner) {
+            const float c = nx * rsx + ny * rsy + nz;
+            if (alive && fabsf(c) < 1e-6f) {
+                flags |= F_DEGENERATE;
+                alive = false;
+                cost_out = 0.f;
+                nv_out = 0;
+            }
+            tangent_basis(nx, ny, nz, b1x, b1y, b1z, b2x, b2y, b2z);
+            lst[ST_ID] = id; lst[ST_NX] = nx; lst[ST_NY] = ny; lst[ST_NZ] = nz;
+            lst[ST_B1X] = b1x; lst[ST_B1Y] = b1y; lst[ST_B1Z] = b1z;
+            lst[ST_B2X] = b2x; lst[ST_B2Y] = b2y; lst[ST_B2Z] = b2z;
+            lst[ST_INVC] = rcp_fast(c);
+            lst[ST_RSX] = rsx; lst[ST_RSY] = rsy;
+            lst[ST_ALIVE] = alive ? 1.f : 0.f;
+        }
+        wave_sync();
+        {
+            const float4 sa = *(const float4*)(lst + 0);
+            const float4 sb = *(const float4*)(lst + 4);
+            const float4 sc = *(const float4*)(lst + 8);
+            const float2 sd = *(const float2*)(lst + 12);
+            const float sid = sa.x, snx = sa.y, sny = sa.z;
+            const float sb1x = sb.x, sb1y = sb.y, sb1z = sb.z;
+            const float sb2x = sb.w, sb2y = sc.x, sb2z = sc.y, inv_c = sc.z, srsx = sc.w;
+            const float srsy = sd.x;
+            const bool salive = sd.y != 0.f;
+            float ph[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            float pnv = 0.f, pcs = 0.f;
+#pragma unroll
+            for (int j = 0; j < kDiscPPL; ++j) {
+                if (j < nslots) {
+                    const float drx = (bdx[j] + fox) * ifx, dry = (bdy[j] + foy) * ify;
+                    const float sigma = (snx * drx + sny * dry) * inv_c;
+                    const float idu = fmaf(sid, sigma, sid);
+                    const float dx3 = fmaf(-sigma, srsx, drx);
+                    const float dy3 = fmaf(-sigma, srsy, dry);
+                    const float dz3 = -sigma;
+                    const float kk = sid * inv_c;
+                    const float g0 = 1.f + sigma;
+                    const float g1 = depth_only ? 0.f : kk * (sb1x * dx3 + sb1y * dy3 + sb1z * dz3);
+                    const float g2 = depth_only ? 0.f : kk * (sb2x * dx3 + sb2y * dy3 + sb2z * dz3);
+                    const bool pix_ok = salive && pv[j] && (idu > 0.f);
+                    float A = 0.f, B = 0.f, cst = 0.f;
+                    int nvl = 0;
+                    if (last || lm)
+                        frame_loop<T, true>(pairs, fr, nf, bdx[j], bdy[j], idu, pix_ok, pitch_b, img_bytes,
+                                            wm1, hm1, ikf[j], hk, img_scale, A, B, cst, nvl);
+                    else
+                        frame_loop<T, false>(pairs, fr, nf, bdx[j], bdy[j], idu, pix_ok, pitch_b,
+                                             img_bytes, wm1, hm1, ikf[j], hk, img_scale, A, B, cst, nvl);
+                    {
+#pragma clang fp contract(off)
+                        const float ag0 = A * g0, ag1 = A * g1, ag2 = A * g2;
+                        ph[0] += ag0 * g0; ph[1] += ag0 * g1; ph[2] += ag0 * g2;
+                        ph[3] += ag1 * g1; ph[4] += ag1 * g2; ph[5] += ag2 * g2;
+                        ph[6] += B * g0; ph[7] += B * g1; ph[8] += B * g2;
+                        pnv += (float)nvl;
+                        pcs += cst;
+                    }
+                }
+            }
+            float s0, s1, s2, s3, s4;
+            {
+#pragma clang fp contract(off)
+                const bool odd = (lane & 1) != 0;
+                s0 = pair_sum<kWaveSize>(ph[0], ph[1], odd);
+                s1 = pair_sum<kWaveSize>(ph[2], ph[3], odd);
+                s2 = pair_sum<kWaveSize>(ph[4], ph[5], odd);
+                s3 = pair_sum<kWaveSize>(ph[6], ph[7], odd);
+                s4 = pair_sum<kWaveSize>(ph[8], pnv, odd);
+            }
+            float cs = 0.f;
+            if (last || lm) cs = group_sum<kWaveSize>(pcs);
+            if (lane < 2) {
+                float* o = lsm + lane;
+                o[0] = s0; o[2] = s1; o[4] = s2; o[6] = s3; o[8] = s4;
+                if (lane == 0) o[SM_COST] = cs;
+            }
+        }
+        wave_sync();
+        bool cand = false;
+        float id_c = 0.f, nx_c = 0.f, ny_c = 0.f, nz_c = 0.f, cost_here = 0.f;
+        int nv = 0;
+        if (owner)
+            cand = owner_step(lsm, alive, last, depth_only, lm, kap2, lam, id, nx, ny, nz, b1x, b1y, b1z,
+                              b2x, b2y, b2z, flags, cost_out, nv_out, nv, cost_here, id_c, nx_c, ny_c,
+                              nz_c);
+        if (lm) {
+            float inv_cc = 0.f;
+            bool cand_ok = cand;
+            if (owner && cand) {
+                const float cc = nx_c * rsx + ny_c * rsy + nz_c;
+                if (fabsf(cc) < 1e-6f) {             // candidate plane contains r_s
+                    flags |= F_REJECTED;
+                    lam *= 10.f;
+                    cand_ok = false;
+                }
+                inv_cc = rcp_fast(cc);
+            }
+            if (owner) {
+                lst[ST_ID] = id_c; lst[ST_NX] = nx_c; lst[ST_NY] = ny_c; lst[ST_NZ] = nz_c;
+                lst[ST_INVC] = inv_cc;
+                lst[ST_ALIVE] = cand_ok ? 1.f : 0.f;
+            }
+            wave_sync();
+            {
+                const float4 sa = *(const float4*)(lst + 0);
+                const float inv_c = lst[ST_INVC];
+                const bool calive = lst[ST_ALIVE] != 0.f;
+                float cst2 = 0.f;
+                int nv2l = 0;
+#pragma unroll
+                for (int j = 0; j < kDiscPPL; ++j) {
+                    if (j < nslots) {
+                        const float drx = (bdx[j] + fox) * ifx, dry = (bdy[j] + foy) * ify;
+                        const float sig = (sa.y * drx + sa.z * dry) * inv_c;
+                        const float idu_c = fmaf(sa.x, sig, sa.x);
+                        frame_cost<T>(pairs, fr, nf, bdx[j], bdy[j], idu_c, calive && pv[j] && (idu_c > 0.f),
+                                      pitch_b, img_bytes, wm1, hm1, ikf[j], hk, img_scale, cst2, nv2l);
+                    }
+                }
+                const float c2 = group_sum<kWaveSize>(cst2);
+                const int n2 = group_sum<kWaveSize>(nv2l);
+                if (lane == 0) {
+                    lsm[SM_COST] = c2;
+                    lsm[SM_NV] = __int_as_float(n2);
+                }
+            }
+            wave_sync();
+            if (owner && cand_ok) cand_ok = lm_accept(lsm[SM_COST], __float_as_int(lsm[SM_NV]), cost_here, nv, lam);
+            cand = cand_ok;
+        }
+        if (owner && cand) {
+            id = id_c;
+            nx = nx_c; ny = ny_c; nz = nz_c;
+            updated = true;
+        }
+    }
+    if (owner) {
+        ((gmut<float>)Kd->inv_depth)[sidx] = id;
+        ((gmut<float>)Kd->nx)[sidx] = nx;
+        ((gmut<float>)Kd->ny)[sidx] = ny;
+        ((gmut<float>)Kd->nz)[sidx] = nz;
+        ((gmut<uint32_t>)Kd->flags)[sidx] = flags;
+        ((gmut<float>)Kd->cost)[sidx] = iters > 0 ? cost_out : 0.f;
+        ((gmut<uint32_t>)Kd->nvalid)[sidx] = (uint32_t)(iters > 0 ? nv_out : 0);
+        if (updated) ((gmut<uint32_t>)Kd->last_update)[sidx] = hdr->stamp;
+    }
+}
+
+// Depth-buffered render (Inverse Depth Calculation section): every usable
+// surfel writes Eq. 3 into the pixels of its disc, the closest (largest
+// id_u) wins and equal values go to the lower index.  Pass 0 takes the
+// maximum of the double bit patterns (positive doubles order like their
+// bits), pass 1 the lowest index among the surfels that reach it, and the
+// resolve step writes the outputs.  id_u is evaluated in double in the
+// printed form of Eq. 3, id_u = (r_u . n) / ((r_s / id_s) . n).
+__global__ void disc_clear_kernel(unsigned long long* __restrict__ key, int32_t* __restrict__ idx, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        key[i] = 0ull;
+        idx[i] = 0x7fffffff;
+    }
+}
+
+template <int PASS>
+__global__ __launch_bounds__(kBlockThreads) void disc_scatter_kernel(DiscRenderArgs a) {
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const int wave = threadIdx.x >> 6;
+    const int s = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlockThreads / kWaveSize) + wave);
+    if (s >= a.count) return;
+    if (a.flags[s] & (F_DEGENERATE | F_UNINIT)) return;
+    __shared__ int s_rows[kBlockThreads / kWaveSize][kDiscRowWords];
+    int* const row_x0 = s_rows[wave];
+    int* const row_start = s_rows[wave] + kDiscMaxRows;
+    const double n0 = a.nx[s], n1 = a.ny[s], n2 = a.nz[s], ids = a.inv_depth[s];
+    const double rs0 = ((double)a.ux[s] - a.cx) / a.fx, rs1 = ((double)a.uy[s] - a.cy) / a.fy;
+    if (fabs(n0 * rs0 + n1 * rs1 + n2 * 1.0) < 1e-6) return;
+    const double ps0 = rs0 / ids, ps1 = rs1 / ids, ps2 = 1.0 / ids;
+    const double den = ps0 * n0 + ps1 * n1 + ps2 * n2;
+    wave_sync();
+    const DiscRows d = disc_rows(a.ux[s], a.uy[s], a.radius, a.width, a.height, lane, row_x0, row_start);
+    for (int k = lane; k < d.total; k += kWaveSize) {
+        int x, y;
+        disc_pixel(d, row_x0, row_start, k, x, y);
+        const double ru0 = ((double)x - a.cx) / a.fx, ru1 = ((double)y - a.cy) / a.fy;
+        const double v = (ru0 * n0 + ru1 * n1 + 1.0 * n2) / den;
+        if (!(v > 0.0) || !isfinite(v)) continue;
+        const size_t o = (size_t)y * (size_t)a.width + (size_t)x;
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+        if (PASS == 0)
+            atomicMax(a.key + o, bits);
+        else if (a.key[o] == bits)
+            atomicMin(a.idx + o, s);
+    }
+}
+
+__global__ void disc_resolve_kernel(DiscRenderArgs a) {
+    const int n = a.width * a.height;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const unsigned long long k = a.key[i];
+        a.inv_depth_out[i] = k ? (float)__longlong_as_double((long long)k) : 0.f;
+        if (a.index_out) a.index_out[i] = k ? a.idx[i] : -1;
+    }
+}
+
+// The search for empty areas (Surfel Initialization section): one thread per
+// lattice candidate u_ns = (spacing/2 + i spacing, spacing/2 + j spacing); it
+// qualifies when no non-empty pixel of the index map lies within alpha r
+// (integer squared distance against (alpha r)^2 in double).
+__global__ void disc_search_kernel(DiscPlaceArgs a) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.cand_x * a.cand_y) return;
+    const int cx = a.spacing / 2 + (c % a.cand_x) * a.spacing;
+    const int cy = a.spacing / 2 + (c / a.cand_x) * a.spacing;
+    const double ar = (double)a.alpha * (double)a.radius;
+    const double ar2 = ar * ar;
+    const int reach = (int)floor(ar);
+    bool empty = true;
+    for (int y = max(0, cy - reach); y <= min(a.height - 1, cy + reach) && empty; ++y) {
+        const int dy = y - cy;
+        for (int x = max(0, cx - reach); x <= min(a.width - 1, cx + reach); ++x) {
+            const int dx = x - cx;
+            if (a.index_map[(size_t)y * a.width + x] >= 0 && (double)(dx * dx + dy * dy) <= ar2) {
+                empty = false;
+                break;
+            }
+        }
+    }
+    a.cand_flag[c] = empty ? 1 : 0;
+}
+
+// Placement: the qualifying candidates in lattice order become surfels
+// first, first + 1, ... (as many as there is room for); counts[0] = placed,
+// counts[1] = qualifying.  One workgroup scans the flags in chunks.
+__global__ __launch_bounds__(1024) void disc_compact_kernel(DiscPlaceArgs a) {
+    __shared__ int s_wave[1024 / kWaveSize + 1];
+    const int n = a.cand_x * a.cand_y;
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const int wave = threadIdx.x >> 6;
+    constexpr int kWaves = 1024 / kWaveSize;
+    int base = 0;
+    for (int c0 = 0; c0 < n; c0 += 1024) {
+        const int c = c0 + (int)threadIdx.x;
+        const bool f = c < n && a.cand_flag[c] != 0;
+        const unsigned long long ball = __ballot(f);
+        const int below = __popcll(ball & ((1ull << lane) - 1ull));
+        if (lane == 0) s_wave[wave] = __popcll(ball);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int acc = 0;
+            for (int w = 0; w < kWaves; ++w) {
+                const int t = s_wave[w];
+                s_wave[w] = acc;
+                acc += t;
+            }
+            s_wave[kWaves] = acc;
+        }
+        __syncthreads();
+        const int rank = base + s_wave[wave] + below;
+        if (f && rank < a.room) {
+            const int cx = a.spacing / 2 + (c % a.cand_x) * a.spacing;
+            const int cy = a.spacing / 2 + (c / a.cand_x) * a.spacing;
+            a.ux[a.first + rank] = (float)cx;
+            a.uy[a.first + rank] = (float)cy;
+        }
+        base += s_wave[kWaves];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.counts[0] = min(base, a.room);
+        a.counts[1] = base;
+    }
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+    for (int m = 1; m < kWaveSize; m <<= 1) v = min(v, __shfl_xor(v, m));
+    return v;
+}
+
+// Neighbour initialisation of the placed surfels (Surfel Initialization
+// section), one wavefront each: the neighbours are the surfels below
+// `first` that own a pixel of the index map closer than beta r to the new
+// centre, visited in index order (the wavefront finds the next smallest
+// index each round); id = mean of Eq. 3 of their planes at the new ray,
+// n = mean of their normals sign-aligned to the first, renormalised; none
+// usable: UNINIT with id 0 and n = (0, 0, -1).
+__global__ __launch_bounds__(kBlockThreads) void disc_init_kernel(DiscPlaceArgs a) {
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const int wave = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlockThreads / kWaveSize) + wave);
+    if (w >= a.counts[0]) return;
+    const int i = a.first + w;
+    const int cx = (int)a.ux[i], cy = (int)a.uy[i];
+    const double br = (double)a.beta * (double)a.radius;
+    const double br2 = br * br;
+    const int reach = (int)ceil(br);
+    const int side = 2 * reach + 1, npix = side * side;
+    const float rnx = ((float)cx - a.cx) / a.fx, rny = ((float)cy - a.cy) / a.fy;
+    int last = -1, count = 0;
+    float id_sum = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, rx = 0.f, ry = 0.f, rz = 0.f;
+    for (;;) {
+        int best = 0x7fffffff;
+        for (int k = lane; k < npix; k += kWaveSize) {
+            const int dy = k / side - reach, dx = k % side - reach;
+            const int x = cx + dx, y = cy + dy;
+            if (x < 0 || y < 0 || x >= a.width || y >= a.height) continue;
+            const int j = a.index_map[(size_t)y * a.width + x];
+            if (j <= last || j >= a.first) continue;
+            if ((double)(dx * dx + dy * dy) < br2) best = min(best, j);
+        }
+        const int j = __builtin_amdgcn_readfirstlane(wave_min(best));
+        if (j == 0x7fffffff) break;
+        last = j;
+        if (a.flags[j] & (F_UNINIT | F_DEGENERATE)) continue;
+        const float njx = a.nx[j], njy = a.ny[j], njz = a.nz[j];
+        const float rjx = (a.ux[j] - a.cx) / a.fx, rjy = (a.uy[j] - a.cy) / a.fy;
+        const float cj = njx * rjx + njy * rjy + njz;
+        if (fabsf(cj) < 1e-6f) continue;
+        // Eq. 3 of plane j at the new surfel's ray
+        const float id = a.inv_depth[j] * (njx * rnx + njy * rny + njz) / cj;
+        if (count == 0) { rx = njx; ry = njy; rz = njz; }
+        const float sg = (njx * rx + njy * ry + njz * rz) < 0.f ? -1.f : 1.f;
+        id_sum += id;
+        sx += sg * njx; sy += sg * njy; sz += sg * njz;
+        ++count;
+    }
+    if (lane != 0) return;
+    bool ok = count > 0;
+    float idn = 0.f, l2 = 0.f;
+    if (ok) {
+        const float inv = 1.0f / (float)count;
+        idn = id_sum * inv;
+        sx *= inv; sy *= inv; sz *= inv;
+        l2 = sx * sx + sy * sy + sz * sz;
+        ok = (l2 > 0.f) && (idn > 0.f) && isfinite(idn) && isfinite(l2);
+    }
+    if (ok) {
+        const float il = 1.0f / sqrtf(l2);
+        a.inv_depth[i] = idn;
+        a.nx[i] = sx * il; a.ny[i] = sy * il; a.nz[i] = sz * il;
+        a.flags[i] = 0u;
+    } else {
+        a.inv_depth[i] = 0.f;
+        a.nx[i] = 0.f; a.ny[i] = 0.f; a.nz[i] = -1.f;
+        a.flags[i] = F_UNINIT;
+    }
+    a.cost[i] = 0.f;
+    a.nvalid[i] = 0u;
+    a.last_update[i] = 0u;
+}
+
+hipError_t launch_disc_gn(int dtype, const BatchHeader* hdr, int total_surfels, hipStream_t s) {
+    if (total_surfels <= 0) return hipSuccess;
+    const int waves = kBlockThreads / kWaveSize;
+    const dim3 grid((total_surfels + waves - 1) / waves);
+    if (dtype == 0) disc_gn_kernel<float><<<grid, kBlockThreads, 0, s>>>(hdr, total_surfels);
+    else if (dtype == 1) disc_gn_kernel<_Float16><<<grid, kBlockThreads, 0, s>>>(hdr, total_surfels);
+    else disc_gn_kernel<uint8_t><<<grid, kBlockThreads, 0, s>>>(hdr, total_surfels);
+    return hipGetLastError();
+}
+
+hipError_t launch_disc_render(const DiscRenderArgs& a, hipStream_t s) {
+    const int n = a.width * a.height;
+    const int fill = std::min((n + 255) / 256, 4096);
+    disc_clear_kernel<<<fill, 256, 0, s>>>(a.key, a.idx, n);
+    if (a.count > 0) {
+        const int waves = kBlockThreads / kWaveSize;
+        const dim3 grid((a.count + waves - 1) / waves);
+        disc_scatter_kernel<0><<<grid, kBlockThreads, 0, s>>>(a);
+        disc_scatter_kernel<1><<<grid, kBlockThreads, 0, s>>>(a);
+    }
+    disc_resolve_kernel<<<fill, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_disc_place(const DiscPlaceArgs& a, hipStream_t s) {
+    const int n = a.cand_x * a.cand_y;
+    if (n > 0) disc_search_kernel<<<(n + 255) / 256, 256, 0, s>>>(a);
+    disc_compact_kernel<<<1, 1024, 0, s>>>(a);
+    const int most = std::min(a.room, n);
+    if (most > 0) {
+        const int waves = kBlockThreads / kWaveSize;
+        disc_init_kernel<<<(most + waves - 1) / waves, kBlockThreads, 0, s>>>(a);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace sgn

@@ -116,6 +116,85 @@ def update_batch(ctx: sg.Context, dks: Sequence[DeviceKeyframe], prm: sg.sgn_par
     return items
 
 
+class DiscKeyframe:
+    """Disc surfels (Eq. 4) of one keyframe on the GPU: the images (as in
+    DeviceKeyframe), the surfel state and centres with room for `capacity`
+    surfels (the first `count` in use), and a rendered inverse-depth and
+    surfel-index map."""
+
+    def __init__(self, ctx: sg.Context, kf_image, nbr_images, R, t, K, radius: float, ux, uy,
+                 init_id, init_n, flags=None, capacity: Optional[int] = None, storage: str = "f32",
+                 u8_scale: float = U8_SCALE):
+        dev = torch.device("cuda", ctx.device)
+        self.ctx = ctx
+        self.img = DeviceKeyframe(ctx, kf_image, nbr_images, R, t, K, 1, np.zeros(1, np.float32),
+                                  np.zeros((1, 3), np.float32), storage=storage, render=False,
+                                  u8_scale=u8_scale)
+        self.K, self.R, self.t = self.img.K, self.img.R, self.img.t
+        self.width, self.height = self.img.width, self.img.height
+        self.radius = float(radius)
+        m = int(np.asarray(ux).size)
+        cap = max(m, int(capacity) if capacity else m)
+        self.capacity = cap
+        self.count = m
+        pad = lambda a, v: np.concatenate([np.asarray(a, np.float32).reshape(-1),
+                                           np.full(cap - m, v, np.float32)])
+        idn = pad(init_id, 0.0)
+        nn = np.concatenate([np.asarray(init_n, np.float32).reshape(-1, 3),
+                             np.tile(np.float32([0.0, 0.0, -1.0]), (cap - m, 1))])
+        fl = np.zeros(cap, np.uint32)
+        if flags is not None:
+            fl[:m] = np.asarray(flags, np.uint32).reshape(-1)
+        self.state = sg.SurfelState.from_arrays(idn, nn, flags=fl, device=dev)
+        self.ux = torch.as_tensor(pad(ux, 0.0), device=dev)
+        self.uy = torch.as_tensor(pad(uy, 0.0), device=dev)
+        self.inv_depth_out = torch.zeros((self.height, self.width), dtype=torch.float32, device=dev)
+        self.index_out = torch.full((self.height, self.width), -1, dtype=torch.int32, device=dev)
+        self.counts = torch.zeros(2, dtype=torch.int32, device=dev)
+
+    @classmethod
+    def from_scene(cls, ctx, kf, discs, capacity=None, storage="f32", u8_scale: float = U8_SCALE):
+        return cls(ctx, kf.kf_image, kf.nbr_images, kf.R, kf.t, kf.K, discs.radius, discs.ux,
+                   discs.uy, discs.init_id, discs.init_n, capacity=capacity, storage=storage,
+                   u8_scale=u8_scale)
+
+    def item(self) -> sg.sgn_disc_item:
+        return sg.sgn_disc_item(self.img.view.c, self.state.c, self.ux.data_ptr(), self.uy.data_ptr(),
+                                int(self.count), float(self.radius))
+
+    def dequantized_images(self):
+        return self.img.dequantized_images()
+
+    def render(self):
+        sg.sgn_disc_render(self.ctx.handle, self.item(), self.inv_depth_out.data_ptr(),
+                           self.index_out.data_ptr())
+
+    def place(self, alpha: float = 1.0, beta: float = 2.0, spacing: int = 0):
+        """Empty-area search and placement from the current index map; waits
+        for the device and returns (placed, qualifying)."""
+        sp = int(spacing) if spacing else int(np.floor(self.radius * np.sqrt(2.0)))
+        sg.sgn_disc_place(self.ctx.handle, self.item(), self.index_out.data_ptr(), self.capacity,
+                          sg.sgn_disc_place_params(float(alpha), float(beta), sp),
+                          self.counts.data_ptr())
+        placed, found = (int(v) for v in self.counts.cpu().tolist())
+        self.count += placed
+        return placed, found
+
+    def centres(self):
+        return (self.ux[:self.count].cpu().numpy(), self.uy[:self.count].cpu().numpy())
+
+    def state_host(self) -> dict:
+        h = self.state.to_host()
+        return {k: v[:self.count] for k, v in h.items()}
+
+
+def disc_update(ctx: sg.Context, dks: Sequence[DiscKeyframe], prm: sg.sgn_params):
+    """Gauss-Newton over the disc surfels of several keyframes in one launch."""
+    items = sg.disc_array([d.item() for d in dks])
+    sg.sgn_disc_optimize(ctx.handle, items, len(dks), prm)
+    return items
+
+
 _STATE_FIELDS = ("inv_depth", "nx", "ny", "nz", "flags", "cost", "nvalid", "last_update")
 
 

@@ -36,7 +36,7 @@ EXPORTED = [
     "sgn_create", "sgn_destroy", "sgn_set_stream", "sgn_init_from_neighbours",
     "sgn_optimize_keyframe", "sgn_render_inverse_depth", "sgn_optimize_batch", "sgn_autotune",
     "sgn_quantize", "sgn_last_kernel_ms", "sgn_device_info", "sgn_status_str", "sgn_last_error",
-    "sgn_version", "sgn_transfer_surfels",
+    "sgn_version", "sgn_transfer_surfels", "sgn_disc_optimize", "sgn_disc_render", "sgn_disc_place",
 ]
 
 
@@ -95,6 +95,15 @@ class sgn_batch_item(C.Structure):
                 ("inv_depth_out", C.c_void_p), ("index_out", C.c_void_p)]
 
 
+class sgn_disc_item(C.Structure):
+    _fields_ = [("kf", sgn_keyframe), ("surfels", sgn_surfels), ("ux", C.c_void_p),
+                ("uy", C.c_void_p), ("count", C.c_int32), ("radius", C.c_float)]
+
+
+class sgn_disc_place_params(C.Structure):
+    _fields_ = [("alpha", C.c_float), ("beta", C.c_float), ("spacing", C.c_int32)]
+
+
 class sgn_device_props(C.Structure):
     _fields_ = [("device", C.c_int32), ("compute_units", C.c_int32), ("xcds", C.c_int32),
                 ("clock_khz", C.c_int32), ("memory_clock_khz", C.c_int32),
@@ -142,6 +151,13 @@ def lib():
         L.sgn_transfer_surfels.argtypes = [vp, C.POINTER(sgn_grid), C.POINTER(sgn_surfels),
                                            C.POINTER(sgn_pose), C.POINTER(sgn_grid),
                                            C.POINTER(sgn_surfels), vp, vp]
+        L.sgn_disc_optimize.restype = st
+        L.sgn_disc_optimize.argtypes = [vp, C.POINTER(sgn_disc_item), C.c_int32, C.POINTER(sgn_params)]
+        L.sgn_disc_render.restype = st
+        L.sgn_disc_render.argtypes = [vp, C.POINTER(sgn_disc_item), vp, vp]
+        L.sgn_disc_place.restype = st
+        L.sgn_disc_place.argtypes = [vp, C.POINTER(sgn_disc_item), vp, C.c_int32,
+                                     C.POINTER(sgn_disc_place_params), vp]
         L.sgn_last_kernel_ms.restype = st
         L.sgn_last_kernel_ms.argtypes = [vp, C.POINTER(C.c_float)]
         L.sgn_device_info.restype = st
@@ -224,6 +240,29 @@ def sgn_transfer_surfels(ctx, src_grid: sgn_grid, src: sgn_surfels, pose: sgn_po
                                      C.c_void_p(dst_is_new_ptr),
                                      C.c_void_p(dst_src_index_ptr) if dst_src_index_ptr else None),
           "sgn_transfer_surfels")
+
+
+def sgn_disc_optimize(ctx, items, n: int, params: sgn_params):
+    check(lib().sgn_disc_optimize(C.c_void_p(ctx), items, int(n), C.byref(params)), "sgn_disc_optimize")
+
+
+def sgn_disc_render(ctx, item: sgn_disc_item, inv_depth_ptr: int, index_ptr: int = 0):
+    check(lib().sgn_disc_render(C.c_void_p(ctx), C.byref(item), C.c_void_p(inv_depth_ptr),
+                                C.c_void_p(index_ptr or None)), "sgn_disc_render")
+
+
+def sgn_disc_place(ctx, item: sgn_disc_item, index_map_ptr: int, capacity: int,
+                   params: sgn_disc_place_params, counts_ptr: int):
+    check(lib().sgn_disc_place(C.c_void_p(ctx), C.byref(item), C.c_void_p(index_map_ptr),
+                               int(capacity), C.byref(params), C.c_void_p(counts_ptr)),
+          "sgn_disc_place")
+
+
+def disc_array(items: List[sgn_disc_item]):
+    arr = (sgn_disc_item * len(items))()
+    for i, it in enumerate(items):
+        arr[i] = it
+    return arr
 
 
 def grid_of(K, width: int, height: int, patch: int) -> sgn_grid:

@@ -16,3 +16,4 @@ from .scene import (  # noqa: F401
     stream_specs,
     rotation_about,
 )
+from .discs import DiscSet, lattice, make_disc_surfels  # noqa: F401,E402

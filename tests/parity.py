@@ -25,7 +25,7 @@ def angle_deg(n1, n2):
 
 def oracle_keyframe(dk):
     kf, nb = dk.dequantized_images()
-    return oracle.OracleKeyframe(dk.K, kf, nb, dk.R, dk.t, dk.patch)
+    return oracle.OracleKeyframe(dk.K, kf, nb, dk.R, dk.t, getattr(dk, "patch", 1))
 
 
 def oracle_state(init_id, init_n, flags=None):
@@ -34,9 +34,19 @@ def oracle_state(init_id, init_n, flags=None):
                             np.asarray(init_n, np.float32).astype(np.float64), flags)
 
 
-def run_oracle(dk, init_id, init_n, is_new, params: "oracle.OracleParams", subset=None):
+def run_oracle(dk, init_id, init_n, is_new, params: "oracle.OracleParams", subset=None, disc=None,
+               init_flags=None):
+    """Oracle run from the device's starting state (with its flags, if
+    given).  disc = (ux, uy, radius) selects disc surfels (Eq. 4) with those
+    centres; is_new is then unused."""
     ok = oracle_keyframe(dk)
-    st = oracle_state(init_id, init_n)
+    st = oracle_state(init_id, init_n, init_flags)
+    if disc is not None:
+        ux, uy, radius = disc
+        oracle.disc_optimize(ok, st, np.asarray(ux, np.float32).astype(np.float64),
+                             np.asarray(uy, np.float32).astype(np.float64),
+                             float(np.float32(radius)), params, subset=subset)
+        return ok, st
     if is_new is not None and np.any(is_new):
         if subset is not None:
             # the initialisation reads only non-new surfels, so a subset's
@@ -102,7 +112,7 @@ def as_dev(st: dict) -> dict:
             "flags": st["flags"], "nvalid": st["nvalid"], "cost": st["cost"]}
 
 
-def unstable_set(dk, init_id, init_n, is_new, params, base, subset=None):
+def unstable_set(dk, init_id, init_n, is_new, params, base, subset=None, disc=None, init_flags=None):
     """Surfels whose oracle result is not stable under the conditioning
     probe, and the probe runs' final states."""
     import dataclasses
@@ -112,21 +122,28 @@ def unstable_set(dk, init_id, init_n, is_new, params, base, subset=None):
     runs = []
     for seed in (PROBE_SEEDS if idx.size > SMALL_CASE else PROBE_SEEDS_SMALL):
         p = dataclasses.replace(params, perturb=PROBE_EPS, perturb_seed=seed)
-        _, st = run_oracle(dk, init_id, init_n, is_new, p, subset=subset)
+        _, st = run_oracle(dk, init_id, init_n, is_new, p, subset=subset, disc=disc, init_flags=init_flags)
         c = compare(as_dev(st), base, idx=idx)
         bad[idx] |= ~c["within"] | ~c["same_flags"]
         runs.append(st)
     return bad, runs
 
 
-def final_costs(okf, states: dict, idx, huber_k=9.0 / 255.0):
+def final_costs(okf, states: dict, idx, huber_k=9.0 / 255.0, disc=None):
     """Oracle Huber cost at each listed surfel's state (id, n)."""
-    gw = okf.grid[0]
     out = np.zeros(len(idx))
     for j, i in enumerate(idx):
         n = np.array(states["n"][i], np.float64)
-        _, _, cost, nv = oracle.linearize(okf, int(i) % gw, int(i) // gw, float(states["inv_depth"][i]),
-                                          n / np.linalg.norm(n), huber_k)
+        n = n / np.linalg.norm(n)
+        if disc is not None:
+            ux, uy, radius = disc
+            _, _, cost, nv = oracle.disc_linearize(okf, (float(np.float32(ux[i])), float(np.float32(uy[i]))),
+                                                   float(np.float32(radius)), float(states["inv_depth"][i]),
+                                                   n, huber_k)
+        else:
+            gw = okf.grid[0]
+            _, _, cost, nv = oracle.linearize(okf, int(i) % gw, int(i) // gw, float(states["inv_depth"][i]),
+                                              n, huber_k)
         out[j] = cost
     return out
 
@@ -139,20 +156,24 @@ class ParityResult(tuple):
     gross_fraction: float = 0.0  # unstable surfels above UNSTABLE_GROSS_RATIO x worst outcome
 
 
-def check_parity(dk, dev: dict, init_id, init_n, is_new, params, subset=None, label=""):
-    """Oracle base run + conditioning probe; returns a ParityResult."""
-    okf, base = run_oracle(dk, init_id, init_n, is_new, params, subset=subset)
+def check_parity(dk, dev: dict, init_id, init_n, is_new, params, subset=None, label="", disc=None,
+                 init_flags=None):
+    """Oracle base run + conditioning probe; returns a ParityResult.  disc =
+    (ux, uy, radius) for disc surfels; init_flags: the starting flags."""
+    okf, base = run_oracle(dk, init_id, init_n, is_new, params, subset=subset, disc=disc,
+                           init_flags=init_flags)
     idx = np.arange(base["inv_depth"].shape[0]) if subset is None else np.asarray(subset)
     c = compare(dev, base, idx=idx)
-    uns_all, runs = unstable_set(dk, init_id, init_n, is_new, params, base, subset=subset)
+    uns_all, runs = unstable_set(dk, init_id, init_n, is_new, params, base, subset=subset, disc=disc,
+                                 init_flags=init_flags)
     uns = uns_all[idx]
     ratios = np.zeros(0)
     mean_ratio, gross = 1.0, 0.0
     ua = idx[uns]
     cg = refs = None
     if ua.size:
-        cg = final_costs(okf, dev, ua, params.huber_k)
-        refs = [final_costs(okf, as_dev(st), ua, params.huber_k) for st in [base] + runs]
+        cg = final_costs(okf, dev, ua, params.huber_k, disc=disc)
+        refs = [final_costs(okf, as_dev(st), ua, params.huber_k, disc=disc) for st in [base] + runs]
         worst = np.max(refs, axis=0)
         all_ratios = cg / np.maximum(worst, 1e-12)
         ratios = all_ratios[~c["within"][uns]]

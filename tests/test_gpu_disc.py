@@ -1,0 +1,244 @@
+"""Disc surfels (Eq. 4) on the device, through the C ABI, against the oracle:
+the Gauss-Newton update over disc pixels in every storage form and with the
+damped variant, the depth-buffered render and its surfel-index map, the
+empty-area search with placement and neighbour initialisation, the whole
+keyframe step chained, batch == alone, edge cases and argument errors."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from scenegen import make_disc_surfels, make_keyframe, spec_for_config
+from tests.parity import angle_deg, assert_parity, check_parity, oracle_keyframe, oracle_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_01997_amd import surfgn as sg
+    c = sg.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _mods():
+    from paper_1910_01997_amd import engine, surfgn
+    return surfgn, engine
+
+
+def _scene(width=320, height=240, n_nbr=4, seed=61, radius=10.0, **kw):
+    spec = dataclasses.replace(spec_for_config(1), width=width, height=height, n_nbr=n_nbr,
+                               n_rects=8, seed=seed, half_new=False)
+    kf = make_keyframe(spec, device="cuda")
+    return kf, make_disc_surfels(kf, radius=radius, **kw)
+
+
+def _disc_of(dk):
+    ux, uy = dk.centres()
+    return (ux, uy, dk.radius)
+
+
+def _state_equal(a: dict, b: dict):
+    for k in ("inv_depth", "n", "flags", "cost", "nvalid"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "u8"])
+def test_disc_gauss_newton_matches_oracle(ctx, storage):
+    sg, engine = _mods()
+    kf, discs = _scene()
+    print(f"case disc GN 320x240 r10 N4 {storage} ({discs.ux.size} surfels)", flush=True)
+    dk = engine.DiscKeyframe.from_scene(ctx, kf, discs, storage=storage)
+    engine.disc_update(ctx, [dk], sg.params(iters=10))
+    torch.cuda.synchronize()
+    dev = dk.state_host()
+    res = check_parity(dk, dev, discs.init_id, discs.init_n, None, oracle.OracleParams(iters=10),
+                       label=f"disc {storage}", disc=_disc_of(dk))
+    assert_parity(res, label=f"disc {storage}")
+    assert np.all(dev["nvalid"][dev["flags"] == 0] > 0)
+
+
+def test_disc_damped_depth_only_and_radius_five(ctx):
+    sg, engine = _mods()
+    kf, discs = _scene(seed=62, radius=5.0)
+    for name, prm, oprm in (
+            ("LM", sg.params(iters=8, lm_lambda=1e-3), oracle.OracleParams(iters=8, lm_lambda=1e-3)),
+            ("depth-only", sg.params(iters=8, depth_only=True), oracle.OracleParams(iters=8, depth_only=True))):
+        print(f"case disc r5 {name}", flush=True)
+        dk = engine.DiscKeyframe.from_scene(ctx, kf, discs)
+        engine.disc_update(ctx, [dk], prm)
+        torch.cuda.synchronize()
+        dev = dk.state_host()
+        if name == "depth-only":
+            assert np.array_equal(dev["n"], discs.init_n)
+        res = check_parity(dk, dev, discs.init_id, discs.init_n, None, oprm, label=f"disc r5 {name}",
+                           disc=_disc_of(dk))
+        # 5 px discs have ~80 pixels: more of them sit at the edge of what
+        # float resolution determines, as with the small tiles
+        assert_parity(res, label=f"disc r5 {name}", max_unstable=0.25)
+
+
+def test_disc_render_matches_oracle_exactly(ctx):
+    """Both sides evaluate Eq. 3 in double in the printed order, so the depth
+    test takes the same decisions: the surfel-index map is equal and the
+    inverse depths are the oracle's doubles rounded to float."""
+    sg, engine = _mods()
+    kf, discs = _scene(seed=63)
+    # extra surfels: centres beyond the border, and a coincident pair (a tie)
+    ux = np.concatenate([discs.ux, np.float32([-4.5, 323.0, 150.0, 150.0])])
+    uy = np.concatenate([discs.uy, np.float32([100.0, 7.25, 120.0, 120.0])])
+    ids = np.concatenate([discs.init_id, np.float32([0.6, 0.7, 2.0, 2.0])])
+    ns = np.concatenate([discs.init_n, np.float32([[0, 0, -1], [0.1, 0, -1], [0, 0.2, -1], [0, 0.2, -1]])])
+    ns = (ns / np.linalg.norm(ns, axis=1, keepdims=True)).astype(np.float32)
+    flags = np.zeros(ids.size, np.uint32)
+    flags[5] = oracle.UNINIT
+    flags[9] = oracle.DEGENERATE
+    print("case disc render 320x240", flush=True)
+    dk = engine.DiscKeyframe(ctx, kf.kf_image, kf.nbr_images, kf.R, kf.t, kf.K, 10.0, ux, uy, ids, ns,
+                             flags=flags)
+    dk.render()
+    torch.cuda.synchronize()
+    okf = oracle_keyframe(dk)
+    st = oracle_state(ids, ns, flags)
+    idm, ind = oracle.disc_render(okf, st, ux.astype(np.float64), uy.astype(np.float64), 10.0)
+    got_i = dk.index_out.cpu().numpy()
+    got_d = dk.inv_depth_out.cpu().numpy()
+    assert np.array_equal(got_i, ind)
+    assert np.array_equal(got_d, idm.astype(np.float32))
+    assert not np.any(got_i == 5) and not np.any(got_i == 9)
+    assert np.any(got_i == ids.size - 2) and not np.any(got_i == ids.size - 1)
+    assert np.any(got_i == -1) and (got_i >= 0).mean() > 0.8
+
+
+def test_disc_place_matches_oracle_and_respects_capacity(ctx):
+    sg, engine = _mods()
+    kf, discs = _scene(seed=64, n_holes=4, hole_frac=(0.2, 0.3))
+    print("case disc placement 320x240", flush=True)
+    m = discs.ux.size
+    for room in (1000, 5):
+        dk = engine.DiscKeyframe.from_scene(ctx, kf, discs, capacity=m + room)
+        dk.render()
+        imap = dk.index_out.cpu().numpy()
+        placed, found = dk.place(alpha=1.0, beta=2.0)
+        torch.cuda.synchronize()
+        xs, ys, o_found = oracle.disc_search(imap, 10.0, 1.0, discs.spacing)
+        assert found == o_found and found > 5
+        assert placed == min(found, room)
+        ux, uy = dk.centres()
+        assert np.array_equal(ux[m:], xs[:placed].astype(np.float32))
+        assert np.array_equal(uy[m:], ys[:placed].astype(np.float32))
+        dev = dk.state_host()
+        st = oracle_state(np.concatenate([discs.init_id, np.zeros(placed, np.float32)]),
+                          np.concatenate([discs.init_n, np.tile(np.float32([0, 0, -1]), (placed, 1))]))
+        oracle.disc_init(oracle_keyframe(dk), st, ux.astype(np.float64), uy.astype(np.float64), imap, m,
+                         10.0, 2.0)
+        new = np.arange(m, m + placed)
+        assert np.array_equal(dev["flags"][new], st["flags"][new].astype(np.uint32))
+        ok = st["flags"][new] == 0
+        assert ok.sum() >= 1
+        rel = np.abs(dev["inv_depth"][new][ok] / st["inv_depth"][new][ok] - 1)
+        on = np.stack([st["nx"], st["ny"], st["nz"]], 1)[new][ok]
+        assert rel.max() < 1e-5 and angle_deg(dev["n"][new][ok], on).max() < 1e-3
+        assert np.all(dev["inv_depth"][new][~ok] == 0) and np.all(dev["cost"][new] == 0)
+        # old surfels are untouched
+        assert np.array_equal(dev["inv_depth"][:m], discs.init_id)
+
+
+def test_disc_keyframe_step_chained(ctx):
+    """render -> search and placement -> Gauss-Newton over old and new
+    surfels -> render, each stage against the oracle from the device's input
+    to that stage."""
+    sg, engine = _mods()
+    kf, discs = _scene(640, 480, 8, seed=65)
+    print("case disc step 640x480 r10 N8", flush=True)
+    dk = engine.DiscKeyframe.from_scene(ctx, kf, discs, capacity=discs.ux.size + 600, storage="f16")
+    dk.render()
+    placed, found = dk.place()
+    start = dk.state_host()
+    engine.disc_update(ctx, [dk], sg.params(iters=6))
+    dk.render()
+    torch.cuda.synchronize()
+    assert placed == found and placed > 10
+    dev = dk.state_host()
+    res = check_parity(dk, dev, start["inv_depth"], start["n"], None, oracle.OracleParams(iters=6),
+                       label="disc step", disc=_disc_of(dk), init_flags=start["flags"])
+    assert_parity(res, label="disc step")
+    ux, uy = dk.centres()
+    idm, ind = oracle.disc_render(oracle_keyframe(dk), oracle_state(dev["inv_depth"], dev["n"], dev["flags"]),
+                                  ux.astype(np.float64), uy.astype(np.float64), 10.0)
+    assert np.array_equal(dk.index_out.cpu().numpy(), ind)
+    # the rims of the holes are filled (their middles, farther than beta r
+    # from any measurement, stay uninitialised): fewer empty pixels
+    before = oracle.disc_render(oracle_keyframe(dk), oracle_state(discs.init_id, discs.init_n),
+                                discs.ux.astype(np.float64), discs.uy.astype(np.float64), 10.0)[1]
+    assert (ind < 0).sum() < (before < 0).sum()
+
+
+def test_disc_batch_equals_alone_and_empty_cases(ctx):
+    sg, engine = _mods()
+    scenes = [_scene(seed=66 + i, n_nbr=3 + i) for i in range(3)]
+    print("case disc batch of 3 == alone", flush=True)
+    prm = sg.params(iters=5)
+    alone = []
+    for kf, discs in scenes:
+        dk = engine.DiscKeyframe.from_scene(ctx, kf, discs, storage="u8")
+        engine.disc_update(ctx, [dk], prm)
+        torch.cuda.synchronize()
+        alone.append(dk.state_host())
+    dks = [engine.DiscKeyframe.from_scene(ctx, kf, discs, storage="u8") for kf, discs in scenes]
+    engine.disc_update(ctx, dks, prm)
+    torch.cuda.synchronize()
+    for dk, ref in zip(dks, alone):
+        _state_equal(dk.state_host(), ref)
+    # no surfels: render gives no measurement, every candidate qualifies and
+    # none can be initialised, the update is a no-op
+    kf, discs = scenes[0]
+    empty = engine.DiscKeyframe(ctx, kf.kf_image, kf.nbr_images, kf.R, kf.t, kf.K, 10.0,
+                                np.zeros(0, np.float32), np.zeros(0, np.float32), np.zeros(0, np.float32),
+                                np.zeros((0, 3), np.float32), capacity=2000)
+    engine.disc_update(ctx, [empty], prm)
+    empty.render()
+    assert np.all(empty.index_out.cpu().numpy() == -1) and np.all(empty.inv_depth_out.cpu().numpy() == 0)
+    placed, found = empty.place()
+    n_lat = len(range(7, 320, 14)) * len(range(7, 240, 14))
+    assert placed == found == n_lat
+    assert np.all(empty.state_host()["flags"] == oracle.UNINIT)
+
+
+def test_disc_argument_errors(ctx):
+    sg, engine = _mods()
+    L = sg.lib()
+    kf, discs = _scene(seed=70)
+    dk = engine.DiscKeyframe.from_scene(ctx, kf, discs, capacity=discs.ux.size + 10)
+    print("case disc argument errors", flush=True)
+    prm = sg.params(iters=3)
+    for r in (0.0, -1.0, 12.5, float("nan")):
+        it = dk.item()
+        it.radius = r
+        assert L.sgn_disc_optimize(ctx.handle, sg.disc_array([it]), 1, prm) == sg.SGN_E_INVALID
+        assert L.sgn_disc_render(ctx.handle, it, dk.inv_depth_out.data_ptr(), None) == sg.SGN_E_INVALID
+    it = dk.item()
+    it.ux = None
+    assert L.sgn_disc_optimize(ctx.handle, sg.disc_array([it]), 1, prm) == sg.SGN_E_INVALID
+    it = dk.item()
+    it.count = -1
+    assert L.sgn_disc_optimize(ctx.handle, sg.disc_array([it]), 1, prm) == sg.SGN_E_INVALID
+    ok_pp = sg.sgn_disc_place_params(1.0, 2.0, 14)
+    cnt = dk.counts.data_ptr()
+    imap = dk.index_out.data_ptr()
+    assert L.sgn_disc_place(ctx.handle, dk.item(), imap, discs.ux.size - 1, ok_pp, cnt) == sg.SGN_E_INVALID
+    for pp in (sg.sgn_disc_place_params(0.0, 2.0, 14), sg.sgn_disc_place_params(1.0, 4.5, 14),
+               sg.sgn_disc_place_params(1.0, 2.0, 0)):
+        assert L.sgn_disc_place(ctx.handle, dk.item(), imap, dk.capacity, pp, cnt) == sg.SGN_E_INVALID
+    assert L.sgn_disc_place(ctx.handle, dk.item(), None, dk.capacity, ok_pp, cnt) == sg.SGN_E_INVALID
+    assert L.sgn_disc_render(ctx.handle, dk.item(), None, None) == sg.SGN_E_INVALID
+    # nothing was enqueued: the state is untouched
+    torch.cuda.synchronize()
+    assert np.array_equal(dk.state_host()["inv_depth"], discs.init_id)
