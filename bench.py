@@ -10,6 +10,10 @@ FP16.  Inputs are synthetic and resident in HBM before timing starts.
 Prints one JSON line: metric, value (surfel-frame GN updates per second),
 the roofline of the fused GN kernel (timed with HIP events on its own
 stream), and the FP64 oracle timed on a bounded sample on the host cores.
+Beside the metric it reports the other image storages, the plain
+single-keyframe form, the depth-only ablation against ground truth, the disc
+surfels of Eq. 4 on the same keyframes (radius 10 px: Gauss-Newton kernel and
+the whole keyframe step with the empty-area search), and serving latency.
 """
 from __future__ import annotations
 

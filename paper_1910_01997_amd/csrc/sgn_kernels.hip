@@ -1487,6 +1487,8 @@ hipError_t launch_gn(const GnVariant& v, const BatchHeader* hdr, uint32_t* count
 constexpr int kDiscMaxRows = 2 * (int)kDiscMaxRadius + 2;
 constexpr int kDiscPPL = 8;        // 512 pixels > pi (12 + sqrt(2)/2)^2, the largest disc
 constexpr int kDiscRowWords = 2 * kDiscMaxRows + 2;
+// largest ceil(beta r) of the neighbour search (beta <= 4, r <= 12)
+constexpr int kDiscMaxWindowReach = 4 * (int)kDiscMaxRadius;
 
 struct DiscRows {
     int y0, nrows, total;
@@ -1549,8 +1551,10 @@ __device__ __forceinline__ void disc_pixel(const DiscRows& d, const int* row_x0,
 // items are its surfels), the same per-pixel terms, frame loop, reduction
 // and owner-lane step as the tile kernel, over the disc's pixels.  The warp
 // constants are anchored at the pixel nearest the centre.
+// Five wavefronts per SIMD: the register budget (96 VGPRs) the slot loop
+// fits without spilling; the default allocation takes 100 and four.
 template <typename T>
-__global__ __launch_bounds__(kBlockThreads) void disc_gn_kernel(const BatchHeader* __restrict__ hdr_,
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void disc_gn_kernel(const BatchHeader* __restrict__ hdr_,
                                                                 int total) {
     const cptr<BatchHeader> hdr = (cptr<BatchHeader>)hdr_;
     const int lane = threadIdx.x & (kWaveSize - 1);
@@ -1561,6 +1565,9 @@ __global__ __launch_bounds__(kBlockThreads) void disc_gn_kernel(const BatchHeade
     __shared__ float4 s_state[kBlockThreads / kWaveSize][ST_WORDS / 4];
     __shared__ float4 s_sums[kBlockThreads / kWaveSize][SM_WORDS / 4];
     __shared__ int s_rows[kBlockThreads / kWaveSize][kDiscRowWords];
+    // each lane's pixels: offsets from the anchor (two int16) and keyframe values
+    __shared__ int s_off[kBlockThreads / kWaveSize][kDiscPPL][kWaveSize];
+    __shared__ float s_ikf[kBlockThreads / kWaveSize][kDiscPPL][kWaveSize];
     float* const pairs = (float*)s_pairs[wave];
     float* const lst = (float*)s_state[wave];
     float* const lsm = (float*)s_sums[wave];
@@ -1600,24 +1607,22 @@ __global__ __launch_bounds__(kBlockThreads) void disc_gn_kernel(const BatchHeade
     const uint32_t fr_hi = __builtin_amdgcn_readfirstlane((uint32_t)(fr_bits >> 32));
     const cptr<FrameDev> fr = (cptr<FrameDev>)(((uint64_t)fr_hi << 32) | fr_lo);
 
-    // this lane's pixels: offsets from the anchor and keyframe values
-    float bdx[kDiscPPL], bdy[kDiscPPL], ikf[kDiscPPL];
-    bool pv[kDiscPPL];
+    // this lane's pixels k = lane + 64 j: offsets from the anchor (|.| <= 13)
+    // and keyframe values, kept in LDS so that the slot loop holds one pixel's
+    // terms in registers at a time
     const gptr<T> kimg = (gptr<T>)Kd->kf_img;
-#pragma unroll
-    for (int j = 0; j < kDiscPPL; ++j) {
+    for (int j = 0; j < nslots; ++j) {
         const int k = lane + kWaveSize * j;
-        pv[j] = k < d.total;
-        bdx[j] = 0.f;
-        bdy[j] = 0.f;
-        ikf[j] = 0.f;
-        if (pv[j]) {
+        int off = 0;
+        float v = 0.f;
+        if (k < d.total) {
             int x, y;
             disc_pixel(d, row_x0, row_start, k, x, y);
-            bdx[j] = (float)(x - ax);
-            bdy[j] = (float)(y - ay);
-            ikf[j] = ldg<T>(kimg + ((unsigned)y * (unsigned)Kd->kf_pitch + (unsigned)x)) * Kd->kf_scale;
+            off = ((x - ax) & 0xffff) | ((y - ay) << 16);
+            v = ldg<T>(kimg + ((unsigned)y * (unsigned)Kd->kf_pitch + (unsigned)x)) * Kd->kf_scale;
         }
+        s_off[wave][j][lane] = off;
+        s_ikf[wave][j][lane] = v;
     }
     // r_u - r_s = (anchor offset + (anchor - u_s)) / f
     const float fox = (float)((double)ax - (double)ux), foy = (float)((double)ay - (double)uy);
@@ -1668,10 +1673,13 @@ __global__ __launch_bounds__(kBlockThreads) void disc_gn_kernel(const BatchHeade
             const bool salive = sd.y != 0.f;
             float ph[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             float pnv = 0.f, pcs = 0.f;
-#pragma unroll
-            for (int j = 0; j < kDiscPPL; ++j) {
-                if (j < nslots) {
-                    const float drx = (bdx[j] + fox) * ifx, dry = (bdy[j] + foy) * ify;
+            for (int j = 0; j < nslots; ++j) {
+                {
+                    const int off = s_off[wave][j][lane];
+                    const float bdx = (float)(int16_t)(off & 0xffff), bdy = (float)(off >> 16);
+                    const float ikf = s_ikf[wave][j][lane];
+                    const bool pv = lane + kWaveSize * j < d.total;
+                    const float drx = (bdx + fox) * ifx, dry = (bdy + foy) * ify;
                     const float sigma = (snx * drx + sny * dry) * inv_c;
                     const float idu = fmaf(sid, sigma, sid);
                     const float dx3 = fmaf(-sigma, srsx, drx);
@@ -1681,15 +1689,15 @@ __global__ __launch_bounds__(kBlockThreads) void disc_gn_kernel(const BatchHeade
                     const float g0 = 1.f + sigma;
                     const float g1 = depth_only ? 0.f : kk * (sb1x * dx3 + sb1y * dy3 + sb1z * dz3);
                     const float g2 = depth_only ? 0.f : kk * (sb2x * dx3 + sb2y * dy3 + sb2z * dz3);
-                    const bool pix_ok = salive && pv[j] && (idu > 0.f);
+                    const bool pix_ok = salive && pv && (idu > 0.f);
                     float A = 0.f, B = 0.f, cst = 0.f;
                     int nvl = 0;
                     if (last || lm)
-                        frame_loop<T, true>(pairs, fr, nf, bdx[j], bdy[j], idu, pix_ok, pitch_b, img_bytes,
-                                            wm1, hm1, ikf[j], hk, img_scale, A, B, cst, nvl);
+                        frame_loop<T, true>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes,
+                                            wm1, hm1, ikf, hk, img_scale, A, B, cst, nvl);
                     else
-                        frame_loop<T, false>(pairs, fr, nf, bdx[j], bdy[j], idu, pix_ok, pitch_b,
-                                             img_bytes, wm1, hm1, ikf[j], hk, img_scale, A, B, cst, nvl);
+                        frame_loop<T, false>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b,
+                                             img_bytes, wm1, hm1, ikf, hk, img_scale, A, B, cst, nvl);
                     {
 #pragma clang fp contract(off)
                         const float ag0 = A * g0, ag1 = A * g1, ag2 = A * g2;
@@ -1751,15 +1759,15 @@ __global__ __launch_bounds__(kBlockThreads) void disc_gn_kernel(const BatchHeade
                 const bool calive = lst[ST_ALIVE] != 0.f;
                 float cst2 = 0.f;
                 int nv2l = 0;
-#pragma unroll
-                for (int j = 0; j < kDiscPPL; ++j) {
-                    if (j < nslots) {
-                        const float drx = (bdx[j] + fox) * ifx, dry = (bdy[j] + foy) * ify;
-                        const float sig = (sa.y * drx + sa.z * dry) * inv_c;
-                        const float idu_c = fmaf(sa.x, sig, sa.x);
-                        frame_cost<T>(pairs, fr, nf, bdx[j], bdy[j], idu_c, calive && pv[j] && (idu_c > 0.f),
-                                      pitch_b, img_bytes, wm1, hm1, ikf[j], hk, img_scale, cst2, nv2l);
-                    }
+                for (int j = 0; j < nslots; ++j) {
+                    const int off = s_off[wave][j][lane];
+                    const float bdx = (float)(int16_t)(off & 0xffff), bdy = (float)(off >> 16);
+                    const bool pv = lane + kWaveSize * j < d.total;
+                    const float drx = (bdx + fox) * ifx, dry = (bdy + foy) * ify;
+                    const float sig = (sa.y * drx + sa.z * dry) * inv_c;
+                    const float idu_c = fmaf(sa.x, sig, sa.x);
+                    frame_cost<T>(pairs, fr, nf, bdx, bdy, idu_c, calive && pv && (idu_c > 0.f), pitch_b,
+                                  img_bytes, wm1, hm1, s_ikf[wave][j][lane], hk, img_scale, cst2, nv2l);
                 }
                 const float c2 = group_sum<kWaveSize>(cst2);
                 const int n2 = group_sum<kWaveSize>(nv2l);
@@ -1846,30 +1854,37 @@ __global__ void disc_resolve_kernel(DiscRenderArgs a) {
     }
 }
 
-// The search for empty areas (Surfel Initialization section): one thread per
-// lattice candidate u_ns = (spacing/2 + i spacing, spacing/2 + j spacing); it
-// qualifies when no non-empty pixel of the index map lies within alpha r
-// (integer squared distance against (alpha r)^2 in double).
-__global__ void disc_search_kernel(DiscPlaceArgs a) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// The search for empty areas (Surfel Initialization section): one wavefront
+// per lattice candidate u_ns = (spacing/2 + i spacing, spacing/2 + j
+// spacing), its lanes sharing the window of pixels within alpha r; the
+// candidate qualifies when no non-empty pixel of the index map lies within
+// alpha r (integer squared distance against (alpha r)^2 in double).
+__global__ __launch_bounds__(kBlockThreads) void disc_search_kernel(DiscPlaceArgs a) {
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const int c = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlockThreads / kWaveSize) +
+                                                 (int)(threadIdx.x >> 6));
     if (c >= a.cand_x * a.cand_y) return;
     const int cx = a.spacing / 2 + (c % a.cand_x) * a.spacing;
     const int cy = a.spacing / 2 + (c / a.cand_x) * a.spacing;
     const double ar = (double)a.alpha * (double)a.radius;
     const double ar2 = ar * ar;
     const int reach = (int)floor(ar);
-    bool empty = true;
-    for (int y = max(0, cy - reach); y <= min(a.height - 1, cy + reach) && empty; ++y) {
-        const int dy = y - cy;
-        for (int x = max(0, cx - reach); x <= min(a.width - 1, cx + reach); ++x) {
-            const int dx = x - cx;
-            if (a.index_map[(size_t)y * a.width + x] >= 0 && (double)(dx * dx + dy * dy) <= ar2) {
-                empty = false;
-                break;
-            }
+    const int side = 2 * reach + 1, npix = side * side;
+    bool hit = false;
+    for (int k0 = 0; k0 < npix; k0 += kWaveSize) {
+        const int k = k0 + lane;
+        if (k < npix) {
+            const int dy = k / side - reach, dx = k % side - reach;
+            const int x = cx + dx, y = cy + dy;
+            if (x >= 0 && y >= 0 && x < a.width && y < a.height &&
+                (double)(dx * dx + dy * dy) <= ar2 && a.index_map[(size_t)y * a.width + x] >= 0)
+                hit = true;
         }
+        if (__ballot(hit) != 0ull) break;     // wave-uniform
     }
-    a.cand_flag[c] = empty ? 1 : 0;
+    // the vote of the whole wavefront, taken before narrowing to one lane
+    const bool empty = __ballot(hit) == 0ull;
+    if (lane == 0) a.cand_flag[c] = empty ? 1 : 0;
 }
 
 // Placement: the qualifying candidates in lattice order become surfels
@@ -1927,10 +1942,11 @@ __device__ __forceinline__ int wave_min(int v) {
 // index each round); id = mean of Eq. 3 of their planes at the new ray,
 // n = mean of their normals sign-aligned to the first, renormalised; none
 // usable: UNINIT with id 0 and n = (0, 0, -1).
-__global__ __launch_bounds__(kBlockThreads) void disc_init_kernel(DiscPlaceArgs a) {
-    const int lane = threadIdx.x & (kWaveSize - 1);
-    const int wave = threadIdx.x >> 6;
-    const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlockThreads / kWaveSize) + wave);
+__global__ __launch_bounds__(kWaveSize) void disc_init_kernel(DiscPlaceArgs a) {
+    // the window's surfel indices (those within beta r, below `first`), or -1
+    __shared__ int s_win[(2 * kDiscMaxWindowReach + 1) * (2 * kDiscMaxWindowReach + 1)];
+    const int lane = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
     if (w >= a.counts[0]) return;
     const int i = a.first + w;
     const int cx = (int)a.ux[i], cy = (int)a.uy[i];
@@ -1938,18 +1954,26 @@ __global__ __launch_bounds__(kBlockThreads) void disc_init_kernel(DiscPlaceArgs 
     const double br2 = br * br;
     const int reach = (int)ceil(br);
     const int side = 2 * reach + 1, npix = side * side;
+    for (int k = lane; k < npix; k += kWaveSize) {
+        const int dy = k / side - reach, dx = k % side - reach;
+        const int x = cx + dx, y = cy + dy;
+        int j = -1;
+        if (x >= 0 && y >= 0 && x < a.width && y < a.height && (double)(dx * dx + dy * dy) < br2) {
+            j = a.index_map[(size_t)y * a.width + x];
+            if (j >= a.first) j = -1;
+        }
+        s_win[k] = j;
+    }
+    wave_sync();
     const float rnx = ((float)cx - a.cx) / a.fx, rny = ((float)cy - a.cy) / a.fy;
     int last = -1, count = 0;
     float id_sum = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, rx = 0.f, ry = 0.f, rz = 0.f;
     for (;;) {
+        // next neighbour in index order
         int best = 0x7fffffff;
         for (int k = lane; k < npix; k += kWaveSize) {
-            const int dy = k / side - reach, dx = k % side - reach;
-            const int x = cx + dx, y = cy + dy;
-            if (x < 0 || y < 0 || x >= a.width || y >= a.height) continue;
-            const int j = a.index_map[(size_t)y * a.width + x];
-            if (j <= last || j >= a.first) continue;
-            if ((double)(dx * dx + dy * dy) < br2) best = min(best, j);
+            const int j = s_win[k];
+            if (j > last) best = min(best, j);
         }
         const int j = __builtin_amdgcn_readfirstlane(wave_min(best));
         if (j == 0x7fffffff) break;
@@ -2018,13 +2042,11 @@ hipError_t launch_disc_render(const DiscRenderArgs& a, hipStream_t s) {
 
 hipError_t launch_disc_place(const DiscPlaceArgs& a, hipStream_t s) {
     const int n = a.cand_x * a.cand_y;
-    if (n > 0) disc_search_kernel<<<(n + 255) / 256, 256, 0, s>>>(a);
+    const int waves = kBlockThreads / kWaveSize;
+    if (n > 0) disc_search_kernel<<<(n + waves - 1) / waves, kBlockThreads, 0, s>>>(a);
     disc_compact_kernel<<<1, 1024, 0, s>>>(a);
     const int most = std::min(a.room, n);
-    if (most > 0) {
-        const int waves = kBlockThreads / kWaveSize;
-        disc_init_kernel<<<(most + waves - 1) / waves, kBlockThreads, 0, s>>>(a);
-    }
+    if (most > 0) disc_init_kernel<<<most, kWaveSize, 0, s>>>(a);
     return hipGetLastError();
 }
 
