@@ -285,6 +285,11 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # Each step waits for its GN kernel's end event before the host builds the
+    # next one.  Without that wait the host runs several steps ahead, and
+    # graph launches queued that far ahead stalled the stream for a few
+    # steps (measured: GN windows of 8-16 ms among 4.8 ms ones); the wait
+    # costs about 0.03 ms per step.
     kernel_ms = []
     t_start = time.perf_counter()
     for _ in range(args.steps):

@@ -331,6 +331,13 @@ sgn_status sgn_quantize(sgn_ctx* ctx, const float* src, int32_t src_pitch, const
  * (HIP events on the context's stream around that kernel alone; waits for it). */
 sgn_status sgn_last_kernel_ms(sgn_ctx* ctx, float* ms_out);
 
+/* Milliseconds of the last n fused Gauss-Newton kernels of this context
+ * (tile or disc), oldest first, into ms_out (host, n floats): the same HIP
+ * events as sgn_last_kernel_ms, kept for the last 64 launches, so a caller
+ * can time many launches without waiting between them.  Waits for the
+ * kernels.  Errors: n outside [1, min(launches, 64)] (SGN_E_INVALID). */
+sgn_status sgn_recent_kernel_ms(sgn_ctx* ctx, int32_t n, float* ms_out);
+
 sgn_status sgn_device_info(int32_t device, sgn_device_props* out);
 const char* sgn_status_str(sgn_status status);
 const char* sgn_last_error(void);

@@ -42,6 +42,7 @@ sgn_status hip_fail(hipError_t e, const char* what) {
 size_t dtype_size(int dt) { return dt == SGN_F32 ? 4 : dt == SGN_F16 ? 2 : 1; }
 
 constexpr int kRingSlots = 4;
+constexpr int kTimingRing = 64;
 
 struct GraphKey {
     int dtype, patch, tx, ty, lds, persistent, grid, part, do_init, groups, frames_cap;
@@ -67,6 +68,10 @@ struct sgn_ctx {
     void* dev_table = nullptr;
     uint32_t* counters = nullptr;
     // timing of the last GN kernel
+    // timing of the GN kernels: a ring of event pairs, the last kTimingRing
+    // launches; gn_start/gn_end point at the latest pair
+    hipEvent_t gn_ring[2][kTimingRing] = {};
+    int64_t gn_launches = 0;
     hipEvent_t gn_start = nullptr, gn_end = nullptr;
     bool gn_timed = false;
     // graphs
@@ -163,6 +168,14 @@ sgn_status check_keyframe(const sgn_keyframe* kf, bool need_nbr, bool disc = fal
             if (!std::isfinite(kf->pose[i].t[j])) return fail(SGN_E_INVALID, "non-finite translation");
     }
     return SGN_OK;
+}
+
+// Event pair of the next GN launch (its slot in the timing ring).
+void next_timing_slot(sgn_ctx* c) {
+    const int slot = (int)(c->gn_launches % kTimingRing);
+    c->gn_start = c->gn_ring[0][slot];
+    c->gn_end = c->gn_ring[1][slot];
+    ++c->gn_launches;
 }
 
 sgn_status ensure_scratch(sgn_ctx* c, size_t need) {
@@ -431,6 +444,7 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
     st = run_part(0, true, enqueue_pre);
     if (st) return st;
     if (run_gn) {
+        next_timing_slot(c);
         SGN_HIP(hipEventRecord(c->gn_start, c->stream));
         st = run_part(1, true, enqueue_gn);
         if (st) return st;
@@ -551,6 +565,7 @@ sgn_status run_disc_batch(sgn_ctx* c, const sgn_disc_item* items, int n, const s
     hipError_t e = launch_setup(dH, c->counters, frames_cap, c->stream);
     if (e != hipSuccess) return hip_fail(e, "setup launch");
     if (surfel_base > 0) {
+        next_timing_slot(c);
         SGN_HIP(hipEventRecord(c->gn_start, c->stream));
         e = launch_disc_gn(dtype, dH, surfel_base, c->stream);
         if (e != hipSuccess) return hip_fail(e, "disc Gauss-Newton launch");
@@ -620,8 +635,15 @@ sgn_status sgn_create(sgn_ctx** out, int32_t device, void* hip_stream) {
             delete c;
             return fail(SGN_E_DEVICE, "event creation failed");
         }
-    if (hipEventCreate(&c->gn_start) != hipSuccess || hipEventCreate(&c->gn_end) != hipSuccess ||
-        hipMalloc(&c->counters, kNumCounters * sizeof(uint32_t)) != hipSuccess) {
+    for (int k = 0; k < 2; ++k)
+        for (int i = 0; i < kTimingRing; ++i)
+            if (hipEventCreate(&c->gn_ring[k][i]) != hipSuccess) {
+                delete c;
+                return fail(SGN_E_DEVICE, "event creation failed");
+            }
+    c->gn_start = c->gn_ring[0][0];
+    c->gn_end = c->gn_ring[1][0];
+    if (hipMalloc(&c->counters, kNumCounters * sizeof(uint32_t)) != hipSuccess) {
         delete c;
         return fail(SGN_E_DEVICE, "context allocation failed");
     }
@@ -641,8 +663,9 @@ sgn_status sgn_destroy(sgn_ctx* c) {
     }
     if (c->dev_table) hipFree(c->dev_table);
     if (c->counters) hipFree(c->counters);
-    if (c->gn_start) hipEventDestroy(c->gn_start);
-    if (c->gn_end) hipEventDestroy(c->gn_end);
+    for (int k = 0; k < 2; ++k)
+        for (int i = 0; i < kTimingRing; ++i)
+            if (c->gn_ring[k][i]) hipEventDestroy(c->gn_ring[k][i]);
     if (c->scratch) hipFree(c->scratch);
     delete c;
     return SGN_OK;
@@ -711,6 +734,18 @@ sgn_status sgn_last_kernel_ms(sgn_ctx* c, float* ms) {
     if (!c->gn_timed) return fail(SGN_E_INVALID, "no timed kernel yet");
     SGN_HIP(hipEventSynchronize(c->gn_end));
     SGN_HIP(hipEventElapsedTime(ms, c->gn_start, c->gn_end));
+    return SGN_OK;
+}
+
+sgn_status sgn_recent_kernel_ms(sgn_ctx* c, int32_t n, float* ms_out) {
+    if (!c || !ms_out) return fail(SGN_E_INVALID, "null argument");
+    const int64_t avail = std::min<int64_t>(c->gn_launches, kTimingRing);
+    if (n < 1 || n > avail) return fail(SGN_E_INVALID, "n must be in [1, launches kept]");
+    for (int i = 0; i < n; ++i) {
+        const int slot = (int)((c->gn_launches - n + i) % kTimingRing);
+        SGN_HIP(hipEventSynchronize(c->gn_ring[1][slot]));
+        SGN_HIP(hipEventElapsedTime(&ms_out[i], c->gn_ring[0][slot], c->gn_ring[1][slot]));
+    }
     return SGN_OK;
 }
 

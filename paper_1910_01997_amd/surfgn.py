@@ -37,6 +37,7 @@ EXPORTED = [
     "sgn_optimize_keyframe", "sgn_render_inverse_depth", "sgn_optimize_batch", "sgn_autotune",
     "sgn_quantize", "sgn_last_kernel_ms", "sgn_device_info", "sgn_status_str", "sgn_last_error",
     "sgn_version", "sgn_transfer_surfels", "sgn_disc_optimize", "sgn_disc_render", "sgn_disc_place",
+    "sgn_recent_kernel_ms",
 ]
 
 
@@ -158,6 +159,8 @@ def lib():
         L.sgn_disc_place.restype = st
         L.sgn_disc_place.argtypes = [vp, C.POINTER(sgn_disc_item), vp, C.c_int32,
                                      C.POINTER(sgn_disc_place_params), vp]
+        L.sgn_recent_kernel_ms.restype = st
+        L.sgn_recent_kernel_ms.argtypes = [vp, C.c_int32, C.POINTER(C.c_float)]
         L.sgn_last_kernel_ms.restype = st
         L.sgn_last_kernel_ms.argtypes = [vp, C.POINTER(C.c_float)]
         L.sgn_device_info.restype = st
@@ -273,6 +276,12 @@ def sgn_last_kernel_ms(ctx) -> float:
     ms = C.c_float(0.0)
     check(lib().sgn_last_kernel_ms(C.c_void_p(ctx), C.byref(ms)), "sgn_last_kernel_ms")
     return float(ms.value)
+
+
+def sgn_recent_kernel_ms(ctx, n: int) -> List[float]:
+    out = (C.c_float * int(n))()
+    check(lib().sgn_recent_kernel_ms(C.c_void_p(ctx), int(n), out), "sgn_recent_kernel_ms")
+    return [float(v) for v in out]
 
 
 def sgn_device_info(device: int = 0) -> dict:

@@ -337,3 +337,30 @@ def test_batch_render_with_odd_sizes_matches_plain(ctx):
         assert not np.any(got == -7.0)
         assert np.array_equal(got, dm)
         assert np.array_equal(d.index_out.cpu().numpy(), im)
+
+
+def test_recent_kernel_times_ring(ctx):
+    """sgn_recent_kernel_ms returns the last launches' GN times, oldest first;
+    the newest equals sgn_last_kernel_ms; the ring keeps 64."""
+    sg, engine = sgmod()
+    L = sg.lib()
+    print("case kernel timing ring", flush=True)
+    fresh = sg.Context(0)
+    import ctypes
+    buf = (ctypes.c_float * 2)()
+    assert L.sgn_recent_kernel_ms(fresh.handle, 1, buf) == sg.SGN_E_INVALID   # nothing launched yet
+    kf = make_keyframe(_small_spec(half_new=False), device="cuda")
+    d = engine.DeviceKeyframe.from_scene(fresh, kf)
+    for _ in range(3):
+        engine.update_batch(fresh, [d], sg.params(iters=2))
+    t = sg.sgn_recent_kernel_ms(fresh.handle, 3)
+    assert len(t) == 3 and all(v > 0 for v in t)
+    assert t[-1] == sg.sgn_last_kernel_ms(fresh.handle)
+    assert L.sgn_recent_kernel_ms(fresh.handle, 4, (ctypes.c_float * 4)()) == sg.SGN_E_INVALID
+    assert L.sgn_recent_kernel_ms(fresh.handle, 0, buf) == sg.SGN_E_INVALID
+    for _ in range(70):
+        engine.update_batch(fresh, [d], sg.params(iters=1))
+    assert len(sg.sgn_recent_kernel_ms(fresh.handle, 64)) == 64
+    assert L.sgn_recent_kernel_ms(fresh.handle, 65, (ctypes.c_float * 65)()) == sg.SGN_E_INVALID
+    torch.cuda.synchronize()
+    fresh.close()
