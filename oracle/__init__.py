@@ -141,6 +141,10 @@ def lib():
         L.sgo_disc_init.restype = C.c_int
         L.sgo_disc_init.argtypes = [C.POINTER(KeyframeC), C.POINTER(SurfelsC), dp, dp, ip,
                                     C.c_int32, C.c_int32, C.c_double, C.c_double]
+        L.sgo_disc_transfer.restype = C.c_int32
+        L.sgo_disc_transfer.argtypes = [C.POINTER(Intrinsics), C.POINTER(Intrinsics), C.c_int32,
+                                        C.c_int32, C.POINTER(Pose), C.POINTER(SurfelsC), dp, dp,
+                                        C.c_int32, C.POINTER(SurfelsC), dp, dp, C.c_int32, ip, ip]
         L.sgo_set_threads.restype = None
         L.sgo_set_threads.argtypes = [C.c_int32]
         L.sgo_max_threads.restype = C.c_int32
@@ -476,6 +480,27 @@ def disc_init(kf: OracleKeyframe, st, ux, uy, index_map, first, radius, beta):
     if rc != 0:
         raise RuntimeError("sgo_disc_init failed")
     return st
+
+
+def disc_transfer(src_K, dst_K, dst_size, R, t, st, ux, uy, capacity=None):
+    """Eq. 10 for disc surfels (see ``sgo_disc_transfer``): returns (dst state
+    dict, centres (ux, uy), source indices, number landed)."""
+    m = int(np.asarray(ux).size)
+    cap = m if capacity is None else int(capacity)
+    out = new_state(np.zeros(max(cap, 1)), np.zeros((max(cap, 1), 3)))
+    dux = np.zeros(max(cap, 1))
+    duy = np.zeros(max(cap, 1))
+    idx = np.zeros(max(cap, 1), np.int32)
+    landed = C.c_int32(0)
+    sc, dc = _surfels_c(st), _surfels_c(out)
+    cx, cy = _f64(ux).reshape(-1), _f64(uy).reshape(-1)
+    Ks, Kd = intrinsics(src_K), intrinsics(dst_K)
+    P = pose(R, t)
+    n = lib().sgo_disc_transfer(C.byref(Ks), C.byref(Kd), int(dst_size[0]), int(dst_size[1]), C.byref(P),
+                                C.byref(sc), _dp(cx), _dp(cy), m, C.byref(dc), _dp(dux), _dp(duy), cap,
+                                _ip(idx), C.byref(landed))
+    out = {k: v[:n] for k, v in out.items()}
+    return out, (dux[:n], duy[:n]), idx[:n], int(landed.value)
 
 
 def set_threads(n: int):

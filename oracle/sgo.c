@@ -827,6 +827,54 @@ int sgo_transfer_surfels(const sgo_intrinsics* K, const sgo_pose* P, int32_t cou
     return ok;
 }
 
+/* Eq. 10 for disc surfels.  Reading: a disc surfel stays a disc; a usable
+ * source surfel (no DEGENERATE or UNINIT flag, id_s > 0) moves to
+ * p' = R (r_s / id_s) + t with n' = R n, and in the destination keyframe it is
+ * centred at u' = K_dst pi(p') with inverse depth 1/p'_z (Eq. 1 with
+ * r' = pi(p')).  Those with p'_z > 0 and u' inside [0, W-1] x [0, H-1] are
+ * written in source order to destination surfels 0, 1, ... (the first
+ * `capacity`): id, n, centre, flags 0, cost 0, nvalid 0 and the source's
+ * last_update; src_index (may be NULL) receives the source index.  Returns
+ * the number written; *landed_out the number that landed. */
+int32_t sgo_disc_transfer(const sgo_intrinsics* Ks, const sgo_intrinsics* Kd, int32_t dst_w,
+                          int32_t dst_h, const sgo_pose* P, const sgo_surfels* src,
+                          const double* ux, const double* uy, int32_t count, sgo_surfels* dst,
+                          double* dux, double* duy, int32_t capacity, int32_t* src_index,
+                          int32_t* landed_out) {
+    int32_t landed = 0;
+    for (int32_t k = 0; k < count; ++k) {
+        if (src->flags[k] & (SGO_DEGENERATE | SGO_UNINIT)) continue;
+        if (!(src->inv_depth[k] > 0.0)) continue;
+        double rs[3], p0[3], p1[3], n1[3];
+        double n0[3] = {src->nx[k], src->ny[k], src->nz[k]};
+        sgo_ray(Ks, ux[k], uy[k], rs);
+        for (int i = 0; i < 3; ++i) p0[i] = rs[i] / src->inv_depth[k];          /* Eq. 1 */
+        for (int i = 0; i < 3; ++i) {                                            /* Eq. 10 */
+            p1[i] = P->R[3 * i] * p0[0] + P->R[3 * i + 1] * p0[1] + P->R[3 * i + 2] * p0[2] + P->t[i];
+            n1[i] = P->R[3 * i] * n0[0] + P->R[3 * i + 1] * n0[1] + P->R[3 * i + 2] * n0[2];
+        }
+        if (!(p1[2] > 0.0)) continue;
+        double r1[2] = {p1[0] / p1[2], p1[1] / p1[2]};                          /* pi(p') */
+        double u = Kd->fx * r1[0] + Kd->cx, v = Kd->fy * r1[1] + Kd->cy;
+        if (!(u >= 0.0 && u <= (double)(dst_w - 1) && v >= 0.0 && v <= (double)(dst_h - 1))) continue;
+        if (landed < capacity) {
+            int32_t j = landed;
+            dst->inv_depth[j] = 1.0 / p1[2];
+            dst->nx[j] = n1[0]; dst->ny[j] = n1[1]; dst->nz[j] = n1[2];
+            dst->flags[j] = 0;
+            dst->cost[j] = 0.0;
+            dst->nvalid[j] = 0;
+            dst->last_update[j] = src->last_update[k];
+            dux[j] = u;
+            duy[j] = v;
+            if (src_index) src_index[j] = k;
+        }
+        ++landed;
+    }
+    if (landed_out) *landed_out = landed;
+    return landed < capacity ? landed : capacity;
+}
+
 /* Landing of one source surfel in the destination keyframe (Eq. 10):
  * returns 0 when the surfel is unusable, behind the destination camera or
  * outside its tiles; else the tile index, 1/p'_z, r' = p'/p'_z and n'. */

@@ -197,6 +197,15 @@ int sgo_disc_init(const sgo_keyframe* kf, sgo_surfels* s, const double* ux, cons
                   const int32_t* surfel_index, int32_t first, int32_t n_new, double radius,
                   double beta);
 
+/* Eq. 10 for disc surfels: usable surfels move to p' = R p + t, n' = R n and
+ * are re-centred at K_dst pi(p'); those landing in the destination image are
+ * written in source order (first `capacity`).  Returns the number written. */
+int32_t sgo_disc_transfer(const sgo_intrinsics* Ks, const sgo_intrinsics* Kd, int32_t dst_w,
+                          int32_t dst_h, const sgo_pose* P, const sgo_surfels* src,
+                          const double* ux, const double* uy, int32_t count, sgo_surfels* dst,
+                          double* dux, double* duy, int32_t capacity, int32_t* src_index,
+                          int32_t* landed_out);
+
 void sgo_set_threads(int32_t n);
 int32_t sgo_max_threads(void);
 

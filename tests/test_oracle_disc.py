@@ -293,3 +293,91 @@ def test_disc_init_mean_over_two_planes_and_uninit():
     assert np.allclose([st["nx"][4], st["ny"][4], st["nz"][4]], [0, 0, -1])
     assert st["flags"][4] == 0
     assert st["flags"][5] == oracle.UNINIT and st["inv_depth"][5] == 0.0
+
+
+# --- Eq. 10 for disc surfels ------------------------------------------------------
+
+def test_disc_transfer_identity_keeps_every_usable_surfel():
+    K = (80.0, 82.0, 40.0, 30.0)
+    rng = np.random.default_rng(21)
+    m = 40
+    ux, uy = rng.uniform(0, 79, m), rng.uniform(0, 59, m)
+    ids = rng.uniform(0.2, 1.0, m)
+    ns = np.array([random_unit_cap(rng, 40) for _ in range(m)])
+    flags = np.zeros(m, np.uint32)
+    flags[3] = oracle.UNINIT
+    flags[7] = oracle.DEGENERATE
+    ids[11] = 0.0
+    st = oracle.new_state(ids, ns, flags)
+    st["last_update"][:] = np.arange(m) + 100
+    out, (dx, dy), idx, landed = oracle.disc_transfer(K, K, (80, 60), np.eye(3), np.zeros(3), st, ux, uy)
+    keep = [i for i in range(m) if i not in (3, 7, 11)]
+    assert landed == len(keep) and list(idx) == keep
+    assert np.max(np.abs(dx - ux[keep])) < 1e-12 and np.max(np.abs(dy - uy[keep])) < 1e-12
+    assert np.max(np.abs(out["inv_depth"] / ids[keep] - 1)) < 1e-14
+    assert np.max(angle_deg(np.stack([out["nx"], out["ny"], out["nz"]], 1), ns[keep])) < 1e-12
+    assert np.array_equal(out["last_update"], np.arange(m)[keep] + 100) and np.all(out["flags"] == 0)
+
+
+def test_disc_transfer_sideways_wall_shifts_by_f_t_over_d():
+    """A fronto-parallel wall at depth 2 m; the camera frame moves so that
+    X' = X + (1/8, 0, 0): every centre shifts by fx (1/8) / 2 = 4 px, depth
+    and normal are kept (every quantity is exact in binary with fx = 64,
+    cx = 32); a centre landing exactly on the last column (x = 79) stays,
+    centres pushed past it drop out, and a capacity keeps the first ones in
+    source order.  A surfel of negative inverse depth is never moved, even
+    where the pose would put its point in front of the camera."""
+    K = (64.0, 64.0, 32.0, 30.0)
+    xs = np.array([3.0, 9.0, 30.0, 57.5, 75.0, 76.0, 78.0])
+    ux = np.tile(xs, 3)
+    uy = np.repeat([5.0, 20.0, 41.5], xs.size)
+    m = ux.size
+    st = oracle.new_state(np.full(m, 0.5), np.tile([0.0, 0.0, -1.0], (m, 1)))
+    out, (dx, dy), idx, landed = oracle.disc_transfer(K, K, (80, 60), np.eye(3), [0.125, 0.0, 0.0], st, ux, uy)
+    inside = ux + 4.0 <= 79.0
+    assert landed == inside.sum() and np.array_equal(idx, np.nonzero(inside)[0])
+    assert np.array_equal(dx, ux[inside] + 4.0) and np.array_equal(dy, uy[inside])
+    assert 79.0 in dx and np.all(out["inv_depth"] == 0.5)
+    out2, _, idx2, landed2 = oracle.disc_transfer(K, K, (80, 60), np.eye(3), [0.125, 0.0, 0.0], st, ux, uy,
+                                                  capacity=5)
+    assert landed2 == landed and np.array_equal(idx2, idx[:5])
+    # id = -0.5 at the principal point: p = (0, 0, -2), moved by t_z = 3 to z = 1
+    neg = oracle.new_state([-0.5, 0.5], [[0.0, 0.0, -1.0], [0.0, 0.0, -1.0]])
+    _, _, nidx, nland = oracle.disc_transfer(K, K, (80, 60), np.eye(3), [0.0, 0.0, 3.0], neg, [32.0, 40.0],
+                                             [30.0, 30.0])
+    assert nland == 1 and list(nidx) == [1]
+
+
+def test_disc_transfer_round_trip_and_matrix_projection():
+    """A general pose and its inverse bring every surfel back; the forward
+    landing equals a 4x4 homogeneous-matrix projection of the back-projected
+    centre."""
+    K = (300.0, 310.0, 160.0, 120.0)
+    rng = np.random.default_rng(22)
+    m = 60
+    ux, uy = rng.uniform(40, 280, m), rng.uniform(30, 210, m)
+    ids = rng.uniform(0.3, 0.8, m)
+    ns = np.array([random_unit_cap(rng, 40) for _ in range(m)])
+    R = rot(rng.normal(size=3), math.radians(3.0))
+    t = np.array([0.05, -0.03, 0.02])
+    st = oracle.new_state(ids, ns)
+    out, (dx, dy), idx, landed = oracle.disc_transfer(K, K, (320, 240), R, t, st, ux, uy)
+    assert landed > 50
+    fx, fy, cx, cy = K
+    T = np.eye(4)
+    T[:3, :3] = R
+    T[:3, 3] = t
+    Km = np.array([[fx, 0, cx], [0, fy, cy], [0, 0, 1.0]])
+    got_n = np.stack([out["nx"], out["ny"], out["nz"]], 1)
+    assert np.max(np.abs(got_n - ns[idx] @ R.T)) < 1e-15      # n' = R n
+    for j, i in enumerate(idx):
+        P = np.append(np.linalg.solve(Km, [ux[i], uy[i], 1.0]) / ids[i], 1.0)
+        q = Km @ (T @ P)[:3]
+        assert q[0] / q[2] == pytest.approx(dx[j], abs=1e-9)
+        assert q[1] / q[2] == pytest.approx(dy[j], abs=1e-9)
+        assert 1.0 / (T @ P)[2] == pytest.approx(out["inv_depth"][j], rel=1e-12)
+    back, (bx, by), bidx, _ = oracle.disc_transfer(K, K, (320, 240), R.T, -R.T @ t, out, dx, dy)
+    src = idx[bidx]
+    assert np.max(np.abs(bx - ux[src])) < 1e-9 and np.max(np.abs(by - uy[src])) < 1e-9
+    assert np.max(np.abs(back["inv_depth"] / ids[src] - 1)) < 1e-12
+    assert np.max(angle_deg(np.stack([back["nx"], back["ny"], back["nz"]], 1), ns[src])) < 1e-9
