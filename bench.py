@@ -132,8 +132,7 @@ def disc_leg(ctx, kfs, storage, iters, steps, with_ablation):
 
     def step():
         ev[0].record()
-        for d in dks:
-            d.render()
+        engine.disc_render(ctx, dks)
         ev[1].record()
         for d in dks:
             sg.sgn_disc_place(ctx.handle, d.item(), d.index_out.data_ptr(), d.capacity, pp,
@@ -144,8 +143,7 @@ def disc_leg(ctx, kfs, storage, iters, steps, with_ablation):
             d.count += int(c[0])
         engine.disc_update(ctx, dks, prm)
         ev[3].record()
-        for d in dks:
-            d.render()
+        engine.disc_render(ctx, dks)
         ev[4].record()
         return counts
 

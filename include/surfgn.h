@@ -292,6 +292,13 @@ sgn_status sgn_disc_optimize(sgn_ctx* ctx, const sgn_disc_item* items, int32_t n
 sgn_status sgn_disc_render(sgn_ctx* ctx, const sgn_disc_item* item, float* inv_depth_out,
                            int32_t* index_out);
 
+/* sgn_disc_render for n_items keyframes in one pass (four launches in all):
+ * inv_depth_outs and index_outs are host arrays of n_items device pointers
+ * (index_outs, or any of its entries, may be NULL).  The scratch holds 12
+ * bytes per pixel of every keyframe. */
+sgn_status sgn_disc_render_batch(sgn_ctx* ctx, const sgn_disc_item* items, int32_t n_items,
+                                 float* const* inv_depth_outs, int32_t* const* index_outs);
+
 /* Parameters of the empty-area search (the paper leaves alpha and beta open). */
 typedef struct {
     float alpha;                /* a candidate needs no measurement within alpha r: (0, 4] */
@@ -321,6 +328,23 @@ typedef struct {
 sgn_status sgn_disc_place(sgn_ctx* ctx, const sgn_disc_item* item, const int32_t* index_map,
                           int32_t capacity, const sgn_disc_place_params* params,
                           int32_t* counts_out);
+
+/* Surfel reference-frame change (Eq. 10) for disc surfels, which stay discs:
+ * a usable surfel of src (no DEGENERATE or UNINIT flag, id_s > 0) moves to
+ * p' = R (r_s / id_s) + t with n' = R n (pose: X_dst = R X_src + t, host
+ * memory) and is centred in the destination keyframe at u' = K_dst pi(p')
+ * with inverse depth 1/p'_z.  Those with p'_z > 0 whose u' lies in
+ * [0, W-1] x [0, H-1] of dst's image are written in source order to dst's
+ * surfels 0, 1, ... up to capacity - 1: id, n, centre, flags 0, cost 0,
+ * nvalid 0 and the source's last_update.  Landing decisions are taken in
+ * double.  dst supplies the destination intrinsics, image size and arrays
+ * (dst->count is not read).  counts_out: device int32[2] receiving the number
+ * written and the number that landed; src_index_out: device int32
+ * [capacity] (source index of each written surfel) or NULL.  src and dst
+ * arrays must not overlap.  Asynchronous. */
+sgn_status sgn_disc_transfer(sgn_ctx* ctx, const sgn_disc_item* src, const sgn_pose* pose,
+                             const sgn_disc_item* dst, int32_t capacity, int32_t* counts_out,
+                             int32_t* src_index_out);
 
 /* Convert a float image (device, src_pitch elements per row) to dst->dtype
  * storage at dst->data: F16 with round-to-nearest-even, or U8 as

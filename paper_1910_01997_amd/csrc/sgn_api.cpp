@@ -816,33 +816,60 @@ sgn_status sgn_disc_optimize(sgn_ctx* c, const sgn_disc_item* items, int32_t n, 
     return run_disc_batch(c, items, n, p);
 }
 
-sgn_status sgn_disc_render(sgn_ctx* c, const sgn_disc_item* item, float* inv_depth_out,
-                           int32_t* index_out) {
+sgn_status sgn_disc_render_batch(sgn_ctx* c, const sgn_disc_item* items, int32_t n,
+                                 float* const* inv_depth_outs, int32_t* const* index_outs) {
     if (!c) return fail(SGN_E_INVALID, "null context");
-    sgn_status st = check_disc_item(item, false);
-    if (st) return st;
-    if (!inv_depth_out) return fail(SGN_E_INVALID, "null output");
+    if (n < 1 || !items || !inv_depth_outs) return fail(SGN_E_INVALID, "empty batch or null array");
+    std::vector<DiscRenderItem> tab(n);
+    int64_t total_surfels = 0, total_pixels = 0;
+    for (int i = 0; i < n; ++i) {
+        const sgn_disc_item* it = &items[i];
+        sgn_status st = check_disc_item(it, false);
+        if (st) return st;
+        if (!inv_depth_outs[i]) return fail(SGN_E_INVALID, "null output");
+        DiscRenderItem& r = tab[i];
+        r.inv_depth = it->surfels.inv_depth;
+        r.nx = it->surfels.nx; r.ny = it->surfels.ny; r.nz = it->surfels.nz;
+        r.flags = it->surfels.flags;
+        r.ux = it->ux; r.uy = it->uy;
+        r.inv_depth_out = inv_depth_outs[i];
+        r.index_out = index_outs ? index_outs[i] : nullptr;
+        r.count = it->count;
+        r.width = it->kf.kf.width; r.height = it->kf.kf.height;
+        r.surfel_base = (int32_t)total_surfels;
+        r.pixel_base = total_pixels;
+        r.radius = it->radius;
+        r.fx = it->kf.K.fx; r.fy = it->kf.K.fy; r.cx = it->kf.K.cx; r.cy = it->kf.K.cy;
+        total_surfels += it->count;
+        total_pixels += (int64_t)r.width * r.height;
+    }
+    if (total_surfels > (int64_t)INT32_MAX / 2) return fail(SGN_E_UNSUPPORTED, "too many surfels in one batch");
     SGN_HIP(hipSetDevice(c->device));
-    const int W = item->kf.kf.width, H = item->kf.kf.height;
-    const size_t npix = (size_t)W * (size_t)H;
-    st = ensure_scratch(c, npix * (sizeof(unsigned long long) + sizeof(int32_t)));
+    sgn_status st = ensure_scratch(c, (size_t)total_pixels * (sizeof(unsigned long long) + sizeof(int32_t)));
     if (st) return st;
-    DiscRenderArgs a{};
-    a.inv_depth = item->surfels.inv_depth;
-    a.nx = item->surfels.nx; a.ny = item->surfels.ny; a.nz = item->surfels.nz;
-    a.flags = item->surfels.flags;
-    a.ux = item->ux; a.uy = item->uy;
-    a.count = item->count;
-    a.width = W; a.height = H;
-    a.radius = item->radius;
-    a.fx = item->kf.K.fx; a.fy = item->kf.K.fy; a.cx = item->kf.K.cx; a.cy = item->kf.K.cy;
-    a.key = (unsigned long long*)c->scratch;
-    a.idx = (int32_t*)((char*)c->scratch + npix * sizeof(unsigned long long));
-    a.inv_depth_out = inv_depth_out;
-    a.index_out = index_out;
-    hipError_t e = launch_disc_render(a, c->stream);
+    // the table goes through the staging ring into the device table
+    const size_t bytes = sizeof(DiscRenderItem) * (size_t)n;
+    st = ensure_table(c, bytes);
+    if (st) return st;
+    const int slot = c->ring_next;
+    c->ring_next = (c->ring_next + 1) % kRingSlots;
+    if (c->ring_used[slot]) SGN_HIP(hipEventSynchronize(c->ring_ev[slot]));
+    std::memcpy(c->host_ring[slot], tab.data(), bytes);
+    SGN_HIP(hipMemcpyAsync(c->dev_table, c->host_ring[slot], bytes, hipMemcpyHostToDevice, c->stream));
+    SGN_HIP(hipEventRecord(c->ring_ev[slot], c->stream));
+    c->ring_used[slot] = true;
+    unsigned long long* key = (unsigned long long*)c->scratch;
+    int32_t* idx = (int32_t*)((char*)c->scratch + (size_t)total_pixels * sizeof(unsigned long long));
+    hipError_t e = launch_disc_render((const DiscRenderItem*)c->dev_table, n, (int)total_surfels, total_pixels,
+                                      key, idx, c->stream);
     if (e != hipSuccess) return hip_fail(e, "disc render launch");
     return SGN_OK;
+}
+
+sgn_status sgn_disc_render(sgn_ctx* c, const sgn_disc_item* item, float* inv_depth_out,
+                           int32_t* index_out) {
+    if (!item) return fail(SGN_E_INVALID, "null disc item");
+    return sgn_disc_render_batch(c, item, 1, &inv_depth_out, &index_out);
 }
 
 sgn_status sgn_disc_place(sgn_ctx* c, const sgn_disc_item* item, const int32_t* index_map,
@@ -884,6 +911,50 @@ sgn_status sgn_disc_place(sgn_ctx* c, const sgn_disc_item* item, const int32_t* 
     a.counts = counts_out;
     hipError_t e = launch_disc_place(a, c->stream);
     if (e != hipSuccess) return hip_fail(e, "disc placement launch");
+    return SGN_OK;
+}
+
+sgn_status sgn_disc_transfer(sgn_ctx* c, const sgn_disc_item* src, const sgn_pose* pose,
+                             const sgn_disc_item* dst, int32_t capacity, int32_t* counts_out,
+                             int32_t* src_index_out) {
+    if (!c || !pose || !counts_out) return fail(SGN_E_INVALID, "null argument");
+    sgn_status st = check_disc_item(src, false);
+    if (st) return st;
+    if (!dst) return fail(SGN_E_INVALID, "null destination");
+    st = check_keyframe(&dst->kf, false, true);
+    if (st) return st;
+    if (capacity < 0) return fail(SGN_E_INVALID, "negative capacity");
+    if (capacity > 0) {
+        if (!dst->ux || !dst->uy) return fail(SGN_E_INVALID, "null destination centre array");
+        st = check_surfels(&dst->surfels);
+        if (st) return st;
+    }
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(pose->R[i])) return fail(SGN_E_INVALID, "pose is not finite");
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(pose->t[i])) return fail(SGN_E_INVALID, "pose is not finite");
+    SGN_HIP(hipSetDevice(c->device));
+    DiscTransferArgs a{};
+    a.inv_depth = src->surfels.inv_depth;
+    a.nx = src->surfels.nx; a.ny = src->surfels.ny; a.nz = src->surfels.nz;
+    a.flags = src->surfels.flags;
+    a.last_update = src->surfels.last_update;
+    a.ux = src->ux; a.uy = src->uy;
+    a.count = src->count;
+    a.dst_w = dst->kf.kf.width; a.dst_h = dst->kf.kf.height;
+    a.capacity = capacity;
+    a.sK[0] = src->kf.K.fx; a.sK[1] = src->kf.K.fy; a.sK[2] = src->kf.K.cx; a.sK[3] = src->kf.K.cy;
+    a.dK[0] = dst->kf.K.fx; a.dK[1] = dst->kf.K.fy; a.dK[2] = dst->kf.K.cx; a.dK[3] = dst->kf.K.cy;
+    for (int i = 0; i < 9; ++i) a.R[i] = pose->R[i];
+    for (int i = 0; i < 3; ++i) a.t[i] = pose->t[i];
+    a.dst = RegridSurfels{dst->surfels.inv_depth, dst->surfels.nx, dst->surfels.ny, dst->surfels.nz,
+                          dst->surfels.flags, dst->surfels.cost, dst->surfels.nvalid,
+                          dst->surfels.last_update};
+    a.dux = dst->ux; a.duy = dst->uy;
+    a.src_index = src_index_out;
+    a.counts = counts_out;
+    hipError_t e = launch_disc_transfer(a, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "disc transfer launch");
     return SGN_OK;
 }
 

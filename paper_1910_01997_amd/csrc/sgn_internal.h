@@ -154,9 +154,10 @@ constexpr float kDiscMaxRadius = 12.f;
 // Gauss-Newton over the disc surfels of a batch: one wavefront per surfel,
 // items are surfels (KfDev::item_base = surfel_base, n_items = count).
 hipError_t launch_disc_gn(int dtype, const BatchHeader* hdr, int total_surfels, hipStream_t s);
-// Depth-buffered render of one keyframe's discs into key/idx scratch (one
-// 64-bit key and one index per pixel), then into the outputs.
-struct DiscRenderArgs {
+// Depth-buffered render of the discs of several keyframes: one table entry
+// per keyframe (device memory); the scratch holds one 64-bit depth key and
+// one index per pixel of every keyframe, keyframe after keyframe.
+struct DiscRenderItem {
     const float* inv_depth;
     const float* nx;
     const float* ny;
@@ -164,15 +165,17 @@ struct DiscRenderArgs {
     const uint32_t* flags;
     const float* ux;
     const float* uy;
-    int32_t count, width, height;
-    float radius;
-    double fx, fy, cx, cy;
-    unsigned long long* key;      // scratch [width * height]
-    int32_t* idx;                 // scratch [width * height]
     float* inv_depth_out;         // [width * height]
     int32_t* index_out;           // [width * height] or null
+    int32_t count, width, height, surfel_base;
+    int64_t pixel_base;
+    float radius;
+    int32_t pad;
+    double fx, fy, cx, cy;
 };
-hipError_t launch_disc_render(const DiscRenderArgs& a, hipStream_t s);
+hipError_t launch_disc_render(const DiscRenderItem* table, int n_items, int total_surfels,
+                              int64_t total_pixels, unsigned long long* key, int32_t* idx,
+                              hipStream_t s);
 // The search for empty areas on the lattice (spacing/2 + i spacing, ...),
 // placement of the qualifying candidates as surfels first .. and their
 // neighbour initialisation from the index map.
@@ -196,6 +199,28 @@ struct DiscPlaceArgs {
     int32_t* counts;              // device [2]: placed, qualifying
 };
 hipError_t launch_disc_place(const DiscPlaceArgs& a, hipStream_t s);
+// Eq. 10 for disc surfels: each usable source surfel moves to p' = R p + t,
+// n' = R n, and is re-centred at K_dst pi(p'); those landing in the
+// destination image are written in source order.
+struct DiscTransferArgs {
+    const float* inv_depth;
+    const float* nx;
+    const float* ny;
+    const float* nz;
+    const uint32_t* flags;
+    const uint32_t* last_update;
+    const float* ux;
+    const float* uy;
+    int32_t count, dst_w, dst_h, capacity;
+    double sK[4], dK[4];          // fx, fy, cx, cy of source and destination
+    double R[9], t[3];            // X_dst = R X_src + t
+    RegridSurfels dst;
+    float* dux;
+    float* duy;
+    int32_t* src_index;           // may be null
+    int32_t* counts;              // device [2]: written, landed
+};
+hipError_t launch_disc_transfer(const DiscTransferArgs& a, hipStream_t s);
 hipError_t launch_quantize(const float* src, int src_pitch, void* dst, int dst_pitch,
                            int width, int height, int dtype, float scale, hipStream_t s);
 // Workgroups of 256 threads of the chosen GN variant that fit on one CU.

@@ -1805,20 +1805,46 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
 // bits), pass 1 the lowest index among the surfels that reach it, and the
 // resolve step writes the outputs.  id_u is evaluated in double in the
 // printed form of Eq. 3, id_u = (r_u . n) / ((r_s / id_s) . n).
-__global__ void disc_clear_kernel(unsigned long long* __restrict__ key, int32_t* __restrict__ idx, int n) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+__global__ void disc_clear_kernel(unsigned long long* __restrict__ key, int32_t* __restrict__ idx,
+                                  int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
         key[i] = 0ull;
         idx[i] = 0x7fffffff;
     }
 }
 
+// Table entry of global surfel g (largest surfel_base <= g among entries
+// with surfels) or of global pixel p (by pixel_base).
+__device__ __forceinline__ int render_item_of_surfel(const DiscRenderItem* tab, int n, int g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].surfel_base <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;        // entries without surfels share the next base and are never the largest
+}
+__device__ __forceinline__ int render_item_of_pixel(const DiscRenderItem* tab, int n, int64_t p) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].pixel_base <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 template <int PASS>
-__global__ __launch_bounds__(kBlockThreads) void disc_scatter_kernel(DiscRenderArgs a) {
+__global__ __launch_bounds__(kBlockThreads) void disc_scatter_kernel(const DiscRenderItem* __restrict__ tab,
+                                                                     int n_items, int total,
+                                                                     unsigned long long* __restrict__ key,
+                                                                     int32_t* __restrict__ idx) {
 #pragma clang fp contract(off)
     const int lane = threadIdx.x & (kWaveSize - 1);
     const int wave = threadIdx.x >> 6;
-    const int s = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlockThreads / kWaveSize) + wave);
-    if (s >= a.count) return;
+    const int g = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlockThreads / kWaveSize) + wave);
+    if (g >= total) return;
+    const DiscRenderItem& a = tab[render_item_of_surfel(tab, n_items, g)];
+    const int s = g - a.surfel_base;
     if (a.flags[s] & (F_DEGENERATE | F_UNINIT)) return;
     __shared__ int s_rows[kBlockThreads / kWaveSize][kDiscRowWords];
     int* const row_x0 = s_rows[wave];
@@ -1830,6 +1856,8 @@ __global__ __launch_bounds__(kBlockThreads) void disc_scatter_kernel(DiscRenderA
     const double den = ps0 * n0 + ps1 * n1 + ps2 * n2;
     wave_sync();
     const DiscRows d = disc_rows(a.ux[s], a.uy[s], a.radius, a.width, a.height, lane, row_x0, row_start);
+    unsigned long long* const kk = key + a.pixel_base;
+    int32_t* const ii = idx + a.pixel_base;
     for (int k = lane; k < d.total; k += kWaveSize) {
         int x, y;
         disc_pixel(d, row_x0, row_start, k, x, y);
@@ -1839,18 +1867,26 @@ __global__ __launch_bounds__(kBlockThreads) void disc_scatter_kernel(DiscRenderA
         const size_t o = (size_t)y * (size_t)a.width + (size_t)x;
         const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
         if (PASS == 0)
-            atomicMax(a.key + o, bits);
-        else if (a.key[o] == bits)
-            atomicMin(a.idx + o, s);
+            atomicMax(kk + o, bits);
+        else if (kk[o] == bits)
+            atomicMin(ii + o, s);
     }
 }
 
-__global__ void disc_resolve_kernel(DiscRenderArgs a) {
-    const int n = a.width * a.height;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const unsigned long long k = a.key[i];
+__global__ void disc_resolve_kernel(const DiscRenderItem* __restrict__ tab, int n_items, int64_t total,
+                                    const unsigned long long* __restrict__ key,
+                                    const int32_t* __restrict__ idx) {
+    int hint = 0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        if (!(p >= tab[hint].pixel_base &&
+              p < tab[hint].pixel_base + (int64_t)tab[hint].width * tab[hint].height))
+            hint = render_item_of_pixel(tab, n_items, p);
+        const DiscRenderItem& a = tab[hint];
+        const int64_t i = p - a.pixel_base;
+        const unsigned long long k = key[p];
         a.inv_depth_out[i] = k ? (float)__longlong_as_double((long long)k) : 0.f;
-        if (a.index_out) a.index_out[i] = k ? a.idx[i] : -1;
+        if (a.index_out) a.index_out[i] = k ? idx[p] : -1;
     }
 }
 
@@ -2016,6 +2052,85 @@ __global__ __launch_bounds__(kWaveSize) void disc_init_kernel(DiscPlaceArgs a) {
     a.last_update[i] = 0u;
 }
 
+// Eq. 10 for disc surfels (a disc stays a disc): a usable source surfel (no
+// DEGENERATE or UNINIT flag, id_s > 0) moves to p' = R (r_s / id_s) + t with
+// n' = R n and is re-centred at u' = K_dst pi(p'), inverse depth 1/p'_z.
+// Those with p'_z > 0 and u' in [0, W-1] x [0, H-1] are written in source
+// order (as many as there is room for).  One workgroup walks the sources in
+// chunks; every landing is computed in double in the oracle's order, so the
+// kept set and the order are the same.
+__global__ __launch_bounds__(1024) void disc_transfer_kernel(DiscTransferArgs a) {
+#pragma clang fp contract(off)
+    __shared__ int s_wave[1024 / kWaveSize + 1];
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const int wave = threadIdx.x >> 6;
+    constexpr int kWaves = 1024 / kWaveSize;
+    int base = 0;
+    for (int c0 = 0; c0 < a.count; c0 += 1024) {
+        const int k = c0 + (int)threadIdx.x;
+        bool land = false;
+        double u = 0.0, v = 0.0, idn = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
+        if (k < a.count && !(a.flags[k] & (F_DEGENERATE | F_UNINIT)) && a.inv_depth[k] > 0.f) {
+            const double ids = a.inv_depth[k];
+            const double rs0 = ((double)a.ux[k] - a.sK[2]) / a.sK[0];
+            const double rs1 = ((double)a.uy[k] - a.sK[3]) / a.sK[1];
+            const double p0 = rs0 / ids, p1 = rs1 / ids, p2 = 1.0 / ids;
+            const double n0 = a.nx[k], n1 = a.ny[k], n2 = a.nz[k];
+            const double q0 = a.R[0] * p0 + a.R[1] * p1 + a.R[2] * p2 + a.t[0];
+            const double q1 = a.R[3] * p0 + a.R[4] * p1 + a.R[5] * p2 + a.t[1];
+            const double q2 = a.R[6] * p0 + a.R[7] * p1 + a.R[8] * p2 + a.t[2];
+            m0 = a.R[0] * n0 + a.R[1] * n1 + a.R[2] * n2;
+            m1 = a.R[3] * n0 + a.R[4] * n1 + a.R[5] * n2;
+            m2 = a.R[6] * n0 + a.R[7] * n1 + a.R[8] * n2;
+            if (q2 > 0.0) {
+                u = a.dK[0] * (q0 / q2) + a.dK[2];
+                v = a.dK[1] * (q1 / q2) + a.dK[3];
+                land = u >= 0.0 && u <= (double)(a.dst_w - 1) && v >= 0.0 && v <= (double)(a.dst_h - 1);
+                idn = 1.0 / q2;
+            }
+        }
+        const unsigned long long ball = __ballot(land);
+        const int below = __popcll(ball & ((1ull << lane) - 1ull));
+        if (lane == 0) s_wave[wave] = __popcll(ball);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int acc = 0;
+            for (int w = 0; w < kWaves; ++w) {
+                const int t = s_wave[w];
+                s_wave[w] = acc;
+                acc += t;
+            }
+            s_wave[kWaves] = acc;
+        }
+        __syncthreads();
+        const int rank = base + s_wave[wave] + below;
+        if (land && rank < a.capacity) {
+            a.dst.inv_depth[rank] = (float)idn;
+            a.dst.nx[rank] = (float)m0;
+            a.dst.ny[rank] = (float)m1;
+            a.dst.nz[rank] = (float)m2;
+            a.dst.flags[rank] = 0u;
+            a.dst.cost[rank] = 0.f;
+            a.dst.nvalid[rank] = 0u;
+            a.dst.last_update[rank] = a.last_update[k];
+            a.dux[rank] = (float)u;
+            a.duy[rank] = (float)v;
+            if (a.src_index) a.src_index[rank] = k;
+        }
+        base += s_wave[kWaves];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.counts[0] = min(base, a.capacity);
+        a.counts[1] = base;
+    }
+}
+
+hipError_t launch_disc_transfer(const DiscTransferArgs& a, hipStream_t s) {
+    disc_transfer_kernel<<<1, 1024, 0, s>>>(a);
+    return hipGetLastError();
+}
+
 hipError_t launch_disc_gn(int dtype, const BatchHeader* hdr, int total_surfels, hipStream_t s) {
     if (total_surfels <= 0) return hipSuccess;
     const int waves = kBlockThreads / kWaveSize;
@@ -2026,17 +2141,18 @@ hipError_t launch_disc_gn(int dtype, const BatchHeader* hdr, int total_surfels, 
     return hipGetLastError();
 }
 
-hipError_t launch_disc_render(const DiscRenderArgs& a, hipStream_t s) {
-    const int n = a.width * a.height;
-    const int fill = std::min((n + 255) / 256, 4096);
-    disc_clear_kernel<<<fill, 256, 0, s>>>(a.key, a.idx, n);
-    if (a.count > 0) {
+hipError_t launch_disc_render(const DiscRenderItem* table, int n_items, int total_surfels,
+                              int64_t total_pixels, unsigned long long* key, int32_t* idx,
+                              hipStream_t s) {
+    const int fill = (int)std::min<int64_t>((total_pixels + 255) / 256, 8192);
+    disc_clear_kernel<<<fill, 256, 0, s>>>(key, idx, total_pixels);
+    if (total_surfels > 0) {
         const int waves = kBlockThreads / kWaveSize;
-        const dim3 grid((a.count + waves - 1) / waves);
-        disc_scatter_kernel<0><<<grid, kBlockThreads, 0, s>>>(a);
-        disc_scatter_kernel<1><<<grid, kBlockThreads, 0, s>>>(a);
+        const dim3 grid((total_surfels + waves - 1) / waves);
+        disc_scatter_kernel<0><<<grid, kBlockThreads, 0, s>>>(table, n_items, total_surfels, key, idx);
+        disc_scatter_kernel<1><<<grid, kBlockThreads, 0, s>>>(table, n_items, total_surfels, key, idx);
     }
-    disc_resolve_kernel<<<fill, 256, 0, s>>>(a);
+    disc_resolve_kernel<<<fill, 256, 0, s>>>(table, n_items, total_pixels, key, idx);
     return hipGetLastError();
 }
 

@@ -180,12 +180,30 @@ class DiscKeyframe:
         self.count += placed
         return placed, found
 
+    def transfer_from(self, src: "DiscKeyframe", R, t, src_index: Optional[torch.Tensor] = None):
+        """Eq. 10: replace this keyframe's surfels with src's, moved by the
+        pose X_self = R X_src + t (the ones that land in this image, up to
+        the capacity); waits for the device and returns (written, landed)."""
+        sg.sgn_disc_transfer(self.ctx.handle, src.item(), sg.pose_of(R, t), self.item(), self.capacity,
+                             self.counts.data_ptr(), src_index.data_ptr() if src_index is not None else 0)
+        written, landed = (int(v) for v in self.counts.cpu().tolist())
+        self.count = written
+        return written, landed
+
     def centres(self):
         return (self.ux[:self.count].cpu().numpy(), self.uy[:self.count].cpu().numpy())
 
     def state_host(self) -> dict:
         h = self.state.to_host()
         return {k: v[:self.count] for k, v in h.items()}
+
+
+def disc_render(ctx: sg.Context, dks: Sequence[DiscKeyframe]):
+    """Depth-buffered render of several keyframes' discs in one pass."""
+    items = sg.disc_array([d.item() for d in dks])
+    sg.sgn_disc_render_batch(ctx.handle, items, len(dks), [d.inv_depth_out.data_ptr() for d in dks],
+                             [d.index_out.data_ptr() for d in dks])
+    return items
 
 
 def disc_update(ctx: sg.Context, dks: Sequence[DiscKeyframe], prm: sg.sgn_params):

@@ -37,7 +37,7 @@ EXPORTED = [
     "sgn_optimize_keyframe", "sgn_render_inverse_depth", "sgn_optimize_batch", "sgn_autotune",
     "sgn_quantize", "sgn_last_kernel_ms", "sgn_device_info", "sgn_status_str", "sgn_last_error",
     "sgn_version", "sgn_transfer_surfels", "sgn_disc_optimize", "sgn_disc_render", "sgn_disc_place",
-    "sgn_recent_kernel_ms",
+    "sgn_recent_kernel_ms", "sgn_disc_transfer", "sgn_disc_render_batch",
 ]
 
 
@@ -159,6 +159,12 @@ def lib():
         L.sgn_disc_place.restype = st
         L.sgn_disc_place.argtypes = [vp, C.POINTER(sgn_disc_item), vp, C.c_int32,
                                      C.POINTER(sgn_disc_place_params), vp]
+        L.sgn_disc_render_batch.restype = st
+        L.sgn_disc_render_batch.argtypes = [vp, C.POINTER(sgn_disc_item), C.c_int32,
+                                            C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]
+        L.sgn_disc_transfer.restype = st
+        L.sgn_disc_transfer.argtypes = [vp, C.POINTER(sgn_disc_item), C.POINTER(sgn_pose),
+                                        C.POINTER(sgn_disc_item), C.c_int32, vp, vp]
         L.sgn_recent_kernel_ms.restype = st
         L.sgn_recent_kernel_ms.argtypes = [vp, C.c_int32, C.POINTER(C.c_float)]
         L.sgn_last_kernel_ms.restype = st
@@ -259,6 +265,20 @@ def sgn_disc_place(ctx, item: sgn_disc_item, index_map_ptr: int, capacity: int,
     check(lib().sgn_disc_place(C.c_void_p(ctx), C.byref(item), C.c_void_p(index_map_ptr),
                                int(capacity), C.byref(params), C.c_void_p(counts_ptr)),
           "sgn_disc_place")
+
+
+def sgn_disc_transfer(ctx, src: sgn_disc_item, pose: sgn_pose, dst: sgn_disc_item, capacity: int,
+                      counts_ptr: int, src_index_ptr: int = 0):
+    check(lib().sgn_disc_transfer(C.c_void_p(ctx), C.byref(src), C.byref(pose), C.byref(dst),
+                                  int(capacity), C.c_void_p(counts_ptr), C.c_void_p(src_index_ptr or None)),
+          "sgn_disc_transfer")
+
+
+def sgn_disc_render_batch(ctx, items, n: int, inv_depth_ptrs: Sequence[int],
+                          index_ptrs: Optional[Sequence[int]] = None):
+    outs = (C.c_void_p * int(n))(*[int(p) for p in inv_depth_ptrs])
+    idxs = (C.c_void_p * int(n))(*[int(p) if p else None for p in index_ptrs]) if index_ptrs else None
+    check(lib().sgn_disc_render_batch(C.c_void_p(ctx), items, int(n), outs, idxs), "sgn_disc_render_batch")
 
 
 def disc_array(items: List[sgn_disc_item]):

@@ -242,3 +242,112 @@ def test_disc_argument_errors(ctx):
     # nothing was enqueued: the state is untouched
     torch.cuda.synchronize()
     assert np.array_equal(dk.state_host()["inv_depth"], discs.init_id)
+
+
+def _as_keyframe_of(kf, j):
+    """Neighbour frame j of kf as a keyframe: its image, with the old keyframe
+    and the other neighbour frames as its neighbours (poses composed:
+    X_i = R_i R_j^T (X_j - t_j) + t_i)."""
+    Rj, tj = kf.R[j], kf.t[j]
+    imgs = [kf.kf_image] + [kf.nbr_images[i] for i in range(kf.n_nbr) if i != j]
+    Rs = [Rj.T] + [kf.R[i] @ Rj.T for i in range(kf.n_nbr) if i != j]
+    ts = [-Rj.T @ tj] + [kf.t[i] - kf.R[i] @ Rj.T @ tj for i in range(kf.n_nbr) if i != j]
+    return kf.nbr_images[j], torch.stack(imgs), np.stack(Rs), np.stack(ts)
+
+
+def test_disc_transfer_matches_oracle_exactly(ctx):
+    sg, engine = _mods()
+    kf, discs = _scene(seed=71)
+    print("case disc transfer 320x240", flush=True)
+    src = engine.DiscKeyframe.from_scene(ctx, kf, discs)
+    engine.disc_update(ctx, [src], sg.params(iters=5))
+    img1, nb1, R1, t1 = _as_keyframe_of(kf, 0)
+    for cap in (src.count + 10, 50):
+        dst = engine.DiscKeyframe(ctx, img1, nb1, R1, t1, kf.K, 10.0, np.zeros(0, np.float32),
+                                  np.zeros(0, np.float32), np.zeros(0, np.float32), np.zeros((0, 3), np.float32),
+                                  capacity=cap)
+        sidx = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+        written, landed = dst.transfer_from(src, kf.R[0], kf.t[0], src_index=sidx)
+        torch.cuda.synchronize()
+        h = src.state_host()
+        ux, uy = src.centres()
+        st = oracle_state(h["inv_depth"], h["n"], h["flags"])
+        st["last_update"][:] = h["last_update"]
+        out, (ox, oy), oidx, o_landed = oracle.disc_transfer(kf.K, kf.K, (320, 240), kf.R[0], kf.t[0], st,
+                                                             ux.astype(np.float64), uy.astype(np.float64),
+                                                             capacity=cap)
+        assert landed == o_landed and written == min(cap, landed) and landed > 250
+        assert np.array_equal(sidx.cpu().numpy()[:written], oidx)
+        dh = dst.state_host()
+        dx, dy = dst.centres()
+        assert np.array_equal(dx, ox.astype(np.float32)) and np.array_equal(dy, oy.astype(np.float32))
+        assert np.array_equal(dh["inv_depth"], out["inv_depth"].astype(np.float32))
+        assert np.array_equal(dh["n"], np.stack([out["nx"], out["ny"], out["nz"]], 1).astype(np.float32))
+        assert np.all(dh["flags"] == 0) and np.array_equal(dh["last_update"], out["last_update"])
+
+
+def test_disc_two_keyframes_chained(ctx):
+    """Keyframe 0 optimised, its surfels moved into keyframe 1 (a neighbour
+    frame, Eq. 10), rendered there, the empty areas filled, and keyframe 1
+    optimised: every stage against the oracle from the device's input."""
+    sg, engine = _mods()
+    kf, discs = _scene(640, 480, 6, seed=72)
+    print("case disc two keyframes 640x480", flush=True)
+    k0 = engine.DiscKeyframe.from_scene(ctx, kf, discs, storage="f16")
+    engine.disc_update(ctx, [k0], sg.params(iters=8))
+    img1, nb1, R1, t1 = _as_keyframe_of(kf, 2)
+    k1 = engine.DiscKeyframe(ctx, img1, nb1, R1, t1, kf.K, 10.0, np.zeros(0, np.float32),
+                             np.zeros(0, np.float32), np.zeros(0, np.float32), np.zeros((0, 3), np.float32),
+                             capacity=k0.count + 800, storage="f16")
+    written, landed = k1.transfer_from(k0, kf.R[2], kf.t[2])
+    assert written == landed and written > 0.9 * k0.count
+    k1.render()
+    placed, found = k1.place()
+    start = k1.state_host()
+    engine.disc_update(ctx, [k1], sg.params(iters=8))
+    k1.render()
+    torch.cuda.synchronize()
+    assert placed == found
+    dev = k1.state_host()
+    res = check_parity(k1, dev, start["inv_depth"], start["n"], None, oracle.OracleParams(iters=8),
+                       label="disc keyframe 1", disc=_disc_of(k1), init_flags=start["flags"])
+    assert_parity(res, label="disc keyframe 1")
+    ux, uy = k1.centres()
+    idm, ind = oracle.disc_render(oracle_keyframe(k1), oracle_state(dev["inv_depth"], dev["n"], dev["flags"]),
+                                  ux.astype(np.float64), uy.astype(np.float64), 10.0)
+    assert np.array_equal(k1.index_out.cpu().numpy(), ind)
+    assert (ind >= 0).mean() > 0.8
+
+
+def test_disc_render_batch_equals_one_by_one(ctx):
+    """The batched render (one pass over several keyframes, an empty one in
+    the middle, one without an index output) equals per-keyframe renders."""
+    sg, engine = _mods()
+    print("case disc render batch", flush=True)
+    dks = []
+    for i, (w, h) in enumerate([(320, 240), (200, 130), (320, 240), (160, 120)]):
+        kf, discs = _scene(w, h, 3, seed=80 + i)
+        if i == 2:
+            dks.append(engine.DiscKeyframe(ctx, kf.kf_image, kf.nbr_images, kf.R, kf.t, kf.K, 10.0,
+                                           np.zeros(0, np.float32), np.zeros(0, np.float32),
+                                           np.zeros(0, np.float32), np.zeros((0, 3), np.float32)))
+        else:
+            dks.append(engine.DiscKeyframe.from_scene(ctx, kf, discs))
+    ref = []
+    for d in dks:
+        d.render()
+        torch.cuda.synchronize()
+        ref.append((d.inv_depth_out.cpu().numpy().copy(), d.index_out.cpu().numpy().copy()))
+        d.inv_depth_out.fill_(7.0)
+        d.index_out.fill_(7)
+    items = sg.disc_array([d.item() for d in dks])
+    sg.sgn_disc_render_batch(ctx.handle, items, len(dks), [d.inv_depth_out.data_ptr() for d in dks],
+                             [d.index_out.data_ptr() if i != 1 else 0 for i, d in enumerate(dks)])
+    torch.cuda.synchronize()
+    for i, (d, (rd, ri)) in enumerate(zip(dks, ref)):
+        assert np.array_equal(d.inv_depth_out.cpu().numpy(), rd)
+        if i != 1:
+            assert np.array_equal(d.index_out.cpu().numpy(), ri)
+        else:
+            assert np.all(d.index_out.cpu().numpy() == 7)        # not written
+    assert np.all(ref[2][1] == -1)
