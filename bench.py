@@ -232,8 +232,8 @@ def disc_leg(ctx, kfs, storage, iters, steps, with_ablation):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(keyframes shard across GPUs with no exchange; see the design notes). "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(keyframes and streams would shard across GPUs with no exchange). "
               "Run with --gpus 1.", file=sys.stderr, flush=True)
         sys.exit(2)
     import numpy as np
