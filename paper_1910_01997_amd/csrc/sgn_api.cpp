@@ -623,30 +623,27 @@ sgn_status sgn_create(sgn_ctx** out, int32_t device, void* hip_stream) {
     sgn_ctx* c = new sgn_ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    // on a failure below, sgn_destroy releases whatever was created so far
+    auto give_up = [&](sgn_status st, const std::string& msg) {
+        sgn_destroy(c);
+        return fail(st, msg);
+    };
     hipDeviceProp_t p;
-    if (hipGetDeviceProperties(&p, device) != hipSuccess) { delete c; return hip_fail(hipErrorUnknown, "props"); }
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) return give_up(SGN_E_DEVICE, "device properties");
     c->cus = p.multiProcessorCount;
-    if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0) {
-        delete c;
-        return fail(SGN_E_UNSUPPORTED, std::string("built for gfx950, device is ") + p.gcnArchName);
-    }
+    if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0)
+        return give_up(SGN_E_UNSUPPORTED, std::string("built for gfx950, device is ") + p.gcnArchName);
     for (int i = 0; i < kRingSlots; ++i)
-        if (hipEventCreateWithFlags(&c->ring_ev[i], hipEventDisableTiming) != hipSuccess) {
-            delete c;
-            return fail(SGN_E_DEVICE, "event creation failed");
-        }
+        if (hipEventCreateWithFlags(&c->ring_ev[i], hipEventDisableTiming) != hipSuccess)
+            return give_up(SGN_E_DEVICE, "event creation failed");
     for (int k = 0; k < 2; ++k)
         for (int i = 0; i < kTimingRing; ++i)
-            if (hipEventCreate(&c->gn_ring[k][i]) != hipSuccess) {
-                delete c;
-                return fail(SGN_E_DEVICE, "event creation failed");
-            }
+            if (hipEventCreate(&c->gn_ring[k][i]) != hipSuccess)
+                return give_up(SGN_E_DEVICE, "event creation failed");
     c->gn_start = c->gn_ring[0][0];
     c->gn_end = c->gn_ring[1][0];
-    if (hipMalloc(&c->counters, kNumCounters * sizeof(uint32_t)) != hipSuccess) {
-        delete c;
-        return fail(SGN_E_DEVICE, "context allocation failed");
-    }
+    if (hipMalloc(&c->counters, kNumCounters * sizeof(uint32_t)) != hipSuccess)
+        return give_up(SGN_E_DEVICE, "context allocation failed");
     if (const char* g = std::getenv("SGN_NO_GRAPHS")) c->use_graphs = !(g[0] == '1');
     *out = c;
     return SGN_OK;
