@@ -500,11 +500,17 @@ sgn_status run_disc_batch(sgn_ctx* c, const sgn_disc_item* items, int n, const s
     KfDev* kfs = (KfDev*)(host + L.kf_off);
     FrameDev* frs = (FrameDev*)(host + L.fr_off);
     std::memset(host, 0, L.total);
+    // longest work first (most neighbour frames): the grid is dispatched in
+    // item order, so the short surfels fill the tail
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return items[x].kf.n_nbr > items[y].kf.n_nbr; });
     int frame_base = 0, surfel_base = 0;
-    for (int i = 0; i < n; ++i) {
-        const sgn_disc_item& it = items[i];
+    for (int oi = 0; oi < n; ++oi) {
+        const sgn_disc_item& it = items[order[oi]];
         const sgn_keyframe& kf = it.kf;
-        KfDev& D = kfs[i];
+        KfDev& D = kfs[oi];
         D.kf_img = kf.kf.data;
         D.inv_depth = it.surfels.inv_depth;
         D.nx = it.surfels.nx; D.ny = it.surfels.ny; D.nz = it.surfels.nz;
