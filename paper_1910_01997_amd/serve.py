@@ -265,12 +265,27 @@ class CameraStream:
         self.frames = extra_frames["images"]          # device tensor (E, H, W) storage dtype
         self.frame_R = extra_frames["R"]
         self.frame_t = extra_frames["t"]
-        self.resp_depth = None
-        self.resp_state = None
+        # the response buffers (pinned host memory, allocated once): a stream
+        # has one request in flight at a time, so a response stays valid
+        # until the stream's next request completes
+        self.resp_depth = torch.empty((self.dk.height, self.dk.width), dtype=torch.float32, pin_memory=True)
+        self.resp_state = torch.empty((8, self.dk.n_surfels), dtype=torch.float32, pin_memory=True)
 
     @property
     def response_bytes(self) -> int:
         return self.dk.width * self.dk.height * 4 + self.dk.n_surfels * 8 * 4
+
+
+def respond(cs: CameraStream, torch):
+    """Enqueue the copies of a stream's depth map and surfel state into its
+    response buffers on the current stream; returns (depth, state)."""
+    dk = cs.dk
+    cs.resp_depth.copy_(dk.inv_depth_out, non_blocking=True)
+    for k, src in enumerate((dk.state.inv_depth, dk.state.nx, dk.state.ny, dk.state.nz,
+                             dk.state.flags.view(torch.float32), dk.state.cost,
+                             dk.state.nvalid.view(torch.float32), dk.state.last_update.view(torch.float32))):
+        cs.resp_state[k].copy_(src, non_blocking=True)
+    return (cs.resp_depth, cs.resp_state)
 
 
 class HipExecutor(Executor):
@@ -278,7 +293,7 @@ class HipExecutor(Executor):
     its own torch stream (default priority)."""
 
     def __init__(self, streams: List[CameraStream], lanes: int = 2, iters: int = 15,
-                 plan=None, pinned_pool: bool = True):
+                 plan=None):
         import torch
 
         from . import surfgn as sg
@@ -293,7 +308,6 @@ class HipExecutor(Executor):
         self.small_plan = sg.plan(2, 2, 1, 0, 0, 1, groups=1)
         self.single_plan = sg.plan(2, 2, 0, 0, 0, 0, groups=1)
         self.small_batch_surfels = 200_000
-        self.pinned_pool = pinned_pool
 
     def request_bytes(self, req: Request) -> int:
         return self.streams[req.stream].response_bytes
@@ -321,13 +335,7 @@ class HipExecutor(Executor):
                 cs.first = False
                 items.append(it)
                 outs.append(view)
-            arr = self.sg.batch_array(items)
-            plan = self.plan
-            if plan is None:
-                # a small batch cannot fill the device with four groups per
-                # work item: use one group per wavefront there
-                total = sum(self.streams[r.stream].dk.n_surfels for r in batch)
-                plan = self.small_plan if total < self.small_batch_surfels else None
+            arr = None
             ctx = self.ctxs[lane].handle
             if len(items) == 1:
                 # a lone request: the single-keyframe calls launch directly and
@@ -339,20 +347,16 @@ class HipExecutor(Executor):
                 self.sg.sgn_optimize_keyframe(ctx, view.c, dk.state.c, self.params, self.single_plan)
                 self.sg.sgn_render_inverse_depth(ctx, view.c, dk.state.c, dk.inv_depth_out.data_ptr())
             else:
+                plan = self.plan
+                if plan is None:
+                    # a small batch cannot fill the device with four groups per
+                    # work item: use one group per wavefront there
+                    total = sum(self.streams[r.stream].dk.n_surfels for r in batch)
+                    plan = self.small_plan if total < self.small_batch_surfels else None
+                arr = self.sg.batch_array(items)
                 self.sg.sgn_optimize_batch(ctx, arr, len(items), self.params, plan)
-            # responses: depth map and surfels copied to host memory
-            results = []
-            for r in batch:
-                dk = self.streams[r.stream].dk
-                depth = torch.empty(dk.inv_depth_out.shape, dtype=torch.float32, pin_memory=self.pinned_pool)
-                depth.copy_(dk.inv_depth_out, non_blocking=True)
-                st = torch.empty((8, dk.n_surfels), dtype=torch.float32, pin_memory=self.pinned_pool)
-                for k, src in enumerate((dk.state.inv_depth, dk.state.nx, dk.state.ny, dk.state.nz,
-                                         dk.state.flags.view(torch.float32), dk.state.cost,
-                                         dk.state.nvalid.view(torch.float32),
-                                         dk.state.last_update.view(torch.float32))):
-                    st[k].copy_(src, non_blocking=True)
-                results.append((depth, st))
+            # responses: depth map and surfels copied into the stream's host buffers
+            results = [respond(self.streams[r.stream], torch) for r in batch]
             ev = torch.cuda.Event()
             ev.record(ts)
         return (ev, batch, results, outs, arr)
@@ -400,17 +404,10 @@ class PlainExecutor(HipExecutor):
             self.sg.sgn_optimize_keyframe(ctx.handle, view.c, dk.state.c, self.params,
                                           self.plain_plan)
             self.sg.sgn_render_inverse_depth(ctx.handle, view.c, dk.state.c, dk.inv_depth_out.data_ptr())
-            depth = torch.empty(dk.inv_depth_out.shape, dtype=torch.float32, pin_memory=True)
-            depth.copy_(dk.inv_depth_out, non_blocking=True)
-            st = torch.empty((8, dk.n_surfels), dtype=torch.float32, pin_memory=True)
-            for k, src in enumerate((dk.state.inv_depth, dk.state.nx, dk.state.ny, dk.state.nz,
-                                     dk.state.flags.view(torch.float32), dk.state.cost,
-                                     dk.state.nvalid.view(torch.float32),
-                                     dk.state.last_update.view(torch.float32))):
-                st[k].copy_(src, non_blocking=True)
+            result = respond(cs, torch)
             ev = torch.cuda.Event()
             ev.record(ts)
-        return (ev, batch, [(depth, st)], [view], None)
+        return (ev, batch, [result], [view], None)
 
 
 def make_streams(ctx, specs, extra: int = 4, storage: str = "f16", device="cuda"):
