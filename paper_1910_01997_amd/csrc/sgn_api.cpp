@@ -506,7 +506,7 @@ sgn_status run_disc_batch(sgn_ctx* c, const sgn_disc_item* items, int n, const s
     for (int i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
                      [&](int x, int y) { return items[x].kf.n_nbr > items[y].kf.n_nbr; });
-    int frame_base = 0, surfel_base = 0;
+    int frame_base = 0, surfel_base = 0, item_base = 0;
     for (int oi = 0; oi < n; ++oi) {
         const sgn_disc_item& it = items[order[oi]];
         const sgn_keyframe& kf = it.kf;
@@ -524,9 +524,10 @@ sgn_status run_disc_batch(sgn_ctx* c, const sgn_disc_item* items, int n, const s
         D.n_nbr = kf.n_nbr;
         D.nbr_pitch_b = kf.n_nbr > 0 ? kf.nbr[0].pitch * (int32_t)dtype_size(kf.kf.dtype) : 0;
         D.frame_base = frame_base;
-        D.item_base = surfel_base;
-        D.n_items = it.count;
+        D.item_base = item_base;
+        D.n_items = (it.count + disc_surfels_per_wave(dtype) - 1) / disc_surfels_per_wave(dtype);
         D.surfel_base = surfel_base;
+        D.disc_count = it.count;
         D.fx = (float)kf.K.fx; D.fy = (float)kf.K.fy; D.cx = (float)kf.K.cx; D.cy = (float)kf.K.cy;
         D.fx_d = kf.K.fx; D.fy_d = kf.K.fy; D.cx_d = kf.K.cx; D.cy_d = kf.K.cy;
         D.kf_scale = kf.kf.scale;
@@ -547,12 +548,13 @@ sgn_status run_disc_batch(sgn_ctx* c, const sgn_disc_item* items, int n, const s
         }
         frame_base += kf.n_nbr;
         surfel_base += it.count;
+        item_base += D.n_items;
     }
     H->kfs = (KfDev*)(dev + L.kf_off);
     H->frames = (FrameDev*)(dev + L.fr_off);
     H->n_kf = n;
     H->n_frames = total_frames;
-    H->total_items = surfel_base;
+    H->total_items = item_base;
     H->total_surfels = surfel_base;
     H->iters = prm->iters;
     H->huber_k = prm->huber_k;
@@ -570,10 +572,10 @@ sgn_status run_disc_batch(sgn_ctx* c, const sgn_disc_item* items, int n, const s
     const int frames_cap = (int)((c->table_cap - L.fr_off) / sizeof(FrameDev));
     hipError_t e = launch_setup(dH, c->counters, frames_cap, c->stream);
     if (e != hipSuccess) return hip_fail(e, "setup launch");
-    if (surfel_base > 0) {
+    if (item_base > 0) {
         next_timing_slot(c);
         SGN_HIP(hipEventRecord(c->gn_start, c->stream));
-        e = launch_disc_gn(dtype, dH, surfel_base, c->stream);
+        e = launch_disc_gn(dtype, dH, item_base, c->stream);
         if (e != hipSuccess) return hip_fail(e, "disc Gauss-Newton launch");
         SGN_HIP(hipEventRecord(c->gn_end, c->stream));
         c->gn_timed = true;

@@ -41,7 +41,7 @@ struct KfDev {
     const float* disc_ux;
     const float* disc_uy;
     float disc_r;
-    int32_t pad2;
+    int32_t disc_count;           // surfels of the keyframe (an item is a run of them)
 };
 
 // Per-neighbour-frame descriptor.  R and t are the caller's pose in double;
@@ -151,9 +151,14 @@ hipError_t launch_regrid(const RegridArgs& a, hipStream_t s);
 
 // Disc surfels (Eq. 4).
 constexpr float kDiscMaxRadius = 12.f;
-// Gauss-Newton over the disc surfels of a batch: one wavefront per surfel,
-// items are surfels (KfDev::item_base = surfel_base, n_items = count).
-hipError_t launch_disc_gn(int dtype, const BatchHeader* hdr, int total_surfels, hipStream_t s);
+// Disc surfels per wavefront of the Gauss-Newton kernel, by image type
+// (0 f32, 1 f16, 2 u8): two (32 lanes each) where a pixel's LDS slot packs
+// into one word, one for f32 images.
+constexpr int disc_surfels_per_wave(int dtype) { return dtype == 0 ? 1 : 2; }
+// Gauss-Newton over the disc surfels of a batch: one wavefront per work item
+// of disc_surfels_per_wave(dtype) surfels of one keyframe (KfDev::n_items =
+// ceil(disc_count / that), item_base their prefix).
+hipError_t launch_disc_gn(int dtype, const BatchHeader* hdr, int total_items, hipStream_t s);
 // Depth-buffered render of the discs of several keyframes: one table entry
 // per keyframe (device memory); the scratch holds one 64-bit depth key and
 // one index per pixel of every keyframe, keyframe after keyframe.

@@ -100,24 +100,21 @@ __device__ __forceinline__ int row_sum(int x) {
     return x;
 }
 
-// Sum over a surfel's lanes: 16 lanes (one DPP row) or the whole wavefront.
+// Sum over a surfel's lanes: 16 lanes (one DPP row), 32 (two rows) or the
+// whole wavefront.
 template <int LANES>
 __device__ __forceinline__ float group_sum(float x) {
 #pragma clang fp contract(off)
     x = row_sum(x);
-    if constexpr (LANES == 64) {
-        x += __shfl_xor(x, 16);
-        x += __shfl_xor(x, 32);
-    }
+    if constexpr (LANES >= 32) x += __shfl_xor(x, 16);
+    if constexpr (LANES == 64) x += __shfl_xor(x, 32);
     return x;
 }
 template <int LANES>
 __device__ __forceinline__ int group_sum(int x) {
     x = row_sum(x);
-    if constexpr (LANES == 64) {
-        x += __shfl_xor(x, 16);
-        x += __shfl_xor(x, 32);
-    }
+    if constexpr (LANES >= 32) x += __shfl_xor(x, 16);
+    if constexpr (LANES == 64) x += __shfl_xor(x, 32);
     return x;
 }
 
@@ -137,10 +134,8 @@ __device__ __forceinline__ float pair_sum(float ev, float od, bool odd) {
     x += dpp_f<0x4E>(x);                  // quad_perm [2,3,0,1]
     x += dpp_f<0x124>(x);                 // row_ror:4
     x += dpp_f<0x128>(x);                 // row_ror:8
-    if constexpr (LANES == 64) {
-        x += __shfl_xor(x, 16);
-        x += __shfl_xor(x, 32);
-    }
+    if constexpr (LANES >= 32) x += __shfl_xor(x, 16);
+    if constexpr (LANES == 64) x += __shfl_xor(x, 32);
     return x;
 }
 
@@ -1481,8 +1476,8 @@ hipError_t launch_gn(const GnVariant& v, const BatchHeader* hdr, uint32_t* count
 // pixels and covers the pixels u (inside the image) with |u - u_s| < r, r
 // the same for every surfel of a keyframe (0 < r <= kDiscMaxRadius).
 // Membership is decided as dx^2 + dy^2 < r^2 in double (dx = x - ux is
-// exact there).  A disc's pixels are numbered row by row; a wavefront holds
-// one surfel and lane l takes pixels l, l + 64, ... (at most kDiscPPL).
+// exact there).  A disc's pixels are numbered row by row; a surfel held by
+// LANES lanes gives lane l pixels l, l + LANES, ... (at most 512 / LANES).
 
 constexpr int kDiscMaxRows = 2 * (int)kDiscMaxRadius + 2;
 constexpr int kDiscPPL = 8;        // 512 pixels > pi (12 + sqrt(2)/2)^2, the largest disc
@@ -1494,25 +1489,56 @@ struct DiscRows {
     int y0, nrows, total;
 };
 
-// The rows of one disc (clipped to the image): lanes below the row count
-// find their row's run of pixels (a disc meets a row in one run), lane 0
+// A disc pixel's slot in LDS: its offset from the anchor pixel as two int8
+// (|offset| <= 12) in the low half-word and, for f16 and u8 images, the
+// keyframe value's stored bits in the high half-word (f32 values go to a
+// float array of their own).
+template <typename T> struct DiscSlot {
+    static constexpr bool packed = true;
+};
+template <> struct DiscSlot<float> {
+    static constexpr bool packed = false;
+};
+__device__ __forceinline__ uint32_t slot_bits(_Float16 v) { return __builtin_bit_cast(uint16_t, v); }
+__device__ __forceinline__ uint32_t slot_bits(uint8_t v) { return v; }
+__device__ __forceinline__ uint32_t slot_bits(float) { return 0u; }
+template <typename T>
+__device__ __forceinline__ float slot_value(uint32_t pk);
+template <>
+__device__ __forceinline__ float slot_value<_Float16>(uint32_t pk) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(pk >> 16));
+}
+template <>
+__device__ __forceinline__ float slot_value<uint8_t>(uint32_t pk) { return (float)(pk >> 16); }
+template <>
+__device__ __forceinline__ float slot_value<float>(uint32_t) { return 0.f; }
+
+// The rows of one disc (clipped to the image): the surfel's lanes below the
+// row count (hl is the lane's index among the surfel's LANES lanes) find
+// their row's run of pixels (a disc meets a row in one run), its lane 0
 // forms the running counts.  row_x0[i] is the first column of row y0 + i and
 // row_start[i] the number of disc pixels before it.  A non-finite centre
-// gives an empty disc.  The caller synchronises the wavefront before.
-__device__ DiscRows disc_rows(float ux, float uy, float radius, int W, int H, int lane,
-                              int* row_x0, int* row_start) {
+// gives an empty disc.  Every lane passes the same synchronisation points;
+// the caller synchronises the wavefront before.
+template <int LANES>
+__device__ DiscRows disc_rows(float ux, float uy, float radius, int W, int H, int hl, int* row_x0,
+                              int* row_start) {
 #pragma clang fp contract(off)
     DiscRows d{0, 0, 0};
     const double cx = (double)ux, cy = (double)uy, r = (double)radius, r2 = r * r;
-    if (!isfinite(cx) || !isfinite(cy)) return d;
     const double xlo = fmax(0.0, ceil(cx - r)), xhi = fmin((double)(W - 1), floor(cx + r));
     const double ylo = fmax(0.0, ceil(cy - r)), yhi = fmin((double)(H - 1), floor(cy + r));
-    if (!(xlo <= xhi) || !(ylo <= yhi) || yhi - ylo >= (double)(kDiscMaxRows - 1)) return d;
-    const int x0 = (int)xlo, x1 = (int)xhi;
-    d.y0 = (int)ylo;
-    d.nrows = (int)yhi - d.y0 + 1;
-    if (lane < d.nrows) {
-        const double dy = (double)(d.y0 + lane) - cy;
+    const bool ok = isfinite(cx) && isfinite(cy) && xlo <= xhi && ylo <= yhi &&
+                    yhi - ylo < (double)(kDiscMaxRows - 1);
+    int x0 = 0, x1 = -1;
+    if (ok) {
+        x0 = (int)xlo;
+        x1 = (int)xhi;
+        d.y0 = (int)ylo;
+        d.nrows = (int)yhi - d.y0 + 1;
+    }
+    if (hl < d.nrows) {
+        const double dy = (double)(d.y0 + hl) - cy;
         int first = x0, cnt = 0;
         for (int x = x0; x <= x1; ++x) {
             const double dx = (double)x - cx;
@@ -1521,11 +1547,11 @@ __device__ DiscRows disc_rows(float ux, float uy, float radius, int W, int H, in
                 ++cnt;
             }
         }
-        row_x0[lane] = first;
-        row_start[lane + 1] = cnt;
+        row_x0[hl] = first;
+        row_start[hl + 1] = cnt;
     }
     wave_sync();
-    if (lane == 0) {
+    if (hl == 0) {
         int acc = 0;
         row_start[0] = 0;
         for (int i = 0; i < d.nrows; ++i) {
@@ -1547,37 +1573,47 @@ __device__ __forceinline__ void disc_pixel(const DiscRows& d, const int* row_x0,
     y = d.y0 + i;
 }
 
-// Gauss-Newton over disc surfels: one wavefront per surfel (the batch's
-// items are its surfels), the same per-pixel terms, frame loop, reduction
-// and owner-lane step as the tile kernel, over the disc's pixels.  The warp
-// constants are anchored at the pixel nearest the centre.
-// Five wavefronts per SIMD: the register budget (96 VGPRs) the slot loop
-// fits without spilling; the default allocation takes 100 and four.
-template <typename T>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void disc_gn_kernel(const BatchHeader* __restrict__ hdr_,
-                                                                int total) {
+// Gauss-Newton over disc surfels: SPW surfels per wavefront, LANES = 64 /
+// SPW lanes each (the batch's items are runs of SPW surfels of one keyframe),
+// with the same per-pixel terms, frame loop, reduction and owner-lane step as
+// the tile kernel, over the discs' pixels.  Each surfel's warp constants are
+// anchored at the pixel nearest its centre.  With two surfels per wavefront
+// the owner step (one lane per surfel) serves two surfels at once and the
+// reductions span 32 lanes.  Six wavefronts per SIMD (80 VGPRs, and the LDS
+// of six workgroups per CU): the few values that spill are read by the owner
+// step once per iteration or by its double-precision fallback only.
+template <typename T, int SPW>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) void disc_gn_kernel(
+    const BatchHeader* __restrict__ hdr_, int total) {
+    constexpr int LANES = kWaveSize / SPW;        // lanes per surfel
+    constexpr int PPL = kDiscPPL * SPW;           // pixel slots per lane
+    constexpr int WPB = kBlockThreads / kWaveSize;
+    constexpr bool packed = DiscSlot<T>::packed;
+    static_assert(kDiscMaxRows <= LANES, "a disc row per lane");
     const cptr<BatchHeader> hdr = (cptr<BatchHeader>)hdr_;
     const int lane = threadIdx.x & (kWaveSize - 1);
     const int wave = threadIdx.x >> 6;
-    const int item = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlockThreads / kWaveSize) + wave);
+    const int h = lane / LANES, hl = lane % LANES;       // surfel of the wave, lane within it
+    const int item = __builtin_amdgcn_readfirstlane((int)blockIdx.x * WPB + wave);
     if (item >= total) return;
-    __shared__ float4 s_pairs[kBlockThreads / kWaveSize][kMaxNbr * kPairWords / 4];
-    __shared__ float4 s_state[kBlockThreads / kWaveSize][ST_WORDS / 4];
-    __shared__ float4 s_sums[kBlockThreads / kWaveSize][SM_WORDS / 4];
-    __shared__ int s_rows[kBlockThreads / kWaveSize][kDiscRowWords];
-    // each lane's pixels: offsets from the anchor (two int16) and keyframe values
-    __shared__ int s_off[kBlockThreads / kWaveSize][kDiscPPL][kWaveSize];
-    __shared__ float s_ikf[kBlockThreads / kWaveSize][kDiscPPL][kWaveSize];
-    float* const pairs = (float*)s_pairs[wave];
-    float* const lst = (float*)s_state[wave];
-    float* const lsm = (float*)s_sums[wave];
-    int* const row_x0 = s_rows[wave];
-    int* const row_start = s_rows[wave] + kDiscMaxRows;
+    __shared__ float4 s_pairs[WPB][SPW][kMaxNbr * kPairWords / 4];
+    __shared__ float4 s_state[WPB][SPW][ST_WORDS / 4];
+    __shared__ float4 s_sums[WPB][SPW][SM_WORDS / 4];
+    __shared__ int s_rows[WPB][SPW][kDiscRowWords];
+    // each lane's pixels: offsets from the anchor and keyframe values
+    __shared__ uint32_t s_pix[WPB][PPL][kWaveSize];
+    __shared__ float s_val[WPB][packed ? 1 : PPL][kWaveSize];
+    float* const pairs = (float*)s_pairs[wave][h];
+    float* const lst = (float*)s_state[wave][h];
+    float* const lsm = (float*)s_sums[wave][h];
+    int* const row_x0 = s_rows[wave][h];
+    int* const row_start = s_rows[wave][h] + kDiscMaxRows;
 
     const cptr<KfDev> kfs = (cptr<KfDev>)hdr->kfs;
     const int kidx = find_kf(kfs, hdr->n_kf, item, 0);
     const cptr<KfDev> Kd = kfs + kidx;
-    const int sidx = item - Kd->item_base;
+    const int sidx = (item - Kd->item_base) * SPW + h;
+    const bool have = sidx < Kd->disc_count;         // an odd count leaves the last half empty
     const int iters = hdr->iters;
     const float hk = hdr->huber_k;
     const float kap2 = hdr->kappa_fp64 * hdr->kappa_fp64;
@@ -1591,52 +1627,60 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
     const unsigned img_bytes = pitch_b * (unsigned)H;
     const unsigned wm1 = (unsigned)(W - 1), hm1 = (unsigned)(H - 1);
     const float fxk = Kd->fx, fyk = Kd->fy, cxk = Kd->cx, cyk = Kd->cy;
-    const float ux = ((gptr<float>)Kd->disc_ux)[sidx];
-    const float uy = ((gptr<float>)Kd->disc_uy)[sidx];
+    const float ux = have ? ((gptr<float>)Kd->disc_ux)[sidx] : __builtin_nanf("");
+    const float uy = have ? ((gptr<float>)Kd->disc_uy)[sidx] : __builtin_nanf("");
 
     wave_sync();
-    const DiscRows d = disc_rows(ux, uy, Kd->disc_r, W, H, lane, row_x0, row_start);
-    const int nslots = (d.total + kWaveSize - 1) / kWaveSize;
+    const DiscRows d = disc_rows<LANES>(ux, uy, Kd->disc_r, W, H, hl, row_x0, row_start);
+    // slot count: the larger of the wavefront's surfels, so the loop is uniform
+    int nslots = (d.total + LANES - 1) / LANES;
+    if constexpr (SPW == 2) nslots = max(nslots, __shfl_xor(nslots, 32));
+    nslots = __builtin_amdgcn_readfirstlane(nslots);
     // anchor pixel (nearest the centre; any fixed point works for the local
     // warp coordinates)
     const int ax = (int)rint(fmin(fmax((double)ux, -1e6), 1e6));
     const int ay = (int)rint(fmin(fmax((double)uy, -1e6), 1e6));
-    stage_pair_words(hdr->frames + Kd->frame_base, nf, lane, (double)ax, (double)ay, pairs);
+    stage_pair_words(hdr->frames + Kd->frame_base, nf, hl, (double)ax, (double)ay, pairs);
     const uint64_t fr_bits = (uint64_t)(const void*)(hdr->frames + Kd->frame_base);
     const uint32_t fr_lo = __builtin_amdgcn_readfirstlane((uint32_t)fr_bits);
     const uint32_t fr_hi = __builtin_amdgcn_readfirstlane((uint32_t)(fr_bits >> 32));
     const cptr<FrameDev> fr = (cptr<FrameDev>)(((uint64_t)fr_hi << 32) | fr_lo);
 
-    // this lane's pixels k = lane + 64 j: offsets from the anchor (|.| <= 13)
-    // and keyframe values, kept in LDS so that the slot loop holds one pixel's
-    // terms in registers at a time
+    // this lane's pixels k = hl + LANES j, kept in LDS so that the slot loop
+    // holds one pixel's terms in registers at a time
     const gptr<T> kimg = (gptr<T>)Kd->kf_img;
+    const float kf_scale = Kd->kf_scale;
     for (int j = 0; j < nslots; ++j) {
-        const int k = lane + kWaveSize * j;
-        int off = 0;
+        const int k = hl + LANES * j;
+        uint32_t pk = 0u;
         float v = 0.f;
         if (k < d.total) {
             int x, y;
             disc_pixel(d, row_x0, row_start, k, x, y);
-            off = ((x - ax) & 0xffff) | ((y - ay) << 16);
-            v = ldg<T>(kimg + ((unsigned)y * (unsigned)Kd->kf_pitch + (unsigned)x)) * Kd->kf_scale;
+            const T raw = kimg[(unsigned)y * (unsigned)Kd->kf_pitch + (unsigned)x];
+            pk = ((uint32_t)(x - ax) & 0xffu) | (((uint32_t)(y - ay) & 0xffu) << 8) | (slot_bits(raw) << 16);
+            v = (float)raw * kf_scale;
         }
-        s_off[wave][j][lane] = off;
-        s_ikf[wave][j][lane] = v;
+        s_pix[wave][j][lane] = pk;
+        if constexpr (!packed) s_val[wave][j][lane] = v;
     }
     // r_u - r_s = (anchor offset + (anchor - u_s)) / f
     const float fox = (float)((double)ax - (double)ux), foy = (float)((double)ay - (double)uy);
     const float ifx = 1.f / fxk, ify = 1.f / fyk;
 
-    // owner (lane 0): the surfel's state
-    const bool owner = lane == 0;
+    // owner (lane 0 of each surfel): the surfel's state
+    const bool owner = hl == 0;
     const float rsx = (ux - cxk) / fxk, rsy = (uy - cyk) / fyk;
-    float id = ((gptr<float>)Kd->inv_depth)[sidx];
-    float nx = ((gptr<float>)Kd->nx)[sidx];
-    float ny = ((gptr<float>)Kd->ny)[sidx];
-    float nz = ((gptr<float>)Kd->nz)[sidx];
-    uint32_t flags = ((gptr<uint32_t>)Kd->flags)[sidx] & ~F_GN_BITS;
-    bool alive = true, updated = false;
+    float id = 0.f, nx = 0.f, ny = 0.f, nz = -1.f;
+    uint32_t flags = 0u;
+    if (have) {
+        id = ((gptr<float>)Kd->inv_depth)[sidx];
+        nx = ((gptr<float>)Kd->nx)[sidx];
+        ny = ((gptr<float>)Kd->ny)[sidx];
+        nz = ((gptr<float>)Kd->nz)[sidx];
+        flags = ((gptr<uint32_t>)Kd->flags)[sidx] & ~F_GN_BITS;
+    }
+    bool alive = have, updated = false;
     float cost_out = 0.f;
     int nv_out = 0;
     float lam = lm0;
@@ -1674,57 +1718,55 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
             float ph[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             float pnv = 0.f, pcs = 0.f;
             for (int j = 0; j < nslots; ++j) {
+                const uint32_t pk = s_pix[wave][j][lane];
+                const float bdx = (float)(int8_t)(pk & 0xffu), bdy = (float)(int8_t)((pk >> 8) & 0xffu);
+                const float ikf = packed ? slot_value<T>(pk) * kf_scale : s_val[wave][packed ? 0 : j][lane];
+                const bool pv = hl + LANES * j < d.total;
+                const float drx = (bdx + fox) * ifx, dry = (bdy + foy) * ify;
+                const float sigma = (snx * drx + sny * dry) * inv_c;
+                const float idu = fmaf(sid, sigma, sid);
+                const float dx3 = fmaf(-sigma, srsx, drx);
+                const float dy3 = fmaf(-sigma, srsy, dry);
+                const float dz3 = -sigma;
+                const float kk = sid * inv_c;
+                const float g0 = 1.f + sigma;
+                const float g1 = depth_only ? 0.f : kk * (sb1x * dx3 + sb1y * dy3 + sb1z * dz3);
+                const float g2 = depth_only ? 0.f : kk * (sb2x * dx3 + sb2y * dy3 + sb2z * dz3);
+                const bool pix_ok = salive && pv && (idu > 0.f);
+                float A = 0.f, B = 0.f, cst = 0.f;
+                int nvl = 0;
+                if (last || lm)
+                    frame_loop<T, true>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes, wm1, hm1,
+                                        ikf, hk, img_scale, A, B, cst, nvl);
+                else
+                    frame_loop<T, false>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes, wm1, hm1,
+                                         ikf, hk, img_scale, A, B, cst, nvl);
                 {
-                    const int off = s_off[wave][j][lane];
-                    const float bdx = (float)(int16_t)(off & 0xffff), bdy = (float)(off >> 16);
-                    const float ikf = s_ikf[wave][j][lane];
-                    const bool pv = lane + kWaveSize * j < d.total;
-                    const float drx = (bdx + fox) * ifx, dry = (bdy + foy) * ify;
-                    const float sigma = (snx * drx + sny * dry) * inv_c;
-                    const float idu = fmaf(sid, sigma, sid);
-                    const float dx3 = fmaf(-sigma, srsx, drx);
-                    const float dy3 = fmaf(-sigma, srsy, dry);
-                    const float dz3 = -sigma;
-                    const float kk = sid * inv_c;
-                    const float g0 = 1.f + sigma;
-                    const float g1 = depth_only ? 0.f : kk * (sb1x * dx3 + sb1y * dy3 + sb1z * dz3);
-                    const float g2 = depth_only ? 0.f : kk * (sb2x * dx3 + sb2y * dy3 + sb2z * dz3);
-                    const bool pix_ok = salive && pv && (idu > 0.f);
-                    float A = 0.f, B = 0.f, cst = 0.f;
-                    int nvl = 0;
-                    if (last || lm)
-                        frame_loop<T, true>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes,
-                                            wm1, hm1, ikf, hk, img_scale, A, B, cst, nvl);
-                    else
-                        frame_loop<T, false>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b,
-                                             img_bytes, wm1, hm1, ikf, hk, img_scale, A, B, cst, nvl);
-                    {
-#pragma clang fp contract(off)
-                        const float ag0 = A * g0, ag1 = A * g1, ag2 = A * g2;
-                        ph[0] += ag0 * g0; ph[1] += ag0 * g1; ph[2] += ag0 * g2;
-                        ph[3] += ag1 * g1; ph[4] += ag1 * g2; ph[5] += ag2 * g2;
-                        ph[6] += B * g0; ph[7] += B * g1; ph[8] += B * g2;
-                        pnv += (float)nvl;
-                        pcs += cst;
-                    }
+                    const float ag0 = A * g0, ag1 = A * g1, ag2 = A * g2;
+                    ph[0] = fmaf(ag0, g0, ph[0]); ph[1] = fmaf(ag0, g1, ph[1]);
+                    ph[2] = fmaf(ag0, g2, ph[2]); ph[3] = fmaf(ag1, g1, ph[3]);
+                    ph[4] = fmaf(ag1, g2, ph[4]); ph[5] = fmaf(ag2, g2, ph[5]);
+                    ph[6] = fmaf(B, g0, ph[6]); ph[7] = fmaf(B, g1, ph[7]); ph[8] = fmaf(B, g2, ph[8]);
+                    pnv += (float)nvl;
+                    pcs += cst;
                 }
             }
             float s0, s1, s2, s3, s4;
             {
 #pragma clang fp contract(off)
-                const bool odd = (lane & 1) != 0;
-                s0 = pair_sum<kWaveSize>(ph[0], ph[1], odd);
-                s1 = pair_sum<kWaveSize>(ph[2], ph[3], odd);
-                s2 = pair_sum<kWaveSize>(ph[4], ph[5], odd);
-                s3 = pair_sum<kWaveSize>(ph[6], ph[7], odd);
-                s4 = pair_sum<kWaveSize>(ph[8], pnv, odd);
+                const bool odd = (hl & 1) != 0;
+                s0 = pair_sum<LANES>(ph[0], ph[1], odd);
+                s1 = pair_sum<LANES>(ph[2], ph[3], odd);
+                s2 = pair_sum<LANES>(ph[4], ph[5], odd);
+                s3 = pair_sum<LANES>(ph[6], ph[7], odd);
+                s4 = pair_sum<LANES>(ph[8], pnv, odd);
             }
             float cs = 0.f;
-            if (last || lm) cs = group_sum<kWaveSize>(pcs);
-            if (lane < 2) {
-                float* o = lsm + lane;
+            if (last || lm) cs = group_sum<LANES>(pcs);
+            if (hl < 2) {
+                float* o = lsm + hl;
                 o[0] = s0; o[2] = s1; o[4] = s2; o[6] = s3; o[8] = s4;
-                if (lane == 0) o[SM_COST] = cs;
+                if (hl == 0) o[SM_COST] = cs;
             }
         }
         wave_sync();
@@ -1760,18 +1802,19 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
                 float cst2 = 0.f;
                 int nv2l = 0;
                 for (int j = 0; j < nslots; ++j) {
-                    const int off = s_off[wave][j][lane];
-                    const float bdx = (float)(int16_t)(off & 0xffff), bdy = (float)(off >> 16);
-                    const bool pv = lane + kWaveSize * j < d.total;
+                    const uint32_t pk = s_pix[wave][j][lane];
+                    const float bdx = (float)(int8_t)(pk & 0xffu), bdy = (float)(int8_t)((pk >> 8) & 0xffu);
+                    const float ikf = packed ? slot_value<T>(pk) * kf_scale : s_val[wave][packed ? 0 : j][lane];
+                    const bool pv = hl + LANES * j < d.total;
                     const float drx = (bdx + fox) * ifx, dry = (bdy + foy) * ify;
                     const float sig = (sa.y * drx + sa.z * dry) * inv_c;
                     const float idu_c = fmaf(sa.x, sig, sa.x);
                     frame_cost<T>(pairs, fr, nf, bdx, bdy, idu_c, calive && pv && (idu_c > 0.f), pitch_b,
-                                  img_bytes, wm1, hm1, s_ikf[wave][j][lane], hk, img_scale, cst2, nv2l);
+                                  img_bytes, wm1, hm1, ikf, hk, img_scale, cst2, nv2l);
                 }
-                const float c2 = group_sum<kWaveSize>(cst2);
-                const int n2 = group_sum<kWaveSize>(nv2l);
-                if (lane == 0) {
+                const float c2 = group_sum<LANES>(cst2);
+                const int n2 = group_sum<LANES>(nv2l);
+                if (hl == 0) {
                     lsm[SM_COST] = c2;
                     lsm[SM_NV] = __int_as_float(n2);
                 }
@@ -1786,7 +1829,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
             updated = true;
         }
     }
-    if (owner) {
+    if (owner && have) {
         ((gmut<float>)Kd->inv_depth)[sidx] = id;
         ((gmut<float>)Kd->nx)[sidx] = nx;
         ((gmut<float>)Kd->ny)[sidx] = ny;
@@ -1855,7 +1898,8 @@ __global__ __launch_bounds__(kBlockThreads) void disc_scatter_kernel(const DiscR
     const double ps0 = rs0 / ids, ps1 = rs1 / ids, ps2 = 1.0 / ids;
     const double den = ps0 * n0 + ps1 * n1 + ps2 * n2;
     wave_sync();
-    const DiscRows d = disc_rows(a.ux[s], a.uy[s], a.radius, a.width, a.height, lane, row_x0, row_start);
+    const DiscRows d = disc_rows<kWaveSize>(a.ux[s], a.uy[s], a.radius, a.width, a.height, lane, row_x0,
+                                            row_start);
     unsigned long long* const kk = key + a.pixel_base;
     int32_t* const ii = idx + a.pixel_base;
     for (int k = lane; k < d.total; k += kWaveSize) {
@@ -2131,13 +2175,16 @@ hipError_t launch_disc_transfer(const DiscTransferArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_disc_gn(int dtype, const BatchHeader* hdr, int total_surfels, hipStream_t s) {
-    if (total_surfels <= 0) return hipSuccess;
+hipError_t launch_disc_gn(int dtype, const BatchHeader* hdr, int total_items, hipStream_t s) {
+    if (total_items <= 0) return hipSuccess;
     const int waves = kBlockThreads / kWaveSize;
-    const dim3 grid((total_surfels + waves - 1) / waves);
-    if (dtype == 0) disc_gn_kernel<float><<<grid, kBlockThreads, 0, s>>>(hdr, total_surfels);
-    else if (dtype == 1) disc_gn_kernel<_Float16><<<grid, kBlockThreads, 0, s>>>(hdr, total_surfels);
-    else disc_gn_kernel<uint8_t><<<grid, kBlockThreads, 0, s>>>(hdr, total_surfels);
+    const dim3 grid((total_items + waves - 1) / waves);
+    if (dtype == 0)
+        disc_gn_kernel<float, disc_surfels_per_wave(0)><<<grid, kBlockThreads, 0, s>>>(hdr, total_items);
+    else if (dtype == 1)
+        disc_gn_kernel<_Float16, disc_surfels_per_wave(1)><<<grid, kBlockThreads, 0, s>>>(hdr, total_items);
+    else
+        disc_gn_kernel<uint8_t, disc_surfels_per_wave(2)><<<grid, kBlockThreads, 0, s>>>(hdr, total_items);
     return hipGetLastError();
 }
 
