@@ -141,15 +141,19 @@ typedef struct {
  * by the caller; all-zero means "library default"). */
 typedef struct {
     int32_t tiles_x, tiles_y;   /* surfels per wavefront as a tiles_x x tiles_y block
-                                   (S = 4: 4x1, 2x2 or 1x4; S = 8 and 16: 1x1; an
-                                   S = 16 surfel gives each lane four pixels) */
+                                   (S = 4: 4x1, 2x2 or 1x4, one pixel per lane; 4x2 or
+                                   2x4, two pixels per lane; 4x4, four pixels per lane;
+                                   S = 8 and 16: 1x1, an S = 16 surfel giving each lane
+                                   four pixels).  Plans with the same pixels per lane
+                                   give bitwise-equal results */
     int32_t persistent;         /* 1: persistent grid pulling work items from a
                                    device queue; 0: one wavefront per work item */
     int32_t waves_per_cu;       /* persistent grid size per compute unit (0: occupancy) */
     int32_t lds_stage;          /* 1: stage neighbour-frame footprints in LDS */
     int32_t xcd_queues;         /* 1: one work queue per XCD, keyframes bound to an XCD */
-    int32_t groups;             /* tiles_x x tiles_y groups per work item: 1, 2 or 4, and
-                                   1 for S = 16 (0: default).  A work item lies in one
+    int32_t groups;             /* tiles_x x tiles_y groups per work item: 1, 2 or 4; 1 or
+                                   2 for the 4x2 and 2x4 blocks; 1 for 4x4 and S = 16 (0:
+                                   as many as fit, at most four).  A work item lies in one
                                    aligned 16 x 16-pixel block; its per-surfel solves run
                                    together, one lane each */
 } sgn_plan;

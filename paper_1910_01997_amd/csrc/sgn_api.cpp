@@ -210,13 +210,23 @@ sgn_status check_params(const sgn_params* p) {
     return SGN_OK;
 }
 
+// Groups per work item when a plan leaves them at 0: as many as fit in an
+// anchor block, up to four.
+int default_groups(int patch, int tiles_x, int tiles_y) {
+    if (patch == 16) return 1;
+    if (patch == 4 && tiles_x * tiles_y >= 16) return 1;
+    if (patch == 4 && tiles_x * tiles_y >= 8) return 2;
+    return 4;
+}
+
 sgn_plan default_plan(int patch) {
     sgn_plan p{};
-    // measured fastest on the 64-keyframe batch: 2x2 groups, four per item;
-    // a 16 x 16 surfel spans a whole anchor block, so it is one group per item
-    if (patch == 4) { p.tiles_x = 2; p.tiles_y = 2; }
+    // measured fastest on the 64-keyframe batch: 2x4 groups (eight surfels per
+    // wavefront, two pixels per lane), two per item (a whole anchor block); a
+    // 16 x 16 surfel spans a whole anchor block, so it is one group per item
+    if (patch == 4) { p.tiles_x = 2; p.tiles_y = 4; }
     else { p.tiles_x = 1; p.tiles_y = 1; }
-    p.groups = patch == 16 ? 1 : 4;
+    p.groups = default_groups(patch, p.tiles_x, p.tiles_y);
     p.persistent = 1;
     p.waves_per_cu = 0;
     p.lds_stage = 0;
@@ -254,7 +264,7 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
     if (st) return st;
     sgn_plan plan = plan_in ? *plan_in : default_plan(patch);
     if (plan.tiles_x == 0 && plan.tiles_y == 0) plan = default_plan(patch);
-    if (plan.groups == 0) plan.groups = default_plan(patch).groups;
+    if (plan.groups == 0) plan.groups = default_groups(patch, plan.tiles_x, plan.tiles_y);
     GnVariant var{dtype, patch, plan.tiles_x, plan.tiles_y, plan.lds_stage, plan.groups};
     if (fl.gn && !gn_variant_supported(var)) return fail(SGN_E_UNSUPPORTED, "plan not supported for this patch");
 
@@ -999,7 +1009,8 @@ sgn_status sgn_autotune(sgn_ctx* c, const sgn_batch_item* items, int32_t n, cons
     };
     std::vector<sgn_plan> cands;
     std::vector<std::pair<int, int>> shapes = patch != 4 ? std::vector<std::pair<int, int>>{{1, 1}}
-                                                         : std::vector<std::pair<int, int>>{{4, 1}, {2, 2}, {1, 4}};
+                                                         : std::vector<std::pair<int, int>>{{4, 1}, {2, 2}, {1, 4},
+                                                                                            {4, 2}, {2, 4}, {4, 4}};
     const std::vector<int> group_counts = patch == 16 ? std::vector<int>{1} : std::vector<int>{1, 2, 4};
     for (auto sh : shapes)
         for (int groups : group_counts)

@@ -103,14 +103,15 @@ struct GnVariant {
 // Work-item geometry of the Gauss-Newton kernel.  Surfels are taken in
 // aligned anchor blocks of 16 x 16 pixels (ab x ab tiles).  A work item is an
 // ix x iy tile sub-block of one anchor block holding K groups of tx x ty
-// tiles (one group fills a wavefront: four 4 x 4 surfels or one 8 x 8
-// surfel), arranged gx x gy; ipb items tile an anchor block.
+// tiles (one group fills a wavefront: four or eight 4 x 4 surfels, one 8 x 8
+// or one 16 x 16 surfel), arranged gx x gy, as wide as the anchor block
+// allows; ipb items tile an anchor block.
 struct ItemGeo {
     int ab, gx, gy, ix, iy, ipb;
 };
 constexpr ItemGeo item_geo(int S, int TX, int TY, int K) {
     const int ab = 16 / S;
-    const int gx = (S == 4) ? (K == 4 ? 4 / TX : (K == 2 ? (TX == 4 ? 1 : 2) : 1)) : (K >= 2 ? 2 : 1);
+    const int gx = (S == 4) ? (K < 4 / TX ? K : 4 / TX) : (K >= 2 ? 2 : 1);
     const int gy = K / gx;
     const int ix = gx * TX, iy = gy * TY;
     return ItemGeo{ab, gx, gy, ix, iy, (ab / ix) * (ab / iy)};

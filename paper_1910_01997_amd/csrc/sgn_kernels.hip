@@ -81,38 +81,31 @@ __device__ __forceinline__ int dpp_i(int x) {
     return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, true);
 }
 
-// Sum over the 16 lanes of a DPP row.  Every lane of the row ends with the
+// Sum over a surfel's lanes: 4 lanes (a quad), 8 (half a DPP row), 16 (one
+// row), 32 (two rows) or the whole wavefront.  Every lane of the surfel ends with the
 // bitwise-same value: each step adds a lane's value and its partner's, and
 // float addition is commutative.
-__device__ __forceinline__ float row_sum(float x) {
-#pragma clang fp contract(off)
-    x += dpp_f<0xB1>(x);   // quad_perm [1,0,3,2]
-    x += dpp_f<0x4E>(x);   // quad_perm [2,3,0,1]
-    x += dpp_f<0x141>(x);  // row_half_mirror
-    x += dpp_f<0x140>(x);  // row_mirror
-    return x;
-}
-__device__ __forceinline__ int row_sum(int x) {
-    x += dpp_i<0xB1>(x);
-    x += dpp_i<0x4E>(x);
-    x += dpp_i<0x141>(x);
-    x += dpp_i<0x140>(x);
-    return x;
-}
-
-// Sum over a surfel's lanes: 16 lanes (one DPP row), 32 (two rows) or the
-// whole wavefront.
 template <int LANES>
 __device__ __forceinline__ float group_sum(float x) {
 #pragma clang fp contract(off)
-    x = row_sum(x);
+    static_assert(LANES == 4 || LANES == 8 || LANES == 16 || LANES == 32 || LANES == 64,
+                  "lanes per surfel");
+    x += dpp_f<0xB1>(x);
+    x += dpp_f<0x4E>(x);
+    if constexpr (LANES >= 8) x += dpp_f<0x141>(x);
+    if constexpr (LANES >= 16) x += dpp_f<0x140>(x);
     if constexpr (LANES >= 32) x += __shfl_xor(x, 16);
     if constexpr (LANES == 64) x += __shfl_xor(x, 32);
     return x;
 }
 template <int LANES>
 __device__ __forceinline__ int group_sum(int x) {
-    x = row_sum(x);
+    static_assert(LANES == 4 || LANES == 8 || LANES == 16 || LANES == 32 || LANES == 64,
+                  "lanes per surfel");
+    x += dpp_i<0xB1>(x);
+    x += dpp_i<0x4E>(x);
+    if constexpr (LANES >= 8) x += dpp_i<0x141>(x);
+    if constexpr (LANES >= 16) x += dpp_i<0x140>(x);
     if constexpr (LANES >= 32) x += __shfl_xor(x, 16);
     if constexpr (LANES == 64) x += __shfl_xor(x, 32);
     return x;
@@ -123,17 +116,26 @@ __device__ __forceinline__ int group_sum(int x) {
 // butterfly step trades halves with the neighbour lane (each lane keeps the
 // value it will own and sends the other), so the remaining steps carry one
 // value instead of two; they pair lanes of equal parity only (quad_perm,
-// then row rotations by 4 and 8).  Lanes 0 and 1 form their sums in a fixed
-// order that depends only on the surfel's pixels.
+// then row rotations by 4 and 8; an 8-lane surfel instead shifts its second
+// quad's sums down by 4 lanes, since a rotation would bring in the
+// neighbouring surfel's).  Lanes 0 and 1 form their sums in a fixed order
+// that depends only on the surfel's pixels.
 template <int LANES>
 __device__ __forceinline__ float pair_sum(float ev, float od, bool odd) {
 #pragma clang fp contract(off)
+    static_assert(LANES == 4 || LANES == 8 || LANES == 16 || LANES == 32 || LANES == 64,
+                  "lanes per surfel");
     const float keep = odd ? od : ev;
     const float send = odd ? ev : od;
     float x = keep + dpp_f<0xB1>(send);   // quad_perm [1,0,3,2]
     x += dpp_f<0x4E>(x);                  // quad_perm [2,3,0,1]
-    x += dpp_f<0x124>(x);                 // row_ror:4
-    x += dpp_f<0x128>(x);                 // row_ror:8
+    if constexpr (LANES == 4) {
+    } else if constexpr (LANES == 8) {
+        x += dpp_f<0x104>(x);             // row_shl:4 (lane i takes lane i + 4)
+    } else {
+        x += dpp_f<0x124>(x);             // row_ror:4
+        x += dpp_f<0x128>(x);             // row_ror:8
+    }
     if constexpr (LANES >= 32) x += __shfl_xor(x, 16);
     if constexpr (LANES == 64) x += __shfl_xor(x, 32);
     return x;
@@ -771,17 +773,18 @@ __device__ __forceinline__ bool lm_accept(float cost2, int nv2, float cost_here,
 // between the pixel lanes and the owners through LDS.  All iterations run in
 // the kernel: surfels never read each other during the optimisation.
 template <typename T, int S, int TX, int TY, int K>
-__global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __restrict__ hdr_,
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void gn_kernel(const BatchHeader* __restrict__ hdr_,
                                                            uint32_t* __restrict__ counters,
                                                            int persistent) {
     constexpr ItemGeo G = item_geo(S, TX, TY, K);
     constexpr int PIX = S * S;                                // pixels per surfel
-    constexpr int LANES = PIX < kWaveSize ? PIX : kWaveSize;  // lanes per surfel
+    constexpr int SLOTS = TX * TY;                            // surfels per group
+    constexpr int LANES = kWaveSize / SLOTS;                  // lanes per surfel
     constexpr int PPL = PIX / LANES;                          // pixels per lane
-    constexpr int SLOTS = kWaveSize / LANES;                  // surfels per group
     constexpr int NS = K * SLOTS;                             // surfels per work item
-    static_assert(TX * TY * LANES == kWaveSize, "a group fills the wavefront");
-    static_assert(NS <= kMaxItemSurfels, "surfels per item");
+    static_assert(PPL * LANES == PIX, "a group fills the wavefront");
+    static_assert(NS <= kMaxItemSurfels && K <= LANES, "surfels per item");
+    static_assert(G.ix <= G.ab && G.iy <= G.ab, "a work item lies in one anchor block");
     const cptr<BatchHeader> hdr = (cptr<BatchHeader>)hdr_;
     const int lane = threadIdx.x & (kWaveSize - 1);
     const int wave = threadIdx.x >> 6;
@@ -800,8 +803,8 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
         dyp[j] = (float)pys[j] - half;
     }
     // owner role: surfel (group ok_g, slot ok_r) of the item
-    const int ok_g = (S == 4) ? (lane & 15) : lane;
-    const int ok_r = (S == 4) ? (lane >> 4) : 0;
+    const int ok_g = SLOTS == 1 ? lane : lane & (LANES - 1);
+    const int ok_r = SLOTS == 1 ? 0 : lane >> __builtin_ctz(LANES);
     const bool owner = ok_g < K;
     const int own = ok_g * SLOTS + ok_r;
 
@@ -972,12 +975,11 @@ __global__ __launch_bounds__(kBlockThreads) void gn_kernel(const BatchHeader* __
                         frame_loop<T, false>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes,
                                              wm1, hm1, ikf[k][j], hk, img_scale, A, B, cst, nvl);
                     {
-#pragma clang fp contract(off)
                         const float ag0 = A * g0, ag1 = A * g1, ag2 = A * g2;
-                        const float t[9] = {ag0 * g0, ag0 * g1, ag0 * g2, ag1 * g1, ag1 * g2,
-                                            ag2 * g2, B * g0, B * g1, B * g2};
+                        const float u[9] = {ag0, ag0, ag0, ag1, ag1, ag2, B, B, B};
+                        const float v[9] = {g0, g1, g2, g1, g2, g2, g0, g1, g2};
 #pragma unroll
-                        for (int e = 0; e < 9; ++e) ph[e] = (j == 0) ? t[e] : ph[e] + t[e];
+                        for (int e = 0; e < 9; ++e) ph[e] = (j == 0) ? u[e] * v[e] : fmaf(u[e], v[e], ph[e]);
                         pnv = (j == 0) ? (float)nvl : pnv + (float)nvl;
                         pcs = (j == 0) ? cst : pcs + cst;
                     }
@@ -1425,11 +1427,12 @@ static void* gn_ptr() {
     return (void*)&gn_kernel<T, S, TX, TY, K>;
 }
 
-template <typename T, int S, int TX, int TY>
+template <typename T, int S, int TX, int TY, int KMAX = 4>
 static void* gn_pick_groups(int groups) {
     if (groups == 1) return gn_ptr<T, S, TX, TY, 1>();
     if (groups == 2) return gn_ptr<T, S, TX, TY, 2>();
-    if (groups == 4) return gn_ptr<T, S, TX, TY, 4>();
+    if constexpr (KMAX >= 4)
+        if (groups == 4) return gn_ptr<T, S, TX, TY, 4>();
     return nullptr;
 }
 
@@ -1441,6 +1444,11 @@ static void* gn_pick(const GnVariant& v) {
     if (v.patch == 4 && v.tiles_x == 4 && v.tiles_y == 1) return gn_pick_groups<T, 4, 4, 1>(v.groups);
     if (v.patch == 4 && v.tiles_x == 2 && v.tiles_y == 2) return gn_pick_groups<T, 4, 2, 2>(v.groups);
     if (v.patch == 4 && v.tiles_x == 1 && v.tiles_y == 4) return gn_pick_groups<T, 4, 1, 4>(v.groups);
+    // eight 4 x 4 surfels per wavefront, two pixels per lane: one or two groups
+    if (v.patch == 4 && v.tiles_x == 4 && v.tiles_y == 2) return gn_pick_groups<T, 4, 4, 2, 2>(v.groups);
+    if (v.patch == 4 && v.tiles_x == 2 && v.tiles_y == 4) return gn_pick_groups<T, 4, 2, 4, 2>(v.groups);
+    // sixteen 4 x 4 surfels (a whole anchor block) per wavefront, four pixels per lane
+    if (v.patch == 4 && v.tiles_x == 4 && v.tiles_y == 4 && v.groups == 1) return gn_ptr<T, 4, 4, 4, 1>();
     return nullptr;
 }
 

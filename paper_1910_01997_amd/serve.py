@@ -305,8 +305,11 @@ class HipExecutor(Executor):
         self.ctxs = [sg.Context(0, stream=s) for s in self.tstreams]
         self.params = sg.params(iters=iters)
         self.plan = plan
+        # every plan here gives a 4x4 surfel 16 lanes (one pixel each), so a
+        # request's result is the same, bitwise, alone and in any mix
         self.small_plan = sg.plan(2, 2, 1, 0, 0, 1, groups=1)
         self.single_plan = sg.plan(2, 2, 0, 0, 0, 0, groups=1)
+        self.large_plan = sg.plan(2, 2, 1, 0, 0, 1, groups=4)
         self.small_batch_surfels = 200_000
 
     def request_bytes(self, req: Request) -> int:
@@ -352,7 +355,7 @@ class HipExecutor(Executor):
                     # a small batch cannot fill the device with four groups per
                     # work item: use one group per wavefront there
                     total = sum(self.streams[r.stream].dk.n_surfels for r in batch)
-                    plan = self.small_plan if total < self.small_batch_surfels else None
+                    plan = self.small_plan if total < self.small_batch_surfels else self.large_plan
                 arr = self.sg.batch_array(items)
                 self.sg.sgn_optimize_batch(ctx, arr, len(items), self.params, plan)
             # responses: depth map and surfels copied into the stream's host buffers

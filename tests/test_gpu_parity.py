@@ -89,6 +89,20 @@ def test_workload1_plain(ctx, storage):
     assert_parity(res, label=f"w1 {storage}")
 
 
+@pytest.mark.parametrize("tiles,groups,persistent", [((4, 2), 2, 1), ((2, 4), 1, 0), ((4, 4), 1, 1)])
+def test_workload1_eight_and_sixteen_surfel_groups(ctx, tiles, groups, persistent):
+    """Eight or sixteen 4x4 surfels per wavefront: two or four pixels per
+    lane, 8- or 4-lane reductions."""
+    from paper_1910_01997_amd import surfgn as sg
+    kf = make_keyframe(spec_for_config(1), device="cuda")
+    pl = sg.plan(tiles[0], tiles[1], persistent, 0, 0, persistent, groups=groups)
+    label = f"w1 f16 tiles {tiles[0]}x{tiles[1]} groups {groups} persistent {persistent}"
+    print("case", label, flush=True)
+    dk, dev = _plain(ctx, kf, storage="f16", plan=pl)
+    res = check_parity(dk, dev, kf.init_id, kf.init_n, kf.is_new, _oparams(kf.iters), label=label)
+    assert_parity(res, label=label)
+
+
 def test_render_matches_oracle(ctx):
     kf = make_keyframe(spec_for_config(1), device="cuda")
     dk, dev = _plain(ctx, kf)

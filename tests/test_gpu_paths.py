@@ -43,27 +43,70 @@ def _state_equal(a: dict, b: dict):
 
 
 def test_batch_equals_plain_bitwise_and_plans_agree(ctx):
+    """Plans that give a surfel the same lanes (pixels per lane) agree
+    bitwise with the plain single-keyframe form, batched or not, persistent
+    or not, whatever the groups per item."""
     sg, engine = sgmod()
     kfs = [make_keyframe(spec_for_config(2, i), device="cuda") for i in (3, 4, 5)]
     print("case batch==plain, keyframes 3,4,5 of the batch workload", flush=True)
     prm = sg.params(iters=6)
-    # plain, one keyframe at a time
-    ref = []
-    for k in kfs:
-        d = engine.DeviceKeyframe.from_scene(ctx, k)
-        engine.update_plain(ctx, d, prm)
-        torch.cuda.synchronize()
-        ref.append((d.state.to_host(), d.inv_depth_out.cpu().numpy()))
-    plans = [None, sg.plan(4, 1, 1, 0, 0, 1, groups=1), sg.plan(2, 2, 1, 0, 0, 1, groups=2),
-             sg.plan(1, 4, 1, 0, 0, 0, groups=4), sg.plan(2, 2, 0, 0, 0, 0, groups=1),
-             sg.plan(4, 1, 0, 0, 0, 0, groups=4)]
-    for pl in plans:
+    layouts = [
+        # two pixels per lane (the default): plain form with the default plan
+        (None, [None, sg.plan(4, 2, 1, 0, 0, 1, groups=2), sg.plan(2, 4, 0, 0, 0, 0, groups=1),
+                sg.plan(2, 4, 1, 0, 0, 0, groups=2)]),
+        # one pixel per lane
+        (sg.plan(2, 2, 0, 0, 0, 0, groups=1),
+         [sg.plan(4, 1, 1, 0, 0, 1, groups=1), sg.plan(2, 2, 1, 0, 0, 1, groups=2),
+          sg.plan(1, 4, 1, 0, 0, 0, groups=4), sg.plan(4, 1, 0, 0, 0, 0, groups=4),
+          sg.plan(2, 2, 1, 0, 0, 1, groups=4)]),
+    ]
+    for plain_plan, plans in layouts:
+        ref = []
+        for k in kfs:
+            d = engine.DeviceKeyframe.from_scene(ctx, k)
+            engine.update_plain(ctx, d, prm, plain_plan)
+            torch.cuda.synchronize()
+            ref.append((d.state.to_host(), d.inv_depth_out.cpu().numpy()))
+        for pl in plans:
+            ds = [engine.DeviceKeyframe.from_scene(ctx, k) for k in kfs]
+            engine.update_batch(ctx, ds, prm, pl)
+            torch.cuda.synchronize()
+            for d, (st, dm) in zip(ds, ref):
+                _state_equal(d.state.to_host(), st)
+                assert np.array_equal(d.inv_depth_out.cpu().numpy(), dm)
+
+
+def test_eight_surfel_groups_batch_equals_plain_and_ragged(ctx):
+    """The 4x2 / 2x4 / 4x4 layouts (eight or sixteen 4x4 surfels per
+    wavefront): batched equals one keyframe at a time bitwise under the same
+    plan, and a ragged image with three neighbours keeps oracle parity."""
+    sg, engine = sgmod()
+    kfs = [make_keyframe(spec_for_config(2, i), device="cuda") for i in (6, 7)]
+    prm = sg.params(iters=6)
+    for pl in (sg.plan(4, 2, 1, 0, 0, 1, groups=2), sg.plan(2, 4, 0, 0, 0, 0, groups=1),
+               sg.plan(4, 4, 1, 0, 0, 1, groups=1)):
+        print(f"case 8-surfel groups batch==plain tiles {pl.tiles_x}x{pl.tiles_y}", flush=True)
+        ref = []
+        for k in kfs:
+            d = engine.DeviceKeyframe.from_scene(ctx, k)
+            engine.update_plain(ctx, d, prm, plan=pl)
+            torch.cuda.synchronize()
+            ref.append((d.state.to_host(), d.inv_depth_out.cpu().numpy()))
         ds = [engine.DeviceKeyframe.from_scene(ctx, k) for k in kfs]
         engine.update_batch(ctx, ds, prm, pl)
         torch.cuda.synchronize()
         for d, (st, dm) in zip(ds, ref):
             _state_equal(d.state.to_host(), st)
             assert np.array_equal(d.inv_depth_out.cpu().numpy(), dm)
+    spec = _small_spec(width=102, height=66, patch=4, n_nbr=3, iters=8, n_rects=3, half_new=False)
+    kf = make_keyframe(spec, device="cuda")
+    print("case 8-surfel groups ragged 102x66 N=3", flush=True)
+    d = engine.DeviceKeyframe.from_scene(ctx, kf)
+    engine.update_plain(ctx, d, sg.params(iters=8), plan=sg.plan(4, 2, 0, 0, 0, 0, groups=2))
+    torch.cuda.synchronize()
+    res = check_parity(d, d.state.to_host(), kf.init_id, kf.init_n, None, oracle.OracleParams(iters=8),
+                       label="ragged 102x66 tiles 4x2")
+    assert_parity(res, label="ragged 102x66 tiles 4x2", max_unstable=0.15)
 
 
 def test_repeated_calls_are_deterministic(ctx):
@@ -197,8 +240,10 @@ def test_argument_errors_are_reported(ctx):
     # bad params
     assert L.sgn_optimize_keyframe(ctx.handle, d.view.c, d.state.c, sg.params(iters=-1), None) == sg.SGN_E_INVALID
     assert L.sgn_optimize_keyframe(ctx.handle, d.view.c, d.state.c, sg.params(huber_k=0.0), None) == sg.SGN_E_INVALID
-    # plans the kernel does not have: LDS-staged taps, 3 groups, 3x1 tiles
-    for pl in (sg.plan(2, 2, lds_stage=1, groups=4), sg.plan(2, 2, groups=3), sg.plan(3, 1, groups=1)):
+    # plans the kernel does not have: LDS-staged taps, 3 groups, 3x1 tiles,
+    # four groups of 4x2 tiles or two of 4x4 (larger than an anchor block)
+    for pl in (sg.plan(2, 2, lds_stage=1, groups=4), sg.plan(2, 2, groups=3), sg.plan(3, 1, groups=1),
+               sg.plan(4, 2, groups=4), sg.plan(4, 4, groups=2)):
         assert L.sgn_optimize_keyframe(ctx.handle, d.view.c, d.state.c, prm, pl) == sg.SGN_E_UNSUPPORTED
     # nothing was enqueued: the state is untouched
     torch.cuda.synchronize()
