@@ -415,7 +415,10 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
     auto enqueue_gn = [&](hipStream_t s) -> hipError_t {
         return launch_gn(var, dH, c->counters, plan.persistent, gn_grid, s);
     };
-    auto enqueue_post = [&](hipStream_t s) -> hipError_t { return launch_render(dH, aux_grid, s); };
+    // render: one segment per thread for the larger batches (runs of 256
+    // segments per block, so blocks past the batch's segments return at once)
+    const int render_grid = std::max(1, c->cus) * 32;
+    auto enqueue_post = [&](hipStream_t s) -> hipError_t { return launch_render(dH, render_grid, s); };
     const bool run_gn = fl.gn && item_base > 0;
     const bool graph_ok = c->use_graphs && (plan.persistent || !run_gn);
     auto run_part = [&](int part, bool needed, auto&& enq) -> sgn_status {

@@ -760,16 +760,17 @@ __device__ __forceinline__ bool lm_accept(float cost2, int nv2, float cost_here,
 //
 // Mapping.  A work item is a block of surfels inside one aligned anchor
 // block (16 x 16 pixels): K groups, each filling the 64 lanes of the
-// wavefront with pixels (S = 4: a TX x TY arrangement of four 4 x 4 surfels,
-// one DPP row of 16 lanes per surfel; S = 8: one 8 x 8 surfel).  Per
-// iteration the wavefront walks its groups; for each, every lane (one pixel)
-// forms the frame-independent terms of its surfel (hoisted as the paper
-// suggests), loops over the neighbour frames (warp, bilinear sample and
-// gradient, Huber-weighted residual, chain factor) and the surfel's lanes
-// reduce J^T W J and J^T W r with DPP.  Each surfel has an owner lane
-// (S = 4: lane k of its row in group k; S = 8: lane k); the owners then solve
-// all K groups' 3 x 3 systems at once, so the per-surfel work (solve,
-// update, tangent basis) is issued once per K groups.  Sums and states pass
+// wavefront with pixels (S = 4: a TX x TY arrangement of four, eight or
+// sixteen 4 x 4 surfels, 16, 8 or 4 lanes per surfel, one, two or four
+// pixels per lane; S = 8: one 8 x 8 surfel; S = 16: one 16 x 16 surfel,
+// four pixels per lane).  Per iteration the wavefront walks its groups; for
+// each, every lane forms the frame-independent terms of its pixels' surfel
+// (hoisted as the paper suggests), loops over the neighbour frames (warp,
+// bilinear sample and gradient, Huber-weighted residual, chain factor) and
+// the surfel's lanes reduce J^T W J and J^T W r with DPP.  Each surfel has
+// an owner lane (lane k among the surfel's lanes for group k); the owners
+// then solve all K groups' 3 x 3 systems at once, so the per-surfel work
+// (solve, update, tangent basis) is issued once per K groups.  Sums and states pass
 // between the pixel lanes and the owners through LDS.  All iterations run in
 // the kernel: surfels never read each other during the optimisation.
 template <typename T, int S, int TX, int TY, int K>
@@ -1191,74 +1192,117 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
 // renders one segment: the up-to-S pixels of one image row that lie in one
 // tile column (segments past the grid write "no measurement"), so a surfel's
 // state is read once per segment.  Segments are numbered keyframe after
-// keyframe (only keyframes with an output).
+// keyframe (only keyframes with an output).  A block takes runs of 256
+// consecutive segments: its first thread finds the run's keyframe, and only
+// threads whose segment lies past that keyframe search for their own.
 
-__global__ void render_kernel(const BatchHeader* __restrict__ hdr_) {
+// The keyframe owning segment g: the last one whose base is <= g (keyframes
+// without an output add no segments, so the next base is larger than g only
+// past the owner).
+__device__ __forceinline__ int render_owner(cptr<KfDev> kfs, int n_kf, int64_t g) {
+    int lo = 0, hi = n_kf - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (kfs[mid].pixel_base <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void render_kernel(const BatchHeader* __restrict__ hdr_) {
     const cptr<BatchHeader> hdr = (cptr<BatchHeader>)hdr_;
     const cptr<KfDev> kfs = (cptr<KfDev>)hdr->kfs;
     const int n_kf = hdr->n_kf;
     const int64_t total = hdr->total_pixels;           // render segments
-    int hint = 0;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
-         g += (int64_t)gridDim.x * blockDim.x) {
-        // keyframe of segment g (fast path: the previous one)
+    __shared__ int s_kf;
+    // the loop bounds are the same for every thread of a block
+    for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x; g0 < total; g0 += (int64_t)gridDim.x * blockDim.x) {
+        __syncthreads();                                // the previous run's s_kf is read
+        if (threadIdx.x == 0) s_kf = render_owner(kfs, n_kf, g0);
+        __syncthreads();
+        const int64_t g = g0 + threadIdx.x;
+        if (g >= total) continue;
+        int kidx = s_kf;
         {
-            const cptr<KfDev> kh = kfs + hint;
+            const cptr<KfDev> kh = kfs + kidx;
             const int64_t nseg = (int64_t)kh->height * ((kh->width + kh->patch - 1) / kh->patch);
-            if (!(kh->inv_depth_out && g >= kh->pixel_base && g < kh->pixel_base + nseg)) {
-                // the last keyframe whose base is <= g owns it (keyframes
-                // without an output add no segments, so the next base is
-                // larger than g only past the owner)
-                int lo = 0, hi = n_kf - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (kfs[mid].pixel_base <= g) lo = mid; else hi = mid - 1;
-                }
-                hint = lo;
-            }
+            if (!(kh->inv_depth_out && g >= kh->pixel_base && g < kh->pixel_base + nseg))
+                kidx = render_owner(kfs, n_kf, g);
         }
-        const cptr<KfDev> K = kfs + hint;
+        const cptr<KfDev> K = kfs + kidx;
         const int W = K->width, S = K->patch;
         const int nsx = (W + S - 1) / S;
         const int sg = (int)(g - K->pixel_base);
         const int y = sg / nsx, tx = sg - y * nsx;
-        const int x0 = tx * S, ty = y / S;
+        const int x0 = tx * S, ty = y >> __builtin_ctz(S);    // S is 4, 8 or 16
         const float half = 0.5f * (float)(S - 1);
         float* const out = K->inv_depth_out + (size_t)y * W + x0;
         int32_t* const idx_out = K->index_out ? K->index_out + (size_t)y * W + x0 : nullptr;
         bool ok = false;
         int i = -1;
-        float id = 0.f, nx = 0.f, ny = 0.f, c = 1.f, usx = 0.f, usy = 0.f;
+        // three divisions per segment; the pixels multiply by the reciprocals
+        const float ifx = 1.f / K->fx, ify = 1.f / K->fy;
+        float id = 0.f, nx = 0.f, ny = 0.f, inv_c = 1.f, usx = 0.f, usy = 0.f;
         if (tx < K->gw && ty < K->gh) {
             i = ty * K->gw + tx;
             if (!(K->flags[i] & (F_DEGENERATE | F_UNINIT))) {
                 usx = (float)(S * tx) + half;
                 usy = (float)(S * ty) + half;
-                const float rsx = (usx - K->cx) / K->fx, rsy = (usy - K->cy) / K->fy;
+                const float rsx = (usx - K->cx) * ifx, rsy = (usy - K->cy) * ify;
                 nx = K->nx[i];
                 ny = K->ny[i];
                 const float nz = K->nz[i];
-                c = nx * rsx + ny * rsy + nz;
+                const float c = nx * rsx + ny * rsy + nz;
                 id = K->inv_depth[i];
                 ok = fabsf(c) >= 1e-6f;
+                inv_c = 1.f / c;
             }
         }
-        const float dry = ((float)y - usy) / K->fy;
+        const float dry = ((float)y - usy) * ify;
         const int n_px = min(S, W - x0);
-        for (int j = 0; j < n_px; ++j) {
-            float val = 0.f;
-            int who = -1;
+        // Eq. 3 at pixel x0 + j of the segment
+        auto pixel = [&](int j, float& val, int& who) {
+            val = 0.f;
+            who = -1;
             if (ok) {
-                const float drx = ((float)(x0 + j) - usx) / K->fx;
-                const float sigma = (nx * drx + ny * dry) / c;
+                const float drx = ((float)(x0 + j) - usx) * ifx;
+                const float sigma = (nx * drx + ny * dry) * inv_c;
                 const float idu = fmaf(id, sigma, id);
                 if (idu > 0.f && isfinite(idu)) {
                     val = idu;
                     who = i;
                 }
             }
-            out[j] = val;
-            if (idx_out) idx_out[j] = who;
+        };
+        if (S == 4) {
+            float v[4];
+            int w[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) pixel(j, v[j], w[j]);
+            // a whole 16-byte aligned segment in one store, else pixel by pixel
+            if (n_px == 4 && ((uintptr_t)out & 15u) == 0) {
+                *(float4*)out = make_float4(v[0], v[1], v[2], v[3]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (j < n_px) out[j] = v[j];
+            }
+            if (idx_out) {
+                if (n_px == 4 && ((uintptr_t)idx_out & 15u) == 0) {
+                    *(int4*)idx_out = make_int4(w[0], w[1], w[2], w[3]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (j < n_px) idx_out[j] = w[j];
+                }
+            }
+        } else {
+            for (int j = 0; j < n_px; ++j) {
+                float v;
+                int w;
+                pixel(j, v, w);
+                out[j] = v;
+                if (idx_out) idx_out[j] = w;
+            }
         }
     }
 }
