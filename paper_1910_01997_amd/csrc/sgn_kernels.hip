@@ -1567,11 +1567,11 @@ __device__ __forceinline__ float slot_value<float>(uint32_t) { return 0.f; }
 
 // The rows of one disc (clipped to the image): the surfel's lanes below the
 // row count (hl is the lane's index among the surfel's LANES lanes) find
-// their row's run of pixels (a disc meets a row in one run), its lane 0
-// forms the running counts.  row_x0[i] is the first column of row y0 + i and
-// row_start[i] the number of disc pixels before it.  A non-finite centre
-// gives an empty disc.  Every lane passes the same synchronisation points;
-// the caller synchronises the wavefront before.
+// their row's run of pixels (a disc meets a row in one run), and a scan over
+// those lanes forms the running counts.  row_x0[i] is the first column of
+// row y0 + i and row_start[i] the number of disc pixels before it.  A
+// non-finite centre gives an empty disc.  Every lane passes the same
+// synchronisation point; the caller synchronises the wavefront before.
 template <int LANES>
 __device__ DiscRows disc_rows(float ux, float uy, float radius, int W, int H, int hl, int* row_x0,
                               int* row_start) {
@@ -1589,9 +1589,9 @@ __device__ DiscRows disc_rows(float ux, float uy, float radius, int W, int H, in
         d.y0 = (int)ylo;
         d.nrows = (int)yhi - d.y0 + 1;
     }
+    int first = x0, cnt = 0;
     if (hl < d.nrows) {
         const double dy = (double)(d.y0 + hl) - cy;
-        int first = x0, cnt = 0;
         for (int x = x0; x <= x1; ++x) {
             const double dx = (double)x - cx;
             if (dx * dx + dy * dy < r2) {
@@ -1599,18 +1599,19 @@ __device__ DiscRows disc_rows(float ux, float uy, float radius, int W, int H, in
                 ++cnt;
             }
         }
+    }
+    // inclusive scan of the row counts over the surfel's lanes
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < LANES; o <<= 1) {
+        const int v = __shfl_up(incl, o, LANES);
+        if (hl >= o) incl += v;
+    }
+    if (hl < d.nrows) {
         row_x0[hl] = first;
-        row_start[hl + 1] = cnt;
+        row_start[hl + 1] = incl;
     }
-    wave_sync();
-    if (hl == 0) {
-        int acc = 0;
-        row_start[0] = 0;
-        for (int i = 0; i < d.nrows; ++i) {
-            acc += row_start[i + 1];
-            row_start[i + 1] = acc;
-        }
-    }
+    if (hl == 0) row_start[0] = 0;
     wave_sync();
     d.total = min(row_start[d.nrows], kWaveSize * kDiscPPL);
     return d;
@@ -1969,16 +1970,24 @@ __global__ __launch_bounds__(kBlockThreads) void disc_scatter_kernel(const DiscR
     }
 }
 
-__global__ void disc_resolve_kernel(const DiscRenderItem* __restrict__ tab, int n_items, int64_t total,
-                                    const unsigned long long* __restrict__ key,
-                                    const int32_t* __restrict__ idx) {
-    int hint = 0;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        if (!(p >= tab[hint].pixel_base &&
-              p < tab[hint].pixel_base + (int64_t)tab[hint].width * tab[hint].height))
-            hint = render_item_of_pixel(tab, n_items, p);
-        const DiscRenderItem& a = tab[hint];
+// One pixel per thread; a block's first thread finds the keyframe of the
+// block's first pixel, and only threads past that keyframe search for their
+// own.  The grid-stride loop has the same bounds for every thread of a block.
+__global__ __launch_bounds__(256) void disc_resolve_kernel(const DiscRenderItem* __restrict__ tab,
+                                                           int n_items, int64_t total,
+                                                           const unsigned long long* __restrict__ key,
+                                                           const int32_t* __restrict__ idx) {
+    __shared__ int s_item;
+    for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x; p0 < total; p0 += (int64_t)gridDim.x * blockDim.x) {
+        __syncthreads();                                // the previous run's s_item is read
+        if (threadIdx.x == 0) s_item = render_item_of_pixel(tab, n_items, p0);
+        __syncthreads();
+        const int64_t p = p0 + threadIdx.x;
+        if (p >= total) continue;
+        int it = s_item;
+        if (!(p < tab[it].pixel_base + (int64_t)tab[it].width * tab[it].height))
+            it = render_item_of_pixel(tab, n_items, p);
+        const DiscRenderItem& a = tab[it];
         const int64_t i = p - a.pixel_base;
         const unsigned long long k = key[p];
         a.inv_depth_out[i] = k ? (float)__longlong_as_double((long long)k) : 0.f;
@@ -2251,7 +2260,9 @@ hipError_t launch_disc_render(const DiscRenderItem* table, int n_items, int tota
         disc_scatter_kernel<0><<<grid, kBlockThreads, 0, s>>>(table, n_items, total_surfels, key, idx);
         disc_scatter_kernel<1><<<grid, kBlockThreads, 0, s>>>(table, n_items, total_surfels, key, idx);
     }
-    disc_resolve_kernel<<<fill, 256, 0, s>>>(table, n_items, total_pixels, key, idx);
+    // one pixel per thread (up to 2^20 blocks, then a grid-stride loop)
+    const int resolve_blocks = (int)std::min<int64_t>((total_pixels + 255) / 256, 1 << 20);
+    disc_resolve_kernel<<<std::max(resolve_blocks, 1), 256, 0, s>>>(table, n_items, total_pixels, key, idx);
     return hipGetLastError();
 }
 
