@@ -51,7 +51,9 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # the first launches of a process run slower while the clock ramps up
+    # (about five steps of the batch); ten warm-up steps take 50 ms
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--storage", default="f16", choices=["f32", "f16", "u8"])
     ap.add_argument("--keyframes", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
