@@ -118,9 +118,12 @@ static double huber_rho(double r, double k) {
     double a = fabs(r);
     return a <= k ? 0.5 * r * r : k * a - 0.5 * k * k;
 }
+/* w = min(1, k/|r|), the minimum taken as IEEE minNum: a residual that is
+ * not a number gets weight 1, so its term of J^T W r and its cost stay not a
+ * number while J^T W J keeps its finite value. */
 static double huber_w(double r, double k) {
     double a = fabs(r);
-    return a <= k ? 1.0 : k / a;
+    return fmin(1.0, k / a);
 }
 
 /* Residual and Jacobian row of one (pixel, frame) sample, by the chain rule

@@ -164,6 +164,38 @@ def test_f16_storage_equals_f32_on_half_exact_images(ctx):
     assert np.array_equal(out["f32"][1], out["f16"][1])
 
 
+def test_nan_pixels_fail_the_step_and_never_reach_the_state(ctx):
+    """NaN pixels (a dead block in one neighbour frame, two in the keyframe)
+    poison only the surfels whose samples read them: their normal equations
+    or their step are not finite, so the solve fails or the step is refused
+    (flags), their state keeps its last finite value, and the whole result
+    agrees with the oracle run on the same images."""
+    sg, engine = sgmod()
+    kf = make_keyframe(_small_spec(width=160, height=120, patch=4, n_nbr=3, seed=41, half_new=False),
+                       device="cuda")
+    nb = kf.nbr_images.clone()
+    nb[0, 40:52, 60:76] = float("nan")
+    ki = kf.kf_image.clone()
+    ki[10, 10] = float("nan")
+    ki[100, 150] = float("nan")
+    kf = dataclasses.replace(kf, kf_image=ki, nbr_images=nb)
+    print("case NaN pixels 160x120 S4 N3", flush=True)
+    d = engine.DeviceKeyframe.from_scene(ctx, kf)
+    engine.update_plain(ctx, d, sg.params(iters=8))
+    torch.cuda.synchronize()
+    dev = d.state.to_host()
+    assert np.all(np.isfinite(dev["inv_depth"])) and np.all(np.isfinite(dev["n"]))
+    hit = (dev["flags"] & (sg.FLAG_SOLVE_FAIL | sg.FLAG_REJECTED)) != 0
+    gw = 160 // 4
+    # the surfels holding the keyframe's NaN pixels see them in every sample
+    assert hit[(10 // 4) * gw + 10 // 4] and hit[(100 // 4) * gw + 150 // 4]
+    assert hit.sum() > 2                      # and some warp into the dead block
+    assert np.all(np.isfinite(d.inv_depth_out.cpu().numpy()))
+    res = check_parity(d, dev, kf.init_id, kf.init_n, None, oracle.OracleParams(iters=8),
+                       label="NaN pixels")
+    assert_parity(res, label="NaN pixels", max_unstable=0.25)
+
+
 def test_zero_iterations_leave_the_state(ctx):
     sg, engine = sgmod()
     kf = make_keyframe(_small_spec(half_new=False), device="cuda")

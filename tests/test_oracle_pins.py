@@ -391,6 +391,30 @@ def test_huber_weight_and_cost_single_pixel_surfels():
     assert hits["in"] > 10 and hits["out"] > 10
 
 
+def test_huber_weight_of_a_nan_residual_is_one():
+    """A keyframe pixel that is not a number: with 1x1 surfels its surfel's
+    samples have NaN residuals and weight 1, so J^T W J is the unweighted
+    sum of J J^T (finite) while J^T W r and the cost are NaN."""
+    okf, gt_id, gt_n = _construction_i(S=1, W=24, H=20)
+    tx, ty = 7, 6
+    okf._kf_arr[ty, tx] = np.nan
+    ids = 0.45
+    n = np.array([0.0, 0.0, -1.0])
+    H, b, cost, nv = oracle.linearize(okf, tx, ty, ids, n, huber_k=0.004)
+    tot_H = np.zeros((3, 3))
+    for f in range(2):
+        R = np.array(okf._poses[f].R[:]).reshape(3, 3)
+        t = np.array(okf._poses[f].t[:])
+        ok, r, J = oracle.eval_sample((128.0, 128.0, 24.0, 20.0), R, t, okf._nbr_arrs[f],
+                                      okf._kf_arr[ty, tx], (tx, ty), (tx, ty), ids, n)
+        if ok:
+            assert np.isnan(r)
+            tot_H += np.outer(J, J)
+    assert nv >= 1 and np.all(np.isfinite(H))
+    assert np.allclose(H, tot_H, rtol=1e-12, atol=1e-300)
+    assert np.all(np.isnan(b)) and np.isnan(cost)
+
+
 # --- 3x3 solve and conditioning ---------------------------------------------
 
 def test_solve3_matches_numpy_on_spd_matrices():
