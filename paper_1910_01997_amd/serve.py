@@ -275,6 +275,65 @@ class CameraStream:
     def response_bytes(self) -> int:
         return self.dk.width * self.dk.height * 4 + self.dk.n_surfels * 8 * 4
 
+    # checkpoint / resume
+    def snapshot(self) -> Dict[str, np.ndarray]:
+        """Host copy of everything the stream's next requests depend on: the
+        surfel state (every field), the keyframe image and the neighbour-frame
+        ring as stored (f32/f16/u8), the ring's poses, which slot is the
+        oldest and whether the next request still initialises new surfels.
+        Take it with no request of the stream in flight."""
+        import torch
+        torch.cuda.synchronize()
+        st = self.dk.state
+        snap = {f"state_{f}": getattr(st, f).cpu().numpy() for f in STATE_FIELDS}
+        snap["kf_image"] = self.dk.kf_img.cpu().numpy()
+        snap["nbr_images"] = self.dk.nbr_imgs.cpu().numpy()
+        snap["R"] = self.R.copy()
+        snap["t"] = self.t.copy()
+        snap["oldest"] = np.array(self.oldest, np.int64)
+        snap["first"] = np.array(self.first, np.bool_)
+        return snap
+
+    def restore(self, snap: Dict[str, np.ndarray]) -> None:
+        """Load a snapshot taken from a stream of the same shape (image size,
+        tile size, neighbour count, storage); raises ValueError otherwise and
+        then changes nothing."""
+        import torch
+        st = self.dk.state
+        targets = [(f"state_{f}", getattr(st, f)) for f in STATE_FIELDS]
+        targets += [("kf_image", self.dk.kf_img), ("nbr_images", self.dk.nbr_imgs)]
+        for key, dst in targets:
+            if key not in snap:
+                raise ValueError(f"snapshot lacks {key}")
+            src = snap[key]
+            if tuple(src.shape) != tuple(dst.shape) or src.dtype != torch.empty(0, dtype=dst.dtype).numpy().dtype:
+                raise ValueError(f"snapshot {key}: {src.dtype}{tuple(src.shape)} does not fit "
+                                 f"{dst.dtype}{tuple(dst.shape)}")
+        if snap["R"].shape != self.R.shape or snap["t"].shape != self.t.shape:
+            raise ValueError("snapshot poses do not fit the neighbour ring")
+        torch.cuda.synchronize()
+        for key, dst in targets:
+            dst.copy_(torch.from_numpy(np.ascontiguousarray(snap[key])))
+        self.R[...] = snap["R"]
+        self.t[...] = snap["t"]
+        self.oldest = int(snap["oldest"])
+        self.first = bool(snap["first"])
+        torch.cuda.synchronize()
+
+
+STATE_FIELDS = ("inv_depth", "nx", "ny", "nz", "flags", "cost", "nvalid", "last_update")
+
+
+def save_snapshot(path, snap: Dict[str, np.ndarray]) -> None:
+    """Write a stream snapshot as an .npz archive (plain arrays, no pickles)."""
+    np.savez(path, **snap)
+
+
+def load_snapshot(path) -> Dict[str, np.ndarray]:
+    """Read a stream snapshot written by save_snapshot."""
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
 
 def respond(cs: CameraStream, torch):
     """Enqueue the copies of a stream's depth map and surfel state into its

@@ -70,3 +70,57 @@ def test_short_trace_with_binding_admission():
         assert st["count"] > 50 and st["errors"] == 0
         assert st["pool_peak_mb"] <= 6.0 + 1e-9
         assert st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_snapshot_resume_equals_uninterrupted(tmp_path):
+    """Checkpoint / resume: a stream snapshot written to .npz after its first
+    request and loaded into freshly built streams gives, for the next
+    requests, bitwise the responses of the uninterrupted run."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_01997_amd import serve
+    from paper_1910_01997_amd import surfgn as sg
+    specs = _specs()[:2]
+
+    def run(streams, frames):
+        ex = serve.HipExecutor(streams, lanes=1, iters=6)
+        srv = serve.Server(ex, pool_bytes=1 << 30, max_batch=1)
+        out = {}
+        for f in frames:
+            for s in range(len(streams)):
+                srv.submit(serve.Request(stream=s, arrival=srv.clock(), frame_index=f))
+                srv.drain()
+        assert all(r.error is None for r in srv.completed)
+        for r in srv.completed:
+            out[(r.stream, r.frame_index)] = (r.result[0].numpy().copy(), r.result[1].numpy().copy())
+        for c in ex.ctxs:
+            c.close()
+        return out
+
+    print("case snapshot after one request, resume two more", flush=True)
+    ctx = sg.Context(0)
+    streams = serve.make_streams(ctx, specs, extra=3)
+    run(streams, [0])
+    paths = []
+    for s, cs in enumerate(streams):
+        paths.append(tmp_path / f"stream{s}.npz")
+        serve.save_snapshot(paths[-1], cs.snapshot())
+    uninterrupted = run(streams, [1, 2])
+    ctx.close()
+
+    ctx2 = sg.Context(0)
+    fresh = serve.make_streams(ctx2, specs, extra=3)
+    for cs, p in zip(fresh, paths):
+        cs.restore(serve.load_snapshot(p))
+    resumed = run(fresh, [1, 2])
+    assert uninterrupted.keys() == resumed.keys()
+    for k in uninterrupted:
+        assert np.array_equal(uninterrupted[k][0], resumed[k][0]), f"depth {k}"
+        assert np.array_equal(uninterrupted[k][1], resumed[k][1]), f"surfels {k}"
+    # a snapshot of another shape is refused and changes nothing
+    before = fresh[0].snapshot()
+    with pytest.raises(ValueError):
+        fresh[0].restore(serve.load_snapshot(paths[1]))
+    after = fresh[0].snapshot()
+    assert all(np.array_equal(before[k], after[k]) for k in before)
+    ctx2.close()

@@ -164,3 +164,22 @@ def test_poisson_trace_rate_and_determinism():
     streams = np.bincount([s for _, s, _ in a], minlength=32)
     assert streams.min() > 80
     assert all(0 <= f < 4 for _, _, f in a)
+
+
+def test_snapshot_archive_round_trip(tmp_path):
+    """Stream snapshots go to .npz and back exactly, dtypes included, with no
+    pickled objects in the archive."""
+    from paper_1910_01997_amd.serve import load_snapshot, save_snapshot
+    rng = np.random.default_rng(3)
+    snap = {"state_inv_depth": rng.random(12, dtype=np.float32),
+            "state_flags": rng.integers(0, 1 << 30, 12).astype(np.int32),
+            "kf_image": rng.random((4, 6)).astype(np.float16),
+            "nbr_images": rng.integers(0, 256, (3, 4, 6)).astype(np.uint8),
+            "R": rng.random((3, 3, 3)), "t": rng.random((3, 3)),
+            "oldest": np.array(2, np.int64), "first": np.array(False)}
+    p = tmp_path / "s.npz"
+    save_snapshot(p, snap)
+    back = load_snapshot(p)
+    assert back.keys() == snap.keys()
+    for k in snap:
+        assert back[k].dtype == snap[k].dtype and np.array_equal(back[k], snap[k]), k
