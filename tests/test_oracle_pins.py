@@ -415,6 +415,117 @@ def test_huber_weight_of_a_nan_residual_is_one():
     assert np.all(np.isnan(b)) and np.isnan(cost)
 
 
+def _bilinear_grad(img, u, v):
+    """Bilinear value and exact gradient of the interpolant at (u, v) (arrays),
+    written out directly for the cross-check below."""
+    x0 = np.floor(u).astype(int)
+    y0 = np.floor(v).astype(int)
+    ax, ay = u - x0, v - y0
+    x0 = np.clip(x0, 0, img.shape[1] - 2)
+    y0 = np.clip(y0, 0, img.shape[0] - 2)
+    i00, i01 = img[y0, x0], img[y0, x0 + 1]
+    i10, i11 = img[y0 + 1, x0], img[y0 + 1, x0 + 1]
+    top = i00 + ax * (i01 - i00)
+    bot = i10 + ax * (i11 - i10)
+    return top + ay * (bot - top), (i01 - i00) + ay * ((i11 - i10) - (i01 - i00)), bot - top
+
+
+def _fit_affine_inverse_depth(K, kfimg, nbrs, Rs, ts, S, tx, ty, p, k, iters):
+    """Gauss-Newton with Huber IRLS weights on the same cost (Eq. 5), with the
+    surfel written as an affine inverse-depth map id_u = a + b dx + c dy
+    (dx, dy: pixel offsets from the centre) instead of (id_s, normal); the
+    warp's derivative in id_u by central differences."""
+    fx, fy, cx, cy = K
+    H, W = kfimg.shape
+    ys, xs = np.mgrid[S * ty:S * ty + S, S * tx:S * tx + S]
+    xs = xs.ravel().astype(np.float64)
+    ys = ys.ravel().astype(np.float64)
+    dx, dy = xs - (S * tx + (S - 1) / 2), ys - (S * ty + (S - 1) / 2)
+    r_u = np.stack([(xs - cx) / fx, (ys - cy) / fy, np.ones_like(xs)])
+    ikf = kfimg[ys.astype(int), xs.astype(int)]
+    p = np.array(p, np.float64)
+
+    def warp(f, idv):
+        Xn = Rs[f] @ (r_u / idv) + ts[f][:, None]
+        return fx * Xn[0] / Xn[2] + cx, fy * Xn[1] / Xn[2] + cy, Xn[2]
+
+    for _ in range(iters):
+        idu = p[0] + p[1] * dx + p[2] * dy
+        A = np.zeros((3, 3))
+        g = np.zeros(3)
+        for f in range(len(nbrs)):
+            u, v, z = warp(f, idu)
+            h = 1e-6 * idu
+            up, vp, _ = warp(f, idu + h)
+            um, vm, _ = warp(f, idu - h)
+            ok = (idu > 0) & (z > 0) & (u >= 0) & (u < W - 1) & (v >= 0) & (v < H - 1)
+            val, gx, gy = _bilinear_grad(nbrs[f], u, v)
+            r = val - ikf
+            w = np.minimum(1.0, k / np.abs(r))
+            jd = gx * (up - um) / (2 * h) + gy * (vp - vm) / (2 * h)
+            J = np.stack([jd, jd * dx, jd * dy])[:, ok]
+            A += (J * w[ok]) @ J.T
+            g += (J * w[ok]) @ r[ok]
+        p = p - np.linalg.solve(A, g)
+    return p
+
+
+def test_affine_inverse_depth_cross_check():
+    """The oracle's Gauss-Newton in (id_s, tangent normal step) and an
+    independent one in the affine inverse-depth parameterisation (a plane's
+    inverse depth is affine in the pixel, Eq. 3) converge to the same plane
+    on noisy three-frame scenes: a pin of the whole linearise-solve-update
+    path, Jacobian and Huber weights included."""
+    W, H, S = 96, 64, 16
+    K = (90.0, 90.0, 48.0, 32.0)
+    rng = np.random.default_rng(21)
+    kfimg = smooth_texture(W, H, 17, periods=(9, 30))
+    n_gt = random_unit_cap(rng, 30)
+    d = float(n_gt @ (ray(K, W / 2, H / 2) * 2.0))
+    Rs, ts, nbrs = [], [], []
+    Y, X = np.mgrid[0:H, 0:W].astype(np.float64)
+    for f in range(3):
+        R = rot(rng.normal(size=3), math.radians(1.5))
+        t = 0.12 * rng.normal(size=3) / math.sqrt(3)
+        Hinv = np.linalg.inv(plane_homography(K, R, t, n_gt, d))
+        pts = Hinv @ np.stack([X.ravel(), Y.ravel(), np.ones(X.size)])
+        img = bilinear_scipy_many(kfimg, pts[0] / pts[2], pts[1] / pts[2]).reshape(H, W)
+        nbrs.append(img + rng.normal(0.0, 0.01, size=img.shape))
+        Rs.append(R)
+        ts.append(t)
+    Rs, ts, nbrs = np.stack(Rs), np.stack(ts), np.stack(nbrs)
+    okf = oracle.OracleKeyframe(K, kfimg, nbrs, Rs, ts, S)
+    gw, gh = W // S, H // S
+    fx, fy, cx, cy = K
+    k = 9.0 / 255.0
+    checked = 0
+    for ty in range(1, gh - 1):
+        for tx in range(1, gw - 1):
+            rs = ray(K, S * tx + (S - 1) / 2, S * ty + (S - 1) / 2)
+            id0 = float(n_gt @ rs) / d * 1.02
+            n0 = rot(np.cross(n_gt, rng.normal(size=3)), math.radians(2.0)) @ n_gt
+            full = oracle.new_state(np.full(gw * gh, id0), np.tile(n0, (gw * gh, 1)))
+            oracle.optimize(okf, full, oracle.OracleParams(iters=40, huber_k=k))
+            i = ty * gw + tx
+            assert full["flags"][i] == 0
+            id1 = full["inv_depth"][i]
+            n1 = np.array([full["nx"][i], full["ny"][i], full["nz"][i]])
+            # the same start in the affine form: id_u = id_s (n . r_u) / (n . r_s)
+            c0 = float(n0 @ rs)
+            p0 = (id0, id0 * n0[0] / (fx * c0), id0 * n0[1] / (fy * c0))
+            a, b, c = _fit_affine_inverse_depth(K, kfimg, nbrs, Rs, ts, S, tx, ty, p0, k, 40)
+            # id_u = alpha . r_u: alpha is the plane's normal over its distance
+            alpha = np.array([b * fx, c * fy, a - b * fx * rs[0] - c * fy * rs[1]])
+            assert a == pytest.approx(id1, rel=1e-8)
+            assert angle_deg(alpha / np.linalg.norm(alpha), n1)[0] < 1e-5
+            # both moved off the start (2 % in depth, 2 degrees in the normal)
+            # to the noisy images' minimum, close to the true depth
+            assert abs(id1 / id0 - 1) > 1e-3 and angle_deg(n1, n0)[0] > 1e-2
+            assert abs(id1 * d / float(n_gt @ rs) - 1) < 3e-2
+            checked += 1
+    assert checked == (gw - 2) * (gh - 2)
+
+
 # --- 3x3 solve and conditioning ---------------------------------------------
 
 def test_solve3_matches_numpy_on_spd_matrices():
