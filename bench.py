@@ -136,9 +136,7 @@ def disc_leg(ctx, kfs, storage, iters, steps, with_ablation):
         ev[0].record()
         engine.disc_render(ctx, dks)
         ev[1].record()
-        for d in dks:
-            sg.sgn_disc_place(ctx.handle, d.item(), d.index_out.data_ptr(), d.capacity, pp,
-                              d.counts.data_ptr())
+        engine.disc_place(ctx, dks, pp.alpha, pp.beta, pp.spacing, wait=False)
         ev[2].record()
         counts = torch.stack([d.counts for d in dks]).cpu().numpy()
         for d, c in zip(dks, counts):

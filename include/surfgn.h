@@ -333,6 +333,20 @@ sgn_status sgn_disc_place(sgn_ctx* ctx, const sgn_disc_item* item, const int32_t
                           int32_t capacity, const sgn_disc_place_params* params,
                           int32_t* counts_out);
 
+/* sgn_disc_place for n keyframes at once (Surfel Initialization section):
+ * three launches for the whole batch instead of three per keyframe, with
+ * the same results as n calls in any order (keyframes share nothing).
+ * items[i], index_maps[i] (device int32 [height * width]), capacities[i] and
+ * counts_outs[i] (device int32[2]) are keyframe i's arguments of
+ * sgn_disc_place; the three arrays of pointers and counts are host memory
+ * read during the call; params apply to every keyframe.  The context's
+ * scratch holds one byte per candidate of the whole batch.  Errors: as
+ * sgn_disc_place for any keyframe (nothing enqueued), SGN_E_INVALID for
+ * n < 1 or a null array. */
+sgn_status sgn_disc_place_batch(sgn_ctx* ctx, const sgn_disc_item* items, int32_t n,
+                                const int32_t* const* index_maps, const int32_t* capacities,
+                                const sgn_disc_place_params* params, int32_t* const* counts_outs);
+
 /* Surfel reference-frame change (Eq. 10) for disc surfels, which stay discs:
  * a usable surfel of src (no DEGENERATE or UNINIT flag, id_s > 0) moves to
  * p' = R (r_s / id_s) + t with n' = R n (pose: X_dst = R X_src + t, host

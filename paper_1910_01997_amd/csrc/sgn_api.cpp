@@ -890,46 +890,78 @@ sgn_status sgn_disc_render(sgn_ctx* c, const sgn_disc_item* item, float* inv_dep
     return sgn_disc_render_batch(c, item, 1, &inv_depth_out, &index_out);
 }
 
-sgn_status sgn_disc_place(sgn_ctx* c, const sgn_disc_item* item, const int32_t* index_map,
-                          int32_t capacity, const sgn_disc_place_params* pp, int32_t* counts_out) {
+sgn_status sgn_disc_place_batch(sgn_ctx* c, const sgn_disc_item* items, int32_t n,
+                                const int32_t* const* index_maps, const int32_t* capacities,
+                                const sgn_disc_place_params* pp, int32_t* const* counts_outs) {
     if (!c) return fail(SGN_E_INVALID, "null context");
-    sgn_status st = check_disc_item(item, false);
-    if (st) return st;
-    if (!index_map || !pp || !counts_out) return fail(SGN_E_INVALID, "null argument");
-    if (!item->ux || !item->uy) return fail(SGN_E_INVALID, "null centre array");
-    st = check_surfels(&item->surfels);
-    if (st) return st;
-    if (capacity < item->count) return fail(SGN_E_INVALID, "capacity below the surfel count");
+    if (n < 1 || !items || !index_maps || !capacities || !pp || !counts_outs)
+        return fail(SGN_E_INVALID, "empty batch or null argument");
     if (!(pp->alpha > 0.f) || !(pp->alpha <= 4.f)) return fail(SGN_E_INVALID, "alpha must be in (0, 4]");
     if (!(pp->beta > 0.f) || !(pp->beta <= 4.f)) return fail(SGN_E_INVALID, "beta must be in (0, 4]");
     if (pp->spacing < 1 || pp->spacing > 1024) return fail(SGN_E_INVALID, "spacing must be in [1, 1024]");
+    std::vector<DiscPlaceArgs> tab(n);
+    int64_t total_cands = 0, total_init = 0;
+    for (int i = 0; i < n; ++i) {
+        const sgn_disc_item* item = &items[i];
+        sgn_status st = check_disc_item(item, false);
+        if (st) return st;
+        if (!index_maps[i] || !counts_outs[i]) return fail(SGN_E_INVALID, "null argument");
+        if (!item->ux || !item->uy) return fail(SGN_E_INVALID, "null centre array");
+        st = check_surfels(&item->surfels);
+        if (st) return st;
+        if (capacities[i] < item->count) return fail(SGN_E_INVALID, "capacity below the surfel count");
+        const int W = item->kf.kf.width, H = item->kf.kf.height, sp = pp->spacing;
+        const int cand_x = W > sp / 2 ? (W - sp / 2 + sp - 1) / sp : 0;
+        const int cand_y = H > sp / 2 ? (H - sp / 2 + sp - 1) / sp : 0;
+        DiscPlaceArgs& a = tab[i];
+        a.inv_depth = item->surfels.inv_depth;
+        a.nx = item->surfels.nx; a.ny = item->surfels.ny; a.nz = item->surfels.nz;
+        a.flags = item->surfels.flags;
+        a.cost = item->surfels.cost;
+        a.nvalid = item->surfels.nvalid;
+        a.last_update = item->surfels.last_update;
+        a.ux = item->ux; a.uy = item->uy;
+        a.index_map = index_maps[i];
+        a.first = item->count;
+        a.room = capacities[i] - item->count;
+        a.width = W; a.height = H; a.spacing = sp;
+        a.cand_x = cand_x; a.cand_y = cand_y;
+        a.radius = item->radius; a.alpha = pp->alpha; a.beta = pp->beta;
+        a.fx = (float)item->kf.K.fx; a.fy = (float)item->kf.K.fy;
+        a.cx = (float)item->kf.K.cx; a.cy = (float)item->kf.K.cy;
+        a.counts = counts_outs[i];
+        a.cand_base = (int32_t)total_cands;
+        a.init_base = (int32_t)total_init;
+        const int64_t cands = (int64_t)cand_x * cand_y;
+        total_cands += cands;
+        total_init += std::min<int64_t>(a.room, cands);
+        if (total_cands > (int64_t)INT32_MAX / 2) return fail(SGN_E_UNSUPPORTED, "too many candidates in one batch");
+    }
     SGN_HIP(hipSetDevice(c->device));
-    const int W = item->kf.kf.width, H = item->kf.kf.height, sp = pp->spacing;
-    const int cand_x = W > sp / 2 ? (W - sp / 2 + sp - 1) / sp : 0;
-    const int cand_y = H > sp / 2 ? (H - sp / 2 + sp - 1) / sp : 0;
-    st = ensure_scratch(c, (size_t)cand_x * (size_t)cand_y + 256);
+    sgn_status st = ensure_scratch(c, (size_t)total_cands + 256);
     if (st) return st;
-    DiscPlaceArgs a{};
-    a.inv_depth = item->surfels.inv_depth;
-    a.nx = item->surfels.nx; a.ny = item->surfels.ny; a.nz = item->surfels.nz;
-    a.flags = item->surfels.flags;
-    a.cost = item->surfels.cost;
-    a.nvalid = item->surfels.nvalid;
-    a.last_update = item->surfels.last_update;
-    a.ux = item->ux; a.uy = item->uy;
-    a.index_map = index_map;
-    a.first = item->count;
-    a.room = capacity - item->count;
-    a.width = W; a.height = H; a.spacing = sp;
-    a.cand_x = cand_x; a.cand_y = cand_y;
-    a.radius = item->radius; a.alpha = pp->alpha; a.beta = pp->beta;
-    a.fx = (float)item->kf.K.fx; a.fy = (float)item->kf.K.fy;
-    a.cx = (float)item->kf.K.cx; a.cy = (float)item->kf.K.cy;
-    a.cand_flag = (uint8_t*)c->scratch;
-    a.counts = counts_out;
-    hipError_t e = launch_disc_place(a, c->stream);
+    for (int i = 0; i < n; ++i) tab[i].cand_flag = (uint8_t*)c->scratch + tab[i].cand_base;
+    // the table goes through the staging ring into the device table
+    const size_t bytes = sizeof(DiscPlaceArgs) * (size_t)n;
+    st = ensure_table(c, bytes);
+    if (st) return st;
+    const int slot = c->ring_next;
+    c->ring_next = (c->ring_next + 1) % kRingSlots;
+    if (c->ring_used[slot]) SGN_HIP(hipEventSynchronize(c->ring_ev[slot]));
+    std::memcpy(c->host_ring[slot], tab.data(), bytes);
+    SGN_HIP(hipMemcpyAsync(c->dev_table, c->host_ring[slot], bytes, hipMemcpyHostToDevice, c->stream));
+    SGN_HIP(hipEventRecord(c->ring_ev[slot], c->stream));
+    c->ring_used[slot] = true;
+    hipError_t e = launch_disc_place((const DiscPlaceArgs*)c->dev_table, n, (int)total_cands, (int)total_init,
+                                     c->stream);
     if (e != hipSuccess) return hip_fail(e, "disc placement launch");
     return SGN_OK;
+}
+
+sgn_status sgn_disc_place(sgn_ctx* c, const sgn_disc_item* item, const int32_t* index_map,
+                          int32_t capacity, const sgn_disc_place_params* pp, int32_t* counts_out) {
+    if (!item) return fail(SGN_E_INVALID, "null disc item");
+    return sgn_disc_place_batch(c, item, 1, &index_map, &capacity, pp, &counts_out);
 }
 
 sgn_status sgn_disc_transfer(sgn_ctx* c, const sgn_disc_item* src, const sgn_pose* pose,

@@ -203,8 +203,14 @@ struct DiscPlaceArgs {
     float fx, fy, cx, cy;
     uint8_t* cand_flag;           // scratch [cand_x * cand_y]
     int32_t* counts;              // device [2]: placed, qualifying
+    int32_t cand_base;            // candidates of the table's earlier keyframes
+    int32_t init_base;            // new-surfel slots (min(room, candidates)) of earlier keyframes
 };
-hipError_t launch_disc_place(const DiscPlaceArgs& a, hipStream_t s);
+// Placement for a device table of n_items keyframes: search (one wavefront
+// per candidate), compaction (one workgroup per keyframe), initialisation
+// (one wavefront per new-surfel slot).
+hipError_t launch_disc_place(const DiscPlaceArgs* table, int n_items, int total_cands, int total_init,
+                             hipStream_t s);
 // Eq. 10 for disc surfels: each usable source surfel moves to p' = R p + t,
 // n' = R n, and is re-centred at K_dst pi(p'); those landing in the
 // destination image are written in source order.

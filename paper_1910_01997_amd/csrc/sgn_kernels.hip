@@ -1995,16 +1995,40 @@ __global__ __launch_bounds__(256) void disc_resolve_kernel(const DiscRenderItem*
     }
 }
 
+// Placement runs over a table of keyframes: candidates and new surfels are
+// numbered keyframe after keyframe (cand_base, init_base); the entry owning
+// number g is the last whose base is <= g (entries with none share the next
+// base and are never the last).
+__device__ __forceinline__ int place_entry_of_cand(const DiscPlaceArgs* tab, int n, int g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].cand_base <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+__device__ __forceinline__ int place_entry_of_init(const DiscPlaceArgs* tab, int n, int g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].init_base <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // The search for empty areas (Surfel Initialization section): one wavefront
 // per lattice candidate u_ns = (spacing/2 + i spacing, spacing/2 + j
 // spacing), its lanes sharing the window of pixels within alpha r; the
 // candidate qualifies when no non-empty pixel of the index map lies within
 // alpha r (integer squared distance against (alpha r)^2 in double).
-__global__ __launch_bounds__(kBlockThreads) void disc_search_kernel(DiscPlaceArgs a) {
+__global__ __launch_bounds__(kBlockThreads) void disc_search_kernel(const DiscPlaceArgs* __restrict__ tab,
+                                                                    int n_items, int total) {
     const int lane = threadIdx.x & (kWaveSize - 1);
-    const int c = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlockThreads / kWaveSize) +
+    const int g = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlockThreads / kWaveSize) +
                                                  (int)(threadIdx.x >> 6));
-    if (c >= a.cand_x * a.cand_y) return;
+    if (g >= total) return;
+    const DiscPlaceArgs& a = tab[place_entry_of_cand(tab, n_items, g)];
+    const int c = g - a.cand_base;
     const int cx = a.spacing / 2 + (c % a.cand_x) * a.spacing;
     const int cy = a.spacing / 2 + (c / a.cand_x) * a.spacing;
     const double ar = (double)a.alpha * (double)a.radius;
@@ -2030,8 +2054,10 @@ __global__ __launch_bounds__(kBlockThreads) void disc_search_kernel(DiscPlaceArg
 
 // Placement: the qualifying candidates in lattice order become surfels
 // first, first + 1, ... (as many as there is room for); counts[0] = placed,
-// counts[1] = qualifying.  One workgroup scans the flags in chunks.
-__global__ __launch_bounds__(1024) void disc_compact_kernel(DiscPlaceArgs a) {
+// counts[1] = qualifying.  One workgroup per keyframe scans its flags in
+// chunks.
+__global__ __launch_bounds__(1024) void disc_compact_kernel(const DiscPlaceArgs* __restrict__ tab) {
+    const DiscPlaceArgs& a = tab[blockIdx.x];
     __shared__ int s_wave[1024 / kWaveSize + 1];
     const int n = a.cand_x * a.cand_y;
     const int lane = threadIdx.x & (kWaveSize - 1);
@@ -2083,11 +2109,14 @@ __device__ __forceinline__ int wave_min(int v) {
 // index each round); id = mean of Eq. 3 of their planes at the new ray,
 // n = mean of their normals sign-aligned to the first, renormalised; none
 // usable: UNINIT with id 0 and n = (0, 0, -1).
-__global__ __launch_bounds__(kWaveSize) void disc_init_kernel(DiscPlaceArgs a) {
+__global__ __launch_bounds__(kWaveSize) void disc_init_kernel(const DiscPlaceArgs* __restrict__ tab,
+                                                              int n_items) {
     // the window's surfel indices (those within beta r, below `first`), or -1
     __shared__ int s_win[(2 * kDiscMaxWindowReach + 1) * (2 * kDiscMaxWindowReach + 1)];
     const int lane = threadIdx.x;
-    const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
+    const int g = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
+    const DiscPlaceArgs& a = tab[place_entry_of_init(tab, n_items, g)];
+    const int w = g - a.init_base;
     if (w >= a.counts[0]) return;
     const int i = a.first + w;
     const int cx = (int)a.ux[i], cy = (int)a.uy[i];
@@ -2266,13 +2295,14 @@ hipError_t launch_disc_render(const DiscRenderItem* table, int n_items, int tota
     return hipGetLastError();
 }
 
-hipError_t launch_disc_place(const DiscPlaceArgs& a, hipStream_t s) {
-    const int n = a.cand_x * a.cand_y;
+hipError_t launch_disc_place(const DiscPlaceArgs* table, int n_items, int total_cands, int total_init,
+                             hipStream_t s) {
     const int waves = kBlockThreads / kWaveSize;
-    if (n > 0) disc_search_kernel<<<(n + waves - 1) / waves, kBlockThreads, 0, s>>>(a);
-    disc_compact_kernel<<<1, 1024, 0, s>>>(a);
-    const int most = std::min(a.room, n);
-    if (most > 0) disc_init_kernel<<<most, kWaveSize, 0, s>>>(a);
+    if (total_cands > 0)
+        disc_search_kernel<<<(total_cands + waves - 1) / waves, kBlockThreads, 0, s>>>(table, n_items,
+                                                                                        total_cands);
+    disc_compact_kernel<<<n_items, 1024, 0, s>>>(table);
+    if (total_init > 0) disc_init_kernel<<<total_init, kWaveSize, 0, s>>>(table, n_items);
     return hipGetLastError();
 }
 

@@ -206,6 +206,27 @@ def disc_render(ctx: sg.Context, dks: Sequence[DiscKeyframe]):
     return items
 
 
+def disc_place(ctx: sg.Context, dks: Sequence[DiscKeyframe], alpha: float = 1.0, beta: float = 2.0,
+               spacing: int = 0, wait: bool = True):
+    """Empty-area search and placement for several keyframes in one batch,
+    each from its current index map (the same results as DiscKeyframe.place
+    one by one).  With wait, synchronises once and returns the (placed,
+    qualifying) pairs, updating each keyframe's count."""
+    sp = int(spacing) if spacing else int(np.floor(dks[0].radius * np.sqrt(2.0)))
+    items = sg.disc_array([d.item() for d in dks])
+    sg.sgn_disc_place_batch(ctx.handle, items, len(dks), [d.index_out.data_ptr() for d in dks],
+                            [d.capacity for d in dks], sg.sgn_disc_place_params(float(alpha), float(beta), sp),
+                            [d.counts.data_ptr() for d in dks])
+    if not wait:
+        return None
+    counts = torch.stack([d.counts for d in dks]).cpu().tolist()
+    out = []
+    for d, (placed, found) in zip(dks, counts):
+        d.count += int(placed)
+        out.append((int(placed), int(found)))
+    return out
+
+
 def disc_update(ctx: sg.Context, dks: Sequence[DiscKeyframe], prm: sg.sgn_params):
     """Gauss-Newton over the disc surfels of several keyframes in one launch."""
     items = sg.disc_array([d.item() for d in dks])

@@ -37,7 +37,7 @@ EXPORTED = [
     "sgn_optimize_keyframe", "sgn_render_inverse_depth", "sgn_optimize_batch", "sgn_autotune",
     "sgn_quantize", "sgn_last_kernel_ms", "sgn_device_info", "sgn_status_str", "sgn_last_error",
     "sgn_version", "sgn_transfer_surfels", "sgn_disc_optimize", "sgn_disc_render", "sgn_disc_place",
-    "sgn_recent_kernel_ms", "sgn_disc_transfer", "sgn_disc_render_batch",
+    "sgn_recent_kernel_ms", "sgn_disc_transfer", "sgn_disc_render_batch", "sgn_disc_place_batch",
 ]
 
 
@@ -159,6 +159,10 @@ def lib():
         L.sgn_disc_place.restype = st
         L.sgn_disc_place.argtypes = [vp, C.POINTER(sgn_disc_item), vp, C.c_int32,
                                      C.POINTER(sgn_disc_place_params), vp]
+        L.sgn_disc_place_batch.restype = st
+        L.sgn_disc_place_batch.argtypes = [vp, C.POINTER(sgn_disc_item), C.c_int32, C.POINTER(C.c_void_p),
+                                           C.POINTER(C.c_int32), C.POINTER(sgn_disc_place_params),
+                                           C.POINTER(C.c_void_p)]
         L.sgn_disc_render_batch.restype = st
         L.sgn_disc_render_batch.argtypes = [vp, C.POINTER(sgn_disc_item), C.c_int32,
                                             C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]
@@ -272,6 +276,15 @@ def sgn_disc_transfer(ctx, src: sgn_disc_item, pose: sgn_pose, dst: sgn_disc_ite
     check(lib().sgn_disc_transfer(C.c_void_p(ctx), C.byref(src), C.byref(pose), C.byref(dst),
                                   int(capacity), C.c_void_p(counts_ptr), C.c_void_p(src_index_ptr or None)),
           "sgn_disc_transfer")
+
+
+def sgn_disc_place_batch(ctx, items, n: int, index_map_ptrs: Sequence[int], capacities: Sequence[int],
+                         params: sgn_disc_place_params, counts_ptrs: Sequence[int]):
+    maps = (C.c_void_p * int(n))(*[int(p) if p else None for p in index_map_ptrs])
+    caps = (C.c_int32 * int(n))(*[int(c) for c in capacities])
+    cnts = (C.c_void_p * int(n))(*[int(p) if p else None for p in counts_ptrs])
+    check(lib().sgn_disc_place_batch(C.c_void_p(ctx), items, int(n), maps, caps, C.byref(params), cnts),
+          "sgn_disc_place_batch")
 
 
 def sgn_disc_render_batch(ctx, items, n: int, inv_depth_ptrs: Sequence[int],

@@ -319,6 +319,42 @@ def test_disc_two_keyframes_chained(ctx):
     assert (ind >= 0).mean() > 0.8
 
 
+def test_disc_place_batch_equals_one_by_one(ctx):
+    """Batched placement (three launches for several keyframes: one without
+    surfels, whose whole lattice qualifies, and one without room) equals
+    per-keyframe placement: counts, centres and state, bitwise."""
+    sg, engine = _mods()
+    print("case disc place batch", flush=True)
+
+    def build():
+        dks = []
+        for i, (w, h) in enumerate([(320, 240), (200, 130), (320, 240), (320, 240)]):
+            kf, discs = _scene(w, h, 3, seed=90 + i, n_holes=4, hole_frac=(0.2, 0.3))
+            if i == 2:
+                z = np.zeros(0, np.float32)
+                dks.append(engine.DiscKeyframe(ctx, kf.kf_image, kf.nbr_images, kf.R, kf.t, kf.K, 10.0,
+                                               z, z, z, np.zeros((0, 3), np.float32), capacity=500))
+            else:
+                room = 0 if i == 3 else 300
+                dks.append(engine.DiscKeyframe.from_scene(ctx, kf, discs, capacity=discs.ux.size + room))
+        for d in dks:
+            d.render()
+        return dks
+
+    ref = build()
+    ref_counts = [d.place(alpha=1.0, beta=2.0) for d in ref]
+    got = build()
+    got_counts = engine.disc_place(ctx, got, 1.0, 2.0)
+    assert got_counts == ref_counts
+    assert ref_counts[0][0] > 0 and ref_counts[2][0] > 100
+    assert ref_counts[3][0] == 0 and ref_counts[3][1] > 0
+    for a, b in zip(ref, got):
+        assert a.count == b.count
+        (ua, va), (ub, vb) = a.centres(), b.centres()
+        assert np.array_equal(ua, ub) and np.array_equal(va, vb)
+        _state_equal(a.state_host(), b.state_host())
+
+
 def test_disc_render_batch_equals_one_by_one(ctx):
     """The batched render (one pass over several keyframes, an empty one in
     the middle, one without an index output) equals per-keyframe renders."""
