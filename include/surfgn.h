@@ -277,7 +277,8 @@ typedef struct {
 /* Gauss-Newton over the disc surfels of n_items keyframes (Proposed
  * Approach section, Eq. 5-9): as sgn_optimize_batch, with each surfel's
  * cost summed over the pixels of its disc (Eq. 5 with u in s read as Eq. 4).
- * One wavefront per surfel; per-surfel results do not depend on the batch.
+ * Two surfels per wavefront for f16 and u8 images, one for f32; per-surfel
+ * results do not depend on the batch.
  * params as for tiles (beta_r unused).  Asynchronous on the context's
  * stream; sgn_last_kernel_ms times the Gauss-Newton kernel.  Errors: invalid
  * items or params (SGN_E_INVALID, nothing enqueued). */

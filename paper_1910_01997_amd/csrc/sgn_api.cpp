@@ -482,8 +482,9 @@ sgn_status check_disc_item(const sgn_disc_item* it, bool need_nbr) {
     return SGN_OK;
 }
 
-// Disc surfels: descriptor table (one KfDev per keyframe, items = surfels),
-// frame constants, then one wavefront per surfel.
+// Disc surfels: descriptor table (one KfDev per keyframe; its items are runs
+// of disc_surfels_per_wave(dtype) surfels), frame constants, then one
+// wavefront per item.
 sgn_status run_disc_batch(sgn_ctx* c, const sgn_disc_item* items, int n, const sgn_params* prm) {
     if (n < 1) return fail(SGN_E_INVALID, "empty batch");
     if (!items) return fail(SGN_E_INVALID, "null items");

@@ -238,16 +238,24 @@ _STATE_FIELDS = ("inv_depth", "nx", "ny", "nz", "flags", "cost", "nvalid", "last
 
 
 class StatePool:
-    """Moves the surfel state of many keyframes into one allocation per field
-    (each keyframe keeps a view), so that snapshots and restores of a whole
-    batch are one copy per field."""
+    """Moves the surfel state of many keyframes into one allocation (each
+    field a contiguous run of it, each keyframe a view into every field), so
+    that a snapshot or a restore of a whole batch is one copy."""
 
     def __init__(self, dks: Sequence[DeviceKeyframe]):
         counts = [d.n_surfels for d in dks]
         total = sum(counts)
         first = dks[0].state
-        self.fields = {f: torch.empty(total, dtype=getattr(first, f).dtype,
-                                      device=getattr(first, f).device) for f in _STATE_FIELDS}
+        dev = first.inv_depth.device
+        # every field is 4 bytes per surfel: one float32 buffer, the integer
+        # fields as int32 views of their runs
+        self.buffer = torch.empty(len(_STATE_FIELDS) * total, dtype=torch.float32, device=dev)
+        self.total = total
+        self.fields = {}
+        for k, f in enumerate(_STATE_FIELDS):
+            run = self.buffer[k * total:(k + 1) * total]
+            dt = getattr(first, f).dtype
+            self.fields[f] = run if dt == torch.float32 else run.view(dt)
         off = 0
         for d, m in zip(dks, counts):
             views = {f: t[off:off + m] for f, t in self.fields.items()}
@@ -257,8 +265,16 @@ class StatePool:
             off += m
 
     def snapshot(self):
-        return {f: t.clone() for f, t in self.fields.items()}
+        return self.buffer.clone()
 
     def restore(self, snap, fields=("inv_depth", "nx", "ny", "nz", "flags")):
+        """Copy the given fields back from a snapshot: the leading run of
+        fields (the default: the state the update reads) in one copy."""
+        k = len(fields)
+        if tuple(fields) == _STATE_FIELDS[:k]:
+            self.buffer[:k * self.total].copy_(snap[:k * self.total], non_blocking=True)
+            return
         for f in fields:
-            self.fields[f].copy_(snap[f], non_blocking=True)
+            i = _STATE_FIELDS.index(f)
+            self.buffer[i * self.total:(i + 1) * self.total].copy_(
+                snap[i * self.total:(i + 1) * self.total], non_blocking=True)
