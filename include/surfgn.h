@@ -293,7 +293,8 @@ sgn_status sgn_disc_optimize(sgn_ctx* ctx, const sgn_disc_item* items, int32_t n
  * inv_depth_out: device float [height * width] (row-major, width per row,
  * 0 = no measurement); index_out: device int32 of the same shape (winning
  * surfel, -1 = none) or NULL.  Reads only the item's surfels, intrinsics and
- * image size.  The context keeps a scratch buffer of 12 bytes per pixel. */
+ * image size.  The context keeps a scratch buffer of 84 bytes per surfel
+ * and 8 bytes per 16 x 16-pixel tile. */
 sgn_status sgn_disc_render(sgn_ctx* ctx, const sgn_disc_item* item, float* inv_depth_out,
                            int32_t* index_out);
 

@@ -78,8 +78,8 @@ struct sgn_ctx {
     bool use_graphs = true;
     std::map<GraphKey, hipGraphExec_t> graphs;
     // scratch of re-gridding (12 bytes per destination tile) and of the disc
-    // render and placement (12 bytes per pixel, one byte per candidate),
-    // grown on demand
+    // render (84 bytes per surfel, 8 per 16 x 16 render tile) and placement
+    // (one byte per candidate), grown on demand
     void* scratch = nullptr;
     size_t scratch_cap = 0;
 };
@@ -840,7 +840,7 @@ sgn_status sgn_disc_render_batch(sgn_ctx* c, const sgn_disc_item* items, int32_t
     if (!c) return fail(SGN_E_INVALID, "null context");
     if (n < 1 || !items || !inv_depth_outs) return fail(SGN_E_INVALID, "empty batch or null array");
     std::vector<DiscRenderItem> tab(n);
-    int64_t total_surfels = 0, total_pixels = 0;
+    int64_t total_surfels = 0, total_pixels = 0, total_tiles = 0;
     for (int i = 0; i < n; ++i) {
         const sgn_disc_item* it = &items[i];
         sgn_status st = check_disc_item(it, false);
@@ -859,12 +859,21 @@ sgn_status sgn_disc_render_batch(sgn_ctx* c, const sgn_disc_item* items, int32_t
         r.pixel_base = total_pixels;
         r.radius = it->radius;
         r.fx = it->kf.K.fx; r.fy = it->kf.K.fy; r.cx = it->kf.K.cx; r.cy = it->kf.K.cy;
+        r.tiles_x = (r.width + kRenderTile - 1) / kRenderTile;
+        r.tile_base = (int32_t)total_tiles;
         total_surfels += it->count;
         total_pixels += (int64_t)r.width * r.height;
+        total_tiles += (int64_t)r.tiles_x * ((r.height + kRenderTile - 1) / kRenderTile);
     }
-    if (total_surfels > (int64_t)INT32_MAX / 2) return fail(SGN_E_UNSUPPORTED, "too many surfels in one batch");
+    if (total_surfels > (int64_t)INT32_MAX / (2 * kDiscMaxTilesPerSurfel) || total_tiles > (int64_t)INT32_MAX / 2)
+        return fail(SGN_E_UNSUPPORTED, "too many surfels or pixels in one batch");
     SGN_HIP(hipSetDevice(c->device));
-    sgn_status st = ensure_scratch(c, (size_t)total_pixels * (sizeof(unsigned long long) + sizeof(int32_t)));
+    // scratch: raster records, then the tile counts, starts, scan sums and lists
+    const size_t n_blocks = (size_t)((total_tiles + 1023) / 1024);
+    const size_t rec_bytes = sizeof(DiscRaster) * (size_t)total_surfels;
+    const size_t int_words = (size_t)total_tiles + ((size_t)total_tiles + 1) + n_blocks +
+                             (size_t)kDiscMaxTilesPerSurfel * (size_t)total_surfels;
+    sgn_status st = ensure_scratch(c, rec_bytes + sizeof(int32_t) * int_words + 256);
     if (st) return st;
     // the table goes through the staging ring into the device table
     const size_t bytes = sizeof(DiscRenderItem) * (size_t)n;
@@ -877,10 +886,14 @@ sgn_status sgn_disc_render_batch(sgn_ctx* c, const sgn_disc_item* items, int32_t
     SGN_HIP(hipMemcpyAsync(c->dev_table, c->host_ring[slot], bytes, hipMemcpyHostToDevice, c->stream));
     SGN_HIP(hipEventRecord(c->ring_ev[slot], c->stream));
     c->ring_used[slot] = true;
-    unsigned long long* key = (unsigned long long*)c->scratch;
-    int32_t* idx = (int32_t*)((char*)c->scratch + (size_t)total_pixels * sizeof(unsigned long long));
-    hipError_t e = launch_disc_render((const DiscRenderItem*)c->dev_table, n, (int)total_surfels, total_pixels,
-                                      key, idx, c->stream);
+    DiscRenderScratch w;
+    w.rec = (DiscRaster*)c->scratch;
+    w.count = (int32_t*)((char*)c->scratch + rec_bytes);
+    w.start = w.count + total_tiles;
+    w.block_sum = w.start + total_tiles + 1;
+    w.list = w.block_sum + n_blocks;
+    hipError_t e = launch_disc_render((const DiscRenderItem*)c->dev_table, n, (int)total_surfels,
+                                      (int)total_tiles, w, c->stream);
     if (e != hipSuccess) return hip_fail(e, "disc render launch");
     return SGN_OK;
 }

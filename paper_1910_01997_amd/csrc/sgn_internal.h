@@ -176,12 +176,29 @@ struct DiscRenderItem {
     int32_t count, width, height, surfel_base;
     int64_t pixel_base;
     float radius;
-    int32_t pad;
+    int32_t tiles_x;              // render tiles per row (kRenderTile pixels square)
     double fx, fy, cx, cy;
+    int32_t tile_base;            // render tiles of the table's earlier keyframes
+    int32_t pad;
 };
-hipError_t launch_disc_render(const DiscRenderItem* table, int n_items, int total_surfels,
-                              int64_t total_pixels, unsigned long long* key, int32_t* idx,
-                              hipStream_t s);
+constexpr int kRenderTile = 16;
+// Per usable surfel: centre, normal and the denominator of Eq. 3, in double.
+struct DiscRaster {
+    double cx, cy, n0, n1, n2, den;
+};
+// The render's scratch: raster records [surfels], tile counts [tiles], list
+// starts [tiles + 1], scan block sums [ceil(tiles / 1024)], tile lists
+// [kDiscMaxTilesPerSurfel * surfels].
+constexpr int kDiscMaxTilesPerSurfel = 9;     // a box of <= 2 r + 1 <= 25 pixels meets <= 3 x 3 tiles
+struct DiscRenderScratch {
+    DiscRaster* rec;
+    int32_t* count;
+    int32_t* start;
+    int32_t* block_sum;
+    int32_t* list;
+};
+hipError_t launch_disc_render(const DiscRenderItem* table, int n_items, int total_surfels, int total_tiles,
+                              const DiscRenderScratch& w, hipStream_t s);
 // The search for empty areas on the lattice (spacing/2 + i spacing, ...),
 // placement of the qualifying candidates as surfels first .. and their
 // neighbour initialisation from the index map.

@@ -1895,23 +1895,21 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
 }
 
 // Depth-buffered render (Inverse Depth Calculation section): every usable
-// surfel writes Eq. 3 into the pixels of its disc, the closest (largest
-// id_u) wins and equal values go to the lower index.  Pass 0 takes the
-// maximum of the double bit patterns (positive doubles order like their
-// bits), pass 1 the lowest index among the surfels that reach it, and the
-// resolve step writes the outputs.  id_u is evaluated in double in the
-// printed form of Eq. 3, id_u = (r_u . n) / ((r_s / id_s) . n).
-__global__ void disc_clear_kernel(unsigned long long* __restrict__ key, int32_t* __restrict__ idx,
-                                  int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        key[i] = 0ull;
-        idx[i] = 0x7fffffff;
-    }
-}
+// surfel (no DEGENERATE or UNINIT flag, finite centre, plane not through its
+// centre ray) writes Eq. 3 into the pixels of its disc; the closest (largest
+// id_u > 0) wins and equal values go to the lower index.  id_u is evaluated
+// in double in the printed form of Eq. 3, id_u = (r_u . n) / ((r_s / id_s) . n).
+//
+// The render works in screen tiles of kRenderTile x kRenderTile pixels.  The
+// usable surfels are binned to the tiles their disc's bounding box meets (a
+// count, an exclusive scan of the counts over the tiles of the whole batch,
+// a fill); then one workgroup per tile gives each pixel to a thread, which
+// walks the tile's list keeping the largest value and the lowest index that
+// reaches it.  The outcome does not depend on the list order, so the fill's
+// atomics leave it deterministic, and the depth test needs no atomics.
 
 // Table entry of global surfel g (largest surfel_base <= g among entries
-// with surfels) or of global pixel p (by pixel_base).
+// with surfels) or of global tile t (by tile_base).
 __device__ __forceinline__ int render_item_of_surfel(const DiscRenderItem* tab, int n, int g) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
@@ -1920,79 +1918,154 @@ __device__ __forceinline__ int render_item_of_surfel(const DiscRenderItem* tab, 
     }
     return lo;        // entries without surfels share the next base and are never the largest
 }
-__device__ __forceinline__ int render_item_of_pixel(const DiscRenderItem* tab, int n, int64_t p) {
+__device__ __forceinline__ int render_item_of_tile(const DiscRenderItem* tab, int n, int t) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (tab[mid].pixel_base <= p) lo = mid; else hi = mid - 1;
+        if (tab[mid].tile_base <= t) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
 
+__global__ void fill_int_kernel(int32_t* __restrict__ p, int n, int32_t v) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Pass 0 counts a usable surfel in each tile its disc's bounding box meets
+// and stores its raster record; pass 1 (after the scan) writes it into those
+// tiles' lists.  One thread per surfel.
 template <int PASS>
-__global__ __launch_bounds__(kBlockThreads) void disc_scatter_kernel(const DiscRenderItem* __restrict__ tab,
-                                                                     int n_items, int total,
-                                                                     unsigned long long* __restrict__ key,
-                                                                     int32_t* __restrict__ idx) {
+__global__ __launch_bounds__(256) void disc_bin_kernel(const DiscRenderItem* __restrict__ tab, int n_items,
+                                                       int total, DiscRaster* __restrict__ rec,
+                                                       int32_t* __restrict__ count,
+                                                       const int32_t* __restrict__ start,
+                                                       int32_t* __restrict__ list) {
 #pragma clang fp contract(off)
-    const int lane = threadIdx.x & (kWaveSize - 1);
-    const int wave = threadIdx.x >> 6;
-    const int g = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlockThreads / kWaveSize) + wave);
+    const int g = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (g >= total) return;
     const DiscRenderItem& a = tab[render_item_of_surfel(tab, n_items, g)];
     const int s = g - a.surfel_base;
     if (a.flags[s] & (F_DEGENERATE | F_UNINIT)) return;
-    __shared__ int s_rows[kBlockThreads / kWaveSize][kDiscRowWords];
-    int* const row_x0 = s_rows[wave];
-    int* const row_start = s_rows[wave] + kDiscMaxRows;
+    const double cx = (double)a.ux[s], cy = (double)a.uy[s], r = (double)a.radius;
+    if (!isfinite(cx) || !isfinite(cy)) return;
     const double n0 = a.nx[s], n1 = a.ny[s], n2 = a.nz[s], ids = a.inv_depth[s];
-    const double rs0 = ((double)a.ux[s] - a.cx) / a.fx, rs1 = ((double)a.uy[s] - a.cy) / a.fy;
+    const double rs0 = (cx - a.cx) / a.fx, rs1 = (cy - a.cy) / a.fy;
     if (fabs(n0 * rs0 + n1 * rs1 + n2 * 1.0) < 1e-6) return;
-    const double ps0 = rs0 / ids, ps1 = rs1 / ids, ps2 = 1.0 / ids;
-    const double den = ps0 * n0 + ps1 * n1 + ps2 * n2;
-    wave_sync();
-    const DiscRows d = disc_rows<kWaveSize>(a.ux[s], a.uy[s], a.radius, a.width, a.height, lane, row_x0,
-                                            row_start);
-    unsigned long long* const kk = key + a.pixel_base;
-    int32_t* const ii = idx + a.pixel_base;
-    for (int k = lane; k < d.total; k += kWaveSize) {
-        int x, y;
-        disc_pixel(d, row_x0, row_start, k, x, y);
-        const double ru0 = ((double)x - a.cx) / a.fx, ru1 = ((double)y - a.cy) / a.fy;
-        const double v = (ru0 * n0 + ru1 * n1 + 1.0 * n2) / den;
-        if (!(v > 0.0) || !isfinite(v)) continue;
-        const size_t o = (size_t)y * (size_t)a.width + (size_t)x;
-        const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-        if (PASS == 0)
-            atomicMax(kk + o, bits);
-        else if (kk[o] == bits)
-            atomicMin(ii + o, s);
+    const double xlo = fmax(0.0, ceil(cx - r)), xhi = fmin((double)(a.width - 1), floor(cx + r));
+    const double ylo = fmax(0.0, ceil(cy - r)), yhi = fmin((double)(a.height - 1), floor(cy + r));
+    if (!(xlo <= xhi) || !(ylo <= yhi)) return;
+    if (PASS == 0) {
+        const double ps0 = rs0 / ids, ps1 = rs1 / ids, ps2 = 1.0 / ids;
+        rec[g] = DiscRaster{cx, cy, n0, n1, n2, ps0 * n0 + ps1 * n1 + ps2 * n2};
     }
+    const int tx0 = (int)xlo / kRenderTile, tx1 = (int)xhi / kRenderTile;
+    const int ty0 = (int)ylo / kRenderTile, ty1 = (int)yhi / kRenderTile;
+    for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) {
+            const int t = a.tile_base + ty * a.tiles_x + tx;
+            if (PASS == 0)
+                atomicAdd(count + t, 1);
+            else
+                list[start[t] + atomicSub(count + t, 1) - 1] = g;
+        }
 }
 
-// One pixel per thread; a block's first thread finds the keyframe of the
-// block's first pixel, and only threads past that keyframe search for their
-// own.  The grid-stride loop has the same bounds for every thread of a block.
-__global__ __launch_bounds__(256) void disc_resolve_kernel(const DiscRenderItem* __restrict__ tab,
-                                                           int n_items, int64_t total,
-                                                           const unsigned long long* __restrict__ key,
-                                                           const int32_t* __restrict__ idx) {
-    __shared__ int s_item;
-    for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x; p0 < total; p0 += (int64_t)gridDim.x * blockDim.x) {
-        __syncthreads();                                // the previous run's s_item is read
-        if (threadIdx.x == 0) s_item = render_item_of_pixel(tab, n_items, p0);
-        __syncthreads();
-        const int64_t p = p0 + threadIdx.x;
-        if (p >= total) continue;
-        int it = s_item;
-        if (!(p < tab[it].pixel_base + (int64_t)tab[it].width * tab[it].height))
-            it = render_item_of_pixel(tab, n_items, p);
-        const DiscRenderItem& a = tab[it];
-        const int64_t i = p - a.pixel_base;
-        const unsigned long long k = key[p];
-        a.inv_depth_out[i] = k ? (float)__longlong_as_double((long long)k) : 0.f;
-        if (a.index_out) a.index_out[i] = k ? idx[p] : -1;
+// Exclusive scan of the tile counts into start[0 .. n] (start[n] = the total):
+// blocks of 1024 scan their counts and report their sums, one block scans the
+// sums (in chunks, with a carry) and writes the total, the sums are added
+// back.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* s_w, int& block_total) {
+    const int lane = threadIdx.x & (kWaveSize - 1), wave = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < kWaveSize; o <<= 1) {
+        const int y = __shfl_up(x, o, kWaveSize);
+        if (lane >= o) x += y;
     }
+    if (lane == kWaveSize - 1) s_w[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int w = 0; w < (int)(blockDim.x / kWaveSize); ++w) {
+            const int t = s_w[w];
+            s_w[w] = acc;
+            acc += t;
+        }
+        s_w[16] = acc;
+    }
+    __syncthreads();
+    block_total = s_w[16];
+    const int ex = s_w[wave] + x - v;
+    __syncthreads();
+    return ex;
+}
+__global__ __launch_bounds__(1024) void bin_scan_block_kernel(const int32_t* __restrict__ count,
+                                                              int32_t* __restrict__ start,
+                                                              int32_t* __restrict__ block_sum, int n) {
+    __shared__ int s_w[17];
+    const int i = (int)(blockIdx.x * 1024 + threadIdx.x);
+    int tot;
+    const int ex = block_exclusive_scan(i < n ? count[i] : 0, s_w, tot);
+    if (i < n) start[i] = ex;
+    if (threadIdx.x == 0) block_sum[blockIdx.x] = tot;
+}
+__global__ __launch_bounds__(1024) void bin_scan_top_kernel(int32_t* __restrict__ block_sum, int nb,
+                                                            int32_t* __restrict__ start, int n) {
+    __shared__ int s_w[17];
+    int carry = 0;
+    for (int c0 = 0; c0 < nb; c0 += 1024) {
+        const int i = c0 + (int)threadIdx.x;
+        int tot;
+        const int ex = block_exclusive_scan(i < nb ? block_sum[i] : 0, s_w, tot);
+        if (i < nb) block_sum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) start[n] = carry;
+}
+__global__ __launch_bounds__(1024) void bin_scan_add_kernel(int32_t* __restrict__ start,
+                                                            const int32_t* __restrict__ block_sum, int n) {
+    const int i = (int)(blockIdx.x * 1024 + threadIdx.x);
+    if (i < n) start[i] += block_sum[blockIdx.x];
+}
+
+// One workgroup per tile, one thread per pixel: the largest Eq. 3 value over
+// the tile's surfels whose disc holds the pixel, and the lowest index among
+// those that reach it.
+__global__ __launch_bounds__(kRenderTile * kRenderTile) void disc_raster_kernel(
+    const DiscRenderItem* __restrict__ tab, int n_items, const DiscRaster* __restrict__ rec,
+    const int32_t* __restrict__ start, const int32_t* __restrict__ list) {
+#pragma clang fp contract(off)
+    const int t = (int)blockIdx.x;
+    const DiscRenderItem& a = tab[render_item_of_tile(tab, n_items, t)];
+    const int lt = t - a.tile_base;
+    const int ty = lt / a.tiles_x, tx = lt - ty * a.tiles_x;
+    const int x = tx * kRenderTile + (int)(threadIdx.x % kRenderTile);
+    const int y = ty * kRenderTile + (int)(threadIdx.x / kRenderTile);
+    if (x >= a.width || y >= a.height) return;
+    const double xd = (double)x, yd = (double)y, r = (double)a.radius, r2 = r * r;
+    const double ru0 = (xd - a.cx) / a.fx, ru1 = (yd - a.cy) / a.fy;
+    unsigned long long best = 0ull;
+    int who = 0x7fffffff;
+    const int k1 = start[t + 1];
+    for (int k = start[t]; k < k1; ++k) {
+        const int g = list[k];
+        const DiscRaster& q = rec[g];
+        const double dx = xd - q.cx, dy = yd - q.cy;
+        if (!(dx * dx + dy * dy < r2)) continue;
+        const double v = (ru0 * q.n0 + ru1 * q.n1 + 1.0 * q.n2) / q.den;
+        if (!(v > 0.0) || !isfinite(v)) continue;
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+        const int s = g - a.surfel_base;
+        if (bits > best) {
+            best = bits;
+            who = s;
+        } else if (bits == best && s < who) {
+            who = s;
+        }
+    }
+    const size_t o = (size_t)y * (size_t)a.width + (size_t)x;
+    a.inv_depth_out[o] = best ? (float)__longlong_as_double((long long)best) : 0.f;
+    if (a.index_out) a.index_out[o] = best ? who : -1;
 }
 
 // Placement runs over a table of keyframes: candidates and new surfels are
@@ -2278,20 +2351,22 @@ hipError_t launch_disc_gn(int dtype, const BatchHeader* hdr, int total_items, hi
     return hipGetLastError();
 }
 
-hipError_t launch_disc_render(const DiscRenderItem* table, int n_items, int total_surfels,
-                              int64_t total_pixels, unsigned long long* key, int32_t* idx,
-                              hipStream_t s) {
-    const int fill = (int)std::min<int64_t>((total_pixels + 255) / 256, 8192);
-    disc_clear_kernel<<<fill, 256, 0, s>>>(key, idx, total_pixels);
-    if (total_surfels > 0) {
-        const int waves = kBlockThreads / kWaveSize;
-        const dim3 grid((total_surfels + waves - 1) / waves);
-        disc_scatter_kernel<0><<<grid, kBlockThreads, 0, s>>>(table, n_items, total_surfels, key, idx);
-        disc_scatter_kernel<1><<<grid, kBlockThreads, 0, s>>>(table, n_items, total_surfels, key, idx);
-    }
-    // one pixel per thread (up to 2^20 blocks, then a grid-stride loop)
-    const int resolve_blocks = (int)std::min<int64_t>((total_pixels + 255) / 256, 1 << 20);
-    disc_resolve_kernel<<<std::max(resolve_blocks, 1), 256, 0, s>>>(table, n_items, total_pixels, key, idx);
+hipError_t launch_disc_render(const DiscRenderItem* table, int n_items, int total_surfels, int total_tiles,
+                              const DiscRenderScratch& w, hipStream_t s) {
+    const int nb = (total_tiles + 1023) / 1024;
+    fill_int_kernel<<<std::min((total_tiles + 255) / 256, 4096), 256, 0, s>>>(w.count, total_tiles, 0);
+    const int sblocks = (total_surfels + 255) / 256;
+    if (total_surfels > 0)
+        disc_bin_kernel<0><<<sblocks, 256, 0, s>>>(table, n_items, total_surfels, w.rec, w.count, w.start,
+                                                   w.list);
+    bin_scan_block_kernel<<<nb, 1024, 0, s>>>(w.count, w.start, w.block_sum, total_tiles);
+    bin_scan_top_kernel<<<1, 1024, 0, s>>>(w.block_sum, nb, w.start, total_tiles);
+    bin_scan_add_kernel<<<nb, 1024, 0, s>>>(w.start, w.block_sum, total_tiles);
+    if (total_surfels > 0)
+        disc_bin_kernel<1><<<sblocks, 256, 0, s>>>(table, n_items, total_surfels, w.rec, w.count, w.start,
+                                                   w.list);
+    disc_raster_kernel<<<total_tiles, kRenderTile * kRenderTile, 0, s>>>(table, n_items, w.rec, w.start,
+                                                                         w.list);
     return hipGetLastError();
 }
 
