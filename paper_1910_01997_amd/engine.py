@@ -198,22 +198,33 @@ class DiscKeyframe:
         return {k: v[:self.count] for k, v in h.items()}
 
 
-def disc_render(ctx: sg.Context, dks: Sequence[DiscKeyframe]):
+def disc_items(dks: Sequence[DiscKeyframe]):
+    """The descriptor array of several disc keyframes (host memory, read by
+    each call); refresh it with refresh_counts after a placement."""
+    return sg.disc_array([d.item() for d in dks])
+
+
+def refresh_counts(items, dks: Sequence[DiscKeyframe]):
+    for i, d in enumerate(dks):
+        items[i].count = int(d.count)
+
+
+def disc_render(ctx: sg.Context, dks: Sequence[DiscKeyframe], items=None):
     """Depth-buffered render of several keyframes' discs in one pass."""
-    items = sg.disc_array([d.item() for d in dks])
+    items = disc_items(dks) if items is None else items
     sg.sgn_disc_render_batch(ctx.handle, items, len(dks), [d.inv_depth_out.data_ptr() for d in dks],
                              [d.index_out.data_ptr() for d in dks])
     return items
 
 
 def disc_place(ctx: sg.Context, dks: Sequence[DiscKeyframe], alpha: float = 1.0, beta: float = 2.0,
-               spacing: int = 0, wait: bool = True):
+               spacing: int = 0, wait: bool = True, items=None):
     """Empty-area search and placement for several keyframes in one batch,
     each from its current index map (the same results as DiscKeyframe.place
     one by one).  With wait, synchronises once and returns the (placed,
     qualifying) pairs, updating each keyframe's count."""
     sp = int(spacing) if spacing else int(np.floor(dks[0].radius * np.sqrt(2.0)))
-    items = sg.disc_array([d.item() for d in dks])
+    items = disc_items(dks) if items is None else items
     sg.sgn_disc_place_batch(ctx.handle, items, len(dks), [d.index_out.data_ptr() for d in dks],
                             [d.capacity for d in dks], sg.sgn_disc_place_params(float(alpha), float(beta), sp),
                             [d.counts.data_ptr() for d in dks])
@@ -227,9 +238,9 @@ def disc_place(ctx: sg.Context, dks: Sequence[DiscKeyframe], alpha: float = 1.0,
     return out
 
 
-def disc_update(ctx: sg.Context, dks: Sequence[DiscKeyframe], prm: sg.sgn_params):
+def disc_update(ctx: sg.Context, dks: Sequence[DiscKeyframe], prm: sg.sgn_params, items=None):
     """Gauss-Newton over the disc surfels of several keyframes in one launch."""
-    items = sg.disc_array([d.item() for d in dks])
+    items = disc_items(dks) if items is None else items
     sg.sgn_disc_optimize(ctx.handle, items, len(dks), prm)
     return items
 
