@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--no-disc", action="store_true",
                     help="skip the disc-surfel leg (Eq. 4 support, 10 px radius)")
     ap.add_argument("--disc-steps", type=int, default=10)
+    ap.add_argument("--no-transfer", action="store_true",
+                    help="skip the reference-frame change leg (Eq. 10 with re-gridding)")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a kernel of "
@@ -93,6 +95,62 @@ def disc_pixel_counts(ux, uy, radius, width, height):
             d2 = (x - ux) ** 2 + (y - uy) ** 2
             out += ((d2 < radius * radius) & (x >= 0) & (y >= 0) & (x < width) & (y < height))
     return out
+
+
+def time_transfer(run, n_surfels, written, bytes_per_surfel, what, reps=5):
+    """Median of `reps` timed runs (HIP events on the context's stream, which
+    is torch's current stream) after one warm-up run; algorithmic bytes:
+    each source surfel read and each destination entry written once."""
+    import numpy as np
+    import torch
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms = []
+    for _ in range(reps):
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    t = float(np.median(ms))
+    gbs = n_surfels * bytes_per_surfel / (t * 1e-3) / 1e9
+    return {"workload": what, "surfels": int(n_surfels), "written": written(), "ms": t,
+            "surfels_per_s": n_surfels / (t * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "bytes_per_surfel": bytes_per_surfel}}
+
+
+def transfer_leg(ctx, kfs, dks):
+    """Eq. 10 with re-gridding: every keyframe's surfels into the tiles of the
+    keyframe seen from its first neighbour's pose (same intrinsics, size and
+    tile edge), one call per keyframe."""
+    import numpy as np
+    import torch
+
+    from paper_1910_01997_amd import surfgn as sg
+    m = [d.n_surfels for d in dks]
+    dsts = [sg.SurfelState.from_arrays(np.zeros(n, np.float32), np.tile(np.float32([0, 0, -1]), (n, 1)))
+            for n in m]
+    is_new = [torch.zeros(n, dtype=torch.uint8, device="cuda") for n in m]
+    src_idx = [torch.empty(n, dtype=torch.int32, device="cuda") for n in m]
+    grids = [sg.grid_of(k.K, k.width, k.height, k.patch) for k in kfs]
+    poses = [sg.pose_of(k.R[0], k.t[0]) for k in kfs]
+
+    srcs = [d.state.c for d in dks]
+    dcs = [t.c for t in dsts]
+    new_ptrs = [t.data_ptr() for t in is_new]
+    idx_ptrs = [t.data_ptr() for t in src_idx]
+
+    def run():
+        sg.sgn_transfer_surfels_batch(ctx.handle, grids, srcs, poses, grids, dcs, new_ptrs, idx_ptrs)
+
+    # bytes per surfel: the source state read (id, normal, flags: 20 B), the
+    # destination tile written (state 32 B, is_new 1 B, source index 4 B)
+    return time_transfer(run, sum(m), lambda: int(sum(int((t == 0).sum()) for t in is_new)),
+                         bytes_per_surfel=20 + 37,
+                         what=f"{len(dks)} keyframes of 4x4 surfels, each into the tiles of the view of "
+                              f"its first neighbour (Eq. 10 and re-gridding), one batched call")
 
 
 def disc_leg(ctx, kfs, storage, iters, steps, with_ablation):
@@ -201,6 +259,34 @@ def disc_leg(ctx, kfs, storage, iters, steps, with_ablation):
     log(f"disc leg: step {step_ms:.3f} ms (render {ph[0]:.3f}, place {ph[1]:.3f}, GN {ph[2]:.3f}, "
         f"render {ph[3]:.3f}); GN kernel {gn_ms:.3f} ms, {samples / (gn_ms * 1e-3):.4e} samples/s, "
         f"frac {achieved / VALU_PEAK_TOPS:.3f}; placed {n_new}")
+    # Eq. 10 for discs: every keyframe's surfels into the keyframe seen from
+    # its first neighbour's pose (same intrinsics and size), one call each
+    tstates, tux, tuy, tcnt = [], [], [], []
+    for d in dks:
+        n = max(1, d.count)
+        tstates.append(sg.SurfelState.from_arrays(np.zeros(n, np.float32),
+                                                  np.tile(np.float32([0, 0, -1]), (n, 1))))
+        tux.append(torch.empty(n, dtype=torch.float32, device="cuda"))
+        tuy.append(torch.empty(n, dtype=torch.float32, device="cuda"))
+        tcnt.append(torch.zeros(2, dtype=torch.int32, device="cuda"))
+    tposes = [sg.pose_of(k.R[0], k.t[0]) for k in kfs]
+
+    tsrc = [d.item() for d in dks]
+    tdst = [sg.sgn_disc_item(d.img.view.c, tstates[i].c, tux[i].data_ptr(), tuy[i].data_ptr(), 0,
+                             float(radius)) for i, d in enumerate(dks)]
+    tcap = [t.numel() for t in tux]
+    tcnt_ptrs = [t.data_ptr() for t in tcnt]
+
+    def transfer():
+        sg.sgn_disc_transfer_batch(ctx.handle, tsrc, tposes, tdst, tcap, tcnt_ptrs)
+
+    out["transfer"] = time_transfer(transfer, sum(d.count for d in dks),
+                                    lambda: int(torch.stack(tcnt)[:, 0].sum()),
+                                    bytes_per_surfel=20 + 8 + 40,
+                                    what=f"{len(dks)} keyframes of disc surfels, each into the view of "
+                                         f"its first neighbour (Eq. 10, a disc stays a disc), one batched "
+                                         f"call")
+    log(f"disc transfer: {out['transfer']}")
     if with_ablation:
         # full vs depth-only against the true planes, on the original discs
         # that see one plane
@@ -410,6 +496,11 @@ def main():
         torch.cuda.synchronize()
 
     discs = None
+    transfer = None
+    if not args.no_transfer:
+        transfer = transfer_leg(ctx, kfs, dks)
+        log(f"tile transfer: {transfer}")
+        restore()
     if not args.no_disc:
         discs = disc_leg(ctx, kfs, args.storage, iters, args.disc_steps, not args.no_ablation)
         torch.cuda.synchronize()
@@ -515,6 +606,7 @@ def main():
         "plain_form": plain,
         "precision_forms": forms,
         "disc_surfels": discs,
+        "transfer": transfer,
         "ablation": ablation,
         "serving": serving,
         "device": {"name": info["name"], "arch": info["arch"], "cus": info["compute_units"]},

@@ -256,6 +256,20 @@ sgn_status sgn_transfer_surfels(sgn_ctx* ctx, const sgn_grid* src_grid, const sg
                                 const sgn_pose* pose, const sgn_grid* dst_grid, sgn_surfels* dst,
                                 uint8_t* dst_is_new, int32_t* dst_src_index);
 
+/* sgn_transfer_surfels for n keyframe pairs at once (Eq. 10, Surfel
+ * reference frame change): four launches for the whole batch, the same
+ * results as n calls (pairs share nothing).  Pair k takes src_grids[k],
+ * srcs[k], poses[k], dst_grids[k], dsts[k], dst_is_new[k] and
+ * dst_src_index[k] (dst_src_index itself may be NULL, as may its entries);
+ * all arrays are host memory read during the call.  The context's scratch
+ * holds 12 bytes per destination tile of the whole batch.  Errors: as
+ * sgn_transfer_surfels for any pair (nothing enqueued), SGN_E_INVALID for
+ * n < 1 or a null array. */
+sgn_status sgn_transfer_surfels_batch(sgn_ctx* ctx, int32_t n, const sgn_grid* src_grids,
+                                      const sgn_surfels* srcs, const sgn_pose* poses,
+                                      const sgn_grid* dst_grids, const sgn_surfels* dsts,
+                                      uint8_t* const* dst_is_new, int32_t* const* dst_src_index);
+
 /* ------------------------------------------------------------ disc surfels
  *
  * Disc surfels (Eq. 4): surfel i is centred at u_s = (ux[i], uy[i]) in
@@ -365,6 +379,18 @@ sgn_status sgn_disc_place_batch(sgn_ctx* ctx, const sgn_disc_item* items, int32_
 sgn_status sgn_disc_transfer(sgn_ctx* ctx, const sgn_disc_item* src, const sgn_pose* pose,
                              const sgn_disc_item* dst, int32_t capacity, int32_t* counts_out,
                              int32_t* src_index_out);
+
+/* sgn_disc_transfer for n keyframe pairs in one launch (one workgroup per
+ * pair), the same results as n calls (pairs share nothing).  Pair k takes
+ * srcs[k], poses[k], dsts[k], capacities[k], counts_outs[k] and
+ * src_index_outs[k] (src_index_outs itself may be NULL, as may its entries);
+ * all arrays are host memory read during the call.  Errors: as
+ * sgn_disc_transfer for any pair (nothing enqueued), SGN_E_INVALID for
+ * n < 1 or a null array. */
+sgn_status sgn_disc_transfer_batch(sgn_ctx* ctx, int32_t n, const sgn_disc_item* srcs,
+                                   const sgn_pose* poses, const sgn_disc_item* dsts,
+                                   const int32_t* capacities, int32_t* const* counts_outs,
+                                   int32_t* const* src_index_outs);
 
 /* Convert a float image (device, src_pitch elements per row) to dst->dtype
  * storage at dst->data: F16 with round-to-nearest-even, or U8 as

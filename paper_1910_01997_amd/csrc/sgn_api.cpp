@@ -781,53 +781,91 @@ sgn_status sgn_quantize(sgn_ctx* c, const float* src, int32_t src_pitch, const s
     return SGN_OK;
 }
 
+sgn_status sgn_transfer_surfels_batch(sgn_ctx* c, int32_t n, const sgn_grid* src_grids,
+                                      const sgn_surfels* srcs, const sgn_pose* poses,
+                                      const sgn_grid* dst_grids, const sgn_surfels* dsts,
+                                      uint8_t* const* dst_is_new, int32_t* const* dst_src_index) {
+    if (!c) return fail(SGN_E_INVALID, "null context");
+    if (n < 1 || !src_grids || !srcs || !poses || !dst_grids || !dsts || !dst_is_new)
+        return fail(SGN_E_INVALID, "empty batch or null argument");
+    std::vector<RegridArgs> tab(n);
+    int64_t total_src = 0, total_dst = 0;
+    for (int k = 0; k < n; ++k) {
+        const sgn_grid* src_grid = &src_grids[k];
+        const sgn_grid* dst_grid = &dst_grids[k];
+        const sgn_pose* pose = &poses[k];
+        if (!dst_is_new[k]) return fail(SGN_E_INVALID, "null argument");
+        for (const sgn_grid* g : {src_grid, dst_grid}) {
+            if (g->patch != 4 && g->patch != 8 && g->patch != 16)
+                return fail(SGN_E_INVALID, "patch must be 4, 8 or 16");
+            if (g->width < g->patch || g->height < g->patch || g->width > 16384 || g->height > 16384)
+                return fail(SGN_E_INVALID, "grid size out of range");
+            if (!(g->K.fx > 0.0) || !(g->K.fy > 0.0) || !std::isfinite(g->K.cx) || !std::isfinite(g->K.cy))
+                return fail(SGN_E_INVALID, "bad intrinsics");
+        }
+        sgn_status st = check_surfels(&srcs[k]);
+        if (st) return st;
+        st = check_surfels(&dsts[k]);
+        if (st) return st;
+        for (int i = 0; i < 9; ++i)
+            if (!std::isfinite(pose->R[i])) return fail(SGN_E_INVALID, "pose is not finite");
+        for (int i = 0; i < 3; ++i)
+            if (!std::isfinite(pose->t[i])) return fail(SGN_E_INVALID, "pose is not finite");
+        RegridArgs& a = tab[k];
+        auto conv = [](const sgn_surfels* x) {
+            return RegridSurfels{x->inv_depth, x->nx, x->ny, x->nz, x->flags, x->cost, x->nvalid,
+                                 x->last_update};
+        };
+        a.src = conv(&srcs[k]);
+        a.dst = conv(&dsts[k]);
+        a.src_K[0] = src_grid->K.fx; a.src_K[1] = src_grid->K.fy; a.src_K[2] = src_grid->K.cx;
+        a.src_K[3] = src_grid->K.cy;
+        a.dst_K[0] = dst_grid->K.fx; a.dst_K[1] = dst_grid->K.fy; a.dst_K[2] = dst_grid->K.cx;
+        a.dst_K[3] = dst_grid->K.cy;
+        for (int i = 0; i < 9; ++i) a.R[i] = pose->R[i];
+        for (int i = 0; i < 3; ++i) a.t[i] = pose->t[i];
+        a.src_w = src_grid->width; a.src_h = src_grid->height; a.src_patch = src_grid->patch;
+        a.dst_w = dst_grid->width; a.dst_h = dst_grid->height; a.dst_patch = dst_grid->patch;
+        a.is_new = dst_is_new[k];
+        a.src_index = dst_src_index ? dst_src_index[k] : nullptr;
+        a.src_base = (int32_t)total_src;
+        a.dst_base = (int32_t)total_dst;
+        total_src += (int64_t)(src_grid->width / src_grid->patch) * (src_grid->height / src_grid->patch);
+        total_dst += (int64_t)(dst_grid->width / dst_grid->patch) * (dst_grid->height / dst_grid->patch);
+        if (total_src > INT32_MAX / 2 || total_dst > INT32_MAX / 2)
+            return fail(SGN_E_UNSUPPORTED, "too many surfels in one batch");
+    }
+    SGN_HIP(hipSetDevice(c->device));
+    sgn_status st = ensure_scratch(c, (size_t)total_dst * (sizeof(unsigned long long) + sizeof(int32_t)));
+    if (st) return st;
+    unsigned long long* best = (unsigned long long*)c->scratch;
+    int32_t* win = (int32_t*)((char*)c->scratch + (size_t)total_dst * sizeof(unsigned long long));
+    for (int k = 0; k < n; ++k) {
+        tab[k].best = best + tab[k].dst_base;
+        tab[k].win = win + tab[k].dst_base;
+    }
+    // the table goes through the staging ring into the device table
+    const size_t bytes = sizeof(RegridArgs) * (size_t)n;
+    st = ensure_table(c, bytes);
+    if (st) return st;
+    const int slot = c->ring_next;
+    c->ring_next = (c->ring_next + 1) % kRingSlots;
+    if (c->ring_used[slot]) SGN_HIP(hipEventSynchronize(c->ring_ev[slot]));
+    std::memcpy(c->host_ring[slot], tab.data(), bytes);
+    SGN_HIP(hipMemcpyAsync(c->dev_table, c->host_ring[slot], bytes, hipMemcpyHostToDevice, c->stream));
+    SGN_HIP(hipEventRecord(c->ring_ev[slot], c->stream));
+    c->ring_used[slot] = true;
+    hipError_t e = launch_regrid((const RegridArgs*)c->dev_table, n, (int)total_src, (int)total_dst, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "re-gridding launch");
+    return SGN_OK;
+}
+
 sgn_status sgn_transfer_surfels(sgn_ctx* c, const sgn_grid* src_grid, const sgn_surfels* src,
                                 const sgn_pose* pose, const sgn_grid* dst_grid, sgn_surfels* dst,
                                 uint8_t* dst_is_new, int32_t* dst_src_index) {
     if (!c || !src_grid || !src || !pose || !dst_grid || !dst || !dst_is_new)
         return fail(SGN_E_INVALID, "null argument");
-    for (const sgn_grid* g : {src_grid, dst_grid}) {
-        if (g->patch != 4 && g->patch != 8 && g->patch != 16)
-            return fail(SGN_E_INVALID, "patch must be 4, 8 or 16");
-        if (g->width < g->patch || g->height < g->patch || g->width > 16384 || g->height > 16384)
-            return fail(SGN_E_INVALID, "grid size out of range");
-        if (!(g->K.fx > 0.0) || !(g->K.fy > 0.0) || !std::isfinite(g->K.cx) || !std::isfinite(g->K.cy))
-            return fail(SGN_E_INVALID, "bad intrinsics");
-    }
-    sgn_status st = check_surfels(src);
-    if (st) return st;
-    st = check_surfels(dst);
-    if (st) return st;
-    for (int i = 0; i < 9; ++i)
-        if (!std::isfinite(pose->R[i])) return fail(SGN_E_INVALID, "pose is not finite");
-    for (int i = 0; i < 3; ++i)
-        if (!std::isfinite(pose->t[i])) return fail(SGN_E_INVALID, "pose is not finite");
-    SGN_HIP(hipSetDevice(c->device));
-    const size_t n_dst = (size_t)(dst_grid->width / dst_grid->patch) * (dst_grid->height / dst_grid->patch);
-    st = ensure_scratch(c, n_dst * (sizeof(unsigned long long) + sizeof(int32_t)));
-    if (st) return st;
-    RegridArgs a{};
-    auto conv = [](const sgn_surfels* x) {
-        return RegridSurfels{x->inv_depth, x->nx, x->ny, x->nz, x->flags, x->cost, x->nvalid,
-                             x->last_update};
-    };
-    a.src = conv(src);
-    a.dst = conv(dst);
-    a.src_K[0] = src_grid->K.fx; a.src_K[1] = src_grid->K.fy; a.src_K[2] = src_grid->K.cx;
-    a.src_K[3] = src_grid->K.cy;
-    a.dst_K[0] = dst_grid->K.fx; a.dst_K[1] = dst_grid->K.fy; a.dst_K[2] = dst_grid->K.cx;
-    a.dst_K[3] = dst_grid->K.cy;
-    for (int i = 0; i < 9; ++i) a.R[i] = pose->R[i];
-    for (int i = 0; i < 3; ++i) a.t[i] = pose->t[i];
-    a.src_w = src_grid->width; a.src_h = src_grid->height; a.src_patch = src_grid->patch;
-    a.dst_w = dst_grid->width; a.dst_h = dst_grid->height; a.dst_patch = dst_grid->patch;
-    a.best = (unsigned long long*)c->scratch;
-    a.win = (int32_t*)((char*)c->scratch + n_dst * sizeof(unsigned long long));
-    a.is_new = dst_is_new;
-    a.src_index = dst_src_index;
-    hipError_t e = launch_regrid(a, c->stream);
-    if (e != hipSuccess) return hip_fail(e, "re-gridding launch");
-    return SGN_OK;
+    return sgn_transfer_surfels_batch(c, 1, src_grid, src, pose, dst_grid, dst, &dst_is_new, &dst_src_index);
 }
 
 sgn_status sgn_disc_optimize(sgn_ctx* c, const sgn_disc_item* items, int32_t n, const sgn_params* p) {
@@ -978,48 +1016,77 @@ sgn_status sgn_disc_place(sgn_ctx* c, const sgn_disc_item* item, const int32_t* 
     return sgn_disc_place_batch(c, item, 1, &index_map, &capacity, pp, &counts_out);
 }
 
+sgn_status sgn_disc_transfer_batch(sgn_ctx* c, int32_t n, const sgn_disc_item* srcs, const sgn_pose* poses,
+                                   const sgn_disc_item* dsts, const int32_t* capacities,
+                                   int32_t* const* counts_outs, int32_t* const* src_index_outs) {
+    if (!c) return fail(SGN_E_INVALID, "null context");
+    if (n < 1 || !srcs || !poses || !dsts || !capacities || !counts_outs)
+        return fail(SGN_E_INVALID, "empty batch or null argument");
+    std::vector<DiscTransferArgs> tab(n);
+    for (int k = 0; k < n; ++k) {
+        const sgn_disc_item* src = &srcs[k];
+        const sgn_disc_item* dst = &dsts[k];
+        const sgn_pose* pose = &poses[k];
+        const int32_t capacity = capacities[k];
+        if (!counts_outs[k]) return fail(SGN_E_INVALID, "null argument");
+        sgn_status st = check_disc_item(src, false);
+        if (st) return st;
+        st = check_keyframe(&dst->kf, false, true);
+        if (st) return st;
+        if (capacity < 0) return fail(SGN_E_INVALID, "negative capacity");
+        if (capacity > 0) {
+            if (!dst->ux || !dst->uy) return fail(SGN_E_INVALID, "null destination centre array");
+            st = check_surfels(&dst->surfels);
+            if (st) return st;
+        }
+        for (int i = 0; i < 9; ++i)
+            if (!std::isfinite(pose->R[i])) return fail(SGN_E_INVALID, "pose is not finite");
+        for (int i = 0; i < 3; ++i)
+            if (!std::isfinite(pose->t[i])) return fail(SGN_E_INVALID, "pose is not finite");
+        DiscTransferArgs& a = tab[k];
+        a.inv_depth = src->surfels.inv_depth;
+        a.nx = src->surfels.nx; a.ny = src->surfels.ny; a.nz = src->surfels.nz;
+        a.flags = src->surfels.flags;
+        a.last_update = src->surfels.last_update;
+        a.ux = src->ux; a.uy = src->uy;
+        a.count = src->count;
+        a.dst_w = dst->kf.kf.width; a.dst_h = dst->kf.kf.height;
+        a.capacity = capacity;
+        a.sK[0] = src->kf.K.fx; a.sK[1] = src->kf.K.fy; a.sK[2] = src->kf.K.cx; a.sK[3] = src->kf.K.cy;
+        a.dK[0] = dst->kf.K.fx; a.dK[1] = dst->kf.K.fy; a.dK[2] = dst->kf.K.cx; a.dK[3] = dst->kf.K.cy;
+        for (int i = 0; i < 9; ++i) a.R[i] = pose->R[i];
+        for (int i = 0; i < 3; ++i) a.t[i] = pose->t[i];
+        a.dst = RegridSurfels{dst->surfels.inv_depth, dst->surfels.nx, dst->surfels.ny, dst->surfels.nz,
+                              dst->surfels.flags, dst->surfels.cost, dst->surfels.nvalid,
+                              dst->surfels.last_update};
+        a.dux = dst->ux; a.duy = dst->uy;
+        a.src_index = src_index_outs ? src_index_outs[k] : nullptr;
+        a.counts = counts_outs[k];
+    }
+    SGN_HIP(hipSetDevice(c->device));
+    // the table goes through the staging ring into the device table
+    const size_t bytes = sizeof(DiscTransferArgs) * (size_t)n;
+    sgn_status st = ensure_table(c, bytes);
+    if (st) return st;
+    const int slot = c->ring_next;
+    c->ring_next = (c->ring_next + 1) % kRingSlots;
+    if (c->ring_used[slot]) SGN_HIP(hipEventSynchronize(c->ring_ev[slot]));
+    std::memcpy(c->host_ring[slot], tab.data(), bytes);
+    SGN_HIP(hipMemcpyAsync(c->dev_table, c->host_ring[slot], bytes, hipMemcpyHostToDevice, c->stream));
+    SGN_HIP(hipEventRecord(c->ring_ev[slot], c->stream));
+    c->ring_used[slot] = true;
+    hipError_t e = launch_disc_transfer((const DiscTransferArgs*)c->dev_table, n, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "disc transfer launch");
+    return SGN_OK;
+}
+
 sgn_status sgn_disc_transfer(sgn_ctx* c, const sgn_disc_item* src, const sgn_pose* pose,
                              const sgn_disc_item* dst, int32_t capacity, int32_t* counts_out,
                              int32_t* src_index_out) {
     if (!c || !pose || !counts_out) return fail(SGN_E_INVALID, "null argument");
-    sgn_status st = check_disc_item(src, false);
-    if (st) return st;
+    if (!src) return fail(SGN_E_INVALID, "null disc item");
     if (!dst) return fail(SGN_E_INVALID, "null destination");
-    st = check_keyframe(&dst->kf, false, true);
-    if (st) return st;
-    if (capacity < 0) return fail(SGN_E_INVALID, "negative capacity");
-    if (capacity > 0) {
-        if (!dst->ux || !dst->uy) return fail(SGN_E_INVALID, "null destination centre array");
-        st = check_surfels(&dst->surfels);
-        if (st) return st;
-    }
-    for (int i = 0; i < 9; ++i)
-        if (!std::isfinite(pose->R[i])) return fail(SGN_E_INVALID, "pose is not finite");
-    for (int i = 0; i < 3; ++i)
-        if (!std::isfinite(pose->t[i])) return fail(SGN_E_INVALID, "pose is not finite");
-    SGN_HIP(hipSetDevice(c->device));
-    DiscTransferArgs a{};
-    a.inv_depth = src->surfels.inv_depth;
-    a.nx = src->surfels.nx; a.ny = src->surfels.ny; a.nz = src->surfels.nz;
-    a.flags = src->surfels.flags;
-    a.last_update = src->surfels.last_update;
-    a.ux = src->ux; a.uy = src->uy;
-    a.count = src->count;
-    a.dst_w = dst->kf.kf.width; a.dst_h = dst->kf.kf.height;
-    a.capacity = capacity;
-    a.sK[0] = src->kf.K.fx; a.sK[1] = src->kf.K.fy; a.sK[2] = src->kf.K.cx; a.sK[3] = src->kf.K.cy;
-    a.dK[0] = dst->kf.K.fx; a.dK[1] = dst->kf.K.fy; a.dK[2] = dst->kf.K.cx; a.dK[3] = dst->kf.K.cy;
-    for (int i = 0; i < 9; ++i) a.R[i] = pose->R[i];
-    for (int i = 0; i < 3; ++i) a.t[i] = pose->t[i];
-    a.dst = RegridSurfels{dst->surfels.inv_depth, dst->surfels.nx, dst->surfels.ny, dst->surfels.nz,
-                          dst->surfels.flags, dst->surfels.cost, dst->surfels.nvalid,
-                          dst->surfels.last_update};
-    a.dux = dst->ux; a.duy = dst->uy;
-    a.src_index = src_index_out;
-    a.counts = counts_out;
-    hipError_t e = launch_disc_transfer(a, c->stream);
-    if (e != hipSuccess) return hip_fail(e, "disc transfer launch");
-    return SGN_OK;
+    return sgn_disc_transfer_batch(c, 1, src, pose, dst, &capacity, &counts_out, &src_index_out);
 }
 
 sgn_status sgn_autotune(sgn_ctx* c, const sgn_batch_item* items, int32_t n, const sgn_params* p,

@@ -138,6 +138,7 @@ struct RegridArgs {
     int32_t* win;                // winning source index per destination tile
     uint8_t* is_new;
     int32_t* src_index;          // may be null
+    int32_t src_base, dst_base;  // source surfels / destination tiles of the table's earlier pairs
 };
 
 // Launchers implemented in sgn_kernels.hip.  All return hipError_t of the
@@ -148,7 +149,9 @@ hipError_t launch_init(const BatchHeader* hdr, int grid, hipStream_t s);
 hipError_t launch_render(const BatchHeader* hdr, int grid, hipStream_t s);
 hipError_t launch_gn(const GnVariant& v, const BatchHeader* hdr, uint32_t* counters,
                      int persistent, int grid_blocks, hipStream_t s);
-hipError_t launch_regrid(const RegridArgs& a, hipStream_t s);
+// Re-gridding of a device table of n_pairs keyframe pairs.
+hipError_t launch_regrid(const RegridArgs* table, int n_pairs, int total_src, int total_dst,
+                         hipStream_t s);
 
 // Disc surfels (Eq. 4).
 constexpr float kDiscMaxRadius = 12.f;
@@ -249,7 +252,8 @@ struct DiscTransferArgs {
     int32_t* src_index;           // may be null
     int32_t* counts;              // device [2]: written, landed
 };
-hipError_t launch_disc_transfer(const DiscTransferArgs& a, hipStream_t s);
+// One workgroup per entry of a device table of n_pairs keyframe pairs.
+hipError_t launch_disc_transfer(const DiscTransferArgs* table, int n_pairs, hipStream_t s);
 hipError_t launch_quantize(const float* src, int src_pitch, void* dst, int dst_pitch,
                            int width, int height, int dtype, float scale, hipStream_t s);
 // Workgroups of 256 threads of the chosen GN variant that fit on one CU.

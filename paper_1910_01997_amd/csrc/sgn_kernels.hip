@@ -1347,9 +1347,30 @@ __device__ __forceinline__ bool regrid_land(const RegridArgs& a, int i, Land& L)
     return true;
 }
 
-__global__ void regrid_clear_kernel(RegridArgs a) {
-    const int n = (a.dst_w / a.dst_patch) * (a.dst_h / a.dst_patch);
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+// The re-gridding kernels run over a table of keyframe pairs: source
+// surfels and destination tiles are numbered pair after pair (src_base,
+// dst_base); the entry owning number g is the last whose base is <= g.
+__device__ __forceinline__ int regrid_entry_of_src(const RegridArgs* tab, int n, int g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].src_base <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+__device__ __forceinline__ int regrid_entry_of_dst(const RegridArgs* tab, int n, int g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].dst_base <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void regrid_clear_kernel(const RegridArgs* __restrict__ tab, int n_pairs, int total_dst) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total_dst; g += gridDim.x * blockDim.x) {
+        const RegridArgs& a = tab[regrid_entry_of_dst(tab, n_pairs, g)];
+        const int j = g - a.dst_base;
         a.best[j] = 0ull;
         a.win[j] = 0x7fffffff;
     }
@@ -1357,9 +1378,11 @@ __global__ void regrid_clear_kernel(RegridArgs a) {
 
 // pass 0: closest landing per tile (1/p'_z > 0, so its bits order like the
 // value); pass 1: the lowest source index among the closest
-__global__ void regrid_scatter_kernel(RegridArgs a, int pass) {
-    const int n = (a.src_w / a.src_patch) * (a.src_h / a.src_patch);
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+__global__ void regrid_scatter_kernel(const RegridArgs* __restrict__ tab, int n_pairs, int total_src,
+                                      int pass) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total_src; g += gridDim.x * blockDim.x) {
+        const RegridArgs& a = tab[regrid_entry_of_src(tab, n_pairs, g)];
+        const int i = g - a.src_base;
         Land L;
         if (!regrid_land(a, i, L)) continue;
         const unsigned long long bits = (unsigned long long)__double_as_longlong(L.idp);
@@ -1370,11 +1393,12 @@ __global__ void regrid_scatter_kernel(RegridArgs a, int pass) {
     }
 }
 
-__global__ void regrid_gather_kernel(RegridArgs a) {
+__global__ void regrid_gather_kernel(const RegridArgs* __restrict__ tab, int n_pairs, int total_dst) {
 #pragma clang fp contract(off)
-    const int S1 = a.dst_patch, gw1 = a.dst_w / S1, gh1 = a.dst_h / S1;
-    const int n = gw1 * gh1;
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total_dst; g += gridDim.x * blockDim.x) {
+        const RegridArgs& a = tab[regrid_entry_of_dst(tab, n_pairs, g)];
+        const int j = g - a.dst_base;
+        const int S1 = a.dst_patch, gw1 = a.dst_w / S1;
         const int w = a.win[j];
         bool ok = false;
         double idt = 0.0, t0 = 0.0, t1 = 0.0, t2 = -1.0;
@@ -1406,14 +1430,19 @@ __global__ void regrid_gather_kernel(RegridArgs a) {
     }
 }
 
-hipError_t launch_regrid(const RegridArgs& a, hipStream_t s) {
-    const int n_src = (a.src_w / a.src_patch) * (a.src_h / a.src_patch);
-    const int n_dst = (a.dst_w / a.dst_patch) * (a.dst_h / a.dst_patch);
-    auto blocks = [](int n) { return std::max(1, std::min(4096, (n + 255) / 256)); };
-    hipLaunchKernelGGL(regrid_clear_kernel, dim3(blocks(n_dst)), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(regrid_scatter_kernel, dim3(blocks(n_src)), dim3(256), 0, s, a, 0);
-    hipLaunchKernelGGL(regrid_scatter_kernel, dim3(blocks(n_src)), dim3(256), 0, s, a, 1);
-    hipLaunchKernelGGL(regrid_gather_kernel, dim3(blocks(n_dst)), dim3(256), 0, s, a);
+hipError_t launch_regrid(const RegridArgs* table, int n_pairs, int total_src, int total_dst,
+                         hipStream_t s) {
+    auto blocks = [](int n) { return std::max(1, std::min(65536, (n + 255) / 256)); };
+    hipLaunchKernelGGL(regrid_clear_kernel, dim3(blocks(total_dst)), dim3(256), 0, s, table, n_pairs,
+                       total_dst);
+    if (total_src > 0) {
+        hipLaunchKernelGGL(regrid_scatter_kernel, dim3(blocks(total_src)), dim3(256), 0, s, table, n_pairs,
+                           total_src, 0);
+        hipLaunchKernelGGL(regrid_scatter_kernel, dim3(blocks(total_src)), dim3(256), 0, s, table, n_pairs,
+                           total_src, 1);
+    }
+    hipLaunchKernelGGL(regrid_gather_kernel, dim3(blocks(total_dst)), dim3(256), 0, s, table, n_pairs,
+                       total_dst);
     return hipGetLastError();
 }
 
@@ -2266,8 +2295,9 @@ __global__ __launch_bounds__(kWaveSize) void disc_init_kernel(const DiscPlaceArg
 // order (as many as there is room for).  One workgroup walks the sources in
 // chunks; every landing is computed in double in the oracle's order, so the
 // kept set and the order are the same.
-__global__ __launch_bounds__(1024) void disc_transfer_kernel(DiscTransferArgs a) {
+__global__ __launch_bounds__(1024) void disc_transfer_kernel(const DiscTransferArgs* __restrict__ tab) {
 #pragma clang fp contract(off)
+    const DiscTransferArgs& a = tab[blockIdx.x];          // one workgroup per keyframe pair
     __shared__ int s_wave[1024 / kWaveSize + 1];
     const int lane = threadIdx.x & (kWaveSize - 1);
     const int wave = threadIdx.x >> 6;
@@ -2333,8 +2363,8 @@ __global__ __launch_bounds__(1024) void disc_transfer_kernel(DiscTransferArgs a)
     }
 }
 
-hipError_t launch_disc_transfer(const DiscTransferArgs& a, hipStream_t s) {
-    disc_transfer_kernel<<<1, 1024, 0, s>>>(a);
+hipError_t launch_disc_transfer(const DiscTransferArgs* table, int n_pairs, hipStream_t s) {
+    disc_transfer_kernel<<<n_pairs, 1024, 0, s>>>(table);
     return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ EXPORTED = [
     "sgn_quantize", "sgn_last_kernel_ms", "sgn_device_info", "sgn_status_str", "sgn_last_error",
     "sgn_version", "sgn_transfer_surfels", "sgn_disc_optimize", "sgn_disc_render", "sgn_disc_place",
     "sgn_recent_kernel_ms", "sgn_disc_transfer", "sgn_disc_render_batch", "sgn_disc_place_batch",
+    "sgn_transfer_surfels_batch", "sgn_disc_transfer_batch",
 ]
 
 
@@ -152,6 +153,11 @@ def lib():
         L.sgn_transfer_surfels.argtypes = [vp, C.POINTER(sgn_grid), C.POINTER(sgn_surfels),
                                            C.POINTER(sgn_pose), C.POINTER(sgn_grid),
                                            C.POINTER(sgn_surfels), vp, vp]
+        L.sgn_transfer_surfels_batch.restype = st
+        L.sgn_transfer_surfels_batch.argtypes = [vp, C.c_int32, C.POINTER(sgn_grid), C.POINTER(sgn_surfels),
+                                                 C.POINTER(sgn_pose), C.POINTER(sgn_grid),
+                                                 C.POINTER(sgn_surfels), C.POINTER(C.c_void_p),
+                                                 C.POINTER(C.c_void_p)]
         L.sgn_disc_optimize.restype = st
         L.sgn_disc_optimize.argtypes = [vp, C.POINTER(sgn_disc_item), C.c_int32, C.POINTER(sgn_params)]
         L.sgn_disc_render.restype = st
@@ -169,6 +175,10 @@ def lib():
         L.sgn_disc_transfer.restype = st
         L.sgn_disc_transfer.argtypes = [vp, C.POINTER(sgn_disc_item), C.POINTER(sgn_pose),
                                         C.POINTER(sgn_disc_item), C.c_int32, vp, vp]
+        L.sgn_disc_transfer_batch.restype = st
+        L.sgn_disc_transfer_batch.argtypes = [vp, C.c_int32, C.POINTER(sgn_disc_item), C.POINTER(sgn_pose),
+                                              C.POINTER(sgn_disc_item), C.POINTER(C.c_int32),
+                                              C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]
         L.sgn_recent_kernel_ms.restype = st
         L.sgn_recent_kernel_ms.argtypes = [vp, C.c_int32, C.POINTER(C.c_float)]
         L.sgn_last_kernel_ms.restype = st
@@ -255,6 +265,21 @@ def sgn_transfer_surfels(ctx, src_grid: sgn_grid, src: sgn_surfels, pose: sgn_po
           "sgn_transfer_surfels")
 
 
+def sgn_transfer_surfels_batch(ctx, src_grids: Sequence[sgn_grid], srcs: Sequence[sgn_surfels],
+                               poses: Sequence[sgn_pose], dst_grids: Sequence[sgn_grid],
+                               dsts: Sequence[sgn_surfels], dst_is_new_ptrs: Sequence[int],
+                               dst_src_index_ptrs: Optional[Sequence[int]] = None):
+    n = len(srcs)
+    arr = lambda T, xs: (T * n)(*xs)
+    idx = (arr(C.c_void_p, [int(p) if p else None for p in dst_src_index_ptrs])
+           if dst_src_index_ptrs is not None else None)
+    check(lib().sgn_transfer_surfels_batch(C.c_void_p(ctx), n, arr(sgn_grid, src_grids), arr(sgn_surfels, srcs),
+                                           arr(sgn_pose, poses), arr(sgn_grid, dst_grids),
+                                           arr(sgn_surfels, dsts),
+                                           arr(C.c_void_p, [int(p) for p in dst_is_new_ptrs]), idx),
+          "sgn_transfer_surfels_batch")
+
+
 def sgn_disc_optimize(ctx, items, n: int, params: sgn_params):
     check(lib().sgn_disc_optimize(C.c_void_p(ctx), items, int(n), C.byref(params)), "sgn_disc_optimize")
 
@@ -285,6 +310,19 @@ def sgn_disc_place_batch(ctx, items, n: int, index_map_ptrs: Sequence[int], capa
     cnts = (C.c_void_p * int(n))(*[int(p) if p else None for p in counts_ptrs])
     check(lib().sgn_disc_place_batch(C.c_void_p(ctx), items, int(n), maps, caps, C.byref(params), cnts),
           "sgn_disc_place_batch")
+
+
+def sgn_disc_transfer_batch(ctx, srcs: Sequence[sgn_disc_item], poses: Sequence[sgn_pose],
+                            dsts: Sequence[sgn_disc_item], capacities: Sequence[int],
+                            counts_ptrs: Sequence[int], src_index_ptrs: Optional[Sequence[int]] = None):
+    n = len(srcs)
+    arr = lambda T, xs: (T * n)(*xs)
+    idx = (arr(C.c_void_p, [int(p) if p else None for p in src_index_ptrs])
+           if src_index_ptrs is not None else None)
+    check(lib().sgn_disc_transfer_batch(C.c_void_p(ctx), n, arr(sgn_disc_item, srcs), arr(sgn_pose, poses),
+                                        arr(sgn_disc_item, dsts), arr(C.c_int32, [int(c) for c in capacities]),
+                                        arr(C.c_void_p, [int(p) for p in counts_ptrs]), idx),
+          "sgn_disc_transfer_batch")
 
 
 def sgn_disc_render_batch(ctx, items, n: int, inv_depth_ptrs: Sequence[int],

@@ -286,6 +286,48 @@ def test_disc_transfer_matches_oracle_exactly(ctx):
         assert np.all(dh["flags"] == 0) and np.array_equal(dh["last_update"], out["last_update"])
 
 
+def test_disc_transfer_batch_equals_one_by_one(ctx):
+    """Batched Eq. 10 for discs (three pairs in one launch, one with less
+    room than it needs, one without a source-index output) equals the calls
+    one by one: counts, centres, state and source indices, bitwise."""
+    sg, engine = _mods()
+    print("case disc transfer batch of three pairs", flush=True)
+    srcs, dsts_ref, dsts_got, poses, caps = [], [], [], [], []
+    for k in range(3):
+        kf, discs = _scene(seed=73 + k)
+        src = engine.DiscKeyframe.from_scene(ctx, kf, discs)
+        engine.disc_update(ctx, [src], sg.params(iters=3))
+        img1, nb1, R1, t1 = _as_keyframe_of(kf, k)
+        cap = 40 if k == 1 else src.count + 10
+        z = np.zeros(0, np.float32)
+        mk = lambda: engine.DiscKeyframe(ctx, img1, nb1, R1, t1, kf.K, 10.0, z, z, z,
+                                         np.zeros((0, 3), np.float32), capacity=cap)
+        srcs.append(src)
+        dsts_ref.append(mk())
+        dsts_got.append(mk())
+        poses.append((kf.R[k], kf.t[k]))
+        caps.append(cap)
+    ref_idx = [torch.full((c,), -2, dtype=torch.int32, device="cuda") for c in caps]
+    ref_counts = [d.transfer_from(s, R, t, src_index=i)
+                  for d, s, (R, t), i in zip(dsts_ref, srcs, poses, ref_idx)]
+    got_idx = [torch.full((c,), -2, dtype=torch.int32, device="cuda") for c in caps]
+    sg.sgn_disc_transfer_batch(ctx.handle, [s.item() for s in srcs], [sg.pose_of(R, t) for R, t in poses],
+                               [d.item() for d in dsts_got], caps, [d.counts.data_ptr() for d in dsts_got],
+                               [i.data_ptr() if k != 2 else 0 for k, i in enumerate(got_idx)])
+    torch.cuda.synchronize()
+    for k, (d_ref, d_got) in enumerate(zip(dsts_ref, dsts_got)):
+        written, landed = (int(v) for v in d_got.counts.cpu().tolist())
+        assert (written, landed) == ref_counts[k]
+        d_got.count = written
+        assert np.array_equal(np.stack(d_got.centres()), np.stack(d_ref.centres()))
+        _state_equal(d_got.state_host(), d_ref.state_host())
+        if k != 2:
+            assert np.array_equal(got_idx[k].cpu().numpy(), ref_idx[k].cpu().numpy())
+        else:
+            assert np.all(got_idx[k].cpu().numpy() == -2)
+    assert ref_counts[1][0] == 40 and ref_counts[1][1] > 40
+
+
 def test_disc_two_keyframes_chained(ctx):
     """Keyframe 0 optimised, its surfels moved into keyframe 1 (a neighbour
     frame, Eq. 10), rendered there, the empty areas filled, and keyframe 1

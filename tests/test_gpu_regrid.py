@@ -189,3 +189,55 @@ def test_keyframe_switch_chain_matches_oracle(ctx):
     res = check_parity(dB, devB, hB["inv_depth"], hB["n"], is_new.cpu().numpy(), op,
                        label="keyframe B from device A")
     assert_parity(res, label="keyframe B from device A", max_unstable=0.2)
+
+
+def test_regrid_batch_equals_one_by_one(ctx):
+    """The batched re-gridding (four pairs with different destination grids
+    in one call, one of them without a source-index output) equals the calls
+    one by one, bitwise, and the first pair the oracle."""
+    from paper_1910_01997_amd import surfgn as sg
+    print("case regrid batch of four pairs", flush=True)
+    src_grid = ((600.0, 600.0, 320.0, 240.0), 640, 480, 4)
+    dst_grids = [src_grid, ((420.0, 430.0, 200.0, 150.0), 400, 300, 8),
+                 ((1100.0, 1100.0, 640.0, 360.0), 1280, 720, 4), ((610.0, 600.0, 330.0, 236.0), 650, 490, 16)]
+    m = (640 // 4) * (480 // 4)
+    cases = []
+    for k, dg in enumerate(dst_grids):
+        rng = np.random.default_rng(20 + k)
+        ids = rng.uniform(0.25, 1.0, m).astype(np.float32)
+        ns = np.array([random_unit_cap(rng, 40) for _ in range(m)], np.float32)
+        flags = np.zeros(m, np.uint32)
+        flags[rng.choice(m, 200, replace=False)] = oracle.DEGENERATE
+        last = rng.integers(1, 1000, m).astype(np.uint32)
+        R = rot(rng.normal(size=3), math.radians(3))
+        t = np.array([0.05, -0.02, -0.06]) * (1 + 0.2 * k)
+        cases.append((ids, ns, flags, last, R, t, dg))
+    singles = [_run(ctx, src_grid, *c) for c in cases]
+    srcs, dsts, news, wins = [], [], [], []
+    for ids, ns, flags, last, R, t, dg in cases:
+        src = sg.SurfelState.from_arrays(ids, ns, flags=flags)
+        src.last_update.copy_(torch.as_tensor(last.astype(np.int32), device="cuda"))
+        m1 = (dg[1] // dg[3]) * (dg[2] // dg[3])
+        srcs.append(src)
+        dsts.append(sg.SurfelState.from_arrays(np.full(m1, 7.0, np.float32), np.ones((m1, 3), np.float32)))
+        news.append(torch.full((m1,), 9, dtype=torch.uint8, device="cuda"))
+        wins.append(torch.full((m1,), -5, dtype=torch.int32, device="cuda"))
+    K0, W0, H0, S0 = src_grid
+    sg.sgn_transfer_surfels_batch(ctx.handle, [sg.grid_of(K0, W0, H0, S0)] * 4, [s.c for s in srcs],
+                                  [sg.pose_of(c[4], c[5]) for c in cases],
+                                  [sg.grid_of(*c[6]) for c in cases], [d.c for d in dsts],
+                                  [n.data_ptr() for n in news],
+                                  [w.data_ptr() if k != 2 else 0 for k, w in enumerate(wins)])
+    torch.cuda.synchronize()
+    for k, (dev1, new1, win1) in enumerate(singles):
+        dev = dsts[k].to_host()
+        for f in ("inv_depth", "n", "flags", "cost", "nvalid", "last_update"):
+            assert np.array_equal(dev[f], dev1[f]), (k, f)
+        assert np.array_equal(news[k].cpu().numpy(), new1)
+        if k != 2:
+            assert np.array_equal(wins[k].cpu().numpy(), win1)
+        else:
+            assert np.all(wins[k].cpu().numpy() == -5)           # not written
+    c = cases[0]
+    _check(dsts[0].to_host(), news[0].cpu().numpy(), wins[0].cpu().numpy(),
+           _oracle(src_grid, c[0], c[1], c[2], c[3], c[4], c[5], c[6]))
