@@ -252,30 +252,65 @@ __global__ void init_kernel(const BatchHeader* __restrict__ hdr) {
         const int reach = (int)floorf((br + half) / (float)S);
         float id_sum = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, rx = 0.f, ry = 0.f, rz = 0.f;
         int count = 0;
-        for (int ny = ty - reach; ny <= ty + reach; ++ny) {
-            if (ny < 0 || ny >= gh) continue;
-            for (int nxt = tx - reach; nxt <= tx + reach; ++nxt) {
-                if (nxt < 0 || nxt >= gw) continue;
-                const int j = ny * gw + nxt;
-                if (j == i || K.is_new[j]) continue;
-                if (K.flags[j] & (F_UNINIT | F_DEGENERATE)) continue;
-                // nearest pixel of tile j to the new surfel's centre
-                const float qx = fminf(fmaxf(ux, (float)(S * nxt)), (float)(S * nxt + S - 1));
-                const float qy = fminf(fmaxf(uy, (float)(S * ny)), (float)(S * ny + S - 1));
-                const float ddx = qx - ux, ddy = qy - uy;
-                if (!(ddx * ddx + ddy * ddy < br2)) continue;
-                const float njx = K.nx[j], njy = K.ny[j], njz = K.nz[j];
-                const float jx = (float)(S * nxt) + half, jy = (float)(S * ny) + half;
-                const float rjx = (jx - K.cx) / K.fx, rjy = (jy - K.cy) / K.fy;
-                const float cj = njx * rjx + njy * rjy + njz;
-                if (fabsf(cj) < 1e-6f) continue;
-                // Eq. 3 of plane j at ray r_s: id_j (n_j . r_s) / (n_j . r_j)
-                const float id = K.inv_depth[j] * (njx * rsx + njy * rsy + njz) / cj;
-                if (count == 0) { rx = njx; ry = njy; rz = njz; }
-                const float sg = (njx * rx + njy * ry + njz * rz) < 0.f ? -1.f : 1.f;
-                id_sum += id;
-                sx += sg * njx; sy += sg * njy; sz += sg * njz;
-                ++count;
+        // one neighbour tile (row ny, column nxt) in visiting order, with its
+        // is_new flag, flags and state
+        auto visit = [&](int ny, int nxt, uint8_t nw, uint32_t fl, float idj, float njx, float njy,
+                         float njz) {
+            if (nw) return;
+            if (fl & (F_UNINIT | F_DEGENERATE)) return;
+            // nearest pixel of tile j to the new surfel's centre
+            const float qx = fminf(fmaxf(ux, (float)(S * nxt)), (float)(S * nxt + S - 1));
+            const float qy = fminf(fmaxf(uy, (float)(S * ny)), (float)(S * ny + S - 1));
+            const float ddx = qx - ux, ddy = qy - uy;
+            if (!(ddx * ddx + ddy * ddy < br2)) return;
+            const float jx = (float)(S * nxt) + half, jy = (float)(S * ny) + half;
+            const float rjx = (jx - K.cx) / K.fx, rjy = (jy - K.cy) / K.fy;
+            const float cj = njx * rjx + njy * rjy + njz;
+            if (fabsf(cj) < 1e-6f) return;
+            // Eq. 3 of plane j at ray r_s: id_j (n_j . r_s) / (n_j . r_j)
+            const float id = idj * (njx * rsx + njy * rsy + njz) / cj;
+            if (count == 0) { rx = njx; ry = njy; rz = njz; }
+            const float sg = (njx * rx + njy * ry + njz * rz) < 0.f ? -1.f : 1.f;
+            id_sum += id;
+            sx += sg * njx; sy += sg * njy; sz += sg * njz;
+            ++count;
+        };
+        if (reach == 1) {
+            // the 3 x 3 neighbourhood (the default radius): every load issued
+            // before the first use (out-of-grid slots read the surfel itself
+            // and are skipped)
+            int js[9];
+            bool in[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const int ny = ty - 1 + k / 3, nxt = tx - 1 + k % 3;
+                in[k] = ny >= 0 && ny < gh && nxt >= 0 && nxt < gw && k != 4;
+                js[k] = in[k] ? ny * gw + nxt : i;
+            }
+            uint8_t nw[9];
+            uint32_t fl[9];
+            float idj[9], njx[9], njy[9], njz[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                nw[k] = K.is_new[js[k]];
+                fl[k] = K.flags[js[k]];
+                idj[k] = K.inv_depth[js[k]];
+                njx[k] = K.nx[js[k]];
+                njy[k] = K.ny[js[k]];
+                njz[k] = K.nz[js[k]];
+            }
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                if (in[k]) visit(ty - 1 + k / 3, tx - 1 + k % 3, nw[k], fl[k], idj[k], njx[k], njy[k], njz[k]);
+        } else {
+            for (int ny = ty - reach; ny <= ty + reach; ++ny) {
+                if (ny < 0 || ny >= gh) continue;
+                for (int nxt = tx - reach; nxt <= tx + reach; ++nxt) {
+                    if (nxt < 0 || nxt >= gw) continue;
+                    const int j = ny * gw + nxt;
+                    if (j == i) continue;
+                    visit(ny, nxt, K.is_new[j], K.flags[j], K.inv_depth[j], K.nx[j], K.ny[j], K.nz[j]);
+                }
             }
         }
         if (count == 0) {
