@@ -109,6 +109,38 @@ def test_eight_surfel_groups_batch_equals_plain_and_ragged(ctx):
     assert_parity(res, label="ragged 102x66 tiles 4x2", max_unstable=0.15)
 
 
+def test_autotune_picks_a_4x4_plan_and_restores_the_state(ctx):
+    """The autotuner on a batch of 4x4-surfel keyframes: every trial starts
+    from the caller's surfels (all fields untouched afterwards), the plan it
+    returns is one the kernel has, and an update with it equals, bitwise,
+    the plain form with the same pixels per lane."""
+    sg, engine = sgmod()
+    kfs = [make_keyframe(spec_for_config(2, i), device="cuda") for i in (8, 9, 10)]
+    print("case autotune on three keyframes of the batch workload", flush=True)
+    prm = sg.params(iters=4)
+    ds = [engine.DeviceKeyframe.from_scene(ctx, k) for k in kfs]
+    before = [d.state.to_host() for d in ds]
+    items = sg.batch_array([d.item(render=False, init=False) for d in ds])
+    best = sg.sgn_autotune(ctx.handle, items, len(ds), prm)
+    torch.cuda.synchronize()
+    for d, b in zip(ds, before):
+        h = d.state.to_host()
+        for f in ("inv_depth", "n", "flags", "cost", "nvalid", "last_update"):
+            assert np.array_equal(h[f], b[f]), f
+    shape = (best.tiles_x, best.tiles_y)
+    assert shape in {(4, 1), (2, 2), (1, 4), (4, 2), (2, 4), (4, 4)}, best.as_dict()
+    assert best.groups in (1, 2, 4) and best.lds_stage == 0
+    engine.update_batch(ctx, ds, prm, best)
+    torch.cuda.synchronize()
+    # the plain form with the same lanes per surfel: one group per item
+    plain = sg.plan(best.tiles_x, best.tiles_y, 0, 0, 0, 0, groups=1)
+    for d, k in zip(ds, kfs):
+        p = engine.DeviceKeyframe.from_scene(ctx, k)
+        engine.update_plain(ctx, p, prm, plain)
+        torch.cuda.synchronize()
+        _state_equal(d.state.to_host(), p.state.to_host())
+
+
 def test_repeated_calls_are_deterministic(ctx):
     sg, engine = sgmod()
     kf = make_keyframe(spec_for_config(1), device="cuda")
