@@ -456,11 +456,12 @@ __device__ __forceinline__ Taps load_taps<float>(__amdgpu_buffer_rsrc_t rs, unsi
 
 template <>
 __device__ __forceinline__ Taps load_taps<uint8_t>(__amdgpu_buffer_rsrc_t rs, unsigned o0, unsigned pitch_b) {
-    const unsigned base = o0 & ~3u, sh = o0 << 3;                  // shift amount is mod 32
+    // the byte shift of v_alignbyte is its third operand mod 4
+    const unsigned base = o0 & ~3u;
     const u32x2 va = __builtin_amdgcn_raw_buffer_load_b64(rs, base, 0, 0);
     const u32x2 vb = __builtin_amdgcn_raw_buffer_load_b64(rs, base, pitch_b, 0);
-    const unsigned a = __builtin_amdgcn_alignbit(va.y, va.x, sh);
-    const unsigned b = __builtin_amdgcn_alignbit(vb.y, vb.x, sh);
+    const unsigned a = __builtin_amdgcn_alignbyte(va.y, va.x, o0);
+    const unsigned b = __builtin_amdgcn_alignbyte(vb.y, vb.x, o0);
     Taps t;
     t.i00 = (float)(a & 0xffu);
     t.i01 = (float)((a >> 8) & 0xffu);
@@ -505,13 +506,13 @@ __device__ __forceinline__ float half_lo_fma(float a, float b, unsigned pk) {
 template <>
 __device__ __forceinline__ Lerp lerp_rows<_Float16>(__amdgpu_buffer_rsrc_t rs, unsigned o0, unsigned pitch_b,
                                                     float ax) {
-    // pitch_b is a multiple of 4; the funnel shift uses its amount mod 32,
-    // so o0 * 8 shifts by 8 (o0 mod 4) bits
-    const unsigned base = o0 & ~3u, sh = o0 << 3;
+    // pitch_b is a multiple of 4; the byte funnel shift (v_alignbyte) takes
+    // its amount mod 4, so o0 itself shifts by o0 mod 4 bytes
+    const unsigned base = o0 & ~3u;
     const u32x2 va = __builtin_amdgcn_raw_buffer_load_b64(rs, base, 0, 0);
     const u32x2 vb = __builtin_amdgcn_raw_buffer_load_b64(rs, base, pitch_b, 0);
-    const unsigned a = __builtin_amdgcn_alignbit(va.y, va.x, sh);   // (I(x0), I(x0+1)) of row y0
-    const unsigned b = __builtin_amdgcn_alignbit(vb.y, vb.x, sh);   // of row y0 + 1
+    const unsigned a = __builtin_amdgcn_alignbyte(va.y, va.x, o0);  // (I(x0), I(x0+1)) of row y0
+    const unsigned b = __builtin_amdgcn_alignbyte(vb.y, vb.x, o0);  // of row y0 + 1
     Lerp l;
     l.d0 = half_pair_diff(a);
     l.d1 = half_pair_diff(b);
