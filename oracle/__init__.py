@@ -32,7 +32,7 @@ def build(force: bool = True) -> str:
     src = os.path.join(_HERE, "sgo.c")
     if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= os.path.getmtime(src):
         return LIB_PATH
-    tmp = LIB_PATH + ".tmp"
+    tmp = f"{LIB_PATH}.tmp{os.getpid()}"
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
            "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp, src, "-lm"]
     subprocess.run(cmd, check=True)
@@ -72,7 +72,7 @@ class GridC(C.Structure):
 class ParamsC(C.Structure):
     _fields_ = [("iters", C.c_int32), ("huber_k", C.c_double), ("depth_only", C.c_int32),
                 ("beta_r", C.c_double), ("stamp", C.c_uint32), ("lm_lambda", C.c_double),
-                ("perturb", C.c_double), ("perturb_seed", C.c_uint32)]
+                ("perturb", C.c_double), ("perturb_seed", C.c_uint32), ("perturb_parts", C.c_int32)]
 
 
 _lib = None
@@ -145,6 +145,9 @@ def lib():
         L.sgo_disc_transfer.argtypes = [C.POINTER(Intrinsics), C.POINTER(Intrinsics), C.c_int32,
                                         C.c_int32, C.POINTER(Pose), C.POINTER(SurfelsC), dp, dp,
                                         C.c_int32, C.POINTER(SurfelsC), dp, dp, C.c_int32, ip, ip]
+        L.sgo_costs_at.restype = C.c_int
+        L.sgo_costs_at.argtypes = [C.POINTER(KeyframeC), dp, dp, dp, dp, ip, C.c_int32, C.c_double,
+                                   dp, dp, C.c_double, dp, ip]
         L.sgo_set_threads.restype = None
         L.sgo_set_threads.argtypes = [C.c_int32]
         L.sgo_max_threads.restype = C.c_int32
@@ -192,12 +195,13 @@ class OracleParams:
     lm_lambda: float = 0.0
     perturb: float = 0.0        # conditioning probe (tests only), 0 = off
     perturb_seed: int = 0
+    perturb_parts: int = 0      # 0 both, 1 normal equations only, 2 state only
 
     def c(self, patch: int) -> ParamsC:
         br = float(self.beta_r) if self.beta_r is not None else float(patch)
         return ParamsC(int(self.iters), float(self.huber_k), int(bool(self.depth_only)), br,
                        int(self.stamp), float(self.lm_lambda), float(self.perturb),
-                       int(self.perturb_seed))
+                       int(self.perturb_seed), int(self.perturb_parts))
 
 
 class OracleKeyframe:
@@ -501,6 +505,29 @@ def disc_transfer(src_K, dst_K, dst_size, R, t, st, ux, uy, capacity=None):
                                 _ip(idx), C.byref(landed))
     out = {k: v[:n] for k, v in out.items()}
     return out, (dux[:n], duy[:n]), idx[:n], int(landed.value)
+
+
+def costs_at(kf: OracleKeyframe, inv_depth, normals, idx, huber_k=9.0 / 255.0, disc=None):
+    """Huber cost and valid count of surfels idx at the states (inv_depth[i],
+    normals[i]) (arrays over all surfels; normals renormalised); disc =
+    (ux, uy, radius) for disc surfels."""
+    ids = _f64(inv_depth).reshape(-1)
+    nn = _f64(normals).reshape(-1, 3)
+    nn = nn / np.linalg.norm(nn, axis=1, keepdims=True)
+    nx, ny, nz = (np.ascontiguousarray(nn[:, k]) for k in range(3))
+    ix = np.ascontiguousarray(np.asarray(idx, np.int32).reshape(-1))
+    cost = np.zeros(ix.size)
+    nv = np.zeros(ix.size, np.int32)
+    if disc is not None:
+        ux, uy = _f64(disc[0]).reshape(-1), _f64(disc[1]).reshape(-1)
+        rc = lib().sgo_costs_at(C.byref(kf.c), _dp(ids), _dp(nx), _dp(ny), _dp(nz), _ip(ix), int(ix.size),
+                                float(huber_k), _dp(ux), _dp(uy), float(disc[2]), _dp(cost), _ip(nv))
+    else:
+        rc = lib().sgo_costs_at(C.byref(kf.c), _dp(ids), _dp(nx), _dp(ny), _dp(nz), _ip(ix), int(ix.size),
+                                float(huber_k), None, None, 0.0, _dp(cost), _ip(nv))
+    if rc != 0:
+        raise RuntimeError("sgo_costs_at failed")
+    return cost, nv
 
 
 def set_threads(n: int):

@@ -442,7 +442,9 @@ static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_param
             flags |= SGO_FEW_SAMPLES;
             continue;
         }
-        if (p->perturb > 0.0) {
+        const int probe_ne = p->perturb > 0.0 && (p->perturb_parts & 1 || p->perturb_parts == 0);
+        const int probe_state = p->perturb > 0.0 && (p->perturb_parts & 2 || p->perturb_parts == 0);
+        if (probe_ne) {
             /* probe: relative noise on the normal equations as well (float
              * accumulation of J^T W J and J^T W r reaches the step scaled by
              * the condition number, which state noise alone does not model) */
@@ -479,10 +481,10 @@ static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_param
             continue;
         }
         if (lambda > 0.0) {
-            /* accept unless the mean Huber cost rises by more than a
-             * relative 1e-4 (below that a rise is at the float noise of a
-             * device's cost sums); a candidate plane that contains the
-             * centre ray is refused */
+            /* Levenberg-Marquardt acceptance: the candidate is taken when
+             * the mean Huber cost per valid sample does not rise (a rise of
+             * any size is refused); a candidate plane that contains the
+             * centre ray is refused as well */
             if (fabs(dot3(n_new, rs)) < 1e-6) {
                 flags |= SGO_REJECTED;
                 lambda *= 10.0;
@@ -491,13 +493,13 @@ static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_param
             double H2[9], b2v[3], cost2;
             int32_t nv2 = linearize(kf, sp, id_new, n_new, p->huber_k, p->depth_only, H2,
                                     b2v, &cost2, s->margin ? &margin : NULL);
-            if (nv2 < 3 || !(cost2 / nv2 <= (cost / nvalid) * (1.0 + 1e-4))) {
+            if (nv2 < 3 || !(cost2 / nv2 <= cost / nvalid)) {
                 lambda *= 10.0;
                 continue;
             }
             lambda = fmax(lambda * 0.1, 1e-9);
         }
-        if (p->perturb > 0.0) {
+        if (probe_state) {
             id_new *= 1.0 + p->perturb * probe_uniform(p->perturb_seed, i, it, 0);
             if (!p->depth_only) {
                 for (int k = 0; k < 3; ++k)
@@ -550,6 +552,28 @@ int sgo_disc_optimize(const sgo_keyframe* kf, sgo_surfels* s, const double* ux, 
             support sp = disc_support(kf->kf.width, kf->kf.height, ux[i], uy[i], radius);
             optimize_one(kf, s, p, i, &sp);
         }
+    }
+    return 0;
+}
+
+/* Huber cost (Eq. 5) and valid-sample count of listed surfels at given
+ * states (test use: judging where an optimisation ended). */
+int sgo_costs_at(const sgo_keyframe* kf, const double* id_s, const double* nx, const double* ny,
+                 const double* nz, const int32_t* idx, int32_t n, double huber_k,
+                 const double* disc_ux, const double* disc_uy, double radius, double* cost_out,
+                 int32_t* nvalid_out) {
+    if (!kf || !id_s || !nx || !ny || !nz || !idx || !cost_out || !nvalid_out) return -1;
+    if (!disc_ux && kf->patch <= 0) return -1;
+    const int gw = disc_ux ? 1 : kf->kf.width / kf->patch;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int32_t k = 0; k < n; ++k) {
+        const int32_t i = idx[k];
+        support sp = disc_ux ? disc_support(kf->kf.width, kf->kf.height, disc_ux[i], disc_uy[i], radius)
+                             : tile_support(kf, i % gw, i / gw);
+        double nn[3] = {nx[i], ny[i], nz[i]};
+        double H[9], b[3], c;
+        nvalid_out[k] = linearize(kf, &sp, id_s[i], nn, huber_k, 0, H, b, &c, NULL);
+        cost_out[k] = c;
     }
     return 0;
 }

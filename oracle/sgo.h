@@ -66,6 +66,8 @@ typedef struct {
                                  by (1 + perturb * u), u in [-1, 1) from a counter hash of
                                  (perturb_seed, surfel, iteration, component) */
     uint32_t perturb_seed;
+    int32_t perturb_parts;    /* which parts the probe perturbs: 0 or 3 = both, 1 = the normal
+                                 equations only, 2 = the state after accepted steps only */
 } sgo_params;
 
 enum {
@@ -121,6 +123,15 @@ double sgo_kappa_eq(const double H[9]);
 /* Gauss-Newton over all surfels (subset == NULL) or the listed surfel indices. */
 int sgo_optimize_keyframe(const sgo_keyframe* kf, sgo_surfels* s, const sgo_params* p,
                           const int32_t* subset, int32_t n_subset);
+
+/* Huber cost and valid-sample count of the surfels idx[0 .. n-1] at the
+ * states (id_s[i], n[i]) (arrays indexed by surfel): tiles, or discs of the
+ * given radius centred at (disc_ux[i], disc_uy[i]) when disc_ux is not NULL.
+ * Test use: judging the end points of different optimisation runs. */
+int sgo_costs_at(const sgo_keyframe* kf, const double* id_s, const double* nx, const double* ny,
+                 const double* nz, const int32_t* idx, int32_t n, double huber_k,
+                 const double* disc_ux, const double* disc_uy, double radius, double* cost_out,
+                 int32_t* nvalid_out);
 
 /* Neighbour-plane initialisation of surfels with is_new[i] != 0. */
 int sgo_init_from_neighbours(const sgo_keyframe* kf, sgo_surfels* s, const uint8_t* is_new,

@@ -614,6 +614,49 @@ def test_gauss_newton_reaches_the_brute_force_minimum():
     assert best[1] == (0.0, 0.0, 0.0)
 
 
+def test_costs_at_matches_an_independent_cost():
+    """The cost evaluator the parity tests use to judge end points (Huber cost
+    of Eq. 5 at given states, tiles and discs) against the plane homography,
+    scipy's bilinear interpolation and the Huber norm, on several surfels
+    and perturbed states at once."""
+    okf, ids, ns, rng = _construction_ii(seed=41)
+    noisy = okf._kf_arr + np.random.default_rng(42).normal(0, 2 / 255, okf._kf_arr.shape)
+    K = (80.0, 80.0, 32.0, 24.0)
+    R = np.array(okf._poses[0].R[:]).reshape(3, 3)
+    t = np.array(okf._poses[0].t[:])
+    okn = oracle.OracleKeyframe(K, noisy, okf._nbr_arrs[0][None], R[None], t[None], 8)
+    k = 9 / 255
+    I1 = okf._nbr_arrs[0]
+    H_, W_ = noisy.shape
+    idv = ids * rng.uniform(0.97, 1.03, ids.size)
+    nv = np.array([rot(np.cross(n, rng.normal(size=3)), math.radians(rng.uniform(0, 4))) @ n for n in ns])
+    pick = np.array([3, 10, 11, 18, 20, 26], np.int32)
+    ux = np.array([8 * (i % 8) + 3.5 + rng.uniform(-2, 2) for i in range(ids.size)])
+    uy = np.array([8 * (i // 8) + 3.5 + rng.uniform(-2, 2) for i in range(ids.size)])
+
+    def cost(us, id_s, n, pix):
+        ps = ray(K, *us) / id_s
+        Hm = plane_homography(K, R, t, n, float(n @ ps))
+        c, v = 0.0, 0
+        for (x, y) in pix:
+            xp, yp = apply_h(Hm, x, y)
+            if 0 <= xp < W_ - 1 and 0 <= yp < H_ - 1:
+                c += huber(bilinear_scipy(I1, xp, yp) - noisy[y, x], k)
+                v += 1
+        return c, v
+
+    got, gnv = oracle.costs_at(okn, idv, nv, pick, k)
+    dgot, dnv = oracle.costs_at(okn, idv, nv, pick, k, disc=(ux, uy, 5.5))
+    for j, i in enumerate(pick):
+        tx, ty = i % 8, i // 8
+        tile = [(8 * tx + px, 8 * ty + py) for py in range(8) for px in range(8)]
+        c, v = cost((8 * tx + 3.5, 8 * ty + 3.5), idv[i], nv[i], tile)
+        assert got[j] == pytest.approx(c, rel=1e-9) and gnv[j] == v
+        disc = [(x, y) for y in range(H_) for x in range(W_) if (x - ux[i]) ** 2 + (y - uy[i]) ** 2 < 5.5 ** 2]
+        c, v = cost((ux[i], uy[i]), idv[i], nv[i], disc)
+        assert dgot[j] == pytest.approx(c, rel=1e-9) and dnv[j] == v
+
+
 # --- depth-only ablation ------------------------------------------------------
 
 def test_depth_only_matches_one_dimensional_search():
@@ -970,6 +1013,55 @@ def test_levenberg_marquardt_refuses_a_step_that_raises_the_mean_cost():
         if found >= 3:
             break
     assert found >= 1, "no cost-raising Gauss-Newton step found"
+
+
+@pytest.mark.parametrize("eps", [5e-5, -5e-5, 1e-6, -1e-6])
+def test_levenberg_marquardt_accepts_exactly_when_the_mean_cost_does_not_rise(eps):
+    """The damped variant takes a candidate when its mean Huber cost per valid
+    sample does not rise, and refuses any rise.  On a keyframe built so that
+    the one damped step changes the mean cost by the factor 1 + eps (checked
+    here by an independent evaluation of the cost: the sideways warp
+    x + fx t_x id, scipy's bilinear interpolation and the Huber norm), one
+    iteration must refuse the step for eps > 0 (state kept, no stamp) and
+    take it for eps < 0; plain Gauss-Newton takes it either way."""
+    from tests import lm_construction as lc
+    lam = 2.0 ** -20
+    case = lc.build(eps, lam)
+    gw = lc.W // lc.S
+    tx, ty = lc.SURFEL % gw, lc.SURFEL // gw
+    fxt = lc.K[0] * case["t"][0][0]
+
+    def cost(id_s):
+        tot, nv = 0.0, 0
+        for y in range(ty * lc.S, ty * lc.S + lc.S):
+            for x in range(tx * lc.S, tx * lc.S + lc.S):
+                xp = x + fxt * id_s
+                assert 0 <= xp < lc.W - 1
+                for f in range(lc.N_FRAMES):
+                    r = bilinear_scipy(case["nbrs"][f], xp, y) - case["kf"][y, x]
+                    tot += huber(r, 9.0 / 255.0)
+                    nv += 1
+        return tot / nv
+
+    ratio = cost(case["candidate_id"]) / cost(lc.ID0)
+    assert ratio == pytest.approx(1.0 + eps, abs=1e-9)
+    okf = oracle.OracleKeyframe(lc.K, case["kf"], case["nbrs"], case["R"], case["t"], lc.S)
+    one = np.array([lc.SURFEL], np.int32)
+    for lm_lambda in (lam, 0.0):
+        st = oracle.new_state(case["init_id"], case["init_n"])
+        oracle.optimize(okf, st, oracle.OracleParams(iters=1, depth_only=True, lm_lambda=lm_lambda,
+                                                     stamp=7), subset=one)
+        taken = lm_lambda == 0.0 or eps < 0
+        i = lc.SURFEL
+        if taken:
+            want = case["candidate_id"] if lm_lambda > 0 else lc.ID0 + 0.5
+            assert st["inv_depth"][i] == pytest.approx(want, rel=1e-12)
+            assert st["last_update"][i] == 7
+        else:
+            assert st["inv_depth"][i] == lc.ID0
+            assert st["last_update"][i] == 0
+        assert st["nvalid"][i] == 48
+        assert st["flags"][i] == 0
 
 
 # --- conditioning probe (test facility) --------------------------------------
