@@ -33,8 +33,21 @@
  *     output arrays are DEVICE pointers (on the context's device).  The
  *     descriptor arrays themselves (sgn_keyframe.nbr, .pose, sgn_batch_item
  *     arrays) are HOST memory, read during the call only.
- *   - The context owns small device tables (descriptors, per-frame constants,
- *     work counters), a pinned host staging ring and captured HIP graphs.
+ *   - The context owns a descriptor table of fixed capacity (SGN_MAX_BATCH
+ *     keyframes or keyframe pairs and SGN_MAX_BATCH_FRAMES neighbour frames
+ *     per call; about 2 MB on the device and four times that in pinned host
+ *     staging memory), the work-queue counters, timing events and captured
+ *     HIP graphs.  sgn_create allocates all of it; no other call allocates
+ *     device or pinned memory.
+ *   - Calls that need scratch memory (re-gridding, disc render and
+ *     placement, the autotuner's state snapshot) take a caller-provided
+ *     workspace `ws` of `ws_bytes` bytes: device memory, 256-byte aligned, at
+ *     least the size the matching sgn_*_workspace_bytes function returns for
+ *     the same arguments.  Its contents need not be initialised and are
+ *     undefined afterwards; it must stay allocated until the call's work on
+ *     the context's stream has completed.  A missing, misaligned or
+ *     undersized workspace is an argument error (SGN_E_INVALID, nothing
+ *     enqueued).
  *   - All work is enqueued asynchronously on the context's stream; the caller
  *     synchronises that stream before reading results.  Calls on one context
  *     must come from one host thread at a time.
@@ -105,6 +118,8 @@ typedef struct {
 } sgn_keyframe;
 
 #define SGN_MAX_NBR 16
+#define SGN_MAX_BATCH 1024          /* keyframes (or keyframe pairs) per call */
+#define SGN_MAX_BATCH_FRAMES 8192   /* neighbour frames per call, all keyframes together */
 
 /* Surfel state, structure of arrays of length gw * gh (device pointers).
  * inv_depth, nx, ny, nz, flags are read and written; cost, nvalid and
@@ -129,12 +144,11 @@ typedef struct {
     float lm_lambda;            /* 0: Gauss-Newton.  > 0: Levenberg-Marquardt (the method
                                    names it; the paper gives no schedule): each iteration
                                    solves (H + lambda diag H) d = -b, evaluates the Huber cost
-                                   at the candidate and accepts it unless the mean cost per
-                                   valid sample rises by more than a relative 1e-4 (then
-                                   lambda /= 10, floor 1e-9), else keeps the state (lambda
-                                   *= 10); a candidate plane containing the centre ray is
-                                   refused.  lm_lambda is the starting lambda of every
-                                   surfel. */
+                                   at the candidate and accepts it when the mean cost per
+                                   valid sample does not rise (then lambda /= 10, floor 1e-9),
+                                   else keeps the state (lambda *= 10); a candidate plane
+                                   containing the centre ray is refused.  lm_lambda is the
+                                   starting lambda of every surfel. */
 } sgn_params;
 
 /* Launch plan for the fused Gauss-Newton kernel (chosen by sgn_autotune or
@@ -225,10 +239,19 @@ sgn_status sgn_render_inverse_depth(sgn_ctx* ctx, const sgn_keyframe* kf,
 sgn_status sgn_optimize_batch(sgn_ctx* ctx, const sgn_batch_item* items, int32_t n_items,
                               const sgn_params* params, const sgn_plan* plan /* NULL: default */);
 
-/* Time candidate plans on a sample batch (the surfel state is restored after
- * every trial) and return the fastest in *out (host). */
+/* Time candidate plans on a sample batch and return the fastest in *out
+ * (host).  The surfel state is snapshotted into the workspace before the
+ * first trial and restored from it after every trial, so the items' state is
+ * unchanged on return.  Synchronous (waits for the trials).  ws: see
+ * sgn_autotune_workspace_bytes. */
 sgn_status sgn_autotune(sgn_ctx* ctx, const sgn_batch_item* sample, int32_t n_items,
-                        const sgn_params* params, sgn_plan* out);
+                        const sgn_params* params, sgn_plan* out, void* ws, size_t ws_bytes);
+
+/* Workspace bytes of sgn_autotune for these items: 256-byte aligned copies of
+ * the eight state arrays of every item (about 32 bytes per surfel).  0 when
+ * the items are invalid (n_items outside [1, SGN_MAX_BATCH], null array, bad
+ * patch or size). */
+size_t sgn_autotune_workspace_bytes(int32_t n_items, const sgn_batch_item* sample);
 
 /* A keyframe's surfel grid for re-gridding: intrinsics, image size and tile
  * edge S (4, 8 or 16); the grid is (width / S) x (height / S) tiles. */
@@ -250,25 +273,32 @@ typedef struct {
  * the two grids (all fields written for dst; cost and nvalid are zeroed,
  * last_update is the winner's).  dst_is_new: device [dst tiles];
  * dst_src_index: device [dst tiles] or NULL (winning source index or -1).
- * The context keeps a scratch buffer of 12 bytes per destination tile,
- * allocated on first use and grown as needed; src and dst must not overlap. */
+ * src and dst must not overlap.  ws: see sgn_transfer_workspace_bytes. */
 sgn_status sgn_transfer_surfels(sgn_ctx* ctx, const sgn_grid* src_grid, const sgn_surfels* src,
                                 const sgn_pose* pose, const sgn_grid* dst_grid, sgn_surfels* dst,
-                                uint8_t* dst_is_new, int32_t* dst_src_index);
+                                uint8_t* dst_is_new, int32_t* dst_src_index, void* ws,
+                                size_t ws_bytes);
+
+/* Workspace bytes of re-gridding into the n destination grids dst_grids
+ * (host array): a 64-bit landing key and a 32-bit winner index per
+ * destination tile, 12 bytes per tile plus alignment.  0 when n is outside
+ * [1, SGN_MAX_BATCH], dst_grids is null or a grid is invalid. */
+size_t sgn_transfer_workspace_bytes(int32_t n, const sgn_grid* dst_grids);
 
 /* sgn_transfer_surfels for n keyframe pairs at once (Eq. 10, Surfel
  * reference frame change): four launches for the whole batch, the same
  * results as n calls (pairs share nothing).  Pair k takes src_grids[k],
  * srcs[k], poses[k], dst_grids[k], dsts[k], dst_is_new[k] and
  * dst_src_index[k] (dst_src_index itself may be NULL, as may its entries);
- * all arrays are host memory read during the call.  The context's scratch
- * holds 12 bytes per destination tile of the whole batch.  Errors: as
+ * all arrays are host memory read during the call.  ws: see
+ * sgn_transfer_workspace_bytes(n, dst_grids).  Errors: as
  * sgn_transfer_surfels for any pair (nothing enqueued), SGN_E_INVALID for
- * n < 1 or a null array. */
+ * n < 1 or a null array, SGN_E_UNSUPPORTED for n > SGN_MAX_BATCH. */
 sgn_status sgn_transfer_surfels_batch(sgn_ctx* ctx, int32_t n, const sgn_grid* src_grids,
                                       const sgn_surfels* srcs, const sgn_pose* poses,
                                       const sgn_grid* dst_grids, const sgn_surfels* dsts,
-                                      uint8_t* const* dst_is_new, int32_t* const* dst_src_index);
+                                      uint8_t* const* dst_is_new, int32_t* const* dst_src_index,
+                                      void* ws, size_t ws_bytes);
 
 /* ------------------------------------------------------------ disc surfels
  *
@@ -307,17 +337,23 @@ sgn_status sgn_disc_optimize(sgn_ctx* ctx, const sgn_disc_item* items, int32_t n
  * inv_depth_out: device float [height * width] (row-major, width per row,
  * 0 = no measurement); index_out: device int32 of the same shape (winning
  * surfel, -1 = none) or NULL.  Reads only the item's surfels, intrinsics and
- * image size.  The context keeps a scratch buffer of 84 bytes per surfel
- * and 8 bytes per 16 x 16-pixel tile. */
+ * image size.  ws: see sgn_disc_render_workspace_bytes(1, item). */
 sgn_status sgn_disc_render(sgn_ctx* ctx, const sgn_disc_item* item, float* inv_depth_out,
-                           int32_t* index_out);
+                           int32_t* index_out, void* ws, size_t ws_bytes);
 
-/* sgn_disc_render for n_items keyframes in one pass (four launches in all):
+/* sgn_disc_render for n_items keyframes in one pass (seven launches in all):
  * inv_depth_outs and index_outs are host arrays of n_items device pointers
- * (index_outs, or any of its entries, may be NULL).  The scratch holds 12
- * bytes per pixel of every keyframe. */
+ * (index_outs, or any of its entries, may be NULL).  ws: see
+ * sgn_disc_render_workspace_bytes(n_items, items). */
 sgn_status sgn_disc_render_batch(sgn_ctx* ctx, const sgn_disc_item* items, int32_t n_items,
-                                 float* const* inv_depth_outs, int32_t* const* index_outs);
+                                 float* const* inv_depth_outs, int32_t* const* index_outs, void* ws,
+                                 size_t ws_bytes);
+
+/* Workspace bytes of a disc render of these items (host array): a raster
+ * record (48 bytes) and up to nine tile-list entries (36 bytes) per surfel,
+ * and 8 bytes per 16 x 16-pixel render tile, plus alignment.  Depends only
+ * on the items' image sizes and counts.  0 when the items are invalid. */
+size_t sgn_disc_render_workspace_bytes(int32_t n_items, const sgn_disc_item* items);
 
 /* Parameters of the empty-area search (the paper leaves alpha and beta open). */
 typedef struct {
@@ -347,7 +383,12 @@ typedef struct {
  * learn the new count. */
 sgn_status sgn_disc_place(sgn_ctx* ctx, const sgn_disc_item* item, const int32_t* index_map,
                           int32_t capacity, const sgn_disc_place_params* params,
-                          int32_t* counts_out);
+                          int32_t* counts_out, void* ws, size_t ws_bytes);
+
+/* Workspace bytes of a placement of these items with this lattice spacing:
+ * one byte per lattice candidate, plus alignment.  Depends only on the
+ * items' image sizes.  0 when the items or the spacing are invalid. */
+size_t sgn_disc_place_workspace_bytes(int32_t n_items, const sgn_disc_item* items, int32_t spacing);
 
 /* sgn_disc_place for n keyframes at once (Surfel Initialization section):
  * three launches for the whole batch instead of three per keyframe, with
@@ -355,13 +396,14 @@ sgn_status sgn_disc_place(sgn_ctx* ctx, const sgn_disc_item* item, const int32_t
  * items[i], index_maps[i] (device int32 [height * width]), capacities[i] and
  * counts_outs[i] (device int32[2]) are keyframe i's arguments of
  * sgn_disc_place; the three arrays of pointers and counts are host memory
- * read during the call; params apply to every keyframe.  The context's
- * scratch holds one byte per candidate of the whole batch.  Errors: as
+ * read during the call; params apply to every keyframe.  ws: see
+ * sgn_disc_place_workspace_bytes(n, items, params->spacing).  Errors: as
  * sgn_disc_place for any keyframe (nothing enqueued), SGN_E_INVALID for
  * n < 1 or a null array. */
 sgn_status sgn_disc_place_batch(sgn_ctx* ctx, const sgn_disc_item* items, int32_t n,
                                 const int32_t* const* index_maps, const int32_t* capacities,
-                                const sgn_disc_place_params* params, int32_t* const* counts_outs);
+                                const sgn_disc_place_params* params, int32_t* const* counts_outs,
+                                void* ws, size_t ws_bytes);
 
 /* Surfel reference-frame change (Eq. 10) for disc surfels, which stay discs:
  * a usable surfel of src (no DEGENERATE or UNINIT flag, id_s > 0) moves to

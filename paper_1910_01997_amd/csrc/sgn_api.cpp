@@ -59,7 +59,8 @@ struct sgn_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int cus = 0;
-    // descriptor table: host staging ring (pinned) + one device copy
+    // descriptor table of fixed capacity (kTableBytes, allocated by
+    // sgn_create): host staging ring (pinned) + one device copy
     size_t table_cap = 0;
     void* host_ring[kRingSlots] = {};
     hipEvent_t ring_ev[kRingSlots] = {};
@@ -77,11 +78,6 @@ struct sgn_ctx {
     // graphs
     bool use_graphs = true;
     std::map<GraphKey, hipGraphExec_t> graphs;
-    // scratch of re-gridding (12 bytes per destination tile) and of the disc
-    // render (84 bytes per surfel, 8 per 16 x 16 render tile) and placement
-    // (one byte per candidate), grown on demand
-    void* scratch = nullptr;
-    size_t scratch_cap = 0;
 };
 
 namespace {
@@ -100,26 +96,21 @@ TableLayout layout_for(int n_kf, int n_frames) {
     return L;
 }
 
-sgn_status ensure_table(sgn_ctx* c, size_t bytes) {
-    if (bytes <= c->table_cap) return SGN_OK;
-    size_t cap = std::max(bytes, c->table_cap * 2);
-    cap = std::max(cap, size_t(64) << 10);
-    // the stream may still read the old buffers
-    SGN_HIP(hipStreamSynchronize(c->stream));
-    for (int i = 0; i < kRingSlots; ++i) {
-        if (c->host_ring[i]) SGN_HIP(hipHostFree(c->host_ring[i]));
-        c->host_ring[i] = nullptr;
-        c->ring_used[i] = false;
-    }
-    if (c->dev_table) SGN_HIP(hipFree(c->dev_table));
-    c->dev_table = nullptr;
-    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
-    c->graphs.clear();
-    for (int i = 0; i < kRingSlots; ++i)
-        if (hipHostMalloc(&c->host_ring[i], cap, hipHostMallocDefault) != hipSuccess)
-            return fail(SGN_E_NOMEM, "pinned staging allocation failed");
-    if (hipMalloc(&c->dev_table, cap) != hipSuccess) return fail(SGN_E_NOMEM, "device table allocation failed");
-    c->table_cap = cap;
+// Capacity of the context's descriptor table: the largest batch one call
+// may describe (SGN_MAX_BATCH keyframes or keyframe pairs, SGN_MAX_BATCH_FRAMES
+// neighbour frames), fixed at sgn_create so that no call allocates.
+size_t table_bytes_needed() {
+    size_t b = layout_for(SGN_MAX_BATCH, SGN_MAX_BATCH_FRAMES).total;
+    const size_t per_pair = std::max(std::max(sizeof(RegridArgs), sizeof(DiscRenderItem)),
+                                     std::max(sizeof(DiscPlaceArgs), sizeof(DiscTransferArgs)));
+    return std::max(b, per_pair * (size_t)SGN_MAX_BATCH);
+}
+
+sgn_status check_table(const sgn_ctx* c, size_t bytes) {
+    if (bytes > c->table_cap)
+        return fail(SGN_E_UNSUPPORTED, "batch larger than the context's descriptor table (at most " +
+                                           std::to_string(SGN_MAX_BATCH) + " keyframes and " +
+                                           std::to_string(SGN_MAX_BATCH_FRAMES) + " neighbour frames per call)");
     return SGN_OK;
 }
 
@@ -135,6 +126,8 @@ sgn_status check_image(const sgn_image& im, int W, int H, int dtype, const char*
         return fail(SGN_E_UNSUPPORTED, std::string(what) + ": scale must be 1 for f32/f16 storage");
     if ((uint64_t)im.pitch * (uint64_t)im.height * dtype_size(im.dtype) >= (1ull << 31))
         return fail(SGN_E_UNSUPPORTED, std::string(what) + ": image larger than 2 GiB");
+    if ((uint64_t)im.pitch * dtype_size(im.dtype) >= (1ull << 24))
+        return fail(SGN_E_UNSUPPORTED, std::string(what) + ": row pitch of 16 MiB or more");
     if (((uint64_t)im.pitch * dtype_size(im.dtype)) % 4 != 0)
         return fail(SGN_E_UNSUPPORTED, std::string(what) + ": row pitch must be a multiple of 4 bytes");
     if (((uintptr_t)im.data) % 4 != 0)
@@ -178,17 +171,109 @@ void next_timing_slot(sgn_ctx* c) {
     ++c->gn_launches;
 }
 
-sgn_status ensure_scratch(sgn_ctx* c, size_t need) {
-    if (need <= c->scratch_cap) return SGN_OK;
-    if (c->scratch) {
-        SGN_HIP(hipStreamSynchronize(c->stream));
-        SGN_HIP(hipFree(c->scratch));
-        c->scratch = nullptr;
-        c->scratch_cap = 0;
-    }
-    if (hipMalloc(&c->scratch, need) != hipSuccess) return fail(SGN_E_NOMEM, "scratch allocation failed");
-    c->scratch_cap = need;
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Caller-provided workspace: device memory of at least the size the
+// matching sgn_*_workspace_bytes function returns, 256-byte aligned.
+sgn_status check_ws(const void* ws, size_t ws_bytes, size_t need) {
+    if (need == 0) return fail(SGN_E_INVALID, "invalid arguments for the workspace size");
+    if (!ws) return fail(SGN_E_INVALID, "null workspace");
+    if (((uintptr_t)ws) % 256 != 0) return fail(SGN_E_INVALID, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(SGN_E_INVALID, "workspace too small: " + std::to_string(need) + " bytes needed, " +
+                                       std::to_string(ws_bytes) + " given");
     return SGN_OK;
+}
+
+// Tiles of a surfel grid, or -1 when the grid is not valid.
+int64_t grid_tiles(const sgn_grid& g) {
+    if (g.patch != 4 && g.patch != 8 && g.patch != 16) return -1;
+    if (g.width < g.patch || g.height < g.patch || g.width > 16384 || g.height > 16384) return -1;
+    return (int64_t)(g.width / g.patch) * (g.height / g.patch);
+}
+
+// Re-gridding workspace: the closest landing (64-bit key) and the winning
+// source index of every destination tile of the batch.
+struct TransferWs {
+    size_t best_off, win_off, total;
+};
+TransferWs transfer_ws(int64_t total_dst) {
+    TransferWs w;
+    w.best_off = 0;
+    w.win_off = align256((size_t)total_dst * sizeof(unsigned long long));
+    w.total = w.win_off + align256((size_t)total_dst * sizeof(int32_t));
+    return w;
+}
+
+// Disc render workspace: raster records [surfels], tile counts [tiles], list
+// starts [tiles + 1], scan block sums [ceil(tiles / 1024)], tile lists
+// [kDiscMaxTilesPerSurfel * surfels].
+struct DiscRenderWs {
+    size_t rec_off, count_off, start_off, block_off, list_off, total;
+};
+DiscRenderWs disc_render_ws(int64_t surfels, int64_t tiles) {
+    DiscRenderWs w;
+    const size_t n_blocks = (size_t)((tiles + 1023) / 1024);
+    w.rec_off = 0;
+    w.count_off = align256(sizeof(DiscRaster) * (size_t)surfels);
+    w.start_off = w.count_off + align256(sizeof(int32_t) * (size_t)tiles);
+    w.block_off = w.start_off + align256(sizeof(int32_t) * ((size_t)tiles + 1));
+    w.list_off = w.block_off + align256(sizeof(int32_t) * n_blocks);
+    w.total = w.list_off + align256(sizeof(int32_t) * (size_t)kDiscMaxTilesPerSurfel * (size_t)surfels);
+    return w;
+}
+
+// Disc render totals of a batch (surfels, 16 x 16 render tiles); false when
+// an item's size or count is out of range.
+bool disc_render_totals(const sgn_disc_item* items, int n, int64_t& surfels, int64_t& tiles) {
+    surfels = tiles = 0;
+    if (!items || n < 1 || n > SGN_MAX_BATCH) return false;
+    for (int i = 0; i < n; ++i) {
+        const int W = items[i].kf.kf.width, H = items[i].kf.kf.height;
+        if (W < 2 || H < 2 || W > 16384 || H > 16384 || items[i].count < 0) return false;
+        surfels += items[i].count;
+        tiles += (int64_t)((W + kRenderTile - 1) / kRenderTile) * ((H + kRenderTile - 1) / kRenderTile);
+    }
+    return surfels <= (int64_t)INT32_MAX / (2 * kDiscMaxTilesPerSurfel) && tiles <= (int64_t)INT32_MAX / 2;
+}
+
+// Lattice candidates of the empty-area search on a W x H keyframe.
+void place_lattice(int W, int H, int sp, int& cand_x, int& cand_y) {
+    cand_x = W > sp / 2 ? (W - sp / 2 + sp - 1) / sp : 0;
+    cand_y = H > sp / 2 ? (H - sp / 2 + sp - 1) / sp : 0;
+}
+
+// Disc placement workspace: one byte per lattice candidate of the batch.
+bool place_candidates(const sgn_disc_item* items, int n, int spacing, int64_t& cands) {
+    cands = 0;
+    if (!items || n < 1 || n > SGN_MAX_BATCH || spacing < 1 || spacing > 1024) return false;
+    for (int i = 0; i < n; ++i) {
+        const int W = items[i].kf.kf.width, H = items[i].kf.kf.height;
+        if (W < 2 || H < 2 || W > 16384 || H > 16384) return false;
+        int cx, cy;
+        place_lattice(W, H, spacing, cx, cy);
+        cands += (int64_t)cx * cy;
+    }
+    return cands <= (int64_t)INT32_MAX / 2;
+}
+
+// Autotune workspace: a snapshot of the eight state arrays of every item.
+bool autotune_surfels(const sgn_batch_item* items, int n, std::vector<size_t>* per_item) {
+    if (!items || n < 1 || n > SGN_MAX_BATCH) return false;
+    for (int i = 0; i < n; ++i) {
+        const sgn_keyframe& kf = items[i].kf;
+        if (kf.patch != 4 && kf.patch != 8 && kf.patch != 16) return false;
+        if (kf.kf.width < kf.patch || kf.kf.height < kf.patch || kf.kf.width > 16384 ||
+            kf.kf.height > 16384)
+            return false;
+        if (per_item) per_item->push_back((size_t)(kf.kf.width / kf.patch) * (kf.kf.height / kf.patch));
+    }
+    return true;
+}
+size_t autotune_ws_bytes(const std::vector<size_t>& m) {
+    size_t tot = 0;
+    for (size_t v : m) tot += 8 * align256(v * 4);
+    return tot;
 }
 
 sgn_status check_surfels(const sgn_surfels* s) {
@@ -260,6 +345,8 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
         if (st) return st;
         total_frames += items[i].kf.n_nbr;
     }
+    if (n > SGN_MAX_BATCH || total_frames > SGN_MAX_BATCH_FRAMES)
+        return fail(SGN_E_UNSUPPORTED, "batch larger than SGN_MAX_BATCH keyframes or SGN_MAX_BATCH_FRAMES frames");
     sgn_status st = check_params(prm);
     if (st) return st;
     sgn_plan plan = plan_in ? *plan_in : default_plan(patch);
@@ -269,7 +356,7 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
     if (fl.gn && !gn_variant_supported(var)) return fail(SGN_E_UNSUPPORTED, "plan not supported for this patch");
 
     TableLayout L = layout_for(n, total_frames);
-    st = ensure_table(c, L.total);
+    st = check_table(c, L.total);
     if (st) return st;
     // pick a staging slot whose previous upload has completed
     int slot = c->ring_next;
@@ -467,6 +554,23 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
     return run_part(2, do_render, enqueue_post);
 }
 
+// Upload a table of n entries through the staging ring into the device
+// table (asynchronous on the context's stream).
+template <class T>
+sgn_status upload_table(sgn_ctx* c, const std::vector<T>& tab) {
+    const size_t bytes = sizeof(T) * tab.size();
+    sgn_status st = check_table(c, bytes);
+    if (st) return st;
+    const int slot = c->ring_next;
+    c->ring_next = (c->ring_next + 1) % kRingSlots;
+    if (c->ring_used[slot]) SGN_HIP(hipEventSynchronize(c->ring_ev[slot]));
+    std::memcpy(c->host_ring[slot], tab.data(), bytes);
+    SGN_HIP(hipMemcpyAsync(c->dev_table, c->host_ring[slot], bytes, hipMemcpyHostToDevice, c->stream));
+    SGN_HIP(hipEventRecord(c->ring_ev[slot], c->stream));
+    c->ring_used[slot] = true;
+    return SGN_OK;
+}
+
 sgn_status check_disc_item(const sgn_disc_item* it, bool need_nbr) {
     if (!it) return fail(SGN_E_INVALID, "null disc item");
     sgn_status st = check_keyframe(&it->kf, need_nbr, true);
@@ -499,11 +603,13 @@ sgn_status run_disc_batch(sgn_ctx* c, const sgn_disc_item* items, int n, const s
         total_surfels += items[i].count;
     }
     if (total_surfels > (int64_t)INT32_MAX / 2) return fail(SGN_E_UNSUPPORTED, "too many surfels in one batch");
+    if (n > SGN_MAX_BATCH || total_frames > SGN_MAX_BATCH_FRAMES)
+        return fail(SGN_E_UNSUPPORTED, "batch larger than SGN_MAX_BATCH keyframes or SGN_MAX_BATCH_FRAMES frames");
     sgn_status st = check_params(prm);
     if (st) return st;
     SGN_HIP(hipSetDevice(c->device));
     TableLayout L = layout_for(n, total_frames);
-    st = ensure_table(c, L.total);
+    st = check_table(c, L.total);
     if (st) return st;
     int slot = c->ring_next;
     c->ring_next = (c->ring_next + 1) % kRingSlots;
@@ -666,6 +772,14 @@ sgn_status sgn_create(sgn_ctx** out, int32_t device, void* hip_stream) {
     c->gn_end = c->gn_ring[1][0];
     if (hipMalloc(&c->counters, kNumCounters * sizeof(uint32_t)) != hipSuccess)
         return give_up(SGN_E_DEVICE, "context allocation failed");
+    // the descriptor table and its pinned staging ring, at the capacity of
+    // the largest batch a call may describe: no later call allocates
+    const size_t cap = table_bytes_needed();
+    for (int i = 0; i < kRingSlots; ++i)
+        if (hipHostMalloc(&c->host_ring[i], cap, hipHostMallocDefault) != hipSuccess)
+            return give_up(SGN_E_NOMEM, "pinned staging allocation failed");
+    if (hipMalloc(&c->dev_table, cap) != hipSuccess) return give_up(SGN_E_NOMEM, "device table allocation failed");
+    c->table_cap = cap;
     if (const char* g = std::getenv("SGN_NO_GRAPHS")) c->use_graphs = !(g[0] == '1');
     *out = c;
     return SGN_OK;
@@ -685,7 +799,6 @@ sgn_status sgn_destroy(sgn_ctx* c) {
     for (int k = 0; k < 2; ++k)
         for (int i = 0; i < kTimingRing; ++i)
             if (c->gn_ring[k][i]) hipEventDestroy(c->gn_ring[k][i]);
-    if (c->scratch) hipFree(c->scratch);
     delete c;
     return SGN_OK;
 }
@@ -781,13 +894,26 @@ sgn_status sgn_quantize(sgn_ctx* c, const float* src, int32_t src_pitch, const s
     return SGN_OK;
 }
 
+size_t sgn_transfer_workspace_bytes(int32_t n, const sgn_grid* dst_grids) {
+    if (n < 1 || n > SGN_MAX_BATCH || !dst_grids) return 0;
+    int64_t total_dst = 0;
+    for (int k = 0; k < n; ++k) {
+        const int64_t t = grid_tiles(dst_grids[k]);
+        if (t < 0) return 0;
+        total_dst += t;
+    }
+    if (total_dst > INT32_MAX / 2) return 0;
+    return transfer_ws(total_dst).total;
+}
+
 sgn_status sgn_transfer_surfels_batch(sgn_ctx* c, int32_t n, const sgn_grid* src_grids,
                                       const sgn_surfels* srcs, const sgn_pose* poses,
                                       const sgn_grid* dst_grids, const sgn_surfels* dsts,
-                                      uint8_t* const* dst_is_new, int32_t* const* dst_src_index) {
-    if (!c) return fail(SGN_E_INVALID, "null context");
+                                      uint8_t* const* dst_is_new, int32_t* const* dst_src_index,
+                                      void* ws, size_t ws_bytes) {
     if (n < 1 || !src_grids || !srcs || !poses || !dst_grids || !dsts || !dst_is_new)
         return fail(SGN_E_INVALID, "empty batch or null argument");
+    if (n > SGN_MAX_BATCH) return fail(SGN_E_UNSUPPORTED, "more keyframe pairs than SGN_MAX_BATCH");
     std::vector<RegridArgs> tab(n);
     int64_t total_src = 0, total_dst = 0;
     for (int k = 0; k < n; ++k) {
@@ -835,26 +961,19 @@ sgn_status sgn_transfer_surfels_batch(sgn_ctx* c, int32_t n, const sgn_grid* src
         if (total_src > INT32_MAX / 2 || total_dst > INT32_MAX / 2)
             return fail(SGN_E_UNSUPPORTED, "too many surfels in one batch");
     }
-    SGN_HIP(hipSetDevice(c->device));
-    sgn_status st = ensure_scratch(c, (size_t)total_dst * (sizeof(unsigned long long) + sizeof(int32_t)));
+    const TransferWs w = transfer_ws(total_dst);
+    sgn_status st = check_ws(ws, ws_bytes, w.total);
     if (st) return st;
-    unsigned long long* best = (unsigned long long*)c->scratch;
-    int32_t* win = (int32_t*)((char*)c->scratch + (size_t)total_dst * sizeof(unsigned long long));
+    if (!c) return fail(SGN_E_INVALID, "null context");
+    SGN_HIP(hipSetDevice(c->device));
+    unsigned long long* best = (unsigned long long*)((char*)ws + w.best_off);
+    int32_t* win = (int32_t*)((char*)ws + w.win_off);
     for (int k = 0; k < n; ++k) {
         tab[k].best = best + tab[k].dst_base;
         tab[k].win = win + tab[k].dst_base;
     }
-    // the table goes through the staging ring into the device table
-    const size_t bytes = sizeof(RegridArgs) * (size_t)n;
-    st = ensure_table(c, bytes);
+    st = upload_table(c, tab);
     if (st) return st;
-    const int slot = c->ring_next;
-    c->ring_next = (c->ring_next + 1) % kRingSlots;
-    if (c->ring_used[slot]) SGN_HIP(hipEventSynchronize(c->ring_ev[slot]));
-    std::memcpy(c->host_ring[slot], tab.data(), bytes);
-    SGN_HIP(hipMemcpyAsync(c->dev_table, c->host_ring[slot], bytes, hipMemcpyHostToDevice, c->stream));
-    SGN_HIP(hipEventRecord(c->ring_ev[slot], c->stream));
-    c->ring_used[slot] = true;
     hipError_t e = launch_regrid((const RegridArgs*)c->dev_table, n, (int)total_src, (int)total_dst, c->stream);
     if (e != hipSuccess) return hip_fail(e, "re-gridding launch");
     return SGN_OK;
@@ -862,10 +981,11 @@ sgn_status sgn_transfer_surfels_batch(sgn_ctx* c, int32_t n, const sgn_grid* src
 
 sgn_status sgn_transfer_surfels(sgn_ctx* c, const sgn_grid* src_grid, const sgn_surfels* src,
                                 const sgn_pose* pose, const sgn_grid* dst_grid, sgn_surfels* dst,
-                                uint8_t* dst_is_new, int32_t* dst_src_index) {
-    if (!c || !src_grid || !src || !pose || !dst_grid || !dst || !dst_is_new)
+                                uint8_t* dst_is_new, int32_t* dst_src_index, void* ws, size_t ws_bytes) {
+    if (!src_grid || !src || !pose || !dst_grid || !dst || !dst_is_new)
         return fail(SGN_E_INVALID, "null argument");
-    return sgn_transfer_surfels_batch(c, 1, src_grid, src, pose, dst_grid, dst, &dst_is_new, &dst_src_index);
+    return sgn_transfer_surfels_batch(c, 1, src_grid, src, pose, dst_grid, dst, &dst_is_new, &dst_src_index,
+                                      ws, ws_bytes);
 }
 
 sgn_status sgn_disc_optimize(sgn_ctx* c, const sgn_disc_item* items, int32_t n, const sgn_params* p) {
@@ -873,10 +993,17 @@ sgn_status sgn_disc_optimize(sgn_ctx* c, const sgn_disc_item* items, int32_t n, 
     return run_disc_batch(c, items, n, p);
 }
 
+size_t sgn_disc_render_workspace_bytes(int32_t n, const sgn_disc_item* items) {
+    int64_t surfels, tiles;
+    if (!disc_render_totals(items, n, surfels, tiles)) return 0;
+    return disc_render_ws(surfels, tiles).total;
+}
+
 sgn_status sgn_disc_render_batch(sgn_ctx* c, const sgn_disc_item* items, int32_t n,
-                                 float* const* inv_depth_outs, int32_t* const* index_outs) {
-    if (!c) return fail(SGN_E_INVALID, "null context");
+                                 float* const* inv_depth_outs, int32_t* const* index_outs, void* ws,
+                                 size_t ws_bytes) {
     if (n < 1 || !items || !inv_depth_outs) return fail(SGN_E_INVALID, "empty batch or null array");
+    if (n > SGN_MAX_BATCH) return fail(SGN_E_UNSUPPORTED, "more keyframes than SGN_MAX_BATCH");
     std::vector<DiscRenderItem> tab(n);
     int64_t total_surfels = 0, total_pixels = 0, total_tiles = 0;
     for (int i = 0; i < n; ++i) {
@@ -905,31 +1032,19 @@ sgn_status sgn_disc_render_batch(sgn_ctx* c, const sgn_disc_item* items, int32_t
     }
     if (total_surfels > (int64_t)INT32_MAX / (2 * kDiscMaxTilesPerSurfel) || total_tiles > (int64_t)INT32_MAX / 2)
         return fail(SGN_E_UNSUPPORTED, "too many surfels or pixels in one batch");
+    const DiscRenderWs lw = disc_render_ws(total_surfels, total_tiles);
+    sgn_status st = check_ws(ws, ws_bytes, lw.total);
+    if (st) return st;
+    if (!c) return fail(SGN_E_INVALID, "null context");
     SGN_HIP(hipSetDevice(c->device));
-    // scratch: raster records, then the tile counts, starts, scan sums and lists
-    const size_t n_blocks = (size_t)((total_tiles + 1023) / 1024);
-    const size_t rec_bytes = sizeof(DiscRaster) * (size_t)total_surfels;
-    const size_t int_words = (size_t)total_tiles + ((size_t)total_tiles + 1) + n_blocks +
-                             (size_t)kDiscMaxTilesPerSurfel * (size_t)total_surfels;
-    sgn_status st = ensure_scratch(c, rec_bytes + sizeof(int32_t) * int_words + 256);
+    st = upload_table(c, tab);
     if (st) return st;
-    // the table goes through the staging ring into the device table
-    const size_t bytes = sizeof(DiscRenderItem) * (size_t)n;
-    st = ensure_table(c, bytes);
-    if (st) return st;
-    const int slot = c->ring_next;
-    c->ring_next = (c->ring_next + 1) % kRingSlots;
-    if (c->ring_used[slot]) SGN_HIP(hipEventSynchronize(c->ring_ev[slot]));
-    std::memcpy(c->host_ring[slot], tab.data(), bytes);
-    SGN_HIP(hipMemcpyAsync(c->dev_table, c->host_ring[slot], bytes, hipMemcpyHostToDevice, c->stream));
-    SGN_HIP(hipEventRecord(c->ring_ev[slot], c->stream));
-    c->ring_used[slot] = true;
     DiscRenderScratch w;
-    w.rec = (DiscRaster*)c->scratch;
-    w.count = (int32_t*)((char*)c->scratch + rec_bytes);
-    w.start = w.count + total_tiles;
-    w.block_sum = w.start + total_tiles + 1;
-    w.list = w.block_sum + n_blocks;
+    w.rec = (DiscRaster*)((char*)ws + lw.rec_off);
+    w.count = (int32_t*)((char*)ws + lw.count_off);
+    w.start = (int32_t*)((char*)ws + lw.start_off);
+    w.block_sum = (int32_t*)((char*)ws + lw.block_off);
+    w.list = (int32_t*)((char*)ws + lw.list_off);
     hipError_t e = launch_disc_render((const DiscRenderItem*)c->dev_table, n, (int)total_surfels,
                                       (int)total_tiles, w, c->stream);
     if (e != hipSuccess) return hip_fail(e, "disc render launch");
@@ -937,17 +1052,24 @@ sgn_status sgn_disc_render_batch(sgn_ctx* c, const sgn_disc_item* items, int32_t
 }
 
 sgn_status sgn_disc_render(sgn_ctx* c, const sgn_disc_item* item, float* inv_depth_out,
-                           int32_t* index_out) {
+                           int32_t* index_out, void* ws, size_t ws_bytes) {
     if (!item) return fail(SGN_E_INVALID, "null disc item");
-    return sgn_disc_render_batch(c, item, 1, &inv_depth_out, &index_out);
+    return sgn_disc_render_batch(c, item, 1, &inv_depth_out, &index_out, ws, ws_bytes);
+}
+
+size_t sgn_disc_place_workspace_bytes(int32_t n, const sgn_disc_item* items, int32_t spacing) {
+    int64_t cands;
+    if (!place_candidates(items, n, spacing, cands)) return 0;
+    return align256((size_t)cands + 1);
 }
 
 sgn_status sgn_disc_place_batch(sgn_ctx* c, const sgn_disc_item* items, int32_t n,
                                 const int32_t* const* index_maps, const int32_t* capacities,
-                                const sgn_disc_place_params* pp, int32_t* const* counts_outs) {
-    if (!c) return fail(SGN_E_INVALID, "null context");
+                                const sgn_disc_place_params* pp, int32_t* const* counts_outs, void* ws,
+                                size_t ws_bytes) {
     if (n < 1 || !items || !index_maps || !capacities || !pp || !counts_outs)
         return fail(SGN_E_INVALID, "empty batch or null argument");
+    if (n > SGN_MAX_BATCH) return fail(SGN_E_UNSUPPORTED, "more keyframes than SGN_MAX_BATCH");
     if (!(pp->alpha > 0.f) || !(pp->alpha <= 4.f)) return fail(SGN_E_INVALID, "alpha must be in (0, 4]");
     if (!(pp->beta > 0.f) || !(pp->beta <= 4.f)) return fail(SGN_E_INVALID, "beta must be in (0, 4]");
     if (pp->spacing < 1 || pp->spacing > 1024) return fail(SGN_E_INVALID, "spacing must be in [1, 1024]");
@@ -963,8 +1085,8 @@ sgn_status sgn_disc_place_batch(sgn_ctx* c, const sgn_disc_item* items, int32_t 
         if (st) return st;
         if (capacities[i] < item->count) return fail(SGN_E_INVALID, "capacity below the surfel count");
         const int W = item->kf.kf.width, H = item->kf.kf.height, sp = pp->spacing;
-        const int cand_x = W > sp / 2 ? (W - sp / 2 + sp - 1) / sp : 0;
-        const int cand_y = H > sp / 2 ? (H - sp / 2 + sp - 1) / sp : 0;
+        int cand_x, cand_y;
+        place_lattice(W, H, sp, cand_x, cand_y);
         DiscPlaceArgs& a = tab[i];
         a.inv_depth = item->surfels.inv_depth;
         a.nx = item->surfels.nx; a.ny = item->surfels.ny; a.nz = item->surfels.nz;
@@ -989,21 +1111,13 @@ sgn_status sgn_disc_place_batch(sgn_ctx* c, const sgn_disc_item* items, int32_t 
         total_init += std::min<int64_t>(a.room, cands);
         if (total_cands > (int64_t)INT32_MAX / 2) return fail(SGN_E_UNSUPPORTED, "too many candidates in one batch");
     }
+    sgn_status st = check_ws(ws, ws_bytes, align256((size_t)total_cands + 1));
+    if (st) return st;
+    if (!c) return fail(SGN_E_INVALID, "null context");
     SGN_HIP(hipSetDevice(c->device));
-    sgn_status st = ensure_scratch(c, (size_t)total_cands + 256);
+    for (int i = 0; i < n; ++i) tab[i].cand_flag = (uint8_t*)ws + tab[i].cand_base;
+    st = upload_table(c, tab);
     if (st) return st;
-    for (int i = 0; i < n; ++i) tab[i].cand_flag = (uint8_t*)c->scratch + tab[i].cand_base;
-    // the table goes through the staging ring into the device table
-    const size_t bytes = sizeof(DiscPlaceArgs) * (size_t)n;
-    st = ensure_table(c, bytes);
-    if (st) return st;
-    const int slot = c->ring_next;
-    c->ring_next = (c->ring_next + 1) % kRingSlots;
-    if (c->ring_used[slot]) SGN_HIP(hipEventSynchronize(c->ring_ev[slot]));
-    std::memcpy(c->host_ring[slot], tab.data(), bytes);
-    SGN_HIP(hipMemcpyAsync(c->dev_table, c->host_ring[slot], bytes, hipMemcpyHostToDevice, c->stream));
-    SGN_HIP(hipEventRecord(c->ring_ev[slot], c->stream));
-    c->ring_used[slot] = true;
     hipError_t e = launch_disc_place((const DiscPlaceArgs*)c->dev_table, n, (int)total_cands, (int)total_init,
                                      c->stream);
     if (e != hipSuccess) return hip_fail(e, "disc placement launch");
@@ -1011,9 +1125,10 @@ sgn_status sgn_disc_place_batch(sgn_ctx* c, const sgn_disc_item* items, int32_t 
 }
 
 sgn_status sgn_disc_place(sgn_ctx* c, const sgn_disc_item* item, const int32_t* index_map,
-                          int32_t capacity, const sgn_disc_place_params* pp, int32_t* counts_out) {
+                          int32_t capacity, const sgn_disc_place_params* pp, int32_t* counts_out, void* ws,
+                          size_t ws_bytes) {
     if (!item) return fail(SGN_E_INVALID, "null disc item");
-    return sgn_disc_place_batch(c, item, 1, &index_map, &capacity, pp, &counts_out);
+    return sgn_disc_place_batch(c, item, 1, &index_map, &capacity, pp, &counts_out, ws, ws_bytes);
 }
 
 sgn_status sgn_disc_transfer_batch(sgn_ctx* c, int32_t n, const sgn_disc_item* srcs, const sgn_pose* poses,
@@ -1022,6 +1137,7 @@ sgn_status sgn_disc_transfer_batch(sgn_ctx* c, int32_t n, const sgn_disc_item* s
     if (!c) return fail(SGN_E_INVALID, "null context");
     if (n < 1 || !srcs || !poses || !dsts || !capacities || !counts_outs)
         return fail(SGN_E_INVALID, "empty batch or null argument");
+    if (n > SGN_MAX_BATCH) return fail(SGN_E_UNSUPPORTED, "more keyframe pairs than SGN_MAX_BATCH");
     std::vector<DiscTransferArgs> tab(n);
     for (int k = 0; k < n; ++k) {
         const sgn_disc_item* src = &srcs[k];
@@ -1064,17 +1180,8 @@ sgn_status sgn_disc_transfer_batch(sgn_ctx* c, int32_t n, const sgn_disc_item* s
         a.counts = counts_outs[k];
     }
     SGN_HIP(hipSetDevice(c->device));
-    // the table goes through the staging ring into the device table
-    const size_t bytes = sizeof(DiscTransferArgs) * (size_t)n;
-    sgn_status st = ensure_table(c, bytes);
+    sgn_status st = upload_table(c, tab);
     if (st) return st;
-    const int slot = c->ring_next;
-    c->ring_next = (c->ring_next + 1) % kRingSlots;
-    if (c->ring_used[slot]) SGN_HIP(hipEventSynchronize(c->ring_ev[slot]));
-    std::memcpy(c->host_ring[slot], tab.data(), bytes);
-    SGN_HIP(hipMemcpyAsync(c->dev_table, c->host_ring[slot], bytes, hipMemcpyHostToDevice, c->stream));
-    SGN_HIP(hipEventRecord(c->ring_ev[slot], c->stream));
-    c->ring_used[slot] = true;
     hipError_t e = launch_disc_transfer((const DiscTransferArgs*)c->dev_table, n, c->stream);
     if (e != hipSuccess) return hip_fail(e, "disc transfer launch");
     return SGN_OK;
@@ -1089,39 +1196,47 @@ sgn_status sgn_disc_transfer(sgn_ctx* c, const sgn_disc_item* src, const sgn_pos
     return sgn_disc_transfer_batch(c, 1, src, pose, dst, &capacity, &counts_out, &src_index_out);
 }
 
+size_t sgn_autotune_workspace_bytes(int32_t n, const sgn_batch_item* items) {
+    std::vector<size_t> m;
+    if (!autotune_surfels(items, n, &m)) return 0;
+    return autotune_ws_bytes(m);
+}
+
 sgn_status sgn_autotune(sgn_ctx* c, const sgn_batch_item* items, int32_t n, const sgn_params* p,
-                        sgn_plan* out) {
-    if (!c || !items || n < 1 || !out) return fail(SGN_E_INVALID, "null argument");
+                        sgn_plan* out, void* ws, size_t ws_bytes) {
+    if (!items || n < 1 || !out) return fail(SGN_E_INVALID, "null argument");
+    std::vector<size_t> m;
+    if (!autotune_surfels(items, n, &m)) return fail(SGN_E_INVALID, "bad batch item");
+    for (int i = 0; i < n; ++i) {
+        sgn_status st = check_surfels(&items[i].surfels);
+        if (st) return st;
+    }
+    sgn_status st = check_ws(ws, ws_bytes, autotune_ws_bytes(m));
+    if (st) return st;
+    if (!c) return fail(SGN_E_INVALID, "null context");
     SGN_HIP(hipSetDevice(c->device));
     const int patch = items[0].kf.patch;
-    // snapshot the state arrays so every trial starts from the same surfels
-    struct Saved { void* dst; std::vector<char> bytes; };
-    std::vector<void*> bufs;
+    // snapshot the state arrays into the workspace so that every trial
+    // starts from the same surfels
     std::vector<std::pair<void*, size_t>> arrays;
     for (int i = 0; i < n; ++i) {
         const sgn_surfels& s = items[i].surfels;
-        size_t m = (size_t)(items[i].kf.kf.width / patch) * (items[i].kf.kf.height / patch);
-        arrays.push_back({s.inv_depth, m * 4});
-        arrays.push_back({s.nx, m * 4});
-        arrays.push_back({s.ny, m * 4});
-        arrays.push_back({s.nz, m * 4});
-        arrays.push_back({s.flags, m * 4});
-        arrays.push_back({s.cost, m * 4});
-        arrays.push_back({s.nvalid, m * 4});
-        arrays.push_back({s.last_update, m * 4});
+        for (void* a : {(void*)s.inv_depth, (void*)s.nx, (void*)s.ny, (void*)s.nz, (void*)s.flags,
+                        (void*)s.cost, (void*)s.nvalid, (void*)s.last_update})
+            arrays.push_back({a, m[i] * 4});
     }
+    std::vector<void*> saved;
+    size_t off = 0;
     for (auto& a : arrays) {
-        void* b = nullptr;
-        if (hipMalloc(&b, a.second) != hipSuccess) {
-            for (void* q : bufs) hipFree(q);
-            return fail(SGN_E_NOMEM, "autotune snapshot allocation failed");
-        }
-        hipMemcpyAsync(b, a.first, a.second, hipMemcpyDeviceToDevice, c->stream);
-        bufs.push_back(b);
+        saved.push_back((char*)ws + off);
+        off += align256(a.second);
+        SGN_HIP(hipMemcpyAsync(saved.back(), a.first, a.second, hipMemcpyDeviceToDevice, c->stream));
     }
-    auto restore = [&]() {
+    auto restore = [&]() -> sgn_status {
         for (size_t i = 0; i < arrays.size(); ++i)
-            hipMemcpyAsync(arrays[i].first, bufs[i], arrays[i].second, hipMemcpyDeviceToDevice, c->stream);
+            SGN_HIP(hipMemcpyAsync(arrays[i].first, saved[i], arrays[i].second, hipMemcpyDeviceToDevice,
+                                   c->stream));
+        return SGN_OK;
     };
     std::vector<sgn_plan> cands;
     std::vector<std::pair<int, int>> shapes = patch != 4 ? std::vector<std::pair<int, int>>{{1, 1}}
@@ -1153,8 +1268,8 @@ sgn_status sgn_autotune(sgn_ctx* c, const sgn_batch_item* items, int32_t n, cons
         float tot = 0.f;
         bool ok = true;
         for (int rep = 0; rep < 3 && ok; ++rep) {
-            restore();
-            sgn_status st = run_batch(c, items, n, p, &pl, RunFlags{false, true, false});
+            st = restore();
+            if (st == SGN_OK) st = run_batch(c, items, n, p, &pl, RunFlags{false, true, false});
             float ms = 0.f;
             if (st == SGN_OK) st = sgn_last_kernel_ms(c, &ms);
             if (st != SGN_OK) { ok = false; result = st; break; }
@@ -1169,9 +1284,8 @@ sgn_status sgn_autotune(sgn_ctx* c, const sgn_batch_item* items, int32_t n, cons
             best_plan = pl;
         }
     }
-    restore();
-    hipStreamSynchronize(c->stream);
-    for (void* b : bufs) hipFree(b);
+    st = restore();
+    if (st) return st;
     *out = best_plan;
     return best < 1e29f ? SGN_OK : (result != SGN_OK ? result : fail(SGN_E_DEVICE, "no plan ran"));
 }

@@ -414,9 +414,6 @@ __device__ __forceinline__ void stage_pair_words(const FrameDev* frames, int nf,
     }
 }
 
-// Levenberg-Marquardt acceptance: largest relative rise of the mean cost.
-constexpr float kLmAcceptRise = 1e-4f;
-
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -778,13 +775,12 @@ __device__ __forceinline__ bool owner_step(const float* sm, bool alive, bool las
 
 // Levenberg-Marquardt acceptance of a candidate on its owner lane: the
 // candidate's cost cost2 over nv2 valid samples against the current cost
-// over nv.  Accepted unless the mean Huber cost per valid sample rises by
-// more than kLmAcceptRise (relative; smaller rises are below the float noise
-// of the cost sums, where the decision would be a coin toss) or fewer than
+// over nv.  Accepted when the mean Huber cost per valid sample does not rise
+// (cost2 / nv2 <= cost / nv, compared as cost2 nv <= cost nv2) and at least
 // three samples remain.  lam shrinks tenfold (floor 1e-9) on acceptance and
 // grows tenfold on refusal.
 __device__ __forceinline__ bool lm_accept(float cost2, int nv2, float cost_here, int nv, float& lam) {
-    if (nv2 < 3 || !(cost2 * (float)nv <= cost_here * (float)nv2 * (1.f + kLmAcceptRise))) {
+    if (nv2 < 3 || !(cost2 * (float)nv <= cost_here * (float)nv2)) {
         lam *= 10.f;
         return false;
     }
@@ -1051,8 +1047,13 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
             float id_c = 0.f, nx_c = 0.f, ny_c = 0.f, nz_c = 0.f, cost_here = 0.f;
             int nv = 0;
             if (owner) {
-                // the step of owner_step, written out here: as a call it costs
-                // this kernel seven VGPRs (and a wavefront of occupancy)
+                // The step of owner_step, written out here: as a call (forced
+                // inline) the compiler allocates 5-10 more VGPRs for this
+                // kernel, which spills in the default plan and costs the
+                // one-group plans their sixth wavefront per SIMD.  The text
+                // between the markers must equal owner_step's body; a CPU test
+                // compares the two.
+                // owner_step body begin
                 const float* sm = lsm + own * SM_WORDS;
                 const float H00 = sm[SM_H00], H01 = sm[SM_H01], H02 = sm[SM_H02];
                 const float H11 = sm[SM_H11], H12 = sm[SM_H12], H22 = sm[SM_H22];
@@ -1147,6 +1148,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
                         }
                     }
                 }
+                // owner_step body end
             }
             if (lm) {
                 // Levenberg-Marquardt: the candidate's cost over the pixels,

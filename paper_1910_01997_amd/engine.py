@@ -116,6 +116,21 @@ def update_batch(ctx: sg.Context, dks: Sequence[DeviceKeyframe], prm: sg.sgn_par
     return items
 
 
+def autotune(ctx: sg.Context, items, n: int, prm: sg.sgn_params) -> sg.sgn_plan:
+    """sgn_autotune on a batch descriptor array, with the context's workspace
+    for the state snapshot."""
+    ws = ctx.workspace(sg.sgn_autotune_workspace_bytes(n, items))
+    return sg.sgn_autotune(ctx.handle, items, n, prm, ws)
+
+
+def transfer_batch(ctx: sg.Context, src_grids, srcs, poses, dst_grids, dsts, dst_is_new_ptrs,
+                   dst_src_index_ptrs=None):
+    """sgn_transfer_surfels_batch with the context's workspace."""
+    ws = ctx.workspace(sg.sgn_transfer_workspace_bytes(dst_grids))
+    sg.sgn_transfer_surfels_batch(ctx.handle, src_grids, srcs, poses, dst_grids, dsts, dst_is_new_ptrs,
+                                  dst_src_index_ptrs, ws)
+
+
 class DiscKeyframe:
     """Disc surfels (Eq. 4) of one keyframe on the GPU: the images (as in
     DeviceKeyframe), the surfel state and centres with room for `capacity`
@@ -166,16 +181,20 @@ class DiscKeyframe:
         return self.img.dequantized_images()
 
     def render(self):
-        sg.sgn_disc_render(self.ctx.handle, self.item(), self.inv_depth_out.data_ptr(),
-                           self.index_out.data_ptr())
+        it = self.item()
+        ws = self.ctx.workspace(sg.sgn_disc_render_workspace_bytes(1, it))
+        sg.sgn_disc_render(self.ctx.handle, it, self.inv_depth_out.data_ptr(), self.index_out.data_ptr(),
+                           ws)
 
     def place(self, alpha: float = 1.0, beta: float = 2.0, spacing: int = 0):
         """Empty-area search and placement from the current index map; waits
         for the device and returns (placed, qualifying)."""
         sp = int(spacing) if spacing else int(np.floor(self.radius * np.sqrt(2.0)))
-        sg.sgn_disc_place(self.ctx.handle, self.item(), self.index_out.data_ptr(), self.capacity,
+        it = self.item()
+        ws = self.ctx.workspace(sg.sgn_disc_place_workspace_bytes(1, it, sp))
+        sg.sgn_disc_place(self.ctx.handle, it, self.index_out.data_ptr(), self.capacity,
                           sg.sgn_disc_place_params(float(alpha), float(beta), sp),
-                          self.counts.data_ptr())
+                          self.counts.data_ptr(), ws)
         placed, found = (int(v) for v in self.counts.cpu().tolist())
         self.count += placed
         return placed, found
@@ -212,8 +231,9 @@ def refresh_counts(items, dks: Sequence[DiscKeyframe]):
 def disc_render(ctx: sg.Context, dks: Sequence[DiscKeyframe], items=None):
     """Depth-buffered render of several keyframes' discs in one pass."""
     items = disc_items(dks) if items is None else items
+    ws = ctx.workspace(sg.sgn_disc_render_workspace_bytes(len(dks), items))
     sg.sgn_disc_render_batch(ctx.handle, items, len(dks), [d.inv_depth_out.data_ptr() for d in dks],
-                             [d.index_out.data_ptr() for d in dks])
+                             [d.index_out.data_ptr() for d in dks], ws)
     return items
 
 
@@ -225,9 +245,10 @@ def disc_place(ctx: sg.Context, dks: Sequence[DiscKeyframe], alpha: float = 1.0,
     qualifying) pairs, updating each keyframe's count."""
     sp = int(spacing) if spacing else int(np.floor(dks[0].radius * np.sqrt(2.0)))
     items = disc_items(dks) if items is None else items
+    ws = ctx.workspace(sg.sgn_disc_place_workspace_bytes(len(dks), items, sp))
     sg.sgn_disc_place_batch(ctx.handle, items, len(dks), [d.index_out.data_ptr() for d in dks],
                             [d.capacity for d in dks], sg.sgn_disc_place_params(float(alpha), float(beta), sp),
-                            [d.counts.data_ptr() for d in dks])
+                            [d.counts.data_ptr() for d in dks], ws)
     if not wait:
         return None
     counts = torch.stack([d.counts for d in dks]).cpu().tolist()

@@ -38,7 +38,8 @@ EXPORTED = [
     "sgn_quantize", "sgn_last_kernel_ms", "sgn_device_info", "sgn_status_str", "sgn_last_error",
     "sgn_version", "sgn_transfer_surfels", "sgn_disc_optimize", "sgn_disc_render", "sgn_disc_place",
     "sgn_recent_kernel_ms", "sgn_disc_transfer", "sgn_disc_render_batch", "sgn_disc_place_batch",
-    "sgn_transfer_surfels_batch", "sgn_disc_transfer_batch",
+    "sgn_transfer_surfels_batch", "sgn_disc_transfer_batch", "sgn_transfer_workspace_bytes",
+    "sgn_disc_render_workspace_bytes", "sgn_disc_place_workspace_bytes", "sgn_autotune_workspace_bytes",
 ]
 
 
@@ -146,32 +147,40 @@ def lib():
                                          C.POINTER(sgn_params), C.POINTER(sgn_plan)]
         L.sgn_autotune.restype = st
         L.sgn_autotune.argtypes = [vp, C.POINTER(sgn_batch_item), C.c_int32, C.POINTER(sgn_params),
-                                   C.POINTER(sgn_plan)]
+                                   C.POINTER(sgn_plan), vp, C.c_size_t]
+        L.sgn_autotune_workspace_bytes.restype = C.c_size_t
+        L.sgn_autotune_workspace_bytes.argtypes = [C.c_int32, C.POINTER(sgn_batch_item)]
         L.sgn_quantize.restype = st
         L.sgn_quantize.argtypes = [vp, vp, C.c_int32, C.POINTER(sgn_image)]
         L.sgn_transfer_surfels.restype = st
         L.sgn_transfer_surfels.argtypes = [vp, C.POINTER(sgn_grid), C.POINTER(sgn_surfels),
                                            C.POINTER(sgn_pose), C.POINTER(sgn_grid),
-                                           C.POINTER(sgn_surfels), vp, vp]
+                                           C.POINTER(sgn_surfels), vp, vp, vp, C.c_size_t]
         L.sgn_transfer_surfels_batch.restype = st
         L.sgn_transfer_surfels_batch.argtypes = [vp, C.c_int32, C.POINTER(sgn_grid), C.POINTER(sgn_surfels),
                                                  C.POINTER(sgn_pose), C.POINTER(sgn_grid),
                                                  C.POINTER(sgn_surfels), C.POINTER(C.c_void_p),
-                                                 C.POINTER(C.c_void_p)]
+                                                 C.POINTER(C.c_void_p), vp, C.c_size_t]
+        L.sgn_transfer_workspace_bytes.restype = C.c_size_t
+        L.sgn_transfer_workspace_bytes.argtypes = [C.c_int32, C.POINTER(sgn_grid)]
         L.sgn_disc_optimize.restype = st
         L.sgn_disc_optimize.argtypes = [vp, C.POINTER(sgn_disc_item), C.c_int32, C.POINTER(sgn_params)]
         L.sgn_disc_render.restype = st
-        L.sgn_disc_render.argtypes = [vp, C.POINTER(sgn_disc_item), vp, vp]
+        L.sgn_disc_render.argtypes = [vp, C.POINTER(sgn_disc_item), vp, vp, vp, C.c_size_t]
         L.sgn_disc_place.restype = st
         L.sgn_disc_place.argtypes = [vp, C.POINTER(sgn_disc_item), vp, C.c_int32,
-                                     C.POINTER(sgn_disc_place_params), vp]
+                                     C.POINTER(sgn_disc_place_params), vp, vp, C.c_size_t]
         L.sgn_disc_place_batch.restype = st
         L.sgn_disc_place_batch.argtypes = [vp, C.POINTER(sgn_disc_item), C.c_int32, C.POINTER(C.c_void_p),
                                            C.POINTER(C.c_int32), C.POINTER(sgn_disc_place_params),
-                                           C.POINTER(C.c_void_p)]
+                                           C.POINTER(C.c_void_p), vp, C.c_size_t]
         L.sgn_disc_render_batch.restype = st
         L.sgn_disc_render_batch.argtypes = [vp, C.POINTER(sgn_disc_item), C.c_int32,
-                                            C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]
+                                            C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), vp, C.c_size_t]
+        L.sgn_disc_render_workspace_bytes.restype = C.c_size_t
+        L.sgn_disc_render_workspace_bytes.argtypes = [C.c_int32, C.POINTER(sgn_disc_item)]
+        L.sgn_disc_place_workspace_bytes.restype = C.c_size_t
+        L.sgn_disc_place_workspace_bytes.argtypes = [C.c_int32, C.POINTER(sgn_disc_item), C.c_int32]
         L.sgn_disc_transfer.restype = st
         L.sgn_disc_transfer.argtypes = [vp, C.POINTER(sgn_disc_item), C.POINTER(sgn_pose),
                                         C.POINTER(sgn_disc_item), C.c_int32, vp, vp]
@@ -243,11 +252,17 @@ def sgn_optimize_batch(ctx, items, n: int, params: sgn_params, plan: Optional[sg
                                    C.byref(plan) if plan is not None else None), "sgn_optimize_batch")
 
 
-def sgn_autotune(ctx, items, n: int, params: sgn_params) -> sgn_plan:
+def sgn_autotune(ctx, items, n: int, params: sgn_params, ws) -> sgn_plan:
+    """ws: (device pointer, bytes) of a workspace of at least
+    sgn_autotune_workspace_bytes(n, items) bytes (Context.workspace)."""
     out = sgn_plan()
-    check(lib().sgn_autotune(C.c_void_p(ctx), items, int(n), C.byref(params), C.byref(out)),
-          "sgn_autotune")
+    check(lib().sgn_autotune(C.c_void_p(ctx), items, int(n), C.byref(params), C.byref(out),
+                             C.c_void_p(ws[0]), C.c_size_t(ws[1])), "sgn_autotune")
     return out
+
+
+def sgn_autotune_workspace_bytes(n: int, items) -> int:
+    return int(lib().sgn_autotune_workspace_bytes(int(n), items))
 
 
 def sgn_quantize(ctx, src_ptr: int, src_pitch: int, dst: sgn_image):
@@ -257,18 +272,26 @@ def sgn_quantize(ctx, src_ptr: int, src_pitch: int, dst: sgn_image):
 
 def sgn_transfer_surfels(ctx, src_grid: sgn_grid, src: sgn_surfels, pose: sgn_pose,
                          dst_grid: sgn_grid, dst: sgn_surfels, dst_is_new_ptr: int,
-                         dst_src_index_ptr: Optional[int] = None):
+                         dst_src_index_ptr: Optional[int], ws):
+    """ws: (device pointer, bytes), at least sgn_transfer_workspace_bytes([dst_grid])."""
     check(lib().sgn_transfer_surfels(C.c_void_p(ctx), C.byref(src_grid), C.byref(src),
                                      C.byref(pose), C.byref(dst_grid), C.byref(dst),
                                      C.c_void_p(dst_is_new_ptr),
-                                     C.c_void_p(dst_src_index_ptr) if dst_src_index_ptr else None),
+                                     C.c_void_p(dst_src_index_ptr) if dst_src_index_ptr else None,
+                                     C.c_void_p(ws[0]), C.c_size_t(ws[1])),
           "sgn_transfer_surfels")
+
+
+def sgn_transfer_workspace_bytes(dst_grids: Sequence[sgn_grid]) -> int:
+    n = len(dst_grids)
+    return int(lib().sgn_transfer_workspace_bytes(n, (sgn_grid * n)(*dst_grids)))
 
 
 def sgn_transfer_surfels_batch(ctx, src_grids: Sequence[sgn_grid], srcs: Sequence[sgn_surfels],
                                poses: Sequence[sgn_pose], dst_grids: Sequence[sgn_grid],
                                dsts: Sequence[sgn_surfels], dst_is_new_ptrs: Sequence[int],
-                               dst_src_index_ptrs: Optional[Sequence[int]] = None):
+                               dst_src_index_ptrs: Optional[Sequence[int]], ws):
+    """ws: (device pointer, bytes), at least sgn_transfer_workspace_bytes(dst_grids)."""
     n = len(srcs)
     arr = lambda T, xs: (T * n)(*xs)
     idx = (arr(C.c_void_p, [int(p) if p else None for p in dst_src_index_ptrs])
@@ -276,7 +299,8 @@ def sgn_transfer_surfels_batch(ctx, src_grids: Sequence[sgn_grid], srcs: Sequenc
     check(lib().sgn_transfer_surfels_batch(C.c_void_p(ctx), n, arr(sgn_grid, src_grids), arr(sgn_surfels, srcs),
                                            arr(sgn_pose, poses), arr(sgn_grid, dst_grids),
                                            arr(sgn_surfels, dsts),
-                                           arr(C.c_void_p, [int(p) for p in dst_is_new_ptrs]), idx),
+                                           arr(C.c_void_p, [int(p) for p in dst_is_new_ptrs]), idx,
+                                           C.c_void_p(ws[0]), C.c_size_t(ws[1])),
           "sgn_transfer_surfels_batch")
 
 
@@ -284,16 +308,32 @@ def sgn_disc_optimize(ctx, items, n: int, params: sgn_params):
     check(lib().sgn_disc_optimize(C.c_void_p(ctx), items, int(n), C.byref(params)), "sgn_disc_optimize")
 
 
-def sgn_disc_render(ctx, item: sgn_disc_item, inv_depth_ptr: int, index_ptr: int = 0):
+def sgn_disc_render(ctx, item: sgn_disc_item, inv_depth_ptr: int, index_ptr: int, ws):
+    """ws: (device pointer, bytes), at least sgn_disc_render_workspace_bytes(1, item)."""
     check(lib().sgn_disc_render(C.c_void_p(ctx), C.byref(item), C.c_void_p(inv_depth_ptr),
-                                C.c_void_p(index_ptr or None)), "sgn_disc_render")
+                                C.c_void_p(index_ptr or None), C.c_void_p(ws[0]), C.c_size_t(ws[1])),
+          "sgn_disc_render")
+
+
+def sgn_disc_render_workspace_bytes(n: int, items) -> int:
+    if isinstance(items, sgn_disc_item):
+        items = C.byref(items)
+    return int(lib().sgn_disc_render_workspace_bytes(int(n), items))
 
 
 def sgn_disc_place(ctx, item: sgn_disc_item, index_map_ptr: int, capacity: int,
-                   params: sgn_disc_place_params, counts_ptr: int):
+                   params: sgn_disc_place_params, counts_ptr: int, ws):
+    """ws: (device pointer, bytes), at least sgn_disc_place_workspace_bytes(1, item, spacing)."""
     check(lib().sgn_disc_place(C.c_void_p(ctx), C.byref(item), C.c_void_p(index_map_ptr),
-                               int(capacity), C.byref(params), C.c_void_p(counts_ptr)),
+                               int(capacity), C.byref(params), C.c_void_p(counts_ptr),
+                               C.c_void_p(ws[0]), C.c_size_t(ws[1])),
           "sgn_disc_place")
+
+
+def sgn_disc_place_workspace_bytes(n: int, items, spacing: int) -> int:
+    if isinstance(items, sgn_disc_item):
+        items = C.byref(items)
+    return int(lib().sgn_disc_place_workspace_bytes(int(n), items, int(spacing)))
 
 
 def sgn_disc_transfer(ctx, src: sgn_disc_item, pose: sgn_pose, dst: sgn_disc_item, capacity: int,
@@ -304,11 +344,12 @@ def sgn_disc_transfer(ctx, src: sgn_disc_item, pose: sgn_pose, dst: sgn_disc_ite
 
 
 def sgn_disc_place_batch(ctx, items, n: int, index_map_ptrs: Sequence[int], capacities: Sequence[int],
-                         params: sgn_disc_place_params, counts_ptrs: Sequence[int]):
+                         params: sgn_disc_place_params, counts_ptrs: Sequence[int], ws):
     maps = (C.c_void_p * int(n))(*[int(p) if p else None for p in index_map_ptrs])
     caps = (C.c_int32 * int(n))(*[int(c) for c in capacities])
     cnts = (C.c_void_p * int(n))(*[int(p) if p else None for p in counts_ptrs])
-    check(lib().sgn_disc_place_batch(C.c_void_p(ctx), items, int(n), maps, caps, C.byref(params), cnts),
+    check(lib().sgn_disc_place_batch(C.c_void_p(ctx), items, int(n), maps, caps, C.byref(params), cnts,
+                                     C.c_void_p(ws[0]), C.c_size_t(ws[1])),
           "sgn_disc_place_batch")
 
 
@@ -326,10 +367,11 @@ def sgn_disc_transfer_batch(ctx, srcs: Sequence[sgn_disc_item], poses: Sequence[
 
 
 def sgn_disc_render_batch(ctx, items, n: int, inv_depth_ptrs: Sequence[int],
-                          index_ptrs: Optional[Sequence[int]] = None):
+                          index_ptrs: Optional[Sequence[int]], ws):
     outs = (C.c_void_p * int(n))(*[int(p) for p in inv_depth_ptrs])
     idxs = (C.c_void_p * int(n))(*[int(p) if p else None for p in index_ptrs]) if index_ptrs else None
-    check(lib().sgn_disc_render_batch(C.c_void_p(ctx), items, int(n), outs, idxs), "sgn_disc_render_batch")
+    check(lib().sgn_disc_render_batch(C.c_void_p(ctx), items, int(n), outs, idxs, C.c_void_p(ws[0]),
+                                      C.c_size_t(ws[1])), "sgn_disc_render_batch")
 
 
 def disc_array(items: List[sgn_disc_item]):
@@ -470,18 +512,32 @@ def plan(tiles_x=0, tiles_y=0, persistent=1, waves_per_cu=0, lds_stage=0, xcd_qu
 
 
 class Context:
-    """Owns one sgn_ctx bound to a torch stream (default: the current stream)."""
+    """Owns one sgn_ctx bound to a torch stream (default: the current stream),
+    and the caller-side workspace its calls use (a torch byte tensor on the
+    context's device, grown on demand; the stream orders its reuse)."""
 
     def __init__(self, device: int = 0, stream=None):
         import torch
         self.device = device
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         self.handle = sgn_create(device, self.stream.cuda_stream)
+        self._ws = None
+
+    def workspace(self, nbytes: int):
+        """(device pointer, bytes) of a workspace of at least nbytes bytes."""
+        import torch
+        if nbytes <= 0:
+            raise ValueError("invalid arguments: the library reports no workspace size")
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(int(nbytes), dtype=torch.uint8,
+                                   device=torch.device("cuda", self.device))
+        return self._ws.data_ptr(), self._ws.numel()
 
     def close(self):
         if self.handle:
             sgn_destroy(self.handle)
             self.handle = None
+        self._ws = None
 
     def __del__(self):
         try:

@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "surfgn.h")
 
 def _declared():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:sgn_status|const char\*)\s+(sgn_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:sgn_status|const char\*|size_t)\s+(sgn_\w+)\s*\(", text, re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -120,3 +120,91 @@ int main(void) {
     assert sizes == mine
     assert offs == [s.sgn_keyframe.K.offset, s.sgn_keyframe.patch.offset,
                     s.sgn_batch_item.is_new.offset, s.sgn_device_props.name.offset]
+
+
+def _fake_surfels(sg, base):
+    """Surfel arrays at made-up device addresses: argument checks never
+    dereference them."""
+    return sg.sgn_surfels(*[base + 0x10000 * i for i in range(8)])
+
+
+def test_workspace_sizes_follow_the_documented_layout(sg):
+    g = sg.grid_of((500.0, 500.0, 320.0, 240.0), 640, 480, 4)
+    tiles = 160 * 120
+    al = lambda v: (v + 255) // 256 * 256
+    assert sg.sgn_transfer_workspace_bytes([g]) == al(8 * tiles) + al(4 * tiles)
+    assert sg.sgn_transfer_workspace_bytes([g, g]) == al(16 * tiles) + al(8 * tiles)
+    bad = sg.grid_of((500.0, 500.0, 320.0, 240.0), 640, 480, 5)
+    assert sg.sgn_transfer_workspace_bytes([g, bad]) == 0
+    img = sg.sgn_image(0x100000, 640, 480, 640, sg.SGN_F16, 1.0)
+    kf = sg.sgn_keyframe(img, None, None, 0, sg.sgn_intrinsics(500.0, 500.0, 320.0, 240.0), 4)
+    item = sg.sgn_disc_item(kf, _fake_surfels(sg, 0x200000), 0x300000, 0x310000, 1000, 10.0)
+    rtiles = 40 * 30
+    assert sg.sgn_disc_render_workspace_bytes(1, item) == (al(48 * 1000) + al(4 * rtiles) + al(4 * (rtiles + 1))
+                                                            + al(4 * 2) + al(4 * 9 * 1000))
+    # lattice 7 + 14 i: 46 x 35 candidates
+    assert sg.sgn_disc_place_workspace_bytes(1, item, 14) == al(46 * 35 + 1)
+    assert sg.sgn_disc_place_workspace_bytes(1, item, 0) == 0
+    bi = sg.sgn_batch_item(kf, _fake_surfels(sg, 0x200000), None, None, None)
+    assert sg.sgn_autotune_workspace_bytes(1, sg.batch_array([bi])) == 8 * al(4 * tiles)
+
+
+def test_undersized_workspace_is_refused_before_anything_is_enqueued(sg):
+    """A missing, misaligned or one-byte-short workspace is an argument error
+    (checked before the context, so no GPU is needed to see it)."""
+    L = sg.lib()
+    g = sg.grid_of((100.0, 100.0, 16.0, 16.0), 32, 32, 4)
+    need = sg.sgn_transfer_workspace_bytes([g])
+    src, dst = _fake_surfels(sg, 0x200000), _fake_surfels(sg, 0x400000)
+    pose = sg.pose_of(__import__("numpy").eye(3), __import__("numpy").zeros(3))
+    call = lambda ws, nb: L.sgn_transfer_surfels(None, C.byref(g), C.byref(src), C.byref(pose), C.byref(g),
+                                                 C.byref(dst), C.c_void_p(0x600000), None, C.c_void_p(ws),
+                                                 C.c_size_t(nb))
+    assert call(0x700000, need - 1) == sg.SGN_E_INVALID
+    assert "workspace too small" in sg.sgn_last_error()
+    assert call(0, need) == sg.SGN_E_INVALID
+    assert "null workspace" in sg.sgn_last_error()
+    assert call(0x700010, need) == sg.SGN_E_INVALID
+    assert "aligned" in sg.sgn_last_error()
+    # with a sufficient workspace the next check is the missing context
+    assert call(0x700000, need) == sg.SGN_E_INVALID
+    assert "null context" in sg.sgn_last_error()
+    img = sg.sgn_image(0x100000, 64, 48, 64, sg.SGN_F32, 1.0)
+    kf = sg.sgn_keyframe(img, None, None, 0, sg.sgn_intrinsics(60.0, 60.0, 32.0, 24.0), 4)
+    item = sg.sgn_disc_item(kf, _fake_surfels(sg, 0x200000), 0x300000, 0x310000, 10, 5.0)
+    rneed = sg.sgn_disc_render_workspace_bytes(1, item)
+    assert L.sgn_disc_render(None, C.byref(item), C.c_void_p(0x800000), None, C.c_void_p(0x700000),
+                             C.c_size_t(rneed - 1)) == sg.SGN_E_INVALID
+    assert "workspace too small" in sg.sgn_last_error()
+    pp = sg.sgn_disc_place_params(1.0, 2.0, 7)
+    pneed = sg.sgn_disc_place_workspace_bytes(1, item, 7)
+    assert L.sgn_disc_place(None, C.byref(item), C.c_void_p(0x800000), 20, C.byref(pp), C.c_void_p(0x900000),
+                            C.c_void_p(0x700000), C.c_size_t(pneed - 1)) == sg.SGN_E_INVALID
+    assert "workspace too small" in sg.sgn_last_error()
+    bi = sg.batch_array([sg.sgn_batch_item(kf, _fake_surfels(sg, 0x200000), None, None, None)])
+    aneed = sg.sgn_autotune_workspace_bytes(1, bi)
+    out = sg.sgn_plan()
+    prm = sg.params(iters=2)
+    assert L.sgn_autotune(None, bi, 1, C.byref(prm), C.byref(out), C.c_void_p(0x700000),
+                          C.c_size_t(aneed - 1)) == sg.SGN_E_INVALID
+    assert "workspace too small" in sg.sgn_last_error()
+
+
+def test_row_pitch_of_16_mib_is_refused(sg):
+    """Tap addresses are formed with 24-bit multiplies: row pitches of 2^24
+    bytes or more are refused (checked before the context)."""
+    L = sg.lib()
+    W = 1 << 22                       # f32: 16 MiB per row
+    img = sg.sgn_image(0x100000, 16, 4, W, sg.SGN_F32, 1.0)
+    kf = sg.sgn_keyframe(img, None, None, 0, sg.sgn_intrinsics(60.0, 60.0, 8.0, 2.0), 4)
+    item = sg.sgn_disc_item(kf, _fake_surfels(sg, 0x200000), 0x300000, 0x310000, 1, 2.0)
+    need = sg.sgn_disc_render_workspace_bytes(1, item)
+    assert L.sgn_disc_render(None, C.byref(item), C.c_void_p(0x800000), None, C.c_void_p(0x700000),
+                             C.c_size_t(need)) == sg.SGN_E_UNSUPPORTED
+    assert "16 MiB" in sg.sgn_last_error()
+    img.pitch = W - 4                 # just below: accepted by the image check
+    kf.kf = img
+    item.kf = kf
+    assert L.sgn_disc_render(None, C.byref(item), C.c_void_p(0x800000), None, C.c_void_p(0x700000),
+                             C.c_size_t(need)) == sg.SGN_E_INVALID
+    assert "null context" in sg.sgn_last_error()

@@ -219,11 +219,14 @@ def test_disc_argument_errors(ctx):
     dk = engine.DiscKeyframe.from_scene(ctx, kf, discs, capacity=discs.ux.size + 10)
     print("case disc argument errors", flush=True)
     prm = sg.params(iters=3)
+    rneed = sg.sgn_disc_render_workspace_bytes(1, dk.item())
+    pneed = sg.sgn_disc_place_workspace_bytes(1, dk.item(), 14)
+    wp, wb = ctx.workspace(max(rneed, pneed))
     for r in (0.0, -1.0, 12.5, float("nan")):
         it = dk.item()
         it.radius = r
         assert L.sgn_disc_optimize(ctx.handle, sg.disc_array([it]), 1, prm) == sg.SGN_E_INVALID
-        assert L.sgn_disc_render(ctx.handle, it, dk.inv_depth_out.data_ptr(), None) == sg.SGN_E_INVALID
+        assert L.sgn_disc_render(ctx.handle, it, dk.inv_depth_out.data_ptr(), None, wp, wb) == sg.SGN_E_INVALID
     it = dk.item()
     it.ux = None
     assert L.sgn_disc_optimize(ctx.handle, sg.disc_array([it]), 1, prm) == sg.SGN_E_INVALID
@@ -233,12 +236,18 @@ def test_disc_argument_errors(ctx):
     ok_pp = sg.sgn_disc_place_params(1.0, 2.0, 14)
     cnt = dk.counts.data_ptr()
     imap = dk.index_out.data_ptr()
-    assert L.sgn_disc_place(ctx.handle, dk.item(), imap, discs.ux.size - 1, ok_pp, cnt) == sg.SGN_E_INVALID
+    assert L.sgn_disc_place(ctx.handle, dk.item(), imap, discs.ux.size - 1, ok_pp, cnt, wp, wb) == sg.SGN_E_INVALID
     for pp in (sg.sgn_disc_place_params(0.0, 2.0, 14), sg.sgn_disc_place_params(1.0, 4.5, 14),
                sg.sgn_disc_place_params(1.0, 2.0, 0)):
-        assert L.sgn_disc_place(ctx.handle, dk.item(), imap, dk.capacity, pp, cnt) == sg.SGN_E_INVALID
-    assert L.sgn_disc_place(ctx.handle, dk.item(), None, dk.capacity, ok_pp, cnt) == sg.SGN_E_INVALID
-    assert L.sgn_disc_render(ctx.handle, dk.item(), None, None) == sg.SGN_E_INVALID
+        assert L.sgn_disc_place(ctx.handle, dk.item(), imap, dk.capacity, pp, cnt, wp, wb) == sg.SGN_E_INVALID
+    assert L.sgn_disc_place(ctx.handle, dk.item(), None, dk.capacity, ok_pp, cnt, wp, wb) == sg.SGN_E_INVALID
+    assert L.sgn_disc_render(ctx.handle, dk.item(), None, None, wp, wb) == sg.SGN_E_INVALID
+    # undersized or missing workspaces
+    assert L.sgn_disc_render(ctx.handle, dk.item(), dk.inv_depth_out.data_ptr(), None, wp,
+                             rneed - 1) == sg.SGN_E_INVALID
+    assert "workspace" in sg.sgn_last_error()
+    assert L.sgn_disc_place(ctx.handle, dk.item(), imap, dk.capacity, ok_pp, cnt, None, pneed) == sg.SGN_E_INVALID
+    assert L.sgn_disc_place(ctx.handle, dk.item(), imap, dk.capacity, ok_pp, cnt, wp, pneed - 1) == sg.SGN_E_INVALID
     # nothing was enqueued: the state is untouched
     torch.cuda.synchronize()
     assert np.array_equal(dk.state_host()["inv_depth"], discs.init_id)
@@ -420,7 +429,8 @@ def test_disc_render_batch_equals_one_by_one(ctx):
         d.index_out.fill_(7)
     items = sg.disc_array([d.item() for d in dks])
     sg.sgn_disc_render_batch(ctx.handle, items, len(dks), [d.inv_depth_out.data_ptr() for d in dks],
-                             [d.index_out.data_ptr() if i != 1 else 0 for i, d in enumerate(dks)])
+                             [d.index_out.data_ptr() if i != 1 else 0 for i, d in enumerate(dks)],
+                             ctx.workspace(sg.sgn_disc_render_workspace_bytes(len(dks), items)))
     torch.cuda.synchronize()
     for i, (d, (rd, ri)) in enumerate(zip(dks, ref)):
         assert np.array_equal(d.inv_depth_out.cpu().numpy(), rd)

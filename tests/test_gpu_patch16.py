@@ -116,7 +116,7 @@ def test_patch16_batch_equals_plain_and_autotune(ctx):
     # leaves the state as it found it
     ds = [engine.DeviceKeyframe.from_scene(ctx, k, storage="f16") for k in kfs]
     items = sg.batch_array([d.item() for d in ds])
-    best = sg.sgn_autotune(ctx.handle, items, len(ds), prm)
+    best = engine.autotune(ctx, items, len(ds), prm)
     torch.cuda.synchronize()
     assert (best.tiles_x, best.tiles_y, best.groups) == (1, 1, 1)
     for d, k in zip(ds, kfs):

@@ -121,7 +121,7 @@ def test_autotune_picks_a_4x4_plan_and_restores_the_state(ctx):
     ds = [engine.DeviceKeyframe.from_scene(ctx, k) for k in kfs]
     before = [d.state.to_host() for d in ds]
     items = sg.batch_array([d.item(render=False, init=False) for d in ds])
-    best = sg.sgn_autotune(ctx.handle, items, len(ds), prm)
+    best = engine.autotune(ctx, items, len(ds), prm)
     torch.cuda.synchronize()
     for d, b in zip(ds, before):
         h = d.state.to_host()

@@ -38,8 +38,10 @@ def _run(ctx, src_grid, ids, ns, flags, last, R, t, dst_grid):
     dst = sg.SurfelState.from_arrays(np.full(m1, 7.0, np.float32), np.ones((m1, 3), np.float32))
     is_new = torch.full((m1,), 9, dtype=torch.uint8, device="cuda")
     win = torch.full((m1,), -5, dtype=torch.int32, device="cuda")
+    g1 = sg.grid_of(K1, W1, H1, S1)
     sg.sgn_transfer_surfels(ctx.handle, sg.grid_of(K0, W0, H0, S0), src.c, sg.pose_of(R, t),
-                            sg.grid_of(K1, W1, H1, S1), dst.c, is_new.data_ptr(), win.data_ptr())
+                            g1, dst.c, is_new.data_ptr(), win.data_ptr(),
+                            ctx.workspace(sg.sgn_transfer_workspace_bytes([g1])))
     torch.cuda.synchronize()
     return dst.to_host(), is_new.cpu().numpy(), win.cpu().numpy()
 
@@ -117,13 +119,21 @@ def test_regrid_argument_errors(ctx):
     g_ok = sg.grid_of((100.0, 100.0, 4.0, 4.0), 8, 8, 4)
     g_bad = sg.grid_of((100.0, 100.0, 4.0, 4.0), 8, 8, 5)
     pose = sg.pose_of(np.eye(3), np.zeros(3))
+    need = sg.sgn_transfer_workspace_bytes([g_ok])
+    ws = ctx.workspace(need)
     with pytest.raises(sg.SurfgnError):
-        sg.sgn_transfer_surfels(ctx.handle, g_bad, src.c, pose, g_ok, dst.c, nw.data_ptr())
+        sg.sgn_transfer_surfels(ctx.handle, g_bad, src.c, pose, g_ok, dst.c, nw.data_ptr(), None, ws)
     with pytest.raises(sg.SurfgnError):
-        sg.sgn_transfer_surfels(ctx.handle, g_ok, src.c, pose, g_ok, dst.c, 0)
+        sg.sgn_transfer_surfels(ctx.handle, g_ok, src.c, pose, g_ok, dst.c, 0, None, ws)
     bad_pose = sg.pose_of(np.full((3, 3), np.nan), np.zeros(3))
     with pytest.raises(sg.SurfgnError):
-        sg.sgn_transfer_surfels(ctx.handle, g_ok, src.c, bad_pose, g_ok, dst.c, nw.data_ptr())
+        sg.sgn_transfer_surfels(ctx.handle, g_ok, src.c, bad_pose, g_ok, dst.c, nw.data_ptr(), None, ws)
+    # a workspace one byte short, or none, is refused before anything is enqueued
+    with pytest.raises(sg.SurfgnError, match="workspace"):
+        sg.sgn_transfer_surfels(ctx.handle, g_ok, src.c, pose, g_ok, dst.c, nw.data_ptr(), None,
+                                (ws[0], need - 1))
+    with pytest.raises(sg.SurfgnError, match="workspace"):
+        sg.sgn_transfer_surfels(ctx.handle, g_ok, src.c, pose, g_ok, dst.c, nw.data_ptr(), None, (0, need))
 
 
 def test_keyframe_switch_chain_matches_oracle(ctx):
@@ -163,7 +173,8 @@ def test_keyframe_switch_chain_matches_oracle(ctx):
     stB = sg.SurfelState.from_arrays(np.zeros(m, np.float32), np.tile([0, 0, -1.0], (m, 1)))
     is_new = torch.zeros(m, dtype=torch.uint8, device="cuda")
     sg.sgn_transfer_surfels(ctx.handle, sg.grid_of(*grid), dA.state.c, sg.pose_of(R0, t0),
-                            sg.grid_of(*grid), stB.c, is_new.data_ptr())
+                            sg.grid_of(*grid), stB.c, is_new.data_ptr(), None,
+                            ctx.workspace(sg.sgn_transfer_workspace_bytes([sg.grid_of(*grid)])))
     torch.cuda.synchronize()
     hB = stB.to_host()
     dB = engine.DeviceKeyframe(ctx, kf.nbr_images[0], imgs_b, np.stack(Rb), np.stack(tb), kf.K,
@@ -223,11 +234,13 @@ def test_regrid_batch_equals_one_by_one(ctx):
         news.append(torch.full((m1,), 9, dtype=torch.uint8, device="cuda"))
         wins.append(torch.full((m1,), -5, dtype=torch.int32, device="cuda"))
     K0, W0, H0, S0 = src_grid
+    dgrids = [sg.grid_of(*c[6]) for c in cases]
     sg.sgn_transfer_surfels_batch(ctx.handle, [sg.grid_of(K0, W0, H0, S0)] * 4, [s.c for s in srcs],
                                   [sg.pose_of(c[4], c[5]) for c in cases],
-                                  [sg.grid_of(*c[6]) for c in cases], [d.c for d in dsts],
+                                  dgrids, [d.c for d in dsts],
                                   [n.data_ptr() for n in news],
-                                  [w.data_ptr() if k != 2 else 0 for k, w in enumerate(wins)])
+                                  [w.data_ptr() if k != 2 else 0 for k, w in enumerate(wins)],
+                                  ctx.workspace(sg.sgn_transfer_workspace_bytes(dgrids)))
     torch.cuda.synchronize()
     for k, (dev1, new1, win1) in enumerate(singles):
         dev = dsts[k].to_host()
