@@ -72,7 +72,8 @@ class GridC(C.Structure):
 class ParamsC(C.Structure):
     _fields_ = [("iters", C.c_int32), ("huber_k", C.c_double), ("depth_only", C.c_int32),
                 ("beta_r", C.c_double), ("stamp", C.c_uint32), ("lm_lambda", C.c_double),
-                ("perturb", C.c_double), ("perturb_seed", C.c_uint32), ("perturb_parts", C.c_int32)]
+                ("perturb", C.c_double), ("perturb_seed", C.c_uint32), ("perturb_parts", C.c_int32),
+                ("tie_window", C.c_double)]
 
 
 _lib = None
@@ -195,13 +196,14 @@ class OracleParams:
     lm_lambda: float = 0.0
     perturb: float = 0.0        # conditioning probe (tests only), 0 = off
     perturb_seed: int = 0
-    perturb_parts: int = 0      # 0 both, 1 normal equations only, 2 state only
+    perturb_parts: int = 0      # bit set: 1 normal equations, 2 state, 4 LM acceptance; 0 = all
+    tie_window: float = 0.0     # probe: relative noise of the LM acceptance threshold (0: perturb)
 
     def c(self, patch: int) -> ParamsC:
         br = float(self.beta_r) if self.beta_r is not None else float(patch)
         return ParamsC(int(self.iters), float(self.huber_k), int(bool(self.depth_only)), br,
                        int(self.stamp), float(self.lm_lambda), float(self.perturb),
-                       int(self.perturb_seed), int(self.perturb_parts))
+                       int(self.perturb_seed), int(self.perturb_parts), float(self.tie_window))
 
 
 class OracleKeyframe:

@@ -444,6 +444,7 @@ static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_param
         }
         const int probe_ne = p->perturb > 0.0 && (p->perturb_parts & 1 || p->perturb_parts == 0);
         const int probe_state = p->perturb > 0.0 && (p->perturb_parts & 2 || p->perturb_parts == 0);
+        const int probe_decision = p->perturb > 0.0 && (p->perturb_parts & 4 || p->perturb_parts == 0);
         if (probe_ne) {
             /* probe: relative noise on the normal equations as well (float
              * accumulation of J^T W J and J^T W r reaches the step scaled by
@@ -493,7 +494,13 @@ static void optimize_one(const sgo_keyframe* kf, sgo_surfels* s, const sgo_param
             double H2[9], b2v[3], cost2;
             int32_t nv2 = linearize(kf, sp, id_new, n_new, p->huber_k, p->depth_only, H2,
                                     b2v, &cost2, s->margin ? &margin : NULL);
-            if (nv2 < 3 || !(cost2 / nv2 <= cost / nvalid)) {
+            /* probe: a relative tie window on the comparison (a float cost
+             * sum decides near-ties either way) */
+            double bar = cost / nvalid;
+            if (probe_decision)
+                bar *= 1.0 + (p->tie_window > 0.0 ? p->tie_window : p->perturb) *
+                                 probe_uniform(p->perturb_seed, i, it, 16);
+            if (nv2 < 3 || !(cost2 / nv2 <= bar)) {
                 lambda *= 10.0;
                 continue;
             }

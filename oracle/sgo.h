@@ -66,8 +66,12 @@ typedef struct {
                                  by (1 + perturb * u), u in [-1, 1) from a counter hash of
                                  (perturb_seed, surfel, iteration, component) */
     uint32_t perturb_seed;
-    int32_t perturb_parts;    /* which parts the probe perturbs: 0 or 3 = both, 1 = the normal
-                                 equations only, 2 = the state after accepted steps only */
+    int32_t perturb_parts;    /* which parts the probe perturbs, a bit set: 1 = the normal
+                                 equations, 2 = the state after accepted steps, 4 = the damped
+                                 variant's acceptance threshold (cost / nvalid scaled by
+                                 (1 + tie_window * u)); 0 = all three */
+    double tie_window;        /* test probe: the acceptance threshold's relative noise (bit 4 of
+                                 perturb_parts); 0 = perturb */
 } sgo_params;
 
 enum {
