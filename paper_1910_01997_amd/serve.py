@@ -7,17 +7,24 @@ asks for the Gauss-Newton iterations on the stream's surfels and returns the
 surfels and the per-pixel inverse depth.
 
 Scheduling (host side, this module):
-  * admission by memory: a request is admitted only when its response buffers
-    fit in the pool budget; otherwise it waits (FIFO) and is admitted as soon
-    as completed requests release memory;
+  * admission by memory: every admitted request owns a region of the
+    response memory (pinned host memory of the pool's size, carved by a
+    first-fit allocator) that its depth map and surfels are copied into; a
+    request is admitted only when its region fits, otherwise it waits and is
+    admitted as soon as completed requests release memory;
+  * per-stream order: a stream never has two requests admitted or in
+    flight, so each request sees the state left by the previous one, and a
+    request that must wait for its stream holds no memory meanwhile (no
+    head-of-line blocking of other streams behind it); among the streams
+    that are free the oldest request is admitted first;
   * continuous batching: whenever an execution lane is free, every admitted
-    request whose stream has nothing in flight is packed into one batch and
-    launched (one persistent fused kernel for the whole batch); batches on
-    different lanes overlap on the device;
-  * per-stream order: a stream never has two requests in flight, so each
-    request sees the state left by the previous one;
+    request is packed into one batch and launched (one persistent fused
+    kernel for the whole batch); batches on different lanes overlap on the
+    device;
   * a request whose execution fails is completed with its error and its
-    memory released; the rest of its batch is not affected by the scheduler.
+    memory released; the rest of its batch is not affected by the scheduler;
+  * on completion a request's response is copied out of its region (when
+    the server keeps results) and the region released.
 
 The executor does the device work.  HipExecutor uses the C ABI
 (sgn_optimize_batch on per-lane contexts and streams); tests substitute a
@@ -45,6 +52,7 @@ class Request:
     launched: float = 0.0
     done: float = 0.0
     nbytes: int = 0
+    offset: int = -1                     # response region in the pool (while admitted)
     error: Optional[str] = None
     result: Any = None
 
@@ -54,36 +62,69 @@ class Request:
 
 
 class MemoryPool:
-    """Byte budget for per-request buffers (admission control)."""
+    """Byte budget of the response memory with first-fit placement: try_take
+    returns the offset of a free region of n bytes (aligned to ALIGN) or None
+    when none fits; give releases it.  Free neighbours merge."""
+
+    ALIGN = 256
 
     def __init__(self, budget: int):
         self.budget = int(budget)
         self.used = 0
         self.peak = 0
+        self._free = [(0, self.budget)]          # sorted (offset, size)
 
-    def try_take(self, n: int) -> bool:
+    def _round(self, n: int) -> int:
+        return (int(n) + self.ALIGN - 1) // self.ALIGN * self.ALIGN
+
+    def try_take(self, n: int) -> Optional[int]:
         if n > self.budget:
             raise ValueError(f"request needs {n} bytes, more than the whole pool ({self.budget})")
-        if self.used + n > self.budget:
-            return False
-        self.used += n
-        self.peak = max(self.peak, self.used)
-        return True
+        need = self._round(n)
+        for i, (off, size) in enumerate(self._free):
+            if size >= need:
+                if size == need:
+                    del self._free[i]
+                else:
+                    self._free[i] = (off + need, size - need)
+                self.used += need
+                self.peak = max(self.peak, self.used)
+                return off
+        return None
 
-    def give(self, n: int):
-        self.used -= n
+    def give(self, off: int, n: int):
+        need = self._round(n)
+        self.used -= need
         assert self.used >= 0
+        import bisect
+        i = bisect.bisect_left(self._free, (off, 0))
+        self._free.insert(i, (off, need))
+        # merge with the following and the preceding region
+        if i + 1 < len(self._free) and self._free[i][0] + self._free[i][1] == self._free[i + 1][0]:
+            self._free[i] = (self._free[i][0], self._free[i][1] + self._free[i + 1][1])
+            del self._free[i + 1]
+        if i > 0 and self._free[i - 1][0] + self._free[i - 1][1] == self._free[i][0]:
+            self._free[i - 1] = (self._free[i - 1][0], self._free[i - 1][1] + self._free[i][1])
+            del self._free[i]
 
 
 class Executor:
     """Device side of the server.  launch() enqueues one batch on a lane and
     returns a handle; poll() says whether it finished; finish() returns the
-    per-request errors (None = success)."""
+    per-request errors (None = success).  attach_memory() hands over the
+    pool's size once (an executor allocates its response memory there);
+    response() returns a completed request's own copy of its response."""
 
     lanes = 1
 
+    def attach_memory(self, nbytes: int):
+        pass
+
     def request_bytes(self, req: Request) -> int:
         raise NotImplementedError
+
+    def response(self, req: Request):
+        return None
 
     def launch(self, lane: int, batch: List[Request]) -> Any:
         raise NotImplementedError
@@ -96,15 +137,21 @@ class Executor:
 
 
 class Server:
+    """keep_results: a completed request keeps its own copy of its response
+    in Request.result (otherwise the response is dropped on completion)."""
+
     def __init__(self, executor: Executor, pool_bytes: int, max_batch: int = 32,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter, keep_results: bool = False):
         self.ex = executor
         self.pool = MemoryPool(pool_bytes)
+        executor.attach_memory(self.pool.budget)
         self.max_batch = max_batch
         self.clock = clock
-        self.waiting: Deque[Request] = collections.deque()     # not yet admitted (FIFO)
+        self.keep_results = keep_results
+        self.waiting: Dict[int, Deque[Request]] = {}            # per stream, not yet admitted
+        self.n_waiting = 0
         self.admitted: Deque[Request] = collections.deque()    # admitted, not launched
-        self.busy_streams: set = set()
+        self.busy_streams: set = set()                         # admitted or in flight
         self.lanes_free = list(range(executor.lanes))
         self.inflight: List[tuple] = []                        # (handle, lane, batch)
         self.completed: List[Request] = []
@@ -116,34 +163,41 @@ class Server:
         self._rid += 1
         req.rid = self._rid
         req.nbytes = self.ex.request_bytes(req)
-        self.waiting.append(req)
+        if req.nbytes > self.pool.budget:
+            raise ValueError(f"request needs {req.nbytes} bytes, more than the whole pool "
+                             f"({self.pool.budget})")
+        self.waiting.setdefault(req.stream, collections.deque()).append(req)
+        self.n_waiting += 1
 
     def _admit(self):
-        while self.waiting and self.pool.try_take(self.waiting[0].nbytes):
-            r = self.waiting.popleft()
-            r.admitted = self.clock()
-            self.admitted.append(r)
+        # the oldest waiting request of a stream with nothing admitted or in
+        # flight, while its response region fits (no overtaking on memory)
+        while self.n_waiting:
+            head = None
+            for s, q in self.waiting.items():
+                if q and s not in self.busy_streams and (head is None or q[0].rid < head.rid):
+                    head = q[0]
+            if head is None:
+                return
+            off = self.pool.try_take(head.nbytes)
+            if off is None:
+                return
+            self.waiting[head.stream].popleft()
+            self.n_waiting -= 1
+            head.offset = off
+            head.admitted = self.clock()
+            self.busy_streams.add(head.stream)
+            self.admitted.append(head)
 
     def _launch(self):
         while self.lanes_free and self.admitted:
-            batch, keep = [], collections.deque()
-            taken = set()
-            while self.admitted:
-                r = self.admitted.popleft()
-                if (r.stream in self.busy_streams or r.stream in taken or
-                        len(batch) >= self.max_batch):
-                    keep.append(r)
-                else:
-                    batch.append(r)
-                    taken.add(r.stream)
-            self.admitted = keep
-            if not batch:
-                return
+            batch = []
+            while self.admitted and len(batch) < self.max_batch:
+                batch.append(self.admitted.popleft())
             lane = self.lanes_free.pop(0)
             now = self.clock()
             for r in batch:
                 r.launched = now
-            self.busy_streams |= taken
             try:
                 h = self.ex.launch(lane, batch)
             except Exception as e:            # nothing was enqueued for this batch
@@ -158,7 +212,9 @@ class Server:
         for r, err in zip(batch, errors):
             r.done = now
             r.error = err
-            self.pool.give(r.nbytes)
+            if err is None and self.keep_results:
+                r.result = self.ex.response(r)
+            self.pool.give(r.offset, r.nbytes)
             self.busy_streams.discard(r.stream)
             self.completed.append(r)
 
@@ -183,7 +239,7 @@ class Server:
         self._launch()
 
     def idle(self) -> bool:
-        return not (self.waiting or self.admitted or self.inflight)
+        return not (self.n_waiting or self.admitted or self.inflight)
 
     def drain(self, timeout: float = 60.0):
         t0 = self.clock()
@@ -265,15 +321,21 @@ class CameraStream:
         self.frames = extra_frames["images"]          # device tensor (E, H, W) storage dtype
         self.frame_R = extra_frames["R"]
         self.frame_t = extra_frames["t"]
-        # the response buffers (pinned host memory, allocated once): a stream
-        # has one request in flight at a time, so a response stays valid
-        # until the stream's next request completes
-        self.resp_depth = torch.empty((self.dk.height, self.dk.width), dtype=torch.float32, pin_memory=True)
-        self.resp_state = torch.empty((8, self.dk.n_surfels), dtype=torch.float32, pin_memory=True)
 
     @property
     def response_bytes(self) -> int:
+        """A response: the inverse-depth map (H x W float32) and the surfels
+        (8 x n float32 rows: id, nx, ny, nz, flags, cost, nvalid,
+        last_update, the integer fields bit-cast)."""
         return self.dk.width * self.dk.height * 4 + self.dk.n_surfels * 8 * 4
+
+    def response_views(self, slab, offset: int):
+        """(depth, state) views of a response region of the pinned slab."""
+        import torch
+        H, W, n = self.dk.height, self.dk.width, self.dk.n_surfels
+        d = slab[offset:offset + H * W * 4].view(torch.float32).view(H, W)
+        st = slab[offset + H * W * 4:offset + H * W * 4 + 8 * n * 4].view(torch.float32).view(8, n)
+        return d, st
 
     # checkpoint / resume
     def snapshot(self) -> Dict[str, np.ndarray]:
@@ -335,16 +397,16 @@ def load_snapshot(path) -> Dict[str, np.ndarray]:
         return {k: z[k] for k in z.files}
 
 
-def respond(cs: CameraStream, torch):
-    """Enqueue the copies of a stream's depth map and surfel state into its
-    response buffers on the current stream; returns (depth, state)."""
+def respond(cs: CameraStream, slab, req: Request, torch):
+    """Enqueue the copies of a stream's depth map and surfel state into the
+    request's response region on the current stream."""
     dk = cs.dk
-    cs.resp_depth.copy_(dk.inv_depth_out, non_blocking=True)
+    depth, state = cs.response_views(slab, req.offset)
+    depth.copy_(dk.inv_depth_out, non_blocking=True)
     for k, src in enumerate((dk.state.inv_depth, dk.state.nx, dk.state.ny, dk.state.nz,
                              dk.state.flags.view(torch.float32), dk.state.cost,
                              dk.state.nvalid.view(torch.float32), dk.state.last_update.view(torch.float32))):
-        cs.resp_state[k].copy_(src, non_blocking=True)
-    return (cs.resp_depth, cs.resp_state)
+        state[k].copy_(src, non_blocking=True)
 
 
 class HipExecutor(Executor):
@@ -370,9 +432,19 @@ class HipExecutor(Executor):
         self.single_plan = sg.plan(2, 2, 0, 0, 0, 0, groups=1)
         self.large_plan = sg.plan(2, 2, 1, 0, 0, 1, groups=4)
         self.small_batch_surfels = 200_000
+        self.slab = None
+
+    def attach_memory(self, nbytes: int):
+        """The response memory: one pinned host allocation of the pool's size."""
+        self.slab = self.torch.empty(int(nbytes), dtype=self.torch.uint8, pin_memory=True)
 
     def request_bytes(self, req: Request) -> int:
         return self.streams[req.stream].response_bytes
+
+    def response(self, req: Request):
+        """The request's own copy of its response: (depth (H, W), surfels (8, n))."""
+        d, st = self.streams[req.stream].response_views(self.slab, req.offset)
+        return d.numpy().copy(), st.numpy().copy()
 
     def launch(self, lane: int, batch: List[Request]):
         torch = self.torch
@@ -417,20 +489,19 @@ class HipExecutor(Executor):
                     plan = self.small_plan if total < self.small_batch_surfels else self.large_plan
                 arr = self.sg.batch_array(items)
                 self.sg.sgn_optimize_batch(ctx, arr, len(items), self.params, plan)
-            # responses: depth map and surfels copied into the stream's host buffers
-            results = [respond(self.streams[r.stream], torch) for r in batch]
+            # responses: depth map and surfels copied into each request's region
+            for r in batch:
+                respond(self.streams[r.stream], self.slab, r, torch)
             ev = torch.cuda.Event()
             ev.record(ts)
-        return (ev, batch, results, outs, arr)
+        return (ev, batch, outs, arr)
 
     def poll(self, handle) -> bool:
         return handle[0].query()
 
     def finish(self, handle):
-        ev, batch, results, _, _ = handle
+        ev, batch, _, _ = handle
         ev.synchronize()
-        for r, res in zip(batch, results):
-            r.result = res
         return [None] * len(batch)
 
 
@@ -466,10 +537,10 @@ class PlainExecutor(HipExecutor):
             self.sg.sgn_optimize_keyframe(ctx.handle, view.c, dk.state.c, self.params,
                                           self.plain_plan)
             self.sg.sgn_render_inverse_depth(ctx.handle, view.c, dk.state.c, dk.inv_depth_out.data_ptr())
-            result = respond(cs, torch)
+            respond(cs, self.slab, r, torch)
             ev = torch.cuda.Event()
             ev.record(ts)
-        return (ev, batch, [result], [view], None)
+        return (ev, batch, [view], None)
 
 
 def make_streams(ctx, specs, extra: int = 4, storage: str = "f16", device="cuda"):
@@ -508,20 +579,26 @@ def make_streams(ctx, specs, extra: int = 4, storage: str = "f16", device="cuda"
 def serving_benchmark(n_streams: int = 32, rate: float = 200.0, duration: float = 6.0,
                       warmup: float = 1.0, storage: str = "f16", lanes: int = 2,
                       pool_bytes: int = 256 << 20, iters: int = 15, seed: int = 599,
-                      specs=None, log=print):
+                      specs=None, log=print, sweep=(), sweep_duration: float = 2.0,
+                      sweep_warmup: float = 0.25):
     """Served (continuous batching) and plain (FIFO, one request at a time,
-    single-keyframe calls) runs of the same Poisson trace.  Returns the
-    latency / throughput statistics of both."""
+    single-keyframe calls) runs of the same Poisson trace at `rate`, then, on
+    the same resident streams, shorter traces at each rate of `sweep`.
+    Returns the latency / throughput statistics of both modes, the sweep's
+    under "sweep" keyed by rate."""
     import torch
 
     from . import surfgn as sg
     from scenegen import stream_specs
     specs = specs if specs is not None else stream_specs(n_streams)
     extra = 4
-    trace = poisson_arrivals(rate, duration, len(specs), seed, extra)
+    traces = [(rate, duration, warmup)] + [(r, sweep_duration, sweep_warmup) for r in sweep]
     out = {"trace": {"streams": len(specs), "rate_rps": rate, "seconds": duration,
-                     "warmup_s": warmup, "requests": len(trace), "iterations": iters,
-                     "storage": storage, "pool_mb": pool_bytes >> 20, "lanes": lanes}}
+                     "warmup_s": warmup, "iterations": iters, "storage": storage,
+                     "pool_mb": pool_bytes >> 20, "lanes": lanes,
+                     "requests": len(poisson_arrivals(rate, duration, len(specs), seed, extra))}}
+    if sweep:
+        out["sweep"] = {str(int(r) if float(r).is_integer() else r): {} for r in sweep}
     for mode in ("served", "plain"):
         ctx = sg.Context(0)
         streams = make_streams(ctx, specs, extra=extra, storage=storage)
@@ -533,18 +610,25 @@ def serving_benchmark(n_streams: int = 32, rate: float = 200.0, duration: float 
         for s in range(min(4, len(streams))):
             srv.submit(Request(stream=s, arrival=srv.clock(), frame_index=0))
         srv.drain()
-        srv.completed.clear()
-        srv.batches.clear()
-        done = run_trace(srv, trace, warmup=warmup)
-        st = latency_stats(done)
-        sf = sum(streams[r.stream].dk.n_surfels * streams[r.stream].dk.n_nbr for r in done
-                 if r.error is None) * iters
-        span = max(r.done for r in done) - min(r.arrival for r in done) if done else 1.0
-        st["surfel_frame_updates_per_s"] = sf / span
-        st["mean_batch"] = float(np.mean(srv.batches)) if srv.batches else 0.0
-        st["pool_peak_mb"] = srv.pool.peak / 2 ** 20
-        out[mode] = st
-        log(f"{mode}: {st}")
+        for k, (r_rate, r_dur, r_warm) in enumerate(traces):
+            srv.completed.clear()
+            srv.batches.clear()
+            srv.pool.peak = 0
+            trace = poisson_arrivals(r_rate, r_dur, len(specs), seed + k, extra)
+            done = run_trace(srv, trace, warmup=r_warm)
+            st = latency_stats(done)
+            st["offered_rps"] = r_rate
+            sf = sum(streams[r.stream].dk.n_surfels * streams[r.stream].dk.n_nbr for r in done
+                     if r.error is None) * iters
+            span = max(r.done for r in done) - min(r.arrival for r in done) if done else 1.0
+            st["surfel_frame_updates_per_s"] = sf / span
+            st["mean_batch"] = float(np.mean(srv.batches)) if srv.batches else 0.0
+            st["pool_peak_mb"] = srv.pool.peak / 2 ** 20
+            if k == 0:
+                out[mode] = st
+            else:
+                out["sweep"][str(int(r_rate) if float(r_rate).is_integer() else r_rate)][mode] = st
+            log(f"{mode} at {r_rate:g} req/s: {st}")
         for c in getattr(ex, "ctxs", []):
             c.close()
         ctx.close()

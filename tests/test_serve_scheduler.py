@@ -66,22 +66,37 @@ def _run(server, clock, arrivals, step=0.25, horizon=100.0):
 
 
 def test_memory_pool_never_exceeds_budget():
-    p = MemoryPool(1000)
-    assert p.try_take(600)
-    assert not p.try_take(500)
-    p.give(600)
-    assert p.try_take(1000)
+    p = MemoryPool(1024)
+    a = p.try_take(600)                 # 768 bytes with the 256-byte alignment
+    assert a == 0
+    assert p.try_take(500) is None      # 512 more do not fit
+    p.give(a, 600)
+    assert p.used == 0
+    assert p.try_take(1024) == 0
     with pytest.raises(ValueError):
-        p.try_take(1001)
+        p.try_take(1025)
+
+
+def test_memory_pool_first_fit_and_merging():
+    p = MemoryPool(4 * 256)
+    offs = [p.try_take(256) for _ in range(4)]
+    assert offs == [0, 256, 512, 768] and p.try_take(1) is None
+    p.give(256, 256)
+    p.give(768, 256)
+    # two free regions of 256, not adjacent: 512 does not fit
+    assert p.try_take(512) is None
+    p.give(512, 256)                    # merges 256..1024 into one region
+    assert p.try_take(768) == 256
+    assert p.used == 1024 and p.peak == 1024
 
 
 def test_admission_waits_for_memory_and_is_fifo():
     clock = FakeClock()
-    ex = FakeExecutor(clock, lanes=4, service=1.0, sizes={s: 300 for s in range(10)})
-    srv = Server(ex, pool_bytes=1000, clock=clock)
+    ex = FakeExecutor(clock, lanes=4, service=1.0, sizes={s: 256 for s in range(10)})
+    srv = Server(ex, pool_bytes=3 * 256 + 100, clock=clock)
     done = _run(srv, clock, [(0.0, s) for s in range(6)])
     assert len(done) == 6 and all(r.error is None for r in done)
-    assert srv.pool.peak <= 1000
+    assert srv.pool.peak <= 3 * 256
     assert srv.pool.used == 0
     # only three requests fit at once: the later ones were admitted after a completion
     adm = sorted(done, key=lambda r: r.rid)
@@ -89,6 +104,29 @@ def test_admission_waits_for_memory_and_is_fifo():
     assert min(r.admitted for r in adm[3:]) >= 1.0
     # admission order follows arrival order
     assert [r.rid for r in sorted(done, key=lambda r: (r.admitted, r.rid))] == [1, 2, 3, 4, 5, 6]
+
+
+def test_a_request_waiting_for_its_stream_holds_no_memory():
+    """Stream 0 sends three requests at once; stream 1's request, arriving
+    after them, is admitted beside stream 0's first one instead of queueing
+    behind requests that could not run anyway."""
+    clock = FakeClock()
+    ex = FakeExecutor(clock, lanes=2, service=1.0, sizes={0: 256, 1: 256})
+    srv = Server(ex, pool_bytes=2 * 256, clock=clock)
+    done = _run(srv, clock, [(0.0, 0), (0.0, 0), (0.0, 0), (0.1, 1)])
+    by_rid = {r.rid: r for r in done}
+    assert by_rid[4].stream == 1 and by_rid[4].admitted < 0.5
+    assert by_rid[2].admitted >= 1.0 and by_rid[3].admitted >= 2.0
+    assert srv.pool.peak <= 2 * 256
+
+
+def test_requests_larger_than_the_pool_are_refused_at_submission():
+    clock = FakeClock()
+    ex = FakeExecutor(clock, sizes={0: 2048})
+    srv = Server(ex, pool_bytes=1024, clock=clock)
+    with pytest.raises(ValueError):
+        srv.submit(Request(stream=0, arrival=0.0, frame_index=0))
+    assert srv.idle()
 
 
 def test_continuous_batching_uses_free_lanes_without_waiting_for_the_batch():
