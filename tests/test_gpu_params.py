@@ -56,7 +56,7 @@ def test_huber_threshold_and_init_radius(ctx):
     d, dev = _run(ctx, kf, sg.params(iters=10, huber_k=0.01, beta_r=8.0))
     res = check_parity(d, dev, kf.init_id, kf.init_n, kf.is_new,
                        oracle.OracleParams(iters=10, huber_k=0.01, beta_r=8.0), label="huber beta")
-    assert_parity(res, label="huber beta", max_unstable=0.25)
+    assert_parity(res, label="huber beta", max_unstable=0.17)          # measured 0.144
 
 
 def test_double_precision_solve_for_every_surfel(ctx):
@@ -68,7 +68,7 @@ def test_double_precision_solve_for_every_surfel(ctx):
     assert np.all(dev["flags"][solved] & oracle.FP64_SOLVE)
     res = check_parity(d, dev, kf.init_id, kf.init_n, kf.is_new, oracle.OracleParams(iters=10),
                        label="fp64 everywhere")
-    assert_parity(res, label="fp64 everywhere", max_unstable=0.25)
+    assert_parity(res, label="fp64 everywhere", max_unstable=0.19)     # measured 0.168
 
 
 def test_damped_depth_only(ctx):
@@ -80,7 +80,7 @@ def test_damped_depth_only(ctx):
     res = check_parity(d, dev, kf.init_id, kf.init_n, None,
                        oracle.OracleParams(iters=10, depth_only=True, lm_lambda=1e-2),
                        label="LM depth-only")
-    assert_parity(res, label="LM depth-only", max_unstable=0.25)
+    assert_parity(res, label="LM depth-only", max_unstable=0.03)       # measured 0.009
 
 
 def test_u8_with_another_scale(ctx):
@@ -96,7 +96,7 @@ def test_u8_with_another_scale(ctx):
                        oracle.OracleParams(iters=10, huber_k=4.5 / 255.0), label="u8 1/200")
     # half the contrast doubles the relative weight of the noise, so more
     # surfels sit near the edge of what float resolution determines
-    assert_parity(res, label="u8 1/200", min_stable=0.998, max_unstable=0.25)
+    assert_parity(res, label="u8 1/200", min_stable=0.998, max_unstable=0.15)  # measured 0.128
 
 
 def test_surfel_index_map_matches_oracle(ctx):
@@ -123,4 +123,4 @@ def test_single_surfel_keyframes(ctx, W, H, S, N):
     assert dev["inv_depth"].size == (W // S) * (H // S) == 1
     res = check_parity(d, dev, kf.init_id, kf.init_n, None, oracle.OracleParams(iters=5),
                        label=f"single {W}x{H}")
-    assert_parity(res, label=f"single {W}x{H}", max_unstable=1.0)
+    assert_parity(res, label=f"single {W}x{H}", max_unstable=0.0)      # measured 0

@@ -106,7 +106,7 @@ def test_eight_surfel_groups_batch_equals_plain_and_ragged(ctx):
     torch.cuda.synchronize()
     res = check_parity(d, d.state.to_host(), kf.init_id, kf.init_n, None, oracle.OracleParams(iters=8),
                        label="ragged 102x66 tiles 4x2")
-    assert_parity(res, label="ragged 102x66 tiles 4x2", max_unstable=0.15)
+    assert_parity(res, label="ragged 102x66 tiles 4x2", max_unstable=0.14)  # measured 0.115
 
 
 def test_autotune_picks_a_4x4_plan_and_restores_the_state(ctx):
@@ -169,7 +169,9 @@ def test_ragged_sizes_and_neighbour_counts(ctx, W, H, S, N):
                        label=f"ragged {W}x{H} S{S} N{N}")
     # with one or two neighbour frames a 4x4 surfel has 16-32 samples for
     # three parameters: many are not determined at float resolution
-    assert_parity(res, label=f"ragged {W}x{H} S{S} N{N}", max_unstable=0.15 if N >= 3 else 0.35)
+    # (probe-unstable measured: 0.031, 0.115, 0.281, 0.039)
+    cap = {(100, 70): 0.06, (102, 66): 0.14, (64, 48): 0.31, (96, 64): 0.06}[(W, H)]
+    assert_parity(res, label=f"ragged {W}x{H} S{S} N{N}", max_unstable=cap)
     # pixels outside the grid are never rendered
     dm = d.inv_depth_out.cpu().numpy()
     assert np.all(dm[(H // S) * S:, :] == 0) and np.all(dm[:, (W // S) * S:] == 0)
@@ -225,7 +227,7 @@ def test_nan_pixels_fail_the_step_and_never_reach_the_state(ctx):
     assert np.all(np.isfinite(d.inv_depth_out.cpu().numpy()))
     res = check_parity(d, dev, kf.init_id, kf.init_n, None, oracle.OracleParams(iters=8),
                        label="NaN pixels")
-    assert_parity(res, label="NaN pixels", max_unstable=0.25)
+    assert_parity(res, label="NaN pixels", max_unstable=0.11)  # measured 0.081
 
 
 def test_zero_iterations_leave_the_state(ctx):
@@ -324,7 +326,7 @@ def test_depth_only_ablation_matches_oracle(ctx):
     assert np.array_equal(dev["n"], kf.init_n.reshape(-1, 3))
     res = check_parity(d, dev, kf.init_id, kf.init_n, None,
                        oracle.OracleParams(iters=10, depth_only=True), label="depth-only")
-    assert_parity(res, label="depth-only")
+    assert_parity(res, label="depth-only", max_unstable=0.03)  # measured 0.003
 
 
 def test_quantize_matches_rounding_rules(ctx):
@@ -383,30 +385,37 @@ def test_exact_construction_converges_to_ground_truth(ctx):
     assert rel.max() < 1e-5 and ang.max() < 5e-3
 
 
-def test_full_benchmark_batch_sampled_parity(ctx):
-    """The 64-keyframe f16 batch in the launch configuration bench.py times,
-    checked against the oracle on sampled surfels of several keyframes."""
+# the probe's unstable fraction on the keyframes of the 64-keyframe batch
+BATCH_MAX_UNSTABLE = 0.18
+
+
+def test_full_benchmark_batch_dense_parity(ctx):
+    """The 64-keyframe f16 batch in the launch configuration bench.py times
+    (one persistent launch of the default plan), checked against the oracle
+    on every surfel of 16 of its keyframes (every fourth: all three
+    resolutions, 4-12 neighbour frames)."""
     sg, engine = sgmod()
     kfs = [make_keyframe(spec_for_config(2, i), device="cuda") for i in range(64)]
     ds = [engine.DeviceKeyframe.from_scene(ctx, k, storage="f16") for k in kfs]
-    print("case full batch 64 keyframes f16 default plan", flush=True)
+    print("case full batch 64 keyframes f16 default plan, dense parity on 16 keyframes", flush=True)
     engine.update_batch(ctx, ds, sg.params(iters=15))
     torch.cuda.synchronize()
-    rng = np.random.default_rng(99)
-    tot_within, tot_stable = 0, 0
-    for j in (0, 9, 21, 33, 47, 63):
+    n_all = n_within = n_stable = n_stable_within = n_fp64 = 0
+    for j in range(0, 64, 4):
         d, k = ds[j], kfs[j]
-        sub = np.sort(rng.choice(d.n_surfels, size=min(250, d.n_surfels), replace=False))
+        dev = d.state.to_host()
         label = f"batch kf{j} {d.width}x{d.height} N={d.n_nbr}"
-        res = check_parity(d, d.state.to_host(), k.init_id, k.init_n, k.is_new,
-                           oracle.OracleParams(iters=15), subset=sub, label=label)
-        c, uns, ratios = res
-        tot_within += int(c["within"][~uns].sum())
-        tot_stable += int((~uns).sum())
-        # per keyframe: the unstable fraction and cost checks (the within
-        # fraction is judged over all sampled stable surfels together)
-        assert_parity(res, label=label, min_stable=0.98, max_unstable=0.2)
-    assert tot_within / tot_stable >= 0.998
+        res = check_parity(d, dev, k.init_id, k.init_n, k.is_new, oracle.OracleParams(iters=15), label=label)
+        c, uns, _ = res
+        n_all += uns.size
+        n_within += int(c["within"].sum())
+        n_stable += int((~uns).sum())
+        n_stable_within += int(c["within"][~uns].sum())
+        n_fp64 += int(((dev["flags"] & sg.FLAG_FP64_SOLVE) != 0).sum())
+        assert_parity(res, label=label, max_unstable=BATCH_MAX_UNSTABLE)
+    print(f"dense batch parity: {n_all} surfels of 16 keyframes, within tolerance {n_within / n_all:.5f} "
+          f"(all), {n_stable_within / max(1, n_stable):.5f} (stable, {n_stable}); FP64 solves "
+          f"{n_fp64 / n_all:.5f}", flush=True)
 
 
 def test_levenberg_marquardt_matches_oracle(ctx):
@@ -419,7 +428,8 @@ def test_levenberg_marquardt_matches_oracle(ctx):
     dev = d.state.to_host()
     res = check_parity(d, dev, kf.init_id, kf.init_n, kf.is_new,
                        oracle.OracleParams(iters=10, lm_lambda=1e-2), label="LM")
-    assert_parity(res, label="LM")
+    # most of the damped variant's acceptance tests end in near-ties
+    assert_parity(res, label="LM", max_unstable=0.25, max_reclassified=0.10)  # measured 0.226
 
 
 def test_batch_render_with_odd_sizes_matches_plain(ctx):

@@ -199,7 +199,7 @@ def test_keyframe_switch_chain_matches_oracle(ctx):
     # the device's own chain from its own A is checked exactly by the parity bar
     res = check_parity(dB, devB, hB["inv_depth"], hB["n"], is_new.cpu().numpy(), op,
                        label="keyframe B from device A")
-    assert_parity(res, label="keyframe B from device A", max_unstable=0.2)
+    assert_parity(res, label="keyframe B from device A", max_unstable=0.10)  # measured 0.079
 
 
 def test_regrid_batch_equals_one_by_one(ctx):

@@ -208,5 +208,6 @@ def test_served_responses_match_the_oracle_across_requests():
     ctx.close()
 
 
-# the probe's unstable fraction on the three streams
-SERVE_MAX_UNSTABLE = (0.20, 0.20, 0.20)
+# the probe's unstable fraction on the three streams (measured over the three
+# requests: 0.072-0.145, 0.046-0.113, 0.034-0.104)
+SERVE_MAX_UNSTABLE = (0.17, 0.14, 0.13)
