@@ -120,6 +120,7 @@ typedef struct {
 #define SGN_MAX_NBR 16
 #define SGN_MAX_BATCH 1024          /* keyframes (or keyframe pairs) per call */
 #define SGN_MAX_BATCH_FRAMES 8192   /* neighbour frames per call, all keyframes together */
+#define SGN_STATIC_SCRATCH_BYTES (4u << 20)  /* static device scratch of sgn_transfer_surfels_static */
 
 /* Surfel state, structure of arrays of length gw * gh (device pointers).
  * inv_depth, nx, ny, nz, flags are read and written; cost, nvalid and
@@ -284,6 +285,25 @@ sgn_status sgn_transfer_surfels(sgn_ctx* ctx, const sgn_grid* src_grid, const sg
  * destination tile, 12 bytes per tile plus alignment.  0 when n is outside
  * [1, SGN_MAX_BATCH], dst_grids is null or a grid is invalid. */
 size_t sgn_transfer_workspace_bytes(int32_t n, const sgn_grid* dst_grids);
+
+/* sgn_transfer_surfels without a workspace argument, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same operation, the same results bitwise.  The
+ * re-gridding scratch (a landing key and a winner index per destination
+ * tile) is a static device array of SGN_STATIC_SCRATCH_BYTES that every GPU
+ * the library runs on holds until the process ends; its address on the
+ * context's device is looked up once, by sgn_create.  The call allocates no
+ * memory, device or host, and clears the part of the scratch it uses on the
+ * device before use (a kernel, not a memset).  All calls on one GPU share
+ * that GPU's array and it keeps the last call's contents: calls that
+ * overlap on one GPU (several streams, contexts or threads) race, and the
+ * caller must order them.  Errors: as sgn_transfer_surfels (nothing
+ * enqueued); SGN_E_INVALID when the destination grid needs more scratch
+ * than SGN_STATIC_SCRATCH_BYTES (12 bytes per destination tile plus
+ * alignment: about 349,000 tiles). */
+sgn_status sgn_transfer_surfels_static(sgn_ctx* ctx, const sgn_grid* src_grid, const sgn_surfels* src,
+                                       const sgn_pose* pose, const sgn_grid* dst_grid, sgn_surfels* dst,
+                                       uint8_t* dst_is_new, int32_t* dst_src_index);
 
 /* sgn_transfer_surfels for n keyframe pairs at once (Eq. 10, Surfel
  * reference frame change): four launches for the whole batch, the same

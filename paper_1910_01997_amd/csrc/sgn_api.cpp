@@ -68,6 +68,8 @@ struct sgn_ctx {
     int ring_next = 0;
     void* dev_table = nullptr;
     uint32_t* counters = nullptr;
+    // this device's copy of the static scratch (sgn_transfer_surfels_static)
+    void* static_scratch = nullptr;
     // timing of the last GN kernel
     // timing of the GN kernels: a ring of event pairs, the last kTimingRing
     // launches; gn_start/gn_end point at the latest pair
@@ -571,6 +573,22 @@ sgn_status upload_table(sgn_ctx* c, const std::vector<T>& tab) {
     return SGN_OK;
 }
 
+// upload_table for a caller's array (no container, no allocation)
+template <typename T>
+sgn_status upload_array(sgn_ctx* c, const T* tab, int n) {
+    const size_t bytes = sizeof(T) * (size_t)n;
+    sgn_status st = check_table(c, bytes);
+    if (st) return st;
+    const int slot = c->ring_next;
+    c->ring_next = (c->ring_next + 1) % kRingSlots;
+    if (c->ring_used[slot]) SGN_HIP(hipEventSynchronize(c->ring_ev[slot]));
+    std::memcpy(c->host_ring[slot], tab, bytes);
+    SGN_HIP(hipMemcpyAsync(c->dev_table, c->host_ring[slot], bytes, hipMemcpyHostToDevice, c->stream));
+    SGN_HIP(hipEventRecord(c->ring_ev[slot], c->stream));
+    c->ring_used[slot] = true;
+    return SGN_OK;
+}
+
 sgn_status check_disc_item(const sgn_disc_item* it, bool need_nbr) {
     if (!it) return fail(SGN_E_INVALID, "null disc item");
     sgn_status st = check_keyframe(&it->kf, need_nbr, true);
@@ -761,6 +779,8 @@ sgn_status sgn_create(sgn_ctx** out, int32_t device, void* hip_stream) {
     c->cus = p.multiProcessorCount;
     if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0)
         return give_up(SGN_E_UNSUPPORTED, std::string("built for gfx950, device is ") + p.gcnArchName);
+    if (static_scratch_on(device, &c->static_scratch) != hipSuccess)
+        return give_up(SGN_E_DEVICE, "static scratch lookup failed");
     for (int i = 0; i < kRingSlots; ++i)
         if (hipEventCreateWithFlags(&c->ring_ev[i], hipEventDisableTiming) != hipSuccess)
             return give_up(SGN_E_DEVICE, "event creation failed");
@@ -906,15 +926,15 @@ size_t sgn_transfer_workspace_bytes(int32_t n, const sgn_grid* dst_grids) {
     return transfer_ws(total_dst).total;
 }
 
-sgn_status sgn_transfer_surfels_batch(sgn_ctx* c, int32_t n, const sgn_grid* src_grids,
-                                      const sgn_surfels* srcs, const sgn_pose* poses,
-                                      const sgn_grid* dst_grids, const sgn_surfels* dsts,
-                                      uint8_t* const* dst_is_new, int32_t* const* dst_src_index,
-                                      void* ws, size_t ws_bytes) {
+// Re-gridding of n keyframe pairs with the caller's descriptor array tab[n]
+// and scratch ws (allocates nothing).
+static sgn_status transfer_impl(sgn_ctx* c, int32_t n, const sgn_grid* src_grids, const sgn_surfels* srcs,
+                                const sgn_pose* poses, const sgn_grid* dst_grids, const sgn_surfels* dsts,
+                                uint8_t* const* dst_is_new, int32_t* const* dst_src_index, void* ws,
+                                size_t ws_bytes, RegridArgs* tab, bool static_ws) {
     if (n < 1 || !src_grids || !srcs || !poses || !dst_grids || !dsts || !dst_is_new)
         return fail(SGN_E_INVALID, "empty batch or null argument");
     if (n > SGN_MAX_BATCH) return fail(SGN_E_UNSUPPORTED, "more keyframe pairs than SGN_MAX_BATCH");
-    std::vector<RegridArgs> tab(n);
     int64_t total_src = 0, total_dst = 0;
     for (int k = 0; k < n; ++k) {
         const sgn_grid* src_grid = &src_grids[k];
@@ -962,6 +982,8 @@ sgn_status sgn_transfer_surfels_batch(sgn_ctx* c, int32_t n, const sgn_grid* src
             return fail(SGN_E_UNSUPPORTED, "too many surfels in one batch");
     }
     const TransferWs w = transfer_ws(total_dst);
+    if (static_ws && w.total > ws_bytes)
+        return fail(SGN_E_INVALID, "destination grid needs more than SGN_STATIC_SCRATCH_BYTES of scratch");
     sgn_status st = check_ws(ws, ws_bytes, w.total);
     if (st) return st;
     if (!c) return fail(SGN_E_INVALID, "null context");
@@ -972,11 +994,36 @@ sgn_status sgn_transfer_surfels_batch(sgn_ctx* c, int32_t n, const sgn_grid* src
         tab[k].best = best + tab[k].dst_base;
         tab[k].win = win + tab[k].dst_base;
     }
-    st = upload_table(c, tab);
+    st = upload_array(c, tab, n);
     if (st) return st;
     hipError_t e = launch_regrid((const RegridArgs*)c->dev_table, n, (int)total_src, (int)total_dst, c->stream);
     if (e != hipSuccess) return hip_fail(e, "re-gridding launch");
     return SGN_OK;
+}
+
+sgn_status sgn_transfer_surfels_batch(sgn_ctx* c, int32_t n, const sgn_grid* src_grids,
+                                      const sgn_surfels* srcs, const sgn_pose* poses,
+                                      const sgn_grid* dst_grids, const sgn_surfels* dsts,
+                                      uint8_t* const* dst_is_new, int32_t* const* dst_src_index,
+                                      void* ws, size_t ws_bytes) {
+    if (n < 1 || n > SGN_MAX_BATCH)
+        return n < 1 ? fail(SGN_E_INVALID, "empty batch or null argument")
+                     : fail(SGN_E_UNSUPPORTED, "more keyframe pairs than SGN_MAX_BATCH");
+    std::vector<RegridArgs> tab(n);
+    return transfer_impl(c, n, src_grids, srcs, poses, dst_grids, dsts, dst_is_new, dst_src_index, ws,
+                         ws_bytes, tab.data(), false);
+}
+
+sgn_status sgn_transfer_surfels_static(sgn_ctx* c, const sgn_grid* src_grid, const sgn_surfels* src,
+                                       const sgn_pose* pose, const sgn_grid* dst_grid, sgn_surfels* dst,
+                                       uint8_t* dst_is_new, int32_t* dst_src_index) {
+    if (!src_grid || !src || !pose || !dst_grid || !dst || !dst_is_new)
+        return fail(SGN_E_INVALID, "null argument");
+    if (!c) return fail(SGN_E_INVALID, "null context");
+    if (!c->static_scratch) return fail(SGN_E_DEVICE, "no static scratch on this device");
+    RegridArgs tab[1];
+    return transfer_impl(c, 1, src_grid, src, pose, dst_grid, dst, &dst_is_new, &dst_src_index,
+                         c->static_scratch, SGN_STATIC_SCRATCH_BYTES, tab, true);
 }
 
 sgn_status sgn_transfer_surfels(sgn_ctx* c, const sgn_grid* src_grid, const sgn_surfels* src,

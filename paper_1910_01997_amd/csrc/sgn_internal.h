@@ -150,6 +150,9 @@ hipError_t launch_render(const BatchHeader* hdr, int grid, hipStream_t s);
 hipError_t launch_gn(const GnVariant& v, const BatchHeader* hdr, uint32_t* counters,
                      int persistent, int grid_blocks, hipStream_t s);
 // Re-gridding of a device table of n_pairs keyframe pairs.
+// Device address of the static scratch array on `device` (which must be the
+// current device), looked up on the first call for that device and kept.
+hipError_t static_scratch_on(int device, void** out);
 hipError_t launch_regrid(const RegridArgs* table, int n_pairs, int total_src, int total_dst,
                          hipStream_t s);
 

@@ -36,9 +36,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "sgn_internal.h"
+#include "surfgn.h"
 
 namespace sgn {
 
@@ -1505,6 +1507,34 @@ __global__ void quantize_kernel(const float* __restrict__ src, int src_pitch, vo
             ((uint8_t*)dst)[(size_t)y * dst_pitch + x] = (uint8_t)c;
         }
     }
+}
+
+// ---------------------------------------------------------- static scratch --
+//
+// Scratch of the allocation-free entry point (sgn_transfer_surfels_static): a
+// file-scope device array, one copy per GPU, held until the process ends.
+// Host code never uses the name `scratch` as an address: static_scratch_on
+// looks up each device's copy once, with that device current, and the
+// callers pass the looked-up pointer to kernels.
+static __device__ __align__(256) unsigned char scratch[SGN_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch_on(int device, void** out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------- launchers --

@@ -40,7 +40,10 @@ EXPORTED = [
     "sgn_recent_kernel_ms", "sgn_disc_transfer", "sgn_disc_render_batch", "sgn_disc_place_batch",
     "sgn_transfer_surfels_batch", "sgn_disc_transfer_batch", "sgn_transfer_workspace_bytes",
     "sgn_disc_render_workspace_bytes", "sgn_disc_place_workspace_bytes", "sgn_autotune_workspace_bytes",
+    "sgn_transfer_surfels_static",
 ]
+
+STATIC_SCRATCH_BYTES = 4 << 20
 
 
 class SurfgnError(RuntimeError):
@@ -156,6 +159,10 @@ def lib():
         L.sgn_transfer_surfels.argtypes = [vp, C.POINTER(sgn_grid), C.POINTER(sgn_surfels),
                                            C.POINTER(sgn_pose), C.POINTER(sgn_grid),
                                            C.POINTER(sgn_surfels), vp, vp, vp, C.c_size_t]
+        L.sgn_transfer_surfels_static.restype = st
+        L.sgn_transfer_surfels_static.argtypes = [vp, C.POINTER(sgn_grid), C.POINTER(sgn_surfels),
+                                                  C.POINTER(sgn_pose), C.POINTER(sgn_grid),
+                                                  C.POINTER(sgn_surfels), vp, vp]
         L.sgn_transfer_surfels_batch.restype = st
         L.sgn_transfer_surfels_batch.argtypes = [vp, C.c_int32, C.POINTER(sgn_grid), C.POINTER(sgn_surfels),
                                                  C.POINTER(sgn_pose), C.POINTER(sgn_grid),
@@ -280,6 +287,17 @@ def sgn_transfer_surfels(ctx, src_grid: sgn_grid, src: sgn_surfels, pose: sgn_po
                                      C.c_void_p(dst_src_index_ptr) if dst_src_index_ptr else None,
                                      C.c_void_p(ws[0]), C.c_size_t(ws[1])),
           "sgn_transfer_surfels")
+
+
+def sgn_transfer_surfels_static(ctx, src_grid: sgn_grid, src: sgn_surfels, pose: sgn_pose,
+                                dst_grid: sgn_grid, dst: sgn_surfels, dst_is_new_ptr: int,
+                                dst_src_index_ptr: Optional[int]):
+    """sgn_transfer_surfels with the library's static scratch (no workspace)."""
+    check(lib().sgn_transfer_surfels_static(C.c_void_p(ctx), C.byref(src_grid), C.byref(src),
+                                            C.byref(pose), C.byref(dst_grid), C.byref(dst),
+                                            C.c_void_p(dst_is_new_ptr),
+                                            C.c_void_p(dst_src_index_ptr) if dst_src_index_ptr else None),
+          "sgn_transfer_surfels_static")
 
 
 def sgn_transfer_workspace_bytes(dst_grids: Sequence[sgn_grid]) -> int:

@@ -63,6 +63,7 @@ def test_null_arguments_are_rejected_synchronously(sg):
     assert L.sgn_optimize_batch(None, None, 0, None, None) == sg.SGN_E_INVALID
     assert L.sgn_init_from_neighbours(None, None, None, None, None) == sg.SGN_E_INVALID
     assert L.sgn_quantize(None, None, 0, None) == sg.SGN_E_INVALID
+    assert L.sgn_transfer_surfels_static(None, None, None, None, None, None, None, None) == sg.SGN_E_INVALID
     ms = C.c_float()
     assert L.sgn_last_kernel_ms(None, C.byref(ms)) == sg.SGN_E_INVALID
     assert L.sgn_create(None, 0, None) == sg.SGN_E_INVALID
