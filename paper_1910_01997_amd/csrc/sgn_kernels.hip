@@ -608,6 +608,89 @@ __device__ __forceinline__ void frame_loop(const float* __restrict__ pc, cptr<Fr
     }
 }
 
+// One sample from its homogeneous warp q = (nxq, nyq, qz) in local
+// coordinates (see the pair words): validity on the integer corner, the
+// bilinear value and exact gradient, residual, Huber IRLS weight and chain
+// factor; accumulates A, B, the valid count and (LAST) the Huber cost.
+template <typename T, bool LAST>
+__device__ __forceinline__ void sample_at(float nxq, float nyq, float qz, const float4& c0, const float4& c1,
+                                          const float4& c2, float k2, __amdgpu_buffer_rsrc_t rs, bool pix_ok,
+                                          unsigned pitch_b, unsigned wm1, unsigned hm1, float ikf, float hk,
+                                          float img_scale, float& A, float& B, float& cst, int& nvl) {
+    constexpr bool SCALED = std::is_same<T, uint8_t>::value;
+    const float rq = rcp_fast(qz);
+    const float fx = nxq * rq;                            // x_p - X0
+    const float fy = nyq * rq;                            // y_p - Y0
+    const int flx = cvt_floor(fx), fly = cvt_floor(fy);
+    // unsigned wrap-around: out-of-range (or saturated) corners fail the test
+    const unsigned ix = __float_as_uint(c2.y) + (unsigned)flx;
+    const unsigned iy = __float_as_uint(c2.z) + (unsigned)fly;
+    if (pix_ok & (qz > 0.f) & (ix < wm1) & (iy < hm1)) {
+        const float ax = __builtin_amdgcn_fractf(fx);
+        const float ay = __builtin_amdgcn_fractf(fy);
+        const unsigned o0 = __umul24(iy, pitch_b) + ix * (unsigned)sizeof(T);
+        const Lerp l = lerp_rows<T>(rs, o0, pitch_b, ax);
+        // bilinear value and the exact gradient of the interpolant
+        const float gy = l.bot - l.top;
+        const float val = fmaf(ay, gy, l.top);
+        const float gx = fmaf(ay, l.d1 - l.d0, l.d0);
+        // residual (Eq. 5) and Huber IRLS weight w = min(1, k/|r|) (Eq. 8)
+        const float r = SCALED ? fmaf(val, img_scale, -ikf) : val - ikf;
+        const float ar = fabsf(r);
+        // (the clamp to [0, 1] folds into the multiply; it maps a NaN weight
+        // to 0 where min(1, NaN) gives 1, which changes nothing the update
+        // reports: B = sum w a r is NaN either way)
+        const float wt = fminf(fmaxf(hk * rcp_fast(ar), 0.f), 1.f);
+        // dr/did_u = grad I . dpi/dq . K t  (Eq. 8 with dq/did_u = K t):
+        // (k0 - x_p k2) = kx - (x_p - X0) k2, likewise for y
+        const float tx_ = fmaf(-fx, k2, c0.z);
+        const float ty_ = fmaf(-fy, k2, c1.z);
+        const float a = fmaf(gx, tx_, gy * ty_) * (SCALED ? rq * img_scale : rq);
+        const float wa = wt * a;
+        A = fmaf(wa, a, A);
+        B = fmaf(wa, r, B);
+        ++nvl;
+        if constexpr (LAST) cst += (ar <= hk) ? 0.5f * r * r : hk * (ar - 0.5f * hk);
+    }
+}
+
+// The frame loop for the NP pixels of one lane at once: for each neighbour
+// frame the frame's constants are read once, the first pixel's warp is
+// formed from its offset (dx, dy) from the anchor block centre and the
+// others' incrementally (pixel j lies dyr rows below pixel j-1 of the same
+// surfel, so its q adds dyr times the homography's y column and K t times
+// the change of id_u, didu[j]).  Accumulates per pixel as frame_loop does.
+template <typename T, bool LAST, int NP>
+__device__ __forceinline__ void frame_loop_px(const float* __restrict__ pc, cptr<FrameDev> fr, int nf,
+                                              float dx, float dy, float dyr, const float (&idu)[NP],
+                                              const float (&didu)[NP], const bool (&pix_ok)[NP],
+                                              unsigned pitch_b, unsigned img_bytes, unsigned wm1,
+                                              unsigned hm1, const float (&ikf)[NP], float hk, float img_scale,
+                                              float (&A)[NP], float (&B)[NP], float (&cst)[NP],
+                                              int (&nvl)[NP]) {
+    for (int f = 0; f < nf; ++f) {
+        const float4 c0 = *(const float4*)(pc + f * kPairWords);
+        const float4 c1 = *(const float4*)(pc + f * kPairWords + 4);
+        const float4 c2 = *(const float4*)(pc + f * kPairWords + 8);
+        const float h6 = fr[f].zrow[0], h7 = fr[f].zrow[1], k2 = fr[f].zrow[2];
+        const __amdgpu_buffer_rsrc_t rs = image_rsrc(fr[f].img, img_bytes);
+        // Eq. 6 in local coordinates
+        float nxq = fmaf(c0.x, dx, fmaf(c0.y, dy, fmaf(c0.z, idu[0], c0.w)));
+        float nyq = fmaf(c1.x, dx, fmaf(c1.y, dy, fmaf(c1.z, idu[0], c1.w)));
+        float qz = fmaf(h6, dx, fmaf(h7, dy, fmaf(k2, idu[0], c2.x)));
+        sample_at<T, LAST>(nxq, nyq, qz, c0, c1, c2, k2, rs, pix_ok[0], pitch_b, wm1, hm1, ikf[0], hk,
+                           img_scale, A[0], B[0], cst[0], nvl[0]);
+#pragma unroll
+        for (int j = 1; j < NP; ++j) {
+            nxq = fmaf(c0.z, didu[j], fmaf(c0.y, dyr, nxq));
+            nyq = fmaf(c1.z, didu[j], fmaf(c1.y, dyr, nyq));
+            qz = fmaf(k2, didu[j], fmaf(h7, dyr, qz));
+            sample_at<T, LAST>(nxq, nyq, qz, c0, c1, c2, k2, rs, pix_ok[j], pitch_b, wm1, hm1, ikf[j], hk,
+                               img_scale, A[j], B[j], cst[j], nvl[j]);
+        }
+    }
+}
+
 // Huber cost (Eq. 5) and valid-sample count of one pixel at a candidate
 // state, over all neighbour frames (no Jacobian): the Levenberg-Marquardt
 // acceptance test.
@@ -821,7 +904,9 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
     constexpr int LANES = kWaveSize / SLOTS;                  // lanes per surfel
     constexpr int PPL = PIX / LANES;                          // pixels per lane
     constexpr int NS = K * SLOTS;                             // surfels per work item
+    constexpr float DYR = (float)(LANES / S);                 // rows between a lane's pixels
     static_assert(PPL * LANES == PIX, "a group fills the wavefront");
+    static_assert(PPL == 1 || LANES % S == 0, "a lane's pixels share a column");
     static_assert(NS <= kMaxItemSurfels && K <= LANES, "surfels per item");
     static_assert(G.ix <= G.ab && G.iy <= G.ab, "a work item lies in one anchor block");
     const cptr<BatchHeader> hdr = (cptr<BatchHeader>)hdr_;
@@ -976,24 +1061,51 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
             for (int k = 0; k < K; ++k) {
                 const float* st = lst + (k * SLOTS + r) * ST_WORDS;
                 const float4 sa = *(const float4*)(st + 0);      // id, nx, ny, nz
-                const float4 sb = *(const float4*)(st + 4);      // b1, b2x
-                const float4 sc = *(const float4*)(st + 8);      // b2y, b2z, 1/c, rsx
-                const float2 sd = *(const float2*)(st + 12);     // rsy, alive
                 const float sid = sa.x, snx = sa.y, sny = sa.z;
-                const float sb1x = sb.x, sb1y = sb.y, sb1z = sb.z;
-                const float sb2x = sb.w, sb2y = sc.x, sb2z = sc.y, inv_c = sc.z, srsx = sc.w;
-                const float srsy = sd.x;
-                const bool salive = sd.y != 0.f;
+                const float inv_c = st[ST_INVC];
+                const bool salive = st[ST_ALIVE] != 0.f;
                 const int tx = it0x + (k % G.gx) * TX + r % TX, ty = it0y + (k / G.gx) * TY + r / TX;
                 // this lane's share of J^T W J = sum_u A_u g g^T and
                 // J^T W r = sum_u B_u g (the frame sum hoisted), its valid
                 // count and cost, over its pixels in order
                 float ph[9], pnv, pcs;
+                // frame-independent per-pixel terms (Eq. 3, Eq. 9)
+                float sig[PPL], idu[PPL], didu[PPL];
+                bool pix_ok[PPL];
 #pragma unroll
                 for (int j = 0; j < PPL; ++j) {
-                    // frame-independent per-pixel terms (Eq. 3, Eq. 9)
-                    const float sigma = (snx * drx[j] + sny * dry[j]) * inv_c;
-                    const float idu = fmaf(sid, sigma, sid);
+                    sig[j] = (snx * drx[j] + sny * dry[j]) * inv_c;
+                    idu[j] = fmaf(sid, sig[j], sid);
+                    didu[j] = j == 0 ? 0.f : idu[j] - idu[j - 1];
+                    pix_ok[j] = salive && (idu[j] > 0.f);
+                }
+                // the first pixel's offset from the anchor block centre; the
+                // lane's later pixels lie DYR rows apart in the same column
+                const float bdx = (float)(S * tx + pxs[0] - bpx) - 0.5f * (float)(G.ab * S - 1);
+                const float bdy = (float)(S * ty + pys[0] - bpy) - 0.5f * (float)(G.ab * S - 1);
+                float A[PPL], B[PPL], cst[PPL];
+                int nvl[PPL];
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) {
+                    A[j] = 0.f; B[j] = 0.f; cst[j] = 0.f; nvl[j] = 0;
+                }
+                if (last || lm)
+                    frame_loop_px<T, true, PPL>(pairs, fr, nf, bdx, bdy, DYR, idu, didu, pix_ok, pitch_b,
+                                                img_bytes, wm1, hm1, ikf[k], hk, img_scale, A, B, cst, nvl);
+                else
+                    frame_loop_px<T, false, PPL>(pairs, fr, nf, bdx, bdy, DYR, idu, didu, pix_ok, pitch_b,
+                                                 img_bytes, wm1, hm1, ikf[k], hk, img_scale, A, B, cst, nvl);
+                // the tangent basis and r_s, read again from LDS after the frame
+                // loop rather than held in registers through it
+                __asm__ volatile("" ::: "memory");
+                const float4 sb = *(const float4*)(st + 4);      // b1, b2x
+                const float4 sc = *(const float4*)(st + 8);      // b2y, b2z, 1/c, rsx
+                const float srsy = st[ST_RSY];
+                const float sb1x = sb.x, sb1y = sb.y, sb1z = sb.z;
+                const float sb2x = sb.w, sb2y = sc.x, sb2z = sc.y, srsx = sc.w;
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) {
+                    const float sigma = sig[j];
                     const float dx3 = fmaf(-sigma, srsx, drx[j]);
                     const float dy3 = fmaf(-sigma, srsy, dry[j]);
                     const float dz3 = -sigma;
@@ -1001,27 +1113,13 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
                     const float g0 = 1.f + sigma;
                     const float g1 = depth_only ? 0.f : kk * (sb1x * dx3 + sb1y * dy3 + sb1z * dz3);
                     const float g2 = depth_only ? 0.f : kk * (sb2x * dx3 + sb2y * dy3 + sb2z * dz3);
-                    const bool pix_ok = salive && (idu > 0.f);
-                    // pixel offset from the anchor block centre
-                    const float bdx = (float)(S * tx + pxs[j] - bpx) - 0.5f * (float)(G.ab * S - 1);
-                    const float bdy = (float)(S * ty + pys[j] - bpy) - 0.5f * (float)(G.ab * S - 1);
-                    float A = 0.f, B = 0.f, cst = 0.f;
-                    int nvl = 0;
-                    if (last || lm)
-                        frame_loop<T, true>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes,
-                                            wm1, hm1, ikf[k][j], hk, img_scale, A, B, cst, nvl);
-                    else
-                        frame_loop<T, false>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes,
-                                             wm1, hm1, ikf[k][j], hk, img_scale, A, B, cst, nvl);
-                    {
-                        const float ag0 = A * g0, ag1 = A * g1, ag2 = A * g2;
-                        const float u[9] = {ag0, ag0, ag0, ag1, ag1, ag2, B, B, B};
-                        const float v[9] = {g0, g1, g2, g1, g2, g2, g0, g1, g2};
+                    const float ag0 = A[j] * g0, ag1 = A[j] * g1, ag2 = A[j] * g2;
+                    const float u[9] = {ag0, ag0, ag0, ag1, ag1, ag2, B[j], B[j], B[j]};
+                    const float v[9] = {g0, g1, g2, g1, g2, g2, g0, g1, g2};
 #pragma unroll
-                        for (int e = 0; e < 9; ++e) ph[e] = (j == 0) ? u[e] * v[e] : fmaf(u[e], v[e], ph[e]);
-                        pnv = (j == 0) ? (float)nvl : pnv + (float)nvl;
-                        pcs = (j == 0) ? cst : pcs + cst;
-                    }
+                    for (int e = 0; e < 9; ++e) ph[e] = (j == 0) ? u[e] * v[e] : fmaf(u[e], v[e], ph[e]);
+                    pnv = (j == 0) ? (float)nvl[j] : pnv + (float)nvl[j];
+                    pcs = (j == 0) ? cst[j] : pcs + cst[j];
                 }
                 // reduced two at a time: lane 0 of the surfel ends with words
                 // 0, 2, 4, 6, 8 and lane 1 with words 1, 3, 5, 7, 9 (the valid
