@@ -616,7 +616,8 @@ template <typename T, bool LAST>
 __device__ __forceinline__ void sample_at(float nxq, float nyq, float qz, const float4& c0, const float4& c1,
                                           const float4& c2, float k2, __amdgpu_buffer_rsrc_t rs, bool pix_ok,
                                           unsigned pitch_b, unsigned wm1, unsigned hm1, float ikf, float hk,
-                                          float img_scale, float& A, float& B, float& cst, int& nvl) {
+                                          float img_scale, float& A, float& B, float& cst, unsigned& nvl,
+                                          unsigned one = 1u) {
     constexpr bool SCALED = std::is_same<T, uint8_t>::value;
     const float rq = rcp_fast(qz);
     const float fx = nxq * rq;                            // x_p - X0
@@ -649,7 +650,7 @@ __device__ __forceinline__ void sample_at(float nxq, float nyq, float qz, const 
         const float wa = wt * a;
         A = fmaf(wa, a, A);
         B = fmaf(wa, r, B);
-        ++nvl;
+        nvl += one;
         if constexpr (LAST) cst += (ar <= hk) ? 0.5f * r * r : hk * (ar - 0.5f * hk);
     }
 }
@@ -659,7 +660,9 @@ __device__ __forceinline__ void sample_at(float nxq, float nyq, float qz, const 
 // formed from its offset (dx, dy) from the anchor block centre and the
 // others' incrementally (pixel j lies dyr rows below pixel j-1 of the same
 // surfel, so its q adds dyr times the homography's y column and K t times
-// the change of id_u, didu[j]).  Accumulates per pixel as frame_loop does.
+// the change of id_u, didu[j]).  Accumulates A, B and the cost per pixel as
+// frame_loop does; the valid counts of the pixels are packed one per byte of
+// nvp (pixel j in byte j; at most 16 frames each).
 template <typename T, bool LAST, int NP>
 __device__ __forceinline__ void frame_loop_px(const float* __restrict__ pc, cptr<FrameDev> fr, int nf,
                                               float dx, float dy, float dyr, const float (&idu)[NP],
@@ -667,7 +670,8 @@ __device__ __forceinline__ void frame_loop_px(const float* __restrict__ pc, cptr
                                               unsigned pitch_b, unsigned img_bytes, unsigned wm1,
                                               unsigned hm1, const float (&ikf)[NP], float hk, float img_scale,
                                               float (&A)[NP], float (&B)[NP], float (&cst)[NP],
-                                              int (&nvl)[NP]) {
+                                              unsigned& nvp) {
+    static_assert(NP <= 4, "four byte counters");
     for (int f = 0; f < nf; ++f) {
         const float4 c0 = *(const float4*)(pc + f * kPairWords);
         const float4 c1 = *(const float4*)(pc + f * kPairWords + 4);
@@ -679,14 +683,14 @@ __device__ __forceinline__ void frame_loop_px(const float* __restrict__ pc, cptr
         float nyq = fmaf(c1.x, dx, fmaf(c1.y, dy, fmaf(c1.z, idu[0], c1.w)));
         float qz = fmaf(h6, dx, fmaf(h7, dy, fmaf(k2, idu[0], c2.x)));
         sample_at<T, LAST>(nxq, nyq, qz, c0, c1, c2, k2, rs, pix_ok[0], pitch_b, wm1, hm1, ikf[0], hk,
-                           img_scale, A[0], B[0], cst[0], nvl[0]);
+                           img_scale, A[0], B[0], cst[0], nvp, 1u);
 #pragma unroll
         for (int j = 1; j < NP; ++j) {
             nxq = fmaf(c0.z, didu[j], fmaf(c0.y, dyr, nxq));
             nyq = fmaf(c1.z, didu[j], fmaf(c1.y, dyr, nyq));
             qz = fmaf(k2, didu[j], fmaf(h7, dyr, qz));
             sample_at<T, LAST>(nxq, nyq, qz, c0, c1, c2, k2, rs, pix_ok[j], pitch_b, wm1, hm1, ikf[j], hk,
-                               img_scale, A[j], B[j], cst[j], nvl[j]);
+                               img_scale, A[j], B[j], cst[j], nvp, 1u << (8 * j));
         }
     }
 }
@@ -1084,17 +1088,17 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
                 const float bdx = (float)(S * tx + pxs[0] - bpx) - 0.5f * (float)(G.ab * S - 1);
                 const float bdy = (float)(S * ty + pys[0] - bpy) - 0.5f * (float)(G.ab * S - 1);
                 float A[PPL], B[PPL], cst[PPL];
-                int nvl[PPL];
+                unsigned nvp = 0u;
 #pragma unroll
                 for (int j = 0; j < PPL; ++j) {
-                    A[j] = 0.f; B[j] = 0.f; cst[j] = 0.f; nvl[j] = 0;
+                    A[j] = 0.f; B[j] = 0.f; cst[j] = 0.f;
                 }
                 if (last || lm)
                     frame_loop_px<T, true, PPL>(pairs, fr, nf, bdx, bdy, DYR, idu, didu, pix_ok, pitch_b,
-                                                img_bytes, wm1, hm1, ikf[k], hk, img_scale, A, B, cst, nvl);
+                                                img_bytes, wm1, hm1, ikf[k], hk, img_scale, A, B, cst, nvp);
                 else
                     frame_loop_px<T, false, PPL>(pairs, fr, nf, bdx, bdy, DYR, idu, didu, pix_ok, pitch_b,
-                                                 img_bytes, wm1, hm1, ikf[k], hk, img_scale, A, B, cst, nvl);
+                                                 img_bytes, wm1, hm1, ikf[k], hk, img_scale, A, B, cst, nvp);
                 // the tangent basis and r_s, read again from LDS after the frame
                 // loop rather than held in registers through it
                 __asm__ volatile("" ::: "memory");
@@ -1118,9 +1122,10 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
                     const float v[9] = {g0, g1, g2, g1, g2, g2, g0, g1, g2};
 #pragma unroll
                     for (int e = 0; e < 9; ++e) ph[e] = (j == 0) ? u[e] * v[e] : fmaf(u[e], v[e], ph[e]);
-                    pnv = (j == 0) ? (float)nvl[j] : pnv + (float)nvl[j];
                     pcs = (j == 0) ? cst[j] : pcs + cst[j];
                 }
+                // the lane's valid samples: the byte counters summed (v_sad_u8)
+                pnv = (float)__builtin_amdgcn_sad_u8(nvp, 0u, 0u);
                 // reduced two at a time: lane 0 of the surfel ends with words
                 // 0, 2, 4, 6, 8 and lane 1 with words 1, 3, 5, 7, 9 (the valid
                 // count as an exact float)
