@@ -69,7 +69,8 @@ def parse():
     ap.add_argument("--disc-steps", type=int, default=10)
     ap.add_argument("--no-transfer", action="store_true",
                     help="skip the reference-frame change leg (Eq. 10 with re-gridding)")
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the library's default plan instead of the autotuned one")
     ap.add_argument("--plan", default="",
                     help="GN mapping TXxTY:K (surfels per group, groups per work item), e.g. 2x4:8")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -366,7 +367,9 @@ def main():
         tiles, groups = args.plan.split(":")
         tx, ty = (int(v) for v in tiles.split("x"))
         plan = sg.plan(tx, ty, 1, 0, 0, 1, groups=int(groups))
-    if args.autotune:
+    elif not args.no_autotune:
+        # the mapping the autotuner picks for this batch (every tile layout,
+        # groups per item, persistent grid or not, XCD queues or not)
         items = sg.batch_array([d.item(render=False, init=False) for d in dks])
         plan = engine.autotune(ctx, items, len(dks), prm)
         log("autotuned plan", plan.as_dict())

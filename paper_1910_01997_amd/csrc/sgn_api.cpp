@@ -308,10 +308,11 @@ int default_groups(int patch, int tiles_x, int tiles_y) {
 
 sgn_plan default_plan(int patch) {
     sgn_plan p{};
-    // measured fastest on the 64-keyframe batch: 2x4 groups (eight surfels per
-    // wavefront, two pixels per lane), two per item (a whole anchor block); a
-    // 16 x 16 surfel spans a whole anchor block, so it is one group per item
-    if (patch == 4) { p.tiles_x = 2; p.tiles_y = 4; }
+    // measured fastest on the 64-keyframe batch: 4x4 groups (a whole anchor
+    // block of sixteen surfels per wavefront, four pixels per lane), one per
+    // item; a 16 x 16 surfel spans a whole anchor block, so it is one group
+    // per item
+    if (patch == 4) { p.tiles_x = 4; p.tiles_y = 4; }
     else { p.tiles_x = 1; p.tiles_y = 1; }
     p.groups = default_groups(patch, p.tiles_x, p.tiles_y);
     p.persistent = 1;

@@ -51,9 +51,13 @@ def test_batch_equals_plain_bitwise_and_plans_agree(ctx):
     print("case batch==plain, keyframes 3,4,5 of the batch workload", flush=True)
     prm = sg.params(iters=6)
     layouts = [
-        # two pixels per lane (the default): plain form with the default plan
-        (None, [None, sg.plan(4, 2, 1, 0, 0, 1, groups=2), sg.plan(2, 4, 0, 0, 0, 0, groups=1),
-                sg.plan(2, 4, 1, 0, 0, 0, groups=2)]),
+        # four pixels per lane (the default): plain form with the default plan
+        (None, [None, sg.plan(4, 4, 1, 0, 0, 1, groups=1), sg.plan(4, 4, 0, 0, 0, 0, groups=1),
+                sg.plan(4, 4, 1, 0, 0, 0, groups=1)]),
+        # two pixels per lane
+        (sg.plan(2, 4, 0, 0, 0, 0, groups=1),
+         [sg.plan(4, 2, 1, 0, 0, 1, groups=2), sg.plan(2, 4, 1, 0, 0, 0, groups=2),
+          sg.plan(2, 4, 1, 0, 0, 1, groups=2)]),
         # one pixel per lane
         (sg.plan(2, 2, 0, 0, 0, 0, groups=1),
          [sg.plan(4, 1, 1, 0, 0, 1, groups=1), sg.plan(2, 2, 1, 0, 0, 1, groups=2),
@@ -391,14 +395,17 @@ BATCH_MAX_UNSTABLE = 0.18
 
 def test_full_benchmark_batch_dense_parity(ctx):
     """The 64-keyframe f16 batch in the launch configuration bench.py times
-    (one persistent launch of the default plan), checked against the oracle
-    on every surfel of 16 of its keyframes (every fourth: all three
-    resolutions, 4-12 neighbour frames)."""
+    (one persistent launch of the plan the autotuner picks for the batch),
+    checked against the oracle on every surfel of 16 of its keyframes (every
+    fourth: all three resolutions, 4-12 neighbour frames)."""
     sg, engine = sgmod()
     kfs = [make_keyframe(spec_for_config(2, i), device="cuda") for i in range(64)]
     ds = [engine.DeviceKeyframe.from_scene(ctx, k, storage="f16") for k in kfs]
-    print("case full batch 64 keyframes f16 default plan, dense parity on 16 keyframes", flush=True)
-    engine.update_batch(ctx, ds, sg.params(iters=15))
+    prm = sg.params(iters=15)
+    plan = engine.autotune(ctx, sg.batch_array([d.item(render=False, init=False) for d in ds]), len(ds), prm)
+    print(f"case full batch 64 keyframes f16, autotuned plan {plan.as_dict()}, dense parity on 16 keyframes",
+          flush=True)
+    engine.update_batch(ctx, ds, prm, plan)
     torch.cuda.synchronize()
     n_all = n_within = n_stable = n_stable_within = n_fp64 = 0
     for j in range(0, 64, 4):
@@ -429,7 +436,9 @@ def test_levenberg_marquardt_matches_oracle(ctx):
     res = check_parity(d, dev, kf.init_id, kf.init_n, kf.is_new,
                        oracle.OracleParams(iters=10, lm_lambda=1e-2), label="LM")
     # most of the damped variant's acceptance tests end in near-ties
-    assert_parity(res, label="LM", max_unstable=0.25, max_reclassified=0.10)  # measured 0.226
+    # (measured: probe-unstable 0.226; reclassified 0.086 with two pixels
+    # per lane, 0.110 with four)
+    assert_parity(res, label="LM", max_unstable=0.25, max_reclassified=0.14)
 
 
 def test_batch_render_with_odd_sizes_matches_plain(ctx):
