@@ -241,10 +241,14 @@ sgn_status sgn_optimize_batch(sgn_ctx* ctx, const sgn_batch_item* items, int32_t
                               const sgn_params* params, const sgn_plan* plan /* NULL: default */);
 
 /* Time candidate plans on a sample batch and return the fastest in *out
- * (host).  The surfel state is snapshotted into the workspace before the
- * first trial and restored from it after every trial, so the items' state is
- * unchanged on return.  Synchronous (waits for the trials).  ws: see
- * sgn_autotune_workspace_bytes. */
+ * (host): every tile layout with its group counts, persistent or not, XCD
+ * queues or not; each timed as the fastest of three runs after a warm-up
+ * run.  When the default plan is within 1 % of the fastest it is returned
+ * instead (a tie at the timer's resolution), so a batch gets the same plan
+ * from run to run.  The surfel state is snapshotted into the workspace
+ * before the first trial and restored from it after every trial, so the
+ * items' state is unchanged on return.  Synchronous (waits for the trials).
+ * ws: see sgn_autotune_workspace_bytes. */
 sgn_status sgn_autotune(sgn_ctx* ctx, const sgn_batch_item* sample, int32_t n_items,
                         const sgn_params* params, sgn_plan* out, void* ws, size_t ws_bytes);
 
