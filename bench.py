@@ -551,7 +551,8 @@ def main():
             from paper_1910_01997_amd import build as hb
             rec = json.load(open(prof))
             if rec.get("kernel_source_sha256") == hb.kernel_source_hash() and \
-                    rec.get("storage") == args.storage and rec.get("keyframes") == args.keyframes:
+                    rec.get("storage") == args.storage and rec.get("keyframes") == args.keyframes and \
+                    same_plan(rec.get("plan"), plan):
                 traffic = rec.get("hbm_bytes_per_launch")
         except Exception as e:  # a stale or unreadable summary gives null
             log("traffic summary unusable:", e)
@@ -619,7 +620,7 @@ def main():
                          "frac": hbm_gbs / HBM_PEAK_GBS, "bytes_per_launch": int(hbm_bytes),
                          "definition": "every image once and the surfel state read and written, "
                                        "per iteration"},
-            "valu_issue_view": issue_view(samples, gn_ms),
+            "valu_issue_view": issue_view(samples, gn_ms, plan),
         },
         "cpu_baseline": cpu,
         "plain_form": plain,
@@ -642,7 +643,18 @@ def compulsory_bytes(dks, iters):
     return per_it * iters
 
 
-def issue_view(samples, gn_ms):
+def same_plan(rec_plan, plan):
+    """Whether a profile's plan (dict) is the plan the bench ran (None: the
+    library's default, 4x4 tiles, one group, persistent, XCD queues)."""
+    if not rec_plan:
+        return False
+    run = plan.as_dict() if plan is not None else {"tiles_x": 4, "tiles_y": 4, "groups": 1, "persistent": 1,
+                                                  "xcd_queues": 1}
+    return all(int(rec_plan.get(k, -1)) == int(run.get(k, -2))
+               for k in ("tiles_x", "tiles_y", "groups", "persistent", "xcd_queues"))
+
+
+def issue_view(samples, gn_ms, plan=None):
     """VALU issue slots: the 44 lane operations per sample against the issue
     peak, and beside it what the counters measured for this kernel build (the
     summary under profiles/ is used only when its source hash matches)."""
@@ -655,7 +667,7 @@ def issue_view(samples, gn_ms):
         try:
             from paper_1910_01997_amd import build as hb
             rec = json.load(open(prof))
-            if rec.get("kernel_source_sha256") == hb.kernel_source_hash():
+            if rec.get("kernel_source_sha256") == hb.kernel_source_hash() and same_plan(rec.get("plan"), plan):
                 per = rec["valu_insts_per_wave_sample"]
                 out["measured_valu_insts_per_wave_sample"] = per
                 out["measured_issue_frac"] = rate * per / 1e12 / VALU_PEAK_TOPS
