@@ -1076,9 +1076,13 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
                 // frame-independent per-pixel terms (Eq. 3, Eq. 9)
                 float sig[PPL], idu[PPL], didu[PPL];
                 bool pix_ok[PPL];
+                // sigma_u = n . (r_u - r_s) / (n . r_s); the lane's pixels
+                // share a column, so r_u - r_s differs between them in y only
+                const float cnx = snx * inv_c, cny = sny * inv_c;
+                const float sx0 = cnx * drx[0];
 #pragma unroll
                 for (int j = 0; j < PPL; ++j) {
-                    sig[j] = (snx * drx[j] + sny * dry[j]) * inv_c;
+                    sig[j] = fmaf(cny, dry[j], sx0);
                     idu[j] = fmaf(sid, sig[j], sid);
                     didu[j] = j == 0 ? 0.f : idu[j] - idu[j - 1];
                     pix_ok[j] = salive && (idu[j] > 0.f);
@@ -1107,16 +1111,22 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
                 const float srsy = st[ST_RSY];
                 const float sb1x = sb.x, sb1y = sb.y, sb1z = sb.z;
                 const float sb2x = sb.w, sb2y = sc.x, sb2z = sc.y, srsx = sc.w;
+                // g_u = (1 + sigma_u, kk b1 . d_u, kk b2 . d_u) with
+                // d_u = (r_u - r_s) - sigma_u (r_s, 1) and kk = id_s / (n . r_s):
+                // b . d_u = (b_x drx + b_y dry_u) - sigma_u (b . (r_s, 1)), the
+                // surfel's and the column's parts formed once.  The depth-only
+                // ablation zeroes kk, and with it the normal columns.
+                const float kk = depth_only ? 0.f : sid * inv_c;
+                const float k1x = kk * sb1x, k1y = kk * sb1y, k2x = kk * sb2x, k2y = kk * sb2y;
+                const float q1 = kk * fmaf(sb1x, srsx, fmaf(sb1y, srsy, sb1z));
+                const float q2 = kk * fmaf(sb2x, srsx, fmaf(sb2y, srsy, sb2z));
+                const float c1 = k1x * drx[0], c2 = k2x * drx[0];
 #pragma unroll
                 for (int j = 0; j < PPL; ++j) {
                     const float sigma = sig[j];
-                    const float dx3 = fmaf(-sigma, srsx, drx[j]);
-                    const float dy3 = fmaf(-sigma, srsy, dry[j]);
-                    const float dz3 = -sigma;
-                    const float kk = sid * inv_c;
                     const float g0 = 1.f + sigma;
-                    const float g1 = depth_only ? 0.f : kk * (sb1x * dx3 + sb1y * dy3 + sb1z * dz3);
-                    const float g2 = depth_only ? 0.f : kk * (sb2x * dx3 + sb2y * dy3 + sb2z * dz3);
+                    const float g1 = fmaf(-sigma, q1, fmaf(k1y, dry[j], c1));
+                    const float g2 = fmaf(-sigma, q2, fmaf(k2y, dry[j], c2));
                     const float ag0 = A[j] * g0, ag1 = A[j] * g1, ag2 = A[j] * g2;
                     const float u[9] = {ag0, ag0, ag0, ag1, ag1, ag2, B[j], B[j], B[j]};
                     const float v[9] = {g0, g1, g2, g1, g2, g2, g0, g1, g2};
@@ -1142,12 +1152,18 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
                     s3 = pair_sum<LANES>(ph[6], ph[7], odd);     // b0  | b1
                     s4 = pair_sum<LANES>(ph[8], pnv, odd);       // b2  | nv
                 }
-                float cs = 0.f;
-                if (last || lm) cs = group_sum<LANES>(pcs);
-                if (p < 2) {
-                    float* o = lsm + (k * SLOTS + r) * SM_WORDS + p;
-                    o[0] = s0; o[2] = s1; o[4] = s2; o[6] = s3; o[8] = s4;
-                    if (p == 0) o[SM_COST] = cs;
+                // In a 4-lane surfel lanes 2 and 3 end with the sums of lanes 0
+                // and 1, formed from the same two partial sums (the adds
+                // commute), so they store the same words: no branch, and the
+                // last butterfly add stays a DPP add over the whole wavefront.
+                float* const o = lsm + (k * SLOTS + r) * SM_WORDS;
+                if (LANES == 4 || p < 2) {
+                    const int w = p & 1;
+                    o[w] = s0; o[w + 2] = s1; o[w + 4] = s2; o[w + 6] = s3; o[w + 8] = s4;
+                }
+                if (last || lm) {
+                    const float cs = group_sum<LANES>(pcs);    // 4 lanes: the same in each
+                    if (LANES == 4 || p == 0) o[SM_COST] = cs;
                 }
             }
             wave_sync();
@@ -1289,9 +1305,11 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
                     const int tx = it0x + (k % G.gx) * TX + r % TX, ty = it0y + (k / G.gx) * TY + r / TX;
                     float cst2 = 0.f;
                     int nv2l = 0;
+                    const float cnx = sa.y * inv_c, cny = sa.z * inv_c;
+                    const float sx0 = cnx * drx[0];
 #pragma unroll
                     for (int j = 0; j < PPL; ++j) {
-                        const float sig = (sa.y * drx[j] + sa.z * dry[j]) * inv_c;
+                        const float sig = fmaf(cny, dry[j], sx0);
                         const float idu_c = fmaf(sa.x, sig, sa.x);
                         const float bdx = (float)(S * tx + pxs[j] - bpx) - 0.5f * (float)(G.ab * S - 1);
                         const float bdy = (float)(S * ty + pys[j] - bpy) - 0.5f * (float)(G.ab * S - 1);
