@@ -793,35 +793,37 @@ __device__ __forceinline__ bool owner_step(const float* sm, bool alive, bool las
                 ok = false;
             }
         } else if (ok) {
-            // equilibrate: E = D^-1/2 H D^-1/2 (unit diagonal)
+            // equilibrate: E = D^-1/2 H D^-1/2 (unit diagonal).  The float
+            // solve is formed unconditionally (no branches: the tests below
+            // are combined with |) and replaced by the double-precision one
+            // where a diagonal is not positive and finite or the system is
+            // too ill-conditioned for float.
             const float maxd = fmaxf(H00, fmaxf(H11, H22));
-            bool need64 = !(H00 > 0.f) || !(H11 > 0.f) || !(H22 > 0.f) || !isfinite(maxd);
-            if (!need64) {
-                const float e0 = __frsqrt_rn(H00), e1 = __frsqrt_rn(H11), e2 = __frsqrt_rn(H22);
-                const float e01 = H01 * e0 * e1, e02 = H02 * e0 * e2, e12 = H12 * e1 * e2;
-                // adjugate and determinant of E (diagonal dd = 1 + lambda)
-                const float d2 = dd * dd;
-                const float c00 = fmaf(-e12, e12, d2), c11 = fmaf(-e02, e02, d2);
-                const float c22 = fmaf(-e01, e01, d2);
-                const float c01 = fmaf(e02, e12, -dd * e01), c02 = fmaf(e01, e12, -dd * e02);
-                const float c12 = fmaf(e01, e02, -dd * e12);
-                const float det = fmaf(e01, c01, fmaf(e02, c02, dd * c00));
-                // kappa_F(E)^2 = ||E||_F^2 ||adj E||_F^2 / det^2  (>= kappa_2(E)^2)
-                const float fro2 = 3.f * d2 + 2.f * (e01 * e01 + e02 * e02 + e12 * e12);
-                const float adj2 = c00 * c00 + c11 * c11 + c22 * c22 +
-                                   2.f * (c01 * c01 + c02 * c02 + c12 * c12);
-                // raw Cholesky pivots are H_jj times the equilibrated ones
-                const float p1 = c22 * rcp_fast(dd);   // dd - e01^2 / dd (only compared)
-                const float p2 = det * rcp_fast(c22);  // (only compared)
-                need64 = !(fro2 * adj2 <= kap2 * det * det) || !(det > 0.f) || !(c22 > 0.f) ||
-                         !(H11 * p1 > 1e-10f * maxd * dd) || !(H22 * p2 > 1e-10f * maxd * dd);
-                if (!need64) {
-                    const float bh0 = bb0 * e0, bh1 = bb1 * e1, bh2 = bb2 * e2;
-                    const float idet = rcp_fast(det);
-                    d0s = -(c00 * bh0 + c01 * bh1 + c02 * bh2) * idet * e0;
-                    d1s = -(c01 * bh0 + c11 * bh1 + c12 * bh2) * idet * e1;
-                    d2s = -(c02 * bh0 + c12 * bh1 + c22 * bh2) * idet * e2;
-                }
+            const float e0 = __frsqrt_rn(H00), e1 = __frsqrt_rn(H11), e2 = __frsqrt_rn(H22);
+            const float e01 = H01 * e0 * e1, e02 = H02 * e0 * e2, e12 = H12 * e1 * e2;
+            // adjugate and determinant of E (diagonal dd = 1 + lambda)
+            const float d2 = dd * dd;
+            const float c00 = fmaf(-e12, e12, d2), c11 = fmaf(-e02, e02, d2);
+            const float c22 = fmaf(-e01, e01, d2);
+            const float c01 = fmaf(e02, e12, -dd * e01), c02 = fmaf(e01, e12, -dd * e02);
+            const float c12 = fmaf(e01, e02, -dd * e12);
+            const float det = fmaf(e01, c01, fmaf(e02, c02, dd * c00));
+            // kappa_F(E)^2 = ||E||_F^2 ||adj E||_F^2 / det^2  (>= kappa_2(E)^2)
+            const float fro2 = 3.f * d2 + 2.f * (e01 * e01 + e02 * e02 + e12 * e12);
+            const float adj2 = c00 * c00 + c11 * c11 + c22 * c22 +
+                               2.f * (c01 * c01 + c02 * c02 + c12 * c12);
+            // raw Cholesky pivots are H_jj times the equilibrated ones
+            const float p1 = c22 * rcp_fast(dd);   // dd - e01^2 / dd (only compared)
+            const float p2 = det * rcp_fast(c22);  // (only compared)
+            const bool need64 = !(H00 > 0.f) | !(H11 > 0.f) | !(H22 > 0.f) | !isfinite(maxd) |
+                                !(fro2 * adj2 <= kap2 * det * det) | !(det > 0.f) | !(c22 > 0.f) |
+                                !(H11 * p1 > 1e-10f * maxd * dd) | !(H22 * p2 > 1e-10f * maxd * dd);
+            {
+                const float bh0 = bb0 * e0, bh1 = bb1 * e1, bh2 = bb2 * e2;
+                const float idet = rcp_fast(det);
+                d0s = -(c00 * bh0 + c01 * bh1 + c02 * bh2) * idet * e0;
+                d1s = -(c01 * bh0 + c11 * bh1 + c12 * bh2) * idet * e1;
+                d2s = -(c02 * bh0 + c12 * bh1 + c22 * bh2) * idet * e2;
             }
             if (need64) {
                 flags |= F_FP64_SOLVE;
@@ -1041,6 +1043,9 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
 
         for (int it = 0; it < iters; ++it) {
             const bool last = (it == iters - 1);
+            // the cost is summed on the last iteration and for the damped
+            // variant: a wave-uniform flag, kept in a scalar register
+            const bool with_cost = __builtin_amdgcn_readfirstlane((int)(last || lm)) != 0;
             // ---- owners: degeneracy, tangent basis, broadcast of the state
             if (owner) {
                 const float c = nx * rsx + ny * rsy + nz;     // n . r_s
@@ -1097,7 +1102,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
                 for (int j = 0; j < PPL; ++j) {
                     A[j] = 0.f; B[j] = 0.f; cst[j] = 0.f;
                 }
-                if (last || lm)
+                if (with_cost)
                     frame_loop_px<T, true, PPL>(pairs, fr, nf, bdx, bdy, DYR, idu, didu, pix_ok, pitch_b,
                                                 img_bytes, wm1, hm1, ikf[k], hk, img_scale, A, B, cst, nvp);
                 else
@@ -1161,7 +1166,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
                     const int w = p & 1;
                     o[w] = s0; o[w + 2] = s1; o[w + 4] = s2; o[w + 6] = s3; o[w + 8] = s4;
                 }
-                if (last || lm) {
+                if (with_cost) {
                     const float cs = group_sum<LANES>(pcs);    // 4 lanes: the same in each
                     if (LANES == 4 || p == 0) o[SM_COST] = cs;
                 }
@@ -1203,35 +1208,37 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
                             ok = false;
                         }
                     } else if (ok) {
-                        // equilibrate: E = D^-1/2 H D^-1/2 (unit diagonal)
+                        // equilibrate: E = D^-1/2 H D^-1/2 (unit diagonal).  The float
+                        // solve is formed unconditionally (no branches: the tests below
+                        // are combined with |) and replaced by the double-precision one
+                        // where a diagonal is not positive and finite or the system is
+                        // too ill-conditioned for float.
                         const float maxd = fmaxf(H00, fmaxf(H11, H22));
-                        bool need64 = !(H00 > 0.f) || !(H11 > 0.f) || !(H22 > 0.f) || !isfinite(maxd);
-                        if (!need64) {
-                            const float e0 = __frsqrt_rn(H00), e1 = __frsqrt_rn(H11), e2 = __frsqrt_rn(H22);
-                            const float e01 = H01 * e0 * e1, e02 = H02 * e0 * e2, e12 = H12 * e1 * e2;
-                            // adjugate and determinant of E (diagonal dd = 1 + lambda)
-                            const float d2 = dd * dd;
-                            const float c00 = fmaf(-e12, e12, d2), c11 = fmaf(-e02, e02, d2);
-                            const float c22 = fmaf(-e01, e01, d2);
-                            const float c01 = fmaf(e02, e12, -dd * e01), c02 = fmaf(e01, e12, -dd * e02);
-                            const float c12 = fmaf(e01, e02, -dd * e12);
-                            const float det = fmaf(e01, c01, fmaf(e02, c02, dd * c00));
-                            // kappa_F(E)^2 = ||E||_F^2 ||adj E||_F^2 / det^2  (>= kappa_2(E)^2)
-                            const float fro2 = 3.f * d2 + 2.f * (e01 * e01 + e02 * e02 + e12 * e12);
-                            const float adj2 = c00 * c00 + c11 * c11 + c22 * c22 +
-                                               2.f * (c01 * c01 + c02 * c02 + c12 * c12);
-                            // raw Cholesky pivots are H_jj times the equilibrated ones
-                            const float p1 = c22 * rcp_fast(dd);   // dd - e01^2 / dd (only compared)
-                            const float p2 = det * rcp_fast(c22);  // (only compared)
-                            need64 = !(fro2 * adj2 <= kap2 * det * det) || !(det > 0.f) || !(c22 > 0.f) ||
-                                     !(H11 * p1 > 1e-10f * maxd * dd) || !(H22 * p2 > 1e-10f * maxd * dd);
-                            if (!need64) {
-                                const float bh0 = bb0 * e0, bh1 = bb1 * e1, bh2 = bb2 * e2;
-                                const float idet = rcp_fast(det);
-                                d0s = -(c00 * bh0 + c01 * bh1 + c02 * bh2) * idet * e0;
-                                d1s = -(c01 * bh0 + c11 * bh1 + c12 * bh2) * idet * e1;
-                                d2s = -(c02 * bh0 + c12 * bh1 + c22 * bh2) * idet * e2;
-                            }
+                        const float e0 = __frsqrt_rn(H00), e1 = __frsqrt_rn(H11), e2 = __frsqrt_rn(H22);
+                        const float e01 = H01 * e0 * e1, e02 = H02 * e0 * e2, e12 = H12 * e1 * e2;
+                        // adjugate and determinant of E (diagonal dd = 1 + lambda)
+                        const float d2 = dd * dd;
+                        const float c00 = fmaf(-e12, e12, d2), c11 = fmaf(-e02, e02, d2);
+                        const float c22 = fmaf(-e01, e01, d2);
+                        const float c01 = fmaf(e02, e12, -dd * e01), c02 = fmaf(e01, e12, -dd * e02);
+                        const float c12 = fmaf(e01, e02, -dd * e12);
+                        const float det = fmaf(e01, c01, fmaf(e02, c02, dd * c00));
+                        // kappa_F(E)^2 = ||E||_F^2 ||adj E||_F^2 / det^2  (>= kappa_2(E)^2)
+                        const float fro2 = 3.f * d2 + 2.f * (e01 * e01 + e02 * e02 + e12 * e12);
+                        const float adj2 = c00 * c00 + c11 * c11 + c22 * c22 +
+                                           2.f * (c01 * c01 + c02 * c02 + c12 * c12);
+                        // raw Cholesky pivots are H_jj times the equilibrated ones
+                        const float p1 = c22 * rcp_fast(dd);   // dd - e01^2 / dd (only compared)
+                        const float p2 = det * rcp_fast(c22);  // (only compared)
+                        const bool need64 = !(H00 > 0.f) | !(H11 > 0.f) | !(H22 > 0.f) | !isfinite(maxd) |
+                                            !(fro2 * adj2 <= kap2 * det * det) | !(det > 0.f) | !(c22 > 0.f) |
+                                            !(H11 * p1 > 1e-10f * maxd * dd) | !(H22 * p2 > 1e-10f * maxd * dd);
+                        {
+                            const float bh0 = bb0 * e0, bh1 = bb1 * e1, bh2 = bb2 * e2;
+                            const float idet = rcp_fast(det);
+                            d0s = -(c00 * bh0 + c01 * bh1 + c02 * bh2) * idet * e0;
+                            d1s = -(c01 * bh0 + c11 * bh1 + c12 * bh2) * idet * e1;
+                            d2s = -(c02 * bh0 + c12 * bh1 + c22 * bh2) * idet * e2;
                         }
                         if (need64) {
                             flags |= F_FP64_SOLVE;
