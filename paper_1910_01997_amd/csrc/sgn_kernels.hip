@@ -900,8 +900,15 @@ __device__ __forceinline__ bool lm_accept(float cost2, int nv2, float cost_here,
 // (solve, update, tangent basis) is issued once per K groups.  Sums and states pass
 // between the pixel lanes and the owners through LDS.  All iterations run in
 // the kernel: surfels never read each other during the optimisation.
+// Wavefronts per SIMD each plan's kernel is compiled for (the register
+// budget: 80 VGPRs for six, 96 for five).  Occupancy pays: the 4x4 one-group
+// kernel runs 7 % faster at six than at five, and 9 % slower at four.  Plans
+// with several groups per item keep five (at six they spill 2-18 VGPRs).
+template <int S, int K>
+constexpr int gn_waves() { return (K == 1 || S == 8) ? 6 : 5; }
+
 template <typename T, int S, int TX, int TY, int K>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void gn_kernel(const BatchHeader* __restrict__ hdr_,
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(gn_waves<S, K>(), 8))) void gn_kernel(const BatchHeader* __restrict__ hdr_,
                                                            uint32_t* __restrict__ counters,
                                                            int persistent) {
     constexpr ItemGeo G = item_geo(S, TX, TY, K);
@@ -942,7 +949,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
     const int total = hdr->total_items;
     const int iters = hdr->iters;
     const float hk = hdr->huber_k;
-    const float kap2 = hdr->kappa_fp64 * hdr->kappa_fp64;
+    const float kappa_s = hdr->kappa_fp64;
     const bool depth_only = hdr->depth_only != 0;
     const uint32_t stamp = hdr->stamp;
     const float lm0 = hdr->lm_lambda;
@@ -981,12 +988,10 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
         const unsigned img_bytes = pitch_b * (unsigned)Kd->height;
         const unsigned wm1 = (unsigned)(Kd->width - 1), hm1 = (unsigned)(Kd->height - 1);
         const float fxk = Kd->fx, fyk = Kd->fy, cxk = Kd->cx, cyk = Kd->cy;
-        float drx[PPL], dry[PPL];                                       // r_u - r_s
-#pragma unroll
-        for (int j = 0; j < PPL; ++j) {
-            drx[j] = dxp[j] / fxk;
-            dry[j] = dyp[j] / fyk;
-        }
+        // r_u - r_s of the lane's first pixel; its later pixels lie DYR rows
+        // apart in the same column, dyr_f apart in r
+        const float drx0 = dxp[0] / fxk, dry0 = dyp[0] / fyk;
+        const float dyr_f = DYR / fyk;
         // anchor block centre (pixels)
         const int bpx = bx * G.ab * S, bpy = by * G.ab * S;
         {
@@ -1079,16 +1084,17 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
                 // count and cost, over its pixels in order
                 float ph[9], pnv, pcs;
                 // frame-independent per-pixel terms (Eq. 3, Eq. 9)
-                float sig[PPL], idu[PPL], didu[PPL];
+                float idu[PPL], didu[PPL];
                 bool pix_ok[PPL];
-                // sigma_u = n . (r_u - r_s) / (n . r_s); the lane's pixels
-                // share a column, so r_u - r_s differs between them in y only
+                // sigma_u = n . (r_u - r_s) / (n . r_s): the lane's first
+                // pixel's, and the step between its pixels (same column)
                 const float cnx = snx * inv_c, cny = sny * inv_c;
-                const float sx0 = cnx * drx[0];
+                const float sig0 = fmaf(cny, dry0, cnx * drx0);
+                const float dsig = cny * dyr_f;
 #pragma unroll
                 for (int j = 0; j < PPL; ++j) {
-                    sig[j] = fmaf(cny, dry[j], sx0);
-                    idu[j] = fmaf(sid, sig[j], sid);
+                    const float sig = fmaf((float)j, dsig, sig0);
+                    idu[j] = fmaf(sid, sig, sid);
                     didu[j] = j == 0 ? 0.f : idu[j] - idu[j - 1];
                     pix_ok[j] = salive && (idu[j] > 0.f);
                 }
@@ -1108,30 +1114,39 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
                 else
                     frame_loop_px<T, false, PPL>(pairs, fr, nf, bdx, bdy, DYR, idu, didu, pix_ok, pitch_b,
                                                  img_bytes, wm1, hm1, ikf[k], hk, img_scale, A, B, cst, nvp);
-                // the tangent basis and r_s, read again from LDS after the frame
-                // loop rather than held in registers through it
+                // the surfel's state and tangent basis, read again from LDS
+                // after the frame loop rather than held in registers through it
                 __asm__ volatile("" ::: "memory");
+                const float4 sa2 = *(const float4*)(st + 0);     // id, nx, ny, nz
                 const float4 sb = *(const float4*)(st + 4);      // b1, b2x
                 const float4 sc = *(const float4*)(st + 8);      // b2y, b2z, 1/c, rsx
                 const float srsy = st[ST_RSY];
                 const float sb1x = sb.x, sb1y = sb.y, sb1z = sb.z;
                 const float sb2x = sb.w, sb2y = sc.x, sb2z = sc.y, srsx = sc.w;
+                const float pinv_c = sc.z;
                 // g_u = (1 + sigma_u, kk b1 . d_u, kk b2 . d_u) with
                 // d_u = (r_u - r_s) - sigma_u (r_s, 1) and kk = id_s / (n . r_s):
-                // b . d_u = (b_x drx + b_y dry_u) - sigma_u (b . (r_s, 1)), the
-                // surfel's and the column's parts formed once.  The depth-only
-                // ablation zeroes kk, and with it the normal columns.
-                const float kk = depth_only ? 0.f : sid * inv_c;
+                // b . d_u = (b_x drx + b_y dry_u) - sigma_u (b . (r_s, 1)).  All
+                // three are affine in the pixel's row, so each is its value at
+                // the lane's first pixel plus j steps.  The depth-only ablation
+                // zeroes kk, and with it the normal columns.
+                const float pcnx = sa2.y * pinv_c, pcny = sa2.z * pinv_c;
+                const float psig0 = fmaf(pcny, dry0, pcnx * drx0);
+                const float pdsig = pcny * dyr_f;
+                const float kk = depth_only ? 0.f : sa2.x * pinv_c;
                 const float k1x = kk * sb1x, k1y = kk * sb1y, k2x = kk * sb2x, k2y = kk * sb2y;
                 const float q1 = kk * fmaf(sb1x, srsx, fmaf(sb1y, srsy, sb1z));
                 const float q2 = kk * fmaf(sb2x, srsx, fmaf(sb2y, srsy, sb2z));
-                const float c1 = k1x * drx[0], c2 = k2x * drx[0];
+                const float g00 = 1.f + psig0;
+                const float g10 = fmaf(-psig0, q1, fmaf(k1y, dry0, k1x * drx0));
+                const float g20 = fmaf(-psig0, q2, fmaf(k2y, dry0, k2x * drx0));
+                const float dg1 = fmaf(-pdsig, q1, k1y * dyr_f);
+                const float dg2 = fmaf(-pdsig, q2, k2y * dyr_f);
 #pragma unroll
                 for (int j = 0; j < PPL; ++j) {
-                    const float sigma = sig[j];
-                    const float g0 = 1.f + sigma;
-                    const float g1 = fmaf(-sigma, q1, fmaf(k1y, dry[j], c1));
-                    const float g2 = fmaf(-sigma, q2, fmaf(k2y, dry[j], c2));
+                    const float g0 = fmaf((float)j, pdsig, g00);
+                    const float g1 = fmaf((float)j, dg1, g10);
+                    const float g2 = fmaf((float)j, dg2, g20);
                     const float ag0 = A[j] * g0, ag1 = A[j] * g1, ag2 = A[j] * g2;
                     const float u[9] = {ag0, ag0, ag0, ag1, ag1, ag2, B[j], B[j], B[j]};
                     const float v[9] = {g0, g1, g2, g1, g2, g2, g0, g1, g2};
@@ -1172,6 +1187,18 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
                 }
             }
             wave_sync();
+            // the owner's state and tangent basis, read back from the words it
+            // wrote before the group loop rather than held in registers
+            // through the frame loops
+            __asm__ volatile("" ::: "memory");
+            if (owner) {
+                const float* o = lst + own * ST_WORDS;
+                const float4 w0 = *(const float4*)(o + 0);
+                const float4 w1 = *(const float4*)(o + 4);
+                const float4 w2 = *(const float4*)(o + 8);
+                id = w0.x; nx = w0.y; ny = w0.z; nz = w0.w;
+                b1x = w1.x; b1y = w1.y; b1z = w1.z; b2x = w1.w; b2y = w2.x; b2z = w2.y;
+            }
             // ---- owners: solve, update (Levenberg-Marquardt candidate test below)
             bool cand = false;
             float id_c = 0.f, nx_c = 0.f, ny_c = 0.f, nz_c = 0.f, cost_here = 0.f;
@@ -1182,7 +1209,11 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
                 // kernel, which spills in the default plan and costs the
                 // one-group plans their sixth wavefront per SIMD.  The text
                 // between the markers must equal owner_step's body; a CPU test
-                // compares the two.
+                // compares the two.  kappa^2 is formed here, each iteration,
+                // rather than held in a register through the frame loops.
+                float kappa_it = kappa_s;
+                __asm__ volatile("" : "+s"(kappa_it));
+                const float kap2 = kappa_it * kappa_it;
                 // owner_step body begin
                 const float* sm = lsm + own * SM_WORDS;
                 const float H00 = sm[SM_H00], H01 = sm[SM_H01], H02 = sm[SM_H02];
@@ -1313,13 +1344,17 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(5
                     float cst2 = 0.f;
                     int nv2l = 0;
                     const float cnx = sa.y * inv_c, cny = sa.z * inv_c;
-                    const float sx0 = cnx * drx[0];
+                    const float sig0 = fmaf(cny, dry0, cnx * drx0);
+                    const float dsig = cny * dyr_f;
 #pragma unroll
                     for (int j = 0; j < PPL; ++j) {
-                        const float sig = fmaf(cny, dry[j], sx0);
+                        const float sig = fmaf((float)j, dsig, sig0);
                         const float idu_c = fmaf(sa.x, sig, sa.x);
-                        const float bdx = (float)(S * tx + pxs[j] - bpx) - 0.5f * (float)(G.ab * S - 1);
-                        const float bdy = (float)(S * ty + pys[j] - bpy) - 0.5f * (float)(G.ab * S - 1);
+                        float bdx = (float)(S * tx + pxs[j] - bpx) - 0.5f * (float)(G.ab * S - 1);
+                        float bdy = (float)(S * ty + pys[j] - bpy) - 0.5f * (float)(G.ab * S - 1);
+                        // formed here, not kept from the item's start through the
+                        // iterations (registers)
+                        __asm__ volatile("" : "+v"(bdx), "+v"(bdy));
                         frame_cost<T>(pairs, fr, nf, bdx, bdy, idu_c, calive && (idu_c > 0.f), pitch_b,
                                       img_bytes, wm1, hm1, ikf[k][j], hk, img_scale, cst2, nv2l);
                     }
