@@ -728,7 +728,9 @@ __device__ __forceinline__ void frame_cost(const float* __restrict__ pc, cptr<Fr
 enum : int {
     // state broadcast to the pixel lanes
     ST_ID = 0, ST_NX, ST_NY, ST_NZ, ST_B1X, ST_B1Y, ST_B1Z, ST_B2X, ST_B2Y, ST_B2Z, ST_INVC,
-    ST_RSX, ST_RSY, ST_ALIVE, ST_WORDS = 16
+    ST_RSX, ST_RSY, ST_ALIVE,
+    // the owner's own bookkeeping, parked here through the group loop
+    ST_FLAGS, ST_LAM, ST_COSTO, ST_NVO, ST_WORDS = 20
 };
 enum : int {
     // reduced normal equations sent to the owner
@@ -901,11 +903,13 @@ __device__ __forceinline__ bool lm_accept(float cost2, int nv2, float cost_here,
 // between the pixel lanes and the owners through LDS.  All iterations run in
 // the kernel: surfels never read each other during the optimisation.
 // Wavefronts per SIMD each plan's kernel is compiled for (the register
-// budget: 80 VGPRs for six, 96 for five).  Occupancy pays: the 4x4 one-group
-// kernel runs 7 % faster at six than at five, and 9 % slower at four.  Plans
-// with several groups per item keep five (at six they spill 2-18 VGPRs).
+// budget: 72 VGPRs for seven, 80 for six, 96 for five).  Occupancy pays: on
+// the 64-keyframe f16 batch the 4x4 one-group kernel takes 4.69 ms at four,
+// 4.30 at five, 3.94 at six and 3.76 at seven (its 12 spilled words are
+// stored and reloaded once per work item, or in the damped variant's
+// branches); at eight, with spills inside the iteration loop, 4.05 ms.
 template <int S, int K>
-constexpr int gn_waves() { return (K == 1 || S == 8) ? 6 : 5; }
+constexpr int gn_waves() { return K == 1 ? 7 : (S == 8 ? 6 : 5); }
 
 template <typename T, int S, int TX, int TY, int K>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(gn_waves<S, K>(), 8))) void gn_kernel(const BatchHeader* __restrict__ hdr_,
@@ -1045,6 +1049,12 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(g
         int nv_out = 0;
         float lam = lm0;             // Levenberg-Marquardt damping of this surfel
         float b1x = 0.f, b1y = 0.f, b1z = 0.f, b2x = 0.f, b2y = 0.f, b2z = 0.f;
+        // r_s is the item's: written once (the words are the previous item's
+        // until the sync before the pair words, which is behind us)
+        if (owner) {
+            float* o = lst + own * ST_WORDS;
+            o[ST_RSX] = rsx; o[ST_RSY] = rsy;
+        }
 
         for (int it = 0; it < iters; ++it) {
             const bool last = (it == iters - 1);
@@ -1053,7 +1063,8 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(g
             const bool with_cost = __builtin_amdgcn_readfirstlane((int)(last || lm)) != 0;
             // ---- owners: degeneracy, tangent basis, broadcast of the state
             if (owner) {
-                const float c = nx * rsx + ny * rsy + nz;     // n . r_s
+                const float* os = lst + own * ST_WORDS;
+                const float c = nx * os[ST_RSX] + ny * os[ST_RSY] + nz;     // n . r_s
                 if (alive && fabsf(c) < 1e-6f) {
                     flags |= F_DEGENERATE;
                     alive = false;
@@ -1066,8 +1077,9 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(g
                 o[ST_B1X] = b1x; o[ST_B1Y] = b1y; o[ST_B1Z] = b1z;
                 o[ST_B2X] = b2x; o[ST_B2Y] = b2y; o[ST_B2Z] = b2z;
                 o[ST_INVC] = rcp_fast(c);                    // |c| >= 1e-6 where used
-                o[ST_RSX] = rsx; o[ST_RSY] = rsy;
                 o[ST_ALIVE] = alive ? 1.f : 0.f;
+                o[ST_FLAGS] = __uint_as_float(flags); o[ST_LAM] = lam;
+                o[ST_COSTO] = cost_out; o[ST_NVO] = __int_as_float(nv_out);
             }
             wave_sync();
             // ---- pixel lanes: linearise every group and reduce per surfel
@@ -1196,8 +1208,13 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(g
                 const float4 w0 = *(const float4*)(o + 0);
                 const float4 w1 = *(const float4*)(o + 4);
                 const float4 w2 = *(const float4*)(o + 8);
+                const float4 w3 = *(const float4*)(o + 12);
+                const float4 w4 = *(const float4*)(o + 16);
                 id = w0.x; nx = w0.y; ny = w0.z; nz = w0.w;
                 b1x = w1.x; b1y = w1.y; b1z = w1.z; b2x = w1.w; b2y = w2.x; b2z = w2.y;
+                alive = w3.y != 0.f;
+                flags = __float_as_uint(w3.z); lam = w3.w;
+                cost_out = w4.x; nv_out = __float_as_int(w4.y);
             }
             // ---- owners: solve, update (Levenberg-Marquardt candidate test below)
             bool cand = false;
