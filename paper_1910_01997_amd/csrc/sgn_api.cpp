@@ -45,11 +45,11 @@ constexpr int kRingSlots = 4;
 constexpr int kTimingRing = 64;
 
 struct GraphKey {
-    int dtype, patch, tx, ty, lds, persistent, grid, part, do_init, groups, frames_cap;
+    int dtype, patch, tx, ty, lds, persistent, grid, part, do_init, groups, frames_cap, by_row;
     bool operator<(const GraphKey& o) const {
-        return std::tie(dtype, patch, tx, ty, lds, persistent, grid, part, do_init, groups, frames_cap) <
+        return std::tie(dtype, patch, tx, ty, lds, persistent, grid, part, do_init, groups, frames_cap, by_row) <
                std::tie(o.dtype, o.patch, o.tx, o.ty, o.lds, o.persistent, o.grid, o.part, o.do_init,
-                        o.groups, o.frames_cap);
+                        o.groups, o.frames_cap, o.by_row);
     }
 };
 
@@ -326,6 +326,16 @@ struct RunFlags {
     bool init, gn, render;
 };
 
+// neighbour rows read by index: every keyframe's neighbour row pitch (bytes)
+// fits the buffer descriptor's stride field
+bool rows_by_index(const sgn_batch_item* items, int n) {
+    for (int i = 0; i < n; ++i) {
+        const sgn_keyframe& kf = items[i].kf;
+        if (kf.n_nbr > 0 && (size_t)kf.nbr[0].pitch * dtype_size(kf.kf.dtype) >= kMaxRowStride) return false;
+    }
+    return true;
+}
+
 int persistent_grid(sgn_ctx* c, const GnVariant& v, const sgn_plan& plan) {
     int per_cu = plan.waves_per_cu > 0 ? std::max(1, plan.waves_per_cu / 4) : gn_blocks_per_cu(v);
     if (per_cu < 1) per_cu = 1;
@@ -355,7 +365,8 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
     sgn_plan plan = plan_in ? *plan_in : default_plan(patch);
     if (plan.tiles_x == 0 && plan.tiles_y == 0) plan = default_plan(patch);
     if (plan.groups == 0) plan.groups = default_groups(patch, plan.tiles_x, plan.tiles_y);
-    GnVariant var{dtype, patch, plan.tiles_x, plan.tiles_y, plan.lds_stage, plan.groups};
+    GnVariant var{dtype, patch, plan.tiles_x, plan.tiles_y, plan.lds_stage, plan.groups,
+                  (int)rows_by_index(items, n)};
     if (fl.gn && !gn_variant_supported(var)) return fail(SGN_E_UNSUPPORTED, "plan not supported for this patch");
 
     TableLayout L = layout_for(n, total_frames);
@@ -518,7 +529,7 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
             return e == hipSuccess ? SGN_OK : hip_fail(e, "kernel launch");
         }
         GraphKey key{dtype, patch, plan.tiles_x, plan.tiles_y, plan.lds_stage, plan.persistent,
-                     part == 1 ? gn_grid : aux_grid, part, (int)do_init, plan.groups, frames_cap};
+                     part == 1 ? gn_grid : aux_grid, part, (int)do_init, plan.groups, frames_cap, var.by_row};
         auto found = c->graphs.find(key);
         if (found == c->graphs.end()) {
             hipStream_t cap = nullptr;
@@ -1313,7 +1324,8 @@ sgn_status sgn_autotune(sgn_ctx* c, const sgn_batch_item* items, int32_t n, cons
     const sgn_plan dflt = default_plan(patch);
     float dflt_ms = 1e30f;
     for (const sgn_plan& pl : cands) {
-        GnVariant v{items[0].kf.kf.dtype, patch, pl.tiles_x, pl.tiles_y, pl.lds_stage, pl.groups};
+        GnVariant v{items[0].kf.kf.dtype, patch, pl.tiles_x, pl.tiles_y, pl.lds_stage, pl.groups,
+                    (int)rows_by_index(items, n)};
         if (!gn_variant_supported(v)) continue;
         float tmin = 1e30f;
         bool ok = true;

@@ -98,7 +98,12 @@ struct GnVariant {
     int tiles_x, tiles_y;
     int lds;        // stage footprints in LDS
     int groups;     // surfel groups per work item (1, 2 or 4)
+    int by_row;     // neighbour rows read by index (every row pitch below kMaxRowStride)
 };
+// Row pitch (bytes) up to which neighbour images are read through a
+// structured buffer, the row as the index: the descriptor's stride field holds
+// 14 bits.  Wider rows are read with raw byte offsets.
+constexpr unsigned kMaxRowStride = 16384;
 
 // Work-item geometry of the Gauss-Newton kernel.  Surfels are taken in
 // aligned anchor blocks of 16 x 16 pixels (ab x ab tiles).  A work item is an

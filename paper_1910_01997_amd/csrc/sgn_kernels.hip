@@ -423,12 +423,20 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // The four bilinear taps (x0, y0), (x0+1, y0), (x0, y0+1), (x0+1, y0+1) of
-// one image, read with range-checked buffer loads (bytes past the image read
-// as zero, nothing faults); the second row uses the row pitch as the scalar
-// offset.  f32: one 8-byte load per row.  f16 / u8: one 8-byte load per row
-// from the aligned dword below the pair, and a funnel shift (4- and 2-byte
-// loads at the pair's own, unaligned address measured 11 % slower for the
-// whole kernel).  o0 is the byte offset of (x0, y0).
+// one image, read with buffer loads; the second row uses the row pitch as
+// the scalar offset.  f32: one 8-byte load per row.  f16 / u8: one 8-byte
+// load per row from the aligned dword below the pair, and a funnel shift (4-
+// and 2-byte loads at the pair's own, unaligned address measured 11 % slower
+// for the whole kernel).  The tap corner is (row y0, byte column col of x0).
+// Two addressings:
+//  - by row (BY_ROW: every row pitch of the batch below kMaxRowStride): a
+//    structured buffer whose stride is the row pitch, the row as the index
+//    (range-checked against the row count) and col as the offset, so no
+//    multiply forms the address;
+//  - raw: the byte offset row x pitch + col, range-checked against the
+//    image's bytes.
+// Either way the loads run only for samples whose corner passed the validity
+// test (x0 < W - 1, y0 < H - 1), so every tap lies inside the image.
 struct Taps {
     float i00, i01, i10, i11;
 };
@@ -438,35 +446,50 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const void* img, unsigned nbytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(img), (short)0, (int)nbytes, 0x00020000);
 }
-
-template <typename T>
-__device__ __forceinline__ Taps load_taps(__amdgpu_buffer_rsrc_t rs, unsigned o0, unsigned pitch_b);
-
-template <>
-__device__ __forceinline__ Taps load_taps<float>(__amdgpu_buffer_rsrc_t rs, unsigned o0, unsigned pitch_b) {
-    const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(rs, o0, 0, 0);
-    const u32x2 b = __builtin_amdgcn_raw_buffer_load_b64(rs, o0, pitch_b, 0);
-    Taps t;
-    t.i00 = __uint_as_float(a.x);
-    t.i01 = __uint_as_float(a.y);
-    t.i10 = __uint_as_float(b.x);
-    t.i11 = __uint_as_float(b.y);
-    return t;
+template <bool BY_ROW>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc_for(const void* img, unsigned pitch_b,
+                                                                 unsigned rows) {
+    if constexpr (BY_ROW) return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(img), (short)pitch_b, (int)rows, 0x00020000);
+    else return image_rsrc(img, pitch_b * rows);
 }
-
-template <>
-__device__ __forceinline__ Taps load_taps<uint8_t>(__amdgpu_buffer_rsrc_t rs, unsigned o0, unsigned pitch_b) {
-    // the byte shift of v_alignbyte is its third operand mod 4
-    const unsigned base = o0 & ~3u;
-    const u32x2 va = __builtin_amdgcn_raw_buffer_load_b64(rs, base, 0, 0);
-    const u32x2 vb = __builtin_amdgcn_raw_buffer_load_b64(rs, base, pitch_b, 0);
-    const unsigned a = __builtin_amdgcn_alignbyte(va.y, va.x, o0);
-    const unsigned b = __builtin_amdgcn_alignbyte(vb.y, vb.x, o0);
+// buffer_load_dwordx2 ... idxen offen: base + index x stride + offset + soffset
+__device__ u32x2 struct_buffer_load_b64(__amdgpu_buffer_rsrc_t rsrc, int vindex, int voffset, int soffset,
+                                        int aux) __asm("llvm.amdgcn.struct.ptr.buffer.load.v2i32");
+// the 8 bytes at byte column col of tap rows y0 and y0 + 1
+template <bool BY_ROW>
+__device__ __forceinline__ void load_row_pair(__amdgpu_buffer_rsrc_t rs, unsigned row, unsigned col,
+                                              unsigned pitch_b, u32x2& a, u32x2& b) {
+    if constexpr (BY_ROW) {
+        a = struct_buffer_load_b64(rs, (int)row, (int)col, 0, 0);
+        b = struct_buffer_load_b64(rs, (int)row, (int)col, (int)pitch_b, 0);
+    } else {
+        const unsigned o = __umul24(row, pitch_b) + col;
+        a = __builtin_amdgcn_raw_buffer_load_b64(rs, o, 0, 0);
+        b = __builtin_amdgcn_raw_buffer_load_b64(rs, o, pitch_b, 0);
+    }
+}
+template <typename T, bool BY_ROW>
+__device__ __forceinline__ Taps load_taps(__amdgpu_buffer_rsrc_t rs, unsigned row, unsigned col,
+                                          unsigned pitch_b) {
     Taps t;
-    t.i00 = (float)(a & 0xffu);
-    t.i01 = (float)((a >> 8) & 0xffu);
-    t.i10 = (float)(b & 0xffu);
-    t.i11 = (float)((b >> 8) & 0xffu);
+    u32x2 a, b;
+    if constexpr (std::is_same<T, float>::value) {
+        load_row_pair<BY_ROW>(rs, row, col, pitch_b, a, b);
+        t.i00 = __uint_as_float(a.x);
+        t.i01 = __uint_as_float(a.y);
+        t.i10 = __uint_as_float(b.x);
+        t.i11 = __uint_as_float(b.y);
+    } else {
+        // u8: the byte shift of v_alignbyte is its third operand mod 4 (the
+        // pitch is a multiple of 4, so col's shift is the address's)
+        load_row_pair<BY_ROW>(rs, row, col & ~3u, pitch_b, a, b);
+        const unsigned pa = __builtin_amdgcn_alignbyte(a.y, a.x, col);
+        const unsigned pb = __builtin_amdgcn_alignbyte(b.y, b.x, col);
+        t.i00 = (float)(pa & 0xffu);
+        t.i01 = (float)((pa >> 8) & 0xffu);
+        t.i10 = (float)(pb & 0xffu);
+        t.i11 = (float)((pb >> 8) & 0xffu);
+    }
     return t;
 }
 
@@ -479,9 +502,10 @@ struct Lerp {
     float d0, top, d1, bot;
 };
 
-template <typename T>
-__device__ __forceinline__ Lerp lerp_rows(__amdgpu_buffer_rsrc_t rs, unsigned o0, unsigned pitch_b, float ax) {
-    const Taps t = load_taps<T>(rs, o0, pitch_b);
+template <typename T, bool BY_ROW>
+__device__ __forceinline__ Lerp lerp_rows(__amdgpu_buffer_rsrc_t rs, unsigned row, unsigned col, unsigned pitch_b,
+                                          float ax) {
+    const Taps t = load_taps<T, BY_ROW>(rs, row, col, pitch_b);
     Lerp l;
     l.d0 = t.i01 - t.i00;
     l.d1 = t.i11 - t.i10;
@@ -503,22 +527,28 @@ __device__ __forceinline__ float half_lo_fma(float a, float b, unsigned pk) {
     return r;
 }
 
-template <>
-__device__ __forceinline__ Lerp lerp_rows<_Float16>(__amdgpu_buffer_rsrc_t rs, unsigned o0, unsigned pitch_b,
-                                                    float ax) {
+template <bool BY_ROW>
+__device__ __forceinline__ Lerp lerp_rows_f16(__amdgpu_buffer_rsrc_t rs, unsigned row, unsigned col,
+                                              unsigned pitch_b, float ax) {
     // pitch_b is a multiple of 4; the byte funnel shift (v_alignbyte) takes
-    // its amount mod 4, so o0 itself shifts by o0 mod 4 bytes
-    const unsigned base = o0 & ~3u;
-    const u32x2 va = __builtin_amdgcn_raw_buffer_load_b64(rs, base, 0, 0);
-    const u32x2 vb = __builtin_amdgcn_raw_buffer_load_b64(rs, base, pitch_b, 0);
-    const unsigned a = __builtin_amdgcn_alignbyte(va.y, va.x, o0);  // (I(x0), I(x0+1)) of row y0
-    const unsigned b = __builtin_amdgcn_alignbyte(vb.y, vb.x, o0);  // of row y0 + 1
+    // its amount mod 4, so col gives the address's shift
+    u32x2 va, vb;
+    load_row_pair<BY_ROW>(rs, row, col & ~3u, pitch_b, va, vb);
+    const unsigned a = __builtin_amdgcn_alignbyte(va.y, va.x, col);  // (I(x0), I(x0+1)) of row y0
+    const unsigned b = __builtin_amdgcn_alignbyte(vb.y, vb.x, col);  // of row y0 + 1
     Lerp l;
     l.d0 = half_pair_diff(a);
     l.d1 = half_pair_diff(b);
     l.top = half_lo_fma(ax, l.d0, a);
     l.bot = half_lo_fma(ax, l.d1, b);
     return l;
+}
+
+template <typename T, bool BY_ROW>
+__device__ __forceinline__ Lerp sample_rows(__amdgpu_buffer_rsrc_t rs, unsigned row, unsigned col,
+                                            unsigned pitch_b, float ax) {
+    if constexpr (std::is_same<T, _Float16>::value) return lerp_rows_f16<BY_ROW>(rs, row, col, pitch_b, ax);
+    else return lerp_rows<T, BY_ROW>(rs, row, col, pitch_b, ax);
 }
 
 // floor(x) converted to int in one instruction (v_cvt_flr_i32_f32).
@@ -529,12 +559,12 @@ __device__ __forceinline__ int cvt_floor(float x) {
 }
 
 // Warp of one sample into frame f in local coordinates (see the pair words):
-// returns validity; on success the integer tap corner offset o0 and the
+// returns validity; on success the integer tap corner (row, col) and the
 // bilinear fractions.  Valid iff q_z > 0 and 0 <= x_p < W-1, 0 <= y_p < H-1,
 // decided exactly on the integer corner X0 + floor(x_p - X0).
 struct Warp {
     float fx, fy, rq, ax, ay;
-    unsigned o0;
+    unsigned row, col;          // tap corner: row y0, byte column of x0
     bool v;
 };
 
@@ -557,7 +587,7 @@ __device__ __forceinline__ Warp warp_sample(const float4& c0, const float4& c1, 
     w.v = pix_ok & (qz > 0.f) & (ix < wm1) & (iy < hm1);
     w.ax = __builtin_amdgcn_fractf(w.fx);
     w.ay = __builtin_amdgcn_fractf(w.fy);
-    w.o0 = __umul24(iy, pitch_b) + ix * (unsigned)sizeof(T);
+    w.row = iy; w.col = ix * (unsigned)sizeof(T);
     return w;
 }
 
@@ -566,7 +596,7 @@ __device__ __forceinline__ Warp warp_sample(const float4& c0, const float4& c1, 
 // residual, and the scalar chain factor a = dr/did_u.  Accumulates
 // A = sum w a^2 and B = sum w a r (the per-pixel Jacobian g is applied after
 // the loop, hoisted as the paper suggests).  LAST also sums the Huber cost.
-template <typename T, bool LAST>
+template <typename T, bool LAST, bool BY_ROW>
 __device__ __forceinline__ void frame_loop(const float* __restrict__ pc, cptr<FrameDev> fr, int nf,
                                            float dx, float dy, float idu, bool pix_ok,
                                            unsigned pitch_b, unsigned img_bytes, unsigned wm1,
@@ -578,11 +608,11 @@ __device__ __forceinline__ void frame_loop(const float* __restrict__ pc, cptr<Fr
         const float4 c1 = *(const float4*)(pc + f * kPairWords + 4);
         const float4 c2 = *(const float4*)(pc + f * kPairWords + 8);
         const float h6 = fr[f].zrow[0], h7 = fr[f].zrow[1], k2 = fr[f].zrow[2];
-        const __amdgpu_buffer_rsrc_t rs = image_rsrc(fr[f].img, img_bytes);
+        const __amdgpu_buffer_rsrc_t rs = image_rsrc_for<BY_ROW>(fr[f].img, pitch_b, hm1 + 1);
         // Eq. 6 in local coordinates
         const Warp w = warp_sample<T>(c0, c1, c2, h6, h7, k2, dx, dy, idu, pix_ok, wm1, hm1, pitch_b);
         if (w.v) {
-            const Lerp l = lerp_rows<T>(rs, w.o0, pitch_b, w.ax);
+            const Lerp l = sample_rows<T, BY_ROW>(rs, w.row, w.col, pitch_b, w.ax);
             // bilinear value and the exact gradient of the interpolant
             const float gy = l.bot - l.top;
             const float val = fmaf(w.ay, gy, l.top);
@@ -612,7 +642,7 @@ __device__ __forceinline__ void frame_loop(const float* __restrict__ pc, cptr<Fr
 // coordinates (see the pair words): validity on the integer corner, the
 // bilinear value and exact gradient, residual, Huber IRLS weight and chain
 // factor; accumulates A, B, the valid count and (LAST) the Huber cost.
-template <typename T, bool LAST>
+template <typename T, bool LAST, bool BY_ROW>
 __device__ __forceinline__ void sample_at(float nxq, float nyq, float qz, const float4& c0, const float4& c1,
                                           const float4& c2, float k2, __amdgpu_buffer_rsrc_t rs, bool pix_ok,
                                           unsigned pitch_b, unsigned wm1, unsigned hm1, float ikf, float hk,
@@ -629,8 +659,7 @@ __device__ __forceinline__ void sample_at(float nxq, float nyq, float qz, const 
     if (pix_ok & (qz > 0.f) & (ix < wm1) & (iy < hm1)) {
         const float ax = __builtin_amdgcn_fractf(fx);
         const float ay = __builtin_amdgcn_fractf(fy);
-        const unsigned o0 = __umul24(iy, pitch_b) + ix * (unsigned)sizeof(T);
-        const Lerp l = lerp_rows<T>(rs, o0, pitch_b, ax);
+        const Lerp l = sample_rows<T, BY_ROW>(rs, iy, ix * (unsigned)sizeof(T), pitch_b, ax);
         // bilinear value and the exact gradient of the interpolant
         const float gy = l.bot - l.top;
         const float val = fmaf(ay, gy, l.top);
@@ -663,7 +692,7 @@ __device__ __forceinline__ void sample_at(float nxq, float nyq, float qz, const 
 // the change of id_u, didu[j]).  Accumulates A, B and the cost per pixel as
 // frame_loop does; the valid counts of the pixels are packed one per byte of
 // nvp (pixel j in byte j; at most 16 frames each).
-template <typename T, bool LAST, int NP>
+template <typename T, bool LAST, int NP, bool BY_ROW>
 __device__ __forceinline__ void frame_loop_px(const float* __restrict__ pc, cptr<FrameDev> fr, int nf,
                                               float dx, float dy, float dyr, const float (&idu)[NP],
                                               const float (&didu)[NP], const bool (&pix_ok)[NP],
@@ -677,19 +706,19 @@ __device__ __forceinline__ void frame_loop_px(const float* __restrict__ pc, cptr
         const float4 c1 = *(const float4*)(pc + f * kPairWords + 4);
         const float4 c2 = *(const float4*)(pc + f * kPairWords + 8);
         const float h6 = fr[f].zrow[0], h7 = fr[f].zrow[1], k2 = fr[f].zrow[2];
-        const __amdgpu_buffer_rsrc_t rs = image_rsrc(fr[f].img, img_bytes);
+        const __amdgpu_buffer_rsrc_t rs = image_rsrc_for<BY_ROW>(fr[f].img, pitch_b, hm1 + 1);
         // Eq. 6 in local coordinates
         float nxq = fmaf(c0.x, dx, fmaf(c0.y, dy, fmaf(c0.z, idu[0], c0.w)));
         float nyq = fmaf(c1.x, dx, fmaf(c1.y, dy, fmaf(c1.z, idu[0], c1.w)));
         float qz = fmaf(h6, dx, fmaf(h7, dy, fmaf(k2, idu[0], c2.x)));
-        sample_at<T, LAST>(nxq, nyq, qz, c0, c1, c2, k2, rs, pix_ok[0], pitch_b, wm1, hm1, ikf[0], hk,
+        sample_at<T, LAST, BY_ROW>(nxq, nyq, qz, c0, c1, c2, k2, rs, pix_ok[0], pitch_b, wm1, hm1, ikf[0], hk,
                            img_scale, A[0], B[0], cst[0], nvp, 1u);
 #pragma unroll
         for (int j = 1; j < NP; ++j) {
             nxq = fmaf(c0.z, didu[j], fmaf(c0.y, dyr, nxq));
             nyq = fmaf(c1.z, didu[j], fmaf(c1.y, dyr, nyq));
             qz = fmaf(k2, didu[j], fmaf(h7, dyr, qz));
-            sample_at<T, LAST>(nxq, nyq, qz, c0, c1, c2, k2, rs, pix_ok[j], pitch_b, wm1, hm1, ikf[j], hk,
+            sample_at<T, LAST, BY_ROW>(nxq, nyq, qz, c0, c1, c2, k2, rs, pix_ok[j], pitch_b, wm1, hm1, ikf[j], hk,
                                img_scale, A[j], B[j], cst[j], nvp, 1u << (8 * j));
         }
     }
@@ -698,7 +727,7 @@ __device__ __forceinline__ void frame_loop_px(const float* __restrict__ pc, cptr
 // Huber cost (Eq. 5) and valid-sample count of one pixel at a candidate
 // state, over all neighbour frames (no Jacobian): the Levenberg-Marquardt
 // acceptance test.
-template <typename T>
+template <typename T, bool BY_ROW>
 __device__ __forceinline__ void frame_cost(const float* __restrict__ pc, cptr<FrameDev> fr, int nf,
                                            float dx, float dy, float idu, bool pix_ok,
                                            unsigned pitch_b, unsigned img_bytes, unsigned wm1,
@@ -710,10 +739,10 @@ __device__ __forceinline__ void frame_cost(const float* __restrict__ pc, cptr<Fr
         const float4 c1 = *(const float4*)(pc + f * kPairWords + 4);
         const float4 c2 = *(const float4*)(pc + f * kPairWords + 8);
         const float h6 = fr[f].zrow[0], h7 = fr[f].zrow[1], k2 = fr[f].zrow[2];
-        const __amdgpu_buffer_rsrc_t rs = image_rsrc(fr[f].img, img_bytes);
+        const __amdgpu_buffer_rsrc_t rs = image_rsrc_for<BY_ROW>(fr[f].img, pitch_b, hm1 + 1);
         const Warp w = warp_sample<T>(c0, c1, c2, h6, h7, k2, dx, dy, idu, pix_ok, wm1, hm1, pitch_b);
         if (w.v) {
-            const Lerp l = lerp_rows<T>(rs, w.o0, pitch_b, w.ax);
+            const Lerp l = sample_rows<T, BY_ROW>(rs, w.row, w.col, pitch_b, w.ax);
             const float val = fmaf(w.ay, l.bot - l.top, l.top);
             const float r = SCALED ? fmaf(val, img_scale, -ikf) : val - ikf;
             const float ar = fabsf(r);
@@ -911,7 +940,7 @@ __device__ __forceinline__ bool lm_accept(float cost2, int nv2, float cost_here,
 template <int S, int K>
 constexpr int gn_waves() { return K == 1 ? 7 : (S == 8 ? 6 : 5); }
 
-template <typename T, int S, int TX, int TY, int K>
+template <typename T, int S, int TX, int TY, int K, bool BY_ROW>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(gn_waves<S, K>(), 8))) void gn_kernel(const BatchHeader* __restrict__ hdr_,
                                                            uint32_t* __restrict__ counters,
                                                            int persistent) {
@@ -1121,10 +1150,10 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(g
                     A[j] = 0.f; B[j] = 0.f; cst[j] = 0.f;
                 }
                 if (with_cost)
-                    frame_loop_px<T, true, PPL>(pairs, fr, nf, bdx, bdy, DYR, idu, didu, pix_ok, pitch_b,
+                    frame_loop_px<T, true, PPL, BY_ROW>(pairs, fr, nf, bdx, bdy, DYR, idu, didu, pix_ok, pitch_b,
                                                 img_bytes, wm1, hm1, ikf[k], hk, img_scale, A, B, cst, nvp);
                 else
-                    frame_loop_px<T, false, PPL>(pairs, fr, nf, bdx, bdy, DYR, idu, didu, pix_ok, pitch_b,
+                    frame_loop_px<T, false, PPL, BY_ROW>(pairs, fr, nf, bdx, bdy, DYR, idu, didu, pix_ok, pitch_b,
                                                  img_bytes, wm1, hm1, ikf[k], hk, img_scale, A, B, cst, nvp);
                 // the surfel's state and tangent basis, read again from LDS
                 // after the frame loop rather than held in registers through it
@@ -1372,7 +1401,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(g
                         // formed here, not kept from the item's start through the
                         // iterations (registers)
                         __asm__ volatile("" : "+v"(bdx), "+v"(bdy));
-                        frame_cost<T>(pairs, fr, nf, bdx, bdy, idu_c, calive && (idu_c > 0.f), pitch_b,
+                        frame_cost<T, BY_ROW>(pairs, fr, nf, bdx, bdy, idu_c, calive && (idu_c > 0.f), pitch_b,
                                       img_bytes, wm1, hm1, ikf[k][j], hk, img_scale, cst2, nv2l);
                     }
                     const float c2 = group_sum<LANES>(cst2);
@@ -1747,41 +1776,41 @@ hipError_t launch_quantize(const float* src, int src_pitch, void* dst, int dst_p
     return hipGetLastError();
 }
 
-template <typename T, int S, int TX, int TY, int K>
+template <typename T, int S, int TX, int TY, int K, bool R>
 static void* gn_ptr() {
-    return (void*)&gn_kernel<T, S, TX, TY, K>;
+    return (void*)&gn_kernel<T, S, TX, TY, K, R>;
 }
 
-template <typename T, int S, int TX, int TY, int KMAX = 4>
+template <typename T, int S, int TX, int TY, bool R, int KMAX = 4>
 static void* gn_pick_groups(int groups) {
-    if (groups == 1) return gn_ptr<T, S, TX, TY, 1>();
-    if (groups == 2) return gn_ptr<T, S, TX, TY, 2>();
+    if (groups == 1) return gn_ptr<T, S, TX, TY, 1, R>();
+    if (groups == 2) return gn_ptr<T, S, TX, TY, 2, R>();
     if constexpr (KMAX >= 4)
-        if (groups == 4) return gn_ptr<T, S, TX, TY, 4>();
+        if (groups == 4) return gn_ptr<T, S, TX, TY, 4, R>();
     return nullptr;
 }
 
-template <typename T>
+template <typename T, bool R>
 static void* gn_pick(const GnVariant& v) {
-    if (v.patch == 8 && v.tiles_x == 1 && v.tiles_y == 1) return gn_pick_groups<T, 8, 1, 1>(v.groups);
+    if (v.patch == 8 && v.tiles_x == 1 && v.tiles_y == 1) return gn_pick_groups<T, 8, 1, 1, R>(v.groups);
     // a 16 x 16 surfel is its own anchor block: one group per item
-    if (v.patch == 16 && v.tiles_x == 1 && v.tiles_y == 1 && v.groups == 1) return gn_ptr<T, 16, 1, 1, 1>();
-    if (v.patch == 4 && v.tiles_x == 4 && v.tiles_y == 1) return gn_pick_groups<T, 4, 4, 1>(v.groups);
-    if (v.patch == 4 && v.tiles_x == 2 && v.tiles_y == 2) return gn_pick_groups<T, 4, 2, 2>(v.groups);
-    if (v.patch == 4 && v.tiles_x == 1 && v.tiles_y == 4) return gn_pick_groups<T, 4, 1, 4>(v.groups);
+    if (v.patch == 16 && v.tiles_x == 1 && v.tiles_y == 1 && v.groups == 1) return gn_ptr<T, 16, 1, 1, 1, R>();
+    if (v.patch == 4 && v.tiles_x == 4 && v.tiles_y == 1) return gn_pick_groups<T, 4, 4, 1, R>(v.groups);
+    if (v.patch == 4 && v.tiles_x == 2 && v.tiles_y == 2) return gn_pick_groups<T, 4, 2, 2, R>(v.groups);
+    if (v.patch == 4 && v.tiles_x == 1 && v.tiles_y == 4) return gn_pick_groups<T, 4, 1, 4, R>(v.groups);
     // eight 4 x 4 surfels per wavefront, two pixels per lane: one or two groups
-    if (v.patch == 4 && v.tiles_x == 4 && v.tiles_y == 2) return gn_pick_groups<T, 4, 4, 2, 2>(v.groups);
-    if (v.patch == 4 && v.tiles_x == 2 && v.tiles_y == 4) return gn_pick_groups<T, 4, 2, 4, 2>(v.groups);
+    if (v.patch == 4 && v.tiles_x == 4 && v.tiles_y == 2) return gn_pick_groups<T, 4, 4, 2, R, 2>(v.groups);
+    if (v.patch == 4 && v.tiles_x == 2 && v.tiles_y == 4) return gn_pick_groups<T, 4, 2, 4, R, 2>(v.groups);
     // sixteen 4 x 4 surfels (a whole anchor block) per wavefront, four pixels per lane
-    if (v.patch == 4 && v.tiles_x == 4 && v.tiles_y == 4 && v.groups == 1) return gn_ptr<T, 4, 4, 4, 1>();
+    if (v.patch == 4 && v.tiles_x == 4 && v.tiles_y == 4 && v.groups == 1) return gn_ptr<T, 4, 4, 4, 1, R>();
     return nullptr;
 }
 
 static void* gn_select(const GnVariant& v) {
     if (v.lds) return nullptr;
-    if (v.dtype == 0) return gn_pick<float>(v);
-    if (v.dtype == 1) return gn_pick<_Float16>(v);
-    if (v.dtype == 2) return gn_pick<uint8_t>(v);
+    if (v.dtype == 0) return v.by_row ? gn_pick<float, true>(v) : gn_pick<float, false>(v);
+    if (v.dtype == 1) return v.by_row ? gn_pick<_Float16, true>(v) : gn_pick<_Float16, false>(v);
+    if (v.dtype == 2) return v.by_row ? gn_pick<uint8_t, true>(v) : gn_pick<uint8_t, false>(v);
     return nullptr;
 }
 
@@ -2070,10 +2099,10 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
                 float A = 0.f, B = 0.f, cst = 0.f;
                 int nvl = 0;
                 if (last || lm)
-                    frame_loop<T, true>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes, wm1, hm1,
+                    frame_loop<T, true, false>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes, wm1, hm1,
                                         ikf, hk, img_scale, A, B, cst, nvl);
                 else
-                    frame_loop<T, false>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes, wm1, hm1,
+                    frame_loop<T, false, false>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes, wm1, hm1,
                                          ikf, hk, img_scale, A, B, cst, nvl);
                 {
                     const float ag0 = A * g0, ag1 = A * g1, ag2 = A * g2;
@@ -2143,7 +2172,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
                     const float drx = (bdx + fox) * ifx, dry = (bdy + foy) * ify;
                     const float sig = (sa.y * drx + sa.z * dry) * inv_c;
                     const float idu_c = fmaf(sa.x, sig, sa.x);
-                    frame_cost<T>(pairs, fr, nf, bdx, bdy, idu_c, calive && pv && (idu_c > 0.f), pitch_b,
+                    frame_cost<T, false>(pairs, fr, nf, bdx, bdy, idu_c, calive && pv && (idu_c > 0.f), pitch_b,
                                   img_bytes, wm1, hm1, ikf, hk, img_scale, cst2, nv2l);
                 }
                 const float c2 = group_sum<LANES>(cst2);

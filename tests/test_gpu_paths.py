@@ -145,6 +145,39 @@ def test_autotune_picks_a_4x4_plan_and_restores_the_state(ctx):
         _state_equal(d.state.to_host(), p.state.to_host())
 
 
+def test_wide_row_pitch_reads_by_byte_offset_and_agrees_bitwise(ctx):
+    """Neighbour images whose row pitch is 16 KiB or more are read with raw
+    byte offsets instead of row-indexed buffer loads (the descriptor's
+    stride field holds 14 bits): the same images behind a wide pitch give
+    bitwise the same update, for f32 and f16 storage, batched and plain."""
+    sg, engine = sgmod()
+    kf = make_keyframe(spec_for_config(1), device="cuda")
+    prm = sg.params(iters=6)
+    for storage, pad_elems in (("f32", 4200), ("f16", 8400)):
+        print(f"case wide pitch {storage}: {pad_elems} elements per row", flush=True)
+        d = engine.DeviceKeyframe.from_scene(ctx, kf, storage=storage)
+        engine.update_plain(ctx, d, prm)
+        torch.cuda.synchronize()
+        ref = d.state.to_host()
+        w = engine.DeviceKeyframe.from_scene(ctx, kf, storage=storage)
+        wide = torch.zeros((w.n_nbr, w.height, pad_elems), dtype=w.nbr_imgs.dtype, device="cuda")
+        wide[:, :, :w.width] = w.nbr_imgs
+        views = [wide[i, :, :w.width] for i in range(w.n_nbr)]
+        assert views[0].stride(0) * views[0].element_size() >= 16384
+        w.view = sg.KeyframeView(w.kf_img, views, w.R, w.t, w.K, w.patch, w.scale)
+        engine.update_plain(ctx, w, prm)
+        torch.cuda.synchronize()
+        _state_equal(w.state.to_host(), ref)
+        # a batch with one wide keyframe reads all of its keyframes by byte offset
+        b1 = engine.DeviceKeyframe.from_scene(ctx, kf, storage=storage)
+        b2 = engine.DeviceKeyframe.from_scene(ctx, kf, storage=storage)
+        b2.view = sg.KeyframeView(b2.kf_img, views, b2.R, b2.t, b2.K, b2.patch, b2.scale)
+        engine.update_batch(ctx, [b1, b2], prm)
+        torch.cuda.synchronize()
+        _state_equal(b1.state.to_host(), ref)
+        _state_equal(b2.state.to_host(), ref)
+
+
 def test_repeated_calls_are_deterministic(ctx):
     sg, engine = sgmod()
     kf = make_keyframe(spec_for_config(1), device="cuda")
