@@ -1183,17 +1183,46 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(g
                 const float g20 = fmaf(-psig0, q2, fmaf(k2y, dry0, k2x * drx0));
                 const float dg1 = fmaf(-pdsig, q1, k1y * dyr_f);
                 const float dg2 = fmaf(-pdsig, q2, k2y * dyr_f);
+                if constexpr (PPL == 4) {
+                    // sum_j A_j g_j g_j^T and sum_j B_j g_j with g_j = ga + j gb,
+                    // through the lane's moments S_m = sum_j j^m A_j and
+                    // T_m = sum_j j^m B_j: with u = S0 ga + S1 gb and
+                    // v = S1 ga + S2 gb, H = u ga^T + v gb^T and b = T0 ga + T1 gb
+                    // (42 instructions for the four pixels against 60 per pixel)
+                    const float S0 = (A[0] + A[1]) + (A[2] + A[3]);
+                    const float S1 = fmaf(3.f, A[3], fmaf(2.f, A[2], A[1]));
+                    const float S2 = fmaf(9.f, A[3], fmaf(4.f, A[2], A[1]));
+                    const float T0 = (B[0] + B[1]) + (B[2] + B[3]);
+                    const float T1 = fmaf(3.f, B[3], fmaf(2.f, B[2], B[1]));
+                    const float ga[3] = {g00, g10, g20}, gb[3] = {pdsig, dg1, dg2};
+                    float uu[3], vv[3];
 #pragma unroll
-                for (int j = 0; j < PPL; ++j) {
-                    const float g0 = fmaf((float)j, pdsig, g00);
-                    const float g1 = fmaf((float)j, dg1, g10);
-                    const float g2 = fmaf((float)j, dg2, g20);
-                    const float ag0 = A[j] * g0, ag1 = A[j] * g1, ag2 = A[j] * g2;
-                    const float u[9] = {ag0, ag0, ag0, ag1, ag1, ag2, B[j], B[j], B[j]};
-                    const float v[9] = {g0, g1, g2, g1, g2, g2, g0, g1, g2};
+                    for (int a = 0; a < 3; ++a) {
+                        uu[a] = fmaf(S1, gb[a], S0 * ga[a]);
+                        vv[a] = fmaf(S2, gb[a], S1 * ga[a]);
+                    }
+                    ph[0] = fmaf(vv[0], gb[0], uu[0] * ga[0]);     // H00
+                    ph[1] = fmaf(vv[0], gb[1], uu[0] * ga[1]);     // H01
+                    ph[2] = fmaf(vv[0], gb[2], uu[0] * ga[2]);     // H02
+                    ph[3] = fmaf(vv[1], gb[1], uu[1] * ga[1]);     // H11
+                    ph[4] = fmaf(vv[1], gb[2], uu[1] * ga[2]);     // H12
+                    ph[5] = fmaf(vv[2], gb[2], uu[2] * ga[2]);     // H22
 #pragma unroll
-                    for (int e = 0; e < 9; ++e) ph[e] = (j == 0) ? u[e] * v[e] : fmaf(u[e], v[e], ph[e]);
-                    pcs = (j == 0) ? cst[j] : pcs + cst[j];
+                    for (int a = 0; a < 3; ++a) ph[6 + a] = fmaf(T1, gb[a], T0 * ga[a]);
+                    pcs = (cst[0] + cst[1]) + (cst[2] + cst[3]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < PPL; ++j) {
+                        const float g0 = fmaf((float)j, pdsig, g00);
+                        const float g1 = fmaf((float)j, dg1, g10);
+                        const float g2 = fmaf((float)j, dg2, g20);
+                        const float ag0 = A[j] * g0, ag1 = A[j] * g1, ag2 = A[j] * g2;
+                        const float u[9] = {ag0, ag0, ag0, ag1, ag1, ag2, B[j], B[j], B[j]};
+                        const float v[9] = {g0, g1, g2, g1, g2, g2, g0, g1, g2};
+#pragma unroll
+                        for (int e = 0; e < 9; ++e) ph[e] = (j == 0) ? u[e] * v[e] : fmaf(u[e], v[e], ph[e]);
+                        pcs = (j == 0) ? cst[j] : pcs + cst[j];
+                    }
                 }
                 // the lane's valid samples: the byte counters summed (v_sad_u8)
                 pnv = (float)__builtin_amdgcn_sad_u8(nvp, 0u, 0u);
