@@ -1134,7 +1134,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(g
                 const float dsig = cny * dyr_f;
 #pragma unroll
                 for (int j = 0; j < PPL; ++j) {
-                    const float sig = fmaf((float)j, dsig, sig0);
+                    const float sig = j == 0 ? sig0 : fmaf((float)j, dsig, sig0);
                     idu[j] = fmaf(sid, sig, sid);
                     didu[j] = j == 0 ? 0.f : idu[j] - idu[j - 1];
                     pix_ok[j] = salive && (idu[j] > 0.f);
@@ -1423,7 +1423,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(g
                     const float dsig = cny * dyr_f;
 #pragma unroll
                     for (int j = 0; j < PPL; ++j) {
-                        const float sig = fmaf((float)j, dsig, sig0);
+                        const float sig = j == 0 ? sig0 : fmaf((float)j, dsig, sig0);
                         const float idu_c = fmaf(sa.x, sig, sa.x);
                         float bdx = (float)(S * tx + pxs[j] - bpx) - 0.5f * (float)(G.ab * S - 1);
                         float bdy = (float)(S * ty + pys[j] - bpy) - 0.5f * (float)(G.ab * S - 1);
