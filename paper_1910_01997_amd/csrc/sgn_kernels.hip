@@ -931,6 +931,12 @@ __device__ __forceinline__ bool lm_accept(float cost2, int nv2, float cost_here,
 // (solve, update, tangent basis) is issued once per K groups.  Sums and states pass
 // between the pixel lanes and the owners through LDS.  All iterations run in
 // the kernel: surfels never read each other during the optimisation.
+// Registers are the budget that matters (the kernel issues a VALU
+// instruction on nearly every cycle it can, and more wavefronts per SIMD
+// hide the rest): values that the frame loop does not use are not held
+// through it but formed again or read back from LDS afterwards.  BY_ROW
+// reads the neighbour rows by index (row pitches below kMaxRowStride).
+//
 // Wavefronts per SIMD each plan's kernel is compiled for (the register
 // budget: 72 VGPRs for seven, 80 for six, 96 for five).  Occupancy pays: on
 // the 64-keyframe f16 batch the 4x4 one-group kernel takes 4.69 ms at four,
