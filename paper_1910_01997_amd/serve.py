@@ -414,7 +414,7 @@ class HipExecutor(Executor):
     its own torch stream (default priority)."""
 
     def __init__(self, streams: List[CameraStream], lanes: int = 2, iters: int = 15,
-                 plan=None):
+                 plan=None, pixels_per_lane: int = 4):
         import torch
 
         from . import surfgn as sg
@@ -426,11 +426,19 @@ class HipExecutor(Executor):
         self.ctxs = [sg.Context(0, stream=s) for s in self.tstreams]
         self.params = sg.params(iters=iters)
         self.plan = plan
-        # every plan here gives a 4x4 surfel 16 lanes (one pixel each), so a
-        # request's result is the same, bitwise, alone and in any mix
-        self.small_plan = sg.plan(2, 2, 1, 0, 0, 1, groups=1)
-        self.single_plan = sg.plan(2, 2, 0, 0, 0, 0, groups=1)
-        self.large_plan = sg.plan(2, 2, 1, 0, 0, 1, groups=4)
+        # every plan here gives a 4x4 surfel the same lanes (16 lanes of one
+        # pixel, or 4 lanes of four pixels), so a request's result is the
+        # same, bitwise, alone and in any mix
+        if pixels_per_lane == 4:
+            self.small_plan = sg.plan(4, 4, 1, 0, 0, 1, groups=1)
+            self.single_plan = sg.plan(4, 4, 0, 0, 0, 0, groups=1)
+            self.large_plan = sg.plan(4, 4, 0, 0, 0, 0, groups=1)
+        elif pixels_per_lane == 1:
+            self.small_plan = sg.plan(2, 2, 1, 0, 0, 1, groups=1)
+            self.single_plan = sg.plan(2, 2, 0, 0, 0, 0, groups=1)
+            self.large_plan = sg.plan(2, 2, 1, 0, 0, 1, groups=4)
+        else:
+            raise ValueError("pixels_per_lane is 1 or 4")
         self.small_batch_surfels = 200_000
         self.slab = None
 
@@ -509,10 +517,10 @@ class PlainExecutor(HipExecutor):
     """The plain form: one request at a time with the single-keyframe calls
     (init, non-persistent Gauss-Newton launch, render) on one lane."""
 
-    def __init__(self, streams, iters: int = 15):
-        super().__init__(streams, lanes=1, iters=iters)
+    def __init__(self, streams, iters: int = 15, pixels_per_lane: int = 4):
+        super().__init__(streams, lanes=1, iters=iters, pixels_per_lane=pixels_per_lane)
         # the single-keyframe plan: one group per wavefront, one wavefront per item
-        self.plain_plan = self.sg.plan(2, 2, 0, 0, 0, 0, groups=1)
+        self.plain_plan = self.single_plan
 
     def launch(self, lane: int, batch: List[Request]):
         assert len(batch) == 1
@@ -580,7 +588,7 @@ def serving_benchmark(n_streams: int = 32, rate: float = 200.0, duration: float 
                       warmup: float = 1.0, storage: str = "f16", lanes: int = 2,
                       pool_bytes: int = 256 << 20, iters: int = 15, seed: int = 599,
                       specs=None, log=print, sweep=(), sweep_duration: float = 2.0,
-                      sweep_warmup: float = 0.25):
+                      sweep_warmup: float = 0.25, pixels_per_lane: int = 4):
     """Served (continuous batching) and plain (FIFO, one request at a time,
     single-keyframe calls) runs of the same Poisson trace at `rate`, then, on
     the same resident streams, shorter traces at each rate of `sweep`.
@@ -603,8 +611,8 @@ def serving_benchmark(n_streams: int = 32, rate: float = 200.0, duration: float 
         ctx = sg.Context(0)
         streams = make_streams(ctx, specs, extra=extra, storage=storage)
         torch.cuda.synchronize()
-        ex = HipExecutor(streams, lanes=lanes, iters=iters) if mode == "served" else \
-            PlainExecutor(streams, iters=iters)
+        ex = HipExecutor(streams, lanes=lanes, iters=iters, pixels_per_lane=pixels_per_lane) \
+            if mode == "served" else PlainExecutor(streams, iters=iters, pixels_per_lane=pixels_per_lane)
         srv = Server(ex, pool_bytes=pool_bytes, max_batch=32 if mode == "served" else 1)
         # warm the kernels and graphs on a short burst outside the measured trace
         for s in range(min(4, len(streams))):
