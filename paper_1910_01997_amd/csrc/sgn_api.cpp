@@ -725,7 +725,14 @@ sgn_status run_disc_batch(sgn_ctx* c, const sgn_disc_item* items, int n, const s
     if (item_base > 0) {
         next_timing_slot(c);
         SGN_HIP(hipEventRecord(c->gn_start, c->stream));
-        e = launch_disc_gn(dtype, dH, item_base, c->stream);
+        // neighbour rows read by index unless a row pitch exceeds the
+        // descriptor's stride field
+        bool by_row = true;
+        for (int i = 0; i < n; ++i) {
+            const sgn_keyframe& kf = items[i].kf;
+            if (kf.n_nbr > 0 && (size_t)kf.nbr[0].pitch * dtype_size(kf.kf.dtype) >= kMaxRowStride) by_row = false;
+        }
+        e = launch_disc_gn(dtype, dH, item_base, by_row, c->stream);
         if (e != hipSuccess) return hip_fail(e, "disc Gauss-Newton launch");
         SGN_HIP(hipEventRecord(c->gn_end, c->stream));
         c->gn_timed = true;

@@ -1980,7 +1980,7 @@ __device__ __forceinline__ void disc_pixel(const DiscRows& d, const int* row_x0,
 // reductions span 32 lanes.  Six wavefronts per SIMD (80 VGPRs, and the LDS
 // of six workgroups per CU): the few values that spill are read by the owner
 // step once per iteration or by its double-precision fallback only.
-template <typename T, int SPW>
+template <typename T, int SPW, bool BY_ROW>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) void disc_gn_kernel(
     const BatchHeader* __restrict__ hdr_, int total) {
     constexpr int LANES = kWaveSize / SPW;        // lanes per surfel
@@ -2113,6 +2113,13 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
             const float sb2x = sb.w, sb2y = sc.x, sb2z = sc.y, inv_c = sc.z, srsx = sc.w;
             const float srsy = sd.x;
             const bool salive = sd.y != 0.f;
+            // the surfel's parts of sigma_u and g_u (see gn_kernel), formed
+            // once per iteration; the depth-only ablation zeroes kk
+            const float cnx = snx * inv_c, cny = sny * inv_c;
+            const float kk = depth_only ? 0.f : sid * inv_c;
+            const float k1x = kk * sb1x, k1y = kk * sb1y, k2x = kk * sb2x, k2y = kk * sb2y;
+            const float q1 = kk * fmaf(sb1x, srsx, fmaf(sb1y, srsy, sb1z));
+            const float q2 = kk * fmaf(sb2x, srsx, fmaf(sb2y, srsy, sb2z));
             float ph[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             float pnv = 0.f, pcs = 0.f;
             for (int j = 0; j < nslots; ++j) {
@@ -2121,23 +2128,19 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
                 const float ikf = packed ? slot_value<T>(pk) * kf_scale : s_val[wave][packed ? 0 : j][lane];
                 const bool pv = hl + LANES * j < d.total;
                 const float drx = (bdx + fox) * ifx, dry = (bdy + foy) * ify;
-                const float sigma = (snx * drx + sny * dry) * inv_c;
+                const float sigma = fmaf(cny, dry, cnx * drx);
                 const float idu = fmaf(sid, sigma, sid);
-                const float dx3 = fmaf(-sigma, srsx, drx);
-                const float dy3 = fmaf(-sigma, srsy, dry);
-                const float dz3 = -sigma;
-                const float kk = sid * inv_c;
                 const float g0 = 1.f + sigma;
-                const float g1 = depth_only ? 0.f : kk * (sb1x * dx3 + sb1y * dy3 + sb1z * dz3);
-                const float g2 = depth_only ? 0.f : kk * (sb2x * dx3 + sb2y * dy3 + sb2z * dz3);
+                const float g1 = fmaf(-sigma, q1, fmaf(k1y, dry, k1x * drx));
+                const float g2 = fmaf(-sigma, q2, fmaf(k2y, dry, k2x * drx));
                 const bool pix_ok = salive && pv && (idu > 0.f);
                 float A = 0.f, B = 0.f, cst = 0.f;
                 int nvl = 0;
                 if (last || lm)
-                    frame_loop<T, true, false>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes, wm1, hm1,
+                    frame_loop<T, true, BY_ROW>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes, wm1, hm1,
                                         ikf, hk, img_scale, A, B, cst, nvl);
                 else
-                    frame_loop<T, false, false>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes, wm1, hm1,
+                    frame_loop<T, false, BY_ROW>(pairs, fr, nf, bdx, bdy, idu, pix_ok, pitch_b, img_bytes, wm1, hm1,
                                          ikf, hk, img_scale, A, B, cst, nvl);
                 {
                     const float ag0 = A * g0, ag1 = A * g1, ag2 = A * g2;
@@ -2205,9 +2208,9 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
                     const float ikf = packed ? slot_value<T>(pk) * kf_scale : s_val[wave][packed ? 0 : j][lane];
                     const bool pv = hl + LANES * j < d.total;
                     const float drx = (bdx + fox) * ifx, dry = (bdy + foy) * ify;
-                    const float sig = (sa.y * drx + sa.z * dry) * inv_c;
+                    const float sig = fmaf(sa.z * inv_c, dry, (sa.y * inv_c) * drx);
                     const float idu_c = fmaf(sa.x, sig, sa.x);
-                    frame_cost<T, false>(pairs, fr, nf, bdx, bdy, idu_c, calive && pv && (idu_c > 0.f), pitch_b,
+                    frame_cost<T, BY_ROW>(pairs, fr, nf, bdx, bdy, idu_c, calive && pv && (idu_c > 0.f), pitch_b,
                                   img_bytes, wm1, hm1, ikf, hk, img_scale, cst2, nv2l);
                 }
                 const float c2 = group_sum<LANES>(cst2);
@@ -2684,16 +2687,22 @@ hipError_t launch_disc_transfer(const DiscTransferArgs* table, int n_pairs, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_disc_gn(int dtype, const BatchHeader* hdr, int total_items, hipStream_t s) {
+template <bool R>
+static void launch_disc_gn_rows(int dtype, const BatchHeader* hdr, int total_items, dim3 grid, hipStream_t s) {
+    if (dtype == 0)
+        disc_gn_kernel<float, disc_surfels_per_wave(0), R><<<grid, kBlockThreads, 0, s>>>(hdr, total_items);
+    else if (dtype == 1)
+        disc_gn_kernel<_Float16, disc_surfels_per_wave(1), R><<<grid, kBlockThreads, 0, s>>>(hdr, total_items);
+    else
+        disc_gn_kernel<uint8_t, disc_surfels_per_wave(2), R><<<grid, kBlockThreads, 0, s>>>(hdr, total_items);
+}
+
+hipError_t launch_disc_gn(int dtype, const BatchHeader* hdr, int total_items, bool by_row, hipStream_t s) {
     if (total_items <= 0) return hipSuccess;
     const int waves = kBlockThreads / kWaveSize;
     const dim3 grid((total_items + waves - 1) / waves);
-    if (dtype == 0)
-        disc_gn_kernel<float, disc_surfels_per_wave(0)><<<grid, kBlockThreads, 0, s>>>(hdr, total_items);
-    else if (dtype == 1)
-        disc_gn_kernel<_Float16, disc_surfels_per_wave(1)><<<grid, kBlockThreads, 0, s>>>(hdr, total_items);
-    else
-        disc_gn_kernel<uint8_t, disc_surfels_per_wave(2)><<<grid, kBlockThreads, 0, s>>>(hdr, total_items);
+    if (by_row) launch_disc_gn_rows<true>(dtype, hdr, total_items, grid, s);
+    else launch_disc_gn_rows<false>(dtype, hdr, total_items, grid, s);
     return hipGetLastError();
 }
 
