@@ -18,6 +18,7 @@ the whole keyframe step with the empty-area search), and serving latency.
 from __future__ import annotations
 
 import argparse
+import ctypes as C
 import json
 import os
 import sys
@@ -147,9 +148,14 @@ def transfer_leg(ctx, kfs, dks):
     idx_ptrs = [t.data_ptr() for t in src_idx]
 
     ws = ctx.workspace(sg.sgn_transfer_workspace_bytes(grids))
+    # the call's argument arrays, built once (a C caller holds them as arrays)
+    a_grids, a_srcs, a_poses = sg.c_array(sg.sgn_grid, grids), sg.c_array(sg.sgn_surfels, srcs), \
+        sg.c_array(sg.sgn_pose, poses)
+    a_dsts, a_new, a_idx = sg.c_array(sg.sgn_surfels, dcs), sg.c_array(C.c_void_p, new_ptrs), \
+        sg.c_array(C.c_void_p, idx_ptrs)
 
     def run():
-        sg.sgn_transfer_surfels_batch(ctx.handle, grids, srcs, poses, grids, dcs, new_ptrs, idx_ptrs, ws)
+        sg.sgn_transfer_surfels_batch(ctx.handle, a_grids, a_srcs, a_poses, a_grids, a_dsts, a_new, a_idx, ws)
 
     # bytes per surfel: the source state read (id, normal, flags: 20 B), the
     # destination tile written (state 32 B, is_new 1 B, source index 4 B)
@@ -282,8 +288,13 @@ def disc_leg(ctx, kfs, storage, iters, steps, with_ablation):
     tcap = [t.numel() for t in tux]
     tcnt_ptrs = [t.data_ptr() for t in tcnt]
 
+    # the call's argument arrays, built once (a C caller holds them as arrays)
+    a_src, a_poses, a_dst = sg.c_array(sg.sgn_disc_item, tsrc), sg.c_array(sg.sgn_pose, tposes), \
+        sg.c_array(sg.sgn_disc_item, tdst)
+    a_cap, a_cnt = sg.c_array(C.c_int32, tcap), sg.c_array(C.c_void_p, tcnt_ptrs)
+
     def transfer():
-        sg.sgn_disc_transfer_batch(ctx.handle, tsrc, tposes, tdst, tcap, tcnt_ptrs)
+        sg.sgn_disc_transfer_batch(ctx.handle, a_src, a_poses, a_dst, a_cap, a_cnt)
 
     out["transfer"] = time_transfer(transfer, sum(d.count for d in dks),
                                     lambda: int(torch.stack(tcnt)[:, 0].sum()),

@@ -954,7 +954,7 @@ static sgn_status transfer_impl(sgn_ctx* c, int32_t n, const sgn_grid* src_grids
     if (n < 1 || !src_grids || !srcs || !poses || !dst_grids || !dsts || !dst_is_new)
         return fail(SGN_E_INVALID, "empty batch or null argument");
     if (n > SGN_MAX_BATCH) return fail(SGN_E_UNSUPPORTED, "more keyframe pairs than SGN_MAX_BATCH");
-    int64_t total_src = 0, total_dst = 0;
+    int64_t total_src = 0, total_dst = 0, src_waves = 0, dst_waves = 0;
     for (int k = 0; k < n; ++k) {
         const sgn_grid* src_grid = &src_grids[k];
         const sgn_grid* dst_grid = &dst_grids[k];
@@ -993,10 +993,16 @@ static sgn_status transfer_impl(sgn_ctx* c, int32_t n, const sgn_grid* src_grids
         a.dst_w = dst_grid->width; a.dst_h = dst_grid->height; a.dst_patch = dst_grid->patch;
         a.is_new = dst_is_new[k];
         a.src_index = dst_src_index ? dst_src_index[k] : nullptr;
-        a.src_base = (int32_t)total_src;
         a.dst_base = (int32_t)total_dst;
-        total_src += (int64_t)(src_grid->width / src_grid->patch) * (src_grid->height / src_grid->patch);
-        total_dst += (int64_t)(dst_grid->width / dst_grid->patch) * (dst_grid->height / dst_grid->patch);
+        a.src_count = (src_grid->width / src_grid->patch) * (src_grid->height / src_grid->patch);
+        a.dst_count = (dst_grid->width / dst_grid->patch) * (dst_grid->height / dst_grid->patch);
+        // each pair starts a wavefront of its own (64 lanes)
+        a.src_wave = (int32_t)src_waves;
+        a.dst_wave = (int32_t)dst_waves;
+        total_src += a.src_count;
+        total_dst += a.dst_count;
+        src_waves += (a.src_count + 63) / 64;
+        dst_waves += (a.dst_count + 63) / 64;
         if (total_src > INT32_MAX / 2 || total_dst > INT32_MAX / 2)
             return fail(SGN_E_UNSUPPORTED, "too many surfels in one batch");
     }
@@ -1015,7 +1021,7 @@ static sgn_status transfer_impl(sgn_ctx* c, int32_t n, const sgn_grid* src_grids
     }
     st = upload_array(c, tab, n);
     if (st) return st;
-    hipError_t e = launch_regrid((const RegridArgs*)c->dev_table, n, (int)total_src, (int)total_dst, c->stream);
+    hipError_t e = launch_regrid((const RegridArgs*)c->dev_table, n, (int)src_waves, (int)dst_waves, c->stream);
     if (e != hipSuccess) return hip_fail(e, "re-gridding launch");
     return SGN_OK;
 }

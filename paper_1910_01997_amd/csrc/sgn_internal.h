@@ -143,7 +143,9 @@ struct RegridArgs {
     int32_t* win;                // winning source index per destination tile
     uint8_t* is_new;
     int32_t* src_index;          // may be null
-    int32_t src_base, dst_base;  // source surfels / destination tiles of the table's earlier pairs
+    int32_t dst_base;              // destination tiles of the table's earlier pairs (best, win offsets)
+    int32_t src_count, dst_count;  // this pair's source surfels / destination tiles
+    int32_t src_wave, dst_wave;    // this pair's first 64-lane wavefront over sources / tiles
 };
 
 // Launchers implemented in sgn_kernels.hip.  All return hipError_t of the
@@ -154,11 +156,15 @@ hipError_t launch_init(const BatchHeader* hdr, int grid, hipStream_t s);
 hipError_t launch_render(const BatchHeader* hdr, int grid, hipStream_t s);
 hipError_t launch_gn(const GnVariant& v, const BatchHeader* hdr, uint32_t* counters,
                      int persistent, int grid_blocks, hipStream_t s);
-// Re-gridding of a device table of n_pairs keyframe pairs.
 // Device address of the static scratch array on `device` (which must be the
 // current device), looked up on the first call for that device and kept.
 hipError_t static_scratch_on(int device, void** out);
-hipError_t launch_regrid(const RegridArgs* table, int n_pairs, int total_src, int total_dst,
+// Re-gridding of a device table of n_pairs keyframe pairs.  A wavefront
+// never spans two pairs: pair k's sources run over the
+// wavefronts from src_wave on (surfel i at lane i % 64 of wavefront
+// src_wave + i / 64), likewise its tiles from dst_wave; src_waves and
+// dst_waves are the totals.
+hipError_t launch_regrid(const RegridArgs* table, int n_pairs, int src_waves, int dst_waves,
                          hipStream_t s);
 
 // Disc surfels (Eq. 4).

@@ -1635,44 +1635,51 @@ __device__ __forceinline__ bool regrid_land(const RegridArgs& a, int i, Land& L)
     return true;
 }
 
-// The re-gridding kernels run over a table of keyframe pairs: source
-// surfels and destination tiles are numbered pair after pair (src_base,
-// dst_base); the entry owning number g is the last whose base is <= g.
-__device__ __forceinline__ int regrid_entry_of_src(const RegridArgs* tab, int n, int g) {
+// The re-gridding kernels run over a table of keyframe pairs in wavefronts
+// of 64 lanes that never span two pairs: pair k's sources (destination
+// tiles) take the wavefronts from src_wave (dst_wave) on, so the entry is
+// the last whose first wavefront is <= the wavefront's number.  It is found
+// and read with wavefront-uniform (scalar) loads.
+template <bool DST>
+__device__ __forceinline__ int regrid_entry_of_wave(const RegridArgs* __restrict__ tab, int n, int wv) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (tab[mid].src_base <= g) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-__device__ __forceinline__ int regrid_entry_of_dst(const RegridArgs* tab, int n, int g) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tab[mid].dst_base <= g) lo = mid; else hi = mid - 1;
+        if ((DST ? tab[mid].dst_wave : tab[mid].src_wave) <= wv) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
 
-__global__ void regrid_clear_kernel(const RegridArgs* __restrict__ tab, int n_pairs, int total_dst) {
-    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total_dst; g += gridDim.x * blockDim.x) {
-        const RegridArgs& a = tab[regrid_entry_of_dst(tab, n_pairs, g)];
-        const int j = g - a.dst_base;
-        a.best[j] = 0ull;
-        a.win[j] = 0x7fffffff;
+// The wavefront's number among the grid's (four wavefronts per workgroup),
+// uniform for the compiler, and the grid's count of wavefronts.
+__device__ __forceinline__ int grid_wave() {
+    return __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+}
+__device__ __forceinline__ int grid_waves() { return (int)gridDim.x * 4; }
+
+__global__ __launch_bounds__(256) void regrid_clear_kernel(const RegridArgs* __restrict__ tab, int n_pairs,
+                                                           int dst_waves) {
+    const int lane = threadIdx.x & 63;
+    for (int wv = grid_wave(); wv < dst_waves; wv += grid_waves()) {
+        const RegridArgs& a = tab[regrid_entry_of_wave<true>(tab, n_pairs, wv)];
+        const int j = (wv - a.dst_wave) * 64 + lane;
+        if (j < a.dst_count) {
+            a.best[j] = 0ull;
+            a.win[j] = 0x7fffffff;
+        }
     }
 }
 
 // pass 0: closest landing per tile (1/p'_z > 0, so its bits order like the
 // value); pass 1: the lowest source index among the closest
-__global__ void regrid_scatter_kernel(const RegridArgs* __restrict__ tab, int n_pairs, int total_src,
-                                      int pass) {
-    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total_src; g += gridDim.x * blockDim.x) {
-        const RegridArgs& a = tab[regrid_entry_of_src(tab, n_pairs, g)];
-        const int i = g - a.src_base;
+__global__ __launch_bounds__(256) void regrid_scatter_kernel(const RegridArgs* __restrict__ tab, int n_pairs,
+                                                             int src_waves, int pass) {
+    const int lane = threadIdx.x & 63;
+    for (int wv = grid_wave(); wv < src_waves; wv += grid_waves()) {
+        const RegridArgs& a = tab[regrid_entry_of_wave<false>(tab, n_pairs, wv)];
+        const int i = (wv - a.src_wave) * 64 + lane;
         Land L;
-        if (!regrid_land(a, i, L)) continue;
+        if (i >= a.src_count || !regrid_land(a, i, L)) continue;
         const unsigned long long bits = (unsigned long long)__double_as_longlong(L.idp);
         if (pass == 0)
             atomicMax(&a.best[L.tile], bits);
@@ -1681,11 +1688,14 @@ __global__ void regrid_scatter_kernel(const RegridArgs* __restrict__ tab, int n_
     }
 }
 
-__global__ void regrid_gather_kernel(const RegridArgs* __restrict__ tab, int n_pairs, int total_dst) {
+__global__ __launch_bounds__(256) void regrid_gather_kernel(const RegridArgs* __restrict__ tab, int n_pairs,
+                                                            int dst_waves) {
 #pragma clang fp contract(off)
-    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total_dst; g += gridDim.x * blockDim.x) {
-        const RegridArgs& a = tab[regrid_entry_of_dst(tab, n_pairs, g)];
-        const int j = g - a.dst_base;
+    const int lane = threadIdx.x & 63;
+    for (int wv = grid_wave(); wv < dst_waves; wv += grid_waves()) {
+        const RegridArgs& a = tab[regrid_entry_of_wave<true>(tab, n_pairs, wv)];
+        const int j = (wv - a.dst_wave) * 64 + lane;
+        if (j >= a.dst_count) continue;
         const int S1 = a.dst_patch, gw1 = a.dst_w / S1;
         const int w = a.win[j];
         bool ok = false;
@@ -1718,19 +1728,20 @@ __global__ void regrid_gather_kernel(const RegridArgs* __restrict__ tab, int n_p
     }
 }
 
-hipError_t launch_regrid(const RegridArgs* table, int n_pairs, int total_src, int total_dst,
+hipError_t launch_regrid(const RegridArgs* table, int n_pairs, int src_waves, int dst_waves,
                          hipStream_t s) {
-    auto blocks = [](int n) { return std::max(1, std::min(65536, (n + 255) / 256)); };
-    hipLaunchKernelGGL(regrid_clear_kernel, dim3(blocks(total_dst)), dim3(256), 0, s, table, n_pairs,
-                       total_dst);
-    if (total_src > 0) {
-        hipLaunchKernelGGL(regrid_scatter_kernel, dim3(blocks(total_src)), dim3(256), 0, s, table, n_pairs,
-                           total_src, 0);
-        hipLaunchKernelGGL(regrid_scatter_kernel, dim3(blocks(total_src)), dim3(256), 0, s, table, n_pairs,
-                           total_src, 1);
+    // four wavefronts per workgroup
+    auto blocks = [](int waves) { return std::max(1, std::min(65536, (waves + 3) / 4)); };
+    hipLaunchKernelGGL(regrid_clear_kernel, dim3(blocks(dst_waves)), dim3(256), 0, s, table, n_pairs,
+                       dst_waves);
+    if (src_waves > 0) {
+        hipLaunchKernelGGL(regrid_scatter_kernel, dim3(blocks(src_waves)), dim3(256), 0, s, table, n_pairs,
+                           src_waves, 0);
+        hipLaunchKernelGGL(regrid_scatter_kernel, dim3(blocks(src_waves)), dim3(256), 0, s, table, n_pairs,
+                           src_waves, 1);
     }
-    hipLaunchKernelGGL(regrid_gather_kernel, dim3(blocks(total_dst)), dim3(256), 0, s, table, n_pairs,
-                       total_dst);
+    hipLaunchKernelGGL(regrid_gather_kernel, dim3(blocks(dst_waves)), dim3(256), 0, s, table, n_pairs,
+                       dst_waves);
     return hipGetLastError();
 }
 

@@ -305,20 +305,35 @@ def sgn_transfer_workspace_bytes(dst_grids: Sequence[sgn_grid]) -> int:
     return int(lib().sgn_transfer_workspace_bytes(n, (sgn_grid * n)(*dst_grids)))
 
 
+def c_array(T, xs):
+    """xs as a ctypes array of T: returned as it is when it already is one
+    (so a caller that calls with the same arguments many times can build
+    them once), else built from the sequence.  Integers of a c_void_p array
+    may be None (a null pointer)."""
+    if isinstance(xs, C.Array) and getattr(xs, "_type_", None) is T:
+        return xs
+    if T is C.c_void_p:
+        xs = [int(p) if p else None for p in xs]
+    elif T is C.c_int32:
+        xs = [int(v) for v in xs]
+    return (T * len(xs))(*xs)
+
+
 def sgn_transfer_surfels_batch(ctx, src_grids: Sequence[sgn_grid], srcs: Sequence[sgn_surfels],
                                poses: Sequence[sgn_pose], dst_grids: Sequence[sgn_grid],
                                dsts: Sequence[sgn_surfels], dst_is_new_ptrs: Sequence[int],
                                dst_src_index_ptrs: Optional[Sequence[int]], ws):
-    """ws: (device pointer, bytes), at least sgn_transfer_workspace_bytes(dst_grids)."""
+    """ws: (device pointer, bytes), at least sgn_transfer_workspace_bytes(dst_grids).
+    Each sequence may also be a ctypes array of its type (see c_array)."""
     n = len(srcs)
-    arr = lambda T, xs: (T * n)(*xs)
-    idx = (arr(C.c_void_p, [int(p) if p else None for p in dst_src_index_ptrs])
-           if dst_src_index_ptrs is not None else None)
-    check(lib().sgn_transfer_surfels_batch(C.c_void_p(ctx), n, arr(sgn_grid, src_grids), arr(sgn_surfels, srcs),
-                                           arr(sgn_pose, poses), arr(sgn_grid, dst_grids),
-                                           arr(sgn_surfels, dsts),
-                                           arr(C.c_void_p, [int(p) for p in dst_is_new_ptrs]), idx,
-                                           C.c_void_p(ws[0]), C.c_size_t(ws[1])),
+    args = [c_array(sgn_grid, src_grids), c_array(sgn_surfels, srcs), c_array(sgn_pose, poses),
+            c_array(sgn_grid, dst_grids), c_array(sgn_surfels, dsts), c_array(C.c_void_p, dst_is_new_ptrs)]
+    if any(len(x) != n for x in args):
+        raise ValueError("sgn_transfer_surfels_batch: sequences of different lengths")
+    idx = c_array(C.c_void_p, dst_src_index_ptrs) if dst_src_index_ptrs is not None else None
+    if idx is not None and len(idx) != n:
+        raise ValueError("sgn_transfer_surfels_batch: sequences of different lengths")
+    check(lib().sgn_transfer_surfels_batch(C.c_void_p(ctx), n, *args, idx, C.c_void_p(ws[0]), C.c_size_t(ws[1])),
           "sgn_transfer_surfels_batch")
 
 
@@ -375,13 +390,12 @@ def sgn_disc_transfer_batch(ctx, srcs: Sequence[sgn_disc_item], poses: Sequence[
                             dsts: Sequence[sgn_disc_item], capacities: Sequence[int],
                             counts_ptrs: Sequence[int], src_index_ptrs: Optional[Sequence[int]] = None):
     n = len(srcs)
-    arr = lambda T, xs: (T * n)(*xs)
-    idx = (arr(C.c_void_p, [int(p) if p else None for p in src_index_ptrs])
-           if src_index_ptrs is not None else None)
-    check(lib().sgn_disc_transfer_batch(C.c_void_p(ctx), n, arr(sgn_disc_item, srcs), arr(sgn_pose, poses),
-                                        arr(sgn_disc_item, dsts), arr(C.c_int32, [int(c) for c in capacities]),
-                                        arr(C.c_void_p, [int(p) for p in counts_ptrs]), idx),
-          "sgn_disc_transfer_batch")
+    args = [c_array(sgn_disc_item, srcs), c_array(sgn_pose, poses), c_array(sgn_disc_item, dsts),
+            c_array(C.c_int32, capacities), c_array(C.c_void_p, counts_ptrs)]
+    idx = c_array(C.c_void_p, src_index_ptrs) if src_index_ptrs is not None else None
+    if any(len(x) != n for x in args) or (idx is not None and len(idx) != n):
+        raise ValueError("sgn_disc_transfer_batch: sequences of different lengths")
+    check(lib().sgn_disc_transfer_batch(C.c_void_p(ctx), n, *args, idx), "sgn_disc_transfer_batch")
 
 
 def sgn_disc_render_batch(ctx, items, n: int, inv_depth_ptrs: Sequence[int],

@@ -204,8 +204,9 @@ def test_keyframe_switch_chain_matches_oracle(ctx):
 
 def test_regrid_batch_equals_one_by_one(ctx):
     """The batched re-gridding (four pairs with different destination grids
-    in one call, one of them without a source-index output) equals the calls
-    one by one, bitwise, and the first pair the oracle."""
+    in one call, one of them without a source-index output; two of them
+    with a ragged last wavefront of tiles) equals the calls one by one,
+    bitwise, and every pair the oracle."""
     from paper_1910_01997_amd import surfgn as sg
     print("case regrid batch of four pairs", flush=True)
     src_grid = ((600.0, 600.0, 320.0, 240.0), 640, 480, 4)
@@ -251,6 +252,9 @@ def test_regrid_batch_equals_one_by_one(ctx):
             assert np.array_equal(wins[k].cpu().numpy(), win1)
         else:
             assert np.all(wins[k].cpu().numpy() == -5)           # not written
-    c = cases[0]
-    _check(dsts[0].to_host(), news[0].cpu().numpy(), wins[0].cpu().numpy(),
-           _oracle(src_grid, c[0], c[1], c[2], c[3], c[4], c[5], c[6]))
+    for k, c in enumerate(cases):
+        ref = _oracle(src_grid, c[0], c[1], c[2], c[3], c[4], c[5], c[6])
+        if k == 2:                       # no source-index output: its single call, equal to it above
+            _check(*singles[k], ref)
+        else:
+            _check(dsts[k].to_host(), news[k].cpu().numpy(), wins[k].cpu().numpy(), ref)
