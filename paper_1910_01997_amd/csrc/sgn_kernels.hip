@@ -2623,68 +2623,91 @@ __global__ __launch_bounds__(kWaveSize) void disc_init_kernel(const DiscPlaceArg
 // n' = R n and is re-centred at u' = K_dst pi(p'), inverse depth 1/p'_z.
 // Those with p'_z > 0 and u' in [0, W-1] x [0, H-1] are written in source
 // order (as many as there is room for).  One workgroup walks the sources in
-// chunks; every landing is computed in double in the oracle's order, so the
-// kept set and the order are the same.
+// passes of kDiscXferSub chunks of 1024 (a thread's kDiscXferSub landings
+// are independent, so their loads and double arithmetic overlap), ranks the
+// pass's landings in source order with one scan over (chunk, wavefront)
+// and writes them; every landing is computed in double in the oracle's
+// order, so the kept set and the order are the same.
+constexpr int kDiscXferSub = 4;
 __global__ __launch_bounds__(1024) void disc_transfer_kernel(const DiscTransferArgs* __restrict__ tab) {
 #pragma clang fp contract(off)
     const DiscTransferArgs& a = tab[blockIdx.x];          // one workgroup per keyframe pair
-    __shared__ int s_wave[1024 / kWaveSize + 1];
+    constexpr int kWaves = 1024 / kWaveSize;
+    constexpr int kSlots = kDiscXferSub * kWaves;         // (chunk, wavefront) in source order
+    static_assert(kSlots <= kWaveSize, "one wavefront scans the slots");
+    __shared__ int s_cnt[kSlots + 1];
     const int lane = threadIdx.x & (kWaveSize - 1);
     const int wave = threadIdx.x >> 6;
-    constexpr int kWaves = 1024 / kWaveSize;
     int base = 0;
-    for (int c0 = 0; c0 < a.count; c0 += 1024) {
-        const int k = c0 + (int)threadIdx.x;
-        bool land = false;
-        double u = 0.0, v = 0.0, idn = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
-        if (k < a.count && !(a.flags[k] & (F_DEGENERATE | F_UNINIT)) && a.inv_depth[k] > 0.f) {
-            const double ids = a.inv_depth[k];
-            const double rs0 = ((double)a.ux[k] - a.sK[2]) / a.sK[0];
-            const double rs1 = ((double)a.uy[k] - a.sK[3]) / a.sK[1];
-            const double p0 = rs0 / ids, p1 = rs1 / ids, p2 = 1.0 / ids;
-            const double n0 = a.nx[k], n1 = a.ny[k], n2 = a.nz[k];
-            const double q0 = a.R[0] * p0 + a.R[1] * p1 + a.R[2] * p2 + a.t[0];
-            const double q1 = a.R[3] * p0 + a.R[4] * p1 + a.R[5] * p2 + a.t[1];
-            const double q2 = a.R[6] * p0 + a.R[7] * p1 + a.R[8] * p2 + a.t[2];
-            m0 = a.R[0] * n0 + a.R[1] * n1 + a.R[2] * n2;
-            m1 = a.R[3] * n0 + a.R[4] * n1 + a.R[5] * n2;
-            m2 = a.R[6] * n0 + a.R[7] * n1 + a.R[8] * n2;
-            if (q2 > 0.0) {
-                u = a.dK[0] * (q0 / q2) + a.dK[2];
-                v = a.dK[1] * (q1 / q2) + a.dK[3];
-                land = u >= 0.0 && u <= (double)(a.dst_w - 1) && v >= 0.0 && v <= (double)(a.dst_h - 1);
-                idn = 1.0 / q2;
+    for (int c0 = 0; c0 < a.count; c0 += 1024 * kDiscXferSub) {
+        bool land[kDiscXferSub];
+        float fu[kDiscXferSub], fv[kDiscXferSub], fid[kDiscXferSub];
+        float f0[kDiscXferSub], f1[kDiscXferSub], f2[kDiscXferSub];
+        int below[kDiscXferSub];
+#pragma unroll
+        for (int j = 0; j < kDiscXferSub; ++j) {
+            const int k = c0 + j * 1024 + (int)threadIdx.x;
+            land[j] = false;
+            double u = 0.0, v = 0.0, idn = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
+            if (k < a.count && !(a.flags[k] & (F_DEGENERATE | F_UNINIT)) && a.inv_depth[k] > 0.f) {
+                const double ids = a.inv_depth[k];
+                const double rs0 = ((double)a.ux[k] - a.sK[2]) / a.sK[0];
+                const double rs1 = ((double)a.uy[k] - a.sK[3]) / a.sK[1];
+                const double p0 = rs0 / ids, p1 = rs1 / ids, p2 = 1.0 / ids;
+                const double n0 = a.nx[k], n1 = a.ny[k], n2 = a.nz[k];
+                const double q0 = a.R[0] * p0 + a.R[1] * p1 + a.R[2] * p2 + a.t[0];
+                const double q1 = a.R[3] * p0 + a.R[4] * p1 + a.R[5] * p2 + a.t[1];
+                const double q2 = a.R[6] * p0 + a.R[7] * p1 + a.R[8] * p2 + a.t[2];
+                m0 = a.R[0] * n0 + a.R[1] * n1 + a.R[2] * n2;
+                m1 = a.R[3] * n0 + a.R[4] * n1 + a.R[5] * n2;
+                m2 = a.R[6] * n0 + a.R[7] * n1 + a.R[8] * n2;
+                if (q2 > 0.0) {
+                    u = a.dK[0] * (q0 / q2) + a.dK[2];
+                    v = a.dK[1] * (q1 / q2) + a.dK[3];
+                    land[j] = u >= 0.0 && u <= (double)(a.dst_w - 1) && v >= 0.0 && v <= (double)(a.dst_h - 1);
+                    idn = 1.0 / q2;
+                }
+            }
+            // the stored values (rounded to float here rather than at the store)
+            fu[j] = (float)u; fv[j] = (float)v; fid[j] = (float)idn;
+            f0[j] = (float)m0; f1[j] = (float)m1; f2[j] = (float)m2;
+            const unsigned long long ball = __ballot(land[j]);
+            below[j] = __popcll(ball & ((1ull << lane) - 1ull));
+            if (lane == 0) s_cnt[j * kWaves + wave] = __popcll(ball);
+        }
+        __syncthreads();
+        if (wave == 0) {
+            // exclusive scan of the slot counts (slot = lane), total in s_cnt[kSlots]
+            const int c = lane < kSlots ? s_cnt[lane] : 0;
+            int incl = c;
+#pragma unroll
+            for (int d = 1; d < kWaveSize; d <<= 1) {
+                const int t = __shfl_up(incl, d);
+                if (lane >= d) incl += t;
+            }
+            if (lane < kSlots) s_cnt[lane] = incl - c;
+            if (lane == kWaveSize - 1) s_cnt[kSlots] = incl;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kDiscXferSub; ++j) {
+            const int k = c0 + j * 1024 + (int)threadIdx.x;
+            const int rank = base + s_cnt[j * kWaves + wave] + below[j];
+            if (land[j] && rank < a.capacity) {
+                a.dst.inv_depth[rank] = fid[j];
+                a.dst.nx[rank] = f0[j];
+                a.dst.ny[rank] = f1[j];
+                a.dst.nz[rank] = f2[j];
+                a.dst.flags[rank] = 0u;
+                a.dst.cost[rank] = 0.f;
+                a.dst.nvalid[rank] = 0u;
+                a.dst.last_update[rank] = a.last_update[k];
+                a.dux[rank] = fu[j];
+                a.duy[rank] = fv[j];
+                if (a.src_index) a.src_index[rank] = k;
             }
         }
-        const unsigned long long ball = __ballot(land);
-        const int below = __popcll(ball & ((1ull << lane) - 1ull));
-        if (lane == 0) s_wave[wave] = __popcll(ball);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int acc = 0;
-            for (int w = 0; w < kWaves; ++w) {
-                const int t = s_wave[w];
-                s_wave[w] = acc;
-                acc += t;
-            }
-            s_wave[kWaves] = acc;
-        }
-        __syncthreads();
-        const int rank = base + s_wave[wave] + below;
-        if (land && rank < a.capacity) {
-            a.dst.inv_depth[rank] = (float)idn;
-            a.dst.nx[rank] = (float)m0;
-            a.dst.ny[rank] = (float)m1;
-            a.dst.nz[rank] = (float)m2;
-            a.dst.flags[rank] = 0u;
-            a.dst.cost[rank] = 0.f;
-            a.dst.nvalid[rank] = 0u;
-            a.dst.last_update[rank] = a.last_update[k];
-            a.dux[rank] = (float)u;
-            a.duy[rank] = (float)v;
-            if (a.src_index) a.src_index[rank] = k;
-        }
-        base += s_wave[kWaves];
+        base += s_cnt[kSlots];
         __syncthreads();
     }
     if (threadIdx.x == 0) {

@@ -299,6 +299,55 @@ def test_disc_transfer_matches_oracle_exactly(ctx):
         assert np.all(dh["flags"] == 0) and np.array_equal(dh["last_update"], out["last_update"])
 
 
+def test_disc_transfer_many_surfels_matches_oracle_exactly(ctx):
+    """More sources than one pass of the transfer workgroup (9,500, over
+    4 x 1024 per pass), unusable ones among them (degenerate, uninitialised,
+    zero or negative inverse depth); room for all, and room that runs out
+    inside the first and inside the second pass: the written set, its order
+    and its values equal the oracle's exactly."""
+    sg, engine = _mods()
+    kf, _ = _scene(width=1280, height=720, seed=79)
+    print("case disc transfer 1280x720, 9500 synthetic sources", flush=True)
+    rng = np.random.default_rng(79)
+    m = 9500
+    ux = rng.uniform(0.0, 1279.0, m).astype(np.float32)
+    uy = rng.uniform(0.0, 719.0, m).astype(np.float32)
+    ids = rng.uniform(0.2, 1.0, m).astype(np.float32)
+    ids[rng.choice(m, 60, replace=False)] = 0.0
+    ids[rng.choice(m, 60, replace=False)] = -0.5
+    g = rng.normal(size=(m, 3)) * [0.3, 0.3, 1.0]
+    g[:, 2] = -np.abs(g[:, 2])
+    ns = (g / np.linalg.norm(g, axis=1, keepdims=True)).astype(np.float32)
+    flags = np.zeros(m, np.uint32)
+    flags[rng.choice(m, 300, replace=False)] |= oracle.DEGENERATE
+    flags[rng.choice(m, 300, replace=False)] |= oracle.UNINIT
+    src = engine.DiscKeyframe(ctx, kf.kf_image, kf.nbr_images, kf.R, kf.t, kf.K, 10.0, ux, uy, ids, ns,
+                              flags=flags)
+    src.state.last_update.copy_(torch.as_tensor(rng.integers(1, 1000, m).astype(np.int32), device="cuda"))
+    img1, nb1, R1, t1 = _as_keyframe_of(kf, 0)
+    h = src.state_host()
+    st = oracle_state(h["inv_depth"], h["n"], h["flags"])
+    st["last_update"][:] = h["last_update"]
+    for cap in (m + 10, 2500, 6000):
+        dst = engine.DiscKeyframe(ctx, img1, nb1, R1, t1, kf.K, 10.0, np.zeros(0, np.float32),
+                                  np.zeros(0, np.float32), np.zeros(0, np.float32), np.zeros((0, 3), np.float32),
+                                  capacity=cap)
+        sidx = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+        written, landed = dst.transfer_from(src, kf.R[0], kf.t[0], src_index=sidx)
+        torch.cuda.synchronize()
+        out, (ox, oy), oidx, o_landed = oracle.disc_transfer(kf.K, kf.K, (1280, 720), kf.R[0], kf.t[0], st,
+                                                             ux.astype(np.float64), uy.astype(np.float64),
+                                                             capacity=cap)
+        assert landed == o_landed and written == min(cap, landed) and landed > 6000, (cap, landed, o_landed)
+        assert np.array_equal(sidx.cpu().numpy()[:written], oidx)
+        dh = dst.state_host()
+        dx, dy = dst.centres()
+        assert np.array_equal(dx, ox.astype(np.float32)) and np.array_equal(dy, oy.astype(np.float32))
+        assert np.array_equal(dh["inv_depth"], out["inv_depth"].astype(np.float32))
+        assert np.array_equal(dh["n"], np.stack([out["nx"], out["ny"], out["nz"]], 1).astype(np.float32))
+        assert np.all(dh["flags"] == 0) and np.array_equal(dh["last_update"], out["last_update"])
+
+
 def test_disc_transfer_batch_equals_one_by_one(ctx):
     """Batched Eq. 10 for discs (three pairs in one launch, one with less
     room than it needs, one without a source-index output) equals the calls
