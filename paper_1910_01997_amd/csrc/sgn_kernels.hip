@@ -381,7 +381,7 @@ __device__ __forceinline__ bool solve3_fp64(double h00, double h01, double h02, 
 // the same words for a surfel.
 constexpr int kPairWords = 12;
 enum : int {
-    W_HX0 = 0, W_HX1, W_KX, W_EX, W_HY0, W_HY1, W_KY, W_EY, W_QZ, W_X0, W_Y0, W_B0
+    W_HX0 = 0, W_HX1, W_KX, W_EX, W_HY0, W_HY1, W_KY, W_EY, W_QZ, W_X0, W_Y0, W_HZ1
 };
 // The pair words of every neighbour frame for the anchor point (qbx, qby),
 // one frame per lane (lanes below nf), formed in double and rounded once,
@@ -412,7 +412,7 @@ __device__ __forceinline__ void stage_pair_words(const FrameDev* frames, int nf,
         w[W_QZ] = (float)Qz;
         w[W_X0] = __int_as_float((int)X0);
         w[W_Y0] = __int_as_float((int)Y0);
-        w[W_B0] = 0.f;
+        w[W_HZ1] = (float)hm[7];     // h7 again, beside the words the pixel step reads
     }
 }
 
@@ -686,16 +686,17 @@ __device__ __forceinline__ void sample_at(float nxq, float nyq, float qz, const 
 
 // The frame loop for the NP pixels of one lane at once: for each neighbour
 // frame the frame's constants are read once, the first pixel's warp is
-// formed from its offset (dx, dy) from the anchor block centre and the
-// others' incrementally (pixel j lies dyr rows below pixel j-1 of the same
-// surfel, so its q adds dyr times the homography's y column and K t times
-// the change of id_u, didu[j]).  Accumulates A, B and the cost per pixel as
-// frame_loop does; the valid counts of the pixels are packed one per byte of
-// nvp (pixel j in byte j; at most 16 frames each).
+// formed from its offset (dx, dy) from the anchor block centre and its
+// inverse depth idu0, and the others' incrementally: pixel j lies dyr rows
+// below pixel j-1 of the same surfel and its id_u is didu larger (id_u is
+// affine along the column), so its q adds the frame's step, dyr times the
+// homography's y column plus didu times K t.  Accumulates A, B and the cost
+// per pixel as frame_loop does; the valid counts of the pixels are packed
+// one per byte of nvp (pixel j in byte j; at most 16 frames each).
 template <typename T, bool LAST, int NP, bool BY_ROW>
 __device__ __forceinline__ void frame_loop_px(const float* __restrict__ pc, cptr<FrameDev> fr, int nf,
-                                              float dx, float dy, float dyr, const float (&idu)[NP],
-                                              const float (&didu)[NP], const bool (&pix_ok)[NP],
+                                              float dx, float dy, float dyr, float idu0, float didu,
+                                              const bool (&pix_ok)[NP],
                                               unsigned pitch_b, unsigned img_bytes, unsigned wm1,
                                               unsigned hm1, const float (&ikf)[NP], float hk, float img_scale,
                                               float (&A)[NP], float (&B)[NP], float (&cst)[NP],
@@ -708,18 +709,23 @@ __device__ __forceinline__ void frame_loop_px(const float* __restrict__ pc, cptr
         const float h6 = fr[f].zrow[0], h7 = fr[f].zrow[1], k2 = fr[f].zrow[2];
         const __amdgpu_buffer_rsrc_t rs = image_rsrc_for<BY_ROW>(fr[f].img, pitch_b, hm1 + 1);
         // Eq. 6 in local coordinates
-        float nxq = fmaf(c0.x, dx, fmaf(c0.y, dy, fmaf(c0.z, idu[0], c0.w)));
-        float nyq = fmaf(c1.x, dx, fmaf(c1.y, dy, fmaf(c1.z, idu[0], c1.w)));
-        float qz = fmaf(h6, dx, fmaf(h7, dy, fmaf(k2, idu[0], c2.x)));
+        float nxq = fmaf(c0.x, dx, fmaf(c0.y, dy, fmaf(c0.z, idu0, c0.w)));
+        float nyq = fmaf(c1.x, dx, fmaf(c1.y, dy, fmaf(c1.z, idu0, c1.w)));
+        float qz = fmaf(h6, dx, fmaf(h7, dy, fmaf(k2, idu0, c2.x)));
         sample_at<T, LAST, BY_ROW>(nxq, nyq, qz, c0, c1, c2, k2, rs, pix_ok[0], pitch_b, wm1, hm1, ikf[0], hk,
                            img_scale, A[0], B[0], cst[0], nvp, 1u);
+        if constexpr (NP > 1) {
+            const float sx = fmaf(c0.z, didu, c0.y * dyr);
+            const float sy = fmaf(c1.z, didu, c1.y * dyr);
+            const float sz = fmaf(k2, didu, c2.w * dyr);     // c2.w = h7
 #pragma unroll
-        for (int j = 1; j < NP; ++j) {
-            nxq = fmaf(c0.z, didu[j], fmaf(c0.y, dyr, nxq));
-            nyq = fmaf(c1.z, didu[j], fmaf(c1.y, dyr, nyq));
-            qz = fmaf(k2, didu[j], fmaf(h7, dyr, qz));
-            sample_at<T, LAST, BY_ROW>(nxq, nyq, qz, c0, c1, c2, k2, rs, pix_ok[j], pitch_b, wm1, hm1, ikf[j], hk,
-                               img_scale, A[j], B[j], cst[j], nvp, 1u << (8 * j));
+            for (int j = 1; j < NP; ++j) {
+                nxq += sx;
+                nyq += sy;
+                qz += sz;
+                sample_at<T, LAST, BY_ROW>(nxq, nyq, qz, c0, c1, c2, k2, rs, pix_ok[j], pitch_b, wm1, hm1, ikf[j],
+                                   hk, img_scale, A[j], B[j], cst[j], nvp, 1u << (8 * j));
+            }
         }
     }
 }
@@ -1131,19 +1137,19 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(g
                 // count and cost, over its pixels in order
                 float ph[9], pnv, pcs;
                 // frame-independent per-pixel terms (Eq. 3, Eq. 9)
-                float idu[PPL], didu[PPL];
                 bool pix_ok[PPL];
                 // sigma_u = n . (r_u - r_s) / (n . r_s): the lane's first
-                // pixel's, and the step between its pixels (same column)
+                // pixel's, and the step between its pixels (same column);
+                // id_u = id_s (1 + sigma_u) steps by id_s dsig
                 const float cnx = snx * inv_c, cny = sny * inv_c;
                 const float sig0 = fmaf(cny, dry0, cnx * drx0);
                 const float dsig = cny * dyr_f;
+                const float idu0 = fmaf(sid, sig0, sid);
+                const float didu = sid * dsig;
 #pragma unroll
                 for (int j = 0; j < PPL; ++j) {
                     const float sig = j == 0 ? sig0 : fmaf((float)j, dsig, sig0);
-                    idu[j] = fmaf(sid, sig, sid);
-                    didu[j] = j == 0 ? 0.f : idu[j] - idu[j - 1];
-                    pix_ok[j] = salive && (idu[j] > 0.f);
+                    pix_ok[j] = salive && (fmaf(sid, sig, sid) > 0.f);
                 }
                 // the first pixel's offset from the anchor block centre; the
                 // lane's later pixels lie DYR rows apart in the same column
@@ -1156,10 +1162,10 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(g
                     A[j] = 0.f; B[j] = 0.f; cst[j] = 0.f;
                 }
                 if (with_cost)
-                    frame_loop_px<T, true, PPL, BY_ROW>(pairs, fr, nf, bdx, bdy, DYR, idu, didu, pix_ok, pitch_b,
+                    frame_loop_px<T, true, PPL, BY_ROW>(pairs, fr, nf, bdx, bdy, DYR, idu0, didu, pix_ok, pitch_b,
                                                 img_bytes, wm1, hm1, ikf[k], hk, img_scale, A, B, cst, nvp);
                 else
-                    frame_loop_px<T, false, PPL, BY_ROW>(pairs, fr, nf, bdx, bdy, DYR, idu, didu, pix_ok, pitch_b,
+                    frame_loop_px<T, false, PPL, BY_ROW>(pairs, fr, nf, bdx, bdy, DYR, idu0, didu, pix_ok, pitch_b,
                                                  img_bytes, wm1, hm1, ikf[k], hk, img_scale, A, B, cst, nvp);
                 // the surfel's state and tangent basis, read again from LDS
                 // after the frame loop rather than held in registers through it
