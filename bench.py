@@ -73,7 +73,9 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the library's default plan instead of the autotuned one")
     ap.add_argument("--plan", default="",
-                    help="GN mapping TXxTY:K (surfels per group, groups per work item), e.g. 2x4:8")
+                    help="GN mapping TXxTY:K[:P[:X]] (surfels per group, groups per work item, "
+                         "persistent grid 0/1, XCD queues or shares 0/1; P and X default to 1), "
+                         "e.g. 2x4:2 or 4x4:1:0:1")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a kernel of "
                          "known traffic for scaling the HBM counters)")
@@ -375,9 +377,11 @@ def main():
     samples = sum(d.n_surfels * d.n_nbr * d.patch * d.patch for d in dks) * iters
     plan = None
     if args.plan:
-        tiles, groups = args.plan.split(":")
-        tx, ty = (int(v) for v in tiles.split("x"))
-        plan = sg.plan(tx, ty, 1, 0, 0, 1, groups=int(groups))
+        fields = args.plan.split(":")
+        tx, ty = (int(v) for v in fields[0].split("x"))
+        pers = int(fields[2]) if len(fields) > 2 else 1
+        xq = int(fields[3]) if len(fields) > 3 else 1
+        plan = sg.plan(tx, ty, pers, 0, 0, xq, groups=int(fields[1]))
     elif not args.no_autotune:
         # the mapping the autotuner picks for this batch (every tile layout,
         # groups per item, persistent grid or not, XCD queues or not)

@@ -165,7 +165,12 @@ typedef struct {
                                    device queue; 0: one wavefront per work item */
     int32_t waves_per_cu;       /* persistent grid size per compute unit (0: occupancy) */
     int32_t lds_stage;          /* 1: stage neighbour-frame footprints in LDS */
-    int32_t xcd_queues;         /* 1: one work queue per XCD, keyframes bound to an XCD */
+    int32_t xcd_queues;         /* 1: keyframes bound to an XCD, balanced by work: with
+                                   persistent, one device queue per XCD; without, the
+                                   workgroups the hardware gives XCD x (every eighth,
+                                   from x) take XCD x's share of the work items in
+                                   order (batches of eight keyframes or more; fewer
+                                   run as with 0) */
     int32_t groups;             /* tiles_x x tiles_y groups per work item: 1, 2 or 4; 1 or
                                    2 for the 4x2 and 2x4 blocks; 1 for 4x4 and S = 16 (0:
                                    as many as fit, at most four).  A work item lies in one

@@ -310,12 +310,13 @@ sgn_plan default_plan(int patch) {
     sgn_plan p{};
     // measured fastest on the 64-keyframe batch: 4x4 groups (a whole anchor
     // block of sixteen surfels per wavefront, four pixels per lane), one per
-    // item; a 16 x 16 surfel spans a whole anchor block, so it is one group
+    // item, one wavefront per item with the items split into one share per
+    // XCD; a 16 x 16 surfel spans a whole anchor block, so it is one group
     // per item
     if (patch == 4) { p.tiles_x = 4; p.tiles_y = 4; }
     else { p.tiles_x = 1; p.tiles_y = 1; }
     p.groups = default_groups(patch, p.tiles_x, p.tiles_y);
-    p.persistent = 1;
+    p.persistent = patch == 4 ? 0 : 1;
     p.waves_per_cu = 0;
     p.lds_stage = 0;
     p.xcd_queues = 1;
@@ -394,7 +395,12 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
         int64_t gw = kf.kf.width / kf.patch, gh = kf.kf.height / kf.patch;
         work[i] = gw * gh * std::max(1, kf.n_nbr);
     }
-    const int nq = (fl.gn && plan.persistent && plan.xcd_queues) ? std::min(kXcds, n) : 1;
+    // XCD-bound keyframes: a persistent grid pulls from one queue per XCD
+    // (as many as there are keyframes); a one-wavefront-per-item grid maps
+    // its workgroups onto the eight XCDs' shares, so it needs all eight
+    const int nq = !(fl.gn && plan.xcd_queues) ? 1
+                   : plan.persistent ? std::min(kXcds, n)
+                   : (n >= kXcds ? kXcds : 1);
     std::vector<int> queue_of(n, 0);
     if (nq > 1) {
         // greedy balance: biggest keyframe to the least loaded queue
@@ -502,8 +508,17 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
     const BatchHeader* dH = (const BatchHeader*)(dev + L.hdr_off);
     const int frames_cap = (int)((c->table_cap - L.fr_off) / sizeof(FrameDev));
     const int aux_grid = std::max(1, c->cus) * 8;
-    const int gn_grid = plan.persistent ? persistent_grid(c, var, plan)
-                                        : std::max(1, (item_base + 3) / 4);
+    // one wavefront per work item, four per workgroup; with one share per
+    // XCD, workgroup b serves share b % kXcds, so the grid covers the largest
+    // share kXcds times
+    int np_blocks = (item_base + 3) / 4;
+    if (!plan.persistent && nq == kXcds) {
+        int widest = 0;
+        for (int q = 0; q < kXcds; ++q)
+            widest = std::max(widest, (H->queues[q].end - H->queues[q].begin + 3) / 4);
+        np_blocks = kXcds * widest;
+    }
+    const int gn_grid = plan.persistent ? persistent_grid(c, var, plan) : std::max(1, np_blocks);
     const bool do_init = H->do_init, do_render = H->do_render;
     // Kernel sequence in three parts (pre: setup + init, gn, post: render),
     // each replayed from its own captured graph when the launch shape
@@ -1318,7 +1333,10 @@ sgn_status sgn_autotune(sgn_ctx* c, const sgn_batch_item* items, int32_t n, cons
     for (auto sh : shapes)
         for (int groups : group_counts)
             for (int pers = 0; pers <= 1; ++pers)
-                for (int xq = 0; xq <= pers; ++xq) {
+                for (int xq = 0; xq <= 1; ++xq) {
+                    // under eight keyframes the one-wavefront-per-item grid
+                    // ignores xcd_queues: the same launch as xq = 0
+                    if (!pers && xq && n < kXcds) continue;
                     sgn_plan pl{};
                     pl.tiles_x = sh.first;
                     pl.tiles_y = sh.second;

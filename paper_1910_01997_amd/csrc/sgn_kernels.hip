@@ -946,7 +946,7 @@ __device__ __forceinline__ bool lm_accept(float cost2, int nv2, float cost_here,
 // Wavefronts per SIMD each plan's kernel is compiled for (the register
 // budget: 72 VGPRs for seven, 80 for six, 96 for five).  Occupancy pays: on
 // the 64-keyframe f16 batch the 4x4 one-group kernel takes 4.69 ms at four,
-// 4.30 at five, 3.94 at six and 3.76 at seven (its 12 spilled words are
+// 4.30 at five, 3.94 at six and 3.76 at seven (its 11-12 spilled words are
 // stored and reloaded once per work item, or in the damped variant's
 // branches); at eight, with spills inside the iteration loop, 4.05 ms.
 template <int S, int K>
@@ -1010,9 +1010,21 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(g
 
     int q = persistent ? (int)(blockIdx.x % (unsigned)kXcds) % hdr->n_queues : 0;
     int q_left = hdr->n_queues;
-    const int wave_global = blockIdx.x * (kBlockThreads / kWaveSize) + wave;
     int hint = 0;
-    int item = persistent ? pull_item(hdr_, counters, q, q_left, lane, total) : wave_global;
+    int item;
+    if (persistent) {
+        item = pull_item(hdr_, counters, q, q_left, lane, total);
+    } else if (hdr->n_queues == kXcds) {
+        // one share of the work items per XCD: the hardware hands the
+        // workgroups to the XCDs in turn, so workgroup b runs on XCD
+        // b % kXcds and takes that share's items in order
+        const int share = (int)(blockIdx.x % (unsigned)kXcds);
+        const int it = hdr->queues[share].begin +
+                       (int)(blockIdx.x / (unsigned)kXcds) * (kBlockThreads / kWaveSize) + wave;
+        item = it < hdr->queues[share].end ? it : total;
+    } else {
+        item = blockIdx.x * (kBlockThreads / kWaveSize) + wave;
+    }
     for (; item < total;
          item = persistent ? pull_item(hdr_, counters, q, q_left, lane, total) : total) {
         item = __builtin_amdgcn_readfirstlane(item);

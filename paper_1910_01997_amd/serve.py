@@ -432,7 +432,9 @@ class HipExecutor(Executor):
         if pixels_per_lane == 4:
             self.small_plan = sg.plan(4, 4, 1, 0, 0, 1, groups=1)
             self.single_plan = sg.plan(4, 4, 0, 0, 0, 0, groups=1)
-            self.large_plan = sg.plan(4, 4, 0, 0, 0, 0, groups=1)
+            # one wavefront per work item, the items split into one share
+            # per XCD (batches of eight keyframes or more)
+            self.large_plan = sg.plan(4, 4, 0, 0, 0, 1, groups=1)
         elif pixels_per_lane == 1:
             self.small_plan = sg.plan(2, 2, 1, 0, 0, 1, groups=1)
             self.single_plan = sg.plan(2, 2, 0, 0, 0, 0, groups=1)

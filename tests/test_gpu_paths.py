@@ -80,6 +80,30 @@ def test_batch_equals_plain_bitwise_and_plans_agree(ctx):
                 assert np.array_equal(d.inv_depth_out.cpu().numpy(), dm)
 
 
+def test_xcd_shares_without_queues_equal_the_plain_grid_bitwise(ctx):
+    """Ten keyframes (all three sizes, 4-12 neighbours) under the
+    one-wavefront-per-item grid with the work split into one share per XCD
+    (shares of different lengths, so some workgroups find no item) equal the
+    same grid without shares and the persistent grid with XCD queues,
+    bitwise."""
+    sg, engine = sgmod()
+    kfs = [make_keyframe(spec_for_config(2, i), device="cuda") for i in range(10)]
+    print("case xcd shares, keyframes 0-9 of the batch workload", flush=True)
+    prm = sg.params(iters=4)
+    results = []
+    for pl in (sg.plan(4, 4, 0, 0, 0, 0, groups=1), sg.plan(4, 4, 0, 0, 0, 1, groups=1),
+               sg.plan(4, 4, 1, 0, 0, 1, groups=1)):
+        ds = [engine.DeviceKeyframe.from_scene(ctx, k) for k in kfs]
+        engine.update_batch(ctx, ds, prm, pl)
+        torch.cuda.synchronize()
+        results.append([(d.state.to_host(), d.inv_depth_out.cpu().numpy()) for d in ds])
+    for other in results[1:]:
+        for (st, dm), (st0, dm0) in zip(other, results[0]):
+            _state_equal(st, st0)
+            assert np.array_equal(dm, dm0)
+    assert any((st["flags"] == 0).mean() > 0.5 for st, _ in results[0])
+
+
 def test_eight_surfel_groups_batch_equals_plain_and_ragged(ctx):
     """The 4x2 / 2x4 / 4x4 layouts (eight or sixteen 4x4 surfels per
     wavefront): batched equals one keyframe at a time bitwise under the same
