@@ -344,6 +344,33 @@ int persistent_grid(sgn_ctx* c, const GnVariant& v, const sgn_plan& plan) {
 }
 
 // Build the descriptor table for a batch, upload it and enqueue the kernels.
+// Keyframes bound to nq shares (one per XCD) by greedy load balance: the
+// biggest work to the least loaded share.  Returns the keyframe order: by
+// share, and within one by neighbour count, longest first (share_of[i] is
+// keyframe i's share).
+std::vector<int> share_order(int nq, const std::vector<int64_t>& work, const std::vector<int>& n_nbr,
+                             std::vector<int>& share_of) {
+    const int n = (int)work.size();
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    share_of.assign(n, 0);
+    if (nq > 1) {
+        std::vector<int> bysize(order);
+        std::stable_sort(bysize.begin(), bysize.end(), [&](int a, int b) { return work[a] > work[b]; });
+        std::vector<int64_t> load(nq, 0);
+        for (int i : bysize) {
+            const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            share_of[i] = q;
+            load[q] += work[i];
+        }
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (share_of[a] != share_of[b]) return share_of[a] < share_of[b];
+        return n_nbr[a] > n_nbr[b];
+    });
+    return order;
+}
+
 sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_params* prm,
                      const sgn_plan* plan_in, RunFlags fl) {
     if (n < 1) return fail(SGN_E_INVALID, "empty batch");
@@ -387,8 +414,6 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
     // keyframe order: longest work items first, grouped by XCD queue
     const ItemGeo geo = fl.gn ? item_geo(patch, plan.tiles_x, plan.tiles_y, plan.groups)
                               : item_geo(patch, patch == 4 ? 4 : 1, 1, 1);
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
     std::vector<int64_t> work(n);
     for (int i = 0; i < n; ++i) {
         const sgn_keyframe& kf = items[i].kf;
@@ -401,22 +426,10 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
     const int nq = !(fl.gn && plan.xcd_queues) ? 1
                    : plan.persistent ? std::min(kXcds, n)
                    : (n >= kXcds ? kXcds : 1);
-    std::vector<int> queue_of(n, 0);
-    if (nq > 1) {
-        // greedy balance: biggest keyframe to the least loaded queue
-        std::vector<int> bysize(order);
-        std::stable_sort(bysize.begin(), bysize.end(), [&](int a, int b) { return work[a] > work[b]; });
-        std::vector<int64_t> load(nq, 0);
-        for (int i : bysize) {
-            int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-            queue_of[i] = q;
-            load[q] += work[i];
-        }
-    }
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        if (queue_of[a] != queue_of[b]) return queue_of[a] < queue_of[b];
-        return items[a].kf.n_nbr > items[b].kf.n_nbr;
-    });
+    std::vector<int> n_nbr(n);
+    for (int i = 0; i < n; ++i) n_nbr[i] = items[i].kf.n_nbr;
+    std::vector<int> queue_of;
+    const std::vector<int> order = share_order(nq, work, n_nbr, queue_of);
 
     int frame_base = 0, item_base = 0, surfel_base = 0;
     int64_t pixel_base = 0;
@@ -511,11 +524,12 @@ sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_p
     // one wavefront per work item, four per workgroup; with one share per
     // XCD, workgroup b serves share b % kXcds, so the grid covers the largest
     // share kXcds times
-    int np_blocks = (item_base + 3) / 4;
+    constexpr int wpb = kBlockThreads / kWaveSize;    // wavefronts per workgroup
+    int np_blocks = (item_base + wpb - 1) / wpb;
     if (!plan.persistent && nq == kXcds) {
         int widest = 0;
         for (int q = 0; q < kXcds; ++q)
-            widest = std::max(widest, (H->queues[q].end - H->queues[q].begin + 3) / 4);
+            widest = std::max(widest, (H->queues[q].end - H->queues[q].begin + wpb - 1) / wpb);
         np_blocks = kXcds * widest;
     }
     const int gn_grid = plan.persistent ? persistent_grid(c, var, plan) : std::max(1, np_blocks);
@@ -665,12 +679,21 @@ sgn_status run_disc_batch(sgn_ctx* c, const sgn_disc_item* items, int n, const s
     KfDev* kfs = (KfDev*)(host + L.kf_off);
     FrameDev* frs = (FrameDev*)(host + L.fr_off);
     std::memset(host, 0, L.total);
-    // longest work first (most neighbour frames): the grid is dispatched in
-    // item order, so the short surfels fill the tail
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int x, int y) { return items[x].kf.n_nbr > items[y].kf.n_nbr; });
+    // batches of eight keyframes or more: the keyframes split into one share
+    // per XCD, balanced by work (surfels x neighbour frames), and workgroup b
+    // takes the items of XCD b % kXcds's share in order; within a share (or
+    // the one share of a smaller batch) longest work first (most neighbour
+    // frames), so the short surfels fill the tail
+    const int nq = n >= kXcds ? kXcds : 1;
+    std::vector<int64_t> work(n);
+    std::vector<int> n_nbr(n), share_of;
+    for (int i = 0; i < n; ++i) {
+        work[i] = (int64_t)items[i].count * std::max(1, items[i].kf.n_nbr);
+        n_nbr[i] = items[i].kf.n_nbr;
+    }
+    const std::vector<int> order = share_order(nq, work, n_nbr, share_of);
+    for (int q = 0; q < kNumCounters; ++q) H->queues[q].begin = H->queues[q].end = 0;
+    int cur_q = -1;
     int frame_base = 0, surfel_base = 0, item_base = 0;
     for (int oi = 0; oi < n; ++oi) {
         const sgn_disc_item& it = items[order[oi]];
@@ -711,9 +734,15 @@ sgn_status run_disc_batch(sgn_ctx* c, const sgn_disc_item* items, int n, const s
             std::memcpy(F.R, kf.pose[f].R, sizeof(F.R));
             std::memcpy(F.t, kf.pose[f].t, sizeof(F.t));
         }
+        const int q = share_of[order[oi]];
+        if (q != cur_q) {
+            H->queues[q].begin = item_base;
+            cur_q = q;
+        }
         frame_base += kf.n_nbr;
         surfel_base += it.count;
         item_base += D.n_items;
+        H->queues[q].end = item_base;
     }
     H->kfs = (KfDev*)(dev + L.kf_off);
     H->frames = (FrameDev*)(dev + L.fr_off);
@@ -729,7 +758,7 @@ sgn_status run_disc_batch(sgn_ctx* c, const sgn_disc_item* items, int n, const s
     H->stamp = prm->stamp;
     H->lm_lambda = prm->lm_lambda;
     H->do_gn = 1;
-    H->n_queues = 1;
+    H->n_queues = nq;
     SGN_HIP(hipMemcpyAsync(dev, host, L.total, hipMemcpyHostToDevice, c->stream));
     SGN_HIP(hipEventRecord(c->ring_ev[slot], c->stream));
     c->ring_used[slot] = true;
@@ -747,7 +776,17 @@ sgn_status run_disc_batch(sgn_ctx* c, const sgn_disc_item* items, int n, const s
             const sgn_keyframe& kf = items[i].kf;
             if (kf.n_nbr > 0 && (size_t)kf.nbr[0].pitch * dtype_size(kf.kf.dtype) >= kMaxRowStride) by_row = false;
         }
-        e = launch_disc_gn(dtype, dH, item_base, by_row, c->stream);
+        // one wavefront per item, four per workgroup; with shares the grid
+        // covers the largest share once per XCD
+        constexpr int wpb = kBlockThreads / kWaveSize;
+        int blocks = (item_base + wpb - 1) / wpb;
+        if (nq == kXcds) {
+            int widest = 0;
+            for (int q = 0; q < kXcds; ++q)
+                widest = std::max(widest, (H->queues[q].end - H->queues[q].begin + wpb - 1) / wpb);
+            blocks = kXcds * widest;
+        }
+        e = launch_disc_gn(dtype, dH, item_base, std::max(1, blocks), by_row, c->stream);
         if (e != hipSuccess) return hip_fail(e, "disc Gauss-Newton launch");
         SGN_HIP(hipEventRecord(c->gn_end, c->stream));
         c->gn_timed = true;

@@ -176,7 +176,10 @@ constexpr int disc_surfels_per_wave(int dtype) { return dtype == 0 ? 1 : 2; }
 // Gauss-Newton over the disc surfels of a batch: one wavefront per work item
 // of disc_surfels_per_wave(dtype) surfels of one keyframe (KfDev::n_items =
 // ceil(disc_count / that), item_base their prefix).
-hipError_t launch_disc_gn(int dtype, const BatchHeader* hdr, int total_items, bool by_row, hipStream_t s);
+// grid_blocks workgroups of four wavefronts, one work item each (with one
+// share per XCD in the header, workgroup b serves share b % kXcds)
+hipError_t launch_disc_gn(int dtype, const BatchHeader* hdr, int total_items, int grid_blocks, bool by_row,
+                          hipStream_t s);
 // Depth-buffered render of the discs of several keyframes: one table entry
 // per keyframe (device memory); the scratch holds one 64-bit depth key and
 // one index per pixel of every keyframe, keyframe after keyframe.

@@ -2021,7 +2021,14 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
     const int lane = threadIdx.x & (kWaveSize - 1);
     const int wave = threadIdx.x >> 6;
     const int h = lane / LANES, hl = lane % LANES;       // surfel of the wave, lane within it
-    const int item = __builtin_amdgcn_readfirstlane((int)blockIdx.x * WPB + wave);
+    int item_ = (int)blockIdx.x * WPB + wave;
+    if (hdr->n_queues == kXcds) {
+        // one share of the items per XCD (workgroups go to the XCDs in turn)
+        const int share = (int)(blockIdx.x % (unsigned)kXcds);
+        item_ = hdr->queues[share].begin + (int)(blockIdx.x / (unsigned)kXcds) * WPB + wave;
+        if (item_ >= hdr->queues[share].end) item_ = total;
+    }
+    const int item = __builtin_amdgcn_readfirstlane(item_);
     if (item >= total) return;
     __shared__ float4 s_pairs[WPB][SPW][kMaxNbr * kPairWords / 4];
     __shared__ float4 s_state[WPB][SPW][ST_WORDS / 4];
@@ -2749,10 +2756,10 @@ static void launch_disc_gn_rows(int dtype, const BatchHeader* hdr, int total_ite
         disc_gn_kernel<uint8_t, disc_surfels_per_wave(2), R><<<grid, kBlockThreads, 0, s>>>(hdr, total_items);
 }
 
-hipError_t launch_disc_gn(int dtype, const BatchHeader* hdr, int total_items, bool by_row, hipStream_t s) {
+hipError_t launch_disc_gn(int dtype, const BatchHeader* hdr, int total_items, int grid_blocks, bool by_row,
+                          hipStream_t s) {
     if (total_items <= 0) return hipSuccess;
-    const int waves = kBlockThreads / kWaveSize;
-    const dim3 grid((total_items + waves - 1) / waves);
+    const dim3 grid(grid_blocks);
     if (by_row) launch_disc_gn_rows<true>(dtype, hdr, total_items, grid, s);
     else launch_disc_gn_rows<false>(dtype, hdr, total_items, grid, s);
     return hipGetLastError();

@@ -216,6 +216,37 @@ def test_disc_batch_equals_alone_and_empty_cases(ctx):
     assert np.all(empty.state_host()["flags"] == oracle.UNINIT)
 
 
+def test_disc_batch_in_xcd_shares_equals_alone(ctx):
+    """Ten keyframes (2-7 neighbours, one without surfels) run in one launch
+    with the work items in one share per XCD: every keyframe's result equals
+    its update alone, bitwise."""
+    sg, engine = _mods()
+    scenes = [_scene(seed=90 + i, n_nbr=2 + i % 6) for i in range(10)]
+    print("case disc batch of 10 in XCD shares == alone", flush=True)
+    prm = sg.params(iters=4)
+
+    def make(i):
+        kf, discs = scenes[i]
+        if i == 4:
+            z = np.zeros(0, np.float32)
+            return engine.DiscKeyframe(ctx, kf.kf_image, kf.nbr_images, kf.R, kf.t, kf.K, 10.0, z, z, z,
+                                       np.zeros((0, 3), np.float32), capacity=16, storage="f16")
+        return engine.DiscKeyframe.from_scene(ctx, kf, discs, storage="f16")
+
+    alone = []
+    for i in range(len(scenes)):
+        dk = make(i)
+        engine.disc_update(ctx, [dk], prm)
+        torch.cuda.synchronize()
+        alone.append(dk.state_host())
+    dks = [make(i) for i in range(len(scenes))]
+    engine.disc_update(ctx, dks, prm)
+    torch.cuda.synchronize()
+    for dk, ref in zip(dks, alone):
+        _state_equal(dk.state_host(), ref)
+    assert sum(dk.count for dk in dks) > 3000
+
+
 def test_disc_argument_errors(ctx):
     sg, engine = _mods()
     L = sg.lib()
