@@ -660,10 +660,11 @@ def compulsory_bytes(dks, iters):
 
 def same_plan(rec_plan, plan):
     """Whether a profile's plan (dict) is the plan the bench ran (None: the
-    library's default, 4x4 tiles, one group, persistent, XCD queues)."""
+    library's default, 4x4 tiles, one group, one wavefront per item, XCD
+    shares)."""
     if not rec_plan:
         return False
-    run = plan.as_dict() if plan is not None else {"tiles_x": 4, "tiles_y": 4, "groups": 1, "persistent": 1,
+    run = plan.as_dict() if plan is not None else {"tiles_x": 4, "tiles_y": 4, "groups": 1, "persistent": 0,
                                                   "xcd_queues": 1}
     return all(int(rec_plan.get(k, -1)) == int(run.get(k, -2))
                for k in ("tiles_x", "tiles_y", "groups", "persistent", "xcd_queues"))

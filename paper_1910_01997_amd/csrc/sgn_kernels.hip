@@ -1017,7 +1017,9 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(g
     } else if (hdr->n_queues == kXcds) {
         // one share of the work items per XCD: the hardware hands the
         // workgroups to the XCDs in turn, so workgroup b runs on XCD
-        // b % kXcds and takes that share's items in order
+        // b % kXcds and takes that share's items in order (every item is
+        // still taken once under any other dispatch order; only the L2
+        // locality depends on it)
         const int share = (int)(blockIdx.x % (unsigned)kXcds);
         const int it = hdr->queues[share].begin +
                        (int)(blockIdx.x / (unsigned)kXcds) * (kBlockThreads / kWaveSize) + wave;
