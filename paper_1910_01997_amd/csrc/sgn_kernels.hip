@@ -2416,39 +2416,56 @@ __global__ __launch_bounds__(1024) void bin_scan_add_kernel(int32_t* __restrict_
 
 // One workgroup per tile, one thread per pixel: the largest Eq. 3 value over
 // the tile's surfels whose disc holds the pixel, and the lowest index among
-// those that reach it.
+// those that reach it.  The tile's list is staged in LDS a workgroup-wide
+// chunk at a time (one list entry and its raster record per thread, all
+// loads in flight at once), so the per-pixel walk reads LDS instead of
+// waiting on a dependent pair of loads per entry.
 __global__ __launch_bounds__(kRenderTile * kRenderTile) void disc_raster_kernel(
     const DiscRenderItem* __restrict__ tab, int n_items, const DiscRaster* __restrict__ rec,
     const int32_t* __restrict__ start, const int32_t* __restrict__ list) {
 #pragma clang fp contract(off)
+    constexpr int kChunk = kRenderTile * kRenderTile;
+    __shared__ DiscRaster s_rec[kChunk];
+    __shared__ int s_idx[kChunk];
     const int t = (int)blockIdx.x;
     const DiscRenderItem& a = tab[render_item_of_tile(tab, n_items, t)];
     const int lt = t - a.tile_base;
     const int ty = lt / a.tiles_x, tx = lt - ty * a.tiles_x;
     const int x = tx * kRenderTile + (int)(threadIdx.x % kRenderTile);
     const int y = ty * kRenderTile + (int)(threadIdx.x / kRenderTile);
-    if (x >= a.width || y >= a.height) return;
+    const bool inside = x < a.width && y < a.height;
     const double xd = (double)x, yd = (double)y, r = (double)a.radius, r2 = r * r;
     const double ru0 = (xd - a.cx) / a.fx, ru1 = (yd - a.cy) / a.fy;
     unsigned long long best = 0ull;
     int who = 0x7fffffff;
-    const int k1 = start[t + 1];
-    for (int k = start[t]; k < k1; ++k) {
-        const int g = list[k];
-        const DiscRaster& q = rec[g];
-        const double dx = xd - q.cx, dy = yd - q.cy;
-        if (!(dx * dx + dy * dy < r2)) continue;
-        const double v = (ru0 * q.n0 + ru1 * q.n1 + 1.0 * q.n2) / q.den;
-        if (!(v > 0.0) || !isfinite(v)) continue;
-        const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-        const int s = g - a.surfel_base;
-        if (bits > best) {
-            best = bits;
-            who = s;
-        } else if (bits == best && s < who) {
-            who = s;
+    const int k0 = start[t], k1 = start[t + 1];
+    for (int c0 = k0; c0 < k1; c0 += kChunk) {
+        const int nc = min(kChunk, k1 - c0);
+        __syncthreads();                     // the previous chunk is read
+        if ((int)threadIdx.x < nc) {
+            const int g = list[c0 + (int)threadIdx.x];
+            s_idx[threadIdx.x] = g;
+            s_rec[threadIdx.x] = rec[g];
+        }
+        __syncthreads();
+        if (!inside) continue;
+        for (int e = 0; e < nc; ++e) {
+            const DiscRaster& q = s_rec[e];
+            const double dx = xd - q.cx, dy = yd - q.cy;
+            if (!(dx * dx + dy * dy < r2)) continue;
+            const double v = (ru0 * q.n0 + ru1 * q.n1 + 1.0 * q.n2) / q.den;
+            if (!(v > 0.0) || !isfinite(v)) continue;
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+            const int s = s_idx[e] - a.surfel_base;
+            if (bits > best) {
+                best = bits;
+                who = s;
+            } else if (bits == best && s < who) {
+                who = s;
+            }
         }
     }
+    if (!inside) return;
     const size_t o = (size_t)y * (size_t)a.width + (size_t)x;
     a.inv_depth_out[o] = best ? (float)__longlong_as_double((long long)best) : 0.f;
     if (a.index_out) a.index_out[o] = best ? who : -1;
