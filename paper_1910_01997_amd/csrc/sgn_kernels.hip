@@ -1552,15 +1552,20 @@ __global__ __launch_bounds__(256) void render_kernel(const BatchHeader* __restri
         float id = 0.f, nx = 0.f, ny = 0.f, inv_c = 1.f, usx = 0.f, usy = 0.f;
         if (tx < K->gw && ty < K->gh) {
             i = ty * K->gw + tx;
-            if (!(K->flags[i] & (F_DEGENERATE | F_UNINIT))) {
+            // the state is loaded with the flags (one round trip, not two);
+            // a flagged surfel's values are not used
+            const uint32_t fl = K->flags[i];
+            const float snx = K->nx[i], sny = K->ny[i], snz = K->nz[i], sid = K->inv_depth[i];
+            // (kept in front of the flag test, where the compiler would sink them)
+            __asm__ volatile("" ::"v"(snx), "v"(sny), "v"(snz), "v"(sid));
+            if (!(fl & (F_DEGENERATE | F_UNINIT))) {
                 usx = (float)(S * tx) + half;
                 usy = (float)(S * ty) + half;
                 const float rsx = (usx - K->cx) * ifx, rsy = (usy - K->cy) * ify;
-                nx = K->nx[i];
-                ny = K->ny[i];
-                const float nz = K->nz[i];
-                const float c = nx * rsx + ny * rsy + nz;
-                id = K->inv_depth[i];
+                nx = snx;
+                ny = sny;
+                const float c = nx * rsx + ny * rsy + snz;
+                id = sid;
                 ok = fabsf(c) >= 1e-6f;
                 inv_c = 1.f / c;
             }
