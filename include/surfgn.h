@@ -237,8 +237,10 @@ sgn_status sgn_render_inverse_depth(sgn_ctx* ctx, const sgn_keyframe* kf,
                                     int32_t* index_out);
 
 /* The whole per-keyframe update for many keyframes at once: initialisation
- * of new surfels, the Gauss-Newton iterations in one fused persistent kernel,
- * and the inverse-depth render, replayed from a captured HIP graph.  All
+ * of new surfels, the Gauss-Newton iterations in one fused kernel launch
+ * (persistent, or one wavefront per work item as the plan says), and the
+ * inverse-depth render; the setup + initialisation and render parts (and a
+ * persistent GN launch) are replayed from captured HIP graphs.  All
  * items must share patch and image dtype.  Results equal those of the
  * per-keyframe calls for the same plan (each surfel is reduced in a fixed
  * order that does not depend on the batch). */
@@ -247,7 +249,7 @@ sgn_status sgn_optimize_batch(sgn_ctx* ctx, const sgn_batch_item* items, int32_t
 
 /* Time candidate plans on a sample batch and return the fastest in *out
  * (host): every tile layout with its group counts, persistent or not, XCD
- * queues or not; each timed as the fastest of three runs after a warm-up
+ * queues or shares or not; each timed as the fastest of three runs after a warm-up
  * run.  When the default plan is within 1 % of the fastest it is returned
  * instead (a tie at the timer's resolution), so a batch gets the same plan
  * from run to run.  The surfel state is snapshotted into the workspace
