@@ -384,7 +384,7 @@ def main():
         plan = sg.plan(tx, ty, pers, 0, 0, xq, groups=int(fields[1]))
     elif not args.no_autotune:
         # the mapping the autotuner picks for this batch (every tile layout,
-        # groups per item, persistent grid or not, XCD queues or not)
+        # groups per item, persistent grid or not, XCD queues or shares or not)
         items = sg.batch_array([d.item(render=False, init=False) for d in dks])
         plan = engine.autotune(ctx, items, len(dks), prm)
         log("autotuned plan", plan.as_dict())

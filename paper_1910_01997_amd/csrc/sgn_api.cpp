@@ -343,7 +343,6 @@ int persistent_grid(sgn_ctx* c, const GnVariant& v, const sgn_plan& plan) {
     return std::max(1, c->cus) * per_cu;
 }
 
-// Build the descriptor table for a batch, upload it and enqueue the kernels.
 // Keyframes bound to nq shares (one per XCD) by greedy load balance: the
 // biggest work to the least loaded share.  Returns the keyframe order: by
 // share, and within one by neighbour count, longest first (share_of[i] is
@@ -371,6 +370,7 @@ std::vector<int> share_order(int nq, const std::vector<int64_t>& work, const std
     return order;
 }
 
+// Build the descriptor table for a batch, upload it and enqueue the kernels.
 sgn_status run_batch(sgn_ctx* c, const sgn_batch_item* items, int n, const sgn_params* prm,
                      const sgn_plan* plan_in, RunFlags fl) {
     if (n < 1) return fail(SGN_E_INVALID, "empty batch");

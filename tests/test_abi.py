@@ -209,3 +209,24 @@ def test_row_pitch_of_16_mib_is_refused(sg):
     assert L.sgn_disc_render(None, C.byref(item), C.c_void_p(0x800000), None, C.c_void_p(0x700000),
                              C.c_size_t(need)) == sg.SGN_E_INVALID
     assert "null context" in sg.sgn_last_error()
+
+
+def test_c_array_passes_prebuilt_arrays_and_the_batch_wrappers_check_lengths(sg):
+    """The binding's argument arrays: a ctypes array of the right type is
+    passed as it is (a caller builds it once), a sequence is converted
+    (0 and None to null pointers), and sequences of different lengths are
+    refused before the library is called."""
+    grids = [sg.grid_of((60.0, 60.0, 8.0, 6.0), 16, 12, 4) for _ in range(3)]
+    arr = sg.c_array(sg.sgn_grid, grids)
+    assert sg.c_array(sg.sgn_grid, arr) is arr and len(arr) == 3
+    assert arr[1].width == 16 and arr[1].patch == 4
+    ptrs = sg.c_array(C.c_void_p, [0, 0x1000, None])
+    assert ptrs[0] is None and ptrs[1] == 0x1000 and ptrs[2] is None
+    assert list(sg.c_array(C.c_int32, [3, 4.0])) == [3, 4]
+    surf = [sg.sgn_surfels() for _ in range(3)]
+    poses = [sg.sgn_pose() for _ in range(3)]
+    with pytest.raises(ValueError):
+        sg.sgn_transfer_surfels_batch(None, grids, surf, poses[:2], grids, surf, [1, 2, 3], None, (0, 0))
+    items = [sg.sgn_disc_item() for _ in range(2)]
+    with pytest.raises(ValueError):
+        sg.sgn_disc_transfer_batch(None, items, [sg.sgn_pose()], items, [1, 1], [1, 2])
